@@ -1,0 +1,180 @@
+"""Benchmark of the SGTP planning step on one MI355X.
+
+A step is one closed-loop planning step of the mid-scale race (3 vehicles on a
+1.2 km x 12 m synthetic track, N = 40, K = 16384 samples per best response,
+5 IBR sweeps): setup, initialisation, 5 Jacobi sweeps and the extra ego response
+(19 best responses = 12.45 M sample-steps), then every vehicle applies its first
+control through the vehicle model.  Inputs are resident on the GPU before the
+timed region.  Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sample·steps/s per IBR sweep; plan latency p50/p99; learned vs plain cost"
+PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak
+
+
+def flops_per_sample_step(n_opp: int, model: int = 0) -> float:
+    """Algorithmic float operations per sample and horizon step (elementary functions count 1).
+
+    noise (Box-Muller pair: log series, sqrt, sin/cos series)      50
+    perturbation and clip of (a, delta)                             8
+    sin/cos of delta                                                2
+    RK4: 4 derivative evaluations of the single-track model x 45,
+         stage states 36, update 42, speed clamp 1                259
+    Frenet projection: ~3 normal-line tests x 5 + foot 60          75
+    tracking, control and control-rate cost                        33
+    boundary clearance                                              4
+    footprint screening per opponent                                6 n_opp
+    tail lateral sum                                                2
+    Disc-pair distances beyond the screening are not counted.
+    """
+    per = 50 + 8 + 2 + 259 + 75 + 33 + 4 + 2 + 6 * n_opp
+    if model == 1:
+        per -= 4 * (45 - 12)  # kinematic derivative ~12 FLOP
+    return float(per)
+
+
+def cpu_baseline(name: str, seconds: float = 10.0, K_sample: int = 2048):
+    """Oracle (float64 C, OpenMP over samples) on this host: planning steps of the same race at a
+    reduced K, repeated for about `seconds`; rate in sample-steps/s (linear in K)."""
+    import numpy as np
+    import oracle
+    from paper_2607_25388_amd import inputs
+
+    w = inputs.WORKLOADS[name]
+    tr, race, params = inputs.workload_inputs(name)
+    orc = oracle.Oracle(tr, params)
+    per_step = ((w.L_ibr + 1) * w.n_agents + 1) * K_sample * w.N
+    t0 = time.perf_counter()
+    done = 0
+    x = race.x.copy()
+    u_nom = race.u_nom.astype(np.float64)
+    s_prev = race.s_abs.copy()
+    step = 0
+    while True:
+        out = orc.plan_step(race, w.L_ibr, K=K_sample, x=x, u_nom=u_nom, s_prev=s_prev, plan_step=step)
+        done += per_step
+        x = orc.advance(x, out["u_apply"])
+        u_nom = out["u_next"]
+        s_prev = out["s_abs"]
+        step += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    el = time.perf_counter() - t0
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp:
+        cores = min(cores, int(omp))
+    return dict(value=done / el, unit="sample·steps/s", cores=cores, kind="oracle",
+                sample=f"{step} closed-loop planning steps of {name} at K={K_sample} per best response "
+                       f"({per_step} sample-steps each), {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this planner runs on a single device (see the design notes for how "
+              "races, vehicles and samples would be spread over several GPUs)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    from paper_2607_25388_amd import inputs
+
+    name = args.workload
+    w = inputs.WORKLOADS[name]
+    tr, race, params = inputs.workload_inputs(name)
+    planner = sg.Planner(max_agents_total=max(16, w.n_agents), max_races=1)
+    planner.upload_track(0, tr)
+    rt = sg.race_from_inputs(race, 0, w.K, w.N, params["n_tail"])
+    L = w.L_ibr
+    n = w.n_agents
+    u = torch.empty((n, 2), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(i):
+        rt.plan_step = i
+        planner.plan_step(params, [rt], L, u_apply=u)
+        planner.advance(params, [rt], u)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    planner.sweep_stats(reset=True)
+    planner.set_timing(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        step(args.warmup + i)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    planner.set_timing(False)
+    sweep_ms, sweep_launches, sweep_ss = planner.sweep_stats(reset=True)
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    assert np.all(np.isfinite(rt.x.cpu().numpy())), "non-finite state"
+
+    per_step = ((L + 1) * n + 1) * w.K * w.N
+    value = per_step * args.steps / el
+    avg_sweep_ms = sweep_ms / max(1, sweep_launches)
+    flops = flops_per_sample_step(n - 1, params["model"])
+    achieved = flops * (sweep_ss / max(1, sweep_launches)) / (avg_sweep_ms * 1e-3) / 1e12
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "sample·steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{name}: {n} vehicles, {w.track_length:.0f} m x {w.track_width:.0f} m seeded track, "
+                        f"N={w.N}, K={w.K} per best response, {L} IBR sweeps + init + extra ego, "
+                        f"{w.n_disc}-disc footprint, closed loop",
+            "sample_steps_per_plan_step": per_step,
+        },
+        "plan_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                            "mean": float(lat.mean())},
+        "sweep_kernel": {"launches": sweep_launches, "avg_ms": avg_sweep_ms,
+                         "sample_steps_per_launch": sweep_ss / max(1, sweep_launches)},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "flops_per_sample_step": flops},
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(name, args.cpu_seconds)
+    planner.close()
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

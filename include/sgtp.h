@@ -1,0 +1,174 @@
+/*
+ * sgtp.h -- C ABI of the MI355X SGTP planner (Sampling-based Game-Theoretic
+ * Planning for multi-vehicle racing).
+ *
+ * One planning step is Alg. 1 of the paper: initial trajectories without the
+ * game-aware cost, L_IBR Jacobi sweeps in which every vehicle computes a sampled
+ * best response against the previous sweep's trajectories of its opponents,
+ * then one extra best response of the ego vehicle.  A best response (Sec. III)
+ * perturbs the nominal control sequence K times with Gaussian noise, clips the
+ * controls to the admissible box, rolls every sequence out through the vehicle
+ * model, scores it with the tracking cost (eq. ctrack) plus the game-aware cost
+ * (eqs. game_cost, c_contest, c_long, c_block, c_safety; total eq. allc), checks
+ * track boundary (eq. selection-boundary) and collision (eqs. Dmin,
+ * selection-vehicle), and selects the lowest-cost feasible sample (eq.
+ * selection), or the least-violation sample when none is feasible.
+ *
+ * Conventions for every call below
+ *   - Arrays are contiguous, row-major.  Pointers inside sgtp_race and the
+ *     output arrays are DEVICE pointers owned by the caller; the sgtp_params,
+ *     sgtp_race structs themselves and the node table of sgtp_track_upload are
+ *     HOST memory, read during the call only.
+ *   - `stream` is a hipStream_t (NULL = default stream).  Calls only enqueue
+ *     work and return; outputs are valid once the stream reaches that point.
+ *   - Return value: SGTP_OK (0) or a negative error code.  Argument errors are
+ *     detected before anything is enqueued, so outputs are untouched;
+ *     sgtp_last_error() returns a text for the last failing call on a context.
+ *   - A context is bound to the device current at creation and must be used
+ *     from one host thread at a time.  Calls on one context must be issued on
+ *     one stream (the context owns workspace that successive calls reuse).
+ *   - The three planning calls allocate nothing and never synchronise the host.
+ *
+ * Frames and units: world frame in metres and radians; states are
+ * (x, y, psi, v_x, v_y, omega) at the centre of gravity (the kinematic model
+ * uses (x, y, psi, v) in the first four entries); controls (a [m/s^2], delta [rad]).
+ */
+#ifndef SGTP_H
+#define SGTP_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SGTP_OK 0
+#define SGTP_EINVAL (-1)  /* null pointer, bad enum or value out of range */
+#define SGTP_ESHAPE (-2)  /* size beyond what the context was created for */
+#define SGTP_ETRACK (-3)  /* unknown track id, or track does not fit the kernels */
+#define SGTP_EDEVICE (-4) /* HIP runtime or launch error */
+#define SGTP_ENOMEM (-5)  /* device allocation failed (context creation only) */
+
+#define SGTP_MAX_AGENTS 16 /* vehicles per race */
+#define SGTP_MAX_N 64      /* horizon steps */
+#define SGTP_MAX_K (1 << 24)
+#define SGTP_TRAJ_STRIDE 8 /* trajectory row: x, y, psi, vx, vy, omega, s, d */
+
+typedef struct sgtp_ctx sgtp_ctx;
+
+/* Planner parameters (Sec. IV-B lists the paper's values). */
+typedef struct {
+    int model;                 /* 0 = dynamic single-track, 1 = kinematic bicycle */
+    float dt;                  /* control interval [s] */
+    float a_min, a_max;        /* admissible box of Pi_U */
+    float d_min, d_max;
+    float sigma_a, sigma_d;    /* perturbation std devs, Sigma_u = diag(sigma_a^2, sigma_d^2) */
+    float Q[4];                /* tracking weights on (x, y, psi, v) */
+    float R[2];                /* control weights */
+    float S[2];                /* control-rate weights */
+    float w_game, w_contest, w_long, w_block, w_safety;
+    float s_contest, s_role, eps_alpha;
+    float g_safe;              /* safety distance of eq. (c_safety) */
+    float m_bd;                /* boundary margin of eq. (selection-boundary) */
+    float d_col;               /* collision threshold of eq. (selection-vehicle) */
+    int n_disc;                /* footprint discs along the heading: 1 or 3 */
+    float disc_off[4];         /* disc offsets from the centre of gravity [m] */
+    float m, Iz, lf, lr;       /* vehicle mass, yaw inertia, CoG-axle distances */
+    float B, C, mu, g;         /* tyre F_y = mu F_z sin(C atan(B alpha)); gravity */
+    float v_eps;               /* speed floor inside the slip angles [m/s] */
+    int max_moves;             /* segment-search limit of the Frenet projection */
+} sgtp_params;
+
+/* One race (one game) at one planning instant. */
+typedef struct {
+    int n_agents;              /* 1..SGTP_MAX_AGENTS */
+    int ego;                   /* index of the ego vehicle e */
+    int track_id;              /* track uploaded with sgtp_track_upload */
+    int N;                     /* horizon H, 1..SGTP_MAX_N */
+    int n_tail;                /* |T_tail|, 1..N (final steps averaged by eq. c_block) */
+    int K;                     /* samples per best response, 1..SGTP_MAX_K */
+    unsigned long long seed;   /* Philox key of the race */
+    unsigned int plan_step;    /* Philox counter word of this planning step */
+    double *x;                 /* [n][6] current states (read; sgtp_advance updates them) */
+    double *s_abs;             /* [n] unwrapped progress: in = previous value or NaN, out = current */
+    const float *v_scale;      /* [n] reference-speed scale of each vehicle (opponents 0.9, Sec. IV-B) */
+    float *u_nom;              /* [n][N][2] nominal sequences U-bar (in/out: warm start) */
+    double *traj;              /* [n][N+1][8] out: planned trajectories, or NULL */
+} sgtp_race;
+
+/* Result of one best response. */
+typedef struct {
+    int k;                     /* selected sample k* */
+    int fallback;              /* 1 when no sample was feasible (least-violation choice) */
+    int n_feasible;            /* number of feasible samples */
+    float cost;                /* c of k* (eq. allc) */
+    float viol;                /* total violation nu of k* (0 when feasible) */
+} sgtp_choice;
+
+/* ---- context and tracks ---------------------------------------------------- */
+
+/* Create a context on the current device with workspace for up to
+ * max_agents_total vehicles over all races of one call, horizons up to max_N,
+ * max_races races per call and track tables of up to max_track_nodes nodes.
+ * Allocates device memory (the only call that does, with sgtp_track_upload). */
+int sgtp_ctx_create(sgtp_ctx **out, int max_agents_total, int max_N, int max_races, int max_track_nodes);
+int sgtp_ctx_destroy(sgtp_ctx *ctx);
+const char *sgtp_last_error(const sgtp_ctx *ctx);
+
+/* Upload the raceline G (Sec. II) as a HOST table nodes[n_nodes][8] of
+ * (x, y, psi, kappa, w_L, w_R, v_ref, s) at increasing arc length s, psi
+ * unwrapped.  closed != 0 joins node n-1 to node 0; one lap adds `length` to s
+ * and `psi_lap` to psi.  Synchronous; replaces a track with the same id. */
+int sgtp_track_upload(sgtp_ctx *ctx, int track_id, const double *nodes, int n_nodes, int closed, double length,
+                      double psi_lap);
+
+/* ---- planning ------------------------------------------------------------- */
+
+/* One best response of vehicle `agent` in `phase` (0 = initialisation without
+ * the game-aware cost, 1..L = sweeps, any larger value = a sweep with the
+ * game-aware cost), with every other vehicle predicted by the noise-free rollout
+ * of its nominal sequence.  Per-sample DEVICE outputs (each may be NULL):
+ *   cost[K]   c of eq. (allc)              flags[K]  bit0 b, bit1 o, bit2 h = b*o,
+ *   viol[K]   total violation nu                      bit3 search limit, bit4 non-finite
+ *   x_final[K][6] world state after N steps  noise[K][N][2] the drawn perturbations
+ * `out` (DEVICE, 1 entry) receives the selection.  u_nom is not modified.
+ * Also writes race->s_abs. */
+int sgtp_rollout_cost(sgtp_ctx *ctx, const sgtp_params *p, const sgtp_race *race, int agent, int phase,
+                      float *cost, unsigned char *flags, float *viol, double *x_final, float *noise,
+                      sgtp_choice *out, void *stream);
+
+/* One Jacobi sweep (phase 0..L) over all vehicles of all races, or the extra ego
+ * response (phase = L+1, pass ego_only = 1): every participating vehicle answers
+ * the noise-free rollouts of its opponents' current nominals, then adopts its
+ * selected controls as its new nominal (u_nom) and writes traj.
+ * out: DEVICE [sum n_agents] selections (entries of non-participating vehicles
+ * are left untouched). */
+int sgtp_ibr_sweep(sgtp_ctx *ctx, const sgtp_params *p, const sgtp_race *races, int n_races, int phase,
+                   int ego_only, sgtp_choice *out, void *stream);
+
+/* Alg. 1 for every race: initialisation, L_ibr sweeps, extra ego response.
+ * Writes traj (final predictions), s_abs, u_apply (DEVICE [sum n][2], the first
+ * control of each vehicle's final plan), trace (DEVICE [(L_ibr+2)][sum n]
+ * selections, or NULL; non-participants untouched) and replaces u_nom by the
+ * warm start of the next step (final plan shifted by one, last control repeated). */
+int sgtp_plan_step(sgtp_ctx *ctx, const sgtp_params *p, const sgtp_race *races, int n_races, int L_ibr,
+                   float *u_apply, sgtp_choice *trace, void *stream);
+
+/* Closed loop: apply u (DEVICE [sum n][2]) to every vehicle for one interval
+ * dt through the same vehicle model (float64 RK4), updating race->x. */
+int sgtp_advance(sgtp_ctx *ctx, const sgtp_params *p, const sgtp_race *races, int n_races, const float *u,
+                 void *stream);
+
+/* ---- instrumentation ------------------------------------------------------ */
+
+/* Time every sweep-kernel launch with HIP events on its stream (on != 0). */
+int sgtp_set_timing(sgtp_ctx *ctx, int on);
+/* Sum of measured sweep-kernel durations [ms] and launch count since the last
+ * reset; synchronises the events.  reset != 0 clears the counters afterwards. */
+int sgtp_sweep_stats(sgtp_ctx *ctx, double *total_ms, long long *launches, long long *sample_steps, int reset);
+
+int sgtp_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGTP_H */

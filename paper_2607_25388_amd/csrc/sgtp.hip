@@ -1,0 +1,1628 @@
+// sgtp.hip -- MI355X (gfx950) implementation of the SGTP planning step.
+//
+// Hot path: one Jacobi sweep of sampled best responses (Alg. 1, Sec. III).  One
+// lane owns one sample for the whole horizon: its vehicle state, cost
+// accumulators, boundary clearance and per-opponent clearances live in VGPRs;
+// the nominal sequence, reference states, the opponents' footprint trajectories
+// and a window of the raceline are staged in LDS per workgroup; perturbations
+// come from an in-register Philox4x32-10 stream; the argmin over samples is a
+// 64-bit key reduced with DPP row operations and readlane, then one global
+// atomic per wave.  No sample trajectory is written: the selected sample is
+// re-rolled by one lane (same device code, same inputs, same bits).
+//
+// Kernels of one planning step:
+//   k_setup   one workgroup per vehicle: global Frenet projection, unwrapped
+//             progress, local frame, reference states, raceline window.
+//   k_single  NOMINAL mode, one lane per vehicle: noise-free rollout of the
+//             nominal sequence (initial predictions).
+//   k_sweep   every sample of every participating vehicle -> selection keys.
+//   k_single  WINNER mode: re-roll k* -> new nominal, prediction, trajectory, choice.
+//   k_apply   first control out, warm start shifted.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sgtp.h"
+
+namespace {
+
+constexpr int BLOCK = 256;
+constexpr int SINGLE_BLOCK = 64;
+constexpr int MAX_TRACKS = 64;
+constexpr int WIN_BACK = 48;    // raceline nodes kept behind the current segment
+constexpr int WIN_MAX = 1536;   // window nodes per vehicle (workspace bound)
+constexpr int PRED_STRIDE = 8;  // x, y, cos psi, sin psi, s_rel, d, -, - in the owner's frame
+constexpr int NODE_STRIDE = 10; // device node row: x, y, psi, nx, ny, wL, wR, vref, s, kappa
+constexpr unsigned long long KEY_NONE = ~0ull;
+
+enum Mode { SWEEP = 0, WINNER = 1, NOMINAL = 2 };
+
+// ------------------------------------------------------------------------------
+// Kernel-side parameters (float32 with derived constants folded in)
+// ------------------------------------------------------------------------------
+struct KParams {
+    int model, n_disc, max_moves, pad0;
+    float dt, half_dt, dt6;
+    float a_min, a_max, d_min, d_max, sigma_a, sigma_d;
+    float Q0, Q1, Q2, Q3, R0, R1, S0, S1;
+    float w_game, w_contest, w_long, w_block, w_safety, s_contest, s_role, eps_alpha;
+    float g_safe, m_bd, d_col, cap2, skip2;
+    float off[4];
+    float lf, lr, inv_m, inv_Iz, muFzf, muFzr, B, C, v_eps;  // dynamic single-track
+    float lr_over_L, inv_lr;                                 // kinematic bicycle
+};
+
+struct TrackDev {
+    const double *nodes;  // [n][NODE_STRIDE]
+    int n, closed;
+    double length, psi_lap, ds_min, inner_factor;
+};
+
+struct RaceDev {
+    int n_agents, ego, N, n_tail, track, slot0, K, pad0;
+    unsigned long long seed;
+    unsigned int plan_step, pad1;
+    double *x;
+    double *s_abs;
+    const float *v_scale;
+    float *u_nom;
+    double *traj;
+};
+
+struct ItemDev {  // one best response (race, vehicle) of a launch
+    int race, agent, slot, tile0;
+};
+
+struct AgentRec {  // per vehicle, written by k_setup
+    double ox, oy, psi0, c0, s0, s_abs, d0;
+    long long seg_abs, win0;
+    int win_n, seg_loc;
+    float vx, vy, om, lam;
+};
+
+struct LdsLayout {  // byte offsets of the staged tables, identical for every block of a launch
+    int ubar, xref, oppT, oppc, opp, nodes, total;
+    int n_opp_max, w_max, N_max;
+};
+
+struct LaunchArgs {
+    KParams P;
+    LdsLayout L;
+    const TrackDev *tracks;
+    const RaceDev *races;
+    const ItemDev *items;
+    int n_items, n_tiles, spl, phase;
+    AgentRec *agents;
+    const float4 *win;     // [slot][WIN_MAX][2]
+    const float4 *xref;    // [slot][N_max]
+    const float *pred_in;  // [slot][N_max+1][PRED_STRIDE]
+    float *pred_out;
+    unsigned long long *keys;
+    int *nfeas;
+    // WINNER outputs
+    sgtp_choice *choice;   // indexed by slot - choice_base, or NULL
+    int choice_base;
+    int adopt;             // write u_nom / traj
+    // debug outputs of k_sweep (indexed by sample), or NULL
+    float *dbg_cost;
+    unsigned char *dbg_flags;
+    float *dbg_viol;
+    double *dbg_xfinal;
+    float *dbg_noise;
+};
+
+// ------------------------------------------------------------------------------
+// Noise: Philox4x32-10 and the float32 Box-Muller transform
+// ------------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+                       (uint32_t)p0);
+    }
+    return c;
+}
+
+// Gaussian pair from two 32-bit words.  The float32 operation sequence is fixed
+// (IEEE round-to-nearest add, mul, fma, div, sqrt; no contraction), so the
+// perturbations are reproducible bit for bit on any IEEE-conforming device.
+__device__ __forceinline__ float2 gauss_pair(uint32_t r_even, uint32_t r_odd) {
+#pragma clang fp contract(off)
+    const float L3 = 0x1.555556p-1f, L5 = 0x1.99999ap-2f, L7 = 0x1.24924ap-2f;
+    const float L9 = 0x1.c71c72p-3f, L11 = 0x1.745d18p-3f, L13 = 0x1.3b13b2p-3f;
+    const float LN2_HI = 0x1.62e4p-1f, LN2_LO = 0x1.7f7d1cp-20f, SQRT2 = 0x1.6a09e6p+0f;
+    const float S1 = 0x1.921fb6p+2f, S3 = -0x1.4abbcep+5f, S5 = 0x1.466bc6p+6f;
+    const float S7 = -0x1.32d2ccp+6f, S9 = 0x1.507834p+5f;
+    const float C2 = -0x1.3bd3ccp+4f, C4 = 0x1.03c1f0p+6f, C6 = -0x1.55d3c8p+6f;
+    const float C8 = 0x1.e1f506p+5f, C10 = -0x1.a6d1f2p+4f;
+    // radius sqrt(-2 ln u1), u1 = (2*(r_even >> 9) + 1) 2^-24, ln by exponent split + atanh series
+    const float u1 = (float)(2u * (r_even >> 9) + 1u) * 0x1p-24f;
+    const uint32_t b = __float_as_uint(u1);
+    int e = (int)((b >> 23) & 0xffu) - 127;
+    float m = __uint_as_float((b & 0x7fffffu) | 0x3f800000u);
+    if (m > SQRT2) {
+        m = m * 0.5f;
+        e = e + 1;
+    }
+    const float f = m - 1.0f;
+    const float z = f / (m + 1.0f);
+    const float w = z * z;
+    float p = __builtin_fmaf(L13, w, L11);
+    p = __builtin_fmaf(p, w, L9);
+    p = __builtin_fmaf(p, w, L7);
+    p = __builtin_fmaf(p, w, L5);
+    p = __builtin_fmaf(p, w, L3);
+    p = p * w;
+    const float lnm = __builtin_fmaf(z, p, z + z);
+    const float ef = (float)e;
+    const float lnu = __builtin_fmaf(ef, LN2_HI, __builtin_fmaf(ef, LN2_LO, lnm));
+    const float rho = __builtin_sqrtf(-2.0f * lnu);
+    // angle 2 pi u2, u2 = (r_odd >> 8) 2^-24: exact quarter-turn split, Taylor polynomials
+    const uint32_t j = r_odd >> 8;
+    const uint32_t q = (j + (1u << 21)) >> 22;
+    const int32_t ri = (int32_t)j - (int32_t)(q << 22);
+    const float r = (float)ri * 0x1p-24f;
+    const float r2 = r * r;
+    float ps = __builtin_fmaf(S9, r2, S7);
+    ps = __builtin_fmaf(ps, r2, S5);
+    ps = __builtin_fmaf(ps, r2, S3);
+    ps = __builtin_fmaf(ps, r2, S1);
+    const float sn = ps * r;
+    float pc = __builtin_fmaf(C10, r2, C8);
+    pc = __builtin_fmaf(pc, r2, C6);
+    pc = __builtin_fmaf(pc, r2, C4);
+    pc = __builtin_fmaf(pc, r2, C2);
+    const float cs = __builtin_fmaf(pc, r2, 1.0f);
+    const uint32_t qq = q & 3u;
+    const float sin_t = (qq == 0) ? sn : (qq == 1) ? cs : (qq == 2) ? -sn : -cs;
+    const float cos_t = (qq == 0) ? cs : (qq == 1) ? -sn : (qq == 2) ? -cs : sn;
+    return make_float2(rho * cos_t, rho * sin_t);
+}
+
+// ------------------------------------------------------------------------------
+// Elementary functions for the vehicle model
+// ------------------------------------------------------------------------------
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// atan: odd polynomial fitted on [0, 1] (max error 3.3e-7), reflected via pi/2 - atan(1/x)
+__device__ __forceinline__ float fast_atan(float x) {
+    const float ax = fabsf(x);
+    const bool inv = ax > 1.0f;
+    const float t = inv ? fast_rcp(ax) : ax;
+    const float t2 = t * t;
+    float p = 0x1.be6b36p-8f;
+    p = __builtin_fmaf(p, t2, -0x1.134946p-5f);
+    p = __builtin_fmaf(p, t2, 0x1.46238ap-4f);
+    p = __builtin_fmaf(p, t2, -0x1.0f04d8p-3f);
+    p = __builtin_fmaf(p, t2, 0x1.95aa02p-3f);
+    p = __builtin_fmaf(p, t2, -0x1.552b7cp-2f);
+    p = __builtin_fmaf(p, t2, 0x1.ffff7ep-1f);
+    float r = p * t;
+    r = inv ? (1.57079637f - r) : r;
+    return copysignf(r, x);
+}
+
+// sin/cos through the transcendental unit (argument in revolutions)
+__device__ __forceinline__ float fast_sin(float x) { return __builtin_amdgcn_sinf(x * 0.159154943f); }
+__device__ __forceinline__ float fast_cos(float x) { return __builtin_amdgcn_cosf(x * 0.159154943f); }
+
+struct MathF32 {
+    using T = float;
+    static __device__ __forceinline__ T atan_(T x) { return fast_atan(x); }
+    static __device__ __forceinline__ T sin_(T x) { return fast_sin(x); }
+    static __device__ __forceinline__ T cos_(T x) { return fast_cos(x); }
+    static __device__ __forceinline__ T rcp_(T x) { return fast_rcp(x); }
+};
+
+struct MathF64 {
+    using T = double;
+    static __device__ __forceinline__ T atan_(T x) { return ::atan(x); }
+    static __device__ __forceinline__ T sin_(T x) { return ::sin(x); }
+    static __device__ __forceinline__ T cos_(T x) { return ::cos(x); }
+    static __device__ __forceinline__ T rcp_(T x) { return 1.0 / x; }
+};
+
+template <typename T>
+struct VehConst {
+    T lf, lr, inv_m, inv_Iz, muFzf, muFzr, B, C, v_eps, lr_over_L, inv_lr;
+};
+
+// Per control interval: functions of the held control (a, delta).
+template <typename T>
+struct StepConst {
+    T a, delta, sd, cd;  // dynamic: delta, sin delta, cos delta
+    T kc, ks, kw;        // kinematic: cos beta, sin beta, sin(beta)/l_r
+};
+
+template <int MODEL, class M>
+__device__ __forceinline__ StepConst<typename M::T> step_const(const VehConst<typename M::T> &V, typename M::T a,
+                                                                 typename M::T delta) {
+    using T = typename M::T;
+    StepConst<T> c;
+    c.a = a;
+    c.delta = delta;
+    if (MODEL == 0) {
+        c.sd = M::sin_(delta);
+        c.cd = M::cos_(delta);
+        c.kc = c.ks = c.kw = T(0);
+    } else {
+        const T beta = M::atan_(V.lr_over_L * (M::sin_(delta) * M::rcp_(M::cos_(delta))));
+        c.kc = M::cos_(beta);
+        c.ks = M::sin_(beta);
+        c.kw = c.ks * V.inv_lr;
+        c.sd = c.cd = T(0);
+    }
+    return c;
+}
+
+// Vehicle model f (Sec. II).  MODEL 0: dynamic single-track with
+// F_y = mu F_z sin(C atan(B alpha)); MODEL 1: kinematic bicycle at the CoG.
+// Position rates use max(v_x, 0), so no stage of RK4 moves the car backwards.
+template <int MODEL, class M>
+__device__ __forceinline__ void deriv(const VehConst<typename M::T> &V, const StepConst<typename M::T> &c,
+                                      typename M::T psi, typename M::T vx_, typename M::T vy, typename M::T om,
+                                      typename M::T d[6]) {
+    using T = typename M::T;
+    const T vx = vx_ > T(0) ? vx_ : T(0);
+    const T cp = M::cos_(psi), sp = M::sin_(psi);
+    if (MODEL == 0) {
+        const T inv_vh = M::rcp_(vx > V.v_eps ? vx : V.v_eps);
+        const T alpha_f = c.delta - M::atan_((vy + V.lf * om) * inv_vh);
+        const T alpha_r = -M::atan_((vy - V.lr * om) * inv_vh);
+        const T Fyf = V.muFzf * M::sin_(V.C * M::atan_(V.B * alpha_f));
+        const T Fyr = V.muFzr * M::sin_(V.C * M::atan_(V.B * alpha_r));
+        d[0] = vx * cp - vy * sp;
+        d[1] = vx * sp + vy * cp;
+        d[2] = om;
+        d[3] = c.a - Fyf * c.sd * V.inv_m + vy * om;
+        d[4] = (Fyr + Fyf * c.cd) * V.inv_m - vx * om;
+        d[5] = (V.lf * Fyf * c.cd - V.lr * Fyr) * V.inv_Iz;
+    } else {
+        d[0] = vx * (cp * c.kc - sp * c.ks);
+        d[1] = vx * (sp * c.kc + cp * c.ks);
+        d[2] = vx * c.kw;
+        d[3] = c.a;
+        d[4] = T(0);
+        d[5] = T(0);
+    }
+}
+
+// Classic RK4 over one interval with the control held, then v_x <- max(v_x, 0).
+template <int MODEL, class M>
+__device__ __forceinline__ void rk4(const VehConst<typename M::T> &V, const StepConst<typename M::T> &c,
+                                    typename M::T h, typename M::T s[6]) {
+    using T = typename M::T;
+    T k1[6], k2[6], k3[6], k4[6];
+    const T hh = T(0.5) * h;
+    deriv<MODEL, M>(V, c, s[2], s[3], s[4], s[5], k1);
+    deriv<MODEL, M>(V, c, s[2] + hh * k1[2], s[3] + hh * k1[3], s[4] + hh * k1[4], s[5] + hh * k1[5], k2);
+    deriv<MODEL, M>(V, c, s[2] + hh * k2[2], s[3] + hh * k2[3], s[4] + hh * k2[4], s[5] + hh * k2[5], k3);
+    deriv<MODEL, M>(V, c, s[2] + h * k3[2], s[3] + h * k3[3], s[4] + h * k3[4], s[5] + h * k3[5], k4);
+    const T h6 = h / T(6);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) s[i] = s[i] + h6 * (k1[i] + T(2) * k2[i] + T(2) * k3[i] + k4[i]);
+    if (!(s[3] > T(0)) && s[3] == s[3]) s[3] = T(0);
+}
+
+__device__ __forceinline__ VehConst<float> veh_f32(const KParams &P) {
+    VehConst<float> V;
+    V.lf = P.lf; V.lr = P.lr; V.inv_m = P.inv_m; V.inv_Iz = P.inv_Iz; V.muFzf = P.muFzf; V.muFzr = P.muFzr;
+    V.B = P.B; V.C = P.C; V.v_eps = P.v_eps; V.lr_over_L = P.lr_over_L; V.inv_lr = P.inv_lr;
+    return V;
+}
+
+// Pi_U: box clip; a NaN stays NaN so that the sample is flagged non-finite
+__device__ __forceinline__ float clip_keep_nan(float v, float lo, float hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// ------------------------------------------------------------------------------
+// Frenet projection on the staged raceline window (normal-interpolated polyline)
+// ------------------------------------------------------------------------------
+// Node in LDS: A = (x, y, nx, ny), B = (wL, wR, s_rel, 0), local frame.
+__device__ __forceinline__ float ahead_of(const float4 A, float X, float Y) { return (X - A.x) * A.w - (Y - A.y) * A.z; }
+
+struct Foot {
+    float s, d, wL, wR;
+    int seg;
+    bool limit;
+};
+
+// Segment search from `seg` (at most max_moves moves, inside the window), then the
+// foot t solving cross(p - c(t), n(t)) = 0 with the stable quadratic root.
+__device__ __forceinline__ Foot project(const float4 *__restrict__ nodes, int W, int max_moves, float X, float Y,
+                                        int seg) {
+    int moves = 0;
+    float4 A0 = nodes[2 * seg], A1 = nodes[2 * seg + 2];
+    float g1 = ahead_of(A1, X, Y);
+    float g0;
+    bool fwd = false;
+    while (moves < max_moves && seg + 1 <= W - 2 && g1 > 0.0f) {
+        ++seg;
+        ++moves;
+        A0 = A1;
+        A1 = nodes[2 * seg + 2];
+        g0 = g1;
+        g1 = ahead_of(A1, X, Y);
+        fwd = true;
+    }
+    if (!fwd) g0 = ahead_of(A0, X, Y);
+    while (moves < max_moves && seg > 0 && g0 < 0.0f) {
+        --seg;
+        ++moves;
+        A1 = A0;
+        g1 = g0;
+        A0 = nodes[2 * seg];
+        g0 = ahead_of(A0, X, Y);
+    }
+    Foot f;
+    f.seg = seg;
+    f.limit = !(g0 >= 0.0f && g1 <= 0.0f);
+    const float rx = X - A0.x, ry = Y - A0.y;
+    const float Dx = A1.x - A0.x, Dy = A1.y - A0.y;
+    const float dnx = A1.z - A0.z, dny = A1.w - A0.w;
+    const float Cc = g0;
+    const float Bc = (rx * dny - ry * dnx) - (Dx * A0.w - Dy * A0.z);
+    const float Ac = -(Dx * dny - Dy * dnx);
+    const float disc = fmaxf(Bc * Bc - 4.0f * Ac * Cc, 0.0f);
+    const float den = -Bc - copysignf(__builtin_amdgcn_sqrtf(disc), Bc);
+    float t = (den != 0.0f) ? (2.0f * Cc) * fast_rcp(den) : 0.0f;
+    t = fminf(fmaxf(t, 0.0f), 1.0f);
+    const float cx = __builtin_fmaf(t, Dx, A0.x), cy = __builtin_fmaf(t, Dy, A0.y);
+    const float nx = __builtin_fmaf(t, dnx, A0.z), ny = __builtin_fmaf(t, dny, A0.w);
+    f.d = ((X - cx) * nx + (Y - cy) * ny) * __builtin_amdgcn_rsqf(nx * nx + ny * ny);
+    const float4 B0 = nodes[2 * seg + 1], B1 = nodes[2 * seg + 3];
+    f.s = __builtin_fmaf(t, B1.z - B0.z, B0.z);
+    f.wL = __builtin_fmaf(t, B1.x - B0.x, B0.x);
+    f.wR = __builtin_fmaf(t, B1.y - B0.y, B0.y);
+    return f;
+}
+
+// ------------------------------------------------------------------------------
+// Selection key: lexicographic (infeasible, value, k); value = cost if feasible,
+// total violation otherwise; float order mapped onto unsigned order.
+// ------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t float_order(float v) {
+    const uint32_t b = __float_as_uint(v);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ unsigned long long make_key(bool h, float v, uint32_t k) {
+    return ((unsigned long long)(h ? 0u : 1u) << 63) | ((unsigned long long)float_order(v) << 31) |
+           (unsigned long long)(k & 0x7fffffffu);
+}
+
+// Wave-wide minimum of a 64-bit key: DPP butterflies inside each row of 16 lanes
+// (quad permutes, half-row and row mirrors), then the four row minima by readlane.
+template <int CTRL>
+__device__ __forceinline__ void dpp_min_step(uint32_t &lo, uint32_t &hi) {
+    const uint32_t olo = (uint32_t)__builtin_amdgcn_update_dpp((int)0xffffffff, (int)lo, CTRL, 0xf, 0xf, false);
+    const uint32_t ohi = (uint32_t)__builtin_amdgcn_update_dpp((int)0xffffffff, (int)hi, CTRL, 0xf, 0xf, false);
+    const bool take = (ohi < hi) || (ohi == hi && olo < lo);
+    lo = take ? olo : lo;
+    hi = take ? ohi : hi;
+}
+
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    dpp_min_step<0xB1>(lo, hi);   // quad_perm [1,0,3,2]
+    dpp_min_step<0x4E>(lo, hi);   // quad_perm [2,3,0,1]
+    dpp_min_step<0x141>(lo, hi);  // row_half_mirror
+    dpp_min_step<0x140>(lo, hi);  // row_mirror
+    unsigned long long best = KEY_NONE;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint32_t rlo = (uint32_t)__builtin_amdgcn_readlane((int)lo, 16 * r);
+        const uint32_t rhi = (uint32_t)__builtin_amdgcn_readlane((int)hi, 16 * r);
+        const unsigned long long rv = ((unsigned long long)rhi << 32) | rlo;
+        best = rv < best ? rv : best;
+    }
+    return best;
+}
+
+// ------------------------------------------------------------------------------
+// Per-block staging into LDS (shared by the sweep and the single-lane kernels)
+// ------------------------------------------------------------------------------
+struct BlockState {
+    int slot, race, agent, N, n_tail, n_opp, W, seg0, K;
+    float vx0, vy0, om0, inv_n_tail, w_game;
+    uint32_t key0, key1, ctr2, ctr3;
+};
+
+template <int NDISC>
+__device__ void stage_block(const LaunchArgs &A, int item_idx, bool with_opp, int pred_in_stride_slot,
+                            BlockState &bs, char *lds) {
+    const KParams &P = A.P;
+    const LdsLayout &L = A.L;
+    const ItemDev it = A.items[item_idx];
+    const RaceDev R = A.races[it.race];
+    const AgentRec me = A.agents[it.slot];
+    bs.slot = it.slot;
+    bs.race = it.race;
+    bs.agent = it.agent;
+    bs.N = R.N;
+    bs.n_tail = R.n_tail;
+    bs.K = R.K;
+    bs.n_opp = with_opp ? R.n_agents - 1 : 0;
+    bs.W = me.win_n;
+    bs.seg0 = me.seg_loc;
+    bs.vx0 = me.vx;
+    bs.vy0 = me.vy;
+    bs.om0 = me.om;
+    bs.inv_n_tail = 1.0f / (float)R.n_tail;
+    bs.w_game = (A.phase == 0) ? 0.0f : P.w_game;
+    bs.key0 = (uint32_t)R.seed;
+    bs.key1 = (uint32_t)(R.seed >> 32);
+    bs.ctr2 = (uint32_t)it.agent | ((uint32_t)A.phase << 16);
+    bs.ctr3 = R.plan_step;
+
+    const int tid = threadIdx.x, nth = blockDim.x;
+    float2 *ubar = (float2 *)(lds + L.ubar);
+    float4 *xref = (float4 *)(lds + L.xref);
+    float4 *nodes = (float4 *)(lds + L.nodes);
+    const float2 *un = (const float2 *)(R.u_nom) + (size_t)it.agent * R.N;
+    for (int t = tid; t < R.N; t += nth) ubar[t] = un[t];
+    const float4 *xr = A.xref + (size_t)it.slot * L.N_max;
+    for (int t = tid; t < R.N; t += nth) xref[t] = xr[t];
+    const float4 *wn = A.win + (size_t)it.slot * WIN_MAX * 2;
+    for (int t = tid; t < 2 * me.win_n; t += nth) nodes[t] = wn[t];
+
+    if (bs.n_opp > 0) {
+        float4 *oppT = (float4 *)(lds + L.oppT);
+        float4 *oppc = (float4 *)(lds + L.oppc);
+        float2 *opp = (float2 *)(lds + L.opp);
+        if (tid < bs.n_opp) {
+            const int j = tid < it.agent ? tid : tid + 1;
+            const int sj = R.slot0 + j;
+            const AgentRec o = A.agents[sj];
+            // frame j -> frame i: p_i = Rot(psi_j - psi_i) p_j + Rot(-psi_i) (O_j - O_i)
+            const double dpsi = o.psi0 - me.psi0;
+            const double dx = o.ox - me.ox, dy = o.oy - me.oy;
+            oppT[tid] = make_float4((float)cos(dpsi), (float)sin(dpsi), (float)(me.c0 * dx + me.s0 * dy),
+                                    (float)(-me.s0 * dx + me.c0 * dy));
+            const float *pj = A.pred_in + (size_t)sj * pred_in_stride_slot;
+            float dsum = 0.0f;
+            for (int t = R.N - R.n_tail + 1; t <= R.N; ++t) dsum += pj[t * PRED_STRIDE + 5];
+            const double ds0 = me.s_abs - o.s_abs;
+            const double alpha = 1.0 / (1.0 + fabs(ds0) / ((double)P.s_contest + (double)P.eps_alpha));
+            const float gam = (ds0 > (double)P.s_role && ds0 < (double)P.s_contest) ? P.w_block : 0.0f;
+            const float sN = (float)((o.s_abs - me.s_abs) + (double)pj[R.N * PRED_STRIDE + 4]);
+            oppc[tid] = make_float4(sN, dsum / (float)R.n_tail, (float)((double)P.w_long * alpha), gam);
+        }
+        __syncthreads();
+        const int total = R.N * bs.n_opp;
+        for (int e = tid; e < total; e += nth) {
+            const int t = e / bs.n_opp + 1;  // tau = 1..N
+            const int jo = e - (t - 1) * bs.n_opp;
+            const int j = jo < it.agent ? jo : jo + 1;
+            const float *pr = A.pred_in + (size_t)(R.slot0 + j) * pred_in_stride_slot + t * PRED_STRIDE;
+            const float4 T = oppT[jo];
+            const float px = pr[0], py = pr[1], pc = pr[2], psn = pr[3];
+            float2 *dst = opp + ((size_t)(t - 1) * L.n_opp_max + jo) * (NDISC + 1);
+            dst[0] = make_float2(T.x * px - T.y * py + T.z, T.y * px + T.x * py + T.w);
+#pragma unroll
+            for (int b = 0; b < NDISC; ++b) {
+                const float cxj = __builtin_fmaf(P.off[b], pc, px), cyj = __builtin_fmaf(P.off[b], psn, py);
+                dst[1 + b] = make_float2(T.x * cxj - T.y * cyj + T.z, T.y * cxj + T.x * cyj + T.w);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------------------
+// One sample: perturb, clip, roll out, score, check (Sec. III-A, III-B)
+// ------------------------------------------------------------------------------
+struct SampleResult {
+    float cost, viol;
+    bool h;
+    unsigned char flags;
+    float X, Y, PSI, VX, VY, OM;
+};
+
+struct SinkPtrs {  // per-step outputs of the single-lane modes (global memory)
+    float *pred;   // [N+1][PRED_STRIDE]
+    float2 *u;     // [N] adopted controls
+    double *traj;  // [N+1][8] world, or NULL
+    float *noise;  // [N][2] drawn perturbations (sweep debug), or NULL
+    const AgentRec *rec;
+};
+
+template <int MODEL, int NDISC, int MAXOPP, int MODE>
+__device__ __forceinline__ SampleResult eval_sample(const KParams &P, const BlockState &bs, const char *lds,
+                                                   const LdsLayout &L, uint32_t k, const SinkPtrs *sink) {
+    const float2 *ubar = (const float2 *)(lds + L.ubar);
+    const float4 *xref = (const float4 *)(lds + L.xref);
+    const float4 *oppc = (const float4 *)(lds + L.oppc);
+    const float2 *opp = (const float2 *)(lds + L.opp);
+    const float4 *nodes = (const float4 *)(lds + L.nodes);
+    const VehConst<float> V = veh_f32(P);
+
+    float st[6] = {0.0f, 0.0f, 0.0f, bs.vx0, bs.vy0, bs.om0};
+    int seg = bs.seg0;
+    float J = 0.0f, rho_bd = INFINITY, dsum = 0.0f, s = 0.0f;
+    float g2[MAXOPP];
+#pragma unroll
+    for (int j = 0; j < MAXOPP; ++j) g2[j] = P.cap2;
+    float pa = 0.0f, pd = 0.0f;
+    bool limit = false;
+    float2 zn = make_float2(0.0f, 0.0f);  // perturbation of the odd step of a Philox pair
+    if (MODE != SWEEP) {
+        float *pr = sink->pred;
+        pr[0] = 0.0f; pr[1] = 0.0f; pr[2] = 1.0f; pr[3] = 0.0f; pr[4] = 0.0f; pr[5] = (float)sink->rec->d0;
+        if (sink->traj) {
+            const AgentRec &a = *sink->rec;
+            double *o = sink->traj;
+            o[0] = a.ox; o[1] = a.oy; o[2] = a.psi0; o[3] = bs.vx0; o[4] = bs.vy0; o[5] = bs.om0;
+            o[6] = a.s_abs; o[7] = a.d0;
+        }
+    }
+
+    for (int tau = 0; tau < bs.N; ++tau) {
+        float za = 0.0f, zd = 0.0f;
+        if (MODE != NOMINAL) {
+            if ((tau & 1) == 0) {
+                const uint4 r = philox4x32_10(make_uint4(k, (uint32_t)(tau >> 1), bs.ctr2, bs.ctr3), bs.key0, bs.key1);
+                const float2 z0 = gauss_pair(r.x, r.y);
+                zn = gauss_pair(r.z, r.w);
+                za = z0.x;
+                zd = z0.y;
+            } else {
+                za = zn.x;
+                zd = zn.y;
+            }
+            if (sink->noise) {
+                sink->noise[2 * tau] = za;
+                sink->noise[2 * tau + 1] = zd;
+            }
+        }
+        const float2 ub = ubar[tau];
+        const float ua = clip_keep_nan(__builtin_fmaf(P.sigma_a, za, ub.x), P.a_min, P.a_max);
+        const float ud = clip_keep_nan(__builtin_fmaf(P.sigma_d, zd, ub.y), P.d_min, P.d_max);
+        const StepConst<float> sc = step_const<MODEL, MathF32>(V, ua, ud);
+        rk4<MODEL, MathF32>(V, sc, P.dt, st);
+        const Foot f = project(nodes, bs.W, P.max_moves, st[0], st[1], seg);
+        seg = f.seg;
+        limit |= f.limit;
+        s = f.s;
+
+        // tracking and control cost, eq. (ctrack)
+        const float4 xr = xref[tau];
+        const float ex = st[0] - xr.x, ey = st[1] - xr.y, ev = st[3] - xr.w;
+        float ep = st[2] - xr.z;
+        ep = ep - 6.28318531f * rintf(ep * 0.159154943f);
+        J += P.Q0 * ex * ex + P.Q1 * ey * ey + P.Q2 * ep * ep + P.Q3 * ev * ev;
+        J += P.R0 * ua * ua + P.R1 * ud * ud;
+        if (tau >= 1) {
+            const float da = ua - pa, dd = ud - pd;
+            J += P.S0 * da * da + P.S1 * dd * dd;
+        }
+        pa = ua;
+        pd = ud;
+        // boundary clearance, eq. (selection-boundary)
+        rho_bd = fminf(rho_bd, fminf(f.wR + f.d, f.wL - f.d));
+        // footprint distance to each opponent at the same step, eq. (Dmin); only values
+        // below cap = max(g_safe, d_col) change any cost, flag or violation
+        if (MODE != NOMINAL) {
+            float ch = 1.0f, sh = 0.0f;
+            if (NDISC > 1) {
+                ch = fast_cos(st[2]);
+                sh = fast_sin(st[2]);
+            }
+#pragma unroll
+            for (int j = 0; j < MAXOPP; ++j) {
+                if (j < bs.n_opp) {
+                    const float2 *e = opp + ((size_t)tau * L.n_opp_max + j) * (NDISC + 1);
+                    const float2 cg = e[0];
+                    const float dx = st[0] - cg.x, dy = st[1] - cg.y;
+                    if (dx * dx + dy * dy < P.skip2) {
+                        float m2 = g2[j];
+#pragma unroll
+                        for (int a = 0; a < NDISC; ++a) {
+                            const float ax = __builtin_fmaf(P.off[a], ch, st[0]);
+                            const float ay = __builtin_fmaf(P.off[a], sh, st[1]);
+#pragma unroll
+                            for (int b = 0; b < NDISC; ++b) {
+                                const float2 c = e[1 + b];
+                                const float qx = ax - c.x, qy = ay - c.y;
+                                m2 = fminf(m2, qx * qx + qy * qy);
+                            }
+                        }
+                        g2[j] = m2;
+                    }
+                }
+            }
+        }
+        if (tau + 1 > bs.N - bs.n_tail) dsum += f.d;
+
+        if (MODE != SWEEP) {
+            float *pr = sink->pred + (tau + 1) * PRED_STRIDE;
+            pr[0] = st[0]; pr[1] = st[1]; pr[2] = fast_cos(st[2]); pr[3] = fast_sin(st[2]);
+            pr[4] = f.s; pr[5] = f.d;
+            if (sink->u) sink->u[tau] = make_float2(ua, ud);
+            if (sink->traj) {
+                const AgentRec &a = *sink->rec;
+                double *o = sink->traj + (size_t)(tau + 1) * 8;
+                const double X = st[0], Y = st[1];
+                o[0] = a.ox + a.c0 * X - a.s0 * Y;
+                o[1] = a.oy + a.s0 * X + a.c0 * Y;
+                o[2] = a.psi0 + (double)st[2];
+                o[3] = st[3]; o[4] = st[4]; o[5] = st[5];
+                o[6] = a.s_abs + (double)f.s;
+                o[7] = f.d;
+            }
+        }
+    }
+
+    // game-aware cost, eqs. (game_cost), (c_contest), (c_long), (c_block), (c_safety)
+    float cgame = 0.0f, rho_obs = INFINITY;
+    const float dbar_i = dsum * bs.inv_n_tail;
+#pragma unroll
+    for (int j = 0; j < MAXOPP; ++j) {
+        if (j < bs.n_opp) {
+            const float4 c = oppc[j];  // (s_hat_N - s_i, dbar_j, w_long alpha_ij, gamma_ij)
+            const float dsN = s - c.x;
+            const float cc = (fabsf(dsN) < P.s_contest) ? -P.w_contest : 0.0f;
+            const float cl = -c.z * dsN;
+            const float cb = -c.w / (1.0f + fabsf(dbar_i - c.y));
+            const float gj = __builtin_sqrtf(g2[j]);
+            const float shv = fmaxf(0.0f, P.g_safe - gj);
+            cgame += cc + cl + cb + P.w_safety * shv * shv;
+            rho_obs = fminf(rho_obs, gj);
+        }
+    }
+    const float c = J + bs.w_game * cgame;  // eq. (allc)
+    bool finite = isfinite(c) && !isnan(rho_bd) && !isnan(rho_obs);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) finite = finite && isfinite(st[i]);
+    const bool b = finite && rho_bd >= P.m_bd;
+    const bool o = finite && rho_obs >= P.d_col;
+    SampleResult res;
+    res.h = b && o;
+    res.cost = c;
+    res.viol = finite ? fmaxf(0.0f, P.m_bd - rho_bd) + fmaxf(0.0f, P.d_col - rho_obs) : INFINITY;
+    res.flags = (unsigned char)((b ? 1 : 0) | (o ? 2 : 0) | (res.h ? 4 : 0) | (limit ? 8 : 0) | (finite ? 0 : 16));
+    res.X = st[0]; res.Y = st[1]; res.PSI = st[2]; res.VX = st[3]; res.VY = st[4]; res.OM = st[5];
+    return res;
+}
+
+// ------------------------------------------------------------------------------
+// Kernels
+// ------------------------------------------------------------------------------
+__device__ __forceinline__ int find_item(const ItemDev *items, int n, int tile) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int MODEL, int NDISC, int MAXOPP>
+__global__ void __launch_bounds__(BLOCK) k_sweep(LaunchArgs A) {
+    extern __shared__ __align__(16) char lds[];
+    const int tile = blockIdx.x;
+    const int item = find_item(A.items, A.n_items, tile);
+    BlockState bs;
+    stage_block<NDISC>(A, item, true, (A.L.N_max + 1) * PRED_STRIDE, bs, lds);
+    const int lane = threadIdx.x & 63;
+    const int local_tile = tile - A.items[item].tile0;
+    const bool dbg = A.dbg_cost || A.dbg_flags || A.dbg_viol || A.dbg_xfinal || A.dbg_noise;
+    for (int r = 0; r < A.spl; ++r) {
+        const uint32_t k = (uint32_t)((local_tile * A.spl + r) * BLOCK + threadIdx.x);
+        const bool valid = k < (uint32_t)bs.K;
+        SinkPtrs sk{};
+        sk.noise = (A.dbg_noise && valid) ? A.dbg_noise + (size_t)k * bs.N * 2 : nullptr;
+        const SampleResult res = eval_sample<MODEL, NDISC, MAXOPP, SWEEP>(A.P, bs, lds, A.L, valid ? k : 0u, &sk);
+        const unsigned long long key = valid ? make_key(res.h, res.h ? res.cost : res.viol, k) : KEY_NONE;
+        const unsigned long long wmin = wave_min_u64(key);
+        const unsigned long long feas = __ballot(valid && res.h);
+        if (lane == 0) {
+            if (wmin != KEY_NONE) atomicMin(A.keys + bs.slot, wmin);
+            const int cnt = __popcll(feas);
+            if (cnt) atomicAdd(A.nfeas + bs.slot, cnt);
+        }
+        if (dbg && valid) {
+            if (A.dbg_cost) A.dbg_cost[k] = res.cost;
+            if (A.dbg_viol) A.dbg_viol[k] = res.viol;
+            if (A.dbg_flags) A.dbg_flags[k] = res.flags;
+            if (A.dbg_xfinal) {
+                const AgentRec &a = A.agents[bs.slot];
+                double *o = A.dbg_xfinal + (size_t)k * 6;
+                const double X = res.X, Y = res.Y;
+                o[0] = a.ox + a.c0 * X - a.s0 * Y;
+                o[1] = a.oy + a.s0 * X + a.c0 * Y;
+                o[2] = a.psi0 + (double)res.PSI;
+                o[3] = res.VX; o[4] = res.VY; o[5] = res.OM;
+            }
+        }
+    }
+}
+
+// One lane re-rolls a single sample per vehicle: the nominal (NOMINAL) or the
+// selected one (WINNER), writing the prediction of the next sweep and, for the
+// winner, the adopted controls, the world trajectory and the choice record.
+template <int MODEL, int NDISC, int MAXOPP, int MODE>
+__global__ void __launch_bounds__(SINGLE_BLOCK) k_single(LaunchArgs A) {
+    extern __shared__ __align__(16) char lds[];
+    const int item = blockIdx.x;
+    BlockState bs;
+    stage_block<NDISC>(A, item, MODE == WINNER, (A.L.N_max + 1) * PRED_STRIDE, bs, lds);
+    if (threadIdx.x != 0) return;
+    const ItemDev it = A.items[item];
+    const RaceDev R = A.races[it.race];
+    uint32_t k = 0;
+    unsigned long long key = KEY_NONE;
+    if (MODE == WINNER) {
+        key = A.keys[bs.slot];
+        k = (uint32_t)(key & 0x7fffffffu);
+        if (k >= (uint32_t)bs.K) k = 0;
+    }
+    SinkPtrs sk{};
+    sk.pred = A.pred_out + (size_t)bs.slot * (A.L.N_max + 1) * PRED_STRIDE;
+    sk.rec = A.agents + bs.slot;
+    float2 *u_nom = (float2 *)(R.u_nom) + (size_t)it.agent * R.N;
+    if (MODE == WINNER && A.adopt) {
+        sk.u = u_nom;  // the staged copy in LDS is what this lane reads
+        sk.traj = R.traj ? R.traj + (size_t)it.agent * (R.N + 1) * 8 : nullptr;
+    }
+    const SampleResult res = eval_sample<MODEL, NDISC, MAXOPP, MODE>(A.P, bs, lds, A.L, k, &sk);
+    if (MODE == WINNER) {
+        if (A.choice) {
+            sgtp_choice c;
+            c.k = (int)k;
+            c.fallback = (key >> 63) ? 1 : 0;
+            c.n_feasible = A.nfeas[bs.slot];
+            c.cost = res.cost;
+            c.viol = res.viol;
+            A.choice[bs.slot - A.choice_base] = c;
+        }
+        A.keys[bs.slot] = KEY_NONE;
+        A.nfeas[bs.slot] = 0;
+    }
+}
+
+// Global projection of each vehicle's current state, local frame, reference
+// states (Sec. III-A: s^r recursion over v^r) and the raceline window.
+__global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
+    __shared__ double red_v[BLOCK];
+    __shared__ long long red_i[BLOCK];
+    __shared__ double sh[8];
+    __shared__ long long shl[4];
+    const ItemDev it = A.items[blockIdx.x];
+    const RaceDev R = A.races[it.race];
+    const TrackDev T = A.tracks[R.track];
+    const double *xs = R.x + (size_t)it.agent * 6;
+    const double px = xs[0], py = xs[1];
+    const int tid = threadIdx.x;
+    const long long n = T.n;
+    const long long nseg = T.closed ? n : n - 1;
+
+    auto node = [&](long long i, double *o) {  // unwrapped node access
+        long long lap = 0, b = i;
+        if (T.closed) {
+            lap = i / n;
+            if (i - lap * n < 0) --lap;
+            b = i - lap * n;
+        } else {
+            b = i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+        }
+        const double *r = T.nodes + (size_t)b * NODE_STRIDE;
+#pragma unroll
+        for (int c = 0; c < NODE_STRIDE; ++c) o[c] = r[c];
+        o[2] += (double)lap * T.psi_lap;
+        o[8] += (double)lap * T.length;
+    };
+    auto ahead = [&](long long i) {
+        double nd[NODE_STRIDE];
+        node(i, nd);
+        return (px - nd[0]) * nd[4] - (py - nd[1]) * nd[3];
+    };
+    // foot on segment i (float64, same construction as the lanes use in float32)
+    auto foot = [&](long long i, double *o /* s, d, t, wL, wR */) {
+        double a[NODE_STRIDE], b[NODE_STRIDE];
+        node(i, a);
+        node(i + 1, b);
+        const double rx = px - a[0], ry = py - a[1];
+        const double Dx = b[0] - a[0], Dy = b[1] - a[1];
+        const double dnx = b[3] - a[3], dny = b[4] - a[4];
+        const double Cc = rx * a[4] - ry * a[3];
+        const double Bc = (rx * dny - ry * dnx) - (Dx * a[4] - Dy * a[3]);
+        const double Ac = -(Dx * dny - Dy * dnx);
+        double disc = Bc * Bc - 4.0 * Ac * Cc;
+        if (disc < 0.0) disc = 0.0;
+        const double den = -Bc - copysign(sqrt(disc), Bc);
+        double t = (den != 0.0) ? 2.0 * Cc / den : 0.0;
+        if (!(t >= 0.0)) t = 0.0;
+        if (t > 1.0) t = 1.0;
+        const double cx = a[0] + t * Dx, cy = a[1] + t * Dy;
+        const double nx = a[3] + t * dnx, ny = a[4] + t * dny;
+        o[0] = a[8] + t * (b[8] - a[8]);
+        o[1] = ((px - cx) * nx + (py - cy) * ny) / sqrt(nx * nx + ny * ny);
+        o[2] = t;
+        o[3] = a[5] + t * (b[5] - a[5]);
+        o[4] = a[6] + t * (b[6] - a[6]);
+    };
+
+    // 1. global projection: smallest |d| among enclosing segments, lowest index on ties
+    double best = INFINITY;
+    long long bi = -1;
+    for (long long i = tid; i < nseg; i += BLOCK) {
+        if (ahead(i) >= 0.0 && ahead(i + 1) <= 0.0) {
+            double o[5];
+            foot(i, o);
+            const double ad = fabs(o[1]);
+            if (ad < best) {
+                best = ad;
+                bi = i;
+            }
+        }
+    }
+    red_v[tid] = best;
+    red_i[tid] = bi;
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            const double v2 = red_v[tid + w];
+            const long long i2 = red_i[tid + w];
+            if (i2 >= 0 && (red_i[tid] < 0 || v2 < red_v[tid] || (v2 == red_v[tid] && i2 < red_i[tid]))) {
+                red_v[tid] = v2;
+                red_i[tid] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    long long seg = red_i[0];
+    __syncthreads();
+    if (seg < 0) {  // no enclosing segment: the one starting at the nearest node
+        best = INFINITY;
+        bi = -1;
+        for (long long i = tid; i < nseg; i += BLOCK) {
+            double nd[NODE_STRIDE];
+            node(i, nd);
+            const double dd = (px - nd[0]) * (px - nd[0]) + (py - nd[1]) * (py - nd[1]);
+            if (dd < best) {
+                best = dd;
+                bi = i;
+            }
+        }
+        red_v[tid] = best;
+        red_i[tid] = bi;
+        __syncthreads();
+        for (int w = BLOCK / 2; w > 0; w >>= 1) {
+            if (tid < w) {
+                const double v2 = red_v[tid + w];
+                const long long i2 = red_i[tid + w];
+                if (i2 >= 0 && (red_i[tid] < 0 || v2 < red_v[tid] || (v2 == red_v[tid] && i2 < red_i[tid]))) {
+                    red_v[tid] = v2;
+                    red_i[tid] = i2;
+                }
+            }
+            __syncthreads();
+        }
+        seg = red_i[0];
+    }
+
+    // 2. unwrap progress, frame, window size, reference states (one thread)
+    if (tid == 0) {
+        double o[5];
+        foot(seg, o);
+        double s = o[0];
+        const double sp = R.s_abs[it.agent];
+        if (T.closed && isfinite(sp)) {
+            const double lap = rint((sp - s) / T.length);
+            seg += (long long)lap * n;
+            s += lap * T.length;
+        }
+        R.s_abs[it.agent] = s;
+        const double psi0 = xs[2];
+        const double c0 = cos(psi0), s0 = sin(psi0);
+        const double vx = xs[3] > 0.0 ? xs[3] : 0.0, vy = xs[4];
+        const double v = sqrt(vx * vx + vy * vy);
+        const double Th = (double)R.N * (double)A.P.dt;
+        const double reach = v * Th + 0.5 * (double)(A.P.a_max > 0.f ? A.P.a_max : 0.f) * Th * Th + 10.0;
+        long long W = WIN_BACK + (long long)ceil(T.inner_factor * reach / T.ds_min) + 8;
+        if (W > w_limit) W = w_limit;
+        long long win0 = seg - WIN_BACK;
+        if (!T.closed) {
+            if (win0 < 0) win0 = 0;
+            if (W > n - win0) W = n - win0;
+        }
+        AgentRec rec;
+        rec.ox = px; rec.oy = py; rec.psi0 = psi0; rec.c0 = c0; rec.s0 = s0;
+        rec.s_abs = s; rec.d0 = o[1];
+        rec.seg_abs = seg; rec.win0 = win0;
+        rec.win_n = (int)W; rec.seg_loc = (int)(seg - win0);
+        rec.vx = (float)xs[3]; rec.vy = (float)xs[4]; rec.om = (float)xs[5];
+        rec.lam = R.v_scale[it.agent];
+        A.agents[it.slot] = rec;
+        sh[0] = c0; sh[1] = s0; sh[2] = psi0; sh[3] = s;
+        shl[0] = win0; shl[1] = W;
+
+        // reference: s^r_{t+1} = s^r_t + dt lam v^r(s^r_t); x^r at s^r_{t+1} (linear interpolation)
+        float4 *xr = (float4 *)(A.xref + (size_t)it.slot * A.L.N_max);
+        const double lam = (double)rec.lam, dt = (double)A.P.dt;
+        long long hint = seg;
+        double sr = s;
+        double psi_shift = 0.0;
+        auto interp = [&](double sq, double *out /* x, y, psi, v */) {
+            for (int guard = 0; guard < 1 << 20; ++guard) {
+                double a[NODE_STRIDE], b[NODE_STRIDE];
+                node(hint, a);
+                node(hint + 1, b);
+                const bool can_back = T.closed || hint > 0;
+                const bool can_fwd = T.closed || hint + 1 <= n - 2;
+                if (sq < a[8] && can_back) { --hint; continue; }
+                if (sq >= b[8] && can_fwd) { ++hint; continue; }
+                double t = (sq - a[8]) / (b[8] - a[8]);
+                if (t < 0.0) t = 0.0;
+                if (t > 1.0) t = 1.0;
+                out[0] = a[0] + t * (b[0] - a[0]);
+                out[1] = a[1] + t * (b[1] - a[1]);
+                out[2] = a[2] + t * (b[2] - a[2]);
+                out[3] = a[7] + t * (b[7] - a[7]);
+                break;
+            }
+        };
+        for (int t = 0; t < R.N; ++t) {
+            double q[4];
+            interp(sr, q);
+            sr = sr + dt * lam * q[3];
+            interp(sr, q);
+            const double dx = q[0] - px, dy = q[1] - py;
+            double dpsi = q[2] - psi0;
+            if (t == 0) psi_shift = 6.283185307179586 * rint(dpsi / 6.283185307179586);
+            dpsi -= psi_shift;
+            xr[t] = make_float4((float)(c0 * dx + s0 * dy), (float)(-s0 * dx + c0 * dy), (float)dpsi,
+                                (float)(lam * q[3]));
+        }
+        A.keys[it.slot] = KEY_NONE;
+        A.nfeas[it.slot] = 0;
+    }
+    __syncthreads();
+
+    // 3. raceline window in the local frame: A = (x, y, nx, ny), B = (wL, wR, s - s_abs, 0)
+    const double c0 = sh[0], s0 = sh[1], psi0 = sh[2], sa = sh[3];
+    const long long win0 = shl[0], W = shl[1];
+    float4 *dst = (float4 *)(A.win + (size_t)it.slot * WIN_MAX * 2);
+    for (long long w = tid; w < W; w += BLOCK) {
+        double nd[NODE_STRIDE];
+        node(win0 + w, nd);
+        const double dx = nd[0] - px, dy = nd[1] - py;
+        // local normal = world normal rotated by -psi0
+        const double nxl = c0 * nd[3] + s0 * nd[4], nyl = -s0 * nd[3] + c0 * nd[4];
+        dst[2 * w] = make_float4((float)(c0 * dx + s0 * dy), (float)(-s0 * dx + c0 * dy), (float)nxl, (float)nyl);
+        dst[2 * w + 1] = make_float4((float)nd[5], (float)nd[6], (float)(nd[8] - sa), 0.0f);
+    }
+    (void)psi0;
+}
+
+// First control of the final plan, then the warm start: shift by one, repeat the last.
+__global__ void k_apply(const RaceDev *races, const ItemDev *items, int n_items, float2 *u_apply) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_items) return;
+    const ItemDev it = items[i];
+    const RaceDev R = races[it.race];
+    float2 *u = (float2 *)(R.u_nom) + (size_t)it.agent * R.N;
+    u_apply[i] = u[0];
+    for (int t = 0; t + 1 < R.N; ++t) u[t] = u[t + 1];
+}
+
+// Closed loop: one float64 RK4 interval per vehicle.
+template <int MODEL>
+__global__ void k_advance(const RaceDev *races, const ItemDev *items, int n_items, const float2 *u, VehConst<double> V,
+                          double dt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_items) return;
+    const ItemDev it = items[i];
+    const RaceDev R = races[it.race];
+    double *x = R.x + (size_t)it.agent * 6;
+    double s[6];
+    for (int c = 0; c < 6; ++c) s[c] = x[c];
+    const float2 ui = u[i];
+    const StepConst<double> sc = step_const<MODEL, MathF64>(V, (double)ui.x, (double)ui.y);
+    rk4<MODEL, MathF64>(V, sc, dt, s);
+    for (int c = 0; c < 6; ++c) x[c] = s[c];
+}
+
+}  // namespace
+
+// ==============================================================================
+// Host side: context, validation, launches, C ABI
+// ==============================================================================
+struct TrackHost {
+    double *d_nodes = nullptr;
+    int n = 0, closed = 0;
+    double length = 0, psi_lap = 0, ds_min = 0, vmax = 0, inner_factor = 1;
+};
+
+struct sgtp_ctx {
+    int device = 0;
+    int max_agents = 0, max_N = 0, max_races = 0, max_nodes = 0;
+    std::string err;
+    TrackHost tracks[MAX_TRACKS];
+    TrackDev *d_tracks = nullptr;
+    AgentRec *d_agents = nullptr;
+    float4 *d_win = nullptr;
+    float4 *d_xref = nullptr;
+    float *d_pred[2] = {nullptr, nullptr};
+    unsigned long long *d_keys = nullptr;
+    int *d_nfeas = nullptr;
+    // descriptor uploads: pinned ring, each slot guarded by an event
+    static constexpr int RING = 8;
+    char *h_stage[RING] = {};
+    hipEvent_t stage_ev[RING] = {};
+    bool stage_used[RING] = {};
+    int ring_pos = 0;
+    char *d_desc = nullptr;  // [RING][desc_bytes]
+    size_t desc_bytes = 0;
+    // instrumentation
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pairs;
+    std::vector<long long> ev_work;
+    double total_ms = 0;
+    long long launches = 0, sample_steps = 0;
+};
+
+namespace {
+
+int fail(sgtp_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) return fail(ctx, SGTP_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+KParams make_kparams(const sgtp_params *p) {
+    KParams k{};
+    k.model = p->model;
+    k.n_disc = p->n_disc;
+    k.max_moves = p->max_moves;
+    k.dt = p->dt;
+    k.half_dt = 0.5f * p->dt;
+    k.dt6 = p->dt / 6.0f;
+    k.a_min = p->a_min; k.a_max = p->a_max; k.d_min = p->d_min; k.d_max = p->d_max;
+    k.sigma_a = p->sigma_a; k.sigma_d = p->sigma_d;
+    k.Q0 = p->Q[0]; k.Q1 = p->Q[1]; k.Q2 = p->Q[2]; k.Q3 = p->Q[3];
+    k.R0 = p->R[0]; k.R1 = p->R[1]; k.S0 = p->S[0]; k.S1 = p->S[1];
+    k.w_game = p->w_game; k.w_contest = p->w_contest; k.w_long = p->w_long; k.w_block = p->w_block;
+    k.w_safety = p->w_safety; k.s_contest = p->s_contest; k.s_role = p->s_role; k.eps_alpha = p->eps_alpha;
+    k.g_safe = p->g_safe; k.m_bd = p->m_bd; k.d_col = p->d_col;
+    const double cap = std::max((double)p->g_safe, (double)p->d_col);
+    k.cap2 = (float)(cap * cap);
+    double offmax = 0;
+    for (int i = 0; i < 4; ++i) {
+        k.off[i] = (i < p->n_disc) ? p->disc_off[i] : 0.0f;
+        if (i < p->n_disc) offmax = std::max(offmax, (double)std::fabs(p->disc_off[i]));
+    }
+    // a pair of discs can only come closer than cap when the CoGs are within cap + 2 max|offset|
+    const double sk = cap + 2.0 * offmax + 1e-3;
+    k.skip2 = (float)(sk * sk);
+    const double L = (double)p->lf + (double)p->lr;
+    k.lf = p->lf; k.lr = p->lr;
+    k.inv_m = (float)(1.0 / p->m);
+    k.inv_Iz = (float)(1.0 / p->Iz);
+    k.muFzf = (float)((double)p->mu * p->m * p->g * p->lr / L);
+    k.muFzr = (float)((double)p->mu * p->m * p->g * p->lf / L);
+    k.B = p->B; k.C = p->C; k.v_eps = p->v_eps;
+    k.lr_over_L = (float)(p->lr / L);
+    k.inv_lr = (float)(1.0 / p->lr);
+    return k;
+}
+
+VehConst<double> make_veh64(const sgtp_params *p) {
+    VehConst<double> V;
+    const double L = (double)p->lf + (double)p->lr;
+    V.lf = p->lf; V.lr = p->lr; V.inv_m = 1.0 / p->m; V.inv_Iz = 1.0 / p->Iz;
+    V.muFzf = (double)p->mu * p->m * p->g * p->lr / L;
+    V.muFzr = (double)p->mu * p->m * p->g * p->lf / L;
+    V.B = p->B; V.C = p->C; V.v_eps = p->v_eps; V.lr_over_L = p->lr / L; V.inv_lr = 1.0 / p->lr;
+    return V;
+}
+
+int check_params(sgtp_ctx *c, const sgtp_params *p) {
+    if (!p) return fail(c, SGTP_EINVAL, "params is NULL");
+    if (p->model != 0 && p->model != 1) return fail(c, SGTP_EINVAL, "model must be 0 or 1");
+    if (p->n_disc != 1 && p->n_disc != 3) return fail(c, SGTP_EINVAL, "n_disc must be 1 or 3");
+    if (!(p->dt > 0.f) || !(p->a_min <= p->a_max) || !(p->d_min <= p->d_max))
+        return fail(c, SGTP_EINVAL, "bad dt or control bounds");
+    if (p->max_moves < 1 || p->max_moves > 1024) return fail(c, SGTP_EINVAL, "max_moves out of range");
+    if (!(p->m > 0.f) || !(p->Iz > 0.f) || !(p->lf > 0.f) || !(p->lr > 0.f) || !(p->v_eps > 0.f))
+        return fail(c, SGTP_EINVAL, "vehicle constants must be positive");
+    return SGTP_OK;
+}
+
+struct Plan {  // host image of one launch sequence's descriptors
+    std::vector<RaceDev> races;
+    std::vector<ItemDev> all, ego, one;
+    int N_max = 0, n_opp_max = 0, w_max = 0, agents_total = 0;
+    int tiles_all = 0, tiles_ego = 0;
+};
+
+int build_plan(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_races, int spl, Plan &pl,
+               int one_agent = -1) {
+    if (!races || n_races < 1) return fail(c, SGTP_EINVAL, "no races");
+    if (n_races > c->max_races) return fail(c, SGTP_ESHAPE, "n_races exceeds the context");
+    int slot = 0;
+    double wneed = 0;
+    for (int r = 0; r < n_races; ++r) {
+        const sgtp_race &s = races[r];
+        if (s.n_agents < 1 || s.n_agents > SGTP_MAX_AGENTS) return fail(c, SGTP_EINVAL, "n_agents out of range");
+        if (s.ego < 0 || s.ego >= s.n_agents) return fail(c, SGTP_EINVAL, "ego out of range");
+        if (s.N < 1 || s.N > SGTP_MAX_N) return fail(c, SGTP_EINVAL, "N out of range");
+        if (s.N > c->max_N) return fail(c, SGTP_ESHAPE, "N exceeds the context");
+        if (s.n_tail < 1 || s.n_tail > s.N) return fail(c, SGTP_EINVAL, "n_tail out of range");
+        if (s.K < 1 || s.K > SGTP_MAX_K) return fail(c, SGTP_EINVAL, "K out of range");
+        if (!s.x || !s.s_abs || !s.v_scale || !s.u_nom) return fail(c, SGTP_EINVAL, "null race array");
+        if (s.track_id < 0 || s.track_id >= MAX_TRACKS || !c->tracks[s.track_id].d_nodes)
+            return fail(c, SGTP_ETRACK, "unknown track id");
+        const TrackHost &T = c->tracks[s.track_id];
+        RaceDev d{};
+        d.n_agents = s.n_agents; d.ego = s.ego; d.N = s.N; d.n_tail = s.n_tail; d.track = s.track_id;
+        d.slot0 = slot; d.K = s.K; d.seed = s.seed; d.plan_step = s.plan_step;
+        d.x = s.x; d.s_abs = s.s_abs; d.v_scale = s.v_scale; d.u_nom = s.u_nom; d.traj = s.traj;
+        pl.races.push_back(d);
+        const int tiles = (s.K + BLOCK * spl - 1) / (BLOCK * spl);
+        for (int i = 0; i < s.n_agents; ++i) {
+            ItemDev it{r, i, slot + i, pl.tiles_all};
+            pl.tiles_all += tiles;
+            pl.all.push_back(it);
+            if (r == 0 && i == one_agent) {
+                ItemDev o = it;
+                o.tile0 = 0;
+                pl.one.push_back(o);
+            }
+            if (i == s.ego) {
+                ItemDev e = it;
+                e.tile0 = pl.tiles_ego;
+                pl.tiles_ego += tiles;
+                pl.ego.push_back(e);
+            }
+        }
+        slot += s.n_agents;
+        pl.N_max = std::max(pl.N_max, s.N);
+        pl.n_opp_max = std::max(pl.n_opp_max, s.n_agents - 1);
+        // window: reachable arc length at up to 1.2 v_ref,max + 5 m/s, inner-side factor, margins
+        const double Th = s.N * (double)p->dt;
+        const double vb = 1.2 * T.vmax + 5.0;
+        const double reach = vb * Th + 0.5 * std::max(0.0, (double)p->a_max) * Th * Th + 10.0;
+        wneed = std::max(wneed, WIN_BACK + std::ceil(T.inner_factor * reach / T.ds_min) + 8.0);
+    }
+    if (slot > c->max_agents) return fail(c, SGTP_ESHAPE, "total vehicles exceed the context");
+    pl.agents_total = slot;
+    pl.w_max = (int)std::min<double>(WIN_MAX, wneed);
+    return SGTP_OK;
+}
+
+LdsLayout make_layout(const Plan &pl, int maxopp, int ndisc) {
+    LdsLayout L{};
+    int off = 0;
+    auto take = [&](int bytes) {
+        const int o = off;
+        off += (bytes + 15) & ~15;
+        return o;
+    };
+    L.N_max = pl.N_max;
+    L.n_opp_max = std::max(1, maxopp);
+    L.w_max = pl.w_max;
+    L.ubar = take(pl.N_max * 8);
+    L.xref = take(pl.N_max * 16);
+    L.oppT = take(L.n_opp_max * 16);
+    L.oppc = take(L.n_opp_max * 16);
+    L.opp = take(pl.N_max * L.n_opp_max * (ndisc + 1) * 8);
+    L.nodes = take(pl.w_max * 32);
+    L.total = off;
+    return L;
+}
+
+int maxopp_bucket(int n_opp) {
+    if (n_opp <= 1) return 1;
+    if (n_opp <= 3) return 3;
+    if (n_opp <= 9) return 9;
+    return 15;
+}
+
+// Upload the descriptor image of a plan into a ring slot; returns device pointers.
+int upload_plan(sgtp_ctx *c, const Plan &pl, hipStream_t st, RaceDev **d_races, ItemDev **d_all, ItemDev **d_ego,
+                ItemDev **d_one = nullptr) {
+    const size_t nr = pl.races.size() * sizeof(RaceDev);
+    const size_t na = pl.all.size() * sizeof(ItemDev);
+    const size_t ne = pl.ego.size() * sizeof(ItemDev);
+    const size_t no = pl.one.size() * sizeof(ItemDev);
+    const size_t a0 = 0, a1 = (nr + 255) & ~size_t(255), a2 = a1 + ((na + 255) & ~size_t(255));
+    const size_t a3 = a2 + ((ne + 255) & ~size_t(255));
+    const size_t tot = a3 + no;
+    if (tot > c->desc_bytes) return fail(c, SGTP_ESHAPE, "descriptor image too large");
+    const int slot = c->ring_pos;
+    c->ring_pos = (c->ring_pos + 1) % sgtp_ctx::RING;
+    if (c->stage_used[slot]) HIPCHK(c, hipEventSynchronize(c->stage_ev[slot]));
+    char *h = c->h_stage[slot];
+    std::memcpy(h + a0, pl.races.data(), nr);
+    std::memcpy(h + a1, pl.all.data(), na);
+    if (ne) std::memcpy(h + a2, pl.ego.data(), ne);
+    if (no) std::memcpy(h + a3, pl.one.data(), no);
+    char *d = c->d_desc + (size_t)slot * c->desc_bytes;
+    HIPCHK(c, hipMemcpyAsync(d, h, tot, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipEventRecord(c->stage_ev[slot], st));
+    c->stage_used[slot] = true;
+    *d_races = (RaceDev *)(d + a0);
+    *d_all = (ItemDev *)(d + a1);
+    *d_ego = (ItemDev *)(d + a2);
+    if (d_one) *d_one = (ItemDev *)(d + a3);
+    return SGTP_OK;
+}
+
+template <int MODEL, int NDISC, int MAXOPP>
+void launch_sweep_t(const LaunchArgs &A, hipStream_t st) {
+    hipLaunchKernelGGL((k_sweep<MODEL, NDISC, MAXOPP>), dim3(A.n_tiles), dim3(BLOCK), A.L.total, st, A);
+}
+template <int MODEL, int NDISC, int MAXOPP, int MODE>
+void launch_single_t(const LaunchArgs &A, hipStream_t st) {
+    hipLaunchKernelGGL((k_single<MODEL, NDISC, MAXOPP, MODE>), dim3(A.n_items), dim3(SINGLE_BLOCK), A.L.total, st, A);
+}
+
+template <int MODEL, int NDISC>
+void dispatch_opp(int mo, int which, const LaunchArgs &A, hipStream_t st) {
+#define SGTP_CASE(MO)                                                           \
+    if (mo == MO) {                                                             \
+        if (which == 0) launch_sweep_t<MODEL, NDISC, MO>(A, st);                \
+        else if (which == 1) launch_single_t<MODEL, NDISC, MO, WINNER>(A, st);  \
+        else launch_single_t<MODEL, 1, 1, NOMINAL>(A, st);                      \
+        return;                                                                 \
+    }
+    SGTP_CASE(1) SGTP_CASE(3) SGTP_CASE(9) SGTP_CASE(15)
+#undef SGTP_CASE
+}
+
+// which: 0 sweep, 1 winner, 2 nominal
+void dispatch(int model, int ndisc, int mo, int which, const LaunchArgs &A, hipStream_t st) {
+    if (model == 0) {
+        if (ndisc == 1) dispatch_opp<0, 1>(mo, which, A, st);
+        else dispatch_opp<0, 3>(mo, which, A, st);
+    } else {
+        if (ndisc == 1) dispatch_opp<1, 1>(mo, which, A, st);
+        else dispatch_opp<1, 3>(mo, which, A, st);
+    }
+}
+
+struct Runner {
+    sgtp_ctx *c;
+    const sgtp_params *p;
+    hipStream_t st;
+    Plan pl;
+    LaunchArgs A{};
+    RaceDev *d_races = nullptr;
+    ItemDev *d_all = nullptr, *d_ego = nullptr, *d_one = nullptr;
+    int mo = 1;
+
+    int init(const sgtp_race *races, int n_races, int one_agent = -1) {
+        int rc = check_params(c, p);
+        if (rc) return rc;
+        rc = build_plan(c, p, races, n_races, 1, pl, one_agent);
+        if (rc) return rc;
+        rc = upload_plan(c, pl, st, &d_races, &d_all, &d_ego, &d_one);
+        if (rc) return rc;
+        mo = maxopp_bucket(pl.n_opp_max);
+        A.P = make_kparams(p);
+        A.L = make_layout(pl, mo, p->n_disc);
+        if (A.L.total > 64 * 1024) return fail(c, SGTP_ESHAPE, "staged tables exceed 64 KiB of LDS");
+        A.tracks = c->d_tracks;
+        A.races = d_races;
+        A.agents = c->d_agents;
+        A.win = c->d_win;
+        A.xref = c->d_xref;
+        A.keys = c->d_keys;
+        A.nfeas = c->d_nfeas;
+        A.spl = 1;
+        return SGTP_OK;
+    }
+    int setup_all() {  // projection, frames, references, windows, initial predictions
+        LaunchArgs a = A;
+        a.items = d_all;
+        a.n_items = (int)pl.all.size();
+        // every vehicle of every race needs a frame (opponents included)
+        if (pl.all.size() != (size_t)pl.agents_total) return fail(c, SGTP_EINVAL, "internal: setup needs all vehicles");
+        hipLaunchKernelGGL(k_setup, dim3(a.n_items), dim3(BLOCK), 0, st, a, pl.w_max);
+        a.pred_in = c->d_pred[1];
+        a.pred_out = c->d_pred[0];
+        a.phase = 0;
+        dispatch(p->model, p->n_disc, mo, 2, a, st);
+        HIPCHK(c, hipGetLastError());
+        return SGTP_OK;
+    }
+    int sweep(const ItemDev *items, int n_items, int n_tiles, int phase, int par) {
+        LaunchArgs a = A;
+        a.items = items;
+        a.n_items = n_items;
+        a.n_tiles = n_tiles;
+        a.phase = phase;
+        a.pred_in = c->d_pred[par];
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->timing) {
+            HIPCHK(c, hipEventCreate(&e0));
+            HIPCHK(c, hipEventCreate(&e1));
+            HIPCHK(c, hipEventRecord(e0, st));
+        }
+        dispatch(p->model, p->n_disc, mo, 0, a, st);
+        HIPCHK(c, hipGetLastError());
+        if (c->timing) {
+            HIPCHK(c, hipEventRecord(e1, st));
+            c->ev_pairs.push_back(e0);
+            c->ev_pairs.push_back(e1);
+            long long ss = 0;
+            for (int i = 0; i < n_items; ++i) {
+                const ItemDev &it = (items == d_all ? pl.all : pl.ego)[i];
+                ss += (long long)pl.races[it.race].K * pl.races[it.race].N;
+            }
+            c->ev_work.push_back(ss);
+        }
+        return SGTP_OK;
+    }
+    int winner(const ItemDev *items, int n_items, int phase, int par, sgtp_choice *choice, int adopt) {
+        LaunchArgs a = A;
+        a.items = items;
+        a.n_items = n_items;
+        a.phase = phase;
+        a.pred_in = c->d_pred[par];
+        a.pred_out = c->d_pred[par ^ 1];
+        a.choice = choice;
+        a.choice_base = 0;
+        a.adopt = adopt;
+        dispatch(p->model, p->n_disc, mo, 1, a, st);
+        HIPCHK(c, hipGetLastError());
+        return SGTP_OK;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int sgtp_abi_version(void) { return 1; }
+
+int sgtp_ctx_create(sgtp_ctx **out, int max_agents_total, int max_N, int max_races, int max_track_nodes) {
+    if (!out) return SGTP_EINVAL;
+    *out = nullptr;
+    if (max_agents_total < 1 || max_N < 1 || max_N > SGTP_MAX_N || max_races < 1 || max_track_nodes < 2)
+        return SGTP_EINVAL;
+    sgtp_ctx *c = new sgtp_ctx();
+    c->max_agents = max_agents_total;
+    c->max_N = max_N;
+    c->max_races = max_races;
+    c->max_nodes = max_track_nodes;
+    bool ok = hipGetDevice(&c->device) == hipSuccess;
+    auto al = [&](void **p, size_t bytes) {
+        if (ok && hipMalloc(p, bytes) != hipSuccess) ok = false;
+        if (ok && hipMemset(*p, 0, bytes) != hipSuccess) ok = false;
+    };
+    al((void **)&c->d_tracks, sizeof(TrackDev) * MAX_TRACKS);
+    al((void **)&c->d_agents, sizeof(AgentRec) * max_agents_total);
+    al((void **)&c->d_win, sizeof(float4) * 2 * WIN_MAX * (size_t)max_agents_total);
+    al((void **)&c->d_xref, sizeof(float4) * (size_t)max_N * max_agents_total);
+    for (int i = 0; i < 2; ++i) al((void **)&c->d_pred[i], sizeof(float) * PRED_STRIDE * (max_N + 1) * (size_t)max_agents_total);
+    al((void **)&c->d_keys, sizeof(unsigned long long) * max_agents_total);
+    al((void **)&c->d_nfeas, sizeof(int) * max_agents_total);
+    c->desc_bytes = ((sizeof(RaceDev) * max_races + 255) & ~size_t(255)) +
+                    3 * ((sizeof(ItemDev) * max_agents_total + 255) & ~size_t(255)) + 256;
+    al((void **)&c->d_desc, c->desc_bytes * sgtp_ctx::RING);
+    for (int i = 0; i < sgtp_ctx::RING && ok; ++i) {
+        if (hipHostMalloc((void **)&c->h_stage[i], c->desc_bytes, hipHostMallocDefault) != hipSuccess) ok = false;
+        if (ok && hipEventCreateWithFlags(&c->stage_ev[i], hipEventDisableTiming) != hipSuccess) ok = false;
+    }
+    if (!ok) {
+        sgtp_ctx_destroy(c);
+        return SGTP_ENOMEM;
+    }
+    *out = c;
+    return SGTP_OK;
+}
+
+int sgtp_ctx_destroy(sgtp_ctx *c) {
+    if (!c) return SGTP_EINVAL;
+    (void)hipDeviceSynchronize();
+    for (auto &t : c->tracks)
+        if (t.d_nodes) (void)hipFree(t.d_nodes);
+    void *bufs[] = {c->d_tracks, c->d_agents, c->d_win, c->d_xref, c->d_pred[0], c->d_pred[1], c->d_keys, c->d_nfeas, c->d_desc};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    for (int i = 0; i < sgtp_ctx::RING; ++i) {
+        if (c->h_stage[i]) (void)hipHostFree(c->h_stage[i]);
+        if (c->stage_ev[i]) (void)hipEventDestroy(c->stage_ev[i]);
+    }
+    for (auto e : c->ev_pairs) (void)hipEventDestroy(e);
+    delete c;
+    return SGTP_OK;
+}
+
+const char *sgtp_last_error(const sgtp_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int sgtp_track_upload(sgtp_ctx *c, int id, const double *nodes, int n, int closed, double length, double psi_lap) {
+    if (!c) return SGTP_EINVAL;
+    if (id < 0 || id >= MAX_TRACKS) return fail(c, SGTP_ETRACK, "track id out of range");
+    if (!nodes || n < 2 || n > c->max_nodes) return fail(c, SGTP_ESHAPE, "bad node count");
+    if (closed && !(length > 0)) return fail(c, SGTP_EINVAL, "closed track needs a positive length");
+    std::vector<double> h((size_t)n * NODE_STRIDE);
+    double ds_min = INFINITY, vmax = 0, kmax = 0, wmax = 0;
+    for (int i = 0; i < n; ++i) {
+        const double *r = nodes + (size_t)i * 8;
+        double *o = h.data() + (size_t)i * NODE_STRIDE;
+        o[0] = r[0]; o[1] = r[1]; o[2] = r[2];
+        o[3] = -std::sin(r[2]);
+        o[4] = std::cos(r[2]);
+        o[5] = r[4]; o[6] = r[5]; o[7] = r[6]; o[8] = r[7]; o[9] = r[3];
+        if (i + 1 < n) ds_min = std::min(ds_min, nodes[(size_t)(i + 1) * 8 + 7] - r[7]);
+        vmax = std::max(vmax, r[6]);
+        kmax = std::max(kmax, std::fabs(r[3]));
+        wmax = std::max(wmax, std::max(r[4], r[5]));
+        if (!std::isfinite(r[0]) || !std::isfinite(r[1]) || !std::isfinite(r[2]) || !std::isfinite(r[7]))
+            return fail(c, SGTP_ETRACK, "non-finite node");
+    }
+    if (closed) ds_min = std::min(ds_min, length + nodes[7] - nodes[(size_t)(n - 1) * 8 + 7]);
+    if (!(ds_min > 0)) return fail(c, SGTP_ETRACK, "node arc lengths must increase");
+    TrackHost &T = c->tracks[id];
+    if (T.d_nodes) {
+        HIPCHK(c, hipDeviceSynchronize());
+        HIPCHK(c, hipFree(T.d_nodes));
+        T.d_nodes = nullptr;
+    }
+    HIPCHK(c, hipMalloc((void **)&T.d_nodes, h.size() * sizeof(double)));
+    HIPCHK(c, hipMemcpy(T.d_nodes, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+    T.n = n;
+    T.closed = closed ? 1 : 0;
+    T.length = length;
+    T.psi_lap = closed ? psi_lap : 0.0;
+    T.ds_min = ds_min;
+    T.vmax = vmax;
+    T.inner_factor = 1.0 / std::max(0.25, 1.0 - kmax * (wmax + 2.0));
+    TrackDev d{T.d_nodes, T.n, T.closed, T.length, T.psi_lap, T.ds_min, T.inner_factor};
+    HIPCHK(c, hipMemcpy(c->d_tracks + id, &d, sizeof d, hipMemcpyHostToDevice));
+    return SGTP_OK;
+}
+
+int sgtp_rollout_cost(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *race, int agent, int phase, float *cost,
+                      unsigned char *flags, float *viol, double *x_final, float *noise, sgtp_choice *out,
+                      void *stream) {
+    if (!c) return SGTP_EINVAL;
+    if (!race) return fail(c, SGTP_EINVAL, "race is NULL");
+    if (agent < 0 || agent >= race->n_agents) return fail(c, SGTP_EINVAL, "agent out of range");
+    if (phase < 0 || phase > 0xffff) return fail(c, SGTP_EINVAL, "phase out of range");
+    Runner r{c, p, (hipStream_t)stream};
+    int rc = r.init(race, 1, agent);
+    if (rc) return rc;
+    rc = r.setup_all();
+    if (rc) return rc;
+    LaunchArgs a = r.A;
+    a.items = r.d_one;
+    a.n_items = 1;
+    a.phase = phase;
+    a.pred_in = c->d_pred[0];
+    a.n_tiles = (race->K + BLOCK - 1) / BLOCK;
+    a.dbg_cost = cost;
+    a.dbg_flags = flags;
+    a.dbg_viol = viol;
+    a.dbg_xfinal = x_final;
+    a.dbg_noise = noise;
+    dispatch(p->model, p->n_disc, r.mo, 0, a, r.st);
+    HIPCHK(c, hipGetLastError());
+    a.pred_out = c->d_pred[1];
+    a.choice = out;
+    a.choice_base = r.pl.all[agent].slot;
+    a.adopt = 0;
+    a.dbg_cost = nullptr; a.dbg_flags = nullptr; a.dbg_viol = nullptr; a.dbg_xfinal = nullptr; a.dbg_noise = nullptr;
+    dispatch(p->model, p->n_disc, r.mo, 1, a, r.st);
+    HIPCHK(c, hipGetLastError());
+    return SGTP_OK;
+}
+
+int sgtp_ibr_sweep(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_races, int phase, int ego_only,
+                   sgtp_choice *out, void *stream) {
+    if (!c) return SGTP_EINVAL;
+    if (phase < 0 || phase > 0xffff) return fail(c, SGTP_EINVAL, "phase out of range");
+    Runner r{c, p, (hipStream_t)stream};
+    int rc = r.init(races, n_races);
+    if (rc) return rc;
+    rc = r.setup_all();
+    if (rc) return rc;
+    const ItemDev *items = ego_only ? r.d_ego : r.d_all;
+    const int n_items = ego_only ? (int)r.pl.ego.size() : (int)r.pl.all.size();
+    const int n_tiles = ego_only ? r.pl.tiles_ego : r.pl.tiles_all;
+    rc = r.sweep(items, n_items, n_tiles, phase, 0);
+    if (rc) return rc;
+    return r.winner(items, n_items, phase, 0, out, 1);
+}
+
+int sgtp_plan_step(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_races, int L_ibr, float *u_apply,
+                   sgtp_choice *trace, void *stream) {
+    if (!c) return SGTP_EINVAL;
+    if (L_ibr < 0 || L_ibr + 1 > 0xffff) return fail(c, SGTP_EINVAL, "L_ibr out of range");
+    if (!u_apply) return fail(c, SGTP_EINVAL, "u_apply is NULL");
+    Runner r{c, p, (hipStream_t)stream};
+    int rc = r.init(races, n_races);
+    if (rc) return rc;
+    rc = r.setup_all();
+    if (rc) return rc;
+    const int nt = r.pl.agents_total;
+    for (int ph = 0; ph <= L_ibr + 1; ++ph) {
+        const bool ego = ph == L_ibr + 1;
+        const ItemDev *items = ego ? r.d_ego : r.d_all;
+        const int n_items = ego ? (int)r.pl.ego.size() : (int)r.pl.all.size();
+        const int n_tiles = ego ? r.pl.tiles_ego : r.pl.tiles_all;
+        const int par = ph & 1;
+        rc = r.sweep(items, n_items, n_tiles, ph, par);
+        if (rc) return rc;
+        rc = r.winner(items, n_items, ph, par, trace ? trace + (size_t)ph * nt : nullptr, 1);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_apply, dim3((nt + 63) / 64), dim3(64), 0, r.st, r.d_races, r.d_all, nt, (float2 *)u_apply);
+    HIPCHK(c, hipGetLastError());
+    return SGTP_OK;
+}
+
+int sgtp_advance(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_races, const float *u, void *stream) {
+    if (!c) return SGTP_EINVAL;
+    if (!u) return fail(c, SGTP_EINVAL, "u is NULL");
+    int rc = check_params(c, p);
+    if (rc) return rc;
+    Plan pl;
+    rc = build_plan(c, p, races, n_races, 1, pl);
+    if (rc) return rc;
+    RaceDev *dr;
+    ItemDev *da, *de;
+    hipStream_t st = (hipStream_t)stream;
+    rc = upload_plan(c, pl, st, &dr, &da, &de);
+    if (rc) return rc;
+    const int nt = pl.agents_total;
+    const VehConst<double> V = make_veh64(p);
+    if (p->model == 0)
+        hipLaunchKernelGGL(k_advance<0>, dim3((nt + 63) / 64), dim3(64), 0, st, dr, da, nt, (const float2 *)u, V, (double)p->dt);
+    else
+        hipLaunchKernelGGL(k_advance<1>, dim3((nt + 63) / 64), dim3(64), 0, st, dr, da, nt, (const float2 *)u, V, (double)p->dt);
+    HIPCHK(c, hipGetLastError());
+    return SGTP_OK;
+}
+
+int sgtp_set_timing(sgtp_ctx *c, int on) {
+    if (!c) return SGTP_EINVAL;
+    c->timing = on != 0;
+    return SGTP_OK;
+}
+
+int sgtp_sweep_stats(sgtp_ctx *c, double *total_ms, long long *launches, long long *sample_steps, int reset) {
+    if (!c) return SGTP_EINVAL;
+    for (size_t i = 0; i + 1 < c->ev_pairs.size(); i += 2) {
+        HIPCHK(c, hipEventSynchronize(c->ev_pairs[i + 1]));
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pairs[i], c->ev_pairs[i + 1]));
+        c->total_ms += ms;
+        c->launches += 1;
+        c->sample_steps += c->ev_work[i / 2];
+        (void)hipEventDestroy(c->ev_pairs[i]);
+        (void)hipEventDestroy(c->ev_pairs[i + 1]);
+    }
+    c->ev_pairs.clear();
+    c->ev_work.clear();
+    if (total_ms) *total_ms = c->total_ms;
+    if (launches) *launches = c->launches;
+    if (sample_steps) *sample_steps = c->sample_steps;
+    if (reset) {
+        c->total_ms = 0;
+        c->launches = 0;
+        c->sample_steps = 0;
+    }
+    return SGTP_OK;
+}
+
+}  // extern "C"

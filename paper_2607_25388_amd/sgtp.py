@@ -1,0 +1,253 @@
+"""ctypes binding of libsgtp.so (the HIP planner behind include/sgtp.h).
+
+Argument marshalling only: every step of the planner runs in the library's HIP
+kernels.  PyTorch provides device memory and the stream.  There is no fallback:
+if the library or a GPU is missing, the calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsgtp.so")
+
+SGTP_MAX_AGENTS = 16
+SGTP_MAX_N = 64
+ERRORS = {-1: "EINVAL", -2: "ESHAPE", -3: "ETRACK", -4: "EDEVICE", -5: "ENOMEM"}
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("model", C.c_int), ("dt", C.c_float),
+        ("a_min", C.c_float), ("a_max", C.c_float), ("d_min", C.c_float), ("d_max", C.c_float),
+        ("sigma_a", C.c_float), ("sigma_d", C.c_float),
+        ("Q", C.c_float * 4), ("R", C.c_float * 2), ("S", C.c_float * 2),
+        ("w_game", C.c_float), ("w_contest", C.c_float), ("w_long", C.c_float), ("w_block", C.c_float),
+        ("w_safety", C.c_float), ("s_contest", C.c_float), ("s_role", C.c_float), ("eps_alpha", C.c_float),
+        ("g_safe", C.c_float), ("m_bd", C.c_float), ("d_col", C.c_float),
+        ("n_disc", C.c_int), ("disc_off", C.c_float * 4),
+        ("m", C.c_float), ("Iz", C.c_float), ("lf", C.c_float), ("lr", C.c_float),
+        ("B", C.c_float), ("C", C.c_float), ("mu", C.c_float), ("g", C.c_float), ("v_eps", C.c_float),
+        ("max_moves", C.c_int),
+    ]
+
+
+class Race(C.Structure):
+    _fields_ = [
+        ("n_agents", C.c_int), ("ego", C.c_int), ("track_id", C.c_int), ("N", C.c_int), ("n_tail", C.c_int),
+        ("K", C.c_int), ("seed", C.c_ulonglong), ("plan_step", C.c_uint),
+        ("x", C.c_void_p), ("s_abs", C.c_void_p), ("v_scale", C.c_void_p), ("u_nom", C.c_void_p),
+        ("traj", C.c_void_p),
+    ]
+
+
+class Choice(C.Structure):
+    _fields_ = [("k", C.c_int), ("fallback", C.c_int), ("n_feasible", C.c_int), ("cost", C.c_float),
+                ("viol", C.c_float)]
+
+
+CHOICE_DTYPE = np.dtype([("k", np.int32), ("fallback", np.int32), ("n_feasible", np.int32),
+                         ("cost", np.float32), ("viol", np.float32)])
+assert CHOICE_DTYPE.itemsize == C.sizeof(Choice)
+
+_lib = None
+
+
+def load():
+    """Load libsgtp.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2607_25388_amd.build")
+        lib = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        vp = C.c_void_p
+        lib.sgtp_ctx_create.argtypes = [P(vp), C.c_int, C.c_int, C.c_int, C.c_int]
+        lib.sgtp_ctx_destroy.argtypes = [vp]
+        lib.sgtp_last_error.argtypes = [vp]
+        lib.sgtp_last_error.restype = C.c_char_p
+        lib.sgtp_track_upload.argtypes = [vp, C.c_int, vp, C.c_int, C.c_int, C.c_double, C.c_double]
+        lib.sgtp_rollout_cost.argtypes = [vp, P(Params), P(Race), C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp]
+        lib.sgtp_ibr_sweep.argtypes = [vp, P(Params), P(Race), C.c_int, C.c_int, C.c_int, vp, vp]
+        lib.sgtp_plan_step.argtypes = [vp, P(Params), P(Race), C.c_int, C.c_int, vp, vp, vp]
+        lib.sgtp_advance.argtypes = [vp, P(Params), P(Race), C.c_int, vp, vp]
+        lib.sgtp_set_timing.argtypes = [vp, C.c_int]
+        lib.sgtp_sweep_stats.argtypes = [vp, P(C.c_double), P(C.c_longlong), P(C.c_longlong), C.c_int]
+        lib.sgtp_abi_version.restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+def make_params(d: dict) -> Params:
+    p = Params()
+    for name, typ in Params._fields_:
+        v = d[name]
+        if name in ("Q", "R", "S", "disc_off"):
+            arr = getattr(p, name)
+            for i, x in enumerate(v):
+                arr[i] = float(x)
+        elif typ is C.c_int:
+            setattr(p, name, int(v))
+        else:
+            setattr(p, name, float(v))
+    return p
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class RaceTensors:
+    """Device tensors of one race (float64 states/progress, float32 controls)."""
+    n_agents: int
+    ego: int
+    track_id: int
+    N: int
+    n_tail: int
+    K: int
+    seed: int
+    plan_step: int
+    x: "object"        # torch float64 [n, 6]
+    s_abs: "object"    # torch float64 [n]
+    v_scale: "object"  # torch float32 [n]
+    u_nom: "object"    # torch float32 [n, N, 2]
+    traj: "object"     # torch float64 [n, N+1, 8] or None
+
+    def struct(self) -> Race:
+        for name, t in (("x", self.x), ("s_abs", self.s_abs), ("v_scale", self.v_scale), ("u_nom", self.u_nom)):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"race.{name} must be a contiguous device tensor")
+        r = Race()
+        r.n_agents, r.ego, r.track_id, r.N = self.n_agents, self.ego, self.track_id, self.N
+        r.n_tail, r.K, r.seed, r.plan_step = self.n_tail, self.K, self.seed, self.plan_step
+        r.x, r.s_abs, r.v_scale, r.u_nom = (self.x.data_ptr(), self.s_abs.data_ptr(), self.v_scale.data_ptr(),
+                                            self.u_nom.data_ptr())
+        r.traj = self.traj.data_ptr() if self.traj is not None else None
+        return r
+
+
+def race_from_inputs(race, track_id: int, K: int, N: int, n_tail: int, device="cuda", plan_step=None,
+                     with_traj=True) -> RaceTensors:
+    """Device copy of an inputs.Race."""
+    import torch
+    n = race.n_agents
+    return RaceTensors(
+        n, race.ego, track_id, N, n_tail, K, int(race.seed), int(race.plan_step if plan_step is None else plan_step),
+        torch.tensor(race.x, dtype=torch.float64, device=device).contiguous(),
+        torch.tensor(race.s_abs, dtype=torch.float64, device=device).contiguous(),
+        torch.tensor(race.v_scale, dtype=torch.float32, device=device).contiguous(),
+        torch.tensor(np.asarray(race.u_nom, np.float32), device=device).contiguous(),
+        torch.zeros((n, N + 1, 8), dtype=torch.float64, device=device) if with_traj else None,
+    )
+
+
+class Planner:
+    """One planner context on the current device."""
+
+    def __init__(self, max_agents_total=64, max_N=SGTP_MAX_N, max_races=8, max_track_nodes=1 << 16):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the SGTP planner needs a GPU")
+        torch.cuda.init()
+        self.lib = load()
+        self.ctx = C.c_void_p()
+        rc = self.lib.sgtp_ctx_create(C.byref(self.ctx), max_agents_total, max_N, max_races, max_track_nodes)
+        if rc != 0:
+            raise RuntimeError(f"sgtp_ctx_create failed: {ERRORS.get(rc, rc)}")
+
+    def close(self):
+        if self.ctx:
+            self.lib.sgtp_ctx_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != 0:
+            msg = self.lib.sgtp_last_error(self.ctx).decode()
+            raise RuntimeError(f"{what} failed ({ERRORS.get(rc, rc)}): {msg}")
+
+    def upload_track(self, track_id: int, track):
+        nodes = np.ascontiguousarray(track.nodes, np.float64)
+        self._check(self.lib.sgtp_track_upload(self.ctx, track_id, nodes.ctypes.data, nodes.shape[0],
+                                               1 if track.closed else 0, float(track.length),
+                                               float(track.psi_lap)), "sgtp_track_upload")
+
+    def rollout_cost(self, params: dict, race: RaceTensors, agent: int, phase: int, want_noise=False):
+        import torch
+        K, N = race.K, race.N
+        dev = race.x.device
+        out = dict(cost=torch.empty(K, dtype=torch.float32, device=dev),
+                   flags=torch.empty(K, dtype=torch.uint8, device=dev),
+                   viol=torch.empty(K, dtype=torch.float32, device=dev),
+                   x_final=torch.empty((K, 6), dtype=torch.float64, device=dev),
+                   noise=torch.empty((K, N, 2), dtype=torch.float32, device=dev) if want_noise else None,
+                   choice=torch.zeros(CHOICE_DTYPE.itemsize, dtype=torch.uint8, device=dev))
+        P = make_params(params)
+        R = race.struct()
+        rc = self.lib.sgtp_rollout_cost(self.ctx, C.byref(P), C.byref(R), agent, phase, _ptr(out["cost"]),
+                                        _ptr(out["flags"]), _ptr(out["viol"]), _ptr(out["x_final"]),
+                                        _ptr(out["noise"]), _ptr(out["choice"]), _stream())
+        self._check(rc, "sgtp_rollout_cost")
+        return out
+
+    def ibr_sweep(self, params: dict, races, phase: int, ego_only: bool = False):
+        import torch
+        arr = (Race * len(races))(*[r.struct() for r in races])
+        nt = sum(r.n_agents for r in races)
+        out = torch.zeros(nt * CHOICE_DTYPE.itemsize, dtype=torch.uint8, device=races[0].x.device)
+        P = make_params(params)
+        rc = self.lib.sgtp_ibr_sweep(self.ctx, C.byref(P), arr, len(races), phase, 1 if ego_only else 0,
+                                     _ptr(out), _stream())
+        self._check(rc, "sgtp_ibr_sweep")
+        return out
+
+    def plan_step(self, params: dict, races, L_ibr: int, u_apply=None, trace=None):
+        import torch
+        arr = (Race * len(races))(*[r.struct() for r in races])
+        nt = sum(r.n_agents for r in races)
+        dev = races[0].x.device
+        if u_apply is None:
+            u_apply = torch.empty((nt, 2), dtype=torch.float32, device=dev)
+        P = make_params(params)
+        rc = self.lib.sgtp_plan_step(self.ctx, C.byref(P), arr, len(races), L_ibr, _ptr(u_apply), _ptr(trace),
+                                     _stream())
+        self._check(rc, "sgtp_plan_step")
+        return u_apply
+
+    def advance(self, params: dict, races, u):
+        arr = (Race * len(races))(*[r.struct() for r in races])
+        P = make_params(params)
+        self._check(self.lib.sgtp_advance(self.ctx, C.byref(P), arr, len(races), _ptr(u), _stream()),
+                    "sgtp_advance")
+
+    def set_timing(self, on: bool):
+        self._check(self.lib.sgtp_set_timing(self.ctx, 1 if on else 0), "sgtp_set_timing")
+
+    def sweep_stats(self, reset=False):
+        ms = C.c_double()
+        n = C.c_longlong()
+        ss = C.c_longlong()
+        self._check(self.lib.sgtp_sweep_stats(self.ctx, C.byref(ms), C.byref(n), C.byref(ss), 1 if reset else 0),
+                    "sgtp_sweep_stats")
+        return ms.value, n.value, ss.value
+
+
+def choices_to_numpy(t) -> np.ndarray:
+    """Decode a uint8 device buffer of sgtp_choice records."""
+    return np.frombuffer(t.cpu().numpy().tobytes(), dtype=CHOICE_DTYPE)

@@ -1,0 +1,238 @@
+"""GPU parity: the HIP planner (through the C ABI) against the CPU oracle."""
+
+import copy
+import math
+
+import numpy as np
+import pytest
+
+import parity as PY
+from paper_2607_25388_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def planner():
+    import paper_2607_25388_amd.sgtp as sg
+    p = sg.Planner(max_agents_total=64, max_races=4)
+    yield p
+    p.close()
+
+
+def _run(planner, name, agent, phase, K, params_over=None, race_over=None, want_noise=False):
+    tr, race, params, _, w = PY.workload(name)
+    if params_over:
+        params = dict(params, **params_over)
+    if race_over:
+        race = race_over(copy.deepcopy(race))
+    rt = PY.build(planner, tr, race, params, K)
+    g = PY.gpu_rollout(planner, params, rt, agent, phase, want_noise=want_noise)
+    orc = PY.oracle_for(tr, params)
+    r = orc.rollout_cost(race, agent, phase, K, noise=want_noise)
+    return tr, race, params, g, r
+
+
+def test_noise_is_bit_exact(planner):
+    tr, race, params, g, r = _run(planner, "c1", 1, 2, 1000, want_noise=True)
+    assert g["noise"].shape == r["noise"].shape
+    diff = np.nonzero(g["noise"].view(np.uint32) != r["noise"].view(np.uint32))
+    assert len(diff[0]) == 0, f"{len(diff[0])} perturbations differ, first at {diff[0][:5]}"
+
+
+@pytest.mark.parametrize("agent,phase,K", [(0, 0, 1024), (0, 1, 1024), (1, 1, 1024), (1, 3, 1000), (0, 2, 777)])
+def test_rollout_cost_c1(planner, agent, phase, K):
+    tr, race, params, g, r = _run(planner, "c1", agent, phase, K)
+    st = PY.compare_samples(g, r, params, tr.width, f"c1 a{agent} p{phase} K{K}")
+    PY.check_choice(g["choice"], r, params, "c1")
+    assert int(g["choice"]["n_feasible"]) == int(((r["flags"] & 4) > 0).sum()) or st["near"] > 0
+    print(st)
+
+
+@pytest.mark.parametrize("name,agent,K", [("c2", 0, 2048), ("c2", 2, 1500), ("c3", 0, 1024), ("c3", 7, 700)])
+def test_rollout_cost_multi_disc_and_many_agents(planner, name, agent, K):
+    tr, race, params, g, r = _run(planner, name, agent, 1, K)
+    st = PY.compare_samples(g, r, params, tr.width, f"{name} a{agent}")
+    PY.check_choice(g["choice"], r, params, name)
+    print(st)
+
+
+def test_full_size_large_field_sampled(planner):
+    """C3 shape at full K = 65536 for one vehicle, every sample compared."""
+    tr, race, params, g, r = _run(planner, "c3", 4, 2, 65536)
+    st = PY.compare_samples(g, r, params, tr.width, "c3 full")
+    PY.check_choice(g["choice"], r, params, "c3 full")
+    print(st)
+
+
+def test_kinematic_model(planner):
+    tr, race, params, g, r = _run(planner, "c1", 0, 1, 1024, params_over=dict(model=1))
+    PY.compare_samples(g, r, params, tr.width, "kinematic")
+    PY.check_choice(g["choice"], r, params, "kinematic")
+
+
+def test_single_sample_and_single_agent(planner):
+    tr, race, params, g, r = _run(planner, "c1", 0, 1, 1)
+    PY.compare_samples(g, r, params, tr.width, "K=1")
+    assert int(g["choice"]["k"]) == 0
+
+    def solo(rc):
+        rc.n_agents = 1
+        rc.x = rc.x[:1]
+        rc.s_abs = rc.s_abs[:1]
+        rc.v_scale = rc.v_scale[:1]
+        rc.u_nom = rc.u_nom[:1]
+        return rc
+    tr, race, params, g, r = _run(planner, "c1", 0, 1, 512, race_over=solo)
+    PY.compare_samples(g, r, params, tr.width, "n=1")
+    PY.check_choice(g["choice"], r, params, "n=1")
+
+
+def test_all_infeasible_fallback(planner):
+    def stacked(rc):
+        rc.x[1] = rc.x[0]
+        rc.s_abs[1] = rc.s_abs[0]
+        return rc
+    tr, race, params, g, r = _run(planner, "c1", 0, 1, 512, race_over=stacked)
+    assert r["choice"]["fallback"] == 1
+    PY.compare_samples(g, r, params, tr.width, "fallback")
+    PY.check_choice(g["choice"], r, params, "fallback")
+
+
+def test_nan_nominal_is_infeasible(planner):
+    def nan(rc):
+        rc.u_nom = rc.u_nom.copy()
+        rc.u_nom[0, 3, 1] = np.nan
+        return rc
+    tr, race, params, g, r = _run(planner, "c1", 0, 1, 256, race_over=nan)
+    assert np.all(g["flags"] & 16) and np.all(np.isinf(g["viol"]))
+    assert int(g["choice"]["k"]) == 0 and int(g["choice"]["fallback"]) == 1
+
+
+def test_open_straight_track(planner):
+    import oracle
+    import paper_2607_25388_amd.sgtp as sg
+    tr = inputs.make_straight_track(600.0, 10.0, x0=-100.0, y0=20.0, heading=0.3, vref=25.0)
+    params = inputs.default_params(20, 3)
+    race = inputs.make_race(tr, 3, 20, 10.0, True, 11, 12)
+    rt = sg.race_from_inputs(race, 5, 1024, 20, params["n_tail"])
+    planner.upload_track(5, tr)
+    g = PY.gpu_rollout(planner, params, rt, 1, 1)
+    r = oracle.Oracle(tr, params).rollout_cost(race, 1, 1, 1024)
+    PY.compare_samples(g, r, params, tr.width, "straight")
+    PY.check_choice(g["choice"], r, params, "straight")
+
+
+def _plan(planner, name, K, L):
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    tr, race, params, _, w = PY.workload(name)
+    rt = PY.build(planner, tr, race, params, K)
+    n = race.n_agents
+    trace = torch.zeros((L + 2) * n * sg.CHOICE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    u_apply = planner.plan_step(params, [rt], L, trace=trace)
+    torch.cuda.synchronize()
+    gtr = sg.choices_to_numpy(trace).reshape(L + 2, n)
+    return tr, race, params, rt, gtr, u_apply.cpu().numpy()
+
+
+@pytest.mark.parametrize("name,K,L", [("c1", 1024, 3), ("c2", 1024, 2)])
+def test_plan_step_lockstep(planner, name, K, L):
+    """Alg. 1 on the GPU; the oracle replays it adopting the GPU's choices phase by phase
+    and must agree with each choice (or find it a near-tie)."""
+    tr, race, params, rt, gtr, u_apply = _plan(planner, name, K, L)
+    n = race.n_agents
+    forced = np.full((L + 2, n), -1, np.int32)
+    for ph in range(L + 2):
+        for i in range(n):
+            if ph <= L or i == race.ego:
+                forced[ph, i] = gtr[ph, i]["k"]
+    orc = PY.oracle_for(tr, params)
+    ref = orc.plan_step(race, L, K=K, forced=forced)
+    exact = 0
+    for ph in range(L + 2):
+        for i in range(n):
+            if forced[ph, i] < 0:
+                continue
+            rc = ref["trace"][ph][i]
+            gc = gtr[ph, i]
+            assert int(gc["fallback"]) == rc["fallback"], (ph, i)
+            if int(gc["k"]) == rc["k"]:
+                exact += 1
+            elif not rc["fallback"]:
+                assert rc["flags_used"] & 4, (ph, i)
+                assert (rc["cost_used"] - rc["cost"]) / rc["scale_used"] <= PY.TOL_COST, (ph, i, rc, gc)
+            if not rc["fallback"]:
+                assert abs(float(gc["cost"]) - rc["cost_used"]) <= PY.TOL_COST * rc["scale_used"], (ph, i)
+    assert exact >= (L + 1) * n // 2
+    np.testing.assert_allclose(u_apply, ref["u_apply"], atol=1e-5)
+    np.testing.assert_allclose(rt.u_nom.cpu().numpy(), ref["u_next"], atol=1e-5)
+    traj = rt.traj.cpu().numpy()
+    assert np.max(np.abs(traj[:, :, :2] - ref["traj"][:, :, :2])) < PY.TOL_STATE
+    np.testing.assert_allclose(rt.s_abs.cpu().numpy(), ref["s_abs"], atol=1e-6)
+
+
+def test_winner_rerollout_is_bit_identical(planner):
+    """The selected sample re-rolled by one lane reproduces the sweep lane bit for bit."""
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    tr, race, params, _, w = PY.workload("c2")
+    K = 2048
+    rt = PY.build(planner, tr, race, params, K)
+    g = PY.gpu_rollout(planner, params, rt, 1, 1, want_noise=False)
+    k = int(g["choice"]["k"])
+    out = planner.ibr_sweep(params, [rt], 1)
+    torch.cuda.synchronize()
+    ch = sg.choices_to_numpy(out)
+    assert int(ch[1]["k"]) == k
+    assert float(ch[1]["cost"]) == float(g["cost"][k])
+    traj = rt.traj.cpu().numpy()
+    np.testing.assert_array_equal(traj[1, -1, :6], g["x_final"][k])
+
+
+def test_ibr_sweep_matches_plan_step_phase(planner):
+    """sgtp_ibr_sweep(phase 0) followed by (phase 1) reproduces the first two phases of a plan step."""
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    tr, race, params, _, w = PY.workload("c1")
+    K, L = 1024, 1
+    rt1 = PY.build(planner, tr, race, params, K)
+    c0 = sg.choices_to_numpy(planner.ibr_sweep(params, [rt1], 0))
+    c1 = sg.choices_to_numpy(planner.ibr_sweep(params, [rt1], 1))
+    torch.cuda.synchronize()
+    tr_, race_, params_, rt2, gtr, _ = _plan(planner, "c1", K, L)
+    assert [int(c["k"]) for c in c0] == [int(c["k"]) for c in gtr[0]]
+    assert [int(c["k"]) for c in c1] == [int(c["k"]) for c in gtr[1]]
+
+
+def test_advance_matches_oracle(planner):
+    import torch
+    tr, race, params, _, w = PY.workload("c2")
+    rt = PY.build(planner, tr, race, params, 64)
+    u = torch.tensor([[1.0, 0.02], [-2.0, -0.1], [0.5, 0.3]], dtype=torch.float32, device="cuda")
+    planner.advance(params, [rt], u)
+    torch.cuda.synchronize()
+    # the C ABI carries float32 parameters: give the oracle the same (rounded) values
+    p32 = {k: ([float(np.float32(x)) for x in v] if isinstance(v, list) else
+               (float(np.float32(v)) if isinstance(v, float) else v)) for k, v in params.items()}
+    orc = PY.oracle_for(tr, p32)
+    ref = orc.advance(race.x, u.cpu().numpy().astype(np.float64))
+    np.testing.assert_allclose(rt.x.cpu().numpy(), ref, rtol=0, atol=1e-11)
+
+
+def test_argument_errors(planner):
+    import paper_2607_25388_amd.sgtp as sg
+    tr, race, params, _, w = PY.workload("c1")
+    rt = PY.build(planner, tr, race, params, 64)
+    with pytest.raises(RuntimeError, match="EINVAL"):
+        planner.rollout_cost(dict(params, n_disc=2), rt, 0, 1)
+    with pytest.raises(RuntimeError, match="EINVAL"):
+        planner.rollout_cost(params, rt, 5, 1)
+    bad = copy.copy(rt)
+    bad.track_id = 63
+    with pytest.raises(RuntimeError, match="ETRACK"):
+        planner.rollout_cost(params, bad, 0, 1)
+    big = copy.copy(rt)
+    big.N = 65
+    with pytest.raises(RuntimeError, match="EINVAL|ESHAPE"):
+        planner.rollout_cost(params, big, 0, 1)
