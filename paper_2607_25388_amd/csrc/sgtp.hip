@@ -1403,7 +1403,12 @@ int sgtp_ctx_create(sgtp_ctx **out, int max_agents_total, int max_N, int max_rac
     c->max_N = max_N;
     c->max_races = max_races;
     c->max_nodes = max_track_nodes;
-    bool ok = hipGetDevice(&c->device) == hipSuccess;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1 || hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return SGTP_EDEVICE;
+    }
+    bool ok = true;
     auto al = [&](void **p, size_t bytes) {
         if (ok && hipMalloc(p, bytes) != hipSuccess) ok = false;
         if (ok && hipMemset(*p, 0, bytes) != hipSuccess) ok = false;
