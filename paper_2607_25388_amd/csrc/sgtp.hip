@@ -12,12 +12,12 @@
 //
 // Kernels of one planning step:
 //   k_setup   one workgroup per vehicle: global Frenet projection, unwrapped
-//             progress, local frame, reference states, raceline window.
-//   k_single  NOMINAL mode, one lane per vehicle: noise-free rollout of the
-//             nominal sequence (initial predictions).
-//   k_sweep   every sample of every participating vehicle -> selection keys.
-//   k_single  WINNER mode: re-roll k* -> new nominal, prediction, trajectory, choice.
-//   k_apply   first control out, warm start shifted.
+//             progress, local frame, raceline window, reference states, and the
+//             noise-free rollout of the nominal sequence (initial predictions).
+//   k_sweep   every sample of every participating vehicle -> selection keys; the
+//             last workgroup of each vehicle re-rolls k* (new nominal,
+//             prediction, trajectory, choice; first control and warm start in
+//             the vehicle's final phase).
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -33,7 +33,6 @@
 namespace {
 
 constexpr int BLOCK = 256;
-constexpr int SINGLE_BLOCK = 64;
 constexpr int MAX_TRACKS = 64;
 constexpr int WIN_BACK = 48;    // raceline nodes kept behind the current segment
 constexpr int WIN_MAX = 1536;   // window nodes per vehicle (workspace bound)
@@ -54,14 +53,14 @@ struct KParams {
     float w_game, w_contest, w_long, w_block, w_safety, s_contest, s_role, eps_alpha;
     float g_safe, m_bd, d_col, cap2, skip2;
     float off[4];
-    float lf, lr, inv_m, inv_Iz, muFzf, muFzr, B, C, v_eps;  // dynamic single-track
+    float lf, lr, inv_m, inv_Iz, muFzf, muFzr, B, C, v_eps, C_rev;  // dynamic single-track
     float lr_over_L, inv_lr;                                 // kinematic bicycle
 };
 
 struct TrackDev {
     const double *nodes;  // [n][NODE_STRIDE]
     int n, closed;
-    double length, psi_lap, ds_min, inner_factor;
+    double length, psi_lap, ds_min, inner_factor, vmax;
 };
 
 struct RaceDev {
@@ -87,7 +86,9 @@ struct AgentRec {  // per vehicle, written by k_setup
 };
 
 struct LdsLayout {  // byte offsets of the staged tables, identical for every block of a launch
-    int ubar, xref, oppT, oppc, opp, nodes, total;
+    int ubar, xref, oppT, oppc, opp, nodes;
+    int rr_u, rr_st, rr_f, rr_t, rr_g, rr_l;  // re-roll scratch
+    int total;
     int n_opp_max, w_max, N_max;
 };
 
@@ -105,10 +106,13 @@ struct LaunchArgs {
     float *pred_out;
     unsigned long long *keys;
     int *nfeas;
-    // WINNER outputs
+    int *counters;         // finished workgroups per vehicle
+    // outputs of the re-roll of the selected sample
     sgtp_choice *choice;   // indexed by slot - choice_base, or NULL
     int choice_base;
     int adopt;             // write u_nom / traj
+    int final_mode;        // 0 none, 1 every vehicle but the ego, 2 every vehicle: first control + warm start
+    float2 *u_apply;       // [slot] first controls, or NULL
     // debug outputs of k_sweep (indexed by sample), or NULL
     float *dbg_cost;
     unsigned char *dbg_flags;
@@ -196,7 +200,8 @@ __device__ __forceinline__ float2 gauss_pair(uint32_t r_even, uint32_t r_odd) {
 // ------------------------------------------------------------------------------
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// atan: odd polynomial fitted on [0, 1] (max error 3.3e-7), reflected via pi/2 - atan(1/x)
+// atan: odd polynomial fitted on [0, 1] (max error 3.3e-7), reflected via pi/2 - atan(1/x).
+// (A 6-term fit with 1.8e-6 error moved chaotic sliding samples past the 1e-3 state tolerance.)
 __device__ __forceinline__ float fast_atan(float x) {
     const float ax = fabsf(x);
     const bool inv = ax > 1.0f;
@@ -218,12 +223,17 @@ __device__ __forceinline__ float fast_atan(float x) {
 __device__ __forceinline__ float fast_sin(float x) { return __builtin_amdgcn_sinf(x * 0.159154943f); }
 __device__ __forceinline__ float fast_cos(float x) { return __builtin_amdgcn_cosf(x * 0.159154943f); }
 
+// Elementary functions of the vehicle model.  Angles handed to sin_rev/cos_rev are
+// pre-scaled by to_rev (revolutions for the float32 transcendental unit, radians in float64).
 struct MathF32 {
     using T = float;
     static __device__ __forceinline__ T atan_(T x) { return fast_atan(x); }
     static __device__ __forceinline__ T sin_(T x) { return fast_sin(x); }
     static __device__ __forceinline__ T cos_(T x) { return fast_cos(x); }
     static __device__ __forceinline__ T rcp_(T x) { return fast_rcp(x); }
+    static __device__ __forceinline__ T to_rev(T x) { return x * 0.159154943f; }
+    static __device__ __forceinline__ T sin_rev(T x) { return __builtin_amdgcn_sinf(x); }
+    static __device__ __forceinline__ T cos_rev(T x) { return __builtin_amdgcn_cosf(x); }
 };
 
 struct MathF64 {
@@ -232,11 +242,15 @@ struct MathF64 {
     static __device__ __forceinline__ T sin_(T x) { return ::sin(x); }
     static __device__ __forceinline__ T cos_(T x) { return ::cos(x); }
     static __device__ __forceinline__ T rcp_(T x) { return 1.0 / x; }
+    static __device__ __forceinline__ T to_rev(T x) { return x; }
+    static __device__ __forceinline__ T sin_rev(T x) { return ::sin(x); }
+    static __device__ __forceinline__ T cos_rev(T x) { return ::cos(x); }
 };
 
 template <typename T>
 struct VehConst {
     T lf, lr, inv_m, inv_Iz, muFzf, muFzr, B, C, v_eps, lr_over_L, inv_lr;
+    T Cs;  // C scaled to the angle unit of M::sin_rev
 };
 
 // Per control interval: functions of the held control (a, delta).
@@ -276,13 +290,14 @@ __device__ __forceinline__ void deriv(const VehConst<typename M::T> &V, const St
                                       typename M::T d[6]) {
     using T = typename M::T;
     const T vx = vx_ > T(0) ? vx_ : T(0);
-    const T cp = M::cos_(psi), sp = M::sin_(psi);
+    const T pr = M::to_rev(psi);
+    const T cp = M::cos_rev(pr), sp = M::sin_rev(pr);
     if (MODEL == 0) {
         const T inv_vh = M::rcp_(vx > V.v_eps ? vx : V.v_eps);
         const T alpha_f = c.delta - M::atan_((vy + V.lf * om) * inv_vh);
         const T alpha_r = -M::atan_((vy - V.lr * om) * inv_vh);
-        const T Fyf = V.muFzf * M::sin_(V.C * M::atan_(V.B * alpha_f));
-        const T Fyr = V.muFzr * M::sin_(V.C * M::atan_(V.B * alpha_r));
+        const T Fyf = V.muFzf * M::sin_rev(V.Cs * M::atan_(V.B * alpha_f));
+        const T Fyr = V.muFzr * M::sin_rev(V.Cs * M::atan_(V.B * alpha_r));
         d[0] = vx * cp - vy * sp;
         d[1] = vx * sp + vy * cp;
         d[2] = om;
@@ -320,6 +335,7 @@ __device__ __forceinline__ VehConst<float> veh_f32(const KParams &P) {
     VehConst<float> V;
     V.lf = P.lf; V.lr = P.lr; V.inv_m = P.inv_m; V.inv_Iz = P.inv_Iz; V.muFzf = P.muFzf; V.muFzr = P.muFzr;
     V.B = P.B; V.C = P.C; V.v_eps = P.v_eps; V.lr_over_L = P.lr_over_L; V.inv_lr = P.inv_lr;
+    V.Cs = P.C_rev;
     return V;
 }
 
@@ -430,7 +446,7 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
 }
 
 // ------------------------------------------------------------------------------
-// Per-block staging into LDS (shared by the sweep and the single-lane kernels)
+// Per-block staging into LDS (every sweep workgroup of a vehicle stages the same tables)
 // ------------------------------------------------------------------------------
 struct BlockState {
     int slot, race, agent, N, n_tail, n_opp, W, seg0, K;
@@ -439,8 +455,7 @@ struct BlockState {
 };
 
 template <int NDISC>
-__device__ void stage_block(const LaunchArgs &A, int item_idx, bool with_opp, int pred_in_stride_slot,
-                            BlockState &bs, char *lds) {
+__device__ void stage_block(const LaunchArgs &A, int item_idx, BlockState &bs, char *lds) {
     const KParams &P = A.P;
     const LdsLayout &L = A.L;
     const ItemDev it = A.items[item_idx];
@@ -452,7 +467,7 @@ __device__ void stage_block(const LaunchArgs &A, int item_idx, bool with_opp, in
     bs.N = R.N;
     bs.n_tail = R.n_tail;
     bs.K = R.K;
-    bs.n_opp = with_opp ? R.n_agents - 1 : 0;
+    bs.n_opp = R.n_agents - 1;
     bs.W = me.win_n;
     bs.seg0 = me.seg_loc;
     bs.vx0 = me.vx;
@@ -466,6 +481,7 @@ __device__ void stage_block(const LaunchArgs &A, int item_idx, bool with_opp, in
     bs.ctr3 = R.plan_step;
 
     const int tid = threadIdx.x, nth = blockDim.x;
+    const int pstride = (L.N_max + 1) * PRED_STRIDE;
     float2 *ubar = (float2 *)(lds + L.ubar);
     float4 *xref = (float4 *)(lds + L.xref);
     float4 *nodes = (float4 *)(lds + L.nodes);
@@ -489,7 +505,7 @@ __device__ void stage_block(const LaunchArgs &A, int item_idx, bool with_opp, in
             const double dx = o.ox - me.ox, dy = o.oy - me.oy;
             oppT[tid] = make_float4((float)cos(dpsi), (float)sin(dpsi), (float)(me.c0 * dx + me.s0 * dy),
                                     (float)(-me.s0 * dx + me.c0 * dy));
-            const float *pj = A.pred_in + (size_t)sj * pred_in_stride_slot;
+            const float *pj = A.pred_in + (size_t)sj * pstride;
             float dsum = 0.0f;
             for (int t = R.N - R.n_tail + 1; t <= R.N; ++t) dsum += pj[t * PRED_STRIDE + 5];
             const double ds0 = me.s_abs - o.s_abs;
@@ -504,7 +520,7 @@ __device__ void stage_block(const LaunchArgs &A, int item_idx, bool with_opp, in
             const int t = e / bs.n_opp + 1;  // tau = 1..N
             const int jo = e - (t - 1) * bs.n_opp;
             const int j = jo < it.agent ? jo : jo + 1;
-            const float *pr = A.pred_in + (size_t)(R.slot0 + j) * pred_in_stride_slot + t * PRED_STRIDE;
+            const float *pr = A.pred_in + (size_t)(R.slot0 + j) * pstride + t * PRED_STRIDE;
             const float4 T = oppT[jo];
             const float px = pr[0], py = pr[1], pc = pr[2], psn = pr[3];
             float2 *dst = opp + ((size_t)(t - 1) * L.n_opp_max + jo) * (NDISC + 1);
@@ -520,150 +536,68 @@ __device__ void stage_block(const LaunchArgs &A, int item_idx, bool with_opp, in
 }
 
 // ------------------------------------------------------------------------------
-// One sample: perturb, clip, roll out, score, check (Sec. III-A, III-B)
+// Per-step terms.  The sweep lanes and the cooperative re-roll call the same
+// functions on the same values and accumulate in the same order, so the
+// re-rolled sample reproduces its lane bit for bit.
 // ------------------------------------------------------------------------------
+__device__ __forceinline__ float2 controls(const KParams &P, float2 ub, float za, float zd) {
+    return make_float2(clip_keep_nan(__builtin_fmaf(P.sigma_a, za, ub.x), P.a_min, P.a_max),
+                       clip_keep_nan(__builtin_fmaf(P.sigma_d, zd, ub.y), P.d_min, P.d_max));
+}
+
+// tracking term of eq. (ctrack) at one step; heading error wrapped to [-pi, pi]
+__device__ __forceinline__ float track_term(const KParams &P, const float *st, float4 xr) {
+    const float ex = st[0] - xr.x, ey = st[1] - xr.y, ev = st[3] - xr.w;
+    float ep = st[2] - xr.z;
+    ep = ep - 6.28318531f * rintf(ep * 0.159154943f);
+    return P.Q0 * ex * ex + P.Q1 * ey * ey + P.Q2 * ep * ep + P.Q3 * ev * ev;
+}
+__device__ __forceinline__ float ctrl_term(const KParams &P, float2 u) { return P.R0 * u.x * u.x + P.R1 * u.y * u.y; }
+__device__ __forceinline__ float rate_term(const KParams &P, float2 u, float2 up) {
+    const float da = u.x - up.x, dd = u.y - up.y;
+    return P.S0 * da * da + P.S1 * dd * dd;
+}
+// boundary clearance of eq. (selection-boundary) at one step
+__device__ __forceinline__ float bound_term(const Foot &f) { return fminf(f.wR + f.d, f.wL - f.d); }
+
+// Squared footprint distance to one opponent at one step (eq. Dmin over disc pairs),
+// folded into `cur` (values are capped at cap^2: only smaller ones change any result;
+// a pair is skipped when the centres are too far apart for any disc pair to go below it).
+template <int NDISC>
+__device__ __forceinline__ float opp_min2(const KParams &P, const float2 *e, float X, float Y, float ch, float sh,
+                                          float cur) {
+    const float2 cg = e[0];
+    const float dx = X - cg.x, dy = Y - cg.y;
+    if (dx * dx + dy * dy < P.skip2) {
+#pragma unroll
+        for (int a = 0; a < NDISC; ++a) {
+            const float ax = __builtin_fmaf(P.off[a], ch, X);
+            const float ay = __builtin_fmaf(P.off[a], sh, Y);
+#pragma unroll
+            for (int b = 0; b < NDISC; ++b) {
+                const float2 c = e[1 + b];
+                const float qx = ax - c.x, qy = ay - c.y;
+                cur = fminf(cur, qx * qx + qy * qy);
+            }
+        }
+    }
+    return cur;
+}
+
 struct SampleResult {
     float cost, viol;
     bool h;
     unsigned char flags;
-    float X, Y, PSI, VX, VY, OM;
+    float st[6];
 };
 
-struct SinkPtrs {  // per-step outputs of the single-lane modes (global memory)
-    float *pred;   // [N+1][PRED_STRIDE]
-    float2 *u;     // [N] adopted controls
-    double *traj;  // [N+1][8] world, or NULL
-    float *noise;  // [N][2] drawn perturbations (sweep debug), or NULL
-    const AgentRec *rec;
-};
-
-template <int MODEL, int NDISC, int MAXOPP, int MODE>
-__device__ __forceinline__ SampleResult eval_sample(const KParams &P, const BlockState &bs, const char *lds,
-                                                   const LdsLayout &L, uint32_t k, const SinkPtrs *sink) {
-    const float2 *ubar = (const float2 *)(lds + L.ubar);
-    const float4 *xref = (const float4 *)(lds + L.xref);
+// Terminal scoring: game-aware cost (eqs. game_cost, c_contest, c_long, c_block,
+// c_safety), total cost (eq. allc), flags b, o, h and the violation nu.
+template <int MAXOPP>
+__device__ __forceinline__ SampleResult terminal(const KParams &P, const BlockState &bs, const char *lds,
+                                                 const LdsLayout &L, float J, float rho_bd, float dsum, float s,
+                                                 const float *g2, bool limit, const float *st) {
     const float4 *oppc = (const float4 *)(lds + L.oppc);
-    const float2 *opp = (const float2 *)(lds + L.opp);
-    const float4 *nodes = (const float4 *)(lds + L.nodes);
-    const VehConst<float> V = veh_f32(P);
-
-    float st[6] = {0.0f, 0.0f, 0.0f, bs.vx0, bs.vy0, bs.om0};
-    int seg = bs.seg0;
-    float J = 0.0f, rho_bd = INFINITY, dsum = 0.0f, s = 0.0f;
-    float g2[MAXOPP];
-#pragma unroll
-    for (int j = 0; j < MAXOPP; ++j) g2[j] = P.cap2;
-    float pa = 0.0f, pd = 0.0f;
-    bool limit = false;
-    float2 zn = make_float2(0.0f, 0.0f);  // perturbation of the odd step of a Philox pair
-    if (MODE != SWEEP) {
-        float *pr = sink->pred;
-        pr[0] = 0.0f; pr[1] = 0.0f; pr[2] = 1.0f; pr[3] = 0.0f; pr[4] = 0.0f; pr[5] = (float)sink->rec->d0;
-        if (sink->traj) {
-            const AgentRec &a = *sink->rec;
-            double *o = sink->traj;
-            o[0] = a.ox; o[1] = a.oy; o[2] = a.psi0; o[3] = bs.vx0; o[4] = bs.vy0; o[5] = bs.om0;
-            o[6] = a.s_abs; o[7] = a.d0;
-        }
-    }
-
-    for (int tau = 0; tau < bs.N; ++tau) {
-        float za = 0.0f, zd = 0.0f;
-        if (MODE != NOMINAL) {
-            if ((tau & 1) == 0) {
-                const uint4 r = philox4x32_10(make_uint4(k, (uint32_t)(tau >> 1), bs.ctr2, bs.ctr3), bs.key0, bs.key1);
-                const float2 z0 = gauss_pair(r.x, r.y);
-                zn = gauss_pair(r.z, r.w);
-                za = z0.x;
-                zd = z0.y;
-            } else {
-                za = zn.x;
-                zd = zn.y;
-            }
-            if (sink->noise) {
-                sink->noise[2 * tau] = za;
-                sink->noise[2 * tau + 1] = zd;
-            }
-        }
-        const float2 ub = ubar[tau];
-        const float ua = clip_keep_nan(__builtin_fmaf(P.sigma_a, za, ub.x), P.a_min, P.a_max);
-        const float ud = clip_keep_nan(__builtin_fmaf(P.sigma_d, zd, ub.y), P.d_min, P.d_max);
-        const StepConst<float> sc = step_const<MODEL, MathF32>(V, ua, ud);
-        rk4<MODEL, MathF32>(V, sc, P.dt, st);
-        const Foot f = project(nodes, bs.W, P.max_moves, st[0], st[1], seg);
-        seg = f.seg;
-        limit |= f.limit;
-        s = f.s;
-
-        // tracking and control cost, eq. (ctrack)
-        const float4 xr = xref[tau];
-        const float ex = st[0] - xr.x, ey = st[1] - xr.y, ev = st[3] - xr.w;
-        float ep = st[2] - xr.z;
-        ep = ep - 6.28318531f * rintf(ep * 0.159154943f);
-        J += P.Q0 * ex * ex + P.Q1 * ey * ey + P.Q2 * ep * ep + P.Q3 * ev * ev;
-        J += P.R0 * ua * ua + P.R1 * ud * ud;
-        if (tau >= 1) {
-            const float da = ua - pa, dd = ud - pd;
-            J += P.S0 * da * da + P.S1 * dd * dd;
-        }
-        pa = ua;
-        pd = ud;
-        // boundary clearance, eq. (selection-boundary)
-        rho_bd = fminf(rho_bd, fminf(f.wR + f.d, f.wL - f.d));
-        // footprint distance to each opponent at the same step, eq. (Dmin); only values
-        // below cap = max(g_safe, d_col) change any cost, flag or violation
-        if (MODE != NOMINAL) {
-            float ch = 1.0f, sh = 0.0f;
-            if (NDISC > 1) {
-                ch = fast_cos(st[2]);
-                sh = fast_sin(st[2]);
-            }
-#pragma unroll
-            for (int j = 0; j < MAXOPP; ++j) {
-                if (j < bs.n_opp) {
-                    const float2 *e = opp + ((size_t)tau * L.n_opp_max + j) * (NDISC + 1);
-                    const float2 cg = e[0];
-                    const float dx = st[0] - cg.x, dy = st[1] - cg.y;
-                    if (dx * dx + dy * dy < P.skip2) {
-                        float m2 = g2[j];
-#pragma unroll
-                        for (int a = 0; a < NDISC; ++a) {
-                            const float ax = __builtin_fmaf(P.off[a], ch, st[0]);
-                            const float ay = __builtin_fmaf(P.off[a], sh, st[1]);
-#pragma unroll
-                            for (int b = 0; b < NDISC; ++b) {
-                                const float2 c = e[1 + b];
-                                const float qx = ax - c.x, qy = ay - c.y;
-                                m2 = fminf(m2, qx * qx + qy * qy);
-                            }
-                        }
-                        g2[j] = m2;
-                    }
-                }
-            }
-        }
-        if (tau + 1 > bs.N - bs.n_tail) dsum += f.d;
-
-        if (MODE != SWEEP) {
-            float *pr = sink->pred + (tau + 1) * PRED_STRIDE;
-            pr[0] = st[0]; pr[1] = st[1]; pr[2] = fast_cos(st[2]); pr[3] = fast_sin(st[2]);
-            pr[4] = f.s; pr[5] = f.d;
-            if (sink->u) sink->u[tau] = make_float2(ua, ud);
-            if (sink->traj) {
-                const AgentRec &a = *sink->rec;
-                double *o = sink->traj + (size_t)(tau + 1) * 8;
-                const double X = st[0], Y = st[1];
-                o[0] = a.ox + a.c0 * X - a.s0 * Y;
-                o[1] = a.oy + a.s0 * X + a.c0 * Y;
-                o[2] = a.psi0 + (double)st[2];
-                o[3] = st[3]; o[4] = st[4]; o[5] = st[5];
-                o[6] = a.s_abs + (double)f.s;
-                o[7] = f.d;
-            }
-        }
-    }
-
-    // game-aware cost, eqs. (game_cost), (c_contest), (c_long), (c_block), (c_safety)
     float cgame = 0.0f, rho_obs = INFINITY;
     const float dbar_i = dsum * bs.inv_n_tail;
 #pragma unroll
@@ -680,7 +614,7 @@ __device__ __forceinline__ SampleResult eval_sample(const KParams &P, const Bloc
             rho_obs = fminf(rho_obs, gj);
         }
     }
-    const float c = J + bs.w_game * cgame;  // eq. (allc)
+    const float c = J + bs.w_game * cgame;
     bool finite = isfinite(c) && !isnan(rho_bd) && !isnan(rho_obs);
 #pragma unroll
     for (int i = 0; i < 6; ++i) finite = finite && isfinite(st[i]);
@@ -691,7 +625,205 @@ __device__ __forceinline__ SampleResult eval_sample(const KParams &P, const Bloc
     res.cost = c;
     res.viol = finite ? fmaxf(0.0f, P.m_bd - rho_bd) + fmaxf(0.0f, P.d_col - rho_obs) : INFINITY;
     res.flags = (unsigned char)((b ? 1 : 0) | (o ? 2 : 0) | (res.h ? 4 : 0) | (limit ? 8 : 0) | (finite ? 0 : 16));
-    res.X = st[0]; res.Y = st[1]; res.PSI = st[2]; res.VX = st[3]; res.VY = st[4]; res.OM = st[5];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) res.st[i] = st[i];
+    return res;
+}
+
+// ------------------------------------------------------------------------------
+// One sample in one lane: perturb, clip, roll out, score, check (Sec. III)
+// ------------------------------------------------------------------------------
+template <int MODEL, int NDISC, int MAXOPP>
+__device__ __forceinline__ SampleResult lane_sample(const KParams &P, const BlockState &bs, const char *lds,
+                                                   const LdsLayout &L, uint32_t k, float *noise_out) {
+    const float2 *ubar = (const float2 *)(lds + L.ubar);
+    const float4 *xref = (const float4 *)(lds + L.xref);
+    const float2 *opp = (const float2 *)(lds + L.opp);
+    const float4 *nodes = (const float4 *)(lds + L.nodes);
+    const VehConst<float> V = veh_f32(P);
+
+    float st[6] = {0.0f, 0.0f, 0.0f, bs.vx0, bs.vy0, bs.om0};
+    int seg = bs.seg0;
+    float J = 0.0f, rho_bd = INFINITY, dsum = 0.0f, s = 0.0f;
+    float g2[MAXOPP];
+#pragma unroll
+    for (int j = 0; j < MAXOPP; ++j) g2[j] = P.cap2;
+    float2 up = make_float2(0.0f, 0.0f);
+    bool limit = false;
+    float2 zn = make_float2(0.0f, 0.0f);  // perturbation of the odd step of a Philox call
+
+    for (int tau = 0; tau < bs.N; ++tau) {
+        float2 z;
+        if ((tau & 1) == 0) {
+            const uint4 r = philox4x32_10(make_uint4(k, (uint32_t)(tau >> 1), bs.ctr2, bs.ctr3), bs.key0, bs.key1);
+            z = gauss_pair(r.x, r.y);
+            zn = gauss_pair(r.z, r.w);
+        } else {
+            z = zn;
+        }
+        if (noise_out) {
+            noise_out[2 * tau] = z.x;
+            noise_out[2 * tau + 1] = z.y;
+        }
+        const float2 u = controls(P, ubar[tau], z.x, z.y);
+        const StepConst<float> sc = step_const<MODEL, MathF32>(V, u.x, u.y);
+        rk4<MODEL, MathF32>(V, sc, P.dt, st);
+        const Foot f = project(nodes, bs.W, P.max_moves, st[0], st[1], seg);
+        seg = f.seg;
+        limit |= f.limit;
+        s = f.s;
+        J += track_term(P, st, xref[tau]);
+        J += ctrl_term(P, u);
+        if (tau >= 1) J += rate_term(P, u, up);
+        up = u;
+        rho_bd = fminf(rho_bd, bound_term(f));
+        float ch = 1.0f, sh = 0.0f;
+        if (NDISC > 1) {
+            ch = fast_cos(st[2]);
+            sh = fast_sin(st[2]);
+        }
+#pragma unroll
+        for (int j = 0; j < MAXOPP; ++j)
+            if (j < bs.n_opp)
+                g2[j] = opp_min2<NDISC>(P, opp + ((size_t)tau * L.n_opp_max + j) * (NDISC + 1), st[0], st[1], ch, sh,
+                                        g2[j]);
+        if (tau + 1 > bs.N - bs.n_tail) dsum += f.d;
+    }
+    return terminal<MAXOPP>(P, bs, lds, L, J, rho_bd, dsum, s, g2, limit, st);
+}
+
+// ------------------------------------------------------------------------------
+// One sample re-rolled by a whole workgroup: controls, per-step terms and output
+// writes in parallel over the horizon; only the dynamics and the projection run
+// serially in thread 0.  MODE WINNER scores the sample; NOMINAL rolls out the
+// unperturbed nominal (predictions only).
+// ------------------------------------------------------------------------------
+struct RerollOut {
+    float *pred;        // [N+1][PRED_STRIDE] owner's frame
+    float2 *u;          // [N] adopted controls (WINNER with adopt), or NULL
+    double *traj;       // [N+1][8] world, or NULL
+    float2 *u_apply;    // first control (final phase), or NULL
+    bool final_shift;   // write the warm start (shifted) instead of the adopted sequence
+};
+
+template <int MODEL, int NDISC, int MAXOPP, int MODE>
+__device__ SampleResult reroll_block(const KParams &P, const LdsLayout &L, const BlockState &bs, char *lds,
+                                     const AgentRec &rec, uint32_t k, const RerollOut &out) {
+    const int tid = threadIdx.x, nth = blockDim.x, N = bs.N;
+    const float2 *ubar = (const float2 *)(lds + L.ubar);
+    const float4 *xref = (const float4 *)(lds + L.xref);
+    const float2 *opp = (const float2 *)(lds + L.opp);
+    const float4 *nodes = (const float4 *)(lds + L.nodes);
+    float2 *wu = (float2 *)(lds + L.rr_u);
+    float4 *wst = (float4 *)(lds + L.rr_st);  // [N][2]: (X, Y, PSI, VX), (VY, OM, -, -)
+    float4 *wf = (float4 *)(lds + L.rr_f);    // [N]: (s, d, wL, wR)
+    float4 *wt = (float4 *)(lds + L.rr_t);    // [N]: (track, control, rate, boundary)
+    float *wg = (float *)(lds + L.rr_g);      // [N][MAXOPP]
+    int *wl = (int *)(lds + L.rr_l);          // [N] search-limit flags
+    const VehConst<float> V = veh_f32(P);
+
+    // A. controls of every step (one Philox call per pair of steps)
+    for (int m = tid; 2 * m < N; m += nth) {
+        float2 z0 = make_float2(0.0f, 0.0f), z1 = z0;
+        if (MODE != NOMINAL) {
+            const uint4 r = philox4x32_10(make_uint4(k, (uint32_t)m, bs.ctr2, bs.ctr3), bs.key0, bs.key1);
+            z0 = gauss_pair(r.x, r.y);
+            z1 = gauss_pair(r.z, r.w);
+        }
+        wu[2 * m] = controls(P, ubar[2 * m], z0.x, z0.y);
+        if (2 * m + 1 < N) wu[2 * m + 1] = controls(P, ubar[2 * m + 1], z1.x, z1.y);
+    }
+    __syncthreads();
+    // B. dynamics and projection, serial over the horizon
+    if (tid == 0) {
+        float st[6] = {0.0f, 0.0f, 0.0f, bs.vx0, bs.vy0, bs.om0};
+        int seg = bs.seg0;
+        for (int tau = 0; tau < N; ++tau) {
+            const float2 u = wu[tau];
+            const StepConst<float> sc = step_const<MODEL, MathF32>(V, u.x, u.y);
+            rk4<MODEL, MathF32>(V, sc, P.dt, st);
+            const Foot f = project(nodes, bs.W, P.max_moves, st[0], st[1], seg);
+            seg = f.seg;
+            wst[2 * tau] = make_float4(st[0], st[1], st[2], st[3]);
+            wst[2 * tau + 1] = make_float4(st[4], st[5], 0.0f, 0.0f);
+            wf[tau] = make_float4(f.s, f.d, f.wL, f.wR);
+            wl[tau] = f.limit ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    // C. per-step terms, clearances and outputs, parallel over the horizon
+    for (int tau = tid; tau < N; tau += nth) {
+        const float4 a = wst[2 * tau], b = wst[2 * tau + 1];
+        const float st[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
+        const float4 fv = wf[tau];
+        const float2 u = wu[tau];
+        if (MODE == WINNER) {
+            Foot f;
+            f.s = fv.x; f.d = fv.y; f.wL = fv.z; f.wR = fv.w;
+            wt[tau] = make_float4(track_term(P, st, xref[tau]), ctrl_term(P, u),
+                                  tau >= 1 ? rate_term(P, u, wu[tau - 1]) : 0.0f, bound_term(f));
+            float ch = 1.0f, sh = 0.0f;
+            if (NDISC > 1) {
+                ch = fast_cos(st[2]);
+                sh = fast_sin(st[2]);
+            }
+#pragma unroll
+            for (int j = 0; j < MAXOPP; ++j)
+                if (j < bs.n_opp)
+                    wg[tau * MAXOPP + j] = opp_min2<NDISC>(P, opp + ((size_t)tau * L.n_opp_max + j) * (NDISC + 1),
+                                                           st[0], st[1], ch, sh, P.cap2);
+        }
+        float *pr = out.pred + (tau + 1) * PRED_STRIDE;
+        pr[0] = st[0]; pr[1] = st[1]; pr[2] = fast_cos(st[2]); pr[3] = fast_sin(st[2]);
+        pr[4] = fv.x; pr[5] = fv.y; pr[6] = 0.0f; pr[7] = 0.0f;
+        if (out.u) out.u[tau] = out.final_shift ? wu[tau + 1 < N ? tau + 1 : N - 1] : u;
+        if (out.traj) {
+            double *o = out.traj + (size_t)(tau + 1) * 8;
+            const double X = st[0], Y = st[1];
+            o[0] = rec.ox + rec.c0 * X - rec.s0 * Y;
+            o[1] = rec.oy + rec.s0 * X + rec.c0 * Y;
+            o[2] = rec.psi0 + (double)st[2];
+            o[3] = st[3]; o[4] = st[4]; o[5] = st[5];
+            o[6] = rec.s_abs + (double)fv.x;
+            o[7] = fv.y;
+        }
+    }
+    if (tid == 0) {
+        float *pr = out.pred;
+        pr[0] = 0.0f; pr[1] = 0.0f; pr[2] = 1.0f; pr[3] = 0.0f; pr[4] = 0.0f; pr[5] = (float)rec.d0;
+        pr[6] = 0.0f; pr[7] = 0.0f;
+        if (out.traj) {
+            double *o = out.traj;
+            o[0] = rec.ox; o[1] = rec.oy; o[2] = rec.psi0; o[3] = bs.vx0; o[4] = bs.vy0; o[5] = bs.om0;
+            o[6] = rec.s_abs; o[7] = rec.d0;
+        }
+        if (out.u_apply) *out.u_apply = wu[0];
+    }
+    __syncthreads();
+    // D. accumulate in the lanes' order and score
+    SampleResult res{};
+    if (MODE == WINNER && tid == 0) {
+        float J = 0.0f, rho_bd = INFINITY, dsum = 0.0f;
+        float g2[MAXOPP];
+#pragma unroll
+        for (int j = 0; j < MAXOPP; ++j) g2[j] = P.cap2;
+        bool limit = false;
+        for (int tau = 0; tau < N; ++tau) {
+            const float4 t4 = wt[tau];
+            J += t4.x;
+            J += t4.y;
+            if (tau >= 1) J += t4.z;
+            rho_bd = fminf(rho_bd, t4.w);
+#pragma unroll
+            for (int j = 0; j < MAXOPP; ++j)
+                if (j < bs.n_opp) g2[j] = fminf(g2[j], wg[tau * MAXOPP + j]);
+            limit |= wl[tau] != 0;
+            if (tau + 1 > N - bs.n_tail) dsum += wf[tau].y;
+        }
+        const float4 a = wst[2 * (N - 1)], b = wst[2 * (N - 1) + 1];
+        const float st[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
+        res = terminal<MAXOPP>(P, bs, lds, L, J, rho_bd, dsum, wf[N - 1].x, g2, limit, st);
+    }
     return res;
 }
 
@@ -707,22 +839,26 @@ __device__ __forceinline__ int find_item(const ItemDev *items, int n, int tile) 
     return lo;
 }
 
+// Sweep: every sample of every participating vehicle.  The last workgroup of a
+// vehicle to finish (device-scope counter) reads the selection and re-rolls it
+// with the tables it already holds in LDS.
 template <int MODEL, int NDISC, int MAXOPP>
 __global__ void __launch_bounds__(BLOCK) k_sweep(LaunchArgs A) {
     extern __shared__ __align__(16) char lds[];
+    __shared__ int s_last;
     const int tile = blockIdx.x;
     const int item = find_item(A.items, A.n_items, tile);
     BlockState bs;
-    stage_block<NDISC>(A, item, true, (A.L.N_max + 1) * PRED_STRIDE, bs, lds);
+    stage_block<NDISC>(A, item, bs, lds);
     const int lane = threadIdx.x & 63;
-    const int local_tile = tile - A.items[item].tile0;
-    const bool dbg = A.dbg_cost || A.dbg_flags || A.dbg_viol || A.dbg_xfinal || A.dbg_noise;
+    const int t0 = A.items[item].tile0;
+    const int n_tiles_item = (item + 1 < A.n_items ? A.items[item + 1].tile0 : A.n_tiles) - t0;
+    const int local_tile = tile - t0;
     for (int r = 0; r < A.spl; ++r) {
         const uint32_t k = (uint32_t)((local_tile * A.spl + r) * BLOCK + threadIdx.x);
         const bool valid = k < (uint32_t)bs.K;
-        SinkPtrs sk{};
-        sk.noise = (A.dbg_noise && valid) ? A.dbg_noise + (size_t)k * bs.N * 2 : nullptr;
-        const SampleResult res = eval_sample<MODEL, NDISC, MAXOPP, SWEEP>(A.P, bs, lds, A.L, valid ? k : 0u, &sk);
+        float *nz = (A.dbg_noise && valid) ? A.dbg_noise + (size_t)k * bs.N * 2 : nullptr;
+        const SampleResult res = lane_sample<MODEL, NDISC, MAXOPP>(A.P, bs, lds, A.L, valid ? k : 0u, nz);
         const unsigned long long key = valid ? make_key(res.h, res.h ? res.cost : res.viol, k) : KEY_NONE;
         const unsigned long long wmin = wave_min_u64(key);
         const unsigned long long feas = __ballot(valid && res.h);
@@ -731,69 +867,70 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(LaunchArgs A) {
             const int cnt = __popcll(feas);
             if (cnt) atomicAdd(A.nfeas + bs.slot, cnt);
         }
-        if (dbg && valid) {
+        if (valid) {
             if (A.dbg_cost) A.dbg_cost[k] = res.cost;
             if (A.dbg_viol) A.dbg_viol[k] = res.viol;
             if (A.dbg_flags) A.dbg_flags[k] = res.flags;
             if (A.dbg_xfinal) {
                 const AgentRec &a = A.agents[bs.slot];
                 double *o = A.dbg_xfinal + (size_t)k * 6;
-                const double X = res.X, Y = res.Y;
+                const double X = res.st[0], Y = res.st[1];
                 o[0] = a.ox + a.c0 * X - a.s0 * Y;
                 o[1] = a.oy + a.s0 * X + a.c0 * Y;
-                o[2] = a.psi0 + (double)res.PSI;
-                o[3] = res.VX; o[4] = res.VY; o[5] = res.OM;
+                o[2] = a.psi0 + (double)res.st[2];
+                o[3] = res.st[3]; o[4] = res.st[4]; o[5] = res.st[5];
             }
         }
     }
-}
-
-// One lane re-rolls a single sample per vehicle: the nominal (NOMINAL) or the
-// selected one (WINNER), writing the prediction of the next sweep and, for the
-// winner, the adopted controls, the world trajectory and the choice record.
-template <int MODEL, int NDISC, int MAXOPP, int MODE>
-__global__ void __launch_bounds__(SINGLE_BLOCK) k_single(LaunchArgs A) {
-    extern __shared__ __align__(16) char lds[];
-    const int item = blockIdx.x;
-    BlockState bs;
-    stage_block<NDISC>(A, item, MODE == WINNER, (A.L.N_max + 1) * PRED_STRIDE, bs, lds);
-    if (threadIdx.x != 0) return;
+    // hand-off: the last workgroup of this vehicle re-rolls the selected sample
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        s_last = atomicAdd(A.counters + bs.slot, 1) == n_tiles_item - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    const unsigned long long key = atomicMin(A.keys + bs.slot, KEY_NONE);  // current value
+    const int nfeas = atomicAdd(A.nfeas + bs.slot, 0);
+    uint32_t k = (uint32_t)(key & 0x7fffffffu);
+    if (k >= (uint32_t)bs.K) k = 0;
     const ItemDev it = A.items[item];
     const RaceDev R = A.races[it.race];
-    uint32_t k = 0;
-    unsigned long long key = KEY_NONE;
-    if (MODE == WINNER) {
-        key = A.keys[bs.slot];
-        k = (uint32_t)(key & 0x7fffffffu);
-        if (k >= (uint32_t)bs.K) k = 0;
+    const AgentRec rec = A.agents[bs.slot];
+    RerollOut out{};
+    out.pred = A.pred_out + (size_t)bs.slot * (A.L.N_max + 1) * PRED_STRIDE;
+    const bool final_phase = A.final_mode == 2 || (A.final_mode == 1 && it.agent != R.ego);
+    if (A.adopt) {
+        out.u = (float2 *)(R.u_nom) + (size_t)it.agent * R.N;
+        out.traj = R.traj ? R.traj + (size_t)it.agent * (R.N + 1) * 8 : nullptr;
+        out.final_shift = final_phase;
+        out.u_apply = (final_phase && A.u_apply) ? A.u_apply + bs.slot : nullptr;
     }
-    SinkPtrs sk{};
-    sk.pred = A.pred_out + (size_t)bs.slot * (A.L.N_max + 1) * PRED_STRIDE;
-    sk.rec = A.agents + bs.slot;
-    float2 *u_nom = (float2 *)(R.u_nom) + (size_t)it.agent * R.N;
-    if (MODE == WINNER && A.adopt) {
-        sk.u = u_nom;  // the staged copy in LDS is what this lane reads
-        sk.traj = R.traj ? R.traj + (size_t)it.agent * (R.N + 1) * 8 : nullptr;
-    }
-    const SampleResult res = eval_sample<MODEL, NDISC, MAXOPP, MODE>(A.P, bs, lds, A.L, k, &sk);
-    if (MODE == WINNER) {
+    const SampleResult res = reroll_block<MODEL, NDISC, MAXOPP, WINNER>(A.P, A.L, bs, lds, rec, k, out);
+    if (threadIdx.x == 0) {
         if (A.choice) {
             sgtp_choice c;
             c.k = (int)k;
             c.fallback = (key >> 63) ? 1 : 0;
-            c.n_feasible = A.nfeas[bs.slot];
+            c.n_feasible = nfeas;
             c.cost = res.cost;
             c.viol = res.viol;
             A.choice[bs.slot - A.choice_base] = c;
         }
         A.keys[bs.slot] = KEY_NONE;
         A.nfeas[bs.slot] = 0;
+        A.counters[bs.slot] = 0;
     }
 }
 
-// Global projection of each vehicle's current state, local frame, reference
-// states (Sec. III-A: s^r recursion over v^r) and the raceline window.
+// Setup of every vehicle: global Frenet projection of the current state,
+// unwrapped progress, local frame, raceline window, reference states
+// (Sec. III-A: s^r recursion over v^r) and the noise-free rollout of the
+// nominal sequence (initial prediction).
+template <int MODEL>
 __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
+    extern __shared__ __align__(16) char lds[];
     __shared__ double red_v[BLOCK];
     __shared__ long long red_i[BLOCK];
     __shared__ double sh[8];
@@ -807,7 +944,7 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
     const long long n = T.n;
     const long long nseg = T.closed ? n : n - 1;
 
-    auto node = [&](long long i, double *o) {  // unwrapped node access
+    auto node = [&](long long i, double *o) {  // unwrapped node access (float64 row)
         long long lap = 0, b = i;
         if (T.closed) {
             lap = i / n;
@@ -827,8 +964,7 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
         node(i, nd);
         return (px - nd[0]) * nd[4] - (py - nd[1]) * nd[3];
     };
-    // foot on segment i (float64, same construction as the lanes use in float32)
-    auto foot = [&](long long i, double *o /* s, d, t, wL, wR */) {
+    auto foot = [&](long long i, double *o /* s, d, t */) {
         double a[NODE_STRIDE], b[NODE_STRIDE];
         node(i, a);
         node(i + 1, b);
@@ -849,54 +985,10 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
         o[0] = a[8] + t * (b[8] - a[8]);
         o[1] = ((px - cx) * nx + (py - cy) * ny) / sqrt(nx * nx + ny * ny);
         o[2] = t;
-        o[3] = a[5] + t * (b[5] - a[5]);
-        o[4] = a[6] + t * (b[6] - a[6]);
     };
-
-    // 1. global projection: smallest |d| among enclosing segments, lowest index on ties
-    double best = INFINITY;
-    long long bi = -1;
-    for (long long i = tid; i < nseg; i += BLOCK) {
-        if (ahead(i) >= 0.0 && ahead(i + 1) <= 0.0) {
-            double o[5];
-            foot(i, o);
-            const double ad = fabs(o[1]);
-            if (ad < best) {
-                best = ad;
-                bi = i;
-            }
-        }
-    }
-    red_v[tid] = best;
-    red_i[tid] = bi;
-    __syncthreads();
-    for (int w = BLOCK / 2; w > 0; w >>= 1) {
-        if (tid < w) {
-            const double v2 = red_v[tid + w];
-            const long long i2 = red_i[tid + w];
-            if (i2 >= 0 && (red_i[tid] < 0 || v2 < red_v[tid] || (v2 == red_v[tid] && i2 < red_i[tid]))) {
-                red_v[tid] = v2;
-                red_i[tid] = i2;
-            }
-        }
-        __syncthreads();
-    }
-    long long seg = red_i[0];
-    __syncthreads();
-    if (seg < 0) {  // no enclosing segment: the one starting at the nearest node
-        best = INFINITY;
-        bi = -1;
-        for (long long i = tid; i < nseg; i += BLOCK) {
-            double nd[NODE_STRIDE];
-            node(i, nd);
-            const double dd = (px - nd[0]) * (px - nd[0]) + (py - nd[1]) * (py - nd[1]);
-            if (dd < best) {
-                best = dd;
-                bi = i;
-            }
-        }
-        red_v[tid] = best;
-        red_i[tid] = bi;
+    auto block_argmin = [&](double v, long long i) {  // smallest v, lowest index on ties (i < 0: none)
+        red_v[tid] = v;
+        red_i[tid] = i;
         __syncthreads();
         for (int w = BLOCK / 2; w > 0; w >>= 1) {
             if (tid < w) {
@@ -909,12 +1001,44 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
             }
             __syncthreads();
         }
-        seg = red_i[0];
+        const long long r = red_i[0];
+        __syncthreads();
+        return r;
+    };
+
+    // 1. global projection: smallest |d| among enclosing segments, lowest index on ties
+    double best = INFINITY;
+    long long bi = -1;
+    for (long long i = tid; i < nseg; i += BLOCK) {
+        if (ahead(i) >= 0.0 && ahead(i + 1) <= 0.0) {
+            double o[3];
+            foot(i, o);
+            const double ad = fabs(o[1]);
+            if (ad < best) {
+                best = ad;
+                bi = i;
+            }
+        }
+    }
+    long long seg = block_argmin(best, bi);
+    if (seg < 0) {  // no enclosing segment: the one starting at the nearest node
+        best = INFINITY;
+        bi = -1;
+        for (long long i = tid; i < nseg; i += BLOCK) {
+            double nd[NODE_STRIDE];
+            node(i, nd);
+            const double dd = (px - nd[0]) * (px - nd[0]) + (py - nd[1]) * (py - nd[1]);
+            if (dd < best) {
+                best = dd;
+                bi = i;
+            }
+        }
+        seg = block_argmin(best, bi);
     }
 
-    // 2. unwrap progress, frame, window size, reference states (one thread)
+    // 2. unwrapped progress, frame and window extent
     if (tid == 0) {
-        double o[5];
+        double o[3];
         foot(seg, o);
         double s = o[0];
         const double sp = R.s_abs[it.agent];
@@ -929,7 +1053,10 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
         const double vx = xs[3] > 0.0 ? xs[3] : 0.0, vy = xs[4];
         const double v = sqrt(vx * vx + vy * vy);
         const double Th = (double)R.N * (double)A.P.dt;
-        const double reach = v * Th + 0.5 * (double)(A.P.a_max > 0.f ? A.P.a_max : 0.f) * Th * Th + 10.0;
+        const double lam = (double)R.v_scale[it.agent];
+        const double reach_samples = v * Th + 0.5 * (double)(A.P.a_max > 0.f ? A.P.a_max : 0.f) * Th * Th;
+        const double reach_ref = (lam > 1.0 ? lam : 1.0) * T.vmax * Th;
+        const double reach = (reach_samples > reach_ref ? reach_samples : reach_ref) + 10.0;
         long long W = WIN_BACK + (long long)ceil(T.inner_factor * reach / T.ds_min) + 8;
         if (W > w_limit) W = w_limit;
         long long win0 = seg - WIN_BACK;
@@ -945,76 +1072,103 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
         rec.vx = (float)xs[3]; rec.vy = (float)xs[4]; rec.om = (float)xs[5];
         rec.lam = R.v_scale[it.agent];
         A.agents[it.slot] = rec;
-        sh[0] = c0; sh[1] = s0; sh[2] = psi0; sh[3] = s;
-        shl[0] = win0; shl[1] = W;
-
-        // reference: s^r_{t+1} = s^r_t + dt lam v^r(s^r_t); x^r at s^r_{t+1} (linear interpolation)
-        float4 *xr = (float4 *)(A.xref + (size_t)it.slot * A.L.N_max);
-        const double lam = (double)rec.lam, dt = (double)A.P.dt;
-        long long hint = seg;
-        double sr = s;
-        double psi_shift = 0.0;
-        auto interp = [&](double sq, double *out /* x, y, psi, v */) {
-            for (int guard = 0; guard < 1 << 20; ++guard) {
-                double a[NODE_STRIDE], b[NODE_STRIDE];
-                node(hint, a);
-                node(hint + 1, b);
-                const bool can_back = T.closed || hint > 0;
-                const bool can_fwd = T.closed || hint + 1 <= n - 2;
-                if (sq < a[8] && can_back) { --hint; continue; }
-                if (sq >= b[8] && can_fwd) { ++hint; continue; }
-                double t = (sq - a[8]) / (b[8] - a[8]);
-                if (t < 0.0) t = 0.0;
-                if (t > 1.0) t = 1.0;
-                out[0] = a[0] + t * (b[0] - a[0]);
-                out[1] = a[1] + t * (b[1] - a[1]);
-                out[2] = a[2] + t * (b[2] - a[2]);
-                out[3] = a[7] + t * (b[7] - a[7]);
-                break;
-            }
-        };
-        for (int t = 0; t < R.N; ++t) {
-            double q[4];
-            interp(sr, q);
-            sr = sr + dt * lam * q[3];
-            interp(sr, q);
-            const double dx = q[0] - px, dy = q[1] - py;
-            double dpsi = q[2] - psi0;
-            if (t == 0) psi_shift = 6.283185307179586 * rint(dpsi / 6.283185307179586);
-            dpsi -= psi_shift;
-            xr[t] = make_float4((float)(c0 * dx + s0 * dy), (float)(-s0 * dx + c0 * dy), (float)dpsi,
-                                (float)(lam * q[3]));
-        }
+        sh[0] = c0; sh[1] = s0; sh[2] = psi0; sh[3] = s; sh[4] = lam;
+        shl[0] = win0; shl[1] = W; shl[2] = seg - win0;
         A.keys[it.slot] = KEY_NONE;
         A.nfeas[it.slot] = 0;
+        A.counters[it.slot] = 0;
     }
     __syncthreads();
+    const double c0 = sh[0], s0 = sh[1], psi0 = sh[2], sa = sh[3], lam = sh[4];
+    const long long win0 = shl[0], W = shl[1], segl = shl[2];
 
-    // 3. raceline window in the local frame: A = (x, y, nx, ny), B = (wL, wR, s - s_abs, 0)
-    const double c0 = sh[0], s0 = sh[1], psi0 = sh[2], sa = sh[3];
-    const long long win0 = shl[0], W = shl[1];
+    // 3. raceline window in the local frame to HBM: A = (x, y, nx, ny), B = (wL, wR, s - s_abs, 0);
+    //    arc length and reference speed of the window nodes to LDS (float64) for the recursion
     float4 *dst = (float4 *)(A.win + (size_t)it.slot * WIN_MAX * 2);
+    double2 *sv = (double2 *)(lds + A.L.nodes);  // reused below for the float32 window
     for (long long w = tid; w < W; w += BLOCK) {
         double nd[NODE_STRIDE];
         node(win0 + w, nd);
         const double dx = nd[0] - px, dy = nd[1] - py;
-        // local normal = world normal rotated by -psi0
         const double nxl = c0 * nd[3] + s0 * nd[4], nyl = -s0 * nd[3] + c0 * nd[4];
         dst[2 * w] = make_float4((float)(c0 * dx + s0 * dy), (float)(-s0 * dx + c0 * dy), (float)nxl, (float)nyl);
         dst[2 * w + 1] = make_float4((float)nd[5], (float)nd[6], (float)(nd[8] - sa), 0.0f);
+        sv[w] = make_double2(nd[8], nd[7]);
     }
-    (void)psi0;
-}
-
-// First control of the final plan, then the warm start: shift by one, repeat the last.
-__global__ void k_apply(const RaceDev *races, const ItemDev *items, int n_items, float2 *u_apply) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_items) return;
-    const ItemDev it = items[i];
-    const RaceDev R = races[it.race];
-    float2 *u = (float2 *)(R.u_nom) + (size_t)it.agent * R.N;
-    u_apply[i] = u[0];
-    for (int t = 0; t + 1 < R.N; ++t) u[t] = u[t + 1];
+    __syncthreads();
+    // 4. s^r recursion (thread 0, LDS only): s^r_{t+1} = s^r_t + dt lam v^r(s^r_t)
+    double *srs = (double *)(lds + A.L.rr_st);  // N values
+    long long *segs = (long long *)(lds + A.L.rr_t);
+    if (tid == 0) {
+        long long h = segl;
+        double sr = sa;
+        const double dt = (double)A.P.dt;
+        auto seek = [&](double q) {  // segment of the window holding q (clamped to the window)
+            while (q < sv[h].x && h > 0) --h;
+            while (h + 2 < W && q >= sv[h + 1].x) ++h;
+        };
+        for (int t = 0; t < R.N; ++t) {
+            seek(sr);
+            double tt = (sr - sv[h].x) / (sv[h + 1].x - sv[h].x);
+            tt = tt < 0.0 ? 0.0 : (tt > 1.0 ? 1.0 : tt);
+            const double v = sv[h].y + tt * (sv[h + 1].y - sv[h].y);
+            sr = sr + dt * lam * v;
+            seek(sr);
+            srs[t] = sr;
+            segs[t] = h;
+        }
+    }
+    __syncthreads();
+    // 5. reference states x^r(s^r_t), t = 1..N, in the local frame (heading shifted by a
+    //    multiple of 2 pi so it starts near the vehicle's heading)
+    float4 *xr = (float4 *)(A.xref + (size_t)it.slot * A.L.N_max);
+    float4 *xr_l = (float4 *)(lds + A.L.xref);
+    for (int t = tid; t < R.N; t += BLOCK) {
+        const long long h = segs[t];
+        double a[NODE_STRIDE], b[NODE_STRIDE];
+        node(win0 + h, a);
+        node(win0 + h + 1, b);
+        double tt = (srs[t] - a[8]) / (b[8] - a[8]);
+        tt = tt < 0.0 ? 0.0 : (tt > 1.0 ? 1.0 : tt);
+        const double x = a[0] + tt * (b[0] - a[0]), y = a[1] + tt * (b[1] - a[1]);
+        const double ps = a[2] + tt * (b[2] - a[2]), v = a[7] + tt * (b[7] - a[7]);
+        double a0[NODE_STRIDE], b0[NODE_STRIDE];
+        node(win0 + segs[0], a0);
+        node(win0 + segs[0] + 1, b0);
+        double t0 = (srs[0] - a0[8]) / (b0[8] - a0[8]);
+        t0 = t0 < 0.0 ? 0.0 : (t0 > 1.0 ? 1.0 : t0);
+        const double ps0 = a0[2] + t0 * (b0[2] - a0[2]);
+        const double shift = 6.283185307179586 * rint((ps0 - psi0) / 6.283185307179586);
+        const double dx = x - px, dy = y - py;
+        const float4 q = make_float4((float)(c0 * dx + s0 * dy), (float)(-s0 * dx + c0 * dy),
+                                     (float)(ps - psi0 - shift), (float)(lam * v));
+        xr[t] = q;
+        xr_l[t] = q;
+    }
+    __syncthreads();
+    // 6. stage the float32 window and the nominal, roll the nominal out (predictions)
+    float4 *nodes_l = (float4 *)(lds + A.L.nodes);
+    for (long long w = tid; w < W; w += BLOCK) {
+        double nd[NODE_STRIDE];
+        node(win0 + w, nd);
+        const double dx = nd[0] - px, dy = nd[1] - py;
+        const double nxl = c0 * nd[3] + s0 * nd[4], nyl = -s0 * nd[3] + c0 * nd[4];
+        nodes_l[2 * w] = make_float4((float)(c0 * dx + s0 * dy), (float)(-s0 * dx + c0 * dy), (float)nxl, (float)nyl);
+        nodes_l[2 * w + 1] = make_float4((float)nd[5], (float)nd[6], (float)(nd[8] - sa), 0.0f);
+    }
+    float2 *ubar = (float2 *)(lds + A.L.ubar);
+    const float2 *un = (const float2 *)(R.u_nom) + (size_t)it.agent * R.N;
+    for (int t = tid; t < R.N; t += BLOCK) ubar[t] = un[t];
+    __syncthreads();
+    BlockState bs{};
+    bs.slot = it.slot; bs.race = it.race; bs.agent = it.agent; bs.N = R.N; bs.n_tail = R.n_tail; bs.K = R.K;
+    bs.n_opp = 0; bs.W = (int)W; bs.seg0 = (int)segl;
+    bs.vx0 = (float)xs[3]; bs.vy0 = (float)xs[4]; bs.om0 = (float)xs[5];
+    bs.inv_n_tail = 1.0f / (float)R.n_tail; bs.w_game = 0.0f;
+    const AgentRec rec = A.agents[it.slot];
+    RerollOut out{};
+    out.pred = A.pred_out + (size_t)it.slot * (A.L.N_max + 1) * PRED_STRIDE;
+    reroll_block<MODEL, 1, 1, NOMINAL>(A.P, A.L, bs, lds, rec, 0u, out);
 }
 
 // Closed loop: one float64 RK4 interval per vehicle.
@@ -1057,6 +1211,7 @@ struct sgtp_ctx {
     float *d_pred[2] = {nullptr, nullptr};
     unsigned long long *d_keys = nullptr;
     int *d_nfeas = nullptr;
+    int *d_counters = nullptr;
     // descriptor uploads: pinned ring, each slot guarded by an event
     static constexpr int RING = 8;
     char *h_stage[RING] = {};
@@ -1118,6 +1273,7 @@ KParams make_kparams(const sgtp_params *p) {
     k.muFzf = (float)((double)p->mu * p->m * p->g * p->lr / L);
     k.muFzr = (float)((double)p->mu * p->m * p->g * p->lf / L);
     k.B = p->B; k.C = p->C; k.v_eps = p->v_eps;
+    k.C_rev = (float)((double)p->C / (2.0 * M_PI));
     k.lr_over_L = (float)(p->lr / L);
     k.inv_lr = (float)(1.0 / p->lr);
     return k;
@@ -1130,6 +1286,7 @@ VehConst<double> make_veh64(const sgtp_params *p) {
     V.muFzf = (double)p->mu * p->m * p->g * p->lr / L;
     V.muFzr = (double)p->mu * p->m * p->g * p->lf / L;
     V.B = p->B; V.C = p->C; V.v_eps = p->v_eps; V.lr_over_L = p->lr / L; V.inv_lr = 1.0 / p->lr;
+    V.Cs = p->C;
     return V;
 }
 
@@ -1224,6 +1381,12 @@ LdsLayout make_layout(const Plan &pl, int maxopp, int ndisc) {
     L.oppc = take(L.n_opp_max * 16);
     L.opp = take(pl.N_max * L.n_opp_max * (ndisc + 1) * 8);
     L.nodes = take(pl.w_max * 32);
+    L.rr_u = take(pl.N_max * 8);
+    L.rr_st = take(pl.N_max * 32);
+    L.rr_f = take(pl.N_max * 16);
+    L.rr_t = take(pl.N_max * 16);
+    L.rr_g = take(pl.N_max * std::max(1, maxopp) * 4);
+    L.rr_l = take(pl.N_max * 4);
     L.total = off;
     return L;
 }
@@ -1269,32 +1432,22 @@ template <int MODEL, int NDISC, int MAXOPP>
 void launch_sweep_t(const LaunchArgs &A, hipStream_t st) {
     hipLaunchKernelGGL((k_sweep<MODEL, NDISC, MAXOPP>), dim3(A.n_tiles), dim3(BLOCK), A.L.total, st, A);
 }
-template <int MODEL, int NDISC, int MAXOPP, int MODE>
-void launch_single_t(const LaunchArgs &A, hipStream_t st) {
-    hipLaunchKernelGGL((k_single<MODEL, NDISC, MAXOPP, MODE>), dim3(A.n_items), dim3(SINGLE_BLOCK), A.L.total, st, A);
-}
 
 template <int MODEL, int NDISC>
-void dispatch_opp(int mo, int which, const LaunchArgs &A, hipStream_t st) {
-#define SGTP_CASE(MO)                                                           \
-    if (mo == MO) {                                                             \
-        if (which == 0) launch_sweep_t<MODEL, NDISC, MO>(A, st);                \
-        else if (which == 1) launch_single_t<MODEL, NDISC, MO, WINNER>(A, st);  \
-        else launch_single_t<MODEL, 1, 1, NOMINAL>(A, st);                      \
-        return;                                                                 \
-    }
-    SGTP_CASE(1) SGTP_CASE(3) SGTP_CASE(9) SGTP_CASE(15)
-#undef SGTP_CASE
+void dispatch_opp(int mo, const LaunchArgs &A, hipStream_t st) {
+    if (mo == 1) launch_sweep_t<MODEL, NDISC, 1>(A, st);
+    else if (mo == 3) launch_sweep_t<MODEL, NDISC, 3>(A, st);
+    else if (mo == 9) launch_sweep_t<MODEL, NDISC, 9>(A, st);
+    else launch_sweep_t<MODEL, NDISC, 15>(A, st);
 }
 
-// which: 0 sweep, 1 winner, 2 nominal
-void dispatch(int model, int ndisc, int mo, int which, const LaunchArgs &A, hipStream_t st) {
+void dispatch_sweep(int model, int ndisc, int mo, const LaunchArgs &A, hipStream_t st) {
     if (model == 0) {
-        if (ndisc == 1) dispatch_opp<0, 1>(mo, which, A, st);
-        else dispatch_opp<0, 3>(mo, which, A, st);
+        if (ndisc == 1) dispatch_opp<0, 1>(mo, A, st);
+        else dispatch_opp<0, 3>(mo, A, st);
     } else {
-        if (ndisc == 1) dispatch_opp<1, 1>(mo, which, A, st);
-        else dispatch_opp<1, 3>(mo, which, A, st);
+        if (ndisc == 1) dispatch_opp<1, 1>(mo, A, st);
+        else dispatch_opp<1, 3>(mo, A, st);
     }
 }
 
@@ -1313,12 +1466,12 @@ struct Runner {
         if (rc) return rc;
         rc = build_plan(c, p, races, n_races, 1, pl, one_agent);
         if (rc) return rc;
-        rc = upload_plan(c, pl, st, &d_races, &d_all, &d_ego, &d_one);
-        if (rc) return rc;
         mo = maxopp_bucket(pl.n_opp_max);
         A.P = make_kparams(p);
         A.L = make_layout(pl, mo, p->n_disc);
-        if (A.L.total > 64 * 1024) return fail(c, SGTP_ESHAPE, "staged tables exceed 64 KiB of LDS");
+        if (A.L.total > 58 * 1024) return fail(c, SGTP_ESHAPE, "staged tables exceed the LDS budget");
+        rc = upload_plan(c, pl, st, &d_races, &d_all, &d_ego, &d_one);
+        if (rc) return rc;
         A.tracks = c->d_tracks;
         A.races = d_races;
         A.agents = c->d_agents;
@@ -1326,63 +1479,56 @@ struct Runner {
         A.xref = c->d_xref;
         A.keys = c->d_keys;
         A.nfeas = c->d_nfeas;
+        A.counters = c->d_counters;
         A.spl = 1;
         return SGTP_OK;
     }
-    int setup_all() {  // projection, frames, references, windows, initial predictions
+    // projection, frames, windows, references, initial predictions (into pred[0])
+    int setup_all() {
         LaunchArgs a = A;
         a.items = d_all;
         a.n_items = (int)pl.all.size();
-        // every vehicle of every race needs a frame (opponents included)
-        if (pl.all.size() != (size_t)pl.agents_total) return fail(c, SGTP_EINVAL, "internal: setup needs all vehicles");
-        hipLaunchKernelGGL(k_setup, dim3(a.n_items), dim3(BLOCK), 0, st, a, pl.w_max);
-        a.pred_in = c->d_pred[1];
         a.pred_out = c->d_pred[0];
-        a.phase = 0;
-        dispatch(p->model, p->n_disc, mo, 2, a, st);
+        if (p->model == 0)
+            hipLaunchKernelGGL(k_setup<0>, dim3(a.n_items), dim3(BLOCK), A.L.total, st, a, pl.w_max);
+        else
+            hipLaunchKernelGGL(k_setup<1>, dim3(a.n_items), dim3(BLOCK), A.L.total, st, a, pl.w_max);
         HIPCHK(c, hipGetLastError());
         return SGTP_OK;
     }
-    int sweep(const ItemDev *items, int n_items, int n_tiles, int phase, int par) {
-        LaunchArgs a = A;
+    // one sweep over `items` reading predictions pred[par]; the selected samples are
+    // re-rolled in the same launch and write pred[par ^ 1]
+    int sweep(const ItemDev *items, const std::vector<ItemDev> &host_items, int n_tiles, int phase, int par,
+              sgtp_choice *choice, int choice_base, int adopt, int final_mode, float *u_apply,
+              const LaunchArgs *dbg = nullptr) {
+        LaunchArgs a = dbg ? *dbg : A;
         a.items = items;
-        a.n_items = n_items;
+        a.n_items = (int)host_items.size();
         a.n_tiles = n_tiles;
         a.phase = phase;
         a.pred_in = c->d_pred[par];
+        a.pred_out = c->d_pred[par ^ 1];
+        a.choice = choice;
+        a.choice_base = choice_base;
+        a.adopt = adopt;
+        a.final_mode = final_mode;
+        a.u_apply = (float2 *)u_apply;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->timing) {
             HIPCHK(c, hipEventCreate(&e0));
             HIPCHK(c, hipEventCreate(&e1));
             HIPCHK(c, hipEventRecord(e0, st));
         }
-        dispatch(p->model, p->n_disc, mo, 0, a, st);
+        dispatch_sweep(p->model, p->n_disc, mo, a, st);
         HIPCHK(c, hipGetLastError());
         if (c->timing) {
             HIPCHK(c, hipEventRecord(e1, st));
             c->ev_pairs.push_back(e0);
             c->ev_pairs.push_back(e1);
             long long ss = 0;
-            for (int i = 0; i < n_items; ++i) {
-                const ItemDev &it = (items == d_all ? pl.all : pl.ego)[i];
-                ss += (long long)pl.races[it.race].K * pl.races[it.race].N;
-            }
+            for (const ItemDev &it : host_items) ss += (long long)pl.races[it.race].K * pl.races[it.race].N;
             c->ev_work.push_back(ss);
         }
-        return SGTP_OK;
-    }
-    int winner(const ItemDev *items, int n_items, int phase, int par, sgtp_choice *choice, int adopt) {
-        LaunchArgs a = A;
-        a.items = items;
-        a.n_items = n_items;
-        a.phase = phase;
-        a.pred_in = c->d_pred[par];
-        a.pred_out = c->d_pred[par ^ 1];
-        a.choice = choice;
-        a.choice_base = 0;
-        a.adopt = adopt;
-        dispatch(p->model, p->n_disc, mo, 1, a, st);
-        HIPCHK(c, hipGetLastError());
         return SGTP_OK;
     }
 };
@@ -1420,6 +1566,7 @@ int sgtp_ctx_create(sgtp_ctx **out, int max_agents_total, int max_N, int max_rac
     for (int i = 0; i < 2; ++i) al((void **)&c->d_pred[i], sizeof(float) * PRED_STRIDE * (max_N + 1) * (size_t)max_agents_total);
     al((void **)&c->d_keys, sizeof(unsigned long long) * max_agents_total);
     al((void **)&c->d_nfeas, sizeof(int) * max_agents_total);
+    al((void **)&c->d_counters, sizeof(int) * max_agents_total);
     c->desc_bytes = ((sizeof(RaceDev) * max_races + 255) & ~size_t(255)) +
                     3 * ((sizeof(ItemDev) * max_agents_total + 255) & ~size_t(255)) + 256;
     al((void **)&c->d_desc, c->desc_bytes * sgtp_ctx::RING);
@@ -1440,7 +1587,8 @@ int sgtp_ctx_destroy(sgtp_ctx *c) {
     (void)hipDeviceSynchronize();
     for (auto &t : c->tracks)
         if (t.d_nodes) (void)hipFree(t.d_nodes);
-    void *bufs[] = {c->d_tracks, c->d_agents, c->d_win, c->d_xref, c->d_pred[0], c->d_pred[1], c->d_keys, c->d_nfeas, c->d_desc};
+    void *bufs[] = {c->d_tracks, c->d_agents, c->d_win,   c->d_xref,     c->d_pred[0],
+                    c->d_pred[1], c->d_keys,   c->d_nfeas, c->d_counters, c->d_desc};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (int i = 0; i < sgtp_ctx::RING; ++i) {
@@ -1492,7 +1640,7 @@ int sgtp_track_upload(sgtp_ctx *c, int id, const double *nodes, int n, int close
     T.ds_min = ds_min;
     T.vmax = vmax;
     T.inner_factor = 1.0 / std::max(0.25, 1.0 - kmax * (wmax + 2.0));
-    TrackDev d{T.d_nodes, T.n, T.closed, T.length, T.psi_lap, T.ds_min, T.inner_factor};
+    TrackDev d{T.d_nodes, T.n, T.closed, T.length, T.psi_lap, T.ds_min, T.inner_factor, T.vmax};
     HIPCHK(c, hipMemcpy(c->d_tracks + id, &d, sizeof d, hipMemcpyHostToDevice));
     return SGTP_OK;
 }
@@ -1509,27 +1657,14 @@ int sgtp_rollout_cost(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *race, 
     if (rc) return rc;
     rc = r.setup_all();
     if (rc) return rc;
-    LaunchArgs a = r.A;
-    a.items = r.d_one;
-    a.n_items = 1;
-    a.phase = phase;
-    a.pred_in = c->d_pred[0];
-    a.n_tiles = (race->K + BLOCK - 1) / BLOCK;
-    a.dbg_cost = cost;
-    a.dbg_flags = flags;
-    a.dbg_viol = viol;
-    a.dbg_xfinal = x_final;
-    a.dbg_noise = noise;
-    dispatch(p->model, p->n_disc, r.mo, 0, a, r.st);
-    HIPCHK(c, hipGetLastError());
-    a.pred_out = c->d_pred[1];
-    a.choice = out;
-    a.choice_base = r.pl.all[agent].slot;
-    a.adopt = 0;
-    a.dbg_cost = nullptr; a.dbg_flags = nullptr; a.dbg_viol = nullptr; a.dbg_xfinal = nullptr; a.dbg_noise = nullptr;
-    dispatch(p->model, p->n_disc, r.mo, 1, a, r.st);
-    HIPCHK(c, hipGetLastError());
-    return SGTP_OK;
+    LaunchArgs dbg = r.A;
+    dbg.dbg_cost = cost;
+    dbg.dbg_flags = flags;
+    dbg.dbg_viol = viol;
+    dbg.dbg_xfinal = x_final;
+    dbg.dbg_noise = noise;
+    const int tiles = (race->K + BLOCK - 1) / BLOCK;
+    return r.sweep(r.d_one, r.pl.one, tiles, phase, 0, out, r.pl.all[agent].slot, 0, 0, nullptr, &dbg);
 }
 
 int sgtp_ibr_sweep(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_races, int phase, int ego_only,
@@ -1541,12 +1676,8 @@ int sgtp_ibr_sweep(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, in
     if (rc) return rc;
     rc = r.setup_all();
     if (rc) return rc;
-    const ItemDev *items = ego_only ? r.d_ego : r.d_all;
-    const int n_items = ego_only ? (int)r.pl.ego.size() : (int)r.pl.all.size();
-    const int n_tiles = ego_only ? r.pl.tiles_ego : r.pl.tiles_all;
-    rc = r.sweep(items, n_items, n_tiles, phase, 0);
-    if (rc) return rc;
-    return r.winner(items, n_items, phase, 0, out, 1);
+    if (ego_only) return r.sweep(r.d_ego, r.pl.ego, r.pl.tiles_ego, phase, 0, out, 0, 1, 0, nullptr);
+    return r.sweep(r.d_all, r.pl.all, r.pl.tiles_all, phase, 0, out, 0, 1, 0, nullptr);
 }
 
 int sgtp_plan_step(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_races, int L_ibr, float *u_apply,
@@ -1562,17 +1693,14 @@ int sgtp_plan_step(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, in
     const int nt = r.pl.agents_total;
     for (int ph = 0; ph <= L_ibr + 1; ++ph) {
         const bool ego = ph == L_ibr + 1;
-        const ItemDev *items = ego ? r.d_ego : r.d_all;
-        const int n_items = ego ? (int)r.pl.ego.size() : (int)r.pl.all.size();
-        const int n_tiles = ego ? r.pl.tiles_ego : r.pl.tiles_all;
-        const int par = ph & 1;
-        rc = r.sweep(items, n_items, n_tiles, ph, par);
-        if (rc) return rc;
-        rc = r.winner(items, n_items, ph, par, trace ? trace + (size_t)ph * nt : nullptr, 1);
+        const int final_mode = ego ? 2 : (ph == L_ibr ? 1 : 0);
+        sgtp_choice *tr = trace ? trace + (size_t)ph * nt : nullptr;
+        if (ego)
+            rc = r.sweep(r.d_ego, r.pl.ego, r.pl.tiles_ego, ph, ph & 1, tr, 0, 1, final_mode, u_apply);
+        else
+            rc = r.sweep(r.d_all, r.pl.all, r.pl.tiles_all, ph, ph & 1, tr, 0, 1, final_mode, u_apply);
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(k_apply, dim3((nt + 63) / 64), dim3(64), 0, r.st, r.d_races, r.d_all, nt, (float2 *)u_apply);
-    HIPCHK(c, hipGetLastError());
     return SGTP_OK;
 }
 
