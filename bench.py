@@ -84,12 +84,42 @@ def cpu_baseline(name: str, seconds: float = 10.0, K_sample: int = 2048):
                        f"({per_step} sample-steps each), {el:.1f} s")
 
 
+def _races_for(name, sg, inputs, planner):
+    """Device races, parameters, L and per-plan-step sample-steps of a workload."""
+    if name == "c4":
+        tracks, races, specs, params = inputs.batched_workload(256)
+        tid = {20: 10, 40: 11, 50: 12}
+        for N, tr in tracks.items():
+            planner.upload_track(tid[N], tr)
+        rts = [sg.race_from_inputs(rc, tid[sp["N"]], sp["K"], sp["N"], inputs.n_tail_from_fraction(0.3, sp["N"]))
+               for rc, sp in zip(races, specs)]
+        L = 5
+        per_step = sum(((L + 1) * sp["n_agents"] + 1) * sp["K"] * sp["N"] for sp in specs)
+        desc = ("c4: 256 seeded races, 2-10 vehicles (uniform), K in {4096, 16384, 65536}, N in {20, 40, 50}, "
+                "5 IBR sweeps + init + extra ego per race, 3-disc footprint, one persistent launch per sweep, "
+                "hipGraph planning step, autotuned schedule, closed loop")
+        return rts, params, L, per_step, desc, sum(sp["n_agents"] for sp in specs)
+    w = inputs.WORKLOADS[name]
+    tr, race, params = inputs.workload_inputs(name)
+    planner.upload_track(0, tr)
+    rt = sg.race_from_inputs(race, 0, w.K, w.N, params["n_tail"])
+    L = w.L_ibr
+    per_step = ((L + 1) * w.n_agents + 1) * w.K * w.N
+    desc = (f"{name}: {w.n_agents} vehicles, {w.track_length:.0f} m x {w.track_width:.0f} m seeded track, "
+            f"N={w.N}, K={w.K} per best response, {L} IBR sweeps + init + extra ego, {w.n_disc}-disc footprint, "
+            "hipGraph planning step, closed loop")
+    return [rt], params, L, per_step, desc, w.n_agents
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2")
+    ap.add_argument("--mode", choices=["graph", "eager"], default="graph")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the schedule search (default schedule)")
+    ap.add_argument("--roofline-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     args = ap.parse_args()
@@ -104,44 +134,55 @@ def main():
     from paper_2607_25388_amd import inputs
 
     name = args.workload
-    w = inputs.WORKLOADS[name]
-    tr, race, params = inputs.workload_inputs(name)
-    planner = sg.Planner(max_agents_total=max(16, w.n_agents), max_races=1)
-    planner.upload_track(0, tr)
-    rt = sg.race_from_inputs(race, 0, w.K, w.N, params["n_tail"])
-    L = w.L_ibr
-    n = w.n_agents
-    u = torch.empty((n, 2), dtype=torch.float32, device="cuda")
+    planner = sg.Planner(max_agents_total=2048, max_races=256)
+    rts, params, L, per_step, desc, n_total = _races_for(name, sg, inputs, planner)
     stream = torch.cuda.current_stream()
-
-    def step(i):
-        rt.plan_step = i
-        planner.plan_step(params, [rt], L, u_apply=u)
-        planner.advance(params, [rt], u)
+    opts = sg.plan_options(include_advance=1)
+    tuned = None
+    if not args.no_autotune:
+        best, ms = planner.autotune(params, rts, L)
+        best.include_advance = 1
+        opts = best
+        tuned = dict(best.as_dict(), plan_ms=ms)
+    if args.mode == "eager":
+        opts.use_graph = 0
+    plan = planner.plan(params, rts, L, opts, trace=False)
 
     for i in range(args.warmup):
-        step(i)
+        plan.run()
     torch.cuda.synchronize()
-    planner.sweep_stats(reset=True)
-    planner.set_timing(True)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         ev[i][0].record(stream)
-        step(args.warmup + i)
+        plan.run()
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    planner.set_timing(False)
-    sweep_ms, sweep_launches, sweep_ss = planner.sweep_stats(reset=True)
     lat = np.array([a.elapsed_time(b) for a, b in ev])
-    assert np.all(np.isfinite(rt.x.cpu().numpy())), "non-finite state"
+    for r in rts:
+        assert np.all(np.isfinite(r.x.cpu().numpy())), "non-finite state"
+    info = plan.info()
+    plan.close()
 
-    per_step = ((L + 1) * n + 1) * w.K * w.N
+    # sweep-kernel duration: the same planning steps launched eagerly with HIP events
+    # recorded on the launch stream around every sweep launch
+    eager = sg.plan_options(**dict(opts.as_dict(), use_graph=0, include_advance=1))
+    eplan = planner.plan(params, rts, L, eager, trace=False)
+    planner.sweep_stats(reset=True)
+    planner.set_timing(True)
+    for i in range(args.roofline_steps):
+        eplan.run()
+    torch.cuda.synchronize()
+    planner.set_timing(False)
+    eplan.close()
+    sweep_ms, sweep_launches, sweep_ss = planner.sweep_stats(reset=True)
+
     value = per_step * args.steps / el
     avg_sweep_ms = sweep_ms / max(1, sweep_launches)
-    flops = flops_per_sample_step(n - 1, params["model"])
+    n_opp = max(r.n_agents for r in rts) - 1 if name != "c4" else 5
+    flops = flops_per_sample_step(n_opp, params["model"])
     achieved = flops * (sweep_ss / max(1, sweep_launches)) / (avg_sweep_ms * 1e-3) / 1e12
     rec = {
         "metric": METRIC,
@@ -156,21 +197,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": f"{name}: {n} vehicles, {w.track_length:.0f} m x {w.track_width:.0f} m seeded track, "
-                        f"N={w.N}, K={w.K} per best response, {L} IBR sweeps + init + extra ego, "
-                        f"{w.n_disc}-disc footprint, closed loop",
-            "sample_steps_per_plan_step": per_step,
-        },
+        "config": {"workload": desc, "sample_steps_per_plan_step": per_step, "vehicles": n_total,
+                   "mode": args.mode, "schedule": opts.as_dict(), "sweep_grid": info},
         "plan_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                             "mean": float(lat.mean())},
         "sweep_kernel": {"launches": sweep_launches, "avg_ms": avg_sweep_ms,
-                         "sample_steps_per_launch": sweep_ss / max(1, sweep_launches)},
+                         "sample_steps_per_launch": sweep_ss / max(1, sweep_launches),
+                         "timing": "HIP events on the launch stream, eager replay of the same planning step"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
                      "flops_per_sample_step": flops},
     }
-    if not args.no_cpu_baseline:
+    if tuned:
+        rec["config"]["autotune"] = tuned
+    if not args.no_cpu_baseline and name != "c4":
         rec["cpu_baseline"] = cpu_baseline(name, args.cpu_seconds)
     planner.close()
     print(json.dumps(rec), flush=True)

@@ -107,9 +107,11 @@ typedef struct {
 
 /* Create a context on the current device with workspace for up to
  * max_agents_total vehicles over all races of one call, horizons up to max_N,
- * max_races races per call and track tables of up to max_track_nodes nodes.
- * Allocates device memory (the only call that does, with sgtp_track_upload). */
-int sgtp_ctx_create(sgtp_ctx **out, int max_agents_total, int max_N, int max_races, int max_track_nodes);
+ * max_races races per call, track tables of up to max_track_nodes nodes and up to
+ * max_K samples per best response (checkpoint slots: 128 bytes per 64 samples).
+ * Allocates device memory (with sgtp_track_upload, plans and the autotuner). */
+int sgtp_ctx_create(sgtp_ctx **out, int max_agents_total, int max_N, int max_races, int max_track_nodes,
+                    int max_K);
 int sgtp_ctx_destroy(sgtp_ctx *ctx);
 const char *sgtp_last_error(const sgtp_ctx *ctx);
 
@@ -156,6 +158,51 @@ int sgtp_plan_step(sgtp_ctx *ctx, const sgtp_params *p, const sgtp_race *races, 
  * dt through the same vehicle model (float64 RK4), updating race->x. */
 int sgtp_advance(sgtp_ctx *ctx, const sgtp_params *p, const sgtp_race *races, int n_races, const float *u,
                  void *stream);
+
+/* ---- batched planning: plans, persistent sweeps, graphs, autotuning -------- */
+
+/* A plan fixes a set of races (any mix of vehicle counts, K and N), L_ibr and the
+ * output arrays, uploads their descriptors once and runs Alg. 1 for all races per
+ * call: one setup launch, then one sweep launch per phase covering every vehicle
+ * of every race.  Tiles of BLOCK = 256 samples (x samples_per_lane) are the unit
+ * of work; a persistent sweep keeps a fixed grid of workgroups that pull chunks of
+ * tiles from 8 queues (vehicles assigned longest-first; a workgroup serves its own
+ * queue first, then steals), re-staging LDS only when the vehicle changes.  With
+ * use_graph the whole planning step is captured once into a hipGraph and replayed
+ * by sgtp_plan_run.  Each run advances the races' plan_step (Philox counter word)
+ * on the device; the race structs passed at creation are not read again (their
+ * device arrays are: x, s_abs, v_scale, u_nom, traj). */
+typedef struct sgtp_plan sgtp_plan;
+
+typedef struct {
+    int persistent;       /* 1 = persistent sweep with tile queues, 0 = one workgroup per tile */
+    int blocks_per_cu;    /* persistent grid per CU (0 = occupancy limit) */
+    int tiles_per_fetch;  /* tiles taken per queue fetch (persistent) */
+    int samples_per_lane; /* samples evaluated in turn by each lane of a tile */
+    int use_graph;        /* capture the planning step into a hipGraph */
+    int include_advance;  /* append sgtp_advance with u_apply (closed loop inside the graph) */
+} sgtp_plan_options;
+
+/* u_apply: DEVICE [sum n][2]; trace: DEVICE [(L_ibr+2)][sum n] or NULL; opt NULL = defaults
+ * (persistent, 1 tile per fetch, graph).  Allocates the plan's descriptor memory and,
+ * with use_graph, captures on an internal stream (`stream` orders nothing here). */
+int sgtp_plan_create(sgtp_ctx *ctx, const sgtp_params *p, const sgtp_race *races, int n_races, int L_ibr,
+                     float *u_apply, sgtp_choice *trace, const sgtp_plan_options *opt, sgtp_plan **out,
+                     void *stream);
+/* One planning step of every race of the plan (graph replay or eager launches). */
+int sgtp_plan_run(sgtp_plan *plan, void *stream);
+/* Set every race's planning-step counter (synchronises the device). */
+int sgtp_plan_set_step(sgtp_plan *plan, unsigned int plan_step);
+/* Launch shape of the plan's all-vehicle sweeps; any pointer may be NULL. */
+int sgtp_plan_info(const sgtp_plan *plan, int *grid_sweep, int *tiles_sweep, int *lds_bytes);
+int sgtp_plan_destroy(sgtp_plan *plan);
+
+/* Time candidate schedules (one workgroup per tile with 1 or 2 samples per lane;
+ * persistent with 1, 2, 4 tiles per fetch at full or 2-per-CU occupancy) on real
+ * planning steps of these races and return the fastest in *best (use_graph set).
+ * The races' u_nom and s_abs are saved and restored; allocates temporary memory. */
+int sgtp_autotune(sgtp_ctx *ctx, const sgtp_params *p, const sgtp_race *races, int n_races, int L_ibr,
+                  float *u_apply, sgtp_plan_options *best, double *best_ms, void *stream);
 
 /* ---- instrumentation ------------------------------------------------------ */
 

@@ -39,6 +39,9 @@ constexpr int WIN_MAX = 1536;   // window nodes per vehicle (workspace bound)
 constexpr int PRED_STRIDE = 8;  // x, y, cos psi, sin psi, s_rel, d, -, - in the owner's frame
 constexpr int NODE_STRIDE = 10; // device node row: x, y, psi, nx, ny, wL, wR, vref, s, kappa
 constexpr unsigned long long KEY_NONE = ~0ull;
+constexpr int NQ = 8;
+constexpr int NCP = 4;          // re-roll chunks: each lane keeps its state at N/4, N/2, 3N/4
+constexpr int CP_FLOATS = 32;   // export slot per 64-sample group: 3 checkpoints x (6 states + segment)           // tile queues of the persistent sweep (one per XCD under round-robin dispatch)
 
 enum Mode { SWEEP = 0, WINNER = 1, NOMINAL = 2 };
 
@@ -76,6 +79,7 @@ struct RaceDev {
 
 struct ItemDev {  // one best response (race, vehicle) of a launch
     int race, agent, slot, tile0;
+    int group0, pad0;  // first 64-sample group of the vehicle in the checkpoint slots
 };
 
 struct AgentRec {  // per vehicle, written by k_setup
@@ -113,12 +117,19 @@ struct LaunchArgs {
     int adopt;             // write u_nom / traj
     int final_mode;        // 0 none, 1 every vehicle but the ego, 2 every vehicle: first control + warm start
     float2 *u_apply;       // [slot] first controls, or NULL
+    // persistent sweep: per-queue tile ranges and fetch counters
+    int chunk;             // tiles taken per fetch
+    int q_begin[NQ], q_len[NQ];
+    int *qctr;             // [NQ] fetch counters of this sweep
+    int *qreset;           // counters zeroed by k_setup (all sweeps of a planning step), or NULL
+    int n_qreset;
     // debug outputs of k_sweep (indexed by sample), or NULL
     float *dbg_cost;
     unsigned char *dbg_flags;
     float *dbg_viol;
     double *dbg_xfinal;
     float *dbg_noise;
+    float *cp_slots;       // [group][CP_FLOATS] checkpoints of each wave's best sample
 };
 
 // ------------------------------------------------------------------------------
@@ -589,6 +600,7 @@ struct SampleResult {
     bool h;
     unsigned char flags;
     float st[6];
+    float cp[NCP - 1][7];  // state and segment after steps C, 2C, 3C (C = ceil(N / NCP))
 };
 
 // Terminal scoring: game-aware cost (eqs. game_cost, c_contest, c_long, c_block,
@@ -651,6 +663,12 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P, const Bloc
     float2 up = make_float2(0.0f, 0.0f);
     bool limit = false;
     float2 zn = make_float2(0.0f, 0.0f);  // perturbation of the odd step of a Philox call
+    float cp[NCP - 1][7];
+#pragma unroll
+    for (int c = 0; c < NCP - 1; ++c)
+#pragma unroll
+        for (int i = 0; i < 7; ++i) cp[c][i] = 0.0f;
+    const int C = (bs.N + NCP - 1) / NCP;
 
     for (int tau = 0; tau < bs.N; ++tau) {
         float2 z;
@@ -688,8 +706,21 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P, const Bloc
                 g2[j] = opp_min2<NDISC>(P, opp + ((size_t)tau * L.n_opp_max + j) * (NDISC + 1), st[0], st[1], ch, sh,
                                         g2[j]);
         if (tau + 1 > bs.N - bs.n_tail) dsum += f.d;
+#pragma unroll
+        for (int c = 0; c < NCP - 1; ++c) {
+            if (tau + 1 == (c + 1) * C) {
+#pragma unroll
+                for (int i = 0; i < 6; ++i) cp[c][i] = st[i];
+                cp[c][6] = __int_as_float(seg);
+            }
+        }
     }
-    return terminal<MAXOPP>(P, bs, lds, L, J, rho_bd, dsum, s, g2, limit, st);
+    SampleResult res = terminal<MAXOPP>(P, bs, lds, L, J, rho_bd, dsum, s, g2, limit, st);
+#pragma unroll
+    for (int c = 0; c < NCP - 1; ++c)
+#pragma unroll
+        for (int i = 0; i < 7; ++i) res.cp[c][i] = cp[c][i];
+    return res;
 }
 
 // ------------------------------------------------------------------------------
@@ -708,7 +739,8 @@ struct RerollOut {
 
 template <int MODEL, int NDISC, int MAXOPP, int MODE>
 __device__ SampleResult reroll_block(const KParams &P, const LdsLayout &L, const BlockState &bs, char *lds,
-                                     const AgentRec &rec, uint32_t k, const RerollOut &out) {
+                                     const AgentRec &rec, uint32_t k, const RerollOut &out,
+                                     const float *cps = nullptr) {
     const int tid = threadIdx.x, nth = blockDim.x, N = bs.N;
     const float2 *ubar = (const float2 *)(lds + L.ubar);
     const float4 *xref = (const float4 *)(lds + L.xref);
@@ -734,11 +766,22 @@ __device__ SampleResult reroll_block(const KParams &P, const LdsLayout &L, const
         if (2 * m + 1 < N) wu[2 * m + 1] = controls(P, ubar[2 * m + 1], z1.x, z1.y);
     }
     __syncthreads();
-    // B. dynamics and projection, serial over the horizon
-    if (tid == 0) {
+    // B. dynamics and projection, serial over the horizon; with the sample's checkpoints
+    //    (the lane's exact state and segment after steps C, 2C, 3C) NCP threads each run
+    //    one chunk of the horizon
+    const int nch = cps ? NCP : 1;
+    const int C = cps ? (N + NCP - 1) / NCP : N;
+    if (tid < nch) {
         float st[6] = {0.0f, 0.0f, 0.0f, bs.vx0, bs.vy0, bs.om0};
         int seg = bs.seg0;
-        for (int tau = 0; tau < N; ++tau) {
+        if (tid > 0) {
+            const float *c = cps + 7 * (tid - 1);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) st[i] = c[i];
+            seg = __float_as_int(c[6]);
+        }
+        const int t_end = min((tid + 1) * C, N);
+        for (int tau = tid * C; tau < t_end; ++tau) {
             const float2 u = wu[tau];
             const StepConst<float> sc = step_const<MODEL, MathF32>(V, u.x, u.y);
             rk4<MODEL, MathF32>(V, sc, P.dt, st);
@@ -839,17 +882,12 @@ __device__ __forceinline__ int find_item(const ItemDev *items, int n, int tile) 
     return lo;
 }
 
-// Sweep: every sample of every participating vehicle.  The last workgroup of a
-// vehicle to finish (device-scope counter) reads the selection and re-rolls it
-// with the tables it already holds in LDS.
+// One tile (spl x BLOCK consecutive samples) of a staged vehicle, then the hand-off:
+// the workgroup that finishes the vehicle's last tile (device-scope counter) reads
+// the selection and re-rolls it with the tables it holds in LDS.
 template <int MODEL, int NDISC, int MAXOPP>
-__global__ void __launch_bounds__(BLOCK) k_sweep(LaunchArgs A) {
-    extern __shared__ __align__(16) char lds[];
-    __shared__ int s_last;
-    const int tile = blockIdx.x;
-    const int item = find_item(A.items, A.n_items, tile);
-    BlockState bs;
-    stage_block<NDISC>(A, item, bs, lds);
+__device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int item, const BlockState &bs, char *lds,
+                                           int *s_last) {
     const int lane = threadIdx.x & 63;
     const int t0 = A.items[item].tile0;
     const int n_tiles_item = (item + 1 < A.n_items ? A.items[item + 1].tile0 : A.n_tiles) - t0;
@@ -867,6 +905,13 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(LaunchArgs A) {
             const int cnt = __popcll(feas);
             if (cnt) atomicAdd(A.nfeas + bs.slot, cnt);
         }
+        if (A.cp_slots && valid && key == wmin) {  // the wave's best sample keeps its checkpoints
+            float *slot = A.cp_slots + ((size_t)A.items[item].group0 + k / 64) * CP_FLOATS;
+#pragma unroll
+            for (int c = 0; c < NCP - 1; ++c)
+#pragma unroll
+                for (int i = 0; i < 7; ++i) slot[7 * c + i] = res.cp[c][i];
+        }
         if (valid) {
             if (A.dbg_cost) A.dbg_cost[k] = res.cost;
             if (A.dbg_viol) A.dbg_viol[k] = res.viol;
@@ -882,14 +927,13 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(LaunchArgs A) {
             }
         }
     }
-    // hand-off: the last workgroup of this vehicle re-rolls the selected sample
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
-        s_last = atomicAdd(A.counters + bs.slot, 1) == n_tiles_item - 1;
+        *s_last = atomicAdd(A.counters + bs.slot, 1) == n_tiles_item - 1;
     }
     __syncthreads();
-    if (!s_last) return;
+    if (!*s_last) return;
     __threadfence();
     const unsigned long long key = atomicMin(A.keys + bs.slot, KEY_NONE);  // current value
     const int nfeas = atomicAdd(A.nfeas + bs.slot, 0);
@@ -907,7 +951,8 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(LaunchArgs A) {
         out.final_shift = final_phase;
         out.u_apply = (final_phase && A.u_apply) ? A.u_apply + bs.slot : nullptr;
     }
-    const SampleResult res = reroll_block<MODEL, NDISC, MAXOPP, WINNER>(A.P, A.L, bs, lds, rec, k, out);
+    const float *cps = A.cp_slots ? A.cp_slots + ((size_t)it.group0 + k / 64) * CP_FLOATS : nullptr;
+    const SampleResult res = reroll_block<MODEL, NDISC, MAXOPP, WINNER>(A.P, A.L, bs, lds, rec, k, out, cps);
     if (threadIdx.x == 0) {
         if (A.choice) {
             sgtp_choice c;
@@ -921,6 +966,62 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(LaunchArgs A) {
         A.keys[bs.slot] = KEY_NONE;
         A.nfeas[bs.slot] = 0;
         A.counters[bs.slot] = 0;
+    }
+    __syncthreads();
+}
+
+// Sweep with one workgroup per tile.
+template <int MODEL, int NDISC, int MAXOPP>
+__global__ void __launch_bounds__(BLOCK) k_sweep(LaunchArgs A) {
+    extern __shared__ __align__(16) char lds[];
+    __shared__ int s_last;
+    const int tile = blockIdx.x;
+    const int item = find_item(A.items, A.n_items, tile);
+    BlockState bs;
+    stage_block<NDISC>(A, item, bs, lds);
+    sweep_tile<MODEL, NDISC, MAXOPP>(A, tile, item, bs, lds, &s_last);
+}
+
+// Persistent sweep: a fixed grid of workgroups pulls chunks of tiles from NQ queues
+// (its own first, then the others), restaging LDS only when the vehicle changes.
+// Every workgroup leaves once all queues are exhausted.
+template <int MODEL, int NDISC, int MAXOPP>
+__global__ void __launch_bounds__(BLOCK) k_sweep_persistent(LaunchArgs A) {
+    extern __shared__ __align__(16) char lds[];
+    __shared__ int s_last;
+    __shared__ int s_fetch[2];
+    BlockState bs;
+    int staged = -1;
+    const int q0 = blockIdx.x % NQ;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int first = -1, cnt = 0;
+            for (int a = 0; a < NQ; ++a) {
+                const int q = (q0 + a) % NQ;
+                if (A.q_len[q] == 0) continue;
+                const int t = atomicAdd(A.qctr + q, A.chunk);
+                if (t < A.q_len[q]) {
+                    first = A.q_begin[q] + t;
+                    cnt = min(A.chunk, A.q_len[q] - t);
+                    break;
+                }
+            }
+            s_fetch[0] = first;
+            s_fetch[1] = cnt;
+        }
+        __syncthreads();
+        const int first = s_fetch[0], cnt = s_fetch[1];
+        if (first < 0) break;
+        for (int t = first; t < first + cnt; ++t) {
+            const int item = find_item(A.items, A.n_items, t);
+            if (item != staged) {
+                __syncthreads();
+                stage_block<NDISC>(A, item, bs, lds);
+                staged = item;
+            }
+            sweep_tile<MODEL, NDISC, MAXOPP>(A, t, item, bs, lds, &s_last);
+        }
     }
 }
 
@@ -943,6 +1044,8 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
     const int tid = threadIdx.x;
     const long long n = T.n;
     const long long nseg = T.closed ? n : n - 1;
+    if (blockIdx.x == 0 && A.qreset)
+        for (int i = tid; i < A.n_qreset; i += BLOCK) A.qreset[i] = 0;
 
     auto node = [&](long long i, double *o) {  // unwrapped node access (float64 row)
         long long lap = 0, b = i;
@@ -1171,6 +1274,12 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
     reroll_block<MODEL, 1, 1, NOMINAL>(A.P, A.L, bs, lds, rec, 0u, out);
 }
 
+// Advance the Philox counter word of every race (planning-step index).
+__global__ void k_bump_step(RaceDev *races, int n_races) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_races) races[i].plan_step += 1u;
+}
+
 // Closed loop: one float64 RK4 interval per vehicle.
 template <int MODEL>
 __global__ void k_advance(const RaceDev *races, const ItemDev *items, int n_items, const float2 *u, VehConst<double> V,
@@ -1182,7 +1291,7 @@ __global__ void k_advance(const RaceDev *races, const ItemDev *items, int n_item
     double *x = R.x + (size_t)it.agent * 6;
     double s[6];
     for (int c = 0; c < 6; ++c) s[c] = x[c];
-    const float2 ui = u[i];
+    const float2 ui = u[it.slot];
     const StepConst<double> sc = step_const<MODEL, MathF64>(V, (double)ui.x, (double)ui.y);
     rk4<MODEL, MathF64>(V, sc, dt, s);
     for (int c = 0; c < 6; ++c) x[c] = s[c];
@@ -1212,6 +1321,8 @@ struct sgtp_ctx {
     unsigned long long *d_keys = nullptr;
     int *d_nfeas = nullptr;
     int *d_counters = nullptr;
+    float *d_cp = nullptr;     // checkpoint slots, CP_FLOATS per 64-sample group
+    long long max_groups = 0;
     // descriptor uploads: pinned ring, each slot guarded by an event
     static constexpr int RING = 8;
     char *h_stage[RING] = {};
@@ -1314,6 +1425,7 @@ int build_plan(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_
     if (!races || n_races < 1) return fail(c, SGTP_EINVAL, "no races");
     if (n_races > c->max_races) return fail(c, SGTP_ESHAPE, "n_races exceeds the context");
     int slot = 0;
+    long long group_total = 0;
     double wneed = 0;
     for (int r = 0; r < n_races; ++r) {
         const sgtp_race &s = races[r];
@@ -1333,8 +1445,9 @@ int build_plan(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_
         d.x = s.x; d.s_abs = s.s_abs; d.v_scale = s.v_scale; d.u_nom = s.u_nom; d.traj = s.traj;
         pl.races.push_back(d);
         const int tiles = (s.K + BLOCK * spl - 1) / (BLOCK * spl);
+        const long long groups = (s.K + 63) / 64;
         for (int i = 0; i < s.n_agents; ++i) {
-            ItemDev it{r, i, slot + i, pl.tiles_all};
+            ItemDev it{r, i, slot + i, pl.tiles_all, (int)(group_total + i * groups), 0};
             pl.tiles_all += tiles;
             pl.all.push_back(it);
             if (r == 0 && i == one_agent) {
@@ -1350,6 +1463,7 @@ int build_plan(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_
             }
         }
         slot += s.n_agents;
+        group_total += (long long)s.n_agents * groups;
         pl.N_max = std::max(pl.N_max, s.N);
         pl.n_opp_max = std::max(pl.n_opp_max, s.n_agents - 1);
         // window: reachable arc length at up to 1.2 v_ref,max + 5 m/s, inner-side factor, margins
@@ -1359,6 +1473,7 @@ int build_plan(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_
         wneed = std::max(wneed, WIN_BACK + std::ceil(T.inner_factor * reach / T.ds_min) + 8.0);
     }
     if (slot > c->max_agents) return fail(c, SGTP_ESHAPE, "total vehicles exceed the context");
+    if (group_total > c->max_groups) return fail(c, SGTP_ESHAPE, "total samples exceed the context (max_K)");
     pl.agents_total = slot;
     pl.w_max = (int)std::min<double>(WIN_MAX, wneed);
     return SGTP_OK;
@@ -1428,27 +1543,77 @@ int upload_plan(sgtp_ctx *c, const Plan &pl, hipStream_t st, RaceDev **d_races, 
     return SGTP_OK;
 }
 
+// grid = 0: one workgroup per tile; grid > 0: persistent sweep with that many workgroups;
+// grid < 0: query the occupancy (workgroups per CU) of the persistent kernel into *occ.
 template <int MODEL, int NDISC, int MAXOPP>
-void launch_sweep_t(const LaunchArgs &A, hipStream_t st) {
-    hipLaunchKernelGGL((k_sweep<MODEL, NDISC, MAXOPP>), dim3(A.n_tiles), dim3(BLOCK), A.L.total, st, A);
+void launch_sweep_t(const LaunchArgs &A, int grid, hipStream_t st, int *occ) {
+    if (grid < 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sweep_persistent<MODEL, NDISC, MAXOPP>, BLOCK,
+                                                         A.L.total) != hipSuccess)
+            n = 1;
+        *occ = n;
+    } else if (grid == 0) {
+        hipLaunchKernelGGL((k_sweep<MODEL, NDISC, MAXOPP>), dim3(A.n_tiles), dim3(BLOCK), A.L.total, st, A);
+    } else {
+        hipLaunchKernelGGL((k_sweep_persistent<MODEL, NDISC, MAXOPP>), dim3(grid), dim3(BLOCK), A.L.total, st, A);
+    }
 }
 
 template <int MODEL, int NDISC>
-void dispatch_opp(int mo, const LaunchArgs &A, hipStream_t st) {
-    if (mo == 1) launch_sweep_t<MODEL, NDISC, 1>(A, st);
-    else if (mo == 3) launch_sweep_t<MODEL, NDISC, 3>(A, st);
-    else if (mo == 9) launch_sweep_t<MODEL, NDISC, 9>(A, st);
-    else launch_sweep_t<MODEL, NDISC, 15>(A, st);
+void dispatch_opp(int mo, const LaunchArgs &A, int grid, hipStream_t st, int *occ) {
+    if (mo == 1) launch_sweep_t<MODEL, NDISC, 1>(A, grid, st, occ);
+    else if (mo == 3) launch_sweep_t<MODEL, NDISC, 3>(A, grid, st, occ);
+    else if (mo == 9) launch_sweep_t<MODEL, NDISC, 9>(A, grid, st, occ);
+    else launch_sweep_t<MODEL, NDISC, 15>(A, grid, st, occ);
 }
 
-void dispatch_sweep(int model, int ndisc, int mo, const LaunchArgs &A, hipStream_t st) {
+void dispatch_sweep(int model, int ndisc, int mo, const LaunchArgs &A, hipStream_t st, int grid = 0,
+                    int *occ = nullptr) {
     if (model == 0) {
-        if (ndisc == 1) dispatch_opp<0, 1>(mo, A, st);
-        else dispatch_opp<0, 3>(mo, A, st);
+        if (ndisc == 1) dispatch_opp<0, 1>(mo, A, grid, st, occ);
+        else dispatch_opp<0, 3>(mo, A, grid, st, occ);
     } else {
-        if (ndisc == 1) dispatch_opp<1, 1>(mo, A, st);
-        else dispatch_opp<1, 3>(mo, A, st);
+        if (ndisc == 1) dispatch_opp<1, 1>(mo, A, grid, st, occ);
+        else dispatch_opp<1, 3>(mo, A, grid, st, occ);
     }
+}
+
+// Order the items of a sweep for the persistent kernel: vehicles go to NQ queues
+// by longest-processing-time first (work = K N), each queue is a contiguous run of
+// tiles, heaviest vehicles first inside a queue.
+void layout_queues(const Plan &pl, std::vector<ItemDev> &items, int spl, int q_begin[NQ], int q_len[NQ]) {
+    std::vector<int> order(items.size());
+    for (size_t i = 0; i < items.size(); ++i) order[i] = (int)i;
+    auto work = [&](const ItemDev &it) {
+        const RaceDev &r = pl.races[it.race];
+        return (double)r.K * r.N * (1.0 + 0.02 * (r.n_agents - 1));
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(items[a]) > work(items[b]); });
+    double load[NQ] = {0};
+    std::vector<int> qof(items.size());
+    for (int i : order) {
+        int q = 0;
+        for (int j = 1; j < NQ; ++j)
+            if (load[j] < load[q]) q = j;
+        qof[i] = q;
+        load[q] += work(items[i]);
+    }
+    std::vector<ItemDev> out;
+    int tile = 0;
+    for (int q = 0; q < NQ; ++q) {
+        q_begin[q] = tile;
+        for (int i : order) {
+            if (qof[i] != q) continue;
+            ItemDev it = items[i];
+            it.tile0 = tile;
+            const RaceDev &r = pl.races[it.race];
+            tile += (r.K + BLOCK * spl - 1) / (BLOCK * spl);
+            out.push_back(it);
+        }
+        q_len[q] = tile - q_begin[q];
+    }
+    items = out;
 }
 
 struct Runner {
@@ -1480,6 +1645,7 @@ struct Runner {
         A.keys = c->d_keys;
         A.nfeas = c->d_nfeas;
         A.counters = c->d_counters;
+        A.cp_slots = c->d_cp;
         A.spl = 1;
         return SGTP_OK;
     }
@@ -1535,14 +1701,110 @@ struct Runner {
 
 }  // namespace
 
+struct sgtp_plan {
+    sgtp_ctx *c = nullptr;
+    sgtp_params p{};
+    int L = 0;
+    Plan pl;
+    LaunchArgs base{};
+    int mo = 1;
+    char *d_mem = nullptr;  // descriptors + queue counters, owned by the plan
+    RaceDev *d_races = nullptr;
+    ItemDev *d_all = nullptr, *d_ego = nullptr;
+    int *d_qctr = nullptr;  // [(L+2)][NQ]
+    int qb_all[NQ], ql_all[NQ], qb_ego[NQ], ql_ego[NQ];
+    float *u_apply = nullptr;
+    sgtp_choice *trace = nullptr;
+    sgtp_plan_options opt{};
+    int grid_all = 0, grid_ego = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool capturing = false;
+};
+
+namespace {
+
+// Enqueue one planning step of a plan (also used while capturing its graph).
+int plan_enqueue(sgtp_plan *P, hipStream_t st) {
+    sgtp_ctx *c = P->c;
+    LaunchArgs a = P->base;
+    a.items = P->d_all;
+    a.n_items = (int)P->pl.all.size();
+    a.pred_out = c->d_pred[0];
+    a.qreset = P->d_qctr;
+    a.n_qreset = (P->L + 2) * NQ;
+    if (P->p.model == 0)
+        hipLaunchKernelGGL(k_setup<0>, dim3(a.n_items), dim3(BLOCK), a.L.total, st, a, P->pl.w_max);
+    else
+        hipLaunchKernelGGL(k_setup<1>, dim3(a.n_items), dim3(BLOCK), a.L.total, st, a, P->pl.w_max);
+    HIPCHK(c, hipGetLastError());
+    const int nt = P->pl.agents_total;
+    for (int ph = 0; ph <= P->L + 1; ++ph) {
+        const bool ego = ph == P->L + 1;
+        LaunchArgs w = P->base;
+        w.items = ego ? P->d_ego : P->d_all;
+        w.n_items = (int)(ego ? P->pl.ego.size() : P->pl.all.size());
+        w.n_tiles = ego ? P->pl.tiles_ego : P->pl.tiles_all;
+        w.phase = ph;
+        w.pred_in = c->d_pred[ph & 1];
+        w.pred_out = c->d_pred[(ph & 1) ^ 1];
+        w.choice = P->trace ? P->trace + (size_t)ph * nt : nullptr;
+        w.choice_base = 0;
+        w.adopt = 1;
+        w.final_mode = ego ? 2 : (ph == P->L ? 1 : 0);
+        w.u_apply = (float2 *)P->u_apply;
+        w.qctr = P->d_qctr + ph * NQ;
+        for (int q = 0; q < NQ; ++q) {
+            w.q_begin[q] = ego ? P->qb_ego[q] : P->qb_all[q];
+            w.q_len[q] = ego ? P->ql_ego[q] : P->ql_all[q];
+        }
+        const int grid = P->opt.persistent ? (ego ? P->grid_ego : P->grid_all) : 0;
+        const bool timed = c->timing && !P->capturing;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timed) {
+            HIPCHK(c, hipEventCreate(&e0));
+            HIPCHK(c, hipEventCreate(&e1));
+            HIPCHK(c, hipEventRecord(e0, st));
+        }
+        dispatch_sweep(P->p.model, P->p.n_disc, P->mo, w, st, grid);
+        HIPCHK(c, hipGetLastError());
+        if (timed) {
+            HIPCHK(c, hipEventRecord(e1, st));
+            c->ev_pairs.push_back(e0);
+            c->ev_pairs.push_back(e1);
+            long long ss = 0;
+            for (const ItemDev &it : (ego ? P->pl.ego : P->pl.all))
+                ss += (long long)P->pl.races[it.race].K * P->pl.races[it.race].N;
+            c->ev_work.push_back(ss);
+        }
+    }
+    const int nr = (int)P->pl.races.size();
+    hipLaunchKernelGGL(k_bump_step, dim3((nr + 63) / 64), dim3(64), 0, st, P->d_races, nr);
+    HIPCHK(c, hipGetLastError());
+    if (P->opt.include_advance) {
+        if (P->p.model == 0)
+            hipLaunchKernelGGL(k_advance<0>, dim3((nt + 63) / 64), dim3(64), 0, st, P->d_races, P->d_all, nt,
+                               (const float2 *)P->u_apply, make_veh64(&P->p), (double)P->p.dt);
+        else
+            hipLaunchKernelGGL(k_advance<1>, dim3((nt + 63) / 64), dim3(64), 0, st, P->d_races, P->d_all, nt,
+                               (const float2 *)P->u_apply, make_veh64(&P->p), (double)P->p.dt);
+        HIPCHK(c, hipGetLastError());
+    }
+    return SGTP_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int sgtp_abi_version(void) { return 1; }
 
-int sgtp_ctx_create(sgtp_ctx **out, int max_agents_total, int max_N, int max_races, int max_track_nodes) {
+int sgtp_ctx_create(sgtp_ctx **out, int max_agents_total, int max_N, int max_races, int max_track_nodes,
+                    int max_K) {
     if (!out) return SGTP_EINVAL;
     *out = nullptr;
-    if (max_agents_total < 1 || max_N < 1 || max_N > SGTP_MAX_N || max_races < 1 || max_track_nodes < 2)
+    if (max_agents_total < 1 || max_N < 1 || max_N > SGTP_MAX_N || max_races < 1 || max_track_nodes < 2 ||
+        max_K < 1 || max_K > SGTP_MAX_K)
         return SGTP_EINVAL;
     sgtp_ctx *c = new sgtp_ctx();
     c->max_agents = max_agents_total;
@@ -1567,6 +1829,8 @@ int sgtp_ctx_create(sgtp_ctx **out, int max_agents_total, int max_N, int max_rac
     al((void **)&c->d_keys, sizeof(unsigned long long) * max_agents_total);
     al((void **)&c->d_nfeas, sizeof(int) * max_agents_total);
     al((void **)&c->d_counters, sizeof(int) * max_agents_total);
+    c->max_groups = (long long)max_agents_total * ((max_K + 63) / 64);
+    al((void **)&c->d_cp, sizeof(float) * CP_FLOATS * (size_t)c->max_groups);
     c->desc_bytes = ((sizeof(RaceDev) * max_races + 255) & ~size_t(255)) +
                     3 * ((sizeof(ItemDev) * max_agents_total + 255) & ~size_t(255)) + 256;
     al((void **)&c->d_desc, c->desc_bytes * sgtp_ctx::RING);
@@ -1587,8 +1851,8 @@ int sgtp_ctx_destroy(sgtp_ctx *c) {
     (void)hipDeviceSynchronize();
     for (auto &t : c->tracks)
         if (t.d_nodes) (void)hipFree(t.d_nodes);
-    void *bufs[] = {c->d_tracks, c->d_agents, c->d_win,   c->d_xref,     c->d_pred[0],
-                    c->d_pred[1], c->d_keys,   c->d_nfeas, c->d_counters, c->d_desc};
+    void *bufs[] = {c->d_tracks, c->d_agents, c->d_win,      c->d_xref, c->d_pred[0], c->d_pred[1],
+                    c->d_keys,   c->d_nfeas,  c->d_counters, c->d_cp,   c->d_desc};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (int i = 0; i < sgtp_ctx::RING; ++i) {
@@ -1724,6 +1988,237 @@ int sgtp_advance(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int 
     else
         hipLaunchKernelGGL(k_advance<1>, dim3((nt + 63) / 64), dim3(64), 0, st, dr, da, nt, (const float2 *)u, V, (double)p->dt);
     HIPCHK(c, hipGetLastError());
+    return SGTP_OK;
+}
+
+int sgtp_plan_create(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_races, int L_ibr,
+                     float *u_apply, sgtp_choice *trace, const sgtp_plan_options *opt, sgtp_plan **out,
+                     void *stream) {
+    if (!c) return SGTP_EINVAL;
+    if (!out) return fail(c, SGTP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (L_ibr < 0 || L_ibr + 1 > 0xffff) return fail(c, SGTP_EINVAL, "L_ibr out of range");
+    if (!u_apply) return fail(c, SGTP_EINVAL, "u_apply is NULL");
+    int rc = check_params(c, p);
+    if (rc) return rc;
+    sgtp_plan_options o{};
+    o.persistent = 1;
+    o.blocks_per_cu = 0;
+    o.tiles_per_fetch = 1;
+    o.samples_per_lane = 1;
+    o.use_graph = 1;
+    o.include_advance = 0;
+    if (opt) o = *opt;
+    if (o.samples_per_lane < 1 || o.samples_per_lane > 16 || o.tiles_per_fetch < 1 || o.tiles_per_fetch > 64 ||
+        o.blocks_per_cu < 0 || o.blocks_per_cu > 64)
+        return fail(c, SGTP_EINVAL, "plan options out of range");
+    sgtp_plan *P = new sgtp_plan();
+    P->c = c;
+    P->p = *p;
+    P->L = L_ibr;
+    P->opt = o;
+    P->u_apply = u_apply;
+    P->trace = trace;
+    rc = build_plan(c, p, races, n_races, o.samples_per_lane, P->pl);
+    if (rc) {
+        delete P;
+        return rc;
+    }
+    layout_queues(P->pl, P->pl.all, o.samples_per_lane, P->qb_all, P->ql_all);
+    layout_queues(P->pl, P->pl.ego, o.samples_per_lane, P->qb_ego, P->ql_ego);
+    P->pl.tiles_all = P->ql_all[NQ - 1] + P->qb_all[NQ - 1];
+    P->pl.tiles_ego = P->ql_ego[NQ - 1] + P->qb_ego[NQ - 1];
+    P->mo = maxopp_bucket(P->pl.n_opp_max);
+    LaunchArgs &A = P->base;
+    A.P = make_kparams(p);
+    A.L = make_layout(P->pl, P->mo, p->n_disc);
+    if (A.L.total > 58 * 1024) {
+        delete P;
+        return fail(c, SGTP_ESHAPE, "staged tables exceed the LDS budget");
+    }
+    const size_t nr = P->pl.races.size() * sizeof(RaceDev), na = P->pl.all.size() * sizeof(ItemDev),
+                 ne = P->pl.ego.size() * sizeof(ItemDev), nq = (size_t)(L_ibr + 2) * NQ * sizeof(int);
+    const size_t o1 = (nr + 255) & ~size_t(255), o2 = o1 + ((na + 255) & ~size_t(255)),
+                 o3 = o2 + ((ne + 255) & ~size_t(255));
+    bool ok = hipMalloc((void **)&P->d_mem, o3 + nq) == hipSuccess;
+    ok = ok && hipMemcpy(P->d_mem, P->pl.races.data(), nr, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(P->d_mem + o1, P->pl.all.data(), na, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(P->d_mem + o2, P->pl.ego.data(), ne, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemset(P->d_mem + o3, 0, nq) == hipSuccess;
+    if (!ok) {
+        if (P->d_mem) (void)hipFree(P->d_mem);
+        delete P;
+        return fail(c, SGTP_ENOMEM, "plan descriptors");
+    }
+    P->d_races = (RaceDev *)P->d_mem;
+    P->d_all = (ItemDev *)(P->d_mem + o1);
+    P->d_ego = (ItemDev *)(P->d_mem + o2);
+    P->d_qctr = (int *)(P->d_mem + o3);
+    A.tracks = c->d_tracks;
+    A.races = P->d_races;
+    A.agents = c->d_agents;
+    A.win = c->d_win;
+    A.xref = c->d_xref;
+    A.keys = c->d_keys;
+    A.nfeas = c->d_nfeas;
+    A.counters = c->d_counters;
+    A.cp_slots = c->d_cp;
+    A.spl = o.samples_per_lane;
+    A.chunk = o.tiles_per_fetch;
+    if (o.persistent) {
+        int occ = 1, dev = 0, cus = 0;
+        dispatch_sweep(p->model, p->n_disc, P->mo, A, nullptr, -1, &occ);
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        const int bpc = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, std::max(1, occ)) : std::max(1, occ);
+        const int g = std::max(1, cus) * bpc;
+        P->grid_all = std::max(1, std::min(g, P->pl.tiles_all));
+        P->grid_ego = std::max(1, std::min(g, P->pl.tiles_ego));
+    }
+    if (o.use_graph) {
+        hipStream_t st = (hipStream_t)stream;
+        hipStream_t cap = nullptr;
+        ok = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        P->capturing = true;
+        int erc = ok ? plan_enqueue(P, cap) : SGTP_EDEVICE;
+        P->capturing = false;
+        hipGraph_t g = nullptr;
+        if (ok) ok = hipStreamEndCapture(cap, &g) == hipSuccess;
+        ok = ok && erc == SGTP_OK && hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0) == hipSuccess;
+        P->graph = g;
+        if (cap) (void)hipStreamDestroy(cap);
+        (void)st;
+        if (!ok) {
+            sgtp_plan_destroy(P);
+            return fail(c, SGTP_EDEVICE, "graph capture of the planning step failed");
+        }
+    }
+    *out = P;
+    return SGTP_OK;
+}
+
+int sgtp_plan_run(sgtp_plan *P, void *stream) {
+    if (!P) return SGTP_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (P->exec) {
+        HIPCHK(P->c, hipGraphLaunch(P->exec, st));
+        return SGTP_OK;
+    }
+    return plan_enqueue(P, st);
+}
+
+int sgtp_plan_set_step(sgtp_plan *P, unsigned int plan_step) {
+    if (!P) return SGTP_EINVAL;
+    HIPCHK(P->c, hipDeviceSynchronize());
+    for (size_t r = 0; r < P->pl.races.size(); ++r) {
+        P->pl.races[r].plan_step = plan_step;
+        HIPCHK(P->c, hipMemcpy(&P->d_races[r].plan_step, &plan_step, sizeof plan_step, hipMemcpyHostToDevice));
+    }
+    return SGTP_OK;
+}
+
+int sgtp_plan_info(const sgtp_plan *P, int *grid_sweep, int *tiles_sweep, int *lds_bytes) {
+    if (!P) return SGTP_EINVAL;
+    if (grid_sweep) *grid_sweep = P->opt.persistent ? P->grid_all : P->pl.tiles_all;
+    if (tiles_sweep) *tiles_sweep = P->pl.tiles_all;
+    if (lds_bytes) *lds_bytes = P->base.L.total;
+    return SGTP_OK;
+}
+
+int sgtp_plan_destroy(sgtp_plan *P) {
+    if (!P) return SGTP_EINVAL;
+    (void)hipDeviceSynchronize();
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->d_mem) (void)hipFree(P->d_mem);
+    delete P;
+    return SGTP_OK;
+}
+
+int sgtp_autotune(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_races, int L_ibr,
+                  float *u_apply, sgtp_plan_options *best, double *best_ms, void *stream) {
+    if (!c) return SGTP_EINVAL;
+    if (!best) return fail(c, SGTP_EINVAL, "best is NULL");
+    if (!races || n_races < 1) return fail(c, SGTP_EINVAL, "no races");
+    hipStream_t st = (hipStream_t)stream;
+    // the search runs real planning steps: save and restore the mutable race state
+    std::vector<void *> saved;
+    std::vector<size_t> sizes;
+    for (int r = 0; r < n_races; ++r) {
+        sizes.push_back((size_t)races[r].n_agents * races[r].N * 2 * sizeof(float));
+        sizes.push_back((size_t)races[r].n_agents * sizeof(double));
+    }
+    for (size_t i = 0; i < sizes.size(); ++i) {
+        void *b = nullptr;
+        HIPCHK(c, hipMalloc(&b, sizes[i]));
+        saved.push_back(b);
+    }
+    auto save_restore = [&](bool save) -> int {
+        for (int r = 0; r < n_races; ++r) {
+            void *un = races[r].u_nom, *sa = races[r].s_abs;
+            HIPCHK(c, hipMemcpyAsync(save ? saved[2 * r] : un, save ? un : saved[2 * r], sizes[2 * r],
+                                     hipMemcpyDeviceToDevice, st));
+            HIPCHK(c, hipMemcpyAsync(save ? saved[2 * r + 1] : sa, save ? sa : saved[2 * r + 1], sizes[2 * r + 1],
+                                     hipMemcpyDeviceToDevice, st));
+        }
+        return SGTP_OK;
+    };
+    int rc = save_restore(true);
+    std::vector<sgtp_plan_options> cand;
+    for (int spl : {1, 2}) {
+        sgtp_plan_options o{};
+        o.persistent = 0;
+        o.samples_per_lane = spl;
+        o.tiles_per_fetch = 1;
+        cand.push_back(o);
+    }
+    for (int chunk : {1, 2, 4})
+        for (int bpc : {0, 2}) {
+            sgtp_plan_options o{};
+            o.persistent = 1;
+            o.samples_per_lane = 1;
+            o.tiles_per_fetch = chunk;
+            o.blocks_per_cu = bpc;
+            cand.push_back(o);
+        }
+    double best_t = INFINITY;
+    sgtp_plan_options best_o = cand[0];
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    for (const sgtp_plan_options &o : cand) {
+        if (rc) break;
+        sgtp_plan *P = nullptr;
+        rc = sgtp_plan_create(c, p, races, n_races, L_ibr, u_apply, nullptr, &o, &P, stream);
+        if (rc) break;
+        double t = INFINITY;
+        for (int rep = 0; rep < 3 && rc == 0; ++rep) {
+            rc = save_restore(false);
+            if (!rc) (void)hipEventRecord(e0, st);
+            if (!rc) rc = sgtp_plan_run(P, stream);
+            if (!rc) (void)hipEventRecord(e1, st);
+            if (!rc && hipEventSynchronize(e1) == hipSuccess) {
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (rep > 0) t = std::min(t, (double)ms);  // first run warms up
+            }
+        }
+        sgtp_plan_destroy(P);
+        if (t < best_t) {
+            best_t = t;
+            best_o = o;
+        }
+    }
+    if (!rc) rc = save_restore(false);
+    (void)hipStreamSynchronize(st);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (void *b : saved) (void)hipFree(b);
+    if (rc) return rc;
+    best_o.use_graph = 1;
+    *best = best_o;
+    if (best_ms) *best_ms = best_t;
     return SGTP_OK;
 }
 

@@ -364,3 +364,21 @@ def batched_races(n_races: int = 256, seed: int = 4242):
         N = int(rng.choice([20, 40, 50]))
         specs.append(dict(race=r, n_agents=n, K=K, N=N))
     return specs
+
+
+def batched_workload(n_races: int = 256, seed: int = 4242, K_override=None):
+    """Tracks (one per horizon, seeds 1000 + N), races (starts 3000 + r, noise 2000 + r) and
+    parameters (3-disc footprint) of the batched workload.  Returns (tracks, races, specs, params)."""
+    specs = batched_races(n_races, seed)
+    tracks = {}
+    for N, (length, width) in TRACK_FOR_N.items():
+        tracks[N] = make_fourier_track(length, width, 1000 + N)
+    races = []
+    for sp in specs:
+        if K_override is not None:
+            sp["K"] = int(K_override(sp))
+        tr = tracks[sp["N"]]
+        races.append(make_race(tr, sp["n_agents"], sp["N"], 8.0, sp["n_agents"] >= 5, 3000 + sp["race"],
+                               2000 + sp["race"]))
+    params = default_params(50, 3)
+    return tracks, races, specs, params

@@ -51,6 +51,19 @@ class Choice(C.Structure):
                 ("viol", C.c_float)]
 
 
+class PlanOptions(C.Structure):
+    _fields_ = [("persistent", C.c_int), ("blocks_per_cu", C.c_int), ("tiles_per_fetch", C.c_int),
+                ("samples_per_lane", C.c_int), ("use_graph", C.c_int), ("include_advance", C.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def plan_options(persistent=1, blocks_per_cu=0, tiles_per_fetch=1, samples_per_lane=1, use_graph=1,
+                 include_advance=0) -> PlanOptions:
+    return PlanOptions(persistent, blocks_per_cu, tiles_per_fetch, samples_per_lane, use_graph, include_advance)
+
+
 CHOICE_DTYPE = np.dtype([("k", np.int32), ("fallback", np.int32), ("n_feasible", np.int32),
                          ("cost", np.float32), ("viol", np.float32)])
 assert CHOICE_DTYPE.itemsize == C.sizeof(Choice)
@@ -67,7 +80,7 @@ def load():
         lib = C.CDLL(LIB_PATH)
         P = C.POINTER
         vp = C.c_void_p
-        lib.sgtp_ctx_create.argtypes = [P(vp), C.c_int, C.c_int, C.c_int, C.c_int]
+        lib.sgtp_ctx_create.argtypes = [P(vp), C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
         lib.sgtp_ctx_destroy.argtypes = [vp]
         lib.sgtp_last_error.argtypes = [vp]
         lib.sgtp_last_error.restype = C.c_char_p
@@ -79,6 +92,13 @@ def load():
         lib.sgtp_set_timing.argtypes = [vp, C.c_int]
         lib.sgtp_sweep_stats.argtypes = [vp, P(C.c_double), P(C.c_longlong), P(C.c_longlong), C.c_int]
         lib.sgtp_abi_version.restype = C.c_int
+        lib.sgtp_plan_create.argtypes = [vp, P(Params), P(Race), C.c_int, C.c_int, vp, vp, P(PlanOptions), P(vp), vp]
+        lib.sgtp_plan_run.argtypes = [vp, vp]
+        lib.sgtp_plan_set_step.argtypes = [vp, C.c_uint]
+        lib.sgtp_plan_info.argtypes = [vp, P(C.c_int), P(C.c_int), P(C.c_int)]
+        lib.sgtp_plan_destroy.argtypes = [vp]
+        lib.sgtp_autotune.argtypes = [vp, P(Params), P(Race), C.c_int, C.c_int, vp, P(PlanOptions),
+                                      P(C.c_double), vp]
         _lib = lib
     return _lib
 
@@ -155,14 +175,16 @@ def race_from_inputs(race, track_id: int, K: int, N: int, n_tail: int, device="c
 class Planner:
     """One planner context on the current device."""
 
-    def __init__(self, max_agents_total=64, max_N=SGTP_MAX_N, max_races=8, max_track_nodes=1 << 16):
+    def __init__(self, max_agents_total=64, max_N=SGTP_MAX_N, max_races=8, max_track_nodes=1 << 16,
+                 max_K=1 << 16):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the SGTP planner needs a GPU")
         torch.cuda.init()
         self.lib = load()
         self.ctx = C.c_void_p()
-        rc = self.lib.sgtp_ctx_create(C.byref(self.ctx), max_agents_total, max_N, max_races, max_track_nodes)
+        rc = self.lib.sgtp_ctx_create(C.byref(self.ctx), max_agents_total, max_N, max_races, max_track_nodes,
+                                      max_K)
         if rc != 0:
             raise RuntimeError(f"sgtp_ctx_create failed: {ERRORS.get(rc, rc)}")
 
@@ -236,6 +258,22 @@ class Planner:
         self._check(self.lib.sgtp_advance(self.ctx, C.byref(P), arr, len(races), _ptr(u), _stream()),
                     "sgtp_advance")
 
+    def plan(self, params: dict, races, L_ibr: int, options: PlanOptions = None, trace=True):
+        """Batched planning step over `races` (see sgtp_plan_create)."""
+        return Plan(self, params, races, L_ibr, options, trace)
+
+    def autotune(self, params: dict, races, L_ibr: int):
+        import torch
+        arr = (Race * len(races))(*[r.struct() for r in races])
+        nt = sum(r.n_agents for r in races)
+        u = torch.empty((nt, 2), dtype=torch.float32, device=races[0].x.device)
+        best = PlanOptions()
+        ms = C.c_double()
+        P = make_params(params)
+        self._check(self.lib.sgtp_autotune(self.ctx, C.byref(P), arr, len(races), L_ibr, _ptr(u), C.byref(best),
+                                           C.byref(ms), _stream()), "sgtp_autotune")
+        return best, ms.value
+
     def set_timing(self, on: bool):
         self._check(self.lib.sgtp_set_timing(self.ctx, 1 if on else 0), "sgtp_set_timing")
 
@@ -251,3 +289,53 @@ class Planner:
 def choices_to_numpy(t) -> np.ndarray:
     """Decode a uint8 device buffer of sgtp_choice records."""
     return np.frombuffer(t.cpu().numpy().tobytes(), dtype=CHOICE_DTYPE)
+
+
+class Plan:
+    """A batched planning step (sgtp_plan): descriptors uploaded once, optionally a hipGraph."""
+
+    def __init__(self, planner: Planner, params: dict, races, L_ibr: int, options: PlanOptions = None, trace=True):
+        import torch
+        self.planner = planner
+        self.lib = planner.lib
+        self.races = list(races)
+        self.L = L_ibr
+        nt = sum(r.n_agents for r in races)
+        dev = races[0].x.device
+        self.u_apply = torch.zeros((nt, 2), dtype=torch.float32, device=dev)
+        self.trace = (torch.zeros((L_ibr + 2) * nt * CHOICE_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+                      if trace else None)
+        self.options = options if options is not None else plan_options()
+        arr = (Race * len(races))(*[r.struct() for r in races])
+        P = make_params(params)
+        self.handle = C.c_void_p()
+        planner._check(self.lib.sgtp_plan_create(planner.ctx, C.byref(P), arr, len(races), L_ibr, _ptr(self.u_apply),
+                                                 _ptr(self.trace), C.byref(self.options), C.byref(self.handle),
+                                                 _stream()), "sgtp_plan_create")
+
+    def run(self):
+        self.planner._check(self.lib.sgtp_plan_run(self.handle, _stream()), "sgtp_plan_run")
+        return self.u_apply
+
+    def set_step(self, step: int):
+        self.planner._check(self.lib.sgtp_plan_set_step(self.handle, step), "sgtp_plan_set_step")
+
+    def info(self):
+        g, t, l = C.c_int(), C.c_int(), C.c_int()
+        self.planner._check(self.lib.sgtp_plan_info(self.handle, C.byref(g), C.byref(t), C.byref(l)), "sgtp_plan_info")
+        return dict(grid=g.value, tiles=t.value, lds_bytes=l.value)
+
+    def choices(self):
+        nt = sum(r.n_agents for r in self.races)
+        return choices_to_numpy(self.trace).reshape(self.L + 2, nt)
+
+    def close(self):
+        if self.handle:
+            self.lib.sgtp_plan_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

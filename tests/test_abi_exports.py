@@ -60,7 +60,7 @@ def test_context_creation_fails_cleanly_without_a_gpu():
         pytest.skip("a GPU is present")
     lib = sg.load()
     ctx = C.c_void_p()
-    rc = lib.sgtp_ctx_create(C.byref(ctx), 4, 20, 1, 1000)
+    rc = lib.sgtp_ctx_create(C.byref(ctx), 4, 20, 1, 1000, 1024)
     assert rc == -4 and not ctx.value
     with pytest.raises(RuntimeError):
         sg.Planner()

@@ -1,0 +1,145 @@
+"""GPU: batched plans (many uneven races per launch), persistent sweeps, hipGraph replay,
+autotuner.  The per-vehicle computation does not depend on the launch schedule, so every
+schedule must give the same bits as planning each race on its own."""
+
+import numpy as np
+import pytest
+
+from paper_2607_25388_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TRACK_ID = {20: 10, 40: 11, 50: 12}
+
+
+@pytest.fixture(scope="module")
+def planner():
+    import paper_2607_25388_amd.sgtp as sg
+    p = sg.Planner(max_agents_total=256, max_races=64)
+    yield p
+    p.close()
+
+
+def _batch(planner, n_races=7, seed=77):
+    import paper_2607_25388_amd.sgtp as sg
+    tracks, races, specs, params = inputs.batched_workload(n_races, seed, K_override=lambda sp: [300, 777, 1024][
+        sp["race"] % 3])
+    for N, tr in tracks.items():
+        planner.upload_track(TRACK_ID[N], tr)
+    rts = [sg.race_from_inputs(rc, TRACK_ID[sp["N"]], sp["K"], sp["N"], inputs.n_tail_from_fraction(0.3, sp["N"]),
+                               plan_step=0) for rc, sp in zip(races, specs)]
+    return tracks, races, specs, params, rts
+
+
+def _fresh(rts):
+    import copy
+    import torch
+    out = []
+    for r in rts:
+        c = copy.copy(r)
+        c.x, c.s_abs, c.u_nom = r.x.clone(), r.s_abs.clone(), r.u_nom.clone()
+        c.traj = torch.zeros_like(r.traj)
+        out.append(c)
+    return out
+
+
+def _eager_reference(planner, params, rts, L, steps):
+    """Each race alone, eager sgtp_plan_step, plan_step = 0..steps-1."""
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    res = []
+    for r in rts:
+        tr_all, u_all = [], []
+        for s in range(steps):
+            r.plan_step = s
+            trace = torch.zeros((L + 2) * r.n_agents * sg.CHOICE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+            u = planner.plan_step(params, [r], L, trace=trace)
+            torch.cuda.synchronize()
+            tr_all.append(sg.choices_to_numpy(trace).reshape(L + 2, r.n_agents))
+            u_all.append(u.cpu().numpy())
+        res.append(dict(trace=tr_all, u=u_all, traj=r.traj.cpu().numpy(), u_nom=r.u_nom.cpu().numpy()))
+    return res
+
+
+def _plan_run(planner, params, rts, L, steps, options):
+    import torch
+    plan = planner.plan(params, rts, L, options)
+    traces, us = [], []
+    for s in range(steps):
+        plan.run()
+        torch.cuda.synchronize()
+        traces.append(plan.choices().copy())
+        us.append(plan.u_apply.cpu().numpy().copy())
+        # unrelated eager work between replays
+        torch.ones(1024, device="cuda").sum().item()
+    info = plan.info()
+    plan.close()
+    return traces, us, info
+
+
+def _compare(rts, ref, traces, us, L):
+    base = 0
+    for r, rr in zip(rts, ref):
+        n = r.n_agents
+        for s in range(len(traces)):
+            for ph in range(L + 2):
+                for i in range(n):
+                    if ph == L + 1 and i != r.ego:
+                        continue
+                    g = traces[s][ph, base + i]
+                    e = rr["trace"][s][ph, i]
+                    assert int(g["k"]) == int(e["k"]) and float(g["cost"]) == float(e["cost"]), (s, ph, i)
+            np.testing.assert_array_equal(us[s][base:base + n], rr["u"][s])
+        np.testing.assert_array_equal(r.traj.cpu().numpy(), rr["traj"])
+        np.testing.assert_array_equal(r.u_nom.cpu().numpy(), rr["u_nom"])
+        base += n
+
+
+@pytest.mark.parametrize("opts", [
+    dict(persistent=1, tiles_per_fetch=2, use_graph=1),
+    dict(persistent=1, tiles_per_fetch=1, blocks_per_cu=1, use_graph=0),
+    dict(persistent=1, tiles_per_fetch=4, samples_per_lane=2, use_graph=1),
+    dict(persistent=0, samples_per_lane=2, use_graph=1),
+])
+def test_batched_plan_is_schedule_invariant(planner, opts):
+    import paper_2607_25388_amd.sgtp as sg
+    tracks, races, specs, params, rts = _batch(planner)
+    L, steps = 2, 2
+    ref = _eager_reference(planner, params, _fresh(rts), L, steps)
+    mine = _fresh(rts)
+    traces, us, info = _plan_run(planner, params, mine, L, steps, sg.plan_options(**opts))
+    _compare(mine, ref, traces, us, L)
+
+
+def test_graph_with_closed_loop_advance(planner):
+    """Planning step + advance captured in one graph, replayed; equals the eager loop."""
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    tracks, races, specs, params, rts = _batch(planner, 4, 91)
+    L, steps = 1, 3
+    eager = _fresh(rts)
+    for s in range(steps):
+        for r in eager:
+            r.plan_step = s
+            u = planner.plan_step(params, [r], L)
+            planner.advance(params, [r], u)
+    torch.cuda.synchronize()
+    mine = _fresh(rts)
+    plan = planner.plan(params, mine, L, sg.plan_options(include_advance=1), trace=False)
+    for s in range(steps):
+        plan.run()
+    torch.cuda.synchronize()
+    plan.close()
+    for a, b in zip(mine, eager):
+        np.testing.assert_array_equal(a.x.cpu().numpy(), b.x.cpu().numpy())
+        np.testing.assert_array_equal(a.u_nom.cpu().numpy(), b.u_nom.cpu().numpy())
+
+
+def test_autotune_returns_a_valid_schedule(planner):
+    tracks, races, specs, params, rts = _batch(planner, 5, 93)
+    before = [r.u_nom.cpu().numpy().copy() for r in rts]
+    best, ms = planner.autotune(params, rts, 1)
+    assert ms > 0 and best.use_graph == 1
+    assert best.samples_per_lane in (1, 2) and best.tiles_per_fetch in (1, 2, 4)
+    for r, b in zip(rts, before):  # state restored
+        np.testing.assert_array_equal(r.u_nom.cpu().numpy(), b)
