@@ -58,7 +58,8 @@ class RaceS(C.Structure):
                 ("seed", C.c_ulonglong), ("plan_step", C.c_uint), ("pad1", C.c_uint),
                 ("x", C.POINTER(C.c_double)), ("s_prev", C.POINTER(C.c_double)),
                 ("v_scale", C.POINTER(C.c_double)), ("u_nom", C.POINTER(C.c_double)),
-                ("agent_id", C.POINTER(C.c_int))]
+                ("agent_id", C.POINTER(C.c_int)), ("prop", C.POINTER(C.c_double)),
+                ("K_prop", C.c_int), ("pad2", C.c_int)]
 
 
 class Choice(C.Structure):
@@ -80,10 +81,17 @@ class BrIn(C.Structure):
                 ("seed", C.c_ulonglong), ("plan_step", C.c_uint), ("pad0", C.c_uint),
                 ("x0", C.POINTER(C.c_double)), ("xr", C.POINTER(C.c_double)),
                 ("ubar", C.POINTER(C.c_double)), ("opp_traj", C.POINTER(C.c_double)),
-                ("opp_s0", C.POINTER(C.c_double))]
+                ("opp_s0", C.POINTER(C.c_double)), ("prop", C.POINTER(C.c_double)),
+                ("K_prop", C.c_int), ("pad1", C.c_int)]
+
+
+class Mlp(C.Structure):
+    _fields_ = [("d_in", C.c_int), ("d_h", C.c_int), ("d_out", C.c_int), ("pad0", C.c_int)] + \
+               [(nm, C.POINTER(C.c_double)) for nm in ("W1", "b1", "W2", "b2", "W3", "b3")]
 
 
 CHOICE_FIELDS = [f[0] for f in Choice._fields_ if not f[0].startswith("pad")]
+FEAT_DIM = 50
 
 _lib = None
 
@@ -120,6 +128,14 @@ def load(rebuild: bool = False):
         lib.ref_plan_step.argtypes = [P(TrackS), P(Params), P(RaceS), C.c_int, P(C.c_int), P(Choice),
                                       P(C.c_double), P(C.c_double), P(C.c_double), P(C.c_double)]
         lib.ref_advance.argtypes = [P(Params), C.c_int, P(C.c_double), P(C.c_double)]
+        lib.ref_features.argtypes = [P(TrackS), P(Params), P(RaceS), P(C.c_double)]
+        lib.ref_mlp_forward.argtypes = [P(Mlp), C.c_int, P(C.c_double), P(C.c_double), P(C.c_double),
+                                        P(C.c_double), P(C.c_double), P(C.c_double)]
+        lib.ref_mlp_proposal.argtypes = [P(C.c_double), C.c_int, C.c_double, C.c_double, P(C.c_double)]
+        lib.ref_mlp_nll.argtypes = [P(C.c_double), C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                    P(C.c_double), P(C.c_double)]
+        lib.ref_mlp_nll.restype = C.c_double
+        lib.ref_mlp_backward.argtypes = [P(Mlp), C.c_int, P(C.c_double), P(C.c_double)] + [P(C.c_double)] * 6
         _lib = lib
     return _lib
 
@@ -223,8 +239,11 @@ class Oracle:
         return x
 
     # --- race-level calls ----------------------------------------------
-    def _race(self, race, K=None, plan_step=None, u_nom=None, x=None, s_prev="race", agent_id=None):
+    def _race(self, race, K=None, plan_step=None, u_nom=None, x=None, s_prev="race", agent_id=None,
+              prop=None, K_prop=0):
         keep = {}
+        if prop is not None:
+            keep["prop"] = np.ascontiguousarray(prop, np.float64)
         if agent_id is not None:
             keep["id"] = np.ascontiguousarray(agent_id, np.int32)
         keep["x"] = np.ascontiguousarray(race.x if x is None else x, np.float64)
@@ -242,6 +261,9 @@ class Oracle:
         R.u_nom = _dp(keep["u"])
         if agent_id is not None:
             R.agent_id = keep["id"].ctypes.data_as(C.POINTER(C.c_int))
+        if prop is not None:
+            R.prop = _dp(keep["prop"])
+            R.K_prop = int(K_prop)
         sp = race.s_abs if isinstance(s_prev, str) else s_prev
         if sp is not None:
             keep["s"] = np.ascontiguousarray(sp, np.float64)
@@ -292,6 +314,10 @@ class Oracle:
         bi.seed, bi.plan_step = int(br["seed"]), int(br["plan_step"])
         for nm in keep:
             setattr(bi, nm, _dp(keep[nm]))
+        if br.get("prop") is not None:
+            keep["prop"] = np.ascontiguousarray(br["prop"], np.float64)
+            bi.prop = _dp(keep["prop"])
+            bi.K_prop = int(br.get("K_prop", K))
         out = {}
         so = SampleOut()
         if want_samples:
@@ -330,3 +356,57 @@ class Oracle:
             raise RuntimeError(f"ref_plan_step failed: {rc}")
         tr = [[_choice_dict(trace[p * n + i]) for i in range(n)] for p in range(L_ibr + 2)]
         return dict(trace=tr, traj=traj, u_apply=u_apply, u_next=u_next, s_abs=s_abs)
+
+
+# ---- learned proposal (oracle of the MLP kernels) ---------------------------------
+
+class MlpOracle:
+    """Float64 MLP with the planner's output parameterisation; weights W[l] are [fan_in][fan_out]."""
+
+    def __init__(self, W1, b1, W2, b2, W3, b3):
+        self.lib = load()
+        self.arrs = [np.ascontiguousarray(a, np.float64) for a in (W1, b1, W2, b2, W3, b3)]
+        self.d_in, self.d_h = self.arrs[0].shape
+        self.d_out = self.arrs[4].shape[1]
+        self.M = Mlp(self.d_in, self.d_h, self.d_out, 0, *[_dp(a) for a in self.arrs])
+
+    def forward(self, X, intermediates=False):
+        X = np.ascontiguousarray(X, np.float64)
+        B = X.shape[0]
+        out = np.zeros((B, self.d_out))
+        if intermediates:
+            inter = [np.zeros((B, self.d_h)) for _ in range(4)]
+            self.lib.ref_mlp_forward(C.byref(self.M), B, _dp(X), _dp(out), *[_dp(a) for a in inter])
+            return out, inter
+        self.lib.ref_mlp_forward(C.byref(self.M), B, _dp(X), _dp(out), None, None, None, None)
+        return out
+
+    def nll(self, out, U, sig_a, sig_d, grad=True):
+        out = np.ascontiguousarray(out, np.float64)
+        U = np.ascontiguousarray(U, np.float64)
+        B, N = U.shape[0], U.shape[1]
+        g = np.zeros_like(out) if grad else None
+        L = self.lib.ref_mlp_nll(_dp(out), B, N, out.shape[1], sig_a, sig_d, _dp(U),
+                                 _dp(g) if grad else None)
+        return L, g
+
+    def backward(self, X, d_out):
+        X = np.ascontiguousarray(X, np.float64)
+        d_out = np.ascontiguousarray(d_out, np.float64)
+        grads = [np.zeros_like(a) for a in self.arrs]
+        self.lib.ref_mlp_backward(C.byref(self.M), X.shape[0], _dp(X), _dp(d_out), *[_dp(g) for g in grads])
+        return grads
+
+    def proposal(self, out_row, N, sig_a, sig_d):
+        o = np.ascontiguousarray(out_row, np.float64)
+        prop = np.zeros((N, 4))
+        self.lib.ref_mlp_proposal(_dp(o), N, sig_a, sig_d, _dp(prop))
+        return prop
+
+
+def features(orc: "Oracle", race, **kw):
+    R, keep = orc._race(race, K=1, **kw)
+    X = np.zeros((R.n_agents, FEAT_DIM))
+    rc = orc.lib.ref_features(C.byref(orc.T), C.byref(orc.P), C.byref(R), _dp(X))
+    assert rc == 0
+    return X

@@ -85,6 +85,8 @@ typedef struct {
     const double *v_scale; /* [n] */
     const double *u_nom;   /* [n][N][2] */
     const int *agent_id;   /* [n] identity used in the noise counter, or NULL (= index) */
+    const double *prop;    /* [n][N][4] proposal (mu_a, mu_d, sigma_a, sigma_d), or NULL */
+    int K_prop, pad2;      /* samples k < K_prop are drawn from the proposal */
 } ref_race;
 
 typedef struct {
@@ -518,6 +520,8 @@ typedef struct {
     const double *ubar;     /* [N][2] */
     const double *opp_traj; /* [n_opp][N+1][8] */
     const double *opp_s0;   /* [n_opp] */
+    const double *prop;     /* [N][4] proposal (mu_a, mu_d, sigma_a, sigma_d), or NULL */
+    int K_prop, pad1;
 } ref_br_in;
 
 typedef struct {
@@ -546,10 +550,19 @@ static void evaluate_sample(const ref_track *T, const ref_params *p, const ref_b
     double s = in->s0;
     int any_limit = 0;
 
+    /* learned proposal: samples k < K_prop are drawn about the proposal mean with its
+     * scales, the others about the nominal with the plain scales */
+    const int use_prop = in->prop && k < in->K_prop;
     for (int tau = 0; tau < N; ++tau) {
         double u[2];
-        u[0] = clampd(in->ubar[2 * tau] + p->sigma_a * (double)z[2 * tau], p->a_min, p->a_max);
-        u[1] = clampd(in->ubar[2 * tau + 1] + p->sigma_d * (double)z[2 * tau + 1], p->d_min, p->d_max);
+        if (use_prop) {
+            const double *q = in->prop + 4 * tau;
+            u[0] = clampd(q[0] + q[2] * (double)z[2 * tau], p->a_min, p->a_max);
+            u[1] = clampd(q[1] + q[3] * (double)z[2 * tau + 1], p->d_min, p->d_max);
+        } else {
+            u[0] = clampd(in->ubar[2 * tau] + p->sigma_a * (double)z[2 * tau], p->a_min, p->a_max);
+            u[1] = clampd(in->ubar[2 * tau + 1] + p->sigma_d * (double)z[2 * tau + 1], p->d_min, p->d_max);
+        }
         res->U[2 * tau] = u[0];
         res->U[2 * tau + 1] = u[1];
         ref_step(p, x, u);
@@ -790,6 +803,8 @@ static void build_br_in(const ref_params *p, const ref_race *R, const agent_stat
     in->ubar = ubar_all + (size_t)i * N * 2;
     in->opp_traj = opp_buf;
     in->opp_s0 = opp_s0;
+    in->prop = R->prop ? R->prop + (size_t)i * N * 4 : NULL;
+    in->K_prop = R->K_prop;
 }
 
 /* Setup only: projections (s, d, seg) and reference states of every agent. */
@@ -917,4 +932,248 @@ void ref_advance(const ref_params *p, int n, double *x, const double *u)
     for (int i = 0; i < n; ++i) ref_step(p, x + 6 * i, u + 2 * i);
 }
 
-int ref_abi_version(void) { return 1; }
+/* ------------------------------------------------------------------------ */
+/* Learned proposal: features, MLP, Gaussian negative log-likelihood        */
+/* (an extension of this project, not in the paper; the oracle checks the    */
+/* GPU kernels).                                                             */
+/* ------------------------------------------------------------------------ */
+
+#define FEAT_DIM 50
+#define FEAT_OPP 4
+#define FEAT_CURV 20
+#define FEAT_CURV_DS 5.0
+
+/* Features of vehicle i (50 values):
+ *   ego (6): d / w, heading error to the raceline (wrapped), v_x / 30, v_y / 5, omega,
+ *            (v_x - v_ref(s)) / 10
+ *   4 nearest opponents by |s_j - s_i| (6 each, zeros when absent): (s_j - s_i) / 20,
+ *            (d_j - d_i) / w, heading difference (wrapped), (v_x,j - v_x,i) / 10, v_y,j / 5, 1
+ *   curvature ahead (20): 20 kappa(s_i + 5 m * m), m = 1..20 (linear interpolation)
+ * w is the half width at the vehicle. */
+static double wrap_pi(double a) { return remainder(a, 2.0 * M_PI); }
+
+static double kappa_at(const ref_track *T, double s, long *hint)
+{
+    long i = *hint;
+    for (int it = 0; it < 1000000; ++it) {
+        node_t a = node_at(T, i), b = node_at(T, i + 1);
+        if (s < a.s && can_retreat(T, i)) { --i; continue; }
+        if (s >= b.s && can_advance(T, i)) { ++i; continue; }
+        break;
+    }
+    *hint = i;
+    node_t a = node_at(T, i), b = node_at(T, i + 1);
+    long ia = T->closed ? ((i % T->n) + T->n) % T->n : (i < 0 ? 0 : (i > T->n - 1 ? T->n - 1 : i));
+    long ib = T->closed ? (((i + 1) % T->n) + T->n) % T->n : (i + 1 > T->n - 1 ? T->n - 1 : i + 1);
+    double t = (s - a.s) / (b.s - a.s);
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+    return T->nodes[8 * ia + 3] + t * (T->nodes[8 * ib + 3] - T->nodes[8 * ia + 3]);
+}
+
+int ref_features(const ref_track *T, const ref_params *p, const ref_race *R, double *X /*[n][50]*/)
+{
+    const int n = R->n_agents;
+    agent_state *A = (agent_state *)malloc(sizeof(agent_state) * n);
+    double *psi_r = (double *)malloc(sizeof(double) * n);
+    double *vref = (double *)malloc(sizeof(double) * n);
+    double *half = (double *)malloc(sizeof(double) * n);
+    for (int i = 0; i < n; ++i) {
+        agent_setup(T, p, R, i, &A[i]);
+        long h = A[i].seg;
+        double x, y, ps, v;
+        interp_at_s(T, A[i].s, &h, &x, &y, &ps, &v);
+        psi_r[i] = ps;
+        vref[i] = v;
+        double o6[6];
+        ref_project_walk(T, p->max_moves, R->x + 6 * i, A[i].seg, o6);
+        half[i] = 0.5 * (o6[3] + o6[4]);
+    }
+    for (int i = 0; i < n; ++i) {
+        double *f = X + (size_t)i * FEAT_DIM;
+        const double *xi = R->x + 6 * i;
+        for (int c = 0; c < FEAT_DIM; ++c) f[c] = 0.0;
+        f[0] = A[i].d / half[i];
+        f[1] = wrap_pi(xi[2] - psi_r[i]);
+        f[2] = xi[3] / 30.0;
+        f[3] = xi[4] / 5.0;
+        f[4] = xi[5];
+        f[5] = (xi[3] - vref[i]) / 10.0;
+        /* nearest opponents: smallest |s_j - s_i|, ties by index */
+        int used[REF_MAX_OPP + 1] = {0};
+        for (int m = 0; m < FEAT_OPP; ++m) {
+            int best = -1;
+            double bd = INFINITY;
+            for (int j = 0; j < n; ++j) {
+                if (j == i || used[j]) continue;
+                double dd = fabs(A[j].s - A[i].s);
+                if (dd < bd) { bd = dd; best = j; }
+            }
+            if (best < 0) break;
+            used[best] = 1;
+            const double *xj = R->x + 6 * best;
+            double *g = f + 6 + 6 * m;
+            g[0] = (A[best].s - A[i].s) / 20.0;
+            g[1] = (A[best].d - A[i].d) / half[i];
+            g[2] = wrap_pi(xj[2] - xi[2]);
+            g[3] = (xj[3] - xi[3]) / 10.0;
+            g[4] = xj[4] / 5.0;
+            g[5] = 1.0;
+        }
+        long h = A[i].seg;
+        for (int m = 1; m <= FEAT_CURV; ++m)
+            f[6 + 6 * FEAT_OPP + m - 1] = 20.0 * kappa_at(T, A[i].s + FEAT_CURV_DS * m, &h);
+    }
+    free(A); free(psi_r); free(vref); free(half);
+    return 0;
+}
+
+/* MLP d_in -> H -> H -> d_out with tanh-form GELU; W[l] stored [fan_in][fan_out].
+ * Output per horizon step tau (4 values): mu_a = A_SCALE o0, mu_d = D_SCALE o1,
+ * log sigma_a = log sigma_a,plain + clamp(o2), log sigma_d = log sigma_d,plain + clamp(o3),
+ * clamp to [LS_MIN, LS_MAX]. */
+#define MLP_A_SCALE 4.0
+#define MLP_D_SCALE 0.2
+#define MLP_LS_MIN (-4.0)
+#define MLP_LS_MAX 1.0
+
+typedef struct {
+    int d_in, d_h, d_out, pad0;
+    const double *W1, *b1, *W2, *b2, *W3, *b3;
+} ref_mlp;
+
+static double gelu(double x)
+{
+    const double c = 0.7978845608028654; /* sqrt(2/pi) */
+    return 0.5 * x * (1.0 + tanh(c * (x + 0.044715 * x * x * x)));
+}
+static double gelu_grad(double x)
+{
+    const double c = 0.7978845608028654;
+    double u = c * (x + 0.044715 * x * x * x);
+    double t = tanh(u);
+    return 0.5 * (1.0 + t) + 0.5 * x * (1.0 - t * t) * c * (1.0 + 3.0 * 0.044715 * x * x);
+}
+
+/* Forward of B rows; optional intermediates: pre1/h1/pre2/h2 [B][d_h]. */
+void ref_mlp_forward(const ref_mlp *M, int B, const double *X, double *out, double *pre1, double *h1, double *pre2,
+                     double *h2)
+{
+    const int di = M->d_in, dh = M->d_h, dn = M->d_out;
+    double *a1 = (double *)malloc(sizeof(double) * dh), *z1 = (double *)malloc(sizeof(double) * dh);
+    double *a2 = (double *)malloc(sizeof(double) * dh), *z2 = (double *)malloc(sizeof(double) * dh);
+    for (int b = 0; b < B; ++b) {
+        const double *x = X + (size_t)b * di;
+        for (int j = 0; j < dh; ++j) {
+            double acc = M->b1[j];
+            for (int k = 0; k < di; ++k) acc += x[k] * M->W1[(size_t)k * dh + j];
+            z1[j] = acc;
+            a1[j] = gelu(acc);
+        }
+        for (int j = 0; j < dh; ++j) {
+            double acc = M->b2[j];
+            for (int k = 0; k < dh; ++k) acc += a1[k] * M->W2[(size_t)k * dh + j];
+            z2[j] = acc;
+            a2[j] = gelu(acc);
+        }
+        for (int j = 0; j < dn; ++j) {
+            double acc = M->b3[j];
+            for (int k = 0; k < dh; ++k) acc += a2[k] * M->W3[(size_t)k * dn + j];
+            out[(size_t)b * dn + j] = acc;
+        }
+        if (pre1) memcpy(pre1 + (size_t)b * dh, z1, sizeof(double) * dh);
+        if (h1) memcpy(h1 + (size_t)b * dh, a1, sizeof(double) * dh);
+        if (pre2) memcpy(pre2 + (size_t)b * dh, z2, sizeof(double) * dh);
+        if (h2) memcpy(h2 + (size_t)b * dh, a2, sizeof(double) * dh);
+    }
+    free(a1); free(z1); free(a2); free(z2);
+}
+
+/* Proposal of one row of network outputs (N steps): (mu_a, mu_d, sigma_a, sigma_d). */
+void ref_mlp_proposal(const double *o, int N, double sig_a, double sig_d, double *prop)
+{
+    for (int t = 0; t < N; ++t) {
+        double o2 = o[4 * t + 2], o3 = o[4 * t + 3];
+        o2 = o2 < MLP_LS_MIN ? MLP_LS_MIN : (o2 > MLP_LS_MAX ? MLP_LS_MAX : o2);
+        o3 = o3 < MLP_LS_MIN ? MLP_LS_MIN : (o3 > MLP_LS_MAX ? MLP_LS_MAX : o3);
+        prop[4 * t + 0] = MLP_A_SCALE * o[4 * t + 0];
+        prop[4 * t + 1] = MLP_D_SCALE * o[4 * t + 1];
+        prop[4 * t + 2] = sig_a * exp(o2);
+        prop[4 * t + 3] = sig_d * exp(o3);
+    }
+}
+
+/* Mean over the batch of the Gaussian negative log-likelihood of the targets U [B][N][2]
+ * (constant 0.5 log 2 pi dropped), and its gradient d_out [B][d_out] w.r.t. the outputs. */
+double ref_mlp_nll(const double *out, int B, int N, int d_out, double sig_a, double sig_d, const double *U,
+                   double *d_out_grad)
+{
+    double L = 0.0;
+    const double ls_plain[2] = {log(sig_a), log(sig_d)};
+    const double scale[2] = {MLP_A_SCALE, MLP_D_SCALE};
+    for (int b = 0; b < B; ++b) {
+        const double *o = out + (size_t)b * d_out;
+        double *g = d_out_grad ? d_out_grad + (size_t)b * d_out : NULL;
+        if (g) for (int j = 0; j < d_out; ++j) g[j] = 0.0;
+        for (int t = 0; t < N; ++t) {
+            for (int c = 0; c < 2; ++c) {
+                double mu = scale[c] * o[4 * t + c];
+                double raw = o[4 * t + 2 + c];
+                double cl = raw < MLP_LS_MIN ? MLP_LS_MIN : (raw > MLP_LS_MAX ? MLP_LS_MAX : raw);
+                double ls = ls_plain[c] + cl;
+                double sg2 = exp(2.0 * ls);
+                double r = U[((size_t)b * N + t) * 2 + c] - mu;
+                L += 0.5 * r * r / sg2 + ls;
+                if (g) {
+                    g[4 * t + c] = -scale[c] * r / sg2 / B;
+                    g[4 * t + 2 + c] = (raw > MLP_LS_MIN && raw < MLP_LS_MAX) ? (1.0 - r * r / sg2) / B : 0.0;
+                }
+            }
+        }
+    }
+    return L / B;
+}
+
+/* Back-propagation of d_out through the MLP: gradients of W1..b3 (same layouts). */
+void ref_mlp_backward(const ref_mlp *M, int B, const double *X, const double *d_out, double *gW1, double *gb1,
+                      double *gW2, double *gb2, double *gW3, double *gb3)
+{
+    const int di = M->d_in, dh = M->d_h, dn = M->d_out;
+    double *pre1 = (double *)malloc(sizeof(double) * (size_t)B * dh), *h1 = (double *)malloc(sizeof(double) * (size_t)B * dh);
+    double *pre2 = (double *)malloc(sizeof(double) * (size_t)B * dh), *h2 = (double *)malloc(sizeof(double) * (size_t)B * dh);
+    double *out = (double *)malloc(sizeof(double) * (size_t)B * dn);
+    double *d2 = (double *)malloc(sizeof(double) * dh), *d1 = (double *)malloc(sizeof(double) * dh);
+    ref_mlp_forward(M, B, X, out, pre1, h1, pre2, h2);
+    memset(gW1, 0, sizeof(double) * di * dh); memset(gb1, 0, sizeof(double) * dh);
+    memset(gW2, 0, sizeof(double) * dh * dh); memset(gb2, 0, sizeof(double) * dh);
+    memset(gW3, 0, sizeof(double) * dh * dn); memset(gb3, 0, sizeof(double) * dn);
+    for (int b = 0; b < B; ++b) {
+        const double *g = d_out + (size_t)b * dn;
+        const double *a2 = h2 + (size_t)b * dh, *a1 = h1 + (size_t)b * dh, *x = X + (size_t)b * di;
+        for (int j = 0; j < dn; ++j) {
+            gb3[j] += g[j];
+            for (int k = 0; k < dh; ++k) gW3[(size_t)k * dn + j] += a2[k] * g[j];
+        }
+        for (int k = 0; k < dh; ++k) {
+            double acc = 0.0;
+            for (int j = 0; j < dn; ++j) acc += M->W3[(size_t)k * dn + j] * g[j];
+            d2[k] = acc * gelu_grad(pre2[(size_t)b * dh + k]);
+        }
+        for (int j = 0; j < dh; ++j) {
+            gb2[j] += d2[j];
+            for (int k = 0; k < dh; ++k) gW2[(size_t)k * dh + j] += a1[k] * d2[j];
+        }
+        for (int k = 0; k < dh; ++k) {
+            double acc = 0.0;
+            for (int j = 0; j < dh; ++j) acc += M->W2[(size_t)k * dh + j] * d2[j];
+            d1[k] = acc * gelu_grad(pre1[(size_t)b * dh + k]);
+        }
+        for (int j = 0; j < dh; ++j) {
+            gb1[j] += d1[j];
+            for (int k = 0; k < di; ++k) gW1[(size_t)k * dh + j] += x[k] * d1[j];
+        }
+    }
+    free(pre1); free(h1); free(pre2); free(h2); free(out); free(d2); free(d1);
+}
+
+int ref_abi_version(void) { return 2; }
