@@ -84,6 +84,100 @@ def cpu_baseline(name: str, seconds: float = 10.0, K_sample: int = 2048):
                        f"({per_step} sample-steps each), {el:.1f} s")
 
 
+def _latency(plan, steps, warmup=10):
+    """p50 / p99 / mean of planning-step latency [ms] (HIP events on the launch stream)."""
+    import numpy as np
+    import torch
+    st = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.run()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record(st)
+        plan.run()
+        b.record(st)
+    torch.cuda.synchronize()
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)), "mean": float(lat.mean())}
+
+
+def learned_block(planner, n_examples: int, iters: int, eval_races: int = 32, lat_steps: int = 100):
+    """Learned proposal against the plain sampler on races of the mid-scale kind with N = 50:
+    train the network on the plain planner's own selections (closed loop, 256 races), then on
+    held-out races compare the selected best-response cost at K/4 (K/8 from the proposal,
+    K/8 about the nominal) with the plain planner at K and at K/4, and time planning steps
+    of the held-out batch and of one 3-vehicle race, plain at K against learned at K/4 (the
+    network's features, forward pass and tables run inside the captured step)."""
+    import numpy as np
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    from paper_2607_25388_amd import inputs, learned
+
+    K, N, L = 16384, 50, 5
+    t0 = time.perf_counter()
+    tr, races, params = inputs.learned_races(256, 5000, N=N)
+    planner.upload_track(7, tr)
+    rts = [sg.race_from_inputs(r, 7, K, N, params["n_tail"]) for r in races]
+    per_step = sum(r.n_agents for r in rts)
+    steps = max(1, -(-n_examples // per_step))
+    data = learned.collect(planner, params, rts, L, steps)
+    torch.cuda.synchronize()
+    t_collect = time.perf_counter() - t0
+    del rts
+    mlp = sg.Mlp(4096, seed=1)
+    t1 = time.perf_counter()
+    losses = learned.train(mlp, data, params, iters, batch=4096, lr=1e-3, log_every=max(1, iters // 4))
+    losses += learned.train(mlp, data, params, iters // 2, batch=4096, lr=3e-4, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    n_ex = int(data.X.shape[0])
+    del data
+
+    _, hold, _ = inputs.learned_races(eval_races, 7000, N=N)
+    rts = [sg.race_from_inputs(r, 7, K, N, params["n_tail"]) for r in hold]
+    plan = planner.plan(params, rts, L, sg.plan_options(include_advance=1), trace=False)
+    rec = {"K": [], "K4": [], "L4": []}
+    for step in range(30):
+        plan.run()
+        if step % 6 != 5:
+            continue
+        rec["K"].append(learned.best_response_costs(planner, params, rts, K))
+        rec["K4"].append(learned.best_response_costs(planner, params, rts, K // 4))
+        rec["L4"].append(learned.best_response_costs(planner, params, rts, K // 4, K // 8, mlp))
+    plan.close()
+    cat = {k: (np.concatenate([c for c, f in v]), np.concatenate([f for c, f in v])) for k, v in rec.items()}
+    gp, sp = learned.cost_gap(*cat["K4"], *cat["K"])
+    gl, sl = learned.cost_gap(*cat["L4"], *cat["K"])
+
+    def timed(batch, Kv, Kp):
+        rr = [sg.race_from_inputs(r, 7, Kv, N, params["n_tail"]) for r in batch]
+        if Kp:
+            learned.ensure_tables(rr, Kp)
+        pl = planner.plan(params, rr, L, sg.plan_options(include_advance=1), trace=False)
+        if Kp:
+            pl.set_proposal(mlp)
+        out = _latency(pl, lat_steps)
+        pl.close()
+        return out
+
+    lat = {"batch": {"races": len(hold), "plain_K": timed(hold, K, 0), "learned_K4": timed(hold, K // 4, K // 8)},
+           "single": {"vehicles": hold[1].n_agents, "plain_K": timed(hold[1:2], K, 0),
+                      "learned_K4": timed(hold[1:2], K // 4, K // 8)}}
+    mlp.close()
+    return {
+        "workload": (f"learned proposal: 256 training races (2-5 vehicles, 1.2 km x 12 m track, N={N}, K={K}, "
+                     f"{L} IBR sweeps), {n_ex} selected sequences; {eval_races} held-out races, best responses "
+                     f"at 5 closed-loop instants"),
+        "train": {"examples": n_ex, "collect_s": t_collect, "adam_iters": iters + iters // 2, "batch": 4096,
+                  "train_s": t_train, "loss_first": losses[0], "loss_last": losses[-1]},
+        "cost": {"cases": int(len(gl)), "plain_K4_mean_gap": float(gp.mean()), "plain_K4_sum_gap": sp,
+                 "learned_K4_mean_gap": float(gl.mean()), "learned_K4_sum_gap": sl,
+                 "learned_K4_not_worse_frac": float(np.mean(gl <= 0.0)),
+                 "reference": "plain sampler at K, same states and noise stream"},
+        "latency_ms": lat,
+    }
+
+
 def _races_for(name, sg, inputs, planner):
     """Device races, parameters, L and per-plan-step sample-steps of a workload."""
     if name == "c4":
@@ -122,6 +216,10 @@ def main():
     ap.add_argument("--roofline-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
+    ap.add_argument("--learned-examples", type=int, default=100000,
+                    help="training examples of the learned proposal (the c5 workload uses 1e6)")
+    ap.add_argument("--learned-iters", type=int, default=4000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this planner runs on a single device (see the design notes for how "
@@ -135,6 +233,16 @@ def main():
 
     name = args.workload
     planner = sg.Planner(max_agents_total=2048, max_races=256)
+    if name == "c5":
+        rec = {"metric": METRIC, "unit": "relative selected cost", "n_gpus": 1, "higher_is_better": False,
+               "vs_baseline": None, "dtype": "f32 planner, bf16 network (f32 accumulation)", "data": "synthetic"}
+        lb = learned_block(planner, max(args.learned_examples, 1000000), max(args.learned_iters, 20000),
+                           eval_races=64)
+        rec.update({"value": lb["cost"]["learned_K4_mean_gap"], "config": {"workload": lb["workload"]},
+                    "learned": lb})
+        planner.close()
+        print(json.dumps(rec), flush=True)
+        return
     rts, params, L, per_step, desc, n_total = _races_for(name, sg, inputs, planner)
     stream = torch.cuda.current_stream()
     opts = sg.plan_options(include_advance=1)
@@ -210,6 +318,8 @@ def main():
     }
     if tuned:
         rec["config"]["autotune"] = tuned
+    if not args.no_learned:
+        rec["learned"] = learned_block(planner, args.learned_examples, args.learned_iters)
     if not args.no_cpu_baseline and name != "c4":
         rec["cpu_baseline"] = cpu_baseline(name, args.cpu_seconds)
     planner.close()

@@ -92,6 +92,8 @@ typedef struct {
     const float *v_scale;      /* [n] reference-speed scale of each vehicle (opponents 0.9, Sec. IV-B) */
     float *u_nom;              /* [n][N][2] nominal sequences U-bar (in/out: warm start) */
     double *traj;              /* [n][N+1][8] out: planned trajectories, or NULL */
+    float *prop;               /* [n][N][4] learned proposal (mu_a, mu_d, sigma_a, sigma_d), or NULL */
+    int K_prop;                /* samples k < K_prop are drawn about the proposal, the rest about u_nom */
 } sgtp_race;
 
 /* Result of one best response. */
@@ -203,6 +205,69 @@ int sgtp_plan_destroy(sgtp_plan *plan);
  * The races' u_nom and s_abs are saved and restored; allocates temporary memory. */
 int sgtp_autotune(sgtp_ctx *ctx, const sgtp_params *p, const sgtp_race *races, int n_races, int L_ibr,
                   float *u_apply, sgtp_plan_options *best, double *best_ms, void *stream);
+
+/* ---- learned proposal (project extension; network in sgtp_mlp_*) ------------ */
+
+#define SGTP_FEAT_DIM 50
+#define SGTP_MLP_OUT 200 /* 4 values per step for a horizon of 50 */
+
+/* Features of every vehicle of every race, DEVICE X[sum n][50] in slot order (race
+ * by race): ego (d / half width, heading error to the raceline, v_x / 30, v_y / 5,
+ * omega, (v_x - v_ref) / 10); the 4 opponents nearest in progress (s_j - s_i) / 20,
+ * (d_j - d_i) / half width, heading difference, (v_x,j - v_x,i) / 10, v_y,j / 5, 1 -
+ * zeros when absent; curvature x 20 at 5, 10, ..., 100 m ahead.  Runs the setup of
+ * the races (writes s_abs). */
+int sgtp_features(sgtp_ctx *ctx, const sgtp_params *p, const sgtp_race *races, int n_races, float *X,
+                  void *stream);
+/* Proposal tables from DEVICE network outputs out[sum n][ld_out] (per step: o0..o3):
+ * mu_a = 4 o0, mu_d = 0.2 o1 (residual != 0: plus the vehicle's nominal control
+ * u_nom at that step), sigma_a = sigma_a,plain exp(clamp(o2, -4, 1)),
+ * sigma_d = sigma_d,plain exp(clamp(o3, -4, 1)); written to races[r].prop (races
+ * with prop == NULL are skipped; 4 N <= ld_out is required). */
+int sgtp_proposal_from_outputs(sgtp_ctx *ctx, const sgtp_params *p, const sgtp_race *races, int n_races,
+                               const float *out, int ld_out, int residual, void *stream);
+
+/* Proposal network: 50 -> 256 -> 256 -> 200, tanh-form GELU after the two hidden
+ * layers.  Parameters are float32 packed as W1[50][256] b1[256] W2[256][256] b2[256]
+ * W3[256][200] b3[200] (W stored [fan_in][fan_out]), sgtp_mlp_num_params() values.
+ * Every product runs on BF16 matrix cores with float32 accumulation; master weights
+ * and Adam moments stay float32.  A network owns workspaces for batches up to B_max
+ * rows; calls on one network are ordered by the caller's stream and must not overlap. */
+typedef struct sgtp_mlp sgtp_mlp;
+int sgtp_mlp_create(int B_max, sgtp_mlp **out);
+int sgtp_mlp_destroy(sgtp_mlp *m);
+const char *sgtp_mlp_last_error(const sgtp_mlp *m);
+int sgtp_mlp_num_params(void);
+int sgtp_mlp_batch_max(const sgtp_mlp *m);
+/* HOST params in; resets the Adam moments and step count.  Synchronous. */
+int sgtp_mlp_set_params(sgtp_mlp *m, const float *host_params);
+/* HOST params out (current master weights).  Synchronous. */
+int sgtp_mlp_get_params(sgtp_mlp *m, float *host_params);
+/* DEVICE X[B][50] -> DEVICE out[B][ld_out] (ld_out >= 200), float32. */
+int sgtp_mlp_forward(sgtp_mlp *m, const float *X, int B, float *out, int ld_out, void *stream);
+/* Mean over the B rows of the Gaussian negative log-likelihood of the DEVICE targets
+ * U[B][N][2] (N <= 50 steps; the constant 0.5 log 2 pi per value is dropped) under the
+ * proposal of DEVICE features X[B][50] (means 4 o0 and 0.2 o1, log scales
+ * log sigma_plain + clamp(o, -4, 1)), and its gradient w.r.t. every parameter, kept
+ * for sgtp_mlp_adam.  loss (DEVICE, 1 value) and grads (DEVICE, num_params values)
+ * receive copies when not NULL. */
+int sgtp_mlp_grad(sgtp_mlp *m, const float *X, const float *U, int B, int N, float sig_a, float sig_d, float *loss,
+                  float *grads, void *stream);
+/* One Adam step with the last gradients (bias-corrected moments). */
+int sgtp_mlp_adam(sgtp_mlp *m, float lr, float beta1, float beta2, float eps, void *stream);
+/* Make every planning step of `plan` compute the proposal tables itself: after the
+ * setup, the features of every vehicle, the network's forward pass and the tables of
+ * the races created with prop != NULL (their K_prop samples come from the proposal).
+ * m == NULL detaches.  The network must hold batches of the plan's vehicle count and
+ * every race with a table must have N <= 50; it must outlive the plan (or be
+ * detached), and parameter updates take effect at the next run.  A graph plan is
+ * captured again.  Allocates the feature and output buffers; synchronises. */
+int sgtp_plan_set_proposal(sgtp_plan *plan, sgtp_mlp *m, int residual);
+/* The network's matrix product on its own: C[m][n] = sum_k A(m, k) B(k, n) over DEVICE
+ * BF16 operands with element strides (A(m, k) = A[m a_m + k a_k], B(k, n) =
+ * B[k b_k + n b_n]), plus bias[n] when not NULL, into DEVICE float32 C[M][ldc]. */
+int sgtp_gemm_bf16(const void *A, long long a_m, long long a_k, const void *B, long long b_k, long long b_n, int M,
+                   int N, int K, const float *bias, float *C, long long ldc, void *stream);
 
 /* ---- instrumentation ------------------------------------------------------ */
 

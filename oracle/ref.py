@@ -131,7 +131,8 @@ def load(rebuild: bool = False):
         lib.ref_features.argtypes = [P(TrackS), P(Params), P(RaceS), P(C.c_double)]
         lib.ref_mlp_forward.argtypes = [P(Mlp), C.c_int, P(C.c_double), P(C.c_double), P(C.c_double),
                                         P(C.c_double), P(C.c_double), P(C.c_double)]
-        lib.ref_mlp_proposal.argtypes = [P(C.c_double), C.c_int, C.c_double, C.c_double, P(C.c_double)]
+        lib.ref_mlp_proposal.argtypes = [P(C.c_double), C.c_int, C.c_double, C.c_double, P(C.c_double),
+                                         P(C.c_double)]
         lib.ref_mlp_nll.argtypes = [P(C.c_double), C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                     P(C.c_double), P(C.c_double)]
         lib.ref_mlp_nll.restype = C.c_double
@@ -397,10 +398,11 @@ class MlpOracle:
         self.lib.ref_mlp_backward(C.byref(self.M), X.shape[0], _dp(X), _dp(d_out), *[_dp(g) for g in grads])
         return grads
 
-    def proposal(self, out_row, N, sig_a, sig_d):
+    def proposal(self, out_row, N, sig_a, sig_d, ubar=None):
         o = np.ascontiguousarray(out_row, np.float64)
         prop = np.zeros((N, 4))
-        self.lib.ref_mlp_proposal(_dp(o), N, sig_a, sig_d, _dp(prop))
+        ub = None if ubar is None else np.ascontiguousarray(ubar, np.float64)
+        self.lib.ref_mlp_proposal(_dp(o), N, sig_a, sig_d, None if ub is None else _dp(ub), _dp(prop))
         return prop
 
 

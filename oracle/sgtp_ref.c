@@ -1089,15 +1089,16 @@ void ref_mlp_forward(const ref_mlp *M, int B, const double *X, double *out, doub
     free(a1); free(z1); free(a2); free(z2);
 }
 
-/* Proposal of one row of network outputs (N steps): (mu_a, mu_d, sigma_a, sigma_d). */
-void ref_mlp_proposal(const double *o, int N, double sig_a, double sig_d, double *prop)
+/* Proposal of one row of network outputs (N steps): (mu_a, mu_d, sigma_a, sigma_d).
+ * With ubar [N][2] (residual form) the means are offsets from the nominal sequence. */
+void ref_mlp_proposal(const double *o, int N, double sig_a, double sig_d, const double *ubar, double *prop)
 {
     for (int t = 0; t < N; ++t) {
         double o2 = o[4 * t + 2], o3 = o[4 * t + 3];
         o2 = o2 < MLP_LS_MIN ? MLP_LS_MIN : (o2 > MLP_LS_MAX ? MLP_LS_MAX : o2);
         o3 = o3 < MLP_LS_MIN ? MLP_LS_MIN : (o3 > MLP_LS_MAX ? MLP_LS_MAX : o3);
-        prop[4 * t + 0] = MLP_A_SCALE * o[4 * t + 0];
-        prop[4 * t + 1] = MLP_D_SCALE * o[4 * t + 1];
+        prop[4 * t + 0] = (ubar ? ubar[2 * t] : 0.0) + MLP_A_SCALE * o[4 * t + 0];
+        prop[4 * t + 1] = (ubar ? ubar[2 * t + 1] : 0.0) + MLP_D_SCALE * o[4 * t + 1];
         prop[4 * t + 2] = sig_a * exp(o2);
         prop[4 * t + 3] = sig_d * exp(o3);
     }

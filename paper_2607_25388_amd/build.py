@@ -9,7 +9,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = os.path.join(PKG, "csrc", "sgtp.hip")
+SRCS = [os.path.join(PKG, "csrc", f) for f in ("sgtp.hip", "mlp.hip")]
 LIB = os.path.join(PKG, "libsgtp.so")
 ARCH = os.environ.get("SGTP_OFFLOAD_ARCH", "gfx950")
 
@@ -35,7 +35,7 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, SRC]
+    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, *SRCS]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

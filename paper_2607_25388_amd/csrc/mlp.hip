@@ -1,0 +1,412 @@
+// mlp.hip -- learned sampling proposal for the SGTP planner on gfx950 (project
+// extension; not part of the paper's method).
+//
+// A 50 -> 256 -> 256 -> 200 MLP with tanh-form GELU predicts, for every horizon
+// step, the mean and log-scale of the (acceleration, steering) perturbation
+// distribution from the vehicle's features.  All matrix products run on BF16
+// MFMA (v_mfma_f32_16x16x32_bf16) with float32 accumulation: forward, the two
+// backward products per layer (input gradient and weight gradient) and the
+// Gaussian negative log-likelihood of the planner's own selected controls.
+// Master weights and Adam moments are float32; the GEMM operands are BF16 copies.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include <cmath>
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sgtp.h"
+
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int D_IN = SGTP_FEAT_DIM;  // 50 features
+constexpr int D_INP = 64;            // padded input width
+constexpr int D_H = 256;
+constexpr int D_OUT = SGTP_MLP_OUT;  // 200 outputs
+constexpr int D_OUTP = 256;          // padded output width
+constexpr int N_H = SGTP_MLP_OUT / 4;
+constexpr float A_SCALE = 4.0f, D_SCALE = 0.2f, LS_MIN = -4.0f, LS_MAX = 1.0f;
+
+// packed float32 parameter layout (the oracle's): W1[50][256] b1 W2[256][256] b2 W3[256][200] b3
+constexpr size_t P_W1 = 0, P_B1 = P_W1 + (size_t)D_IN * D_H, P_W2 = P_B1 + D_H, P_B2 = P_W2 + (size_t)D_H * D_H,
+                 P_W3 = P_B2 + D_H, P_B3 = P_W3 + (size_t)D_H * D_OUT, P_TOTAL = P_B3 + D_OUT;
+
+// ------------------------------------------------------------------------------
+// BF16 MFMA GEMM: C[m][n] = sum_k A(m, k) B(k, n) (+ bias[n]); optional GELU copy in BF16.
+// A(m, k) = A[m a_m + k a_k], B(k, n) = B[k b_k + n b_n] (any strides, so transposed
+// operands need no copies).  Workgroup tile 64 x 64, K step 32; each of the 4 waves owns
+// a 32 x 32 quarter as 2 x 2 MFMA tiles of 16 x 16 x 32.  Fragments of A and B use the
+// same lane -> k assignment, so the product does not depend on the k order inside a step.
+// ------------------------------------------------------------------------------
+struct GemmArgs {
+    const bf16 *A;
+    long long a_m, a_k;
+    const bf16 *B;
+    long long b_k, b_n;
+    int M, N, K;
+    const float *bias;  // [N] or NULL
+    float *C;           // [M][ldc] float32 result (pre-activation), or NULL
+    long long ldc;
+    bf16 *H;            // [M][ldh] BF16 GELU(result), or NULL
+    long long ldh;
+};
+
+__device__ __forceinline__ float gelu_f(float x) {
+    const float c = 0.7978845608f;
+    return 0.5f * x * (1.0f + tanhf(c * (x + 0.044715f * x * x * x)));
+}
+__device__ __forceinline__ float gelu_grad_f(float x) {
+    const float c = 0.7978845608f;
+    const float u = c * (x + 0.044715f * x * x * x);
+    const float t = tanhf(u);
+    return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * c * (1.0f + 3.0f * 0.044715f * x * x);
+}
+
+__global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
+    __shared__ __align__(16) bf16 As[64][40];  // [m][k], row padded to 80 bytes
+    __shared__ __align__(16) bf16 Bs[64][40];  // [n][k]
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+    // split K: slice z of gridDim.z covers [kbeg, kend) and adds its partial product into C
+    const int kslice = ((g.K + 32 * gridDim.z - 1) / (32 * gridDim.z)) * 32;
+    const int kbeg = blockIdx.z * kslice, kend = min(g.K, kbeg + kslice);
+    for (int k0 = kbeg; k0 < kend; k0 += 32) {
+        // staging walks the operand's unit-stride index across consecutive lanes
+        for (int e = tid; e < 64 * 32; e += 256) {
+            int r = e >> 5, c = e & 31;
+            if (g.a_k != 1) r = e & 63, c = e >> 6;
+            const int m = m0 + r, k = k0 + c;
+            As[r][c] = (m < g.M && k < kend) ? g.A[(long long)m * g.a_m + (long long)k * g.a_k] : (bf16)0.0f;
+        }
+        for (int e = tid; e < 64 * 32; e += 256) {
+            int r = e >> 5, c = e & 31;
+            if (g.b_k != 1) r = e & 63, c = e >> 6;
+            const int n = n0 + r, k = k0 + c;
+            Bs[r][c] = (n < g.N && k < kend) ? g.B[(long long)k * g.b_k + (long long)n * g.b_n] : (bf16)0.0f;
+        }
+        __syncthreads();
+        bf16x8 a[2], b[2];
+        const int kk = 8 * (l >> 4);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            a[i] = *(const bf16x8 *)&As[wm + 16 * i + (l & 15)][kk];
+            b[i] = *(const bf16x8 *)&Bs[wn + 16 * i + (l & 15)][kk];
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // D(16 x 16) of one MFMA: lane l, element v -> row 4 (l / 16) + v, column l % 16
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int m = m0 + wm + 16 * i + 4 * (l >> 4) + v;
+                const int n = n0 + wn + 16 * j + (l & 15);
+                if (m < g.M && n < g.N) {
+                    float x = acc[i][j][v];
+                    if (gridDim.z > 1) {
+                        atomicAdd(&g.C[(long long)m * g.ldc + n], x);
+                        continue;
+                    }
+                    if (g.bias) x += g.bias[n];
+                    if (g.C) g.C[(long long)m * g.ldc + n] = x;
+                    if (g.H) g.H[(long long)m * g.ldh + n] = (bf16)gelu_f(x);
+                }
+            }
+}
+
+__global__ void k_to_bf16_rows(const float *X, int B, int din, int ldx, bf16 *Y, int ldy) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = e / ldy, c = e % ldy;
+    if (b >= B) return;
+    Y[(long long)b * ldy + c] = (c < din) ? (bf16)X[(long long)b * ldx + c] : (bf16)0.0f;
+}
+
+// packed float32 weights -> BF16 GEMM operands (W3 padded to 256 columns)
+__global__ void k_refresh_bf16(const float *P, bf16 *W1, bf16 *W2, bf16 *W3, float *b3p) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < D_IN * D_H) W1[e] = (bf16)P[P_W1 + e];
+    if (e < D_H * D_H) W2[e] = (bf16)P[P_W2 + e];
+    if (e < D_H * D_OUTP) {
+        const int r = e / D_OUTP, c = e % D_OUTP;
+        W3[e] = (c < D_OUT) ? (bf16)P[P_W3 + (size_t)r * D_OUT + c] : (bf16)0.0f;
+    }
+    if (e < D_OUTP) b3p[e] = (e < D_OUT) ? P[P_B3 + e] : 0.0f;
+}
+
+// Gaussian negative log-likelihood of the targets U[B][N][2] (mean over rows, constant
+// 0.5 log 2 pi dropped; steps t >= N do not enter) and its gradient w.r.t. the outputs,
+// as BF16 for the products.  One thread per (row, step < 64, channel).
+__global__ void k_nll(const float *out, int ldo, const float *U, int B, int N, float sig_a, float sig_d, bf16 *dout,
+                      int ldd, float *loss_sum) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = e >> 7, t = (e >> 1) & 63, c = e & 1;
+    float contrib = 0.0f;
+    if (b < B && 4 * t < ldd) {
+        bf16 *g = dout + (long long)b * ldd;
+        if (t < N) {
+            const float *o = out + (long long)b * ldo;
+            const float scale = c ? D_SCALE : A_SCALE;
+            const float lsp = logf(c ? sig_d : sig_a);
+            const float mu = scale * o[4 * t + c];
+            const float raw = o[4 * t + 2 + c];
+            const float cl = fminf(fmaxf(raw, LS_MIN), LS_MAX);
+            const float ls = lsp + cl;
+            const float inv_s2 = expf(-2.0f * ls);
+            const float res = U[((long long)b * N + t) * 2 + c] - mu;
+            contrib = 0.5f * res * res * inv_s2 + ls;
+            g[4 * t + c] = (bf16)(-scale * res * inv_s2 / (float)B);
+            g[4 * t + 2 + c] = (bf16)((raw > LS_MIN && raw < LS_MAX) ? (1.0f - res * res * inv_s2) / (float)B : 0.0f);
+        } else {
+            g[4 * t + c] = (bf16)0.0f;
+            g[4 * t + 2 + c] = (bf16)0.0f;
+        }
+    }
+    // wave reduction of the loss, one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off);
+    if ((threadIdx.x & 63) == 0) atomicAdd(loss_sum, contrib / (float)B);
+}
+
+// dpre = dh * gelu'(pre) as BF16
+__global__ void k_gelu_back(const float *dh, const float *pre, int n, bf16 *dpre) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) dpre[e] = (bf16)(dh[e] * gelu_grad_f(pre[e]));
+}
+
+// column sums of a BF16 [B][ld] matrix added into float32 dst[ncols] (bias gradients; dst
+// cleared beforehand): block x covers 256 columns, block y a slice of 256 rows
+__global__ void k_colsum(const bf16 *D, int B, int ld, int ncols, float *dst) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncols) return;
+    const int b0 = blockIdx.y * 256, b1 = min(B, b0 + 256);
+    float s = 0.0f;
+    for (int b = b0; b < b1; ++b) s += (float)D[(long long)b * ld + c];
+    atomicAdd(&dst[c], s);
+}
+
+// copy a [rows][cols] block of a float32 matrix with row stride lds into packed storage
+__global__ void k_pack(const float *S, int rows, int cols, int lds, float *dst) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * cols) return;
+    const int r = e / cols, c = e % cols;
+    dst[e] = S[(long long)r * lds + c];
+}
+
+__global__ void k_adam(float *P, const float *G, float *m, float *v, int n, float lr, float b1, float b2, float eps,
+                       float bc1, float bc2) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const float g = G[e];
+    const float mm = b1 * m[e] + (1.0f - b1) * g;
+    const float vv = b2 * v[e] + (1.0f - b2) * g * g;
+    m[e] = mm;
+    v[e] = vv;
+    P[e] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+}
+
+}  // namespace
+
+struct sgtp_mlp {
+    int B_max = 0;
+    std::string err;
+    float *P = nullptr, *G = nullptr, *Mm = nullptr, *Vv = nullptr;  // packed float32
+    bf16 *W1 = nullptr, *W2 = nullptr, *W3 = nullptr;              // BF16 operands
+    float *b3p = nullptr;
+    bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *D = nullptr, *D1 = nullptr;
+    float *PRE1 = nullptr, *PRE2 = nullptr, *OUT = nullptr, *DH = nullptr, *GW = nullptr, *loss = nullptr;
+    int adam_t = 0;
+};
+
+namespace {
+
+int mfail(sgtp_mlp *m, int code, const std::string &s) {
+    if (m) m->err = s;
+    return code;
+}
+#define MCHK(m, call)                                                                                        \
+    do {                                                                                                     \
+        hipError_t e_ = (call);                                                                              \
+        if (e_ != hipSuccess) return mfail(m, SGTP_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+void gemm(hipStream_t st, const bf16 *A, long long a_m, long long a_k, const bf16 *B, long long b_k, long long b_n,
+          int M, int N, int K, const float *bias, float *C, long long ldc, bf16 *H, long long ldh, int splits = 1) {
+    GemmArgs g{A, a_m, a_k, B, b_k, b_n, M, N, K, bias, C, ldc, H, ldh};
+    hipLaunchKernelGGL(k_gemm_bf16, dim3((N + 63) / 64, (M + 63) / 64, splits), dim3(256), 0, st, g);
+}
+
+// K split of a weight-gradient product (K = batch): about 512 rows per slice, at most 64 slices
+int k_splits(int K) { return std::max(1, std::min(64, (K + 511) / 512)); }
+
+// forward of B rows (features float32 [B][ldx]) into out[B][ldo], n_out columns (200, or
+// 256 with the zero padding for the loss)
+int forward(sgtp_mlp *m, const float *X, int ldx, int B, float *out, int ldo, int n_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_bf16_rows, dim3((B * D_INP + 255) / 256), dim3(256), 0, st, X, B, D_IN, ldx, m->X, D_INP);
+    gemm(st, m->X, D_INP, 1, m->W1, D_H, 1, B, D_H, D_IN, m->P + P_B1, m->PRE1, D_H, m->H1, D_H);
+    gemm(st, m->H1, D_H, 1, m->W2, D_H, 1, B, D_H, D_H, m->P + P_B2, m->PRE2, D_H, m->H2, D_H);
+    gemm(st, m->H2, D_H, 1, m->W3, D_OUTP, 1, B, n_out, D_H, m->b3p, out, ldo, nullptr, 0);
+    MCHK(m, hipGetLastError());
+    return SGTP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sgtp_mlp_create(int B_max, sgtp_mlp **out) {
+    if (!out || B_max < 1) return SGTP_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return SGTP_EDEVICE;
+    sgtp_mlp *m = new sgtp_mlp();
+    m->B_max = B_max;
+    bool ok = true;
+    auto al = [&](void **p, size_t bytes) {
+        if (ok && hipMalloc(p, bytes) != hipSuccess) ok = false;
+        if (ok && hipMemset(*p, 0, bytes) != hipSuccess) ok = false;
+    };
+    al((void **)&m->P, P_TOTAL * 4);
+    al((void **)&m->G, P_TOTAL * 4);
+    al((void **)&m->Mm, P_TOTAL * 4);
+    al((void **)&m->Vv, P_TOTAL * 4);
+    al((void **)&m->W1, (size_t)D_IN * D_H * 2);
+    al((void **)&m->W2, (size_t)D_H * D_H * 2);
+    al((void **)&m->W3, (size_t)D_H * D_OUTP * 2);
+    al((void **)&m->b3p, D_OUTP * 4);
+    al((void **)&m->X, (size_t)B_max * D_INP * 2);
+    al((void **)&m->H1, (size_t)B_max * D_H * 2);
+    al((void **)&m->H2, (size_t)B_max * D_H * 2);
+    al((void **)&m->D, (size_t)B_max * D_OUTP * 2);
+    al((void **)&m->D1, (size_t)B_max * D_H * 2);
+    al((void **)&m->PRE1, (size_t)B_max * D_H * 4);
+    al((void **)&m->PRE2, (size_t)B_max * D_H * 4);
+    al((void **)&m->OUT, (size_t)B_max * D_OUTP * 4);
+    al((void **)&m->DH, (size_t)B_max * D_H * 4);
+    al((void **)&m->GW, (size_t)D_H * D_OUTP * 4);
+    al((void **)&m->loss, 4);
+    if (!ok) {
+        sgtp_mlp_destroy(m);
+        return SGTP_ENOMEM;
+    }
+    *out = m;
+    return SGTP_OK;
+}
+
+int sgtp_mlp_destroy(sgtp_mlp *m) {
+    if (!m) return SGTP_EINVAL;
+    (void)hipDeviceSynchronize();
+    void *bufs[] = {m->P, m->G, m->Mm, m->Vv, m->W1, m->W2, m->W3, m->b3p, m->X, m->H1, m->H2,
+                    m->D, m->D1, m->PRE1, m->PRE2, m->OUT, m->DH, m->GW, m->loss};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    delete m;
+    return SGTP_OK;
+}
+
+const char *sgtp_mlp_last_error(const sgtp_mlp *m) { return m ? m->err.c_str() : "null network"; }
+
+int sgtp_mlp_num_params(void) { return (int)P_TOTAL; }
+
+int sgtp_mlp_batch_max(const sgtp_mlp *m) { return m ? m->B_max : 0; }
+
+int sgtp_mlp_set_params(sgtp_mlp *m, const float *host) {
+    if (!m || !host) return SGTP_EINVAL;
+    MCHK(m, hipMemcpy(m->P, host, P_TOTAL * 4, hipMemcpyHostToDevice));
+    MCHK(m, hipMemset(m->Mm, 0, P_TOTAL * 4));
+    MCHK(m, hipMemset(m->Vv, 0, P_TOTAL * 4));
+    m->adam_t = 0;
+    hipLaunchKernelGGL(k_refresh_bf16, dim3((D_H * D_OUTP + 255) / 256), dim3(256), 0, nullptr, m->P, m->W1, m->W2,
+                       m->W3, m->b3p);
+    MCHK(m, hipGetLastError());
+    MCHK(m, hipDeviceSynchronize());
+    return SGTP_OK;
+}
+
+int sgtp_mlp_get_params(sgtp_mlp *m, float *host) {
+    if (!m || !host) return SGTP_EINVAL;
+    MCHK(m, hipDeviceSynchronize());
+    MCHK(m, hipMemcpy(host, m->P, P_TOTAL * 4, hipMemcpyDeviceToHost));
+    return SGTP_OK;
+}
+
+int sgtp_mlp_forward(sgtp_mlp *m, const float *X, int B, float *out, int ld_out, void *stream) {
+    if (!m || !X || !out) return SGTP_EINVAL;
+    if (B < 1 || B > m->B_max) return mfail(m, SGTP_ESHAPE, "batch larger than the network workspace");
+    if (ld_out < D_OUT) return mfail(m, SGTP_EINVAL, "ld_out < 200");
+    return forward(m, X, D_IN, B, out, ld_out, D_OUT, (hipStream_t)stream);
+}
+
+int sgtp_mlp_grad(sgtp_mlp *m, const float *X, const float *U, int B, int N, float sig_a, float sig_d, float *loss,
+                  float *grads, void *stream) {
+    if (!m || !X || !U) return SGTP_EINVAL;
+    if (B < 1 || B > m->B_max) return mfail(m, SGTP_ESHAPE, "batch larger than the network workspace");
+    if (N < 1 || N > N_H) return mfail(m, SGTP_ESHAPE, "horizon outside [1, 50]");
+    if (!(sig_a > 0.0f) || !(sig_d > 0.0f)) return mfail(m, SGTP_EINVAL, "plain scales must be positive");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = forward(m, X, D_IN, B, m->OUT, D_OUTP, D_OUTP, st);
+    if (rc) return rc;
+    MCHK(m, hipMemsetAsync(m->loss, 0, 4, st));
+    MCHK(m, hipMemsetAsync(m->G, 0, P_TOTAL * 4, st));
+    MCHK(m, hipMemsetAsync(m->GW, 0, (size_t)D_H * D_OUTP * 4, st));
+    const int sp = k_splits(B), rb = (B + 255) / 256;
+    hipLaunchKernelGGL(k_nll, dim3((B * 128 + 255) / 256), dim3(256), 0, st, m->OUT, D_OUTP, U, B, N, sig_a, sig_d,
+                       m->D, D_OUTP, m->loss);
+    // layer 3: gW3 = H2^T D, gb3 = column sums of D, dH2 = D W3^T
+    gemm(st, m->H2, 1, D_H, m->D, D_OUTP, 1, D_H, D_OUTP, B, nullptr, m->GW, D_OUTP, nullptr, 0, sp);
+    hipLaunchKernelGGL(k_pack, dim3((D_H * D_OUT + 255) / 256), dim3(256), 0, st, m->GW, D_H, D_OUT, D_OUTP, m->G + P_W3);
+    hipLaunchKernelGGL(k_colsum, dim3(1, rb), dim3(256), 0, st, m->D, B, D_OUTP, D_OUT, m->G + P_B3);
+    gemm(st, m->D, D_OUTP, 1, m->W3, 1, D_OUTP, B, D_H, D_OUTP, nullptr, m->DH, D_H, nullptr, 0);
+    hipLaunchKernelGGL(k_gelu_back, dim3((B * D_H + 255) / 256), dim3(256), 0, st, m->DH, m->PRE2, B * D_H, m->D1);
+    // layer 2: gW2 = H1^T D1, gb2, dH1 = D1 W2^T
+    gemm(st, m->H1, 1, D_H, m->D1, D_H, 1, D_H, D_H, B, nullptr, m->G + P_W2, D_H, nullptr, 0, sp);
+    hipLaunchKernelGGL(k_colsum, dim3(1, rb), dim3(256), 0, st, m->D1, B, D_H, D_H, m->G + P_B2);
+    gemm(st, m->D1, D_H, 1, m->W2, 1, D_H, B, D_H, D_H, nullptr, m->DH, D_H, nullptr, 0);
+    hipLaunchKernelGGL(k_gelu_back, dim3((B * D_H + 255) / 256), dim3(256), 0, st, m->DH, m->PRE1, B * D_H, m->D1);
+    // layer 1: gW1 = X^T D1, gb1
+    gemm(st, m->X, 1, D_INP, m->D1, D_H, 1, D_IN, D_H, B, nullptr, m->G + P_W1, D_H, nullptr, 0, sp);
+    hipLaunchKernelGGL(k_colsum, dim3(1, rb), dim3(256), 0, st, m->D1, B, D_H, D_H, m->G + P_B1);
+    MCHK(m, hipGetLastError());
+    if (loss) MCHK(m, hipMemcpyAsync(loss, m->loss, 4, hipMemcpyDeviceToDevice, st));
+    if (grads) MCHK(m, hipMemcpyAsync(grads, m->G, P_TOTAL * 4, hipMemcpyDeviceToDevice, st));
+    return SGTP_OK;
+}
+
+int sgtp_mlp_adam(sgtp_mlp *m, float lr, float beta1, float beta2, float eps, void *stream) {
+    if (!m) return SGTP_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    m->adam_t += 1;
+    const float bc1 = 1.0f - std::pow(beta1, (float)m->adam_t), bc2 = 1.0f - std::pow(beta2, (float)m->adam_t);
+    hipLaunchKernelGGL(k_adam, dim3((P_TOTAL + 255) / 256), dim3(256), 0, st, m->P, m->G, m->Mm, m->Vv, (int)P_TOTAL,
+                       lr, beta1, beta2, eps, bc1, bc2);
+    hipLaunchKernelGGL(k_refresh_bf16, dim3((D_H * D_OUTP + 255) / 256), dim3(256), 0, st, m->P, m->W1, m->W2, m->W3,
+                       m->b3p);
+    MCHK(m, hipGetLastError());
+    return SGTP_OK;
+}
+
+int sgtp_gemm_bf16(const void *A, long long a_m, long long a_k, const void *B, long long b_k, long long b_n, int M,
+                   int N, int K, const float *bias, float *C, long long ldc, void *stream) {
+    if (!A || !B || !C || M < 1 || N < 1 || K < 1) return SGTP_EINVAL;
+    gemm((hipStream_t)stream, (const bf16 *)A, a_m, a_k, (const bf16 *)B, b_k, b_n, M, N, K, bias, C, ldc, nullptr, 0);
+    return hipGetLastError() == hipSuccess ? SGTP_OK : SGTP_EDEVICE;
+}
+
+}  // extern "C"

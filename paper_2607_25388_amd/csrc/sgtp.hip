@@ -75,6 +75,8 @@ struct RaceDev {
     const float *v_scale;
     float *u_nom;
     double *traj;
+    const float4 *prop;  // [n][N] proposal (mu_a, mu_d, sigma_a, sigma_d), or NULL
+    int K_prop, pad2;
 };
 
 struct ItemDev {  // one best response (race, vehicle) of a launch
@@ -84,13 +86,14 @@ struct ItemDev {  // one best response (race, vehicle) of a launch
 
 struct AgentRec {  // per vehicle, written by k_setup
     double ox, oy, psi0, c0, s0, s_abs, d0;
+    double half_w, psi_ref, v_ref;  // at the foot of the current state (features)
     long long seg_abs, win0;
     int win_n, seg_loc;
     float vx, vy, om, lam;
 };
 
 struct LdsLayout {  // byte offsets of the staged tables, identical for every block of a launch
-    int ubar, xref, oppT, oppc, opp, nodes;
+    int ubar, xref, oppT, oppc, opp, nodes, prop;
     int rr_u, rr_st, rr_f, rr_t, rr_g, rr_l;  // re-roll scratch
     int total;
     int n_opp_max, w_max, N_max;
@@ -460,7 +463,7 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
 // Per-block staging into LDS (every sweep workgroup of a vehicle stages the same tables)
 // ------------------------------------------------------------------------------
 struct BlockState {
-    int slot, race, agent, N, n_tail, n_opp, W, seg0, K;
+    int slot, race, agent, N, n_tail, n_opp, W, seg0, K, K_prop;
     float vx0, vy0, om0, inv_n_tail, w_game;
     uint32_t key0, key1, ctr2, ctr3;
 };
@@ -478,6 +481,7 @@ __device__ void stage_block(const LaunchArgs &A, int item_idx, BlockState &bs, c
     bs.N = R.N;
     bs.n_tail = R.n_tail;
     bs.K = R.K;
+    bs.K_prop = R.prop ? R.K_prop : 0;
     bs.n_opp = R.n_agents - 1;
     bs.W = me.win_n;
     bs.seg0 = me.seg_loc;
@@ -498,6 +502,11 @@ __device__ void stage_block(const LaunchArgs &A, int item_idx, BlockState &bs, c
     float4 *nodes = (float4 *)(lds + L.nodes);
     const float2 *un = (const float2 *)(R.u_nom) + (size_t)it.agent * R.N;
     for (int t = tid; t < R.N; t += nth) ubar[t] = un[t];
+    if (R.prop) {
+        float4 *pq = (float4 *)(lds + L.prop);
+        const float4 *src = R.prop + (size_t)it.agent * R.N;
+        for (int t = tid; t < R.N; t += nth) pq[t] = src[t];
+    }
     const float4 *xr = A.xref + (size_t)it.slot * L.N_max;
     for (int t = tid; t < R.N; t += nth) xref[t] = xr[t];
     const float4 *wn = A.win + (size_t)it.slot * WIN_MAX * 2;
@@ -554,6 +563,16 @@ __device__ void stage_block(const LaunchArgs &A, int item_idx, BlockState &bs, c
 __device__ __forceinline__ float2 controls(const KParams &P, float2 ub, float za, float zd) {
     return make_float2(clip_keep_nan(__builtin_fmaf(P.sigma_a, za, ub.x), P.a_min, P.a_max),
                        clip_keep_nan(__builtin_fmaf(P.sigma_d, zd, ub.y), P.d_min, P.d_max));
+}
+// sample k < K_prop of a vehicle with a learned proposal: mean and scale from the proposal table
+__device__ __forceinline__ float2 controls_k(const KParams &P, const BlockState &bs, const char *lds,
+                                            const LdsLayout &L, uint32_t k, int tau, float2 ub, float za, float zd) {
+    if ((int)k < bs.K_prop) {
+        const float4 q = ((const float4 *)(lds + L.prop))[tau];
+        return make_float2(clip_keep_nan(__builtin_fmaf(q.z, za, q.x), P.a_min, P.a_max),
+                           clip_keep_nan(__builtin_fmaf(q.w, zd, q.y), P.d_min, P.d_max));
+    }
+    return controls(P, ub, za, zd);
 }
 
 // tracking term of eq. (ctrack) at one step; heading error wrapped to [-pi, pi]
@@ -683,7 +702,7 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P, const Bloc
             noise_out[2 * tau] = z.x;
             noise_out[2 * tau + 1] = z.y;
         }
-        const float2 u = controls(P, ubar[tau], z.x, z.y);
+        const float2 u = controls_k(P, bs, lds, L, k, tau, ubar[tau], z.x, z.y);
         const StepConst<float> sc = step_const<MODEL, MathF32>(V, u.x, u.y);
         rk4<MODEL, MathF32>(V, sc, P.dt, st);
         const Foot f = project(nodes, bs.W, P.max_moves, st[0], st[1], seg);
@@ -762,8 +781,13 @@ __device__ SampleResult reroll_block(const KParams &P, const LdsLayout &L, const
             z0 = gauss_pair(r.x, r.y);
             z1 = gauss_pair(r.z, r.w);
         }
-        wu[2 * m] = controls(P, ubar[2 * m], z0.x, z0.y);
-        if (2 * m + 1 < N) wu[2 * m + 1] = controls(P, ubar[2 * m + 1], z1.x, z1.y);
+        if (MODE == NOMINAL) {
+            wu[2 * m] = controls(P, ubar[2 * m], z0.x, z0.y);
+            if (2 * m + 1 < N) wu[2 * m + 1] = controls(P, ubar[2 * m + 1], z1.x, z1.y);
+        } else {
+            wu[2 * m] = controls_k(P, bs, lds, L, k, 2 * m, ubar[2 * m], z0.x, z0.y);
+            if (2 * m + 1 < N) wu[2 * m + 1] = controls_k(P, bs, lds, L, k, 2 * m + 1, ubar[2 * m + 1], z1.x, z1.y);
+        }
     }
     __syncthreads();
     // B. dynamics and projection, serial over the horizon; with the sample's checkpoints
@@ -1067,7 +1091,7 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
         node(i, nd);
         return (px - nd[0]) * nd[4] - (py - nd[1]) * nd[3];
     };
-    auto foot = [&](long long i, double *o /* s, d, t */) {
+    auto foot = [&](long long i, double *o /* s, d, t, half width, psi_ref, v_ref */) {
         double a[NODE_STRIDE], b[NODE_STRIDE];
         node(i, a);
         node(i + 1, b);
@@ -1088,6 +1112,9 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
         o[0] = a[8] + t * (b[8] - a[8]);
         o[1] = ((px - cx) * nx + (py - cy) * ny) / sqrt(nx * nx + ny * ny);
         o[2] = t;
+        o[3] = 0.5 * ((a[5] + t * (b[5] - a[5])) + (a[6] + t * (b[6] - a[6])));
+        o[4] = a[2] + t * (b[2] - a[2]);
+        o[5] = a[7] + t * (b[7] - a[7]);
     };
     auto block_argmin = [&](double v, long long i) {  // smallest v, lowest index on ties (i < 0: none)
         red_v[tid] = v;
@@ -1114,7 +1141,7 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
     long long bi = -1;
     for (long long i = tid; i < nseg; i += BLOCK) {
         if (ahead(i) >= 0.0 && ahead(i + 1) <= 0.0) {
-            double o[3];
+            double o[6];
             foot(i, o);
             const double ad = fabs(o[1]);
             if (ad < best) {
@@ -1141,7 +1168,7 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
 
     // 2. unwrapped progress, frame and window extent
     if (tid == 0) {
-        double o[3];
+        double o[6];
         foot(seg, o);
         double s = o[0];
         const double sp = R.s_abs[it.agent];
@@ -1170,6 +1197,7 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
         AgentRec rec;
         rec.ox = px; rec.oy = py; rec.psi0 = psi0; rec.c0 = c0; rec.s0 = s0;
         rec.s_abs = s; rec.d0 = o[1];
+        rec.half_w = o[3]; rec.psi_ref = o[4]; rec.v_ref = o[5];
         rec.seg_abs = seg; rec.win0 = win0;
         rec.win_n = (int)W; rec.seg_loc = (int)(seg - win0);
         rec.vx = (float)xs[3]; rec.vy = (float)xs[4]; rec.om = (float)xs[5];
@@ -1272,6 +1300,111 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
     RerollOut out{};
     out.pred = A.pred_out + (size_t)it.slot * (A.L.N_max + 1) * PRED_STRIDE;
     reroll_block<MODEL, 1, 1, NOMINAL>(A.P, A.L, bs, lds, rec, 0u, out);
+}
+
+// ------------------------------------------------------------------------------
+// Learned proposal: features of every vehicle and the proposal tables from the
+// network outputs (the network itself is in mlp.hip)
+// ------------------------------------------------------------------------------
+constexpr int FEAT_DIM = 50;
+constexpr int FEAT_OPP = 4;
+constexpr int FEAT_CURV = 20;
+constexpr double FEAT_CURV_DS = 5.0;
+constexpr float MLP_A_SCALE = 4.0f, MLP_D_SCALE = 0.2f, MLP_LS_MIN = -4.0f, MLP_LS_MAX = 1.0f;
+
+__device__ void node_row(const TrackDev &T, long long i, double *o) {  // unwrapped node access
+    const long long n = T.n;
+    long long lap = 0, b = i;
+    if (T.closed) {
+        lap = i / n;
+        if (i - lap * n < 0) --lap;
+        b = i - lap * n;
+    } else {
+        b = i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+    }
+    const double *r = T.nodes + (size_t)b * NODE_STRIDE;
+#pragma unroll
+    for (int c = 0; c < NODE_STRIDE; ++c) o[c] = r[c];
+    o[2] += (double)lap * T.psi_lap;
+    o[8] += (double)lap * T.length;
+}
+
+// One thread per vehicle: ego (6), 4 nearest opponents by |s_j - s_i| (6 each, zero when
+// absent), curvature 5..100 m ahead (20); same definitions as the oracle's features.
+__global__ void k_features(LaunchArgs A, float *X) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n_items) return;
+    const ItemDev it = A.items[i];
+    const RaceDev R = A.races[it.race];
+    const AgentRec me = A.agents[it.slot];
+    const TrackDev T = A.tracks[R.track];
+    const double *xi = R.x + (size_t)it.agent * 6;
+    float *f = X + (size_t)it.slot * FEAT_DIM;
+    for (int c = 0; c < FEAT_DIM; ++c) f[c] = 0.0f;
+    f[0] = (float)(me.d0 / me.half_w);
+    f[1] = (float)remainder(xi[2] - me.psi_ref, 6.283185307179586);
+    f[2] = (float)(xi[3] / 30.0);
+    f[3] = (float)(xi[4] / 5.0);
+    f[4] = (float)xi[5];
+    f[5] = (float)((xi[3] - me.v_ref) / 10.0);
+    unsigned used = 0;
+    for (int m = 0; m < FEAT_OPP; ++m) {
+        int best = -1;
+        double bd = INFINITY;
+        for (int j = 0; j < R.n_agents; ++j) {
+            if (j == it.agent || (used >> j) & 1u) continue;
+            const double dd = fabs(A.agents[R.slot0 + j].s_abs - me.s_abs);
+            if (dd < bd) {
+                bd = dd;
+                best = j;
+            }
+        }
+        if (best < 0) break;
+        used |= 1u << best;
+        const AgentRec o = A.agents[R.slot0 + best];
+        const double *xj = R.x + (size_t)best * 6;
+        float *g = f + 6 + 6 * m;
+        g[0] = (float)((o.s_abs - me.s_abs) / 20.0);
+        g[1] = (float)((o.d0 - me.d0) / me.half_w);
+        g[2] = (float)remainder(xj[2] - xi[2], 6.283185307179586);
+        g[3] = (float)((xj[3] - xi[3]) / 10.0);
+        g[4] = (float)(xj[4] / 5.0);
+        g[5] = 1.0f;
+    }
+    long long h = me.seg_abs;
+    for (int m = 1; m <= FEAT_CURV; ++m) {
+        const double sq = me.s_abs + FEAT_CURV_DS * m;
+        double a[NODE_STRIDE], b[NODE_STRIDE];
+        for (int guard = 0; guard < 1 << 20; ++guard) {
+            node_row(T, h, a);
+            node_row(T, h + 1, b);
+            if (sq < a[8] && (T.closed || h > 0)) { --h; continue; }
+            if (sq >= b[8] && (T.closed || h + 1 <= T.n - 2)) { ++h; continue; }
+            break;
+        }
+        double t = (sq - a[8]) / (b[8] - a[8]);
+        t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+        f[6 + 6 * FEAT_OPP + m - 1] = (float)(20.0 * (a[9] + t * (b[9] - a[9])));
+    }
+}
+
+// Network outputs (rows = vehicles in slot order, ld floats each, 4 per horizon step)
+// -> proposal table of every race: mu = scale o (plus the nominal control when
+// residual), sigma = sigma_plain exp(clamp(o)).
+__global__ void k_proposal(const RaceDev *races, const ItemDev *items, int n_items, const float *out, int ld,
+                           float sig_a, float sig_d, int residual) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = e / SGTP_MAX_N, tau = e % SGTP_MAX_N;
+    if (i >= n_items) return;
+    const ItemDev it = items[i];
+    const RaceDev R = races[it.race];
+    if (tau >= R.N || !R.prop) return;
+    const float *o = out + (size_t)it.slot * ld + 4 * tau;
+    const float o2 = fminf(fmaxf(o[2], MLP_LS_MIN), MLP_LS_MAX), o3 = fminf(fmaxf(o[3], MLP_LS_MIN), MLP_LS_MAX);
+    float4 *dst = (float4 *)R.prop + (size_t)it.agent * R.N + tau;
+    float2 base = make_float2(0.0f, 0.0f);
+    if (residual) base = ((const float2 *)R.u_nom)[(size_t)it.agent * R.N + tau];
+    *dst = make_float4(base.x + MLP_A_SCALE * o[0], base.y + MLP_D_SCALE * o[1], sig_a * expf(o2), sig_d * expf(o3));
 }
 
 // Advance the Philox counter word of every race (planning-step index).
@@ -1443,6 +1576,8 @@ int build_plan(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_
         d.n_agents = s.n_agents; d.ego = s.ego; d.N = s.N; d.n_tail = s.n_tail; d.track = s.track_id;
         d.slot0 = slot; d.K = s.K; d.seed = s.seed; d.plan_step = s.plan_step;
         d.x = s.x; d.s_abs = s.s_abs; d.v_scale = s.v_scale; d.u_nom = s.u_nom; d.traj = s.traj;
+        d.prop = (const float4 *)s.prop;
+        d.K_prop = s.prop ? std::min(std::max(s.K_prop, 0), s.K) : 0;
         pl.races.push_back(d);
         const int tiles = (s.K + BLOCK * spl - 1) / (BLOCK * spl);
         const long long groups = (s.K + 63) / 64;
@@ -1496,6 +1631,7 @@ LdsLayout make_layout(const Plan &pl, int maxopp, int ndisc) {
     L.oppc = take(L.n_opp_max * 16);
     L.opp = take(pl.N_max * L.n_opp_max * (ndisc + 1) * 8);
     L.nodes = take(pl.w_max * 32);
+    L.prop = take(pl.N_max * 16);
     L.rr_u = take(pl.N_max * 8);
     L.rr_st = take(pl.N_max * 32);
     L.rr_f = take(pl.N_max * 16);
@@ -1720,6 +1856,9 @@ struct sgtp_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool capturing = false;
+    sgtp_mlp *mlp = nullptr;  // learned proposal computed inside the step, or NULL
+    int residual = 0;
+    float *d_feat = nullptr, *d_mlp_out = nullptr;  // [vehicles][50], [vehicles][200]
 };
 
 namespace {
@@ -1739,6 +1878,16 @@ int plan_enqueue(sgtp_plan *P, hipStream_t st) {
         hipLaunchKernelGGL(k_setup<1>, dim3(a.n_items), dim3(BLOCK), a.L.total, st, a, P->pl.w_max);
     HIPCHK(c, hipGetLastError());
     const int nt = P->pl.agents_total;
+    if (P->mlp) {  // learned proposal: features -> network -> tables, before the first sweep
+        hipLaunchKernelGGL(k_features, dim3((a.n_items + 63) / 64), dim3(64), 0, st, a, P->d_feat);
+        HIPCHK(c, hipGetLastError());
+        const int mrc = sgtp_mlp_forward(P->mlp, P->d_feat, nt, P->d_mlp_out, SGTP_MLP_OUT, st);
+        if (mrc) return fail(c, mrc, std::string("proposal network: ") + sgtp_mlp_last_error(P->mlp));
+        const int n = nt * SGTP_MAX_N;
+        hipLaunchKernelGGL(k_proposal, dim3((n + 255) / 256), dim3(256), 0, st, P->d_races, P->d_all, nt,
+                           P->d_mlp_out, SGTP_MLP_OUT, P->p.sigma_a, P->p.sigma_d, P->residual);
+        HIPCHK(c, hipGetLastError());
+    }
     for (int ph = 0; ph <= P->L + 1; ++ph) {
         const bool ego = ph == P->L + 1;
         LaunchArgs w = P->base;
@@ -1791,6 +1940,22 @@ int plan_enqueue(sgtp_plan *P, hipStream_t st) {
         HIPCHK(c, hipGetLastError());
     }
     return SGTP_OK;
+}
+
+// Capture one planning step into the plan's graph (on a private stream).
+bool capture_plan(sgtp_plan *P) {
+    hipStream_t cap = nullptr;
+    bool ok = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    P->capturing = true;
+    int erc = ok ? plan_enqueue(P, cap) : SGTP_EDEVICE;
+    P->capturing = false;
+    hipGraph_t g = nullptr;
+    if (ok) ok = hipStreamEndCapture(cap, &g) == hipSuccess;
+    ok = ok && erc == SGTP_OK && hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0) == hipSuccess;
+    P->graph = g;
+    if (cap) (void)hipStreamDestroy(cap);
+    return ok;
 }
 
 }  // namespace
@@ -2075,26 +2240,45 @@ int sgtp_plan_create(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, 
         P->grid_all = std::max(1, std::min(g, P->pl.tiles_all));
         P->grid_ego = std::max(1, std::min(g, P->pl.tiles_ego));
     }
-    if (o.use_graph) {
-        hipStream_t st = (hipStream_t)stream;
-        hipStream_t cap = nullptr;
-        ok = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess;
-        ok = ok && hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
-        P->capturing = true;
-        int erc = ok ? plan_enqueue(P, cap) : SGTP_EDEVICE;
-        P->capturing = false;
-        hipGraph_t g = nullptr;
-        if (ok) ok = hipStreamEndCapture(cap, &g) == hipSuccess;
-        ok = ok && erc == SGTP_OK && hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0) == hipSuccess;
-        P->graph = g;
-        if (cap) (void)hipStreamDestroy(cap);
-        (void)st;
-        if (!ok) {
-            sgtp_plan_destroy(P);
-            return fail(c, SGTP_EDEVICE, "graph capture of the planning step failed");
-        }
+    (void)stream;
+    if (o.use_graph && !capture_plan(P)) {
+        sgtp_plan_destroy(P);
+        return fail(c, SGTP_EDEVICE, "graph capture of the planning step failed");
     }
     *out = P;
+    return SGTP_OK;
+}
+
+int sgtp_plan_set_proposal(sgtp_plan *P, sgtp_mlp *m, int residual) {
+    if (!P) return SGTP_EINVAL;
+    sgtp_ctx *c = P->c;
+    if (m) {
+        bool any = false;
+        for (const RaceDev &r : P->pl.races)
+            if (r.prop) {
+                any = true;
+                if (4 * r.N > SGTP_MLP_OUT) return fail(c, SGTP_ESHAPE, "horizon longer than the network's output");
+            }
+        if (!any) return fail(c, SGTP_EINVAL, "no race of the plan has a proposal table");
+        if (sgtp_mlp_batch_max(m) < P->pl.agents_total)
+            return fail(c, SGTP_ESHAPE, "network batch smaller than the plan's vehicle count");
+    }
+    HIPCHK(c, hipDeviceSynchronize());
+    if (m && !P->d_feat) {
+        const size_t nt = (size_t)P->pl.agents_total;
+        if (hipMalloc((void **)&P->d_feat, nt * SGTP_FEAT_DIM * 4) != hipSuccess ||
+            hipMalloc((void **)&P->d_mlp_out, nt * SGTP_MLP_OUT * 4) != hipSuccess)
+            return fail(c, SGTP_ENOMEM, "proposal buffers");
+    }
+    P->mlp = m;
+    P->residual = residual ? 1 : 0;
+    if (P->opt.use_graph) {
+        if (P->exec) (void)hipGraphExecDestroy(P->exec);
+        if (P->graph) (void)hipGraphDestroy(P->graph);
+        P->exec = nullptr;
+        P->graph = nullptr;
+        if (!capture_plan(P)) return fail(c, SGTP_EDEVICE, "graph capture of the planning step failed");
+    }
     return SGTP_OK;
 }
 
@@ -2132,6 +2316,8 @@ int sgtp_plan_destroy(sgtp_plan *P) {
     if (P->exec) (void)hipGraphExecDestroy(P->exec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
     if (P->d_mem) (void)hipFree(P->d_mem);
+    if (P->d_feat) (void)hipFree(P->d_feat);
+    if (P->d_mlp_out) (void)hipFree(P->d_mlp_out);
     delete P;
     return SGTP_OK;
 }
@@ -2219,6 +2405,45 @@ int sgtp_autotune(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int
     best_o.use_graph = 1;
     *best = best_o;
     if (best_ms) *best_ms = best_t;
+    return SGTP_OK;
+}
+
+int sgtp_features(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_races, float *X, void *stream) {
+    if (!c) return SGTP_EINVAL;
+    if (!X) return fail(c, SGTP_EINVAL, "X is NULL");
+    Runner r{c, p, (hipStream_t)stream};
+    int rc = r.init(races, n_races);
+    if (rc) return rc;
+    rc = r.setup_all();
+    if (rc) return rc;
+    LaunchArgs a = r.A;
+    a.items = r.d_all;
+    a.n_items = (int)r.pl.all.size();
+    hipLaunchKernelGGL(k_features, dim3((a.n_items + 63) / 64), dim3(64), 0, r.st, a, X);
+    HIPCHK(c, hipGetLastError());
+    return SGTP_OK;
+}
+
+int sgtp_proposal_from_outputs(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_races,
+                               const float *out, int ld_out, int residual, void *stream) {
+    if (!c) return SGTP_EINVAL;
+    if (!out || ld_out < 4) return fail(c, SGTP_EINVAL, "bad network outputs");
+    int rc = check_params(c, p);
+    if (rc) return rc;
+    Plan pl;
+    rc = build_plan(c, p, races, n_races, 1, pl);
+    if (rc) return rc;
+    for (int r = 0; r < n_races; ++r)
+        if (races[r].prop && 4 * races[r].N > ld_out) return fail(c, SGTP_ESHAPE, "horizon longer than the outputs");
+    RaceDev *dr;
+    ItemDev *da, *de;
+    hipStream_t st = (hipStream_t)stream;
+    rc = upload_plan(c, pl, st, &dr, &da, &de);
+    if (rc) return rc;
+    const int n = pl.agents_total * SGTP_MAX_N;
+    hipLaunchKernelGGL(k_proposal, dim3((n + 255) / 256), dim3(256), 0, st, dr, da, pl.agents_total, out, ld_out,
+                       p->sigma_a, p->sigma_d, residual ? 1 : 0);
+    HIPCHK(c, hipGetLastError());
     return SGTP_OK;
 }
 

@@ -382,3 +382,16 @@ def batched_workload(n_races: int = 256, seed: int = 4242, K_override=None):
                                2000 + sp["race"]))
     params = default_params(50, 3)
     return tracks, races, specs, params
+
+
+def learned_races(n_races: int, seed0: int, N: int = 40, track_seed: int = 1000):
+    """Races for the learned proposal on the mid-scale track (1.2 km x 12 m, track seed
+    `track_seed`): race r has 2 + (r mod 4) vehicles queued 8 m apart from a random start
+    (starts seed0 + r, noise key seed0 + 50000 + r), staggered from 3 vehicles on, 3-disc
+    footprint.  Returns (track, races, params)."""
+    length, width = TRACK_FOR_N[40]
+    tr = make_fourier_track(length, width, track_seed)
+    races = [make_race(tr, 2 + (r % 4), N, 8.0, 2 + (r % 4) >= 3, seed0 + r, seed0 + 50000 + r)
+             for r in range(n_races)]
+    params = default_params(N, 3)
+    return tr, races, params

@@ -42,7 +42,7 @@ class Race(C.Structure):
         ("n_agents", C.c_int), ("ego", C.c_int), ("track_id", C.c_int), ("N", C.c_int), ("n_tail", C.c_int),
         ("K", C.c_int), ("seed", C.c_ulonglong), ("plan_step", C.c_uint),
         ("x", C.c_void_p), ("s_abs", C.c_void_p), ("v_scale", C.c_void_p), ("u_nom", C.c_void_p),
-        ("traj", C.c_void_p),
+        ("traj", C.c_void_p), ("prop", C.c_void_p), ("K_prop", C.c_int),
     ]
 
 
@@ -99,6 +99,22 @@ def load():
         lib.sgtp_plan_destroy.argtypes = [vp]
         lib.sgtp_autotune.argtypes = [vp, P(Params), P(Race), C.c_int, C.c_int, vp, P(PlanOptions),
                                       P(C.c_double), vp]
+        lib.sgtp_features.argtypes = [vp, P(Params), P(Race), C.c_int, vp, vp]
+        lib.sgtp_proposal_from_outputs.argtypes = [vp, P(Params), P(Race), C.c_int, vp, C.c_int, C.c_int, vp]
+        lib.sgtp_mlp_create.argtypes = [C.c_int, P(vp)]
+        lib.sgtp_mlp_destroy.argtypes = [vp]
+        lib.sgtp_mlp_last_error.argtypes = [vp]
+        lib.sgtp_mlp_last_error.restype = C.c_char_p
+        lib.sgtp_mlp_num_params.restype = C.c_int
+        lib.sgtp_mlp_batch_max.argtypes = [vp]
+        lib.sgtp_plan_set_proposal.argtypes = [vp, vp, C.c_int]
+        lib.sgtp_mlp_set_params.argtypes = [vp, vp]
+        lib.sgtp_mlp_get_params.argtypes = [vp, vp]
+        lib.sgtp_mlp_forward.argtypes = [vp, vp, C.c_int, vp, C.c_int, vp]
+        lib.sgtp_mlp_grad.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_float, C.c_float, vp, vp, vp]
+        lib.sgtp_mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+        lib.sgtp_gemm_bf16.argtypes = [vp, C.c_longlong, C.c_longlong, vp, C.c_longlong, C.c_longlong, C.c_int,
+                                       C.c_int, C.c_int, vp, vp, C.c_longlong, vp]
         _lib = lib
     return _lib
 
@@ -143,6 +159,8 @@ class RaceTensors:
     v_scale: "object"  # torch float32 [n]
     u_nom: "object"    # torch float32 [n, N, 2]
     traj: "object"     # torch float64 [n, N+1, 8] or None
+    prop: "object" = None  # torch float32 [n, N, 4] or None (learned proposal)
+    K_prop: int = 0
 
     def struct(self) -> Race:
         for name, t in (("x", self.x), ("s_abs", self.s_abs), ("v_scale", self.v_scale), ("u_nom", self.u_nom)):
@@ -154,6 +172,8 @@ class RaceTensors:
         r.x, r.s_abs, r.v_scale, r.u_nom = (self.x.data_ptr(), self.s_abs.data_ptr(), self.v_scale.data_ptr(),
                                             self.u_nom.data_ptr())
         r.traj = self.traj.data_ptr() if self.traj is not None else None
+        r.prop = self.prop.data_ptr() if self.prop is not None else None
+        r.K_prop = int(self.K_prop)
         return r
 
 
@@ -274,6 +294,22 @@ class Planner:
                                            C.byref(ms), _stream()), "sgtp_autotune")
         return best, ms.value
 
+    def features(self, params: dict, races):
+        import torch
+        arr = (Race * len(races))(*[r.struct() for r in races])
+        nt = sum(r.n_agents for r in races)
+        X = torch.zeros((nt, 50), dtype=torch.float32, device=races[0].x.device)
+        P = make_params(params)
+        self._check(self.lib.sgtp_features(self.ctx, C.byref(P), arr, len(races), _ptr(X), _stream()), "sgtp_features")
+        return X
+
+    def proposal_from_outputs(self, params: dict, races, out, residual: bool = False):
+        arr = (Race * len(races))(*[r.struct() for r in races])
+        P = make_params(params)
+        self._check(self.lib.sgtp_proposal_from_outputs(self.ctx, C.byref(P), arr, len(races), _ptr(out),
+                                                        out.stride(0), 1 if residual else 0, _stream()),
+                    "sgtp_proposal_from_outputs")
+
     def set_timing(self, on: bool):
         self._check(self.lib.sgtp_set_timing(self.ctx, 1 if on else 0), "sgtp_set_timing")
 
@@ -320,6 +356,12 @@ class Plan:
     def set_step(self, step: int):
         self.planner._check(self.lib.sgtp_plan_set_step(self.handle, step), "sgtp_plan_set_step")
 
+    def set_proposal(self, mlp, residual: bool = False):
+        """Compute the proposal tables inside every planning step with `mlp` (None detaches)."""
+        self.mlp = mlp  # the network must outlive its use by the plan
+        self.planner._check(self.lib.sgtp_plan_set_proposal(self.handle, mlp.h if mlp is not None else None,
+                                                            1 if residual else 0), "sgtp_plan_set_proposal")
+
     def info(self):
         g, t, l = C.c_int(), C.c_int(), C.c_int()
         self.planner._check(self.lib.sgtp_plan_info(self.handle, C.byref(g), C.byref(t), C.byref(l)), "sgtp_plan_info")
@@ -339,3 +381,111 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+MLP_SHAPES = (("W1", (50, 256)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)), ("W3", (256, 200)),
+              ("b3", (200,)))
+
+
+def mlp_init(seed: int = 0) -> np.ndarray:
+    """Packed float32 parameters, He-style normal weights with fan-in scaling, zero biases
+    (last layer scaled down so the initial proposal sits near mean 0, plain scales)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shp in MLP_SHAPES:
+        if name.startswith("W"):
+            w = rng.standard_normal(shp) * np.sqrt(2.0 / shp[0])
+            if name == "W3":
+                w *= 0.1
+            parts.append(w.ravel())
+        else:
+            parts.append(np.zeros(shp).ravel())
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_unpack(flat) -> dict:
+    """Split packed parameters into named arrays (views)."""
+    out, o = {}, 0
+    for name, shp in MLP_SHAPES:
+        n = int(np.prod(shp))
+        out[name] = flat[o:o + n].reshape(shp)
+        o += n
+    return out
+
+
+class Mlp:
+    """The proposal network on the current device (see sgtp_mlp_*)."""
+
+    def __init__(self, B_max: int, params=None, seed: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the proposal network needs a GPU")
+        torch.cuda.init()
+        self.lib = load()
+        self.h = C.c_void_p()
+        rc = self.lib.sgtp_mlp_create(B_max, C.byref(self.h))
+        if rc != 0:
+            raise RuntimeError(f"sgtp_mlp_create failed: {ERRORS.get(rc, rc)}")
+        self.B_max = B_max
+        self.n_params = self.lib.sgtp_mlp_num_params()
+        self.set_params(mlp_init(seed) if params is None else params)
+
+    def _check(self, rc, what):
+        if rc != 0:
+            raise RuntimeError(f"{what} failed ({ERRORS.get(rc, rc)}): {self.lib.sgtp_mlp_last_error(self.h).decode()}")
+
+    def set_params(self, flat):
+        flat = np.ascontiguousarray(flat, np.float32)
+        assert flat.size == self.n_params
+        self._check(self.lib.sgtp_mlp_set_params(self.h, flat.ctypes.data), "sgtp_mlp_set_params")
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.n_params, np.float32)
+        self._check(self.lib.sgtp_mlp_get_params(self.h, out.ctypes.data), "sgtp_mlp_get_params")
+        return out
+
+    def forward(self, X, out=None):
+        import torch
+        X = X.contiguous()
+        if out is None:
+            out = torch.empty((X.shape[0], 200), dtype=torch.float32, device=X.device)
+        self._check(self.lib.sgtp_mlp_forward(self.h, _ptr(X), X.shape[0], _ptr(out), out.shape[1], _stream()),
+                    "sgtp_mlp_forward")
+        return out
+
+    def grad(self, X, U, sig_a, sig_d, want_grads=False):
+        """(loss tensor [1], gradient tensor or None) for targets U[B][N][2]."""
+        import torch
+        X, U = X.contiguous(), U.contiguous()
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        g = torch.empty(self.n_params, dtype=torch.float32, device=X.device) if want_grads else None
+        self._check(self.lib.sgtp_mlp_grad(self.h, _ptr(X), _ptr(U), X.shape[0], U.shape[1], float(sig_a),
+                                           float(sig_d), _ptr(loss), _ptr(g), _stream()), "sgtp_mlp_grad")
+        return loss, g
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(self.lib.sgtp_mlp_adam(self.h, lr, beta1, beta2, eps, _stream()), "sgtp_mlp_adam")
+
+    def close(self):
+        if self.h:
+            self.lib.sgtp_mlp_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gemm_bf16(A, a_strides, B, b_strides, M, N, K, bias=None, out=None):
+    """C = A B (+ bias) on the network's BF16 matrix-core product (operands are bf16 tensors)."""
+    import torch
+    lib = load()
+    if out is None:
+        out = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    rc = lib.sgtp_gemm_bf16(_ptr(A), a_strides[0], a_strides[1], _ptr(B), b_strides[0], b_strides[1], M, N, K,
+                            _ptr(bias), _ptr(out), out.stride(0), _stream())
+    if rc != 0:
+        raise RuntimeError(f"sgtp_gemm_bf16 failed ({ERRORS.get(rc, rc)})")
+    return out

@@ -1,0 +1,318 @@
+"""GPU checks of the learned proposal: the BF16 matrix-core product, the network's
+forward / loss / gradients / Adam step against the float64 oracle, the features, the
+proposal tables and the planner's sampler with a proposal."""
+
+import copy
+
+import numpy as np
+import pytest
+
+import parity as PY
+from oracle.ref import MlpOracle, features as oracle_features
+from paper_2607_25388_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def planner():
+    import paper_2607_25388_amd.sgtp as sg
+    p = sg.Planner(max_agents_total=64, max_races=4)
+    yield p
+    p.close()
+
+
+def _bf16_round(a):
+    """Round float32 values to bfloat16 (nearest even) and back, on the CPU."""
+    import torch
+    return torch.as_tensor(np.asarray(a, np.float32)).to(torch.bfloat16).to(torch.float32).numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("M,N,K,ta,tb", [(100, 90, 70, False, False), (64, 64, 32, True, False),
+                                         (257, 130, 300, False, True), (50, 256, 513, True, True)])
+def test_gemm_bf16_matches_float64_product(M, N, K, ta, tb):
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    rng = np.random.default_rng(M + N + K)
+    A = rng.standard_normal((M, K)).astype(np.float32)
+    B = rng.standard_normal((K, N)).astype(np.float32)
+    bias = rng.standard_normal(N).astype(np.float32)
+    # device storage either as given or transposed; strides describe the logical operand
+    Ad = torch.as_tensor(A.T.copy() if ta else A).to(torch.bfloat16).cuda()
+    Bd = torch.as_tensor(B.T.copy() if tb else B).to(torch.bfloat16).cuda()
+    a_str = (1, M) if ta else (K, 1)
+    b_str = (1, K) if tb else (N, 1)
+    C = sg.gemm_bf16(Ad, a_str, Bd, b_str, M, N, K, bias=torch.as_tensor(bias).cuda())
+    torch.cuda.synchronize()
+    ref = _bf16_round(A) @ _bf16_round(B) + bias.astype(np.float64)
+    err = np.abs(C.cpu().numpy() - ref).max()
+    # float32 accumulation of K exact bf16 x bf16 products
+    assert err <= 1e-5 * np.sqrt(K) * np.abs(ref).max() + 1e-5, err
+
+
+def _net(seed=3, scale3=1.0):
+    import paper_2607_25388_amd.sgtp as sg
+    flat = sg.mlp_init(seed)
+    P = sg.mlp_unpack(flat)
+    P["W3"][...] *= scale3
+    rng = np.random.default_rng(seed + 100)
+    for nm in ("b1", "b2", "b3"):
+        P[nm][...] = 0.1 * rng.standard_normal(P[nm].shape)
+    return flat, MlpOracle(*[P[n].astype(np.float64) for n in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def test_mlp_forward_matches_oracle():
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    flat, ref = _net(scale3=10.0)
+    B = 333
+    X = np.random.default_rng(5).standard_normal((B, 50)).astype(np.float32)
+    m = sg.Mlp(512, flat)
+    out = m.forward(torch.as_tensor(X).cuda())
+    torch.cuda.synchronize()
+    r = ref.forward(X.astype(np.float64))
+    g = out.cpu().numpy().astype(np.float64)
+    # BF16 operands (8-bit significands) with float32 accumulation
+    assert _rel(g, r) <= 2e-2, _rel(g, r)
+    assert np.abs(g - r).max() <= 5e-2 * np.abs(r).max()
+    m.close()
+
+
+@pytest.mark.parametrize("B,N", [(200, 50), (1500, 40), (64, 20)])
+def test_mlp_loss_and_gradients_match_oracle(B, N):
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    # outputs of moderate size: with much larger ones the loss is dominated by a few
+    # near-clamped log-scales and the gradient is ill-conditioned in any 8-bit-significand
+    # arithmetic, which a float64 comparison cannot separate from kernel mistakes
+    flat, ref = _net(seed=B, scale3=3.0)
+    rng = np.random.default_rng(B + N)
+    X = rng.standard_normal((B, 50)).astype(np.float32)
+    U = np.stack([rng.uniform(-8, 4, (B, N)), rng.uniform(-0.4, 0.4, (B, N))], axis=-1).astype(np.float32)
+    sig_a, sig_d = 1.5, 0.08
+    m = sg.Mlp(2048, flat)
+    loss, G = m.grad(torch.as_tensor(X).cuda(), torch.as_tensor(U).cuda(), sig_a, sig_d, want_grads=True)
+    torch.cuda.synchronize()
+    out = ref.forward(X.astype(np.float64))
+    # the oracle's network outputs for all 50 steps; its loss sees the first N of them
+    L, dout = ref.nll(out, U.astype(np.float64), sig_a, sig_d)
+    grads = ref.backward(X.astype(np.float64), dout)
+    assert abs(float(loss.item()) - L) <= 5e-3 * abs(L) + 1e-3, (loss.item(), L)
+    gp = sg.mlp_unpack(G.cpu().numpy())
+    for nm, gr in zip(("W1", "b1", "W2", "b2", "W3", "b3"), grads):
+        e = _rel(gp[nm].astype(np.float64), gr)
+        # BF16 operands (relative rounding 2^-9) at every product: a CPU emulation of that
+        # rounding against float64 gives at most 0.6 % on these inputs
+        assert e <= 2e-2, f"{nm}: relative gradient error {e}"
+    # steps beyond the horizon receive no gradient
+    if N < 50:
+        assert np.all(gp["b3"][4 * N:] == 0.0) and np.all(gp["W3"][:, 4 * N:] == 0.0)
+    m.close()
+
+
+def test_adam_first_step_and_training_reduces_loss():
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    flat, _ = _net(seed=7)
+    rng = np.random.default_rng(11)
+    B, N = 1024, 20
+    X = rng.standard_normal((B, 50)).astype(np.float32)
+    # a smooth target the network can fit: controls driven by two of the features
+    ua = np.clip(1.5 * X[:, :1] + 0.3 * np.arange(N)[None, :] / N, -8, 4)
+    ud = np.clip(0.1 * np.tanh(X[:, 1:2]) * np.ones((1, N)), -0.4, 0.4)
+    U = np.stack([ua, ud], axis=-1).astype(np.float32)
+    Xd, Ud = torch.as_tensor(X).cuda(), torch.as_tensor(U).cuda()
+    m = sg.Mlp(B, flat)
+    loss0, G = m.grad(Xd, Ud, 1.5, 0.08, want_grads=True)
+    lr, eps = 1e-3, 1e-8
+    m.adam(lr=lr, eps=eps)
+    p1 = m.get_params()
+    g = G.cpu().numpy().astype(np.float64)
+    # first bias-corrected Adam step: p - lr g / (|g| + eps)
+    exp1 = flat.astype(np.float64) - lr * g / (np.abs(g) + eps)
+    assert np.abs(p1 - exp1).max() <= 1e-6, np.abs(p1 - exp1).max()
+    losses = [float(loss0.item())]
+    for it in range(300):
+        loss, _ = m.grad(Xd, Ud, 1.5, 0.08)
+        m.adam(lr=lr)
+        if it % 50 == 49:
+            losses.append(float(loss.item()))
+    print(losses)
+    assert losses[-1] < losses[0] - 1.0, losses
+    m.close()
+
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_features_match_oracle(planner, name):
+    import torch
+    tr, race, params, K, w = PY.workload(name)
+    rt = PY.build(planner, tr, race, params, 256)
+    X = planner.features(params, [rt])
+    torch.cuda.synchronize()
+    g = X.cpu().numpy().astype(np.float64)
+    orc = PY.oracle_for(tr, params)
+    r = oracle_features(orc, race)
+    assert g.shape == r.shape
+    # presence columns of the opponent blocks exact (nearest-opponent order)
+    for mm in range(4):
+        assert np.array_equal(g[:, 6 + 6 * mm + 5], r[:, 6 + 6 * mm + 5])
+    err = np.abs(g - r).max(axis=0)
+    assert np.all(err <= 1e-3), f"feature errors {err}"
+
+
+@pytest.mark.parametrize("residual", [False, True])
+def test_proposal_tables_match_oracle(planner, residual):
+    import torch
+    tr, race, params, K, w = PY.workload("c2")
+    race = copy.deepcopy(race)
+    n, N = race.x.shape[0], params["N"]
+    rng = np.random.default_rng(2)
+    race.u_nom = np.stack([rng.uniform(-8, 4, (n, N)), rng.uniform(-0.4, 0.4, (n, N))], -1).astype(np.float32)
+    rt = PY.build(planner, tr, race, params, 256)
+    out = (2.5 * rng.standard_normal((n, 200))).astype(np.float32)
+    rt.prop = torch.zeros((n, N, 4), dtype=torch.float32, device="cuda")
+    planner.proposal_from_outputs(params, [rt], torch.as_tensor(out).cuda(), residual=residual)
+    torch.cuda.synchronize()
+    g = rt.prop.cpu().numpy().astype(np.float64)
+    ref = MlpOracle(np.zeros((50, 256)), np.zeros(256), np.zeros((256, 256)), np.zeros(256), np.zeros((256, 200)),
+                    np.zeros(200))
+    for i in range(n):
+        r = ref.proposal(out[i].astype(np.float64), N, float(np.float32(params["sigma_a"])),
+                         float(np.float32(params["sigma_d"])),
+                         ubar=race.u_nom[i].astype(np.float64) if residual else None)
+        assert np.allclose(g[i], r, rtol=2e-6, atol=2e-6), (i, np.abs(g[i] - r).max())
+
+
+def test_plain_proposal_table_reproduces_plain_sampler(planner):
+    """A proposal equal to (nominal, plain scales) gives bit-identical samples."""
+    import torch
+    tr, race, params, K, w = PY.workload("c2")
+    K = 4096
+    rt = PY.build(planner, tr, race, params, K)
+    base = PY.gpu_rollout(planner, params, rt, 1, 1, want_noise=False)
+    n, N = race.x.shape[0], params["N"]
+    prop = np.zeros((n, N, 4), np.float32)
+    prop[..., :2] = race.u_nom.astype(np.float32)
+    prop[..., 2] = np.float32(params["sigma_a"])
+    prop[..., 3] = np.float32(params["sigma_d"])
+    rt.prop = torch.as_tensor(prop).cuda()
+    rt.K_prop = K
+    withp = PY.gpu_rollout(planner, params, rt, 1, 1, want_noise=False)
+    for nm in ("cost", "flags", "viol", "x_final"):
+        assert np.array_equal(base[nm].view(np.uint8), withp[nm].view(np.uint8)), nm
+    assert int(base["choice"]["k"]) == int(withp["choice"]["k"])
+
+
+@pytest.mark.parametrize("name,agent,K,K_prop", [("c1", 0, 1024, 512), ("c2", 2, 2048, 2048), ("c3", 4, 1000, 250)])
+def test_rollout_with_proposal_matches_oracle(planner, name, agent, K, K_prop):
+    import torch
+    tr, race, params, _, w = PY.workload(name)
+    n, N = race.x.shape[0], params["N"]
+    rng = np.random.default_rng(K + agent)
+    prop = np.zeros((n, N, 4), np.float32)
+    prop[..., 0] = rng.uniform(-3.0, 2.0, (n, N))
+    prop[..., 1] = rng.uniform(-0.1, 0.1, (n, N))
+    prop[..., 2] = np.float32(params["sigma_a"]) * np.exp(rng.uniform(-2.0, 0.5, (n, N)))
+    prop[..., 3] = np.float32(params["sigma_d"]) * np.exp(rng.uniform(-2.0, 0.5, (n, N)))
+    prop = prop.astype(np.float32)
+    rt = PY.build(planner, tr, race, params, K)
+    rt.prop = torch.as_tensor(prop).cuda()
+    rt.K_prop = K_prop
+    g = PY.gpu_rollout(planner, params, rt, agent, 1, want_noise=True)
+    orc = PY.oracle_for(tr, params)
+    r = orc.rollout_cost(race, agent, 1, K, noise=True, prop=prop.astype(np.float64), K_prop=K_prop)
+    assert np.array_equal(g["noise"].view(np.uint32), r["noise"].view(np.uint32))
+    st = PY.compare_samples(g, r, params, tr.width, f"{name} proposal")
+    PY.check_choice(g["choice"], r, params, f"{name} proposal")
+    print(st)
+
+
+def _train_small(planner, N=50, n_races=48, steps=30, iters=1500):
+    import paper_2607_25388_amd.sgtp as sg
+    from paper_2607_25388_amd import learned
+    tr, races, params = inputs.learned_races(n_races, 5000, N=N)
+    planner.upload_track(0, tr)
+    rts = [sg.race_from_inputs(r, 0, 16384, N, params["n_tail"]) for r in races]
+    data = learned.collect(planner, params, rts, 5, steps, residual=False)
+    m = sg.Mlp(4096, seed=1)
+    losses = learned.train(m, data, params, iters, batch=2048, lr=1e-3, log_every=500)
+    return m, params, losses
+
+
+@pytest.fixture(scope="module")
+def big_planner():
+    import paper_2607_25388_amd.sgtp as sg
+    p = sg.Planner(max_agents_total=1024, max_races=128)
+    yield p
+    p.close()
+
+
+@pytest.fixture(scope="module")
+def trained(big_planner):
+    m, params, losses = _train_small(big_planner)
+    yield m, params, losses
+    m.close()
+
+
+def test_trained_proposal_beats_plain_sampler(big_planner, trained):
+    """Trained on the plain planner's own selections, the proposal with K/4 samples (half
+    from the proposal, half about the nominal) reaches at least the plain planner's
+    selected cost at full K on held-out races, and beats the plain planner at K/4."""
+    import paper_2607_25388_amd.sgtp as sg
+    from paper_2607_25388_amd import learned
+    m, params, losses = trained
+    assert losses[-1] < losses[0] - 50.0, losses
+    K, N = 16384, params["N"]
+    _, races, _ = inputs.learned_races(16, 7000, N=N)
+    rts = [sg.race_from_inputs(r, 0, K, N, params["n_tail"]) for r in races]
+    plan = big_planner.plan(params, rts, 5, sg.plan_options(include_advance=1), trace=False)
+    rec = {"K": [], "K4": [], "L4": []}
+    for step in range(24):
+        plan.run()
+        if step % 6 != 5:
+            continue
+        rec["K"].append(learned.best_response_costs(big_planner, params, rts, K))
+        rec["K4"].append(learned.best_response_costs(big_planner, params, rts, K // 4))
+        rec["L4"].append(learned.best_response_costs(big_planner, params, rts, K // 4, K // 8, m))
+    plan.close()
+    cat = {k: (np.concatenate([c for c, f in v]), np.concatenate([f for c, f in v])) for k, v in rec.items()}
+    g_plain4, s_plain4 = learned.cost_gap(*cat["K4"], *cat["K"])
+    g_learn4, s_learn4 = learned.cost_gap(*cat["L4"], *cat["K"])
+    print(f"cases {len(g_learn4)}: plain K/4 mean gap {g_plain4.mean():.4f} sum {s_plain4:.4f}; "
+          f"learned K/4 mean gap {g_learn4.mean():.4f} sum {s_learn4:.4f}")
+    assert len(g_learn4) >= 0.9 * len(cat["K"][0])
+    assert g_learn4.mean() <= 0.01 and s_learn4 <= 0.01
+    assert s_learn4 < s_plain4 and g_learn4.mean() < g_plain4.mean()
+
+
+def test_proposal_inside_plan_matches_separate_calls(big_planner, trained):
+    """A plan that computes the proposal itself (graph) selects exactly what an eager plan
+    selects after the features / network / table calls made one by one."""
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    from paper_2607_25388_amd import learned
+    m, params, _ = trained
+    K, N = 4096, params["N"]
+    _, races, _ = inputs.learned_races(6, 8000, N=N)
+    A = [sg.race_from_inputs(r, 0, K, N, params["n_tail"]) for r in races]
+    B = [sg.race_from_inputs(r, 0, K, N, params["n_tail"]) for r in races]
+    learned.ensure_tables(A, K // 2)
+    learned.ensure_tables(B, K // 2)
+    pa = big_planner.plan(params, A, 3, sg.plan_options(include_advance=1, use_graph=1), trace=True)
+    pa.set_proposal(m)
+    pb = big_planner.plan(params, B, 3, sg.plan_options(include_advance=1, use_graph=0), trace=True)
+    for step in range(3):
+        pa.run()
+        learned.attach(big_planner, params, B, m)
+        pb.run()
+        torch.cuda.synchronize()
+        assert np.array_equal(pa.choices()["k"], pb.choices()["k"]), step
+        for ra, rb in zip(A, B):
+            assert torch.equal(ra.prop, rb.prop)
+            assert torch.equal(ra.x, rb.x) and torch.equal(ra.u_nom, rb.u_nom)
+    pa.close()
+    pb.close()

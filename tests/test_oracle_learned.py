@@ -38,6 +38,14 @@ def test_nll_closed_form_and_sigma_identity(oracle_lib):
     assert L == pytest.approx(exp_L, rel=1e-14)
     prop = m.proposal(out[0], 2, 1.5, 0.08)
     np.testing.assert_allclose(prop, [[0, 0, 1.5, 0.08], [0, 0, 1.5, 0.08]], rtol=1e-15)
+    # residual form: zero outputs give the nominal sequence with the plain scales
+    ubar = np.array([[0.5, -0.1], [-1.0, 0.2]])
+    prop = m.proposal(out[0], 2, 1.5, 0.08, ubar=ubar)
+    np.testing.assert_allclose(prop, [[0.5, -0.1, 1.5, 0.08], [-1.0, 0.2, 1.5, 0.08]], rtol=1e-15)
+    # clamps of the log-scale offsets and the mean scales
+    o = np.array([1.0, 1.0, -10.0, 10.0])
+    prop = m.proposal(o, 1, 1.5, 0.08, ubar=np.array([[0.5, -0.1]]))
+    np.testing.assert_allclose(prop, [[4.5, 0.1, 1.5 * math.exp(-4.0), 0.08 * math.e]], rtol=1e-15)
 
 
 def test_backprop_matches_central_differences(oracle_lib):
