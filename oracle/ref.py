@@ -45,7 +45,11 @@ class Params(C.Structure):
         ("m", C.c_double), ("Iz", C.c_double), ("lf", C.c_double), ("lr", C.c_double),
         ("B", C.c_double), ("C", C.c_double), ("mu", C.c_double), ("g", C.c_double), ("v_eps", C.c_double),
         ("max_moves", C.c_int), ("pad0", C.c_int),
+        ("update", C.c_int), ("pad1", C.c_int), ("mppi_lambda", C.c_double), ("mppi_w_viol", C.c_double),
     ]
+
+# parameters with a default (the path-integral ablation is off unless asked for)
+PARAM_DEFAULTS = {"update": 0, "mppi_lambda": 1.0, "mppi_w_viol": 0.0}
 
 
 class TrackS(C.Structure):
@@ -146,7 +150,7 @@ def make_params(d: dict) -> Params:
     for name, typ in Params._fields_:
         if name.startswith("pad"):
             continue
-        v = d[name]
+        v = d[name] if name in d else PARAM_DEFAULTS[name]
         if name in ("Q", "R", "S", "disc_off"):
             arr = getattr(p, name)
             for i, x in enumerate(v):

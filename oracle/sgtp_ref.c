@@ -68,6 +68,11 @@ typedef struct {
     double disc_off[4];
     double m, Iz, lf, lr, B, C, mu, g, v_eps;
     int max_moves, pad0;
+    /* best-response update: 0 = feasibility selection (Sec. III-B); 1 = path-integral
+     * update of the nominal (the paper's GA-IBR-MPPI ablation, Sec. IV-A) with
+     * temperature mppi_lambda on the score c + mppi_w_viol * nu */
+    int update, pad1;
+    double mppi_lambda, mppi_w_viol;
 } ref_params;
 
 typedef struct {
@@ -698,6 +703,54 @@ static void select_sample(int K, const double *cost, const double *viol, const i
     ch->viol = viol[kv];
 }
 
+/* Path-integral update (the GA-IBR-MPPI ablation of Sec. IV-A; the weighting is the
+ * standard MPPI one, the paper gives no temperature): every sample with a finite
+ * score S_k = c_k + w_viol nu_k gets the weight exp(-(S_k - S_min) / lambda); the
+ * new nominal is the weighted mean of the sampled (clipped) control sequences.  No
+ * feasibility selection: constraints enter only through the soft terms of S.  The
+ * record holds the lowest-score sample k, S_min as cost, and the number of feasible
+ * samples; with no finite score the nominal is kept (fallback = 1). */
+static void path_integral(const ref_params *p, int K, int N, const double *cost, const double *viol,
+                          const int *flags, const double *Uall, const double *ubar, ref_choice *ch, double *U_out)
+{
+    int kmin = -1, nfeas = 0;
+    double Smin = INFINITY;
+    for (int k = 0; k < K; ++k) {
+        if (flags[k] & F_H) ++nfeas;
+        const double S = cost[k] + p->mppi_w_viol * viol[k];
+        if (isfinite(S) && S < Smin) {
+            Smin = S;
+            kmin = k;
+        }
+    }
+    ch->n_feasible = nfeas;
+    ch->cost2 = INFINITY;
+    ch->fallback = kmin < 0;
+    ch->k = kmin < 0 ? 0 : kmin;
+    ch->cost = kmin < 0 ? INFINITY : Smin;
+    ch->viol = 0.0;
+    ch->k_used = ch->k;
+    ch->cost_used = ch->cost;
+    ch->scale_used = 0.0;
+    ch->viol_used = 0.0;
+    ch->flags_used = kmin < 0 ? 0 : flags[kmin];
+    if (!U_out) return;
+    if (kmin < 0) {
+        memcpy(U_out, ubar, sizeof(double) * 2 * N);
+        return;
+    }
+    double wsum = 0.0;
+    for (int t = 0; t < 2 * N; ++t) U_out[t] = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const double S = cost[k] + p->mppi_w_viol * viol[k];
+        if (!isfinite(S)) continue;
+        const double w = exp(-(S - Smin) / p->mppi_lambda);
+        wsum += w;
+        for (int t = 0; t < 2 * N; ++t) U_out[t] += w * Uall[(size_t)k * 2 * N + t];
+    }
+    for (int t = 0; t < 2 * N; ++t) U_out[t] /= wsum;
+}
+
 /* One best response: all K samples, optional per-sample outputs, selection.
  * `k_force` >= 0 adopts that sample instead of the selected one (lock-step
  * comparison with another implementation); U_out receives the adopted controls. */
@@ -710,8 +763,14 @@ int ref_best_response(const ref_track *T, const ref_params *p, const ref_br_in *
     double *viol = (double *)malloc(sizeof(double) * K);
     int *flags = (int *)malloc(sizeof(int) * K);
     double *scale = (double *)malloc(sizeof(double) * K);
-    if (!cost || !viol || !flags || !scale) {
+    const int pi_update = p->update == 1;
+    if (pi_update && !(p->mppi_lambda > 0.0)) {
         free(cost); free(viol); free(flags); free(scale);
+        return -1;
+    }
+    double *Uall = pi_update ? (double *)malloc(sizeof(double) * (size_t)K * 2 * N) : NULL;
+    if (!cost || !viol || !flags || !scale || (pi_update && !Uall)) {
+        free(cost); free(viol); free(flags); free(scale); free(Uall);
         return -2;
     }
 #pragma omp parallel for schedule(static)
@@ -722,6 +781,7 @@ int ref_best_response(const ref_track *T, const ref_params *p, const ref_br_in *
         viol[k] = r.viol;
         flags[k] = r.flags;
         scale[k] = r.scale;
+        if (Uall) memcpy(Uall + (size_t)k * 2 * N, r.U, sizeof(double) * 2 * N);
         if (out) {
             if (out->cost) out->cost[k] = r.cost;
             if (out->scale) out->scale[k] = r.scale;
@@ -734,6 +794,11 @@ int ref_best_response(const ref_track *T, const ref_params *p, const ref_br_in *
             if (out->flags) out->flags[k] = r.flags;
             if (out->x_final) memcpy(out->x_final + 6 * (size_t)k, r.x_final, sizeof r.x_final);
         }
+    }
+    if (pi_update) {
+        path_integral(p, K, N, cost, viol, flags, Uall, in->ubar, ch, U_out);
+        free(cost); free(viol); free(flags); free(scale); free(Uall);
+        return 0;
     }
     select_sample(K, cost, viol, flags, ch);
     int ku = (k_force >= 0 && k_force < K) ? k_force : ch->k;

@@ -100,6 +100,9 @@ def default_params(N: int, n_disc: int = 3, model: int = 0) -> dict:
         # gravity, slip-angle speed floor
         m=1200.0, Iz=2000.0, lf=1.2, lr=1.4, B=7.0, C=1.6, mu=1.1, g=9.81, v_eps=3.0,
         max_moves=16,
+        # best-response update: 0 = feasibility selection; 1 = path-integral (MPPI) update of
+        # the GA-IBR-MPPI ablation, temperature and soft violation weight not given in the paper
+        update=0, mppi_lambda=10.0, mppi_w_viol=0.0,
     )
 
 
