@@ -75,6 +75,14 @@ typedef struct {
     float B, C, mu, g;         /* tyre F_y = mu F_z sin(C atan(B alpha)); gravity */
     float v_eps;               /* speed floor inside the slip angles [m/s] */
     int max_moves;             /* segment-search limit of the Frenet projection */
+    /* Best-response update.  0: feasibility selection (Sec. III-B).  1: path-integral
+     * update of the GA-IBR-MPPI ablation (Sec. IV-A): every sample with a finite score
+     * S = c + mppi_w_viol * nu is weighted by exp(-(S - S_min) / mppi_lambda) and the
+     * nominal becomes the weighted mean of the sampled sequences (no feasibility
+     * selection; needs sgtp_ctx_enable_path_integral; no learned proposal). */
+    int update;
+    float mppi_lambda;         /* temperature (> 0) */
+    float mppi_w_viol;         /* weight of the violation nu in the score (>= 0) */
 } sgtp_params;
 
 /* One race (one game) at one planning instant. */
@@ -116,6 +124,12 @@ int sgtp_ctx_create(sgtp_ctx **out, int max_agents_total, int max_N, int max_rac
                     int max_K);
 int sgtp_ctx_destroy(sgtp_ctx *ctx);
 const char *sgtp_last_error(const sgtp_ctx *ctx);
+/* Allocate the per-tile partial sums of the path-integral update (params.update = 1):
+ * (2 max_N + 2) floats per 256 samples of the context's capacity.  Synchronous; calls
+ * with update = 1 fail with SGTP_EINVAL before it.  A choice record of that update
+ * holds the lowest-score sample k, S_min as cost, viol = 0, and fallback = 1 when no
+ * score was finite (the nominal is then kept). */
+int sgtp_ctx_enable_path_integral(sgtp_ctx *ctx);
 
 /* Upload the raceline G (Sec. II) as a HOST table nodes[n_nodes][8] of
  * (x, y, psi, kappa, w_L, w_R, v_ref, s) at increasing arc length s, psi

@@ -128,7 +128,7 @@ def load(rebuild: bool = False):
         lib.ref_agent_setup.argtypes = [P(TrackS), P(Params), P(RaceS), P(C.c_double), P(C.c_double),
                                         P(C.c_long), P(C.c_double)]
         lib.ref_rollout_cost.argtypes = [P(TrackS), P(Params), P(RaceS), C.c_int, C.c_int, P(SampleOut),
-                                         P(Choice)]
+                                         P(Choice), P(C.c_double)]
         lib.ref_plan_step.argtypes = [P(TrackS), P(Params), P(RaceS), C.c_int, P(C.c_int), P(Choice),
                                       P(C.c_double), P(C.c_double), P(C.c_double), P(C.c_double)]
         lib.ref_advance.argtypes = [P(Params), C.c_int, P(C.c_double), P(C.c_double)]
@@ -302,8 +302,9 @@ class Oracle:
             out["noise"] = np.zeros((K, self.N, 2), np.float32)
             so.noise = out["noise"].ctypes.data_as(C.POINTER(C.c_float))
         ch = Choice()
+        out["U"] = np.zeros((self.N, 2))
         rc = self.lib.ref_rollout_cost(C.byref(self.T), C.byref(self.P), C.byref(R), int(agent), int(phase),
-                                       C.byref(so), C.byref(ch))
+                                       C.byref(so), C.byref(ch), _dp(out["U"]))
         if rc != 0:
             raise RuntimeError(f"ref_rollout_cost failed: {rc}")
         out["choice"] = _choice_dict(ch)

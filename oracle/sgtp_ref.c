@@ -890,9 +890,10 @@ int ref_agent_setup(const ref_track *T, const ref_params *p, const ref_race *R, 
 
 /* One best response of `agent` in `phase` at the planning instant R, with every
  * opponent predicted by the noise-free rollout of its nominal sequence (the
- * state at the start of any sweep of Alg. 1). */
+ * state at the start of any sweep of Alg. 1).  U_out [N][2] (or NULL) receives the
+ * adopted sequence: the selected sample's controls, or the path-integral mean. */
 int ref_rollout_cost(const ref_track *T, const ref_params *p, const ref_race *R, int agent, int phase,
-                     const ref_sample_out *out, ref_choice *ch)
+                     const ref_sample_out *out, ref_choice *ch, double *U_out)
 {
     const int n = R->n_agents, N = p->N;
     if (N > REF_MAX_N || n - 1 > REF_MAX_OPP || agent < 0 || agent >= n) return -1;
@@ -908,7 +909,7 @@ int ref_rollout_cost(const ref_track *T, const ref_params *p, const ref_race *R,
                              traj + (size_t)i * (N + 1) * 8);
     ref_br_in in;
     build_br_in(p, R, A, agent, phase, ubar, traj, opp, opp_s0, &in);
-    int rc = ref_best_response(T, p, &in, -1, out, ch, NULL);
+    int rc = ref_best_response(T, p, &in, -1, out, ch, U_out);
     free(A); free(ubar); free(traj); free(opp);
     return rc;
 }

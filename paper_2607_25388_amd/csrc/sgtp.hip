@@ -49,7 +49,7 @@ enum Mode { SWEEP = 0, WINNER = 1, NOMINAL = 2 };
 // Kernel-side parameters (float32 with derived constants folded in)
 // ------------------------------------------------------------------------------
 struct KParams {
-    int model, n_disc, max_moves, pad0;
+    int model, n_disc, max_moves, update;  // update: 0 selection, 1 path-integral
     float dt, half_dt, dt6;
     float a_min, a_max, d_min, d_max, sigma_a, sigma_d;
     float Q0, Q1, Q2, Q3, R0, R1, S0, S1;
@@ -58,6 +58,7 @@ struct KParams {
     float off[4];
     float lf, lr, inv_m, inv_Iz, muFzf, muFzr, B, C, v_eps, C_rev;  // dynamic single-track
     float lr_over_L, inv_lr;                                 // kinematic bicycle
+    float inv_lambda, w_viol;                                // path-integral update
 };
 
 struct TrackDev {
@@ -133,6 +134,7 @@ struct LaunchArgs {
     double *dbg_xfinal;
     float *dbg_noise;
     float *cp_slots;       // [group][CP_FLOATS] checkpoints of each wave's best sample
+    float *pi_part;        // [tile][2 N_max + 2] path-integral partial sums, or NULL
 };
 
 // ------------------------------------------------------------------------------
@@ -457,6 +459,28 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
         best = rv < best ? rv : best;
     }
     return best;
+}
+
+// Sum / minimum over the 64 lanes (every lane active), returned to every lane: DPP
+// butterflies inside each row of 16, then the four row results in a fixed order.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float rows_f32(float v, int r) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16 * r)); }
+__device__ __forceinline__ float wave_sum_f32(float v) {
+    v += dpp_f32<0xB1>(v);
+    v += dpp_f32<0x4E>(v);
+    v += dpp_f32<0x141>(v);
+    v += dpp_f32<0x140>(v);
+    return (rows_f32(v, 0) + rows_f32(v, 1)) + (rows_f32(v, 2) + rows_f32(v, 3));
+}
+__device__ __forceinline__ float wave_min_f32(float v) {
+    v = fminf(v, dpp_f32<0xB1>(v));
+    v = fminf(v, dpp_f32<0x4E>(v));
+    v = fminf(v, dpp_f32<0x141>(v));
+    v = fminf(v, dpp_f32<0x140>(v));
+    return fminf(fminf(rows_f32(v, 0), rows_f32(v, 1)), fminf(rows_f32(v, 2), rows_f32(v, 3)));
 }
 
 // ------------------------------------------------------------------------------
@@ -906,22 +930,79 @@ __device__ __forceinline__ int find_item(const ItemDev *items, int n, int tile) 
     return lo;
 }
 
+// Path-integral accumulation of one wave's samples (update = 1): score S = c + w_viol nu
+// (non-finite scores get no weight), weights exp(-(S - S_ref) / lambda) against the
+// wave's running reference S_ref, and the weighted sums of the sampled controls,
+// regenerated from the same Philox counters.  Lane l holds columns l and l + 64 of
+// (a_0, delta_0, a_1, delta_1, ...).
+struct PiAcc {
+    float S, w, c0, c1;
+};
+
+__device__ __forceinline__ void pi_accumulate(const KParams &P, const BlockState &bs, const char *lds,
+                                              const LdsLayout &L, uint32_t k, bool valid, const SampleResult &res,
+                                              PiAcc &a) {
+    const int lane = threadIdx.x & 63;
+    float S = res.cost + P.w_viol * res.viol;
+    const bool fin = valid && isfinite(S);
+    S = fin ? S : INFINITY;
+    const float Sw = wave_min_f32(S);
+    if (!(Sw < INFINITY)) return;  // uniform over the wave
+    const float w = fin ? expf((Sw - S) * P.inv_lambda) : 0.0f;
+    const float Sn = fminf(a.S, Sw);
+    const float fa = (a.S < INFINITY) ? expf((Sn - a.S) * P.inv_lambda) : 0.0f;
+    const float fb = expf((Sn - Sw) * P.inv_lambda);
+    a.S = Sn;
+    a.w = a.w * fa + wave_sum_f32(w) * fb;
+    a.c0 *= fa;
+    a.c1 *= fa;
+    const float2 *ubar = (const float2 *)(lds + L.ubar);
+    for (int m = 0; 2 * m < bs.N; ++m) {
+        const uint4 r = philox4x32_10(make_uint4(k, (uint32_t)m, bs.ctr2, bs.ctr3), bs.key0, bs.key1);
+        const float2 z0 = gauss_pair(r.x, r.y), z1 = gauss_pair(r.z, r.w);
+        const float2 u0 = controls(P, ubar[2 * m], z0.x, z0.y);
+        const float2 u1 = (2 * m + 1 < bs.N) ? controls(P, ubar[2 * m + 1], z1.x, z1.y) : make_float2(0.0f, 0.0f);
+        const float v[4] = {wave_sum_f32(w * u0.x) * fb, wave_sum_f32(w * u0.y) * fb, wave_sum_f32(w * u1.x) * fb,
+                            wave_sum_f32(w * u1.y) * fb};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = 4 * m + j;
+            if (lane == (c & 63)) {
+                if (c < 64) a.c0 += v[j];
+                else a.c1 += v[j];
+            }
+        }
+    }
+}
+
 // One tile (spl x BLOCK consecutive samples) of a staged vehicle, then the hand-off:
 // the workgroup that finishes the vehicle's last tile (device-scope counter) reads
-// the selection and re-rolls it with the tables it holds in LDS.
+// the selection and re-rolls it with the tables it holds in LDS.  With the
+// path-integral update every tile leaves its weighted partial sums instead, and the
+// last workgroup combines them in tile order, adopts the weighted mean sequence and
+// rolls it out noise-free.
 template <int MODEL, int NDISC, int MAXOPP>
 __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int item, const BlockState &bs, char *lds,
                                            int *s_last) {
     const int lane = threadIdx.x & 63;
+    const bool pi = A.P.update == 1;
     const int t0 = A.items[item].tile0;
     const int n_tiles_item = (item + 1 < A.n_items ? A.items[item + 1].tile0 : A.n_tiles) - t0;
     const int local_tile = tile - t0;
+    const int pstride = 2 * A.L.N_max + 2;
+    PiAcc pa{INFINITY, 0.0f, 0.0f, 0.0f};
     for (int r = 0; r < A.spl; ++r) {
         const uint32_t k = (uint32_t)((local_tile * A.spl + r) * BLOCK + threadIdx.x);
         const bool valid = k < (uint32_t)bs.K;
         float *nz = (A.dbg_noise && valid) ? A.dbg_noise + (size_t)k * bs.N * 2 : nullptr;
         const SampleResult res = lane_sample<MODEL, NDISC, MAXOPP>(A.P, bs, lds, A.L, valid ? k : 0u, nz);
-        const unsigned long long key = valid ? make_key(res.h, res.h ? res.cost : res.viol, k) : KEY_NONE;
+        unsigned long long key;
+        if (pi) {
+            const float S = res.cost + A.P.w_viol * res.viol;
+            key = valid ? make_key(isfinite(S), isfinite(S) ? S : 0.0f, k) : KEY_NONE;
+        } else {
+            key = valid ? make_key(res.h, res.h ? res.cost : res.viol, k) : KEY_NONE;
+        }
         const unsigned long long wmin = wave_min_u64(key);
         const unsigned long long feas = __ballot(valid && res.h);
         if (lane == 0) {
@@ -929,7 +1010,9 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
             const int cnt = __popcll(feas);
             if (cnt) atomicAdd(A.nfeas + bs.slot, cnt);
         }
-        if (A.cp_slots && valid && key == wmin) {  // the wave's best sample keeps its checkpoints
+        if (pi) {
+            pi_accumulate(A.P, bs, lds, A.L, valid ? k : 0u, valid, res, pa);
+        } else if (A.cp_slots && valid && key == wmin) {  // the wave's best sample keeps its checkpoints
             float *slot = A.cp_slots + ((size_t)A.items[item].group0 + k / 64) * CP_FLOATS;
 #pragma unroll
             for (int c = 0; c < NCP - 1; ++c)
@@ -949,6 +1032,30 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
                 o[2] = a.psi0 + (double)res.st[2];
                 o[3] = res.st[3]; o[4] = res.st[4]; o[5] = res.st[5];
             }
+        }
+    }
+    if (pi) {  // the tile's partial: combine the four waves in order
+        float *pw = (float *)(lds + A.L.rr_u);  // [4][2N + 2] (re-roll scratch, free here)
+        const int ws = 2 * bs.N + 2, wv = threadIdx.x >> 6;
+        if (lane == 0) {
+            pw[wv * ws] = pa.S;
+            pw[wv * ws + 1] = pa.w;
+        }
+        if (lane < 2 * bs.N) pw[wv * ws + 2 + lane] = pa.c0;
+        if (lane + 64 < 2 * bs.N) pw[wv * ws + 2 + lane + 64] = pa.c1;
+        __syncthreads();
+        if ((int)threadIdx.x < ws) {
+            float Sb = INFINITY;
+            for (int w = 0; w < BLOCK / 64; ++w) Sb = fminf(Sb, pw[w * ws]);
+            float v = Sb;
+            if (threadIdx.x > 0) {
+                v = 0.0f;
+                for (int w = 0; w < BLOCK / 64; ++w) {
+                    const float Sw = pw[w * ws];
+                    if (Sw < INFINITY) v += pw[w * ws + threadIdx.x] * expf((Sb - Sw) * A.P.inv_lambda);
+                }
+            }
+            A.pi_part[(size_t)tile * pstride + threadIdx.x] = v;
         }
     }
     __syncthreads();
@@ -975,16 +1082,42 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
         out.final_shift = final_phase;
         out.u_apply = (final_phase && A.u_apply) ? A.u_apply + bs.slot : nullptr;
     }
-    const float *cps = A.cp_slots ? A.cp_slots + ((size_t)it.group0 + k / 64) * CP_FLOATS : nullptr;
-    const SampleResult res = reroll_block<MODEL, NDISC, MAXOPP, WINNER>(A.P, A.L, bs, lds, rec, k, out, cps);
+    SampleResult res{};
+    float pi_min = INFINITY;
+    if (pi) {
+        // combine the tiles' partials in tile order; the weighted mean replaces the nominal
+        float *sums = (float *)(lds + A.L.rr_u);  // [2N + 1]: sum of weights, weighted controls
+        const float *pp = A.pi_part + (size_t)t0 * pstride;
+        float Smin = INFINITY;
+        for (int t = 0; t < n_tiles_item; ++t) Smin = fminf(Smin, pp[(size_t)t * pstride]);
+        pi_min = Smin;
+        if (Smin < INFINITY) {
+            if ((int)threadIdx.x < 2 * bs.N + 1) {
+                float v = 0.0f;
+                for (int t = 0; t < n_tiles_item; ++t) {
+                    const float St = pp[(size_t)t * pstride];
+                    if (St < INFINITY) v += pp[(size_t)t * pstride + 1 + threadIdx.x] * expf((Smin - St) * A.P.inv_lambda);
+                }
+                sums[threadIdx.x] = v;
+            }
+            __syncthreads();
+            float *ub = (float *)(lds + A.L.ubar);
+            if ((int)threadIdx.x < 2 * bs.N) ub[threadIdx.x] = sums[1 + threadIdx.x] / sums[0];
+        }
+        __syncthreads();
+        reroll_block<MODEL, NDISC, MAXOPP, NOMINAL>(A.P, A.L, bs, lds, rec, 0u, out);
+    } else {
+        const float *cps = A.cp_slots ? A.cp_slots + ((size_t)it.group0 + k / 64) * CP_FLOATS : nullptr;
+        res = reroll_block<MODEL, NDISC, MAXOPP, WINNER>(A.P, A.L, bs, lds, rec, k, out, cps);
+    }
     if (threadIdx.x == 0) {
         if (A.choice) {
             sgtp_choice c;
             c.k = (int)k;
             c.fallback = (key >> 63) ? 1 : 0;
             c.n_feasible = nfeas;
-            c.cost = res.cost;
-            c.viol = res.viol;
+            c.cost = pi ? pi_min : res.cost;
+            c.viol = pi ? 0.0f : res.viol;
             A.choice[bs.slot - A.choice_base] = c;
         }
         A.keys[bs.slot] = KEY_NONE;
@@ -1456,6 +1589,8 @@ struct sgtp_ctx {
     int *d_counters = nullptr;
     float *d_cp = nullptr;     // checkpoint slots, CP_FLOATS per 64-sample group
     long long max_groups = 0;
+    float *d_pi = nullptr;     // path-integral partial sums per tile (sgtp_ctx_enable_path_integral)
+    long long pi_tiles = 0;
     // descriptor uploads: pinned ring, each slot guarded by an event
     static constexpr int RING = 8;
     char *h_stage[RING] = {};
@@ -1520,6 +1655,9 @@ KParams make_kparams(const sgtp_params *p) {
     k.C_rev = (float)((double)p->C / (2.0 * M_PI));
     k.lr_over_L = (float)(p->lr / L);
     k.inv_lr = (float)(1.0 / p->lr);
+    k.update = p->update;
+    k.inv_lambda = p->update == 1 ? (float)(1.0 / (double)p->mppi_lambda) : 0.0f;
+    k.w_viol = p->mppi_w_viol;
     return k;
 }
 
@@ -1543,6 +1681,13 @@ int check_params(sgtp_ctx *c, const sgtp_params *p) {
     if (p->max_moves < 1 || p->max_moves > 1024) return fail(c, SGTP_EINVAL, "max_moves out of range");
     if (!(p->m > 0.f) || !(p->Iz > 0.f) || !(p->lf > 0.f) || !(p->lr > 0.f) || !(p->v_eps > 0.f))
         return fail(c, SGTP_EINVAL, "vehicle constants must be positive");
+    if (p->update != 0 && p->update != 1) return fail(c, SGTP_EINVAL, "update must be 0 or 1");
+    if (p->update == 1) {
+        if (!(p->mppi_lambda > 0.f) || !std::isfinite(p->mppi_lambda) || !(p->mppi_w_viol >= 0.f) ||
+            !std::isfinite(p->mppi_w_viol))
+            return fail(c, SGTP_EINVAL, "path-integral temperature must be positive, violation weight >= 0");
+        if (!c->d_pi) return fail(c, SGTP_EINVAL, "path-integral update not enabled on this context");
+    }
     return SGTP_OK;
 }
 
@@ -1578,6 +1723,8 @@ int build_plan(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_
         d.x = s.x; d.s_abs = s.s_abs; d.v_scale = s.v_scale; d.u_nom = s.u_nom; d.traj = s.traj;
         d.prop = (const float4 *)s.prop;
         d.K_prop = s.prop ? std::min(std::max(s.K_prop, 0), s.K) : 0;
+        if (p->update == 1 && s.prop && s.K_prop > 0)
+            return fail(c, SGTP_EINVAL, "a learned proposal cannot be combined with the path-integral update");
         pl.races.push_back(d);
         const int tiles = (s.K + BLOCK * spl - 1) / (BLOCK * spl);
         const long long groups = (s.K + 63) / 64;
@@ -1609,6 +1756,8 @@ int build_plan(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_
     }
     if (slot > c->max_agents) return fail(c, SGTP_ESHAPE, "total vehicles exceed the context");
     if (group_total > c->max_groups) return fail(c, SGTP_ESHAPE, "total samples exceed the context (max_K)");
+    if (p->update == 1 && (long long)pl.tiles_all > c->pi_tiles)
+        return fail(c, SGTP_ESHAPE, "tiles exceed the path-integral buffer");
     pl.agents_total = slot;
     pl.w_max = (int)std::min<double>(WIN_MAX, wneed);
     return SGTP_OK;
@@ -1782,6 +1931,7 @@ struct Runner {
         A.nfeas = c->d_nfeas;
         A.counters = c->d_counters;
         A.cp_slots = c->d_cp;
+    A.pi_part = c->d_pi;
         A.spl = 1;
         return SGTP_OK;
     }
@@ -2017,7 +2167,7 @@ int sgtp_ctx_destroy(sgtp_ctx *c) {
     for (auto &t : c->tracks)
         if (t.d_nodes) (void)hipFree(t.d_nodes);
     void *bufs[] = {c->d_tracks, c->d_agents, c->d_win,      c->d_xref, c->d_pred[0], c->d_pred[1],
-                    c->d_keys,   c->d_nfeas,  c->d_counters, c->d_cp,   c->d_desc};
+                    c->d_keys,   c->d_nfeas,  c->d_counters, c->d_cp,   c->d_desc,   c->d_pi};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (int i = 0; i < sgtp_ctx::RING; ++i) {
@@ -2030,6 +2180,19 @@ int sgtp_ctx_destroy(sgtp_ctx *c) {
 }
 
 const char *sgtp_last_error(const sgtp_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int sgtp_ctx_enable_path_integral(sgtp_ctx *c) {
+    if (!c) return SGTP_EINVAL;
+    if (c->d_pi) return SGTP_OK;
+    const long long tiles = c->max_groups / (BLOCK / 64) + c->max_agents;
+    const size_t bytes = sizeof(float) * (size_t)tiles * (size_t)(2 * c->max_N + 2);
+    if (hipMalloc((void **)&c->d_pi, bytes) != hipSuccess) {
+        c->d_pi = nullptr;
+        return fail(c, SGTP_ENOMEM, "path-integral buffer");
+    }
+    c->pi_tiles = tiles;
+    return SGTP_OK;
+}
 
 int sgtp_track_upload(sgtp_ctx *c, int id, const double *nodes, int n, int closed, double length, double psi_lap) {
     if (!c) return SGTP_EINVAL;
@@ -2228,6 +2391,7 @@ int sgtp_plan_create(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, 
     A.nfeas = c->d_nfeas;
     A.counters = c->d_counters;
     A.cp_slots = c->d_cp;
+    A.pi_part = c->d_pi;
     A.spl = o.samples_per_lane;
     A.chunk = o.tiles_per_fetch;
     if (o.persistent) {

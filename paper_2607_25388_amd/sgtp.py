@@ -34,7 +34,12 @@ class Params(C.Structure):
         ("m", C.c_float), ("Iz", C.c_float), ("lf", C.c_float), ("lr", C.c_float),
         ("B", C.c_float), ("C", C.c_float), ("mu", C.c_float), ("g", C.c_float), ("v_eps", C.c_float),
         ("max_moves", C.c_int),
+        ("update", C.c_int), ("mppi_lambda", C.c_float), ("mppi_w_viol", C.c_float),
     ]
+
+
+# parameters with a default (the path-integral update is off unless asked for)
+PARAM_DEFAULTS = {"update": 0, "mppi_lambda": 1.0, "mppi_w_viol": 0.0}
 
 
 class Race(C.Structure):
@@ -82,6 +87,7 @@ def load():
         vp = C.c_void_p
         lib.sgtp_ctx_create.argtypes = [P(vp), C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
         lib.sgtp_ctx_destroy.argtypes = [vp]
+        lib.sgtp_ctx_enable_path_integral.argtypes = [vp]
         lib.sgtp_last_error.argtypes = [vp]
         lib.sgtp_last_error.restype = C.c_char_p
         lib.sgtp_track_upload.argtypes = [vp, C.c_int, vp, C.c_int, C.c_int, C.c_double, C.c_double]
@@ -122,7 +128,7 @@ def load():
 def make_params(d: dict) -> Params:
     p = Params()
     for name, typ in Params._fields_:
-        v = d[name]
+        v = d[name] if name in d else PARAM_DEFAULTS[name]
         if name in ("Q", "R", "S", "disc_off"):
             arr = getattr(p, name)
             for i, x in enumerate(v):
@@ -223,6 +229,10 @@ class Planner:
         if rc != 0:
             msg = self.lib.sgtp_last_error(self.ctx).decode()
             raise RuntimeError(f"{what} failed ({ERRORS.get(rc, rc)}): {msg}")
+
+    def enable_path_integral(self):
+        """Allocate the buffers of the path-integral (GA-IBR-MPPI) update."""
+        self._check(self.lib.sgtp_ctx_enable_path_integral(self.ctx), "sgtp_ctx_enable_path_integral")
 
     def upload_track(self, track_id: int, track):
         nodes = np.ascontiguousarray(track.nodes, np.float64)

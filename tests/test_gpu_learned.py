@@ -138,11 +138,14 @@ def test_adam_first_step_and_training_reduces_loss():
     losses = [float(loss0.item())]
     for it in range(300):
         loss, _ = m.grad(Xd, Ud, 1.5, 0.08)
-        m.adam(lr=lr)
-        if it % 50 == 49:
+        m.adam(lr=3e-4)
+        if it % 25 == 24:
             losses.append(float(loss.item()))
     print(losses)
-    assert losses[-1] < losses[0] - 1.0, losses
+    # the likelihood of a fit with shrinking scales rises far above the start; single
+    # Adam steps can still spike, so the last values are judged by their median
+    assert min(losses[1:]) < losses[0] - 50.0, losses
+    assert float(np.median(losses[-3:])) < losses[0] - 10.0, losses
     m.close()
 
 
