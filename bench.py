@@ -233,6 +233,25 @@ def main():
 
     name = args.workload
     planner = sg.Planner(max_agents_total=2048, max_races=256)
+    if name == "race":
+        # closed-loop race evaluation of the planner variants (Sec. IV-B metrics, Table II)
+        from paper_2607_25388_amd import race_eval
+        planner.close()
+        n_games = 7 * 6 * 3
+        rp = sg.Planner(max_agents_total=n_games * 3, max_races=n_games, max_K=4096)
+        rp.enable_path_integral()
+        res = race_eval.evaluate(rp, race_eval.METHODS, 7, 6, 40, 4096, 5, 50.0,
+                                 log=lambda m: print(m, file=sys.stderr, flush=True))
+        rp.close()
+        rec = {"metric": METRIC, "value": res["sgtp"]["wins"], "unit": "win rate", "n_gpus": 1,
+               "higher_is_better": True, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": ("race evaluation: 42 trials (7 seeded 1.2 km x 12 m tracks x 6 starts), "
+                                       "3 vehicles (ego rearmost, opponents at 0.9 reference speed), every "
+                                       "vehicle plans its own game (N=40, K=4096, 5 IBR sweeps), 50 s, all "
+                                       "126 games batched in one plan per step")},
+               "race_eval": res}
+        print(json.dumps(rec), flush=True)
+        return
     if name == "c5":
         rec = {"metric": METRIC, "unit": "relative selected cost", "n_gpus": 1, "higher_is_better": False,
                "vs_baseline": None, "dtype": "f32 planner, bf16 network (f32 accumulation)", "data": "synthetic"}

@@ -1,0 +1,94 @@
+"""Host-side race metrics (Sec. IV-B) on constructed trajectories with known answers."""
+
+import math
+
+import numpy as np
+import pytest
+
+from paper_2607_25388_amd import race_eval as RE
+from paper_2607_25388_amd.inputs import default_params
+
+P = default_params(40, 3)
+DT = 0.05
+
+
+def _lineup(T, s0, v, lat):
+    """Vehicles on a straight line y = lat[j], x = s = s0[j] + v[j] t."""
+    n = len(s0)
+    t = np.arange(T) * DT
+    s = np.stack([s0[j] + v[j] * t for j in range(n)], axis=1)
+    d = np.tile(np.asarray(lat, float), (T, 1))
+    X = np.zeros((T, n, 6))
+    X[..., 0] = s
+    X[..., 1] = d
+    X[..., 3] = np.asarray(v)[None, :]
+    return s, d, X
+
+
+def test_footprint_distance_closed_form():
+    X = np.zeros((2, 6))
+    X[1, 1] = 3.0  # side by side, 3 m apart laterally
+    dist = RE.footprint_distance(X, P)
+    assert dist[0, 1] == pytest.approx(3.0) and dist[1, 0] == pytest.approx(3.0)
+    assert math.isinf(dist[0, 0])
+    X[1, 1] = 0.0
+    X[1, 0] = 5.0  # in line, 5 m apart: nearest discs 5 - 3 = 2 m
+    assert RE.footprint_distance(X, P)[0, 1] == pytest.approx(2.0)
+
+
+def test_overtake_counts_as_clean_win():
+    T = 200
+    s, d, X = _lineup(T, [0.0, 10.0, 20.0], [30.0, 20.0, 20.0], [-4.0, 0.0, 4.0])
+    m = RE.trial_metrics(s, d, X, np.zeros((T, 2)), np.full(T, 6.0), P, DT)
+    assert m["win"] and not m["collided"] and m["fpr"] == 1.0
+    assert m["duration"] == pytest.approx(T * DT)
+    assert m["mcs"] == 0.0
+
+
+def test_collision_ends_the_trial():
+    T = 100
+    s, d, X = _lineup(T, [0.0, 30.0], [30.0, 10.0], [0.0, 0.0])
+    # the ego closes 20 m/s on a car 30 m ahead: footprints (5 m long discs chain) meet when
+    # the centre gap falls below d_col + 3 m = 5 m -> gap 30 - 20 t < 5 -> t > 1.25 s
+    m = RE.trial_metrics(s, d, X, np.zeros((T, 2)), np.full(T, 6.0), P, DT)
+    assert m["collided"]
+    k_end = int(np.nonzero(30.0 - 20.0 * np.arange(T) * DT < 5.0)[0][0])
+    assert m["duration"] == pytest.approx((k_end + 1) * DT)
+
+
+def test_leaving_the_track_ends_the_trial():
+    T = 50
+    s, d, X = _lineup(T, [0.0, 50.0], [20.0, 20.0], [0.0, 0.0])
+    d[:, 0] = np.linspace(0.0, 8.0, T)  # drifts out of a 6 m half width
+    m = RE.trial_metrics(s, d, X, np.zeros((T, 2)), np.full(T, 6.0), P, DT)
+    assert m["collided"]
+    assert m["duration"] == pytest.approx((int(np.nonzero(d[:, 0] > 6.0)[0][0]) + 1) * DT)
+
+
+def test_close_interaction_segments_and_smoothness():
+    T = 12
+    s, d, X = _lineup(T, [0.0, 100.0], [0.0, 0.0], [0.0, 5.0])
+    lon, lat = RE.csd_box(P)
+    # 3 discs 1.5 m apart and d_col = 2 m: bumper contact at 5 m, box 5.56 m x 1.11 m
+    assert lon == pytest.approx(5.0 / 0.9) and lat == pytest.approx(1.0 / 0.9)
+    # opponent inside the box at steps 2..4 and 7..8
+    for k in (2, 3, 4, 7, 8):
+        s[k, 1] = s[k, 0] + 0.5 * lon
+        d[k, 1] = d[k, 0] + 0.5 * lat
+    u = np.zeros((T, 2))
+    u[5:, 0] = 1.0  # one unit step in acceleration
+    m = RE.trial_metrics(s, d, X, u, np.full(T, 6.0), P, DT)
+    assert m["segments"] == pytest.approx([3 * DT, 2 * DT])
+    assert m["mcs"] == pytest.approx(1.0 / (T - 1))
+
+
+def test_summary():
+    trials = [dict(win=True, collided=False, fpr=1.0, duration=50.0, segments=[1.0], v_ego=[10.0], mcs=0.1),
+              dict(win=True, collided=True, fpr=0.5, duration=10.0, segments=[], v_ego=[20.0], mcs=0.3),
+              dict(win=False, collided=False, fpr=0.0, duration=50.0, segments=[3.0], v_ego=[30.0], mcs=0.2)]
+    s = RE.summarize(trials, 50.0)
+    assert s["wins"] == pytest.approx(2 / 3) and s["cfw"] == pytest.approx(0.5)
+    assert s["fpr"] == pytest.approx(0.5) and s["csd_s"] == pytest.approx(2.0)
+    assert s["d_mean_s"] == pytest.approx(110 / 3) and s["d_max_s"] == 50.0
+    assert s["d_ratio"] == pytest.approx(110 / 150) and s["v_ego_mean"] == pytest.approx(20.0)
+    assert s["ego_collisions"] == 1
