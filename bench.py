@@ -23,6 +23,26 @@ sys.path.insert(0, ROOT)
 METRIC = "sample·steps/s per IBR sweep; plan latency p50/p99; learned vs plain cost"
 PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak
 
+# Hardware counters of the dominant sweep kernel (k_sweep, one workgroup per tile, the
+# schedule the autotuner picks for the mid-scale race), medians over the timed eager
+# launches of `bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-learned --roofline-steps 2
+# --copy-calibration 256` under rocprofv3 --pmc.  HBM bytes: FETCH_SIZE 360.4 KiB x 2.000 +
+# WRITE_SIZE 332.3 KiB x 1.000 per launch, the factors being 256 MiB over what the same
+# counter reads for the 256 MiB elementwise copy (131087 KiB fetched, 262144 KiB written).
+# FP32 FLOPs: 64 x (ADD + MUL + TRANS + 2 FMA) wave instructions of SQ_INSTS_VALU_*_F32.
+# They describe the kernel source with this SHA-256 only; any other source reports null.
+SWEEP_COUNTERS = {
+    "c2": {"source_sha256": "eaf13174ce2f13213d4ec86da327a86e608367ace6a2262644b9b33b2e81f765",
+           "hbm_bytes_per_launch": (360.375 * 1.99981 + 332.344) * 1024.0,
+           "hw_fp32_flop_per_launch": 1.363e9, "valu_wave_insts_per_launch": 22.41e6},
+}
+
+
+def _source_sha256() -> str:
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2607_25388_amd", "csrc", "sgtp.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
 
 def flops_per_sample_step(n_opp: int, model: int = 0) -> float:
     """Algorithmic float operations per sample and horizon step (elementary functions count 1).
@@ -220,6 +240,9 @@ def main():
     ap.add_argument("--learned-examples", type=int, default=100000,
                     help="training examples of the learned proposal (the c5 workload uses 1e6)")
     ap.add_argument("--learned-iters", type=int, default=4000)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the timed region, one elementwise copy of MIB MiB (reads and writes MIB MiB): "
+                         "the reference kernel for scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this planner runs on a single device (see the design notes for how "
@@ -305,6 +328,12 @@ def main():
     planner.set_timing(False)
     eplan.close()
     sweep_ms, sweep_launches, sweep_ss = planner.sweep_stats(reset=True)
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     value = per_step * args.steps / el
     avg_sweep_ms = sweep_ms / max(1, sweep_launches)
@@ -335,6 +364,12 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
                      "flops_per_sample_step": flops},
     }
+    cnt = SWEEP_COUNTERS.get(name)
+    if cnt and cnt["source_sha256"] == _source_sha256():
+        rec["roofline"]["traffic"] = cnt["hbm_bytes_per_launch"]
+        rec["roofline"]["traffic_unit"] = "bytes per sweep launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)"
+        rec["roofline"]["hw_fp32_tflops"] = cnt["hw_fp32_flop_per_launch"] / (avg_sweep_ms * 1e-3) / 1e12
+        rec["roofline"]["hbm_gbps"] = cnt["hbm_bytes_per_launch"] / (avg_sweep_ms * 1e-3) / 1e9
     if tuned:
         rec["config"]["autotune"] = tuned
     if not args.no_learned:
