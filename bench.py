@@ -233,6 +233,9 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--mode", choices=["graph", "eager"], default="graph")
     ap.add_argument("--no-autotune", action="store_true", help="skip the schedule search (default schedule)")
+    ap.add_argument("--schedule", default="", metavar="P,B,C,S",
+                    help="fixed schedule instead of the search: persistent, blocks per CU, tiles per fetch, "
+                         "samples per lane")
     ap.add_argument("--roofline-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -289,7 +292,11 @@ def main():
     stream = torch.cuda.current_stream()
     opts = sg.plan_options(include_advance=1)
     tuned = None
-    if not args.no_autotune:
+    if args.schedule:
+        pp, bb, cc, ss = (int(x) for x in args.schedule.split(","))
+        opts = sg.plan_options(persistent=pp, blocks_per_cu=bb, tiles_per_fetch=cc, samples_per_lane=ss,
+                               include_advance=1)
+    elif not args.no_autotune:
         best, ms = planner.autotune(params, rts, L)
         best.include_advance = 1
         opts = best

@@ -297,9 +297,35 @@ __device__ __forceinline__ StepConst<typename M::T> step_const(const VehConst<ty
     return c;
 }
 
+// Lateral force of one axle: slip angle alpha = delta_axle - atan((v_y + l om) / v_hat)
+// (l = l_f for the front axle, -l_r for the rear one, whose steering angle is 0) and
+// F_y = mu F_z sin(C atan(B alpha)).  Both axles go through this one expression, so the
+// two-lane evaluation below gives the same bits as the one-lane one.
+template <class M>
+__device__ __forceinline__ typename M::T tyre_force(const VehConst<typename M::T> &V, typename M::T l,
+                                                     typename M::T delta_axle, typename M::T muFz, typename M::T vy,
+                                                     typename M::T om, typename M::T inv_vh) {
+    using T = typename M::T;
+    const T alpha = delta_axle - M::atan_((vy + l * om) * inv_vh);
+    return muFz * M::sin_rev(V.Cs * M::atan_(V.B * alpha));
+}
+
 // Vehicle model f (Sec. II).  MODEL 0: dynamic single-track with
 // F_y = mu F_z sin(C atan(B alpha)); MODEL 1: kinematic bicycle at the CoG.
 // Position rates use max(v_x, 0), so no stage of RK4 moves the car backwards.
+template <class M>
+__device__ __forceinline__ void deriv_rates(const VehConst<typename M::T> &V, const StepConst<typename M::T> &c,
+                                            typename M::T vx, typename M::T vy, typename M::T om, typename M::T cp,
+                                            typename M::T sp, typename M::T Fyf, typename M::T Fyr,
+                                            typename M::T d[6]) {
+    d[0] = vx * cp - vy * sp;
+    d[1] = vx * sp + vy * cp;
+    d[2] = om;
+    d[3] = c.a - Fyf * c.sd * V.inv_m + vy * om;
+    d[4] = (Fyr + Fyf * c.cd) * V.inv_m - vx * om;
+    d[5] = (V.lf * Fyf * c.cd - V.lr * Fyr) * V.inv_Iz;
+}
+
 template <int MODEL, class M>
 __device__ __forceinline__ void deriv(const VehConst<typename M::T> &V, const StepConst<typename M::T> &c,
                                       typename M::T psi, typename M::T vx_, typename M::T vy, typename M::T om,
@@ -310,16 +336,9 @@ __device__ __forceinline__ void deriv(const VehConst<typename M::T> &V, const St
     const T cp = M::cos_rev(pr), sp = M::sin_rev(pr);
     if (MODEL == 0) {
         const T inv_vh = M::rcp_(vx > V.v_eps ? vx : V.v_eps);
-        const T alpha_f = c.delta - M::atan_((vy + V.lf * om) * inv_vh);
-        const T alpha_r = -M::atan_((vy - V.lr * om) * inv_vh);
-        const T Fyf = V.muFzf * M::sin_rev(V.Cs * M::atan_(V.B * alpha_f));
-        const T Fyr = V.muFzr * M::sin_rev(V.Cs * M::atan_(V.B * alpha_r));
-        d[0] = vx * cp - vy * sp;
-        d[1] = vx * sp + vy * cp;
-        d[2] = om;
-        d[3] = c.a - Fyf * c.sd * V.inv_m + vy * om;
-        d[4] = (Fyr + Fyf * c.cd) * V.inv_m - vx * om;
-        d[5] = (V.lf * Fyf * c.cd - V.lr * Fyr) * V.inv_Iz;
+        const T Fyf = tyre_force<M>(V, V.lf, c.delta, V.muFzf, vy, om, inv_vh);
+        const T Fyr = tyre_force<M>(V, -V.lr, T(0), V.muFzr, vy, om, inv_vh);
+        deriv_rates<M>(V, c, vx, vy, om, cp, sp, Fyf, Fyr, d);
     } else {
         d[0] = vx * (cp * c.kc - sp * c.ks);
         d[1] = vx * (sp * c.kc + cp * c.ks);
@@ -328,6 +347,21 @@ __device__ __forceinline__ void deriv(const VehConst<typename M::T> &V, const St
         d[4] = T(0);
         d[5] = T(0);
     }
+}
+
+// The dynamic model's derivative on a pair of neighbouring lanes: each lane evaluates
+// one axle (rear = odd lane) and the two forces are swapped with a DPP quad permute;
+// everything else is computed by both lanes alike.  Same values as deriv<0, MathF32>.
+__device__ __forceinline__ void deriv_pair(const VehConst<float> &V, const StepConst<float> &c, float psi, float vx_,
+                                           float vy, float om, bool rear, float d[6]) {
+    const float vx = vx_ > 0.0f ? vx_ : 0.0f;
+    const float pr = MathF32::to_rev(psi);
+    const float cp = MathF32::cos_rev(pr), sp = MathF32::sin_rev(pr);
+    const float inv_vh = MathF32::rcp_(vx > V.v_eps ? vx : V.v_eps);
+    const float F = tyre_force<MathF32>(V, rear ? -V.lr : V.lf, rear ? 0.0f : c.delta, rear ? V.muFzr : V.muFzf, vy,
+                                        om, inv_vh);
+    const float Fo = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(F), 0xB1, 0xf, 0xf, false));
+    deriv_rates<MathF32>(V, c, vx, vy, om, cp, sp, rear ? Fo : F, rear ? F : Fo, d);
 }
 
 // Classic RK4 over one interval with the control held, then v_x <- max(v_x, 0).
@@ -345,6 +379,21 @@ __device__ __forceinline__ void rk4(const VehConst<typename M::T> &V, const Step
 #pragma unroll
     for (int i = 0; i < 6; ++i) s[i] = s[i] + h6 * (k1[i] + T(2) * k2[i] + T(2) * k3[i] + k4[i]);
     if (!(s[3] > T(0)) && s[3] == s[3]) s[3] = T(0);
+}
+
+// rk4<0, MathF32> on a pair of lanes (deriv_pair); same expressions, same bits.
+__device__ __forceinline__ void rk4_pair(const VehConst<float> &V, const StepConst<float> &c, float h, float s[6],
+                                         bool rear) {
+    float k1[6], k2[6], k3[6], k4[6];
+    const float hh = 0.5f * h;
+    deriv_pair(V, c, s[2], s[3], s[4], s[5], rear, k1);
+    deriv_pair(V, c, s[2] + hh * k1[2], s[3] + hh * k1[3], s[4] + hh * k1[4], s[5] + hh * k1[5], rear, k2);
+    deriv_pair(V, c, s[2] + hh * k2[2], s[3] + hh * k2[3], s[4] + hh * k2[4], s[5] + hh * k2[5], rear, k3);
+    deriv_pair(V, c, s[2] + h * k3[2], s[3] + h * k3[3], s[4] + h * k3[4], s[5] + h * k3[5], rear, k4);
+    const float h6 = h / 6.0f;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) s[i] = s[i] + h6 * (k1[i] + 2.0f * k2[i] + 2.0f * k3[i] + k4[i]);
+    if (!(s[3] > 0.0f) && s[3] == s[3]) s[3] = 0.0f;
 }
 
 __device__ __forceinline__ VehConst<float> veh_f32(const KParams &P) {
@@ -370,8 +419,35 @@ struct Foot {
     bool limit;
 };
 
-// Segment search from `seg` (at most max_moves moves, inside the window), then the
-// foot t solving cross(p - c(t), n(t)) = 0 with the stable quadratic root.
+// Foot on segment `seg` between the geometry rows A0, A1 (g0, g1: the point's signed
+// distances ahead of their normal lines): t solves cross(p - c(t), n(t)) = 0 with the
+// stable quadratic root; s, w_L, w_R interpolated from the segment's second rows.
+__device__ __forceinline__ Foot foot_on(const float4 *__restrict__ nodes, float X, float Y, int seg, float4 A0,
+                                        float4 A1, float g0, float g1) {
+    Foot f;
+    f.seg = seg;
+    f.limit = !(g0 >= 0.0f && g1 <= 0.0f);
+    const float4 B0 = nodes[2 * seg + 1], B1 = nodes[2 * seg + 3];
+    const float rx = X - A0.x, ry = Y - A0.y;
+    const float Dx = A1.x - A0.x, Dy = A1.y - A0.y;
+    const float dnx = A1.z - A0.z, dny = A1.w - A0.w;
+    const float Cc = g0;
+    const float Bc = (rx * dny - ry * dnx) - (Dx * A0.w - Dy * A0.z);
+    const float Ac = -(Dx * dny - Dy * dnx);
+    const float disc = fmaxf(Bc * Bc - 4.0f * Ac * Cc, 0.0f);
+    const float den = -Bc - copysignf(__builtin_amdgcn_sqrtf(disc), Bc);
+    float t = (den != 0.0f) ? (2.0f * Cc) * fast_rcp(den) : 0.0f;
+    t = fminf(fmaxf(t, 0.0f), 1.0f);
+    const float cx = __builtin_fmaf(t, Dx, A0.x), cy = __builtin_fmaf(t, Dy, A0.y);
+    const float nx = __builtin_fmaf(t, dnx, A0.z), ny = __builtin_fmaf(t, dny, A0.w);
+    f.d = ((X - cx) * nx + (Y - cy) * ny) * __builtin_amdgcn_rsqf(nx * nx + ny * ny);
+    f.s = __builtin_fmaf(t, B1.z - B0.z, B0.z);
+    f.wL = __builtin_fmaf(t, B1.x - B0.x, B0.x);
+    f.wR = __builtin_fmaf(t, B1.y - B0.y, B0.y);
+    return f;
+}
+
+// Segment search from `seg` (at most max_moves moves, inside the window), then the foot.
 __device__ __forceinline__ Foot project(const float4 *__restrict__ nodes, int W, int max_moves, float X, float Y,
                                         int seg) {
     int moves = 0;
@@ -397,27 +473,62 @@ __device__ __forceinline__ Foot project(const float4 *__restrict__ nodes, int W,
         A0 = nodes[2 * seg];
         g0 = ahead_of(A0, X, Y);
     }
-    Foot f;
-    f.seg = seg;
-    f.limit = !(g0 >= 0.0f && g1 <= 0.0f);
-    const float rx = X - A0.x, ry = Y - A0.y;
-    const float Dx = A1.x - A0.x, Dy = A1.y - A0.y;
-    const float dnx = A1.z - A0.z, dny = A1.w - A0.w;
-    const float Cc = g0;
-    const float Bc = (rx * dny - ry * dnx) - (Dx * A0.w - Dy * A0.z);
-    const float Ac = -(Dx * dny - Dy * dnx);
-    const float disc = fmaxf(Bc * Bc - 4.0f * Ac * Cc, 0.0f);
-    const float den = -Bc - copysignf(__builtin_amdgcn_sqrtf(disc), Bc);
-    float t = (den != 0.0f) ? (2.0f * Cc) * fast_rcp(den) : 0.0f;
-    t = fminf(fmaxf(t, 0.0f), 1.0f);
-    const float cx = __builtin_fmaf(t, Dx, A0.x), cy = __builtin_fmaf(t, Dy, A0.y);
-    const float nx = __builtin_fmaf(t, dnx, A0.z), ny = __builtin_fmaf(t, dny, A0.w);
-    f.d = ((X - cx) * nx + (Y - cy) * ny) * __builtin_amdgcn_rsqf(nx * nx + ny * ny);
-    const float4 B0 = nodes[2 * seg + 1], B1 = nodes[2 * seg + 3];
-    f.s = __builtin_fmaf(t, B1.z - B0.z, B0.z);
-    f.wL = __builtin_fmaf(t, B1.x - B0.x, B0.x);
-    f.wR = __builtin_fmaf(t, B1.y - B0.y, B0.y);
-    return f;
+    return foot_on(nodes, X, Y, seg, A0, A1, g0, g1);
+}
+
+// The same search with the geometry rows of segments seg .. seg + NPF - 1 read ahead
+// (before the step's dynamics, so their LDS latency is hidden): the first NPF - 2
+// forward moves run on registers, further moves read LDS.  Same states, same result.
+template <int NPF>
+struct NodeAhead {
+    float4 q[NPF];
+};
+template <int NPF>
+__device__ __forceinline__ NodeAhead<NPF> read_ahead(const float4 *__restrict__ nodes, int W, int seg) {
+    NodeAhead<NPF> a;
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) a.q[i] = nodes[2 * min(seg + i, W - 1)];
+    return a;
+}
+template <int NPF>
+__device__ __forceinline__ Foot project_ahead(const float4 *__restrict__ nodes, int W, int max_moves, float X,
+                                              float Y, int seg, const NodeAhead<NPF> &a) {
+    int moves = 0;
+    float4 A0 = a.q[0], A1 = a.q[1];
+    float g1 = ahead_of(A1, X, Y);
+    float g0 = 0.0f;
+    bool fwd = false, go = true;
+#pragma unroll
+    for (int i = 1; i < NPF - 1; ++i) {
+        go = go && moves < max_moves && seg + 1 <= W - 2 && g1 > 0.0f;
+        if (go) {
+            ++seg;
+            ++moves;
+            A0 = A1;
+            A1 = a.q[i + 1];
+            g0 = g1;
+            g1 = ahead_of(A1, X, Y);
+            fwd = true;
+        }
+    }
+    while (go && moves < max_moves && seg + 1 <= W - 2 && g1 > 0.0f) {
+        ++seg;
+        ++moves;
+        A0 = A1;
+        A1 = nodes[2 * seg + 2];
+        g0 = g1;
+        g1 = ahead_of(A1, X, Y);
+    }
+    if (!fwd) g0 = ahead_of(A0, X, Y);
+    while (moves < max_moves && seg > 0 && g0 < 0.0f) {
+        --seg;
+        ++moves;
+        A1 = A0;
+        g1 = g0;
+        A0 = nodes[2 * seg];
+        g0 = ahead_of(A0, X, Y);
+    }
+    return foot_on(nodes, X, Y, seg, A0, A1, g0, g1);
 }
 
 // ------------------------------------------------------------------------------
@@ -688,7 +799,9 @@ __device__ __forceinline__ SampleResult terminal(const KParams &P, const BlockSt
 // ------------------------------------------------------------------------------
 // One sample in one lane: perturb, clip, roll out, score, check (Sec. III)
 // ------------------------------------------------------------------------------
-template <int MODEL, int NDISC, int MAXOPP>
+// NPF > 0 (launches with about one wave per SIMD, where nothing hides LDS latency):
+// the raceline rows of the next NPF segments are read ahead of each step's dynamics.
+template <int MODEL, int NDISC, int MAXOPP, int NPF = 0>
 __device__ __forceinline__ SampleResult lane_sample(const KParams &P, const BlockState &bs, const char *lds,
                                                    const LdsLayout &L, uint32_t k, float *noise_out) {
     const float2 *ubar = (const float2 *)(lds + L.ubar);
@@ -714,6 +827,11 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P, const Bloc
     const int C = (bs.N + NCP - 1) / NCP;
 
     for (int tau = 0; tau < bs.N; ++tau) {
+        // LDS reads that do not depend on this step's dynamics go first
+        const float2 ub = ubar[tau];
+        const float4 xr = xref[tau];
+        NodeAhead<(NPF > 0 ? NPF : 1)> ahead;
+        if constexpr (NPF > 0) ahead = read_ahead<NPF>(nodes, bs.W, seg);
         float2 z;
         if ((tau & 1) == 0) {
             const uint4 r = philox4x32_10(make_uint4(k, (uint32_t)(tau >> 1), bs.ctr2, bs.ctr3), bs.key0, bs.key1);
@@ -726,14 +844,16 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P, const Bloc
             noise_out[2 * tau] = z.x;
             noise_out[2 * tau + 1] = z.y;
         }
-        const float2 u = controls_k(P, bs, lds, L, k, tau, ubar[tau], z.x, z.y);
+        const float2 u = controls_k(P, bs, lds, L, k, tau, ub, z.x, z.y);
         const StepConst<float> sc = step_const<MODEL, MathF32>(V, u.x, u.y);
         rk4<MODEL, MathF32>(V, sc, P.dt, st);
-        const Foot f = project(nodes, bs.W, P.max_moves, st[0], st[1], seg);
+        Foot f;
+        if constexpr (NPF > 0) f = project_ahead<NPF>(nodes, bs.W, P.max_moves, st[0], st[1], seg, ahead);
+        else f = project(nodes, bs.W, P.max_moves, st[0], st[1], seg);
         seg = f.seg;
         limit |= f.limit;
         s = f.s;
-        J += track_term(P, st, xref[tau]);
+        J += track_term(P, st, xr);
         J += ctrl_term(P, u);
         if (tau >= 1) J += rate_term(P, u, up);
         up = u;
@@ -815,30 +935,36 @@ __device__ SampleResult reroll_block(const KParams &P, const LdsLayout &L, const
     }
     __syncthreads();
     // B. dynamics and projection, serial over the horizon; with the sample's checkpoints
-    //    (the lane's exact state and segment after steps C, 2C, 3C) NCP threads each run
-    //    one chunk of the horizon
+    //    (the lane's exact state and segment after steps C, 2C, 3C) NCP chunks of the
+    //    horizon run at once; the dynamic model puts each chunk on two lanes (one axle each)
     const int nch = cps ? NCP : 1;
     const int C = cps ? (N + NCP - 1) / NCP : N;
-    if (tid < nch) {
+    constexpr int LPC = MODEL == 0 ? 2 : 1;  // lanes per chunk
+    if (tid < LPC * nch) {
+        const int ch = tid / LPC;
+        const bool rear = LPC == 2 && (tid & 1);
         float st[6] = {0.0f, 0.0f, 0.0f, bs.vx0, bs.vy0, bs.om0};
         int seg = bs.seg0;
-        if (tid > 0) {
-            const float *c = cps + 7 * (tid - 1);
+        if (ch > 0) {
+            const float *c = cps + 7 * (ch - 1);
 #pragma unroll
             for (int i = 0; i < 6; ++i) st[i] = c[i];
             seg = __float_as_int(c[6]);
         }
-        const int t_end = min((tid + 1) * C, N);
-        for (int tau = tid * C; tau < t_end; ++tau) {
+        const int t_end = min((ch + 1) * C, N);
+        for (int tau = ch * C; tau < t_end; ++tau) {
             const float2 u = wu[tau];
             const StepConst<float> sc = step_const<MODEL, MathF32>(V, u.x, u.y);
-            rk4<MODEL, MathF32>(V, sc, P.dt, st);
+            if constexpr (MODEL == 0) rk4_pair(V, sc, P.dt, st, rear);
+            else rk4<MODEL, MathF32>(V, sc, P.dt, st);
             const Foot f = project(nodes, bs.W, P.max_moves, st[0], st[1], seg);
             seg = f.seg;
-            wst[2 * tau] = make_float4(st[0], st[1], st[2], st[3]);
-            wst[2 * tau + 1] = make_float4(st[4], st[5], 0.0f, 0.0f);
-            wf[tau] = make_float4(f.s, f.d, f.wL, f.wR);
-            wl[tau] = f.limit ? 1 : 0;
+            if (!rear) {
+                wst[2 * tau] = make_float4(st[0], st[1], st[2], st[3]);
+                wst[2 * tau + 1] = make_float4(st[4], st[5], 0.0f, 0.0f);
+                wf[tau] = make_float4(f.s, f.d, f.wL, f.wR);
+                wl[tau] = f.limit ? 1 : 0;
+            }
         }
     }
     __syncthreads();
@@ -981,7 +1107,7 @@ __device__ __forceinline__ void pi_accumulate(const KParams &P, const BlockState
 // path-integral update every tile leaves its weighted partial sums instead, and the
 // last workgroup combines them in tile order, adopts the weighted mean sequence and
 // rolls it out noise-free.
-template <int MODEL, int NDISC, int MAXOPP>
+template <int MODEL, int NDISC, int MAXOPP, int NPF = 0>
 __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int item, const BlockState &bs, char *lds,
                                            int *s_last) {
     const int lane = threadIdx.x & 63;
@@ -995,7 +1121,7 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
         const uint32_t k = (uint32_t)((local_tile * A.spl + r) * BLOCK + threadIdx.x);
         const bool valid = k < (uint32_t)bs.K;
         float *nz = (A.dbg_noise && valid) ? A.dbg_noise + (size_t)k * bs.N * 2 : nullptr;
-        const SampleResult res = lane_sample<MODEL, NDISC, MAXOPP>(A.P, bs, lds, A.L, valid ? k : 0u, nz);
+        const SampleResult res = lane_sample<MODEL, NDISC, MAXOPP, NPF>(A.P, bs, lds, A.L, valid ? k : 0u, nz);
         unsigned long long key;
         if (pi) {
             const float S = res.cost + A.P.w_viol * res.viol;
@@ -1128,7 +1254,7 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
 }
 
 // Sweep with one workgroup per tile.
-template <int MODEL, int NDISC, int MAXOPP>
+template <int MODEL, int NDISC, int MAXOPP, int NPF = 0>
 __global__ void __launch_bounds__(BLOCK) k_sweep(LaunchArgs A) {
     extern __shared__ __align__(16) char lds[];
     __shared__ int s_last;
@@ -1136,7 +1262,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(LaunchArgs A) {
     const int item = find_item(A.items, A.n_items, tile);
     BlockState bs;
     stage_block<NDISC>(A, item, bs, lds);
-    sweep_tile<MODEL, NDISC, MAXOPP>(A, tile, item, bs, lds, &s_last);
+    sweep_tile<MODEL, NDISC, MAXOPP, NPF>(A, tile, item, bs, lds, &s_last);
 }
 
 // Persistent sweep: a fixed grid of workgroups pulls chunks of tiles from NQ queues
@@ -1839,7 +1965,13 @@ void launch_sweep_t(const LaunchArgs &A, int grid, hipStream_t st, int *occ) {
             n = 1;
         *occ = n;
     } else if (grid == 0) {
-        hipLaunchKernelGGL((k_sweep<MODEL, NDISC, MAXOPP>), dim3(A.n_tiles), dim3(BLOCK), A.L.total, st, A);
+        // about one wave per SIMD or fewer (small games): the latency variant reads ahead
+        constexpr int LAT_WAVES = 1536;
+        if (MAXOPP <= 3 && A.n_tiles * (BLOCK / 64) <= LAT_WAVES)
+            hipLaunchKernelGGL((k_sweep<MODEL, NDISC, MAXOPP <= 3 ? MAXOPP : 3, 6>), dim3(A.n_tiles), dim3(BLOCK),
+                               A.L.total, st, A);
+        else
+            hipLaunchKernelGGL((k_sweep<MODEL, NDISC, MAXOPP>), dim3(A.n_tiles), dim3(BLOCK), A.L.total, st, A);
     } else {
         hipLaunchKernelGGL((k_sweep_persistent<MODEL, NDISC, MAXOPP>), dim3(grid), dim3(BLOCK), A.L.total, st, A);
     }
