@@ -39,6 +39,7 @@ constexpr int WIN_MAX = 1536;   // window nodes per vehicle (workspace bound)
 constexpr int PRED_STRIDE = 8;  // x, y, cos psi, sin psi, s_rel, d, -, - in the owner's frame
 constexpr int NODE_STRIDE = 10; // device node row: x, y, psi, nx, ny, wL, wR, vref, s, kappa
 constexpr unsigned long long KEY_NONE = ~0ull;
+constexpr long long LPS2_MAX_SAMPLES = 32768;  // pair variant up to 1024 waves
 constexpr int NQ = 8;
 constexpr int NCP = 4;          // re-roll chunks: each lane keeps its state at N/4, N/2, 3N/4
 constexpr int CP_FLOATS = 32;   // export slot per 64-sample group: 3 checkpoints x (6 states + segment)           // tile queues of the persistent sweep (one per XCD under round-robin dispatch)
@@ -107,6 +108,7 @@ struct LaunchArgs {
     const RaceDev *races;
     const ItemDev *items;
     int n_items, n_tiles, spl, phase;
+    int lps;               // lanes per sample (2: the pair variant of small launches)
     AgentRec *agents;
     const float4 *win;     // [slot][WIN_MAX][2]
     const float4 *xref;    // [slot][N_max]
@@ -349,6 +351,11 @@ __device__ __forceinline__ void deriv(const VehConst<typename M::T> &V, const St
     }
 }
 
+// Value of the neighbouring lane of a pair (quad permute [1, 0, 3, 2]).
+__device__ __forceinline__ float dpp_swap_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xf, 0xf, false));
+}
+
 // The dynamic model's derivative on a pair of neighbouring lanes: each lane evaluates
 // one axle (rear = odd lane) and the two forces are swapped with a DPP quad permute;
 // everything else is computed by both lanes alike.  Same values as deriv<0, MathF32>.
@@ -360,7 +367,7 @@ __device__ __forceinline__ void deriv_pair(const VehConst<float> &V, const StepC
     const float inv_vh = MathF32::rcp_(vx > V.v_eps ? vx : V.v_eps);
     const float F = tyre_force<MathF32>(V, rear ? -V.lr : V.lf, rear ? 0.0f : c.delta, rear ? V.muFzr : V.muFzf, vy,
                                         om, inv_vh);
-    const float Fo = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(F), 0xB1, 0xf, 0xf, false));
+    const float Fo = dpp_swap_f32(F);
     deriv_rates<MathF32>(V, c, vx, vy, om, cp, sp, rear ? Fo : F, rear ? F : Fo, d);
 }
 
@@ -801,9 +808,13 @@ __device__ __forceinline__ SampleResult terminal(const KParams &P, const BlockSt
 // ------------------------------------------------------------------------------
 // NPF > 0 (launches with about one wave per SIMD, where nothing hides LDS latency):
 // the raceline rows of the next NPF segments are read ahead of each step's dynamics.
-template <int MODEL, int NDISC, int MAXOPP, int NPF = 0>
+// LPS = 2 (dynamic model, launches far below one wave per SIMD): a pair of lanes runs
+// one sample; each lane draws one of the two Gaussian pairs of a Philox call and
+// evaluates one axle, the halves are swapped by DPP, and both lanes hold the same state.
+template <int MODEL, int NDISC, int MAXOPP, int NPF = 0, int LPS = 1>
 __device__ __forceinline__ SampleResult lane_sample(const KParams &P, const BlockState &bs, const char *lds,
-                                                   const LdsLayout &L, uint32_t k, float *noise_out) {
+                                                   const LdsLayout &L, uint32_t k, float *noise_out,
+                                                   bool rear = false) {
     const float2 *ubar = (const float2 *)(lds + L.ubar);
     const float4 *xref = (const float4 *)(lds + L.xref);
     const float2 *opp = (const float2 *)(lds + L.opp);
@@ -835,8 +846,15 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P, const Bloc
         float2 z;
         if ((tau & 1) == 0) {
             const uint4 r = philox4x32_10(make_uint4(k, (uint32_t)(tau >> 1), bs.ctr2, bs.ctr3), bs.key0, bs.key1);
-            z = gauss_pair(r.x, r.y);
-            zn = gauss_pair(r.z, r.w);
+            if constexpr (LPS == 2) {
+                const float2 g = gauss_pair(rear ? r.z : r.x, rear ? r.w : r.y);
+                const float2 go = make_float2(dpp_swap_f32(g.x), dpp_swap_f32(g.y));
+                z = rear ? go : g;
+                zn = rear ? g : go;
+            } else {
+                z = gauss_pair(r.x, r.y);
+                zn = gauss_pair(r.z, r.w);
+            }
         } else {
             z = zn;
         }
@@ -846,7 +864,8 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P, const Bloc
         }
         const float2 u = controls_k(P, bs, lds, L, k, tau, ub, z.x, z.y);
         const StepConst<float> sc = step_const<MODEL, MathF32>(V, u.x, u.y);
-        rk4<MODEL, MathF32>(V, sc, P.dt, st);
+        if constexpr (LPS == 2 && MODEL == 0) rk4_pair(V, sc, P.dt, st, rear);
+        else rk4<MODEL, MathF32>(V, sc, P.dt, st);
         Foot f;
         if constexpr (NPF > 0) f = project_ahead<NPF>(nodes, bs.W, P.max_moves, st[0], st[1], seg, ahead);
         else f = project(nodes, bs.W, P.max_moves, st[0], st[1], seg);
@@ -1107,9 +1126,11 @@ __device__ __forceinline__ void pi_accumulate(const KParams &P, const BlockState
 // path-integral update every tile leaves its weighted partial sums instead, and the
 // last workgroup combines them in tile order, adopts the weighted mean sequence and
 // rolls it out noise-free.
-template <int MODEL, int NDISC, int MAXOPP, int NPF = 0>
+template <int MODEL, int NDISC, int MAXOPP, int NPF = 0, int LPS = 1>
 __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int item, const BlockState &bs, char *lds,
                                            int *s_last) {
+    constexpr int G = 64 / LPS;  // samples per wave = checkpoint group
+    const bool rear = LPS == 2 && (threadIdx.x & 1);
     const int lane = threadIdx.x & 63;
     const bool pi = A.P.update == 1;
     const int t0 = A.items[item].tile0;
@@ -1118,10 +1139,12 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
     const int pstride = 2 * A.L.N_max + 2;
     PiAcc pa{INFINITY, 0.0f, 0.0f, 0.0f};
     for (int r = 0; r < A.spl; ++r) {
-        const uint32_t k = (uint32_t)((local_tile * A.spl + r) * BLOCK + threadIdx.x);
+        const uint32_t k = LPS == 1 ? (uint32_t)((local_tile * A.spl + r) * BLOCK + threadIdx.x)
+                                    : (uint32_t)(local_tile * (BLOCK / 2) + (threadIdx.x >> 1));
         const bool valid = k < (uint32_t)bs.K;
-        float *nz = (A.dbg_noise && valid) ? A.dbg_noise + (size_t)k * bs.N * 2 : nullptr;
-        const SampleResult res = lane_sample<MODEL, NDISC, MAXOPP, NPF>(A.P, bs, lds, A.L, valid ? k : 0u, nz);
+        float *nz = (A.dbg_noise && valid && !rear) ? A.dbg_noise + (size_t)k * bs.N * 2 : nullptr;
+        const SampleResult res =
+            lane_sample<MODEL, NDISC, MAXOPP, NPF, LPS>(A.P, bs, lds, A.L, valid ? k : 0u, nz, rear);
         unsigned long long key;
         if (pi) {
             const float S = res.cost + A.P.w_viol * res.viol;
@@ -1130,7 +1153,7 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
             key = valid ? make_key(res.h, res.h ? res.cost : res.viol, k) : KEY_NONE;
         }
         const unsigned long long wmin = wave_min_u64(key);
-        const unsigned long long feas = __ballot(valid && res.h);
+        const unsigned long long feas = __ballot(valid && res.h && !rear);
         if (lane == 0) {
             if (wmin != KEY_NONE) atomicMin(A.keys + bs.slot, wmin);
             const int cnt = __popcll(feas);
@@ -1138,14 +1161,14 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
         }
         if (pi) {
             pi_accumulate(A.P, bs, lds, A.L, valid ? k : 0u, valid, res, pa);
-        } else if (A.cp_slots && valid && key == wmin) {  // the wave's best sample keeps its checkpoints
-            float *slot = A.cp_slots + ((size_t)A.items[item].group0 + k / 64) * CP_FLOATS;
+        } else if (A.cp_slots && valid && key == wmin && !rear) {  // the wave's best sample keeps its checkpoints
+            float *slot = A.cp_slots + ((size_t)A.items[item].group0 + k / G) * CP_FLOATS;
 #pragma unroll
             for (int c = 0; c < NCP - 1; ++c)
 #pragma unroll
                 for (int i = 0; i < 7; ++i) slot[7 * c + i] = res.cp[c][i];
         }
-        if (valid) {
+        if (valid && !rear) {
             if (A.dbg_cost) A.dbg_cost[k] = res.cost;
             if (A.dbg_viol) A.dbg_viol[k] = res.viol;
             if (A.dbg_flags) A.dbg_flags[k] = res.flags;
@@ -1233,7 +1256,7 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
         __syncthreads();
         reroll_block<MODEL, NDISC, MAXOPP, NOMINAL>(A.P, A.L, bs, lds, rec, 0u, out);
     } else {
-        const float *cps = A.cp_slots ? A.cp_slots + ((size_t)it.group0 + k / 64) * CP_FLOATS : nullptr;
+        const float *cps = A.cp_slots ? A.cp_slots + ((size_t)it.group0 + k / G) * CP_FLOATS : nullptr;
         res = reroll_block<MODEL, NDISC, MAXOPP, WINNER>(A.P, A.L, bs, lds, rec, k, out, cps);
     }
     if (threadIdx.x == 0) {
@@ -1254,7 +1277,7 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
 }
 
 // Sweep with one workgroup per tile.
-template <int MODEL, int NDISC, int MAXOPP, int NPF = 0>
+template <int MODEL, int NDISC, int MAXOPP, int NPF = 0, int LPS = 1>
 __global__ void __launch_bounds__(BLOCK) k_sweep(LaunchArgs A) {
     extern __shared__ __align__(16) char lds[];
     __shared__ int s_last;
@@ -1262,7 +1285,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(LaunchArgs A) {
     const int item = find_item(A.items, A.n_items, tile);
     BlockState bs;
     stage_block<NDISC>(A, item, bs, lds);
-    sweep_tile<MODEL, NDISC, MAXOPP, NPF>(A, tile, item, bs, lds, &s_last);
+    sweep_tile<MODEL, NDISC, MAXOPP, NPF, LPS>(A, tile, item, bs, lds, &s_last);
 }
 
 // Persistent sweep: a fixed grid of workgroups pulls chunks of tiles from NQ queues
@@ -1571,6 +1594,22 @@ constexpr int FEAT_CURV = 20;
 constexpr double FEAT_CURV_DS = 5.0;
 constexpr float MLP_A_SCALE = 4.0f, MLP_D_SCALE = 0.2f, MLP_LS_MIN = -4.0f, MLP_LS_MAX = 1.0f;
 
+// Unwrapped arc length and curvature of node i (laps add the track length).
+__device__ __forceinline__ void node_s_kappa(const TrackDev &T, long long i, double &s, double &kappa) {
+    const long long n = T.n;
+    long long lap = 0, b = i;
+    if (T.closed) {
+        lap = i / n;
+        if (i - lap * n < 0) --lap;
+        b = i - lap * n;
+    } else {
+        b = i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+    }
+    const double *r = T.nodes + (size_t)b * NODE_STRIDE;
+    s = r[8] + (double)lap * T.length;
+    kappa = r[9];
+}
+
 __device__ void node_row(const TrackDev &T, long long i, double *o) {  // unwrapped node access
     const long long n = T.n;
     long long lap = 0, b = i;
@@ -1588,62 +1627,77 @@ __device__ void node_row(const TrackDev &T, long long i, double *o) {  // unwrap
     o[8] += (double)lap * T.length;
 }
 
-// One thread per vehicle: ego (6), 4 nearest opponents by |s_j - s_i| (6 each, zero when
-// absent), curvature 5..100 m ahead (20); same definitions as the oracle's features.
-__global__ void k_features(LaunchArgs A, float *X) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// One 64-thread block per vehicle: thread 0 writes the ego (6) and the 4 nearest
+// opponents by |s_j - s_i| (6 each, zero when absent); threads 1..20 the curvature
+// 5..100 m ahead (20), each locating its segment (the one whose node arc lengths
+// bracket the query) by bisection.  Same definitions as the oracle's features.
+__global__ void __launch_bounds__(64) k_features(LaunchArgs A, float *X) {
+    const int i = blockIdx.x;
     if (i >= A.n_items) return;
+    const int tid = threadIdx.x;
     const ItemDev it = A.items[i];
     const RaceDev R = A.races[it.race];
     const AgentRec me = A.agents[it.slot];
     const TrackDev T = A.tracks[R.track];
     const double *xi = R.x + (size_t)it.agent * 6;
     float *f = X + (size_t)it.slot * FEAT_DIM;
-    for (int c = 0; c < FEAT_DIM; ++c) f[c] = 0.0f;
-    f[0] = (float)(me.d0 / me.half_w);
-    f[1] = (float)remainder(xi[2] - me.psi_ref, 6.283185307179586);
-    f[2] = (float)(xi[3] / 30.0);
-    f[3] = (float)(xi[4] / 5.0);
-    f[4] = (float)xi[5];
-    f[5] = (float)((xi[3] - me.v_ref) / 10.0);
-    unsigned used = 0;
-    for (int m = 0; m < FEAT_OPP; ++m) {
-        int best = -1;
-        double bd = INFINITY;
-        for (int j = 0; j < R.n_agents; ++j) {
-            if (j == it.agent || (used >> j) & 1u) continue;
-            const double dd = fabs(A.agents[R.slot0 + j].s_abs - me.s_abs);
-            if (dd < bd) {
-                bd = dd;
-                best = j;
+    if (tid == 0) {
+        for (int c = 0; c < 6 + 6 * FEAT_OPP; ++c) f[c] = 0.0f;
+        f[0] = (float)(me.d0 / me.half_w);
+        f[1] = (float)remainder(xi[2] - me.psi_ref, 6.283185307179586);
+        f[2] = (float)(xi[3] / 30.0);
+        f[3] = (float)(xi[4] / 5.0);
+        f[4] = (float)xi[5];
+        f[5] = (float)((xi[3] - me.v_ref) / 10.0);
+        unsigned used = 0;
+        for (int m = 0; m < FEAT_OPP; ++m) {
+            int best = -1;
+            double bd = INFINITY;
+            for (int j = 0; j < R.n_agents; ++j) {
+                if (j == it.agent || (used >> j) & 1u) continue;
+                const double dd = fabs(A.agents[R.slot0 + j].s_abs - me.s_abs);
+                if (dd < bd) {
+                    bd = dd;
+                    best = j;
+                }
             }
+            if (best < 0) break;
+            used |= 1u << best;
+            const AgentRec o = A.agents[R.slot0 + best];
+            const double *xj = R.x + (size_t)best * 6;
+            float *g = f + 6 + 6 * m;
+            g[0] = (float)((o.s_abs - me.s_abs) / 20.0);
+            g[1] = (float)((o.d0 - me.d0) / me.half_w);
+            g[2] = (float)remainder(xj[2] - xi[2], 6.283185307179586);
+            g[3] = (float)((xj[3] - xi[3]) / 10.0);
+            g[4] = (float)(xj[4] / 5.0);
+            g[5] = 1.0f;
         }
-        if (best < 0) break;
-        used |= 1u << best;
-        const AgentRec o = A.agents[R.slot0 + best];
-        const double *xj = R.x + (size_t)best * 6;
-        float *g = f + 6 + 6 * m;
-        g[0] = (float)((o.s_abs - me.s_abs) / 20.0);
-        g[1] = (float)((o.d0 - me.d0) / me.half_w);
-        g[2] = (float)remainder(xj[2] - xi[2], 6.283185307179586);
-        g[3] = (float)((xj[3] - xi[3]) / 10.0);
-        g[4] = (float)(xj[4] / 5.0);
-        g[5] = 1.0f;
-    }
-    long long h = me.seg_abs;
-    for (int m = 1; m <= FEAT_CURV; ++m) {
-        const double sq = me.s_abs + FEAT_CURV_DS * m;
-        double a[NODE_STRIDE], b[NODE_STRIDE];
-        for (int guard = 0; guard < 1 << 20; ++guard) {
-            node_row(T, h, a);
-            node_row(T, h + 1, b);
-            if (sq < a[8] && (T.closed || h > 0)) { --h; continue; }
-            if (sq >= b[8] && (T.closed || h + 1 <= T.n - 2)) { ++h; continue; }
-            break;
+    } else if (tid <= FEAT_CURV) {
+        const double sq = me.s_abs + FEAT_CURV_DS * tid;
+        // bracket: the vehicle's segment up to its index plus the reach over the shortest segment
+        long long lo = me.seg_abs;
+        long long hi = lo + (long long)ceil(FEAT_CURV_DS * FEAT_CURV / T.ds_min) + 2;
+        if (!T.closed) {
+            lo = lo < 0 ? 0 : (lo > T.n - 2 ? T.n - 2 : lo);
+            hi = hi > T.n - 2 ? T.n - 2 : hi;
         }
-        double t = (sq - a[8]) / (b[8] - a[8]);
+        double s_lo, k_lo;
+        node_s_kappa(T, lo, s_lo, k_lo);
+        // largest h in [lo, hi] with s(h) <= sq (lo itself when sq < s(lo))
+        while (lo < hi) {
+            const long long mid = (lo + hi + 1) >> 1;
+            double s_m, k_m;
+            node_s_kappa(T, mid, s_m, k_m);
+            if (s_m <= sq) lo = mid;
+            else hi = mid - 1;
+        }
+        double sa, ka, sb, kb;
+        node_s_kappa(T, lo, sa, ka);
+        node_s_kappa(T, lo + 1, sb, kb);
+        double t = (sq - sa) / (sb - sa);
         t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-        f[6 + 6 * FEAT_OPP + m - 1] = (float)(20.0 * (a[9] + t * (b[9] - a[9])));
+        f[6 + 6 * FEAT_OPP + tid - 1] = (float)(20.0 * (ka + t * (kb - ka)));
     }
 }
 
@@ -1822,12 +1876,27 @@ struct Plan {  // host image of one launch sequence's descriptors
     std::vector<ItemDev> all, ego, one;
     int N_max = 0, n_opp_max = 0, w_max = 0, agents_total = 0;
     int tiles_all = 0, tiles_ego = 0;
+    int lps = 1;          // lanes per sample
+    int tile_samples = 0;  // samples per tile: BLOCK x samples per lane / lanes per sample
 };
 
 int build_plan(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_races, int spl, Plan &pl,
                int one_agent = -1) {
     if (!races || n_races < 1) return fail(c, SGTP_EINVAL, "no races");
     if (n_races > c->max_races) return fail(c, SGTP_ESHAPE, "n_races exceeds the context");
+    // lanes per sample: the pair variant when the launch stays well below one wave per SIMD
+    // (dynamic model, feasibility selection, at most 3 opponents, one sample per lane)
+    {
+        long long samples = 0;
+        int nopp = 0;
+        for (int r = 0; r < n_races; ++r) {
+            samples += (long long)std::max(races[r].K, 0) * std::max(races[r].n_agents, 0);
+            nopp = std::max(nopp, races[r].n_agents - 1);
+        }
+        pl.lps = (spl == 1 && p->model == 0 && p->update == 0 && nopp <= 3 && samples <= LPS2_MAX_SAMPLES) ? 2 : 1;
+        pl.tile_samples = BLOCK * spl / pl.lps;
+    }
+    const int gsz = 64 / pl.lps;  // samples per wave = checkpoint group
     int slot = 0;
     long long group_total = 0;
     double wneed = 0;
@@ -1852,8 +1921,8 @@ int build_plan(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_
         if (p->update == 1 && s.prop && s.K_prop > 0)
             return fail(c, SGTP_EINVAL, "a learned proposal cannot be combined with the path-integral update");
         pl.races.push_back(d);
-        const int tiles = (s.K + BLOCK * spl - 1) / (BLOCK * spl);
-        const long long groups = (s.K + 63) / 64;
+        const int tiles = (s.K + pl.tile_samples - 1) / pl.tile_samples;
+        const long long groups = (s.K + gsz - 1) / gsz;
         for (int i = 0; i < s.n_agents; ++i) {
             ItemDev it{r, i, slot + i, pl.tiles_all, (int)(group_total + i * groups), 0};
             pl.tiles_all += tiles;
@@ -1881,7 +1950,7 @@ int build_plan(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_
         wneed = std::max(wneed, WIN_BACK + std::ceil(T.inner_factor * reach / T.ds_min) + 8.0);
     }
     if (slot > c->max_agents) return fail(c, SGTP_ESHAPE, "total vehicles exceed the context");
-    if (group_total > c->max_groups) return fail(c, SGTP_ESHAPE, "total samples exceed the context (max_K)");
+    if (group_total > c->max_groups * pl.lps) return fail(c, SGTP_ESHAPE, "total samples exceed the context (max_K)");
     if (p->update == 1 && (long long)pl.tiles_all > c->pi_tiles)
         return fail(c, SGTP_ESHAPE, "tiles exceed the path-integral buffer");
     pl.agents_total = slot;
@@ -1967,7 +2036,10 @@ void launch_sweep_t(const LaunchArgs &A, int grid, hipStream_t st, int *occ) {
     } else if (grid == 0) {
         // about one wave per SIMD or fewer (small games): the latency variant reads ahead
         constexpr int LAT_WAVES = 1536;
-        if (MAXOPP <= 3 && A.n_tiles * (BLOCK / 64) <= LAT_WAVES)
+        if (MODEL == 0 && MAXOPP <= 3 && A.lps == 2)
+            hipLaunchKernelGGL((k_sweep<0, NDISC, MAXOPP <= 3 ? MAXOPP : 3, 6, 2>), dim3(A.n_tiles), dim3(BLOCK),
+                               A.L.total, st, A);
+        else if (MAXOPP <= 3 && A.n_tiles * (BLOCK / 64) <= LAT_WAVES)
             hipLaunchKernelGGL((k_sweep<MODEL, NDISC, MAXOPP <= 3 ? MAXOPP : 3, 6>), dim3(A.n_tiles), dim3(BLOCK),
                                A.L.total, st, A);
         else
@@ -1999,7 +2071,7 @@ void dispatch_sweep(int model, int ndisc, int mo, const LaunchArgs &A, hipStream
 // Order the items of a sweep for the persistent kernel: vehicles go to NQ queues
 // by longest-processing-time first (work = K N), each queue is a contiguous run of
 // tiles, heaviest vehicles first inside a queue.
-void layout_queues(const Plan &pl, std::vector<ItemDev> &items, int spl, int q_begin[NQ], int q_len[NQ]) {
+void layout_queues(const Plan &pl, std::vector<ItemDev> &items, int q_begin[NQ], int q_len[NQ]) {
     std::vector<int> order(items.size());
     for (size_t i = 0; i < items.size(); ++i) order[i] = (int)i;
     auto work = [&](const ItemDev &it) {
@@ -2025,7 +2097,7 @@ void layout_queues(const Plan &pl, std::vector<ItemDev> &items, int spl, int q_b
             ItemDev it = items[i];
             it.tile0 = tile;
             const RaceDev &r = pl.races[it.race];
-            tile += (r.K + BLOCK * spl - 1) / (BLOCK * spl);
+            tile += (r.K + pl.tile_samples - 1) / pl.tile_samples;
             out.push_back(it);
         }
         q_len[q] = tile - q_begin[q];
@@ -2065,6 +2137,7 @@ struct Runner {
         A.cp_slots = c->d_cp;
     A.pi_part = c->d_pi;
         A.spl = 1;
+        A.lps = pl.lps;
         return SGTP_OK;
     }
     // projection, frames, windows, references, initial predictions (into pred[0])
@@ -2161,7 +2234,7 @@ int plan_enqueue(sgtp_plan *P, hipStream_t st) {
     HIPCHK(c, hipGetLastError());
     const int nt = P->pl.agents_total;
     if (P->mlp) {  // learned proposal: features -> network -> tables, before the first sweep
-        hipLaunchKernelGGL(k_features, dim3((a.n_items + 63) / 64), dim3(64), 0, st, a, P->d_feat);
+        hipLaunchKernelGGL(k_features, dim3(a.n_items), dim3(64), 0, st, a, P->d_feat);
         HIPCHK(c, hipGetLastError());
         const int mrc = sgtp_mlp_forward(P->mlp, P->d_feat, nt, P->d_mlp_out, SGTP_MLP_OUT, st);
         if (mrc) return fail(c, mrc, std::string("proposal network: ") + sgtp_mlp_last_error(P->mlp));
@@ -2277,7 +2350,7 @@ int sgtp_ctx_create(sgtp_ctx **out, int max_agents_total, int max_N, int max_rac
     al((void **)&c->d_nfeas, sizeof(int) * max_agents_total);
     al((void **)&c->d_counters, sizeof(int) * max_agents_total);
     c->max_groups = (long long)max_agents_total * ((max_K + 63) / 64);
-    al((void **)&c->d_cp, sizeof(float) * CP_FLOATS * (size_t)c->max_groups);
+    al((void **)&c->d_cp, sizeof(float) * CP_FLOATS * 2 * (size_t)c->max_groups);  // 2: pair variant groups of 32
     c->desc_bytes = ((sizeof(RaceDev) * max_races + 255) & ~size_t(255)) +
                     3 * ((sizeof(ItemDev) * max_agents_total + 255) & ~size_t(255)) + 256;
     al((void **)&c->d_desc, c->desc_bytes * sgtp_ctx::RING);
@@ -2387,7 +2460,7 @@ int sgtp_rollout_cost(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *race, 
     dbg.dbg_viol = viol;
     dbg.dbg_xfinal = x_final;
     dbg.dbg_noise = noise;
-    const int tiles = (race->K + BLOCK - 1) / BLOCK;
+    const int tiles = (race->K + r.pl.tile_samples - 1) / r.pl.tile_samples;
     return r.sweep(r.d_one, r.pl.one, tiles, phase, 0, out, r.pl.all[agent].slot, 0, 0, nullptr, &dbg);
 }
 
@@ -2484,8 +2557,9 @@ int sgtp_plan_create(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, 
         delete P;
         return rc;
     }
-    layout_queues(P->pl, P->pl.all, o.samples_per_lane, P->qb_all, P->ql_all);
-    layout_queues(P->pl, P->pl.ego, o.samples_per_lane, P->qb_ego, P->ql_ego);
+    if (P->pl.lps == 2) P->opt.persistent = o.persistent = 0;  // the pair variant runs one workgroup per tile
+    layout_queues(P->pl, P->pl.all, P->qb_all, P->ql_all);
+    layout_queues(P->pl, P->pl.ego, P->qb_ego, P->ql_ego);
     P->pl.tiles_all = P->ql_all[NQ - 1] + P->qb_all[NQ - 1];
     P->pl.tiles_ego = P->ql_ego[NQ - 1] + P->qb_ego[NQ - 1];
     P->mo = maxopp_bucket(P->pl.n_opp_max);
@@ -2525,6 +2599,7 @@ int sgtp_plan_create(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, 
     A.cp_slots = c->d_cp;
     A.pi_part = c->d_pi;
     A.spl = o.samples_per_lane;
+    A.lps = P->pl.lps;
     A.chunk = o.tiles_per_fetch;
     if (o.persistent) {
         int occ = 1, dev = 0, cus = 0;
@@ -2715,7 +2790,7 @@ int sgtp_features(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int
     LaunchArgs a = r.A;
     a.items = r.d_all;
     a.n_items = (int)r.pl.all.size();
-    hipLaunchKernelGGL(k_features, dim3((a.n_items + 63) / 64), dim3(64), 0, r.st, a, X);
+    hipLaunchKernelGGL(k_features, dim3(a.n_items), dim3(64), 0, r.st, a, X);
     HIPCHK(c, hipGetLastError());
     return SGTP_OK;
 }

@@ -236,3 +236,15 @@ def test_argument_errors(planner):
     big.N = 65
     with pytest.raises(RuntimeError, match="EINVAL|ESHAPE"):
         planner.rollout_cost(params, big, 0, 1)
+
+
+@pytest.mark.parametrize("name,agent", [("c1", 0), ("c2", 1)])
+def test_pair_variant_matches_one_lane_variant(planner, name, agent):
+    """Small launches run each sample on a pair of lanes (one axle and one Gaussian pair
+    each); the same samples of a large launch run on one lane.  Both must give the same
+    bits for every per-sample output."""
+    tr, race, params, _, w = PY.workload(name)
+    small = PY.gpu_rollout(planner, params, PY.build(planner, tr, race, params, 2048), agent, 1, want_noise=True)
+    large = PY.gpu_rollout(planner, params, PY.build(planner, tr, race, params, 40000), agent, 1, want_noise=True)
+    for nm in ("cost", "viol", "flags", "x_final", "noise"):
+        assert np.array_equal(small[nm].view(np.uint8), large[nm][:2048].view(np.uint8)), nm
