@@ -33,6 +33,7 @@ constexpr int D_OUT = SGTP_MLP_OUT;  // 200 outputs
 constexpr int D_OUTP = 256;          // padded output width
 constexpr int N_H = SGTP_MLP_OUT / 4;
 constexpr float A_SCALE = 4.0f, D_SCALE = 0.2f, LS_MIN = -4.0f, LS_MAX = 1.0f;
+constexpr int FUSED_MAX_ROWS = 4096;  // forward batches up to this size use the fused kernel
 
 // packed float32 parameter layout (the oracle's): W1[50][256] b1 W2[256][256] b2 W3[256][200] b3
 constexpr size_t P_W1 = 0, P_B1 = P_W1 + (size_t)D_IN * D_H, P_W2 = P_B1 + D_H, P_B2 = P_W2 + (size_t)D_H * D_H,
@@ -152,6 +153,85 @@ __global__ void k_refresh_bf16(const float *P, bf16 *W1, bf16 *W2, bf16 *W3, flo
     if (e < D_OUTP) b3p[e] = (e < D_OUT) ? P[P_B3 + e] : 0.0f;
 }
 
+// Transposed BF16 copies for the fused small-batch forward: W1T [256][64] (k >= 50 zero),
+// W2T [256][256], W3T [256][256] (rows n >= 200 zero); row n holds the weights into unit n.
+__global__ void k_refresh_bf16_t(const float *P, bf16 *W1T, bf16 *W2T, bf16 *W3T) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < D_H * D_INP) {
+        const int n = e / D_INP, k = e % D_INP;
+        W1T[e] = (k < D_IN) ? (bf16)P[P_W1 + (size_t)k * D_H + n] : (bf16)0.0f;
+    }
+    if (e < D_H * D_H) {
+        const int n = e / D_H, k = e % D_H;
+        W2T[e] = (bf16)P[P_W2 + (size_t)k * D_H + n];
+        W3T[e] = (n < D_OUT) ? (bf16)P[P_W3 + (size_t)k * D_OUT + n] : (bf16)0.0f;
+    }
+}
+
+// One 16 x (K) x (16 j .. 16 j + 15) product step of the fused forward: A rows from LDS,
+// B fragments from the transposed weights; same lane -> (row, k) map and k order as
+// k_gemm_bf16, so the sums are the same.
+__device__ __forceinline__ f32x4 mfma_rows16(const bf16 *A, int lda, const bf16 *WT, int K, int n0, int l) {
+    f32x4 acc = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        const int kk = k0 + 8 * (l >> 4);
+        const bf16x8 a = *(const bf16x8 *)&A[(l & 15) * lda + kk];
+        const bf16x8 b = *(const bf16x8 *)&WT[(size_t)(n0 + (l & 15)) * K + kk];
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// Fused forward of 16 rows per workgroup (batches of planning size): the three layers run
+// back to back with the hidden activations in LDS (BF16, as the tiled path stores them).
+__global__ void __launch_bounds__(256) k_mlp_fwd16(const float *X, int ldx, int B, const bf16 *W1T, const bf16 *W2T,
+                                                  const bf16 *W3T, const float *b1, const float *b2,
+                                                  const float *b3, float *out, int ldo, int n_out) {
+    constexpr int LX = D_INP + 8, LH = D_H + 8;  // padded rows (16-byte aligned)
+    __shared__ __align__(16) bf16 xs[16 * LX];
+    __shared__ __align__(16) bf16 h1[16 * LH];
+    __shared__ __align__(16) bf16 h2[16 * LH];
+    const int r0 = blockIdx.x * 16, tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    for (int e = tid; e < 16 * D_INP; e += 256) {
+        const int r = e / D_INP, c = e % D_INP;
+        xs[r * LX + c] = (r0 + r < B && c < D_IN) ? (bf16)X[(long long)(r0 + r) * ldx + c] : (bf16)0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {  // layer 1: each wave 4 column tiles of 16
+        const int n0 = 16 * (4 * w + jj);
+        const f32x4 acc = mfma_rows16(xs, LX, W1T, D_INP, n0, l);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 4 * (l >> 4) + v, col = n0 + (l & 15);
+            h1[row * LH + col] = (bf16)gelu_f(acc[v] + b1[col]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {  // layer 2
+        const int n0 = 16 * (4 * w + jj);
+        const f32x4 acc = mfma_rows16(h1, LH, W2T, D_H, n0, l);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 4 * (l >> 4) + v, col = n0 + (l & 15);
+            h2[row * LH + col] = (bf16)gelu_f(acc[v] + b2[col]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {  // layer 3 (columns >= n_out dropped)
+        const int n0 = 16 * (4 * w + jj);
+        if (n0 >= n_out) continue;
+        const f32x4 acc = mfma_rows16(h2, LH, W3T, D_H, n0, l);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 4 * (l >> 4) + v, col = n0 + (l & 15);
+            if (r0 + row < B && col < n_out) out[(long long)(r0 + row) * ldo + col] = acc[v] + b3[col];
+        }
+    }
+}
+
 // Gaussian negative log-likelihood of the targets U[B][N][2] (mean over rows, constant
 // 0.5 log 2 pi dropped; steps t >= N do not enter) and its gradient w.r.t. the outputs,
 // as BF16 for the products.  One thread per (row, step < 64, channel).
@@ -229,6 +309,7 @@ struct sgtp_mlp {
     std::string err;
     float *P = nullptr, *G = nullptr, *Mm = nullptr, *Vv = nullptr;  // packed float32
     bf16 *W1 = nullptr, *W2 = nullptr, *W3 = nullptr;              // BF16 operands
+    bf16 *W1T = nullptr, *W2T = nullptr, *W3T = nullptr;           // transposed (fused forward)
     float *b3p = nullptr;
     bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *D = nullptr, *D1 = nullptr;
     float *PRE1 = nullptr, *PRE2 = nullptr, *OUT = nullptr, *DH = nullptr, *GW = nullptr, *loss = nullptr;
@@ -291,6 +372,9 @@ int sgtp_mlp_create(int B_max, sgtp_mlp **out) {
     al((void **)&m->W2, (size_t)D_H * D_H * 2);
     al((void **)&m->W3, (size_t)D_H * D_OUTP * 2);
     al((void **)&m->b3p, D_OUTP * 4);
+    al((void **)&m->W1T, (size_t)D_H * D_INP * 2);
+    al((void **)&m->W2T, (size_t)D_H * D_H * 2);
+    al((void **)&m->W3T, (size_t)D_H * D_H * 2);
     al((void **)&m->X, (size_t)B_max * D_INP * 2);
     al((void **)&m->H1, (size_t)B_max * D_H * 2);
     al((void **)&m->H2, (size_t)B_max * D_H * 2);
@@ -313,8 +397,8 @@ int sgtp_mlp_create(int B_max, sgtp_mlp **out) {
 int sgtp_mlp_destroy(sgtp_mlp *m) {
     if (!m) return SGTP_EINVAL;
     (void)hipDeviceSynchronize();
-    void *bufs[] = {m->P, m->G, m->Mm, m->Vv, m->W1, m->W2, m->W3, m->b3p, m->X, m->H1, m->H2,
-                    m->D, m->D1, m->PRE1, m->PRE2, m->OUT, m->DH, m->GW, m->loss};
+    void *bufs[] = {m->P,  m->G,  m->Mm, m->Vv,   m->W1,   m->W2,  m->W3, m->b3p, m->X,    m->H1,   m->H2,
+                    m->D,  m->D1, m->PRE1, m->PRE2, m->OUT, m->DH, m->GW,  m->loss, m->W1T, m->W2T, m->W3T};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete m;
@@ -335,6 +419,8 @@ int sgtp_mlp_set_params(sgtp_mlp *m, const float *host) {
     m->adam_t = 0;
     hipLaunchKernelGGL(k_refresh_bf16, dim3((D_H * D_OUTP + 255) / 256), dim3(256), 0, nullptr, m->P, m->W1, m->W2,
                        m->W3, m->b3p);
+    hipLaunchKernelGGL(k_refresh_bf16_t, dim3((D_H * D_H + 255) / 256), dim3(256), 0, nullptr, m->P, m->W1T, m->W2T,
+                       m->W3T);
     MCHK(m, hipGetLastError());
     MCHK(m, hipDeviceSynchronize());
     return SGTP_OK;
@@ -351,7 +437,14 @@ int sgtp_mlp_forward(sgtp_mlp *m, const float *X, int B, float *out, int ld_out,
     if (!m || !X || !out) return SGTP_EINVAL;
     if (B < 1 || B > m->B_max) return mfail(m, SGTP_ESHAPE, "batch larger than the network workspace");
     if (ld_out < D_OUT) return mfail(m, SGTP_EINVAL, "ld_out < 200");
-    return forward(m, X, D_IN, B, out, ld_out, D_OUT, (hipStream_t)stream);
+    hipStream_t st = (hipStream_t)stream;
+    if (B <= FUSED_MAX_ROWS) {  // planning-size batches: one fused kernel
+        hipLaunchKernelGGL(k_mlp_fwd16, dim3((B + 15) / 16), dim3(256), 0, st, X, D_IN, B, m->W1T, m->W2T, m->W3T,
+                           m->P + P_B1, m->P + P_B2, m->P + P_B3, out, ld_out, D_OUT);
+        MCHK(m, hipGetLastError());
+        return SGTP_OK;
+    }
+    return forward(m, X, D_IN, B, out, ld_out, D_OUT, st);
 }
 
 int sgtp_mlp_grad(sgtp_mlp *m, const float *X, const float *U, int B, int N, float sig_a, float sig_d, float *loss,
@@ -398,6 +491,8 @@ int sgtp_mlp_adam(sgtp_mlp *m, float lr, float beta1, float beta2, float eps, vo
                        lr, beta1, beta2, eps, bc1, bc2);
     hipLaunchKernelGGL(k_refresh_bf16, dim3((D_H * D_OUTP + 255) / 256), dim3(256), 0, st, m->P, m->W1, m->W2, m->W3,
                        m->b3p);
+    hipLaunchKernelGGL(k_refresh_bf16_t, dim3((D_H * D_H + 255) / 256), dim3(256), 0, st, m->P, m->W1T, m->W2T,
+                       m->W3T);
     MCHK(m, hipGetLastError());
     return SGTP_OK;
 }

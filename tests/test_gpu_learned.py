@@ -319,3 +319,18 @@ def test_proposal_inside_plan_matches_separate_calls(big_planner, trained):
             assert torch.equal(ra.x, rb.x) and torch.equal(ra.u_nom, rb.u_nom)
     pa.close()
     pb.close()
+
+
+def test_fused_small_batch_forward_matches_tiled_products():
+    """Planning-size batches run the three layers in one kernel; larger batches use the
+    tiled products.  Same lane-to-k map and k order: the outputs agree bit for bit."""
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    flat, _ = _net(seed=21, scale3=3.0)
+    m = sg.Mlp(8192, flat)
+    X = torch.as_tensor(np.random.default_rng(3).standard_normal((5000, 50)).astype(np.float32)).cuda()
+    big = m.forward(X)             # tiled path (more than 4096 rows)
+    small = m.forward(X[:37].contiguous())  # fused path, ragged row tile
+    torch.cuda.synchronize()
+    assert np.array_equal(small.cpu().numpy().view(np.uint32), big[:37].cpu().numpy().view(np.uint32))
+    m.close()

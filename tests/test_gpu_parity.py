@@ -238,13 +238,20 @@ def test_argument_errors(planner):
         planner.rollout_cost(params, big, 0, 1)
 
 
-@pytest.mark.parametrize("name,agent", [("c1", 0), ("c2", 1)])
-def test_pair_variant_matches_one_lane_variant(planner, name, agent):
+@pytest.mark.parametrize("name,agent,K,N", [("c1", 0, 2048, None), ("c2", 1, 2048, None), ("c2", 2, 777, None),
+                                            ("c1", 1, 1001, 21)])
+def test_pair_variant_matches_one_lane_variant(planner, name, agent, K, N):
     """Small launches run each sample on a pair of lanes (one axle and one Gaussian pair
     each); the same samples of a large launch run on one lane.  Both must give the same
-    bits for every per-sample output."""
+    bits for every per-sample output (ragged K and an odd horizon included)."""
     tr, race, params, _, w = PY.workload(name)
-    small = PY.gpu_rollout(planner, params, PY.build(planner, tr, race, params, 2048), agent, 1, want_noise=True)
+    if N is not None:
+        race = inputs.make_race(tr, race.x.shape[0], N, 10.0, False, 3000, 2000)
+        params = dict(params, N=N, n_tail=inputs.n_tail_from_fraction(0.3, N))
+    small = PY.gpu_rollout(planner, params, PY.build(planner, tr, race, params, K), agent, 1, want_noise=True)
     large = PY.gpu_rollout(planner, params, PY.build(planner, tr, race, params, 40000), agent, 1, want_noise=True)
     for nm in ("cost", "viol", "flags", "x_final", "noise"):
-        assert np.array_equal(small[nm].view(np.uint8), large[nm][:2048].view(np.uint8)), nm
+        assert np.array_equal(small[nm].view(np.uint8), large[nm][:K].view(np.uint8)), nm
+    # the selection over the first K samples: the small launch's choice is its own argmin
+    r = PY.oracle_for(tr, params).rollout_cost(race, agent, 1, K)
+    PY.check_choice(small["choice"], r, params, f"{name} pair variant")
