@@ -46,10 +46,12 @@ class Params(C.Structure):
         ("B", C.c_double), ("C", C.c_double), ("mu", C.c_double), ("g", C.c_double), ("v_eps", C.c_double),
         ("max_moves", C.c_int), ("pad0", C.c_int),
         ("update", C.c_int), ("pad1", C.c_int), ("mppi_lambda", C.c_double), ("mppi_w_viol", C.c_double),
+        ("pred_sig_lon", C.c_double), ("pred_sig_lat", C.c_double),
     ]
 
-# parameters with a default (the path-integral ablation is off unless asked for)
-PARAM_DEFAULTS = {"update": 0, "mppi_lambda": 1.0, "mppi_w_viol": 0.0}
+# parameters with a default (the path-integral ablation and the prediction perturbation
+# are off unless asked for)
+PARAM_DEFAULTS = {"update": 0, "mppi_lambda": 1.0, "mppi_w_viol": 0.0, "pred_sig_lon": 0.0, "pred_sig_lat": 0.0}
 
 
 class TrackS(C.Structure):
@@ -135,6 +137,8 @@ def load(rebuild: bool = False):
         lib.ref_features.argtypes = [P(TrackS), P(Params), P(RaceS), P(C.c_double)]
         lib.ref_mlp_forward.argtypes = [P(Mlp), C.c_int, P(C.c_double), P(C.c_double), P(C.c_double),
                                         P(C.c_double), P(C.c_double), P(C.c_double)]
+        lib.ref_perturb_prediction.argtypes = [P(Params), C.c_ulonglong, C.c_uint, C.c_int, C.c_int, C.c_int,
+                                               C.c_int, P(C.c_double)]
         lib.ref_mlp_proposal.argtypes = [P(C.c_double), C.c_int, C.c_double, C.c_double, P(C.c_double),
                                          P(C.c_double)]
         lib.ref_mlp_nll.argtypes = [P(C.c_double), C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
@@ -342,6 +346,13 @@ class Oracle:
             raise RuntimeError(f"ref_best_response failed: {rc}")
         out["choice"] = _choice_dict(ch)
         out["U"] = U
+        return out
+
+    def perturb_prediction(self, traj, seed, plan_step, observer, phase, j):
+        """Copy of a [N+1][8] world prediction with the perturbation of the given view."""
+        out = np.ascontiguousarray(traj, np.float64).copy()
+        self.lib.ref_perturb_prediction(C.byref(self.P), int(seed), int(plan_step), int(observer), int(phase),
+                                        int(j), out.shape[0] - 1, _dp(out))
         return out
 
     def plan_step(self, race, L_ibr, K=None, forced=None, **kw):

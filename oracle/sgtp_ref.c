@@ -73,6 +73,9 @@ typedef struct {
      * temperature mppi_lambda on the score c + mppi_w_viol * nu */
     int update, pad1;
     double mppi_lambda, mppi_w_viol;
+    /* perturbation of the opponents' predicted positions (robustness experiment,
+     * Sec. IV-C, Table III): standard deviations along / across the predicted heading */
+    double pred_sig_lon, pred_sig_lat;
 } ref_params;
 
 typedef struct {
@@ -842,6 +845,33 @@ static void agent_setup(const ref_track *T, const ref_params *p, const ref_race 
     ref_reference(T, p, seg, s, R->v_scale[i], A->xr);
 }
 
+/* Perturbed opponent prediction (robustness to prediction uncertainty, Sec. IV-C, Table
+ * III; the paper cites its perturbation model without details).  Reading: every predicted
+ * position tau = 1..N of opponent j, as seen by `observer` in `phase`, moves by
+ * sigma_lon z0 along the predicted heading and sigma_lat z1 across it, with (z0, z1) the
+ * Gaussian pair of the first two words of Philox(counter = (2^31 | j, tau,
+ * observer | phase << 16, plan_step), key = seed); headings, progress and lateral offsets
+ * of the prediction are kept.  traj: [N+1][8] world rows (x, y, psi, ...). */
+void ref_perturb_prediction(const ref_params *p, unsigned long long seed, unsigned int plan_step, int observer,
+                            int phase, int j, int N, double *traj)
+{
+    if (!(p->pred_sig_lon > 0.0) && !(p->pred_sig_lat > 0.0)) return;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int tau = 1; tau <= N; ++tau) {
+        const uint32_t ctr[4] = {0x80000000u | (uint32_t)j, (uint32_t)tau,
+                                 (uint32_t)observer | ((uint32_t)phase << 16), plan_step};
+        uint32_t r[4];
+        float z[2];
+        ref_philox4x32_10(ctr, key, r);
+        ref_gauss_pair(r[0], r[1], z);
+        double *row = traj + 8 * (size_t)tau;
+        const double dl = p->pred_sig_lon * (double)z[0], dn = p->pred_sig_lat * (double)z[1];
+        const double c = cos(row[2]), sn = sin(row[2]);
+        row[0] += dl * c - dn * sn;
+        row[1] += dl * sn + dn * c;
+    }
+}
+
 static void build_br_in(const ref_params *p, const ref_race *R, const agent_state *A, int i, int phase,
                         const double *ubar_all, const double *traj_all, double *opp_buf, double *opp_s0,
                         ref_br_in *in)
@@ -851,6 +881,8 @@ static void build_br_in(const ref_params *p, const ref_race *R, const agent_stat
     for (int j = 0; j < n; ++j) {
         if (j == i) continue;
         memcpy(opp_buf + (size_t)no * (N + 1) * 8, traj_all + (size_t)j * (N + 1) * 8, sizeof(double) * (N + 1) * 8);
+        ref_perturb_prediction(p, R->seed, R->plan_step, R->agent_id ? R->agent_id[i] : i, phase,
+                               R->agent_id ? R->agent_id[j] : j, N, opp_buf + (size_t)no * (N + 1) * 8);
         opp_s0[no] = A[j].s;
         ++no;
     }

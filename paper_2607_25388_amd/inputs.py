@@ -103,6 +103,8 @@ def default_params(N: int, n_disc: int = 3, model: int = 0) -> dict:
         # best-response update: 0 = feasibility selection; 1 = path-integral (MPPI) update of
         # the GA-IBR-MPPI ablation, temperature and soft violation weight not given in the paper
         update=0, mppi_lambda=10.0, mppi_w_viol=0.0,
+        # perturbation of the opponents' predicted positions (robustness experiment), off
+        pred_sig_lon=0.0, pred_sig_lat=0.0,
     )
 
 
