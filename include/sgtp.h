@@ -83,6 +83,12 @@ typedef struct {
     int update;
     float mppi_lambda;         /* temperature (> 0) */
     float mppi_w_viol;         /* weight of the violation nu in the score (>= 0) */
+    /* Perturbation of the opponents' predicted positions (robustness experiment, Sec.
+     * IV-C, Table III): each predicted position tau = 1..N of opponent j, as staged for
+     * vehicle i in a phase, moves by pred_sig_lon z0 along and pred_sig_lat z1 across the
+     * predicted heading, (z0, z1) the Box-Muller pair of Philox(counter = (2^31 | j, tau,
+     * i | phase << 16, plan_step), key = seed).  0, 0 = off. */
+    float pred_sig_lon, pred_sig_lat;
 } sgtp_params;
 
 /* One race (one game) at one planning instant. */
@@ -118,7 +124,7 @@ typedef struct {
 /* Create a context on the current device with workspace for up to
  * max_agents_total vehicles over all races of one call, horizons up to max_N,
  * max_races races per call, track tables of up to max_track_nodes nodes and up to
- * max_K samples per best response (checkpoint slots: 128 bytes per 64 samples).
+ * max_K samples per best response (checkpoint slots: 256 bytes per 64 samples).
  * Allocates device memory (with sgtp_track_upload, plans and the autotuner). */
 int sgtp_ctx_create(sgtp_ctx **out, int max_agents_total, int max_N, int max_races, int max_track_nodes,
                     int max_K);

@@ -60,6 +60,7 @@ struct KParams {
     float lf, lr, inv_m, inv_Iz, muFzf, muFzr, B, C, v_eps, C_rev;  // dynamic single-track
     float lr_over_L, inv_lr;                                 // kinematic bicycle
     float inv_lambda, w_viol;                                // path-integral update
+    float pred_sig_lon, pred_sig_lat;                        // opponent-prediction perturbation
 };
 
 struct TrackDev {
@@ -684,7 +685,18 @@ __device__ void stage_block(const LaunchArgs &A, int item_idx, BlockState &bs, c
             const int j = jo < it.agent ? jo : jo + 1;
             const float *pr = A.pred_in + (size_t)(R.slot0 + j) * pstride + t * PRED_STRIDE;
             const float4 T = oppT[jo];
-            const float px = pr[0], py = pr[1], pc = pr[2], psn = pr[3];
+            float px = pr[0], py = pr[1];
+            const float pc = pr[2], psn = pr[3];
+            if (P.pred_sig_lon > 0.0f || P.pred_sig_lat > 0.0f) {
+                // perturbed prediction (robustness experiment): a Gaussian pair of its own
+                // Philox counter moves the position along / across the predicted heading
+                const uint4 r = philox4x32_10(make_uint4(0x80000000u | (uint32_t)j, (uint32_t)t, bs.ctr2, bs.ctr3),
+                                              bs.key0, bs.key1);
+                const float2 z = gauss_pair(r.x, r.y);
+                const float dl = P.pred_sig_lon * z.x, dn = P.pred_sig_lat * z.y;
+                px += dl * pc - dn * psn;
+                py += dl * psn + dn * pc;
+            }
             float2 *dst = opp + ((size_t)(t - 1) * L.n_opp_max + jo) * (NDISC + 1);
             dst[0] = make_float2(T.x * px - T.y * py + T.z, T.y * px + T.x * py + T.w);
 #pragma unroll
@@ -1854,6 +1866,8 @@ KParams make_kparams(const sgtp_params *p) {
     k.update = p->update;
     k.inv_lambda = p->update == 1 ? (float)(1.0 / (double)p->mppi_lambda) : 0.0f;
     k.w_viol = p->mppi_w_viol;
+    k.pred_sig_lon = p->pred_sig_lon;
+    k.pred_sig_lat = p->pred_sig_lat;
     return k;
 }
 
@@ -1877,6 +1891,9 @@ int check_params(sgtp_ctx *c, const sgtp_params *p) {
     if (p->max_moves < 1 || p->max_moves > 1024) return fail(c, SGTP_EINVAL, "max_moves out of range");
     if (!(p->m > 0.f) || !(p->Iz > 0.f) || !(p->lf > 0.f) || !(p->lr > 0.f) || !(p->v_eps > 0.f))
         return fail(c, SGTP_EINVAL, "vehicle constants must be positive");
+    if (!(p->pred_sig_lon >= 0.f) || !(p->pred_sig_lat >= 0.f) || !std::isfinite(p->pred_sig_lon) ||
+        !std::isfinite(p->pred_sig_lat))
+        return fail(c, SGTP_EINVAL, "prediction perturbation scales must be finite and >= 0");
     if (p->update != 0 && p->update != 1) return fail(c, SGTP_EINVAL, "update must be 0 or 1");
     if (p->update == 1) {
         if (!(p->mppi_lambda > 0.f) || !std::isfinite(p->mppi_lambda) || !(p->mppi_w_viol >= 0.f) ||

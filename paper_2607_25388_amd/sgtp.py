@@ -35,11 +35,13 @@ class Params(C.Structure):
         ("B", C.c_float), ("C", C.c_float), ("mu", C.c_float), ("g", C.c_float), ("v_eps", C.c_float),
         ("max_moves", C.c_int),
         ("update", C.c_int), ("mppi_lambda", C.c_float), ("mppi_w_viol", C.c_float),
+        ("pred_sig_lon", C.c_float), ("pred_sig_lat", C.c_float),
     ]
 
 
-# parameters with a default (the path-integral update is off unless asked for)
-PARAM_DEFAULTS = {"update": 0, "mppi_lambda": 1.0, "mppi_w_viol": 0.0}
+# parameters with a default (the path-integral update and the prediction perturbation
+# are off unless asked for)
+PARAM_DEFAULTS = {"update": 0, "mppi_lambda": 1.0, "mppi_w_viol": 0.0, "pred_sig_lon": 0.0, "pred_sig_lat": 0.0}
 
 
 class Race(C.Structure):

@@ -123,10 +123,12 @@ def test_open_straight_track(planner):
     PY.check_choice(g["choice"], r, params, "straight")
 
 
-def _plan(planner, name, K, L):
+def _plan(planner, name, K, L, params_over=None):
     import torch
     import paper_2607_25388_amd.sgtp as sg
     tr, race, params, _, w = PY.workload(name)
+    if params_over:
+        params = dict(params, **params_over)
     rt = PY.build(planner, tr, race, params, K)
     n = race.n_agents
     trace = torch.zeros((L + 2) * n * sg.CHOICE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
@@ -136,11 +138,16 @@ def _plan(planner, name, K, L):
     return tr, race, params, rt, gtr, u_apply.cpu().numpy()
 
 
-@pytest.mark.parametrize("name,K,L", [("c1", 1024, 3), ("c2", 1024, 2)])
-def test_plan_step_lockstep(planner, name, K, L):
+# prediction perturbation of the robustness experiment at a scale that moves clearances
+PERTURB = {"pred_sig_lon": 0.5, "pred_sig_lat": 0.3}
+
+
+@pytest.mark.parametrize("name,K,L,over", [("c1", 1024, 3, None), ("c2", 1024, 2, None), ("c3", 512, 1, PERTURB),
+                                           ("c1", 1024, 2, PERTURB)])
+def test_plan_step_lockstep(planner, name, K, L, over):
     """Alg. 1 on the GPU; the oracle replays it adopting the GPU's choices phase by phase
     and must agree with each choice (or find it a near-tie)."""
-    tr, race, params, rt, gtr, u_apply = _plan(planner, name, K, L)
+    tr, race, params, rt, gtr, u_apply = _plan(planner, name, K, L, over)
     n = race.n_agents
     forced = np.full((L + 2, n), -1, np.int32)
     for ph in range(L + 2):
@@ -255,3 +262,17 @@ def test_pair_variant_matches_one_lane_variant(planner, name, agent, K, N):
     # the selection over the first K samples: the small launch's choice is its own argmin
     r = PY.oracle_for(tr, params).rollout_cost(race, agent, 1, K)
     PY.check_choice(small["choice"], r, params, f"{name} pair variant")
+
+
+@pytest.mark.parametrize("name,agent,K", [("c2", 0, 2048), ("c3", 3, 1000)])
+def test_rollout_cost_with_prediction_perturbation(planner, name, agent, K):
+    """Perturbed opponent predictions (robustness experiment): per-sample parity with the
+    oracle, and the perturbation does change the clearances seen by the samples."""
+    tr, race, params, g, r = _run(planner, name, agent, 1, K, params_over=PERTURB)
+    PY.compare_samples(g, r, params, tr.width, f"{name} perturbed")
+    PY.check_choice(g["choice"], r, params, f"{name} perturbed")
+    _, _, _, g0, r0 = _run(planner, name, agent, 1, K)
+    assert not np.array_equal(r["rho_obs"], r0["rho_obs"])
+    # where some sample comes within the safety distance, the cost sees the perturbation too
+    if np.any(r0["rho_obs"] < params["g_safe"]):
+        assert not np.array_equal(g["cost"], g0["cost"])
