@@ -15,7 +15,8 @@ planning call).
 
 Methods: "sgtp" (feasibility selection with the game-aware cost), "sgtp_wo_gc" (the
 same without the game-aware cost, w_game = 0), "ga_ibr_mppi" (path-integral update with
-the game-aware cost, no feasibility selection).
+the game-aware cost, no feasibility selection), "sgtp_mild" / "sgtp_severe" (SGTP with
+the opponents' predicted positions perturbed, Table III).
 """
 
 from __future__ import annotations
@@ -41,7 +42,11 @@ def csd_box(params):
     lon_contact = params["d_col"] + 2.0 * max(abs(o) for o in offs)
     return CSD_LON / PAPER_D_COL * lon_contact, CSD_LAT / PAPER_D_COL * params["d_col"]
 
-METHODS = ("sgtp", "sgtp_wo_gc", "ga_ibr_mppi")
+METHODS = ("sgtp", "sgtp_wo_gc", "ga_ibr_mppi", "sgtp_mild", "sgtp_severe")
+
+# opponent-prediction perturbation of Table III, (sigma_lon, sigma_lat) at the paper's
+# vehicle scale, carried over by the ratio of the collision thresholds
+PERTURB_LEVELS = {"mild": (0.03, 0.015), "severe": (0.08, 0.04)}
 
 
 def method_params(params: dict, method: str) -> dict:
@@ -51,6 +56,10 @@ def method_params(params: dict, method: str) -> dict:
         return dict(params, w_game=0.0)
     if method == "ga_ibr_mppi":
         return dict(params, update=1)
+    if method.startswith("sgtp_") and method[5:] in PERTURB_LEVELS:
+        lon, lat = PERTURB_LEVELS[method[5:]]
+        sc = params["d_col"] / PAPER_D_COL
+        return dict(params, pred_sig_lon=lon * sc, pred_sig_lat=lat * sc)
     raise ValueError(method)
 
 
