@@ -23,6 +23,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -221,10 +222,15 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 
 // atan: odd polynomial fitted on [0, 1] (max error 3.3e-7), reflected via pi/2 - atan(1/x).
 // (A 6-term fit with 1.8e-6 error moved chaotic sliding samples past the 1e-3 state tolerance.)
+// UNIFORM: the reciprocal of the range reduction only when some lane of the wave needs
+// it (saves issue slots where many waves share a SIMD; a single wave waits on the branch
+// instead); the selected value is the same either way.
+template <bool UNIFORM = false>
 __device__ __forceinline__ float fast_atan(float x) {
     const float ax = fabsf(x);
     const bool inv = ax > 1.0f;
-    const float t = inv ? fast_rcp(ax) : ax;
+    float t = ax;
+    if (!UNIFORM || __builtin_amdgcn_ballot_w64(inv)) t = inv ? fast_rcp(ax) : ax;
     const float t2 = t * t;
     float p = 0x1.be6b36p-8f;
     p = __builtin_fmaf(p, t2, -0x1.134946p-5f);
@@ -246,13 +252,18 @@ __device__ __forceinline__ float fast_cos(float x) { return __builtin_amdgcn_cos
 // pre-scaled by to_rev (revolutions for the float32 transcendental unit, radians in float64).
 struct MathF32 {
     using T = float;
-    static __device__ __forceinline__ T atan_(T x) { return fast_atan(x); }
+    static __device__ __forceinline__ T atan_(T x) { return fast_atan<false>(x); }
     static __device__ __forceinline__ T sin_(T x) { return fast_sin(x); }
     static __device__ __forceinline__ T cos_(T x) { return fast_cos(x); }
     static __device__ __forceinline__ T rcp_(T x) { return fast_rcp(x); }
     static __device__ __forceinline__ T to_rev(T x) { return x * 0.159154943f; }
     static __device__ __forceinline__ T sin_rev(T x) { return __builtin_amdgcn_sinf(x); }
     static __device__ __forceinline__ T cos_rev(T x) { return __builtin_amdgcn_cosf(x); }
+};
+
+// MathF32 with the wave-uniform atan range reduction (throughput kernels)
+struct MathF32U : MathF32 {
+    static __device__ __forceinline__ T atan_(T x) { return fast_atan<true>(x); }
 };
 
 struct MathF64 {
@@ -875,9 +886,11 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P, const Bloc
             noise_out[2 * tau + 1] = z.y;
         }
         const float2 u = controls_k(P, bs, lds, L, k, tau, ub, z.x, z.y);
-        const StepConst<float> sc = step_const<MODEL, MathF32>(V, u.x, u.y);
+        // latency variants (NPF > 0) branch-free, throughput variants with the uniform atan
+        using MS = typename std::conditional<NPF == 0, MathF32U, MathF32>::type;
+        const StepConst<float> sc = step_const<MODEL, MS>(V, u.x, u.y);
         if constexpr (LPS == 2 && MODEL == 0) rk4_pair(V, sc, P.dt, st, rear);
-        else rk4<MODEL, MathF32>(V, sc, P.dt, st);
+        else rk4<MODEL, MS>(V, sc, P.dt, st);
         Foot f;
         if constexpr (NPF > 0) f = project_ahead<NPF>(nodes, bs.W, P.max_moves, st[0], st[1], seg, ahead);
         else f = project(nodes, bs.W, P.max_moves, st[0], st[1], seg);
