@@ -23,18 +23,20 @@ sys.path.insert(0, ROOT)
 METRIC = "sample·steps/s per IBR sweep; plan latency p50/p99; learned vs plain cost"
 PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak
 
-# Hardware counters of the dominant sweep kernel (k_sweep, one workgroup per tile, the
-# schedule the autotuner picks for the mid-scale race), medians over the timed eager
-# launches of `bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-learned --roofline-steps 2
-# --copy-calibration 256` under rocprofv3 --pmc.  HBM bytes: FETCH_SIZE 360.4 KiB x 2.000 +
-# WRITE_SIZE 332.3 KiB x 1.000 per launch, the factors being 256 MiB over what the same
-# counter reads for the 256 MiB elementwise copy (131087 KiB fetched, 262144 KiB written).
-# FP32 FLOPs: 64 x (ADD + MUL + TRANS + 2 FMA) wave instructions of SQ_INSTS_VALU_*_F32.
-# They describe the kernel source with this SHA-256 only; any other source reports null.
+# Hardware counters of the dominant sweep kernel at the mid-scale race (k_sweep in its
+# one-wave-per-SIMD variant, the schedule the autotuner picks), medians over the timed
+# eager launches of `bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-learned
+# --roofline-steps 2 --copy-calibration 256` under rocprofv3 --pmc, weighted like the
+# timed launches (6 all-vehicle sweeps, 1 ego sweep per planning step).  HBM bytes:
+# FETCH_SIZE 354.1 KiB x 2.000 + WRITE_SIZE 300.6 KiB x 1.000 per launch, the factors being
+# 256 MiB over what the same counter reads for the 256 MiB elementwise copy (131087 KiB
+# fetched, 262144 KiB written).  FP32 FLOPs: 64 x (ADD + MUL + TRANS + 2 FMA) wave
+# instructions of SQ_INSTS_VALU_*_F32.  They describe the kernel source with this SHA-256
+# only; any other source reports null.
 SWEEP_COUNTERS = {
-    "c2": {"source_sha256": "eaf13174ce2f13213d4ec86da327a86e608367ace6a2262644b9b33b2e81f765",
-           "hbm_bytes_per_launch": (360.375 * 1.99981 + 332.344) * 1024.0,
-           "hw_fp32_flop_per_launch": 1.363e9, "valu_wave_insts_per_launch": 22.41e6},
+    "c2": {"source_sha256": "7710548e388a5e0619dedab86b51915a3690364fdbda0fc084f4335ff25f8c7b",
+           "hbm_bytes_per_launch": (354.125 * 1.99981 + 300.574) * 1024.0,
+           "hw_fp32_flop_per_launch": 1.2334e9, "valu_wave_insts_per_launch": 21.28e6},
 }
 
 
