@@ -41,9 +41,9 @@ constexpr int PRED_STRIDE = 8;  // x, y, cos psi, sin psi, s_rel, d, -, - in the
 constexpr int NODE_STRIDE = 10; // device node row: x, y, psi, nx, ny, wL, wR, vref, s, kappa
 constexpr unsigned long long KEY_NONE = ~0ull;
 constexpr long long LPS2_MAX_SAMPLES = 32768;  // pair variant up to 1024 waves
-constexpr int NQ = 8;
+constexpr int NQ = 8;           // tile queues of the persistent sweep (one per XCD under round-robin dispatch)
 constexpr int NCP = 4;          // re-roll chunks: each lane keeps its state at N/4, N/2, 3N/4
-constexpr int CP_FLOATS = 32;   // export slot per 64-sample group: 3 checkpoints x (6 states + segment)           // tile queues of the persistent sweep (one per XCD under round-robin dispatch)
+constexpr int CP_FLOATS = 32;   // export slot per 64-sample group: 3 checkpoints x (6 states + segment)
 
 enum Mode { SWEEP = 0, WINNER = 1, NOMINAL = 2 };
 
@@ -1065,29 +1065,55 @@ __device__ SampleResult reroll_block(const KParams &P, const LdsLayout &L, const
         if (out.u_apply) *out.u_apply = wu[0];
     }
     __syncthreads();
-    // D. accumulate in the lanes' order and score
+    // D. score: the minima over the horizon by the first wave (exact in any order), the
+    //    two sums in the lanes' order by one lane, its LDS reads issued UB steps at a time
     SampleResult res{};
-    if (MODE == WINNER && tid == 0) {
-        float J = 0.0f, rho_bd = INFINITY, dsum = 0.0f;
+    if (MODE == WINNER && tid < 64) {
+        float rho_bd = INFINITY;
         float g2[MAXOPP];
 #pragma unroll
         for (int j = 0; j < MAXOPP; ++j) g2[j] = P.cap2;
-        bool limit = false;
-        for (int tau = 0; tau < N; ++tau) {
-            const float4 t4 = wt[tau];
-            J += t4.x;
-            J += t4.y;
-            if (tau >= 1) J += t4.z;
-            rho_bd = fminf(rho_bd, t4.w);
+        bool lim = false;
+        for (int tau = tid; tau < N; tau += 64) {
+            rho_bd = fminf(rho_bd, wt[tau].w);
 #pragma unroll
             for (int j = 0; j < MAXOPP; ++j)
                 if (j < bs.n_opp) g2[j] = fminf(g2[j], wg[tau * MAXOPP + j]);
-            limit |= wl[tau] != 0;
-            if (tau + 1 > N - bs.n_tail) dsum += wf[tau].y;
+            lim |= wl[tau] != 0;
         }
-        const float4 a = wst[2 * (N - 1)], b = wst[2 * (N - 1) + 1];
-        const float st[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
-        res = terminal<MAXOPP>(P, bs, lds, L, J, rho_bd, dsum, wf[N - 1].x, g2, limit, st);
+        rho_bd = wave_min_f32(rho_bd);
+#pragma unroll
+        for (int j = 0; j < MAXOPP; ++j)
+            if (j < bs.n_opp) g2[j] = wave_min_f32(g2[j]);
+        const bool limit = __builtin_amdgcn_ballot_w64(lim) != 0;
+        if (tid == 0) {
+            constexpr int UB = 8;
+            float J = 0.0f, dsum = 0.0f;
+            for (int t0 = 0; t0 < N; t0 += UB) {
+                float4 tv[UB];
+#pragma unroll
+                for (int u = 0; u < UB; ++u) tv[u] = t0 + u < N ? wt[t0 + u] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+                for (int u = 0; u < UB; ++u) {
+                    if (t0 + u < N) {
+                        J += tv[u].x;
+                        J += tv[u].y;
+                        if (t0 + u >= 1) J += tv[u].z;
+                    }
+                }
+            }
+            for (int t0 = max(0, N - bs.n_tail); t0 < N; t0 += UB) {
+                float dv[UB];
+#pragma unroll
+                for (int u = 0; u < UB; ++u) dv[u] = t0 + u < N ? wf[t0 + u].y : 0.0f;
+#pragma unroll
+                for (int u = 0; u < UB; ++u)
+                    if (t0 + u < N) dsum += dv[u];
+            }
+            const float4 a = wst[2 * (N - 1)], b = wst[2 * (N - 1) + 1];
+            const float st[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
+            res = terminal<MAXOPP>(P, bs, lds, L, J, rho_bd, dsum, wf[N - 1].x, g2, limit, st);
+        }
     }
     return res;
 }
@@ -1363,7 +1389,11 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_persistent(LaunchArgs A) {
 // Setup of every vehicle: global Frenet projection of the current state,
 // unwrapped progress, local frame, raceline window, reference states
 // (Sec. III-A: s^r recursion over v^r) and the noise-free rollout of the
-// nominal sequence (initial prediction).
+// nominal sequence (initial prediction).  Two workgroups per vehicle run at once
+// (grid 2 x n_items): the first writes the vehicle record, the window and the
+// reference states, the second rolls out the nominal; both compute the projection
+// and the frame, with the same bits.  The second may read the unwrapped progress
+// before or after the first has updated it; both give the same lap count.
 template <int MODEL>
 __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
     extern __shared__ __align__(16) char lds[];
@@ -1371,7 +1401,9 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
     __shared__ long long red_i[BLOCK];
     __shared__ double sh[8];
     __shared__ long long shl[4];
-    const ItemDev it = A.items[blockIdx.x];
+    __shared__ AgentRec s_rec;
+    const bool roller = (int)blockIdx.x >= A.n_items;
+    const ItemDev it = A.items[roller ? blockIdx.x - A.n_items : blockIdx.x];
     const RaceDev R = A.races[it.race];
     const TrackDev T = A.tracks[R.track];
     const double *xs = R.x + (size_t)it.agent * 6;
@@ -1379,7 +1411,7 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
     const int tid = threadIdx.x;
     const long long n = T.n;
     const long long nseg = T.closed ? n : n - 1;
-    if (blockIdx.x == 0 && A.qreset)
+    if (blockIdx.x == 0 && A.qreset)  // (a first workgroup)
         for (int i = tid; i < A.n_qreset; i += BLOCK) A.qreset[i] = 0;
 
     auto node = [&](long long i, double *o) {  // unwrapped node access (float64 row)
@@ -1500,7 +1532,6 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
             seg += (long long)lap * n;
             s += lap * T.length;
         }
-        R.s_abs[it.agent] = s;
         const double psi0 = xs[2];
         const double c0 = cos(psi0), s0 = sin(psi0);
         const double vx = xs[3] > 0.0 ? xs[3] : 0.0, vy = xs[4];
@@ -1525,16 +1556,46 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
         rec.win_n = (int)W; rec.seg_loc = (int)(seg - win0);
         rec.vx = (float)xs[3]; rec.vy = (float)xs[4]; rec.om = (float)xs[5];
         rec.lam = R.v_scale[it.agent];
-        A.agents[it.slot] = rec;
+        s_rec = rec;
         sh[0] = c0; sh[1] = s0; sh[2] = psi0; sh[3] = s; sh[4] = lam;
         shl[0] = win0; shl[1] = W; shl[2] = seg - win0;
-        A.keys[it.slot] = KEY_NONE;
-        A.nfeas[it.slot] = 0;
-        A.counters[it.slot] = 0;
+        if (!roller) {
+            R.s_abs[it.agent] = s;
+            A.agents[it.slot] = rec;
+            A.keys[it.slot] = KEY_NONE;
+            A.nfeas[it.slot] = 0;
+            A.counters[it.slot] = 0;
+        }
     }
     __syncthreads();
     const double c0 = sh[0], s0 = sh[1], psi0 = sh[2], sa = sh[3], lam = sh[4];
     const long long win0 = shl[0], W = shl[1], segl = shl[2];
+    if (roller) {
+        // stage the float32 window and the nominal, roll the nominal out (predictions)
+        float4 *nodes_l = (float4 *)(lds + A.L.nodes);
+        for (long long w = tid; w < W; w += BLOCK) {
+            double nd[NODE_STRIDE];
+            node(win0 + w, nd);
+            const double dx = nd[0] - px, dy = nd[1] - py;
+            const double nxl = c0 * nd[3] + s0 * nd[4], nyl = -s0 * nd[3] + c0 * nd[4];
+            nodes_l[2 * w] = make_float4((float)(c0 * dx + s0 * dy), (float)(-s0 * dx + c0 * dy), (float)nxl, (float)nyl);
+            nodes_l[2 * w + 1] = make_float4((float)nd[5], (float)nd[6], (float)(nd[8] - sa), 0.0f);
+        }
+        float2 *ubar = (float2 *)(lds + A.L.ubar);
+        const float2 *un = (const float2 *)(R.u_nom) + (size_t)it.agent * R.N;
+        for (int t = tid; t < R.N; t += BLOCK) ubar[t] = un[t];
+        __syncthreads();
+        BlockState bs{};
+        bs.slot = it.slot; bs.race = it.race; bs.agent = it.agent; bs.N = R.N; bs.n_tail = R.n_tail; bs.K = R.K;
+        bs.n_opp = 0; bs.W = (int)W; bs.seg0 = (int)segl;
+        bs.vx0 = (float)xs[3]; bs.vy0 = (float)xs[4]; bs.om0 = (float)xs[5];
+        bs.inv_n_tail = 1.0f / (float)R.n_tail; bs.w_game = 0.0f;
+        const AgentRec rec = s_rec;
+        RerollOut out{};
+        out.pred = A.pred_out + (size_t)it.slot * (A.L.N_max + 1) * PRED_STRIDE;
+        reroll_block<MODEL, 1, 1, NOMINAL, 6>(A.P, A.L, bs, lds, rec, 0u, out);
+        return;
+    }
 
     // 3. raceline window in the local frame to HBM: A = (x, y, nx, ny), B = (wL, wR, s - s_abs, 0);
     //    arc length and reference speed of the window nodes to LDS (float64) for the recursion
@@ -1576,7 +1637,6 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
     // 5. reference states x^r(s^r_t), t = 1..N, in the local frame (heading shifted by a
     //    multiple of 2 pi so it starts near the vehicle's heading)
     float4 *xr = (float4 *)(A.xref + (size_t)it.slot * A.L.N_max);
-    float4 *xr_l = (float4 *)(lds + A.L.xref);
     for (int t = tid; t < R.N; t += BLOCK) {
         const long long h = segs[t];
         double a[NODE_STRIDE], b[NODE_STRIDE];
@@ -1597,32 +1657,7 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
         const float4 q = make_float4((float)(c0 * dx + s0 * dy), (float)(-s0 * dx + c0 * dy),
                                      (float)(ps - psi0 - shift), (float)(lam * v));
         xr[t] = q;
-        xr_l[t] = q;
     }
-    __syncthreads();
-    // 6. stage the float32 window and the nominal, roll the nominal out (predictions)
-    float4 *nodes_l = (float4 *)(lds + A.L.nodes);
-    for (long long w = tid; w < W; w += BLOCK) {
-        double nd[NODE_STRIDE];
-        node(win0 + w, nd);
-        const double dx = nd[0] - px, dy = nd[1] - py;
-        const double nxl = c0 * nd[3] + s0 * nd[4], nyl = -s0 * nd[3] + c0 * nd[4];
-        nodes_l[2 * w] = make_float4((float)(c0 * dx + s0 * dy), (float)(-s0 * dx + c0 * dy), (float)nxl, (float)nyl);
-        nodes_l[2 * w + 1] = make_float4((float)nd[5], (float)nd[6], (float)(nd[8] - sa), 0.0f);
-    }
-    float2 *ubar = (float2 *)(lds + A.L.ubar);
-    const float2 *un = (const float2 *)(R.u_nom) + (size_t)it.agent * R.N;
-    for (int t = tid; t < R.N; t += BLOCK) ubar[t] = un[t];
-    __syncthreads();
-    BlockState bs{};
-    bs.slot = it.slot; bs.race = it.race; bs.agent = it.agent; bs.N = R.N; bs.n_tail = R.n_tail; bs.K = R.K;
-    bs.n_opp = 0; bs.W = (int)W; bs.seg0 = (int)segl;
-    bs.vx0 = (float)xs[3]; bs.vy0 = (float)xs[4]; bs.om0 = (float)xs[5];
-    bs.inv_n_tail = 1.0f / (float)R.n_tail; bs.w_game = 0.0f;
-    const AgentRec rec = A.agents[it.slot];
-    RerollOut out{};
-    out.pred = A.pred_out + (size_t)it.slot * (A.L.N_max + 1) * PRED_STRIDE;
-    reroll_block<MODEL, 1, 1, NOMINAL, 6>(A.P, A.L, bs, lds, rec, 0u, out);
 }
 
 // ------------------------------------------------------------------------------
@@ -2193,9 +2228,9 @@ struct Runner {
         a.n_items = (int)pl.all.size();
         a.pred_out = c->d_pred[0];
         if (p->model == 0)
-            hipLaunchKernelGGL(k_setup<0>, dim3(a.n_items), dim3(BLOCK), A.L.total, st, a, pl.w_max);
+            hipLaunchKernelGGL(k_setup<0>, dim3(2 * a.n_items), dim3(BLOCK), A.L.total, st, a, pl.w_max);
         else
-            hipLaunchKernelGGL(k_setup<1>, dim3(a.n_items), dim3(BLOCK), A.L.total, st, a, pl.w_max);
+            hipLaunchKernelGGL(k_setup<1>, dim3(2 * a.n_items), dim3(BLOCK), A.L.total, st, a, pl.w_max);
         HIPCHK(c, hipGetLastError());
         return SGTP_OK;
     }
@@ -2274,9 +2309,9 @@ int plan_enqueue(sgtp_plan *P, hipStream_t st) {
     a.qreset = P->d_qctr;
     a.n_qreset = (P->L + 2) * NQ;
     if (P->p.model == 0)
-        hipLaunchKernelGGL(k_setup<0>, dim3(a.n_items), dim3(BLOCK), a.L.total, st, a, P->pl.w_max);
+        hipLaunchKernelGGL(k_setup<0>, dim3(2 * a.n_items), dim3(BLOCK), a.L.total, st, a, P->pl.w_max);
     else
-        hipLaunchKernelGGL(k_setup<1>, dim3(a.n_items), dim3(BLOCK), a.L.total, st, a, P->pl.w_max);
+        hipLaunchKernelGGL(k_setup<1>, dim3(2 * a.n_items), dim3(BLOCK), a.L.total, st, a, P->pl.w_max);
     HIPCHK(c, hipGetLastError());
     const int nt = P->pl.agents_total;
     if (P->mlp) {  // learned proposal: features -> network -> tables, before the first sweep
