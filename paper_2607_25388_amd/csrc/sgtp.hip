@@ -42,8 +42,14 @@ constexpr int NODE_STRIDE = 10; // device node row: x, y, psi, nx, ny, wL, wR, v
 constexpr unsigned long long KEY_NONE = ~0ull;
 constexpr long long LPS2_MAX_SAMPLES = 32768;  // pair variant up to 1024 waves
 constexpr int NQ = 8;           // tile queues of the persistent sweep (one per XCD under round-robin dispatch)
-constexpr int NCP = 4;          // re-roll chunks: each lane keeps its state at N/4, N/2, 3N/4
-constexpr int CP_FLOATS = 32;   // export slot per 64-sample group: 3 checkpoints x (6 states + segment)
+// Re-roll chunks: each lane keeps its state after every ceil(N / chunks) steps, so the
+// selected sample is re-rolled in that many pieces at once.  Latency variants (about
+// one wave per SIMD, registers to spare) keep 8, throughput variants 4.
+constexpr int NCP_MAX = 8;
+template <int NPF>
+constexpr int ncp_of() { return NPF > 0 ? 8 : 4; }
+constexpr int CP_FLOATS = 64;   // export slot per group: up to 7 checkpoints x (6 states + segment), cost, violation
+constexpr int CP_COST = 62, CP_VIOL = 63;
 
 enum Mode { SWEEP = 0, WINNER = 1, NOMINAL = 2 };
 
@@ -98,7 +104,7 @@ struct AgentRec {  // per vehicle, written by k_setup
 
 struct LdsLayout {  // byte offsets of the staged tables, identical for every block of a launch
     int ubar, xref, oppT, oppc, opp, nodes, prop;
-    int rr_u, rr_st, rr_f, rr_t, rr_g, rr_l;  // re-roll scratch
+    int rr_u, rr_st, rr_f, rr_t;  // re-roll scratch (rr_t: setup's reference recursion)
     int total;
     int n_opp_max, w_max, N_max;
 };
@@ -784,7 +790,7 @@ struct SampleResult {
     bool h;
     unsigned char flags;
     float st[6];
-    float cp[NCP - 1][7];  // state and segment after steps C, 2C, 3C (C = ceil(N / NCP))
+    float cp[NCP_MAX - 1][7];  // state and segment after steps C, 2C, ... (C = ceil(N / chunks))
 };
 
 // Terminal scoring: game-aware cost (eqs. game_cost, c_contest, c_long, c_block,
@@ -853,12 +859,13 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P, const Bloc
     float2 up = make_float2(0.0f, 0.0f);
     bool limit = false;
     float2 zn = make_float2(0.0f, 0.0f);  // perturbation of the odd step of a Philox call
-    float cp[NCP - 1][7];
+    constexpr int NC = ncp_of<NPF>();
+    float cp[NC - 1][7];
 #pragma unroll
-    for (int c = 0; c < NCP - 1; ++c)
+    for (int c = 0; c < NC - 1; ++c)
 #pragma unroll
         for (int i = 0; i < 7; ++i) cp[c][i] = 0.0f;
-    const int C = (bs.N + NCP - 1) / NCP;
+    const int C = (bs.N + NC - 1) / NC;
 
     for (int tau = 0; tau < bs.N; ++tau) {
         // LDS reads that do not depend on this step's dynamics go first
@@ -914,7 +921,7 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P, const Bloc
                                         g2[j]);
         if (tau + 1 > bs.N - bs.n_tail) dsum += f.d;
 #pragma unroll
-        for (int c = 0; c < NCP - 1; ++c) {
+        for (int c = 0; c < NC - 1; ++c) {
             if (tau + 1 == (c + 1) * C) {
 #pragma unroll
                 for (int i = 0; i < 6; ++i) cp[c][i] = st[i];
@@ -924,17 +931,18 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P, const Bloc
     }
     SampleResult res = terminal<MAXOPP>(P, bs, lds, L, J, rho_bd, dsum, s, g2, limit, st);
 #pragma unroll
-    for (int c = 0; c < NCP - 1; ++c)
+    for (int c = 0; c < NC - 1; ++c)
 #pragma unroll
         for (int i = 0; i < 7; ++i) res.cp[c][i] = cp[c][i];
     return res;
 }
 
 // ------------------------------------------------------------------------------
-// One sample re-rolled by a whole workgroup: controls, per-step terms and output
-// writes in parallel over the horizon; only the dynamics and the projection run
-// serially in thread 0.  MODE WINNER scores the sample; NOMINAL rolls out the
-// unperturbed nominal (predictions only).
+// One sample re-rolled by a whole workgroup for its outputs: controls and output
+// writes in parallel over the horizon, the dynamics and the projection serially (in
+// ncp_of<NPF>() pieces at once when the sample's checkpoints are given).  MODE WINNER
+// re-rolls the selected sample, whose cost and violation its own lane exported;
+// NOMINAL rolls out the unperturbed nominal (predictions only).
 // ------------------------------------------------------------------------------
 struct RerollOut {
     float *pred;        // [N+1][PRED_STRIDE] owner's frame
@@ -944,22 +952,34 @@ struct RerollOut {
     bool final_shift;   // write the warm start (shifted) instead of the adopted sequence
 };
 
-template <int MODEL, int NDISC, int MAXOPP, int MODE, int NPF = 0>
-__device__ SampleResult reroll_block(const KParams &P, const LdsLayout &L, const BlockState &bs, char *lds,
-                                     const AgentRec &rec, uint32_t k, const RerollOut &out,
-                                     const float *cps = nullptr) {
+template <int MODEL, int MODE, int NPF = 0>
+__device__ void reroll_block(const KParams &P, const LdsLayout &L, const BlockState &bs, char *lds,
+                             const AgentRec &rec, uint32_t k, const RerollOut &out, const float *cps = nullptr) {
     const int tid = threadIdx.x, nth = blockDim.x, N = bs.N;
     const float2 *ubar = (const float2 *)(lds + L.ubar);
-    const float4 *xref = (const float4 *)(lds + L.xref);
-    const float2 *opp = (const float2 *)(lds + L.opp);
     const float4 *nodes = (const float4 *)(lds + L.nodes);
     float2 *wu = (float2 *)(lds + L.rr_u);
     float4 *wst = (float4 *)(lds + L.rr_st);  // [N][2]: (X, Y, PSI, VX), (VY, OM, -, -)
     float4 *wf = (float4 *)(lds + L.rr_f);    // [N]: (s, d, wL, wR)
-    float4 *wt = (float4 *)(lds + L.rr_t);    // [N]: (track, control, rate, boundary)
-    float *wg = (float *)(lds + L.rr_g);      // [N][MAXOPP]
-    int *wl = (int *)(lds + L.rr_l);          // [N] search-limit flags
     const VehConst<float> V = veh_f32(P);
+
+    // the pieces of the horizon and their starting states (checkpoints are read before
+    // the controls are drawn); the dynamic model puts each piece on two lanes, one axle each
+    constexpr int NC = ncp_of<NPF>();
+    const int nch = cps ? NC : 1;
+    const int C = cps ? (N + NC - 1) / NC : N;
+    constexpr int LPC = MODEL == 0 ? 2 : 1;  // lanes per piece
+    const bool chunk_lane = tid < LPC * nch;
+    const int ch = tid / LPC;
+    const bool rear = LPC == 2 && (tid & 1);
+    float st[6] = {0.0f, 0.0f, 0.0f, bs.vx0, bs.vy0, bs.om0};
+    int seg = bs.seg0;
+    if (chunk_lane && ch > 0) {
+        const float *c = cps + 7 * (ch - 1);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) st[i] = c[i];
+        seg = __float_as_int(c[6]);
+    }
 
     // A. controls of every step (one Philox call per pair of steps)
     for (int m = tid; 2 * m < N; m += nth) {
@@ -978,23 +998,8 @@ __device__ SampleResult reroll_block(const KParams &P, const LdsLayout &L, const
         }
     }
     __syncthreads();
-    // B. dynamics and projection, serial over the horizon; with the sample's checkpoints
-    //    (the lane's exact state and segment after steps C, 2C, 3C) NCP chunks of the
-    //    horizon run at once; the dynamic model puts each chunk on two lanes (one axle each)
-    const int nch = cps ? NCP : 1;
-    const int C = cps ? (N + NCP - 1) / NCP : N;
-    constexpr int LPC = MODEL == 0 ? 2 : 1;  // lanes per chunk
-    if (tid < LPC * nch) {
-        const int ch = tid / LPC;
-        const bool rear = LPC == 2 && (tid & 1);
-        float st[6] = {0.0f, 0.0f, 0.0f, bs.vx0, bs.vy0, bs.om0};
-        int seg = bs.seg0;
-        if (ch > 0) {
-            const float *c = cps + 7 * (ch - 1);
-#pragma unroll
-            for (int i = 0; i < 6; ++i) st[i] = c[i];
-            seg = __float_as_int(c[6]);
-        }
+    // B. dynamics and projection, serial within each piece
+    if (chunk_lane) {
         const int t_end = min((ch + 1) * C, N);
         for (int tau = ch * C; tau < t_end; ++tau) {
             NodeAhead<(NPF > 0 ? NPF : 1)> ahead;
@@ -1011,33 +1016,16 @@ __device__ SampleResult reroll_block(const KParams &P, const LdsLayout &L, const
                 wst[2 * tau] = make_float4(st[0], st[1], st[2], st[3]);
                 wst[2 * tau + 1] = make_float4(st[4], st[5], 0.0f, 0.0f);
                 wf[tau] = make_float4(f.s, f.d, f.wL, f.wR);
-                wl[tau] = f.limit ? 1 : 0;
             }
         }
     }
     __syncthreads();
-    // C. per-step terms, clearances and outputs, parallel over the horizon
+    // C. outputs, parallel over the horizon
     for (int tau = tid; tau < N; tau += nth) {
         const float4 a = wst[2 * tau], b = wst[2 * tau + 1];
         const float st[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
         const float4 fv = wf[tau];
         const float2 u = wu[tau];
-        if (MODE == WINNER) {
-            Foot f;
-            f.s = fv.x; f.d = fv.y; f.wL = fv.z; f.wR = fv.w;
-            wt[tau] = make_float4(track_term(P, st, xref[tau]), ctrl_term(P, u),
-                                  tau >= 1 ? rate_term(P, u, wu[tau - 1]) : 0.0f, bound_term(f));
-            float ch = 1.0f, sh = 0.0f;
-            if (NDISC > 1) {
-                ch = fast_cos(st[2]);
-                sh = fast_sin(st[2]);
-            }
-#pragma unroll
-            for (int j = 0; j < MAXOPP; ++j)
-                if (j < bs.n_opp)
-                    wg[tau * MAXOPP + j] = opp_min2<NDISC>(P, opp + ((size_t)tau * L.n_opp_max + j) * (NDISC + 1),
-                                                           st[0], st[1], ch, sh, P.cap2);
-        }
         float *pr = out.pred + (tau + 1) * PRED_STRIDE;
         pr[0] = st[0]; pr[1] = st[1]; pr[2] = fast_cos(st[2]); pr[3] = fast_sin(st[2]);
         pr[4] = fv.x; pr[5] = fv.y; pr[6] = 0.0f; pr[7] = 0.0f;
@@ -1065,57 +1053,6 @@ __device__ SampleResult reroll_block(const KParams &P, const LdsLayout &L, const
         if (out.u_apply) *out.u_apply = wu[0];
     }
     __syncthreads();
-    // D. score: the minima over the horizon by the first wave (exact in any order), the
-    //    two sums in the lanes' order by one lane, its LDS reads issued UB steps at a time
-    SampleResult res{};
-    if (MODE == WINNER && tid < 64) {
-        float rho_bd = INFINITY;
-        float g2[MAXOPP];
-#pragma unroll
-        for (int j = 0; j < MAXOPP; ++j) g2[j] = P.cap2;
-        bool lim = false;
-        for (int tau = tid; tau < N; tau += 64) {
-            rho_bd = fminf(rho_bd, wt[tau].w);
-#pragma unroll
-            for (int j = 0; j < MAXOPP; ++j)
-                if (j < bs.n_opp) g2[j] = fminf(g2[j], wg[tau * MAXOPP + j]);
-            lim |= wl[tau] != 0;
-        }
-        rho_bd = wave_min_f32(rho_bd);
-#pragma unroll
-        for (int j = 0; j < MAXOPP; ++j)
-            if (j < bs.n_opp) g2[j] = wave_min_f32(g2[j]);
-        const bool limit = __builtin_amdgcn_ballot_w64(lim) != 0;
-        if (tid == 0) {
-            constexpr int UB = 8;
-            float J = 0.0f, dsum = 0.0f;
-            for (int t0 = 0; t0 < N; t0 += UB) {
-                float4 tv[UB];
-#pragma unroll
-                for (int u = 0; u < UB; ++u) tv[u] = t0 + u < N ? wt[t0 + u] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-#pragma unroll
-                for (int u = 0; u < UB; ++u) {
-                    if (t0 + u < N) {
-                        J += tv[u].x;
-                        J += tv[u].y;
-                        if (t0 + u >= 1) J += tv[u].z;
-                    }
-                }
-            }
-            for (int t0 = max(0, N - bs.n_tail); t0 < N; t0 += UB) {
-                float dv[UB];
-#pragma unroll
-                for (int u = 0; u < UB; ++u) dv[u] = t0 + u < N ? wf[t0 + u].y : 0.0f;
-#pragma unroll
-                for (int u = 0; u < UB; ++u)
-                    if (t0 + u < N) dsum += dv[u];
-            }
-            const float4 a = wst[2 * (N - 1)], b = wst[2 * (N - 1) + 1];
-            const float st[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
-            res = terminal<MAXOPP>(P, bs, lds, L, J, rho_bd, dsum, wf[N - 1].x, g2, limit, st);
-        }
-    }
-    return res;
 }
 
 // ------------------------------------------------------------------------------
@@ -1216,12 +1153,14 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
         }
         if (pi) {
             pi_accumulate(A.P, bs, lds, A.L, valid ? k : 0u, valid, res, pa);
-        } else if (A.cp_slots && valid && key == wmin && !rear) {  // the wave's best sample keeps its checkpoints
+        } else if (valid && key == wmin && !rear) {  // the wave's best sample exports checkpoints and score
             float *slot = A.cp_slots + ((size_t)A.items[item].group0 + k / G) * CP_FLOATS;
 #pragma unroll
-            for (int c = 0; c < NCP - 1; ++c)
+            for (int c = 0; c < ncp_of<NPF>() - 1; ++c)
 #pragma unroll
                 for (int i = 0; i < 7; ++i) slot[7 * c + i] = res.cp[c][i];
+            slot[CP_COST] = res.cost;
+            slot[CP_VIOL] = res.viol;
         }
         if (valid && !rear) {
             if (A.dbg_cost) A.dbg_cost[k] = res.cost;
@@ -1262,6 +1201,10 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
             A.pi_part[(size_t)tile * pstride + threadIdx.x] = v;
         }
     }
+    // descriptors the hand-off needs, read by every workgroup before the counter
+    const ItemDev it = A.items[item];
+    const RaceDev R = A.races[it.race];
+    const AgentRec rec = A.agents[bs.slot];
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
@@ -1274,9 +1217,6 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
     const int nfeas = atomicAdd(A.nfeas + bs.slot, 0);
     uint32_t k = (uint32_t)(key & 0x7fffffffu);
     if (k >= (uint32_t)bs.K) k = 0;
-    const ItemDev it = A.items[item];
-    const RaceDev R = A.races[it.race];
-    const AgentRec rec = A.agents[bs.slot];
     RerollOut out{};
     out.pred = A.pred_out + (size_t)bs.slot * (A.L.N_max + 1) * PRED_STRIDE;
     const bool final_phase = A.final_mode == 2 || (A.final_mode == 1 && it.agent != R.ego);
@@ -1309,10 +1249,12 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
             if ((int)threadIdx.x < 2 * bs.N) ub[threadIdx.x] = sums[1 + threadIdx.x] / sums[0];
         }
         __syncthreads();
-        reroll_block<MODEL, NDISC, MAXOPP, NOMINAL, NPF>(A.P, A.L, bs, lds, rec, 0u, out);
+        reroll_block<MODEL, NOMINAL, NPF>(A.P, A.L, bs, lds, rec, 0u, out);
     } else {
-        const float *cps = A.cp_slots ? A.cp_slots + ((size_t)it.group0 + k / G) * CP_FLOATS : nullptr;
-        res = reroll_block<MODEL, NDISC, MAXOPP, WINNER, NPF>(A.P, A.L, bs, lds, rec, k, out, cps);
+        const float *cps = A.cp_slots + ((size_t)it.group0 + k / G) * CP_FLOATS;  // k's lane exported them
+        reroll_block<MODEL, WINNER, NPF>(A.P, A.L, bs, lds, rec, k, out, cps);
+        res.cost = cps[CP_COST];
+        res.viol = cps[CP_VIOL];
     }
     if (threadIdx.x == 0) {
         if (A.choice) {
@@ -1593,7 +1535,7 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
         const AgentRec rec = s_rec;
         RerollOut out{};
         out.pred = A.pred_out + (size_t)it.slot * (A.L.N_max + 1) * PRED_STRIDE;
-        reroll_block<MODEL, 1, 1, NOMINAL, 6>(A.P, A.L, bs, lds, rec, 0u, out);
+        reroll_block<MODEL, NOMINAL, 6>(A.P, A.L, bs, lds, rec, 0u, out);
         return;
     }
 
@@ -2057,12 +1999,12 @@ LdsLayout make_layout(const Plan &pl, int maxopp, int ndisc) {
     L.opp = take(pl.N_max * L.n_opp_max * (ndisc + 1) * 8);
     L.nodes = take(pl.w_max * 32);
     L.prop = take(pl.N_max * 16);
+    // rr_u..rr_f also hold the path-integral partials of a tile's four waves,
+    // 4 x (2N + 2) floats, which fit for every N >= 1
     L.rr_u = take(pl.N_max * 8);
     L.rr_st = take(pl.N_max * 32);
     L.rr_f = take(pl.N_max * 16);
     L.rr_t = take(pl.N_max * 16);
-    L.rr_g = take(pl.N_max * std::max(1, maxopp) * 4);
-    L.rr_l = take(pl.N_max * 4);
     L.total = off;
     return L;
 }
