@@ -57,15 +57,19 @@ enum Mode { SWEEP = 0, WINNER = 1, NOMINAL = 2 };
 // Kernel-side parameters (float32 with derived constants folded in)
 // ------------------------------------------------------------------------------
 struct KParams {
-    int model, n_disc, max_moves, update;  // update: 0 selection, 1 path-integral
+    // read in the sample loop (kept together: their scalar loads and registers stay compact)
     float dt, half_dt, dt6;
-    float a_min, a_max, d_min, d_max, sigma_a, sigma_d;
-    float Q0, Q1, Q2, Q3, R0, R1, S0, S1;
-    float w_game, w_contest, w_long, w_block, w_safety, s_contest, s_role, eps_alpha;
-    float g_safe, m_bd, d_col, cap2, skip2;
-    float off[4];
     float lf, lr, inv_m, inv_Iz, muFzf, muFzr, B, C, v_eps, C_rev;  // dynamic single-track
     float lr_over_L, inv_lr;                                 // kinematic bicycle
+    float a_min, a_max, d_min, d_max, sigma_a, sigma_d;
+    float Q0, Q1, Q2, Q3, R0, R1, S0, S1;
+    float cap2, skip2;
+    float off[4];
+    int max_moves;
+    // read once per sample or outside the loop
+    int model, n_disc, update;  // update: 0 selection, 1 path-integral
+    float w_game, w_contest, w_long, w_block, w_safety, s_contest, s_role, eps_alpha;
+    float g_safe, m_bd, d_col;
     float inv_lambda, w_viol;                                // path-integral update
     float pred_sig_lon, pred_sig_lat;                        // opponent-prediction perturbation
 };
@@ -421,6 +425,33 @@ __device__ __forceinline__ void rk4_pair(const VehConst<float> &V, const StepCon
     if (!(s[3] > 0.0f) && s[3] == s[3]) s[3] = 0.0f;
 }
 
+// A uniform 32-bit value moved into a scalar register of its own (an opaque copy): the
+// sample loop then holds single registers instead of the wide tuples that kernel
+// arguments are loaded into, and a spilled value is reloaded alone.
+template <class T>
+__device__ __forceinline__ T sreg(T v) {
+    static_assert(sizeof(T) == 4, "32-bit values only");
+    asm("" : "+s"(v));
+    return v;
+}
+
+// The fields of the parameters read inside the sample loop, each in its own register.
+__device__ __forceinline__ KParams loop_params(const KParams &P_in) {
+    KParams P = P_in;
+    P.dt = sreg(P.dt); P.half_dt = sreg(P.half_dt); P.dt6 = sreg(P.dt6);
+    P.lf = sreg(P.lf); P.lr = sreg(P.lr); P.inv_m = sreg(P.inv_m); P.inv_Iz = sreg(P.inv_Iz);
+    P.muFzf = sreg(P.muFzf); P.muFzr = sreg(P.muFzr); P.B = sreg(P.B); P.C = sreg(P.C);
+    P.v_eps = sreg(P.v_eps); P.C_rev = sreg(P.C_rev); P.lr_over_L = sreg(P.lr_over_L); P.inv_lr = sreg(P.inv_lr);
+    P.a_min = sreg(P.a_min); P.a_max = sreg(P.a_max); P.d_min = sreg(P.d_min); P.d_max = sreg(P.d_max);
+    P.sigma_a = sreg(P.sigma_a); P.sigma_d = sreg(P.sigma_d);
+    P.Q0 = sreg(P.Q0); P.Q1 = sreg(P.Q1); P.Q2 = sreg(P.Q2); P.Q3 = sreg(P.Q3);
+    P.R0 = sreg(P.R0); P.R1 = sreg(P.R1); P.S0 = sreg(P.S0); P.S1 = sreg(P.S1);
+    P.cap2 = sreg(P.cap2); P.skip2 = sreg(P.skip2);
+    P.off[0] = sreg(P.off[0]); P.off[1] = sreg(P.off[1]); P.off[2] = sreg(P.off[2]); P.off[3] = sreg(P.off[3]);
+    P.max_moves = sreg(P.max_moves);
+    return P;
+}
+
 __device__ __forceinline__ VehConst<float> veh_f32(const KParams &P) {
     VehConst<float> V;
     V.lf = P.lf; V.lr = P.lr; V.inv_m = P.inv_m; V.inv_Iz = P.inv_Iz; V.muFzf = P.muFzf; V.muFzr = P.muFzr;
@@ -660,6 +691,12 @@ __device__ void stage_block(const LaunchArgs &A, int item_idx, BlockState &bs, c
     float2 *ubar = (float2 *)(lds + L.ubar);
     float4 *xref = (float4 *)(lds + L.xref);
     float4 *nodes = (float4 *)(lds + L.nodes);
+    // window and reference rows: whole buffers (w_max, N_max rows), so these reads do not
+    // wait for the vehicle record; rows past the vehicle's own are never read
+    const float4 *wn = A.win + (size_t)it.slot * WIN_MAX * 2;
+    for (int t = tid; t < 2 * L.w_max; t += nth) nodes[t] = wn[t];
+    const float4 *xr = A.xref + (size_t)it.slot * L.N_max;
+    for (int t = tid; t < L.N_max; t += nth) xref[t] = xr[t];
     const float2 *un = (const float2 *)(R.u_nom) + (size_t)it.agent * R.N;
     for (int t = tid; t < R.N; t += nth) ubar[t] = un[t];
     if (R.prop) {
@@ -667,15 +704,20 @@ __device__ void stage_block(const LaunchArgs &A, int item_idx, BlockState &bs, c
         const float4 *src = R.prop + (size_t)it.agent * R.N;
         for (int t = tid; t < R.N; t += nth) pq[t] = src[t];
     }
-    const float4 *xr = A.xref + (size_t)it.slot * L.N_max;
-    for (int t = tid; t < R.N; t += nth) xref[t] = xr[t];
-    const float4 *wn = A.win + (size_t)it.slot * WIN_MAX * 2;
-    for (int t = tid; t < 2 * me.win_n; t += nth) nodes[t] = wn[t];
 
     if (bs.n_opp > 0) {
         float4 *oppT = (float4 *)(lds + L.oppT);
         float4 *oppc = (float4 *)(lds + L.oppc);
         float2 *opp = (float2 *)(lds + L.opp);
+        const int total = R.N * bs.n_opp;
+        // the first footprint row of this thread, read before the frames are known
+        float4 pre = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (tid < total) {
+            const int t = tid / bs.n_opp + 1;
+            const int jo = tid - (t - 1) * bs.n_opp;
+            const int j = jo < it.agent ? jo : jo + 1;
+            pre = *(const float4 *)(A.pred_in + (size_t)(R.slot0 + j) * pstride + t * PRED_STRIDE);
+        }
         if (tid < bs.n_opp) {
             const int j = tid < it.agent ? tid : tid + 1;
             const int sj = R.slot0 + j;
@@ -695,15 +737,15 @@ __device__ void stage_block(const LaunchArgs &A, int item_idx, BlockState &bs, c
             oppc[tid] = make_float4(sN, dsum / (float)R.n_tail, (float)((double)P.w_long * alpha), gam);
         }
         __syncthreads();
-        const int total = R.N * bs.n_opp;
         for (int e = tid; e < total; e += nth) {
             const int t = e / bs.n_opp + 1;  // tau = 1..N
             const int jo = e - (t - 1) * bs.n_opp;
             const int j = jo < it.agent ? jo : jo + 1;
-            const float *pr = A.pred_in + (size_t)(R.slot0 + j) * pstride + t * PRED_STRIDE;
+            const float4 pr = e == tid ? pre
+                                       : *(const float4 *)(A.pred_in + (size_t)(R.slot0 + j) * pstride + t * PRED_STRIDE);
             const float4 T = oppT[jo];
-            float px = pr[0], py = pr[1];
-            const float pc = pr[2], psn = pr[3];
+            float px = pr.x, py = pr.y;
+            const float pc = pr.z, psn = pr.w;
             if (P.pred_sig_lon > 0.0f || P.pred_sig_lat > 0.0f) {
                 // perturbed prediction (robustness experiment): a Gaussian pair of its own
                 // Philox counter moves the position along / across the predicted heading
@@ -765,24 +807,33 @@ __device__ __forceinline__ float bound_term(const Foot &f) { return fminf(f.wR +
 // folded into `cur` (values are capped at cap^2: only smaller ones change any result;
 // a pair is skipped when the centres are too far apart for any disc pair to go below it).
 template <int NDISC>
-__device__ __forceinline__ float opp_min2(const KParams &P, const float2 *e, float X, float Y, float ch, float sh,
-                                          float cur) {
+__device__ __forceinline__ float opp_min2(const KParams &P, const float2 *e, float X, float Y, const float *ax,
+                                          const float *ay, float cur) {
     const float2 cg = e[0];
     const float dx = X - cg.x, dy = Y - cg.y;
     if (dx * dx + dy * dy < P.skip2) {
 #pragma unroll
         for (int a = 0; a < NDISC; ++a) {
-            const float ax = __builtin_fmaf(P.off[a], ch, X);
-            const float ay = __builtin_fmaf(P.off[a], sh, Y);
 #pragma unroll
             for (int b = 0; b < NDISC; ++b) {
                 const float2 c = e[1 + b];
-                const float qx = ax - c.x, qy = ay - c.y;
+                const float qx = ax[a] - c.x, qy = ay[a] - c.y;
                 cur = fminf(cur, qx * qx + qy * qy);
             }
         }
     }
     return cur;
+}
+
+// Disc centres of the own footprint at (X, Y) with heading cosine / sine (ch, sh).
+template <int NDISC>
+__device__ __forceinline__ void disc_centres(const KParams &P, float X, float Y, float ch, float sh, float *ax,
+                                             float *ay) {
+#pragma unroll
+    for (int a = 0; a < NDISC; ++a) {
+        ax[a] = __builtin_fmaf(P.off[a], ch, X);
+        ay[a] = __builtin_fmaf(P.off[a], sh, Y);
+    }
 }
 
 struct SampleResult {
@@ -841,9 +892,10 @@ __device__ __forceinline__ SampleResult terminal(const KParams &P, const BlockSt
 // one sample; each lane draws one of the two Gaussian pairs of a Philox call and
 // evaluates one axle, the halves are swapped by DPP, and both lanes hold the same state.
 template <int MODEL, int NDISC, int MAXOPP, int NPF = 0, int LPS = 1>
-__device__ __forceinline__ SampleResult lane_sample(const KParams &P, const BlockState &bs, const char *lds,
+__device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const BlockState &bs, const char *lds,
                                                    const LdsLayout &L, uint32_t k, float *noise_out,
                                                    bool rear = false) {
+    const KParams P = loop_params(P_in);
     const float2 *ubar = (const float2 *)(lds + L.ubar);
     const float4 *xref = (const float4 *)(lds + L.xref);
     const float2 *opp = (const float2 *)(lds + L.opp);
@@ -858,7 +910,6 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P, const Bloc
     for (int j = 0; j < MAXOPP; ++j) g2[j] = P.cap2;
     float2 up = make_float2(0.0f, 0.0f);
     bool limit = false;
-    float2 zn = make_float2(0.0f, 0.0f);  // perturbation of the odd step of a Philox call
     constexpr int NC = ncp_of<NPF>();
     float cp[NC - 1][7];
 #pragma unroll
@@ -867,27 +918,25 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P, const Bloc
         for (int i = 0; i < 7; ++i) cp[c][i] = 0.0f;
     const int C = (bs.N + NC - 1) / NC;
 
-    for (int tau = 0; tau < bs.N; ++tau) {
+    // The Gaussian pairs of Philox call m drive steps 2m and 2m + 1.
+    auto draw = [&](int m, float2 &z0, float2 &z1) __attribute__((always_inline)) {
+        const uint4 r = philox4x32_10(make_uint4(k, (uint32_t)m, bs.ctr2, bs.ctr3), bs.key0, bs.key1);
+        if constexpr (LPS == 2) {
+            const float2 g = gauss_pair(rear ? r.z : r.x, rear ? r.w : r.y);
+            const float2 go = make_float2(dpp_swap_f32(g.x), dpp_swap_f32(g.y));
+            z0 = rear ? go : g;
+            z1 = rear ? g : go;
+        } else {
+            z0 = gauss_pair(r.x, r.y);
+            z1 = gauss_pair(r.z, r.w);
+        }
+    };
+    auto step = [&](int tau, float2 z) __attribute__((always_inline)) {
         // LDS reads that do not depend on this step's dynamics go first
         const float2 ub = ubar[tau];
         const float4 xr = xref[tau];
         NodeAhead<(NPF > 0 ? NPF : 1)> ahead;
         if constexpr (NPF > 0) ahead = read_ahead<NPF>(nodes, bs.W, seg);
-        float2 z;
-        if ((tau & 1) == 0) {
-            const uint4 r = philox4x32_10(make_uint4(k, (uint32_t)(tau >> 1), bs.ctr2, bs.ctr3), bs.key0, bs.key1);
-            if constexpr (LPS == 2) {
-                const float2 g = gauss_pair(rear ? r.z : r.x, rear ? r.w : r.y);
-                const float2 go = make_float2(dpp_swap_f32(g.x), dpp_swap_f32(g.y));
-                z = rear ? go : g;
-                zn = rear ? g : go;
-            } else {
-                z = gauss_pair(r.x, r.y);
-                zn = gauss_pair(r.z, r.w);
-            }
-        } else {
-            z = zn;
-        }
         if (noise_out) {
             noise_out[2 * tau] = z.x;
             noise_out[2 * tau + 1] = z.y;
@@ -914,19 +963,47 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P, const Bloc
             ch = fast_cos(st[2]);
             sh = fast_sin(st[2]);
         }
+        float ax[NDISC], ay[NDISC];
+        disc_centres<NDISC>(P, st[0], st[1], ch, sh, ax, ay);
 #pragma unroll
         for (int j = 0; j < MAXOPP; ++j)
             if (j < bs.n_opp)
-                g2[j] = opp_min2<NDISC>(P, opp + ((size_t)tau * L.n_opp_max + j) * (NDISC + 1), st[0], st[1], ch, sh,
+                g2[j] = opp_min2<NDISC>(P, opp + ((size_t)tau * L.n_opp_max + j) * (NDISC + 1), st[0], st[1], ax, ay,
                                         g2[j]);
         if (tau + 1 > bs.N - bs.n_tail) dsum += f.d;
+        // (C re-read at every step: the step counts (c + 1) C are not kept in registers)
+        int Cv = C;
+        asm volatile("" : "+s"(Cv));
 #pragma unroll
         for (int c = 0; c < NC - 1; ++c) {
-            if (tau + 1 == (c + 1) * C) {
+            if (tau + 1 == (c + 1) * Cv) {
 #pragma unroll
                 for (int i = 0; i < 6; ++i) cp[c][i] = st[i];
                 cp[c][6] = __int_as_float(seg);
             }
+        }
+    };
+
+    if constexpr (NPF > 0) {
+        // latency variants: the next Philox call is drawn beside the dynamics of the
+        // current pair of steps (one wave per SIMD: its chain fills their stalls)
+        float2 za, zb;
+        draw(0, za, zb);
+        for (int tau = 0; tau < bs.N; tau += 2) {
+            float2 na, nb;
+            draw((tau >> 1) + 1, na, nb);  // past the horizon on the last pair: unused
+            step(tau, za);
+            if (tau + 1 < bs.N) step(tau + 1, zb);
+            za = na;
+            zb = nb;
+        }
+    } else {
+        float2 zn = make_float2(0.0f, 0.0f);  // perturbation of the odd step of a Philox call
+        for (int tau = 0; tau < bs.N; ++tau) {
+            float2 z;
+            if ((tau & 1) == 0) draw(tau >> 1, z, zn);
+            else z = zn;
+            step(tau, z);
         }
     }
     SampleResult res = terminal<MAXOPP>(P, bs, lds, L, J, rho_bd, dsum, s, g2, limit, st);
@@ -1421,30 +1498,36 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
         return r;
     };
 
-    // 1. global projection: smallest |d| among enclosing segments, lowest index on ties
+    // 1. global projection: smallest |d| among enclosing segments, lowest index on ties.
+    //    Each thread takes a run of consecutive segments (its node reads, one more than
+    //    its segments, are issued UNR at a time); runs ascend with the thread index.
     double best = INFINITY;
     long long bi = -1;
-    constexpr int UNR = 4;  // segments per round whose node reads are issued together
-    for (long long i0 = tid; i0 < nseg; i0 += UNR * BLOCK) {
-        double g0[UNR], g1[UNR];
+    {
+        constexpr int UNR = 16;
+        const long long per = (nseg + BLOCK - 1) / BLOCK;
+        const long long i_lo = (long long)tid * per;
+        const long long i_hi = i_lo + per < nseg ? i_lo + per : nseg;
+        double gprev = i_lo < i_hi ? ahead(i_lo) : 0.0;
+        for (long long i0 = i_lo; i0 < i_hi; i0 += UNR) {
+            double g[UNR];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const long long i = i0 + (long long)u * BLOCK;
-            g0[u] = i < nseg ? ahead(i) : -1.0;
-            g1[u] = i < nseg ? ahead(i + 1) : 1.0;
-        }
+            for (int u = 0; u < UNR; ++u) g[u] = i0 + u < i_hi ? ahead(i0 + u + 1) : 0.0;
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const long long i = i0 + (long long)u * BLOCK;
-            if (i < nseg && g0[u] >= 0.0 && g1[u] <= 0.0) {
-                double o[6];
-                foot(i, o);
-                const double ad = fabs(o[1]);
-                if (ad < best) {
-                    best = ad;
-                    bi = i;
+            for (int u = 0; u < UNR; ++u) {
+                const long long i = i0 + u;
+                const double g0 = u == 0 ? gprev : g[u - 1];
+                if (i < i_hi && g0 >= 0.0 && g[u] <= 0.0) {
+                    double o[6];
+                    foot(i, o);
+                    const double ad = fabs(o[1]);
+                    if (ad < best) {
+                        best = ad;
+                        bi = i;
+                    }
                 }
             }
+            gprev = g[UNR - 1];
         }
     }
     long long seg = block_argmin(best, bi);
@@ -1744,14 +1827,16 @@ __global__ void k_bump_step(RaceDev *races, int n_races) {
     if (i < n_races) races[i].plan_step += 1u;
 }
 
-// Closed loop: one float64 RK4 interval per vehicle.
+// Closed loop: one float64 RK4 interval per vehicle.  With bump != NULL (a plan's step)
+// the thread of each race's first vehicle also advances the race's planning-step counter.
 template <int MODEL>
 __global__ void k_advance(const RaceDev *races, const ItemDev *items, int n_items, const float2 *u, VehConst<double> V,
-                          double dt) {
+                          double dt, RaceDev *bump) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_items) return;
     const ItemDev it = items[i];
     const RaceDev R = races[it.race];
+    if (bump && it.agent == 0) bump[it.race].plan_step = R.plan_step + 1u;
     double *x = R.x + (size_t)it.agent * 6;
     double s[6];
     for (int c = 0; c < 6; ++c) s[c] = x[c];
@@ -2306,17 +2391,17 @@ int plan_enqueue(sgtp_plan *P, hipStream_t st) {
         }
     }
     const int nr = (int)P->pl.races.size();
-    hipLaunchKernelGGL(k_bump_step, dim3((nr + 63) / 64), dim3(64), 0, st, P->d_races, nr);
-    HIPCHK(c, hipGetLastError());
-    if (P->opt.include_advance) {
+    if (P->opt.include_advance) {  // closed-loop step and the step counters in one launch
         if (P->p.model == 0)
             hipLaunchKernelGGL(k_advance<0>, dim3((nt + 63) / 64), dim3(64), 0, st, P->d_races, P->d_all, nt,
-                               (const float2 *)P->u_apply, make_veh64(&P->p), (double)P->p.dt);
+                               (const float2 *)P->u_apply, make_veh64(&P->p), (double)P->p.dt, P->d_races);
         else
             hipLaunchKernelGGL(k_advance<1>, dim3((nt + 63) / 64), dim3(64), 0, st, P->d_races, P->d_all, nt,
-                               (const float2 *)P->u_apply, make_veh64(&P->p), (double)P->p.dt);
-        HIPCHK(c, hipGetLastError());
+                               (const float2 *)P->u_apply, make_veh64(&P->p), (double)P->p.dt, P->d_races);
+    } else {
+        hipLaunchKernelGGL(k_bump_step, dim3((nr + 63) / 64), dim3(64), 0, st, P->d_races, nr);
     }
+    HIPCHK(c, hipGetLastError());
     return SGTP_OK;
 }
 
@@ -2540,9 +2625,9 @@ int sgtp_advance(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int 
     const int nt = pl.agents_total;
     const VehConst<double> V = make_veh64(p);
     if (p->model == 0)
-        hipLaunchKernelGGL(k_advance<0>, dim3((nt + 63) / 64), dim3(64), 0, st, dr, da, nt, (const float2 *)u, V, (double)p->dt);
+        hipLaunchKernelGGL(k_advance<0>, dim3((nt + 63) / 64), dim3(64), 0, st, dr, da, nt, (const float2 *)u, V, (double)p->dt, nullptr);
     else
-        hipLaunchKernelGGL(k_advance<1>, dim3((nt + 63) / 64), dim3(64), 0, st, dr, da, nt, (const float2 *)u, V, (double)p->dt);
+        hipLaunchKernelGGL(k_advance<1>, dim3((nt + 63) / 64), dim3(64), 0, st, dr, da, nt, (const float2 *)u, V, (double)p->dt, nullptr);
     HIPCHK(c, hipGetLastError());
     return SGTP_OK;
 }
