@@ -895,7 +895,11 @@ template <int MODEL, int NDISC, int MAXOPP, int NPF = 0, int LPS = 1>
 __device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const BlockState &bs, const char *lds,
                                                    const LdsLayout &L, uint32_t k, float *noise_out,
                                                    bool rear = false) {
-    const KParams P = loop_params(P_in);
+    // (throughput variants: parameters in single scalar registers; the latency variants,
+    // one wave per SIMD, measured faster with the compiler's own allocation)
+    // parameters in single scalar registers, except in the one-lane latency variant
+    // (about one wave per SIMD), which measured faster with the compiler's own allocation
+    const KParams P = (NPF > 0 && LPS == 1) ? P_in : loop_params(P_in);
     const float2 *ubar = (const float2 *)(lds + L.ubar);
     const float4 *xref = (const float4 *)(lds + L.xref);
     const float2 *opp = (const float2 *)(lds + L.opp);
@@ -918,105 +922,74 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const B
         for (int i = 0; i < 7; ++i) cp[c][i] = 0.0f;
     const int C = (bs.N + NC - 1) / NC;
 
-    // The Gaussian pairs of Philox call m drive steps 2m and 2m + 1.
-    auto draw = [&](int m, float2 &z0, float2 &z1) __attribute__((always_inline)) {
-        const uint4 r = philox4x32_10(make_uint4(k, (uint32_t)m, bs.ctr2, bs.ctr3), bs.key0, bs.key1);
-        if constexpr (LPS == 2) {
-            const float2 g = gauss_pair(rear ? r.z : r.x, rear ? r.w : r.y);
-            const float2 go = make_float2(dpp_swap_f32(g.x), dpp_swap_f32(g.y));
-            z0 = rear ? go : g;
-            z1 = rear ? g : go;
-        } else {
-            z0 = gauss_pair(r.x, r.y);
-            z1 = gauss_pair(r.z, r.w);
-        }
-    };
-    // One step of the sample (the loops below expand it in place; as a lambda the
-    // compiler kept more registers live in the throughput variants).
-#define SGTP_SAMPLE_STEP(TAU, Z)                                                                                        \
-    {                                                                                                                   \
-        const int tau_ = (TAU);                                                                                         \
-        const float2 z_ = (Z);                                                                                          \
-        /* LDS reads that do not depend on this step's dynamics go first */                                             \
-        const float2 ub = ubar[tau_];                                                                                   \
-        const float4 xr = xref[tau_];                                                                                   \
-        NodeAhead<(NPF > 0 ? NPF : 1)> ahead;                                                                           \
-        if constexpr (NPF > 0) ahead = read_ahead<NPF>(nodes, bs.W, seg);                                               \
-        if (noise_out) {                                                                                                \
-            noise_out[2 * tau_] = z_.x;                                                                                 \
-            noise_out[2 * tau_ + 1] = z_.y;                                                                             \
-        }                                                                                                               \
-        const float2 u = controls_k(P, bs, lds, L, k, tau_, ub, z_.x, z_.y);                                            \
-        /* latency variants (NPF > 0) branch-free, throughput variants with the uniform atan */                         \
-        using MS = typename std::conditional<NPF == 0, MathF32U, MathF32>::type;                                        \
-        const StepConst<float> sc = step_const<MODEL, MS>(V, u.x, u.y);                                                 \
-        if constexpr (LPS == 2 && MODEL == 0) rk4_pair(V, sc, P.dt, st, rear);                                          \
-        else rk4<MODEL, MS>(V, sc, P.dt, st);                                                                           \
-        Foot f;                                                                                                         \
-        if constexpr (NPF > 0) f = project_ahead<NPF>(nodes, bs.W, P.max_moves, st[0], st[1], seg, ahead);              \
-        else f = project(nodes, bs.W, P.max_moves, st[0], st[1], seg);                                                  \
-        seg = f.seg;                                                                                                    \
-        limit |= f.limit;                                                                                               \
-        s = f.s;                                                                                                        \
-        J += track_term(P, st, xr);                                                                                     \
-        J += ctrl_term(P, u);                                                                                           \
-        if (tau_ >= 1) J += rate_term(P, u, up);                                                                        \
-        up = u;                                                                                                         \
-        rho_bd = fminf(rho_bd, bound_term(f));                                                                          \
-        float ch = 1.0f, sh = 0.0f;                                                                                     \
-        if (NDISC > 1) {                                                                                                \
-            ch = fast_cos(st[2]);                                                                                       \
-            sh = fast_sin(st[2]);                                                                                       \
-        }                                                                                                               \
-        float ax[NDISC], ay[NDISC];                                                                                     \
-        disc_centres<NDISC>(P, st[0], st[1], ch, sh, ax, ay);                                                           \
-        _Pragma("unroll")                                                                                               \
-        for (int j = 0; j < MAXOPP; ++j)                                                                                \
-            if (j < bs.n_opp)                                                                                           \
-                g2[j] = opp_min2<NDISC>(P, opp + ((size_t)tau_ * L.n_opp_max + j) * (NDISC + 1), st[0], st[1], ax, ay,  \
-                                        g2[j]);                                                                         \
-        if (tau_ + 1 > bs.N - bs.n_tail) dsum += f.d;                                                                   \
-        /* (C re-read at every step: the step counts (c + 1) C are not kept in registers) */                            \
-        int Cv = C;                                                                                                     \
-        asm volatile("" : "+s"(Cv));                                                                                    \
-        _Pragma("unroll")                                                                                               \
-        for (int c = 0; c < NC - 1; ++c) {                                                                              \
-            if (tau_ + 1 == (c + 1) * Cv) {                                                                             \
-                _Pragma("unroll")                                                                                       \
-                for (int i = 0; i < 6; ++i) cp[c][i] = st[i];                                                           \
-                cp[c][6] = __int_as_float(seg);                                                                         \
-            }                                                                                                           \
-        }                                                                                                               \
-    }
-
-    if constexpr (NPF > 0) {
-        // latency variants: the next Philox call is drawn beside the dynamics of the
-        // current pair of steps (one wave per SIMD: its chain fills their stalls)
-        float2 za, zb;
-        draw(0, za, zb);
-        for (int tau = 0; tau < bs.N; tau += 2) {
-            float2 na, nb;
-            draw((tau >> 1) + 1, na, nb);  // past the horizon on the last pair: unused
-            SGTP_SAMPLE_STEP(tau, za);
-            if (tau + 1 < bs.N) SGTP_SAMPLE_STEP(tau + 1, zb);
-            za = na;
-            zb = nb;
-        }
-    } else {
-        float2 zn = make_float2(0.0f, 0.0f);  // perturbation of the odd step of a Philox call
-        for (int tau = 0; tau < bs.N; ++tau) {
-            float2 z;
-            if ((tau & 1) == 0) {
-                const uint4 r = philox4x32_10(make_uint4(k, (uint32_t)(tau >> 1), bs.ctr2, bs.ctr3), bs.key0, bs.key1);
+    float2 zn = make_float2(0.0f, 0.0f);  // perturbation of the odd step of a Philox call
+    for (int tau = 0; tau < bs.N; ++tau) {
+        float2 z;
+        if ((tau & 1) == 0) {
+            const uint4 r = philox4x32_10(make_uint4(k, (uint32_t)(tau >> 1), bs.ctr2, bs.ctr3), bs.key0, bs.key1);
+            if constexpr (LPS == 2) {
+                const float2 g = gauss_pair(rear ? r.z : r.x, rear ? r.w : r.y);
+                const float2 go = make_float2(dpp_swap_f32(g.x), dpp_swap_f32(g.y));
+                z = rear ? go : g;
+                zn = rear ? g : go;
+            } else {
                 z = gauss_pair(r.x, r.y);
                 zn = gauss_pair(r.z, r.w);
-            } else {
-                z = zn;
             }
-            SGTP_SAMPLE_STEP(tau, z);
+        } else {
+            z = zn;
+        }
+        // LDS reads that do not depend on this step's dynamics go first
+        const float2 ub = ubar[tau];
+        const float4 xr = xref[tau];
+        NodeAhead<(NPF > 0 ? NPF : 1)> ahead;
+        if constexpr (NPF > 0) ahead = read_ahead<NPF>(nodes, bs.W, seg);
+        if (noise_out) {
+            noise_out[2 * tau] = z.x;
+            noise_out[2 * tau + 1] = z.y;
+        }
+        const float2 u = controls_k(P, bs, lds, L, k, tau, ub, z.x, z.y);
+        // latency variants (NPF > 0) branch-free, throughput variants with the uniform atan
+        using MS = typename std::conditional<NPF == 0, MathF32U, MathF32>::type;
+        const StepConst<float> sc = step_const<MODEL, MS>(V, u.x, u.y);
+        if constexpr (LPS == 2 && MODEL == 0) rk4_pair(V, sc, P.dt, st, rear);
+        else rk4<MODEL, MS>(V, sc, P.dt, st);
+        Foot f;
+        if constexpr (NPF > 0) f = project_ahead<NPF>(nodes, bs.W, P.max_moves, st[0], st[1], seg, ahead);
+        else f = project(nodes, bs.W, P.max_moves, st[0], st[1], seg);
+        seg = f.seg;
+        limit |= f.limit;
+        s = f.s;
+        J += track_term(P, st, xr);
+        J += ctrl_term(P, u);
+        if (tau >= 1) J += rate_term(P, u, up);
+        up = u;
+        rho_bd = fminf(rho_bd, bound_term(f));
+        float ch = 1.0f, sh = 0.0f;
+        if (NDISC > 1) {
+            ch = fast_cos(st[2]);
+            sh = fast_sin(st[2]);
+        }
+        float ax[NDISC], ay[NDISC];
+        disc_centres<NDISC>(P, st[0], st[1], ch, sh, ax, ay);
+#pragma unroll
+        for (int j = 0; j < MAXOPP; ++j)
+            if (j < bs.n_opp)
+                g2[j] = opp_min2<NDISC>(P, opp + ((size_t)tau * L.n_opp_max + j) * (NDISC + 1), st[0], st[1], ax, ay,
+                                        g2[j]);
+        if (tau + 1 > bs.N - bs.n_tail) dsum += f.d;
+        // (C re-read at every step: the step counts (c + 1) C are not kept in registers)
+        int Cv = C;
+        asm volatile("" : "+s"(Cv));
+#pragma unroll
+        for (int c = 0; c < NC - 1; ++c) {
+            if (tau + 1 == (c + 1) * Cv) {
+#pragma unroll
+                for (int i = 0; i < 6; ++i) cp[c][i] = st[i];
+                cp[c][6] = __int_as_float(seg);
+            }
         }
     }
-#undef SGTP_SAMPLE_STEP
     SampleResult res = terminal<MAXOPP>(P, bs, lds, L, J, rho_bd, dsum, s, g2, limit, st);
 #pragma unroll
     for (int c = 0; c < NC - 1; ++c)
