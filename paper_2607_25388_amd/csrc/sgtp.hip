@@ -1268,12 +1268,14 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
     const AgentRec rec = A.agents[bs.slot];
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
+        // release: the workgroup's key, count, slot and partial writes before its count
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         *s_last = atomicAdd(A.counters + bs.slot, 1) == n_tiles_item - 1;
     }
     __syncthreads();
     if (!*s_last) return;
-    __threadfence();
+    // acquire: every other workgroup's writes of this vehicle are visible from here
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const unsigned long long key = atomicMin(A.keys + bs.slot, KEY_NONE);  // current value
     const int nfeas = atomicAdd(A.nfeas + bs.slot, 0);
     uint32_t k = (uint32_t)(key & 0x7fffffffu);
