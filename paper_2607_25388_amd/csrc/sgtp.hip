@@ -504,37 +504,34 @@ __device__ __forceinline__ Foot foot_on(const float4 *__restrict__ nodes, float 
 }
 
 // Segment search from `seg` (at most max_moves moves, inside the window), then the foot.
+// The search carries only the signed distances; the geometry rows of the final segment
+// are read again together with its second rows.
 __device__ __forceinline__ Foot project(const float4 *__restrict__ nodes, int W, int max_moves, float X, float Y,
                                         int seg) {
     int moves = 0;
-    float4 A0 = nodes[2 * seg], A1 = nodes[2 * seg + 2];
-    float g1 = ahead_of(A1, X, Y);
+    float g1 = ahead_of(nodes[2 * seg + 2], X, Y);
     float g0;
     bool fwd = false;
     while (moves < max_moves && seg + 1 <= W - 2 && g1 > 0.0f) {
         ++seg;
         ++moves;
-        A0 = A1;
-        A1 = nodes[2 * seg + 2];
         g0 = g1;
-        g1 = ahead_of(A1, X, Y);
+        g1 = ahead_of(nodes[2 * seg + 2], X, Y);
         fwd = true;
     }
-    if (!fwd) g0 = ahead_of(A0, X, Y);
+    if (!fwd) g0 = ahead_of(nodes[2 * seg], X, Y);
     while (moves < max_moves && seg > 0 && g0 < 0.0f) {
         --seg;
         ++moves;
-        A1 = A0;
         g1 = g0;
-        A0 = nodes[2 * seg];
-        g0 = ahead_of(A0, X, Y);
+        g0 = ahead_of(nodes[2 * seg], X, Y);
     }
-    return foot_on(nodes, X, Y, seg, A0, A1, g0, g1);
+    return foot_on(nodes, X, Y, seg, nodes[2 * seg], nodes[2 * seg + 2], g0, g1);
 }
 
 // The same search with the geometry rows of segments seg .. seg + NPF - 1 read ahead
 // (before the step's dynamics, so their LDS latency is hidden): the first NPF - 2
-// forward moves run on registers, further moves read LDS.  Same states, same result.
+// forward moves are decided on registers, further moves read LDS.  Same result.
 template <int NPF>
 struct NodeAhead {
     float4 q[NPF];
@@ -549,42 +546,33 @@ __device__ __forceinline__ NodeAhead<NPF> read_ahead(const float4 *__restrict__ 
 template <int NPF>
 __device__ __forceinline__ Foot project_ahead(const float4 *__restrict__ nodes, int W, int max_moves, float X,
                                               float Y, int seg, const NodeAhead<NPF> &a) {
+    float g[NPF];
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) g[i] = ahead_of(a.q[i], X, Y);
     int moves = 0;
-    float4 A0 = a.q[0], A1 = a.q[1];
-    float g1 = ahead_of(A1, X, Y);
-    float g0 = 0.0f;
-    bool fwd = false, go = true;
+    float g0 = g[0], g1 = g[1];
+    bool go = true;
 #pragma unroll
     for (int i = 1; i < NPF - 1; ++i) {
         go = go && moves < max_moves && seg + 1 <= W - 2 && g1 > 0.0f;
-        if (go) {
-            ++seg;
-            ++moves;
-            A0 = A1;
-            A1 = a.q[i + 1];
-            g0 = g1;
-            g1 = ahead_of(A1, X, Y);
-            fwd = true;
-        }
+        seg += go ? 1 : 0;
+        moves += go ? 1 : 0;
+        g0 = go ? g1 : g0;
+        g1 = go ? g[i + 1] : g1;
     }
     while (go && moves < max_moves && seg + 1 <= W - 2 && g1 > 0.0f) {
         ++seg;
         ++moves;
-        A0 = A1;
-        A1 = nodes[2 * seg + 2];
         g0 = g1;
-        g1 = ahead_of(A1, X, Y);
+        g1 = ahead_of(nodes[2 * seg + 2], X, Y);
     }
-    if (!fwd) g0 = ahead_of(A0, X, Y);
     while (moves < max_moves && seg > 0 && g0 < 0.0f) {
         --seg;
         ++moves;
-        A1 = A0;
         g1 = g0;
-        A0 = nodes[2 * seg];
-        g0 = ahead_of(A0, X, Y);
+        g0 = ahead_of(nodes[2 * seg], X, Y);
     }
-    return foot_on(nodes, X, Y, seg, A0, A1, g0, g1);
+    return foot_on(nodes, X, Y, seg, nodes[2 * seg], nodes[2 * seg + 2], g0, g1);
 }
 
 // ------------------------------------------------------------------------------
