@@ -219,9 +219,13 @@ __device__ __forceinline__ float2 gauss_pair(uint32_t r_even, uint32_t r_odd) {
     pc = __builtin_fmaf(pc, r2, C4);
     pc = __builtin_fmaf(pc, r2, C2);
     const float cs = __builtin_fmaf(pc, r2, 1.0f);
+    // quarter turns: (sin, cos) = (sn, cs), (cs, -sn), (-sn, -cs), (-cs, sn) for qq = 0..3;
+    // the signs as sign-bit flips (exact), no branches
     const uint32_t qq = q & 3u;
-    const float sin_t = (qq == 0) ? sn : (qq == 1) ? cs : (qq == 2) ? -sn : -cs;
-    const float cos_t = (qq == 0) ? cs : (qq == 1) ? -sn : (qq == 2) ? -cs : sn;
+    const bool odd = (qq & 1u) != 0u;
+    const float sa = odd ? cs : sn, ca = odd ? sn : cs;
+    const float sin_t = __uint_as_float(__float_as_uint(sa) ^ ((qq & 2u) << 30));
+    const float cos_t = __uint_as_float(__float_as_uint(ca) ^ (((qq + 1u) & 2u) << 30));
     return make_float2(rho * cos_t, rho * sin_t);
 }
 
