@@ -109,6 +109,7 @@ struct AgentRec {  // per vehicle, written by k_setup
 struct LdsLayout {  // byte offsets of the staged tables, identical for every block of a launch
     int ubar, xref, oppT, oppc, opp, nodes, prop;
     int rr_u, rr_st, rr_f, rr_t;  // re-roll scratch (rr_t: setup's reference recursion)
+    int rr_sync;                  // re-roll: states written per piece (NCP_MAX ints)
     int total;
     int n_opp_max, w_max, N_max;
 };
@@ -1025,14 +1026,20 @@ __device__ void reroll_block(const KParams &P, const LdsLayout &L, const BlockSt
     const bool chunk_lane = tid < LPC * nch;
     const int ch = tid / LPC;
     const bool rear = LPC == 2 && (tid & 1);
+    // the projection of each piece runs on a lane of the second wave, one step behind
+    // its dynamics (which do not need it); prog[piece] counts the states written
+    const bool proj_lane = tid >= 64 && tid < 64 + nch;
+    const int pch = tid - 64;
+    volatile int *prog = (volatile int *)(lds + L.rr_sync);
     float st[6] = {0.0f, 0.0f, 0.0f, bs.vx0, bs.vy0, bs.om0};
     int seg = bs.seg0;
     if (chunk_lane && ch > 0) {
         const float *c = cps + 7 * (ch - 1);
 #pragma unroll
         for (int i = 0; i < 6; ++i) st[i] = c[i];
-        seg = __float_as_int(c[6]);
     }
+    if (proj_lane && pch > 0) seg = __float_as_int(cps[7 * (pch - 1) + 6]);
+    if (tid < nch) prog[tid] = tid * C;
 
     // A. controls of every step (one Philox call per pair of steps)
     for (int m = tid; 2 * m < N; m += nth) {
@@ -1051,25 +1058,35 @@ __device__ void reroll_block(const KParams &P, const LdsLayout &L, const BlockSt
         }
     }
     __syncthreads();
-    // B. dynamics and projection, serial within each piece
+    // B. dynamics (first wave) and projection (second wave), serial within each piece
     if (chunk_lane) {
         const int t_end = min((ch + 1) * C, N);
         for (int tau = ch * C; tau < t_end; ++tau) {
-            NodeAhead<(NPF > 0 ? NPF : 1)> ahead;
-            if constexpr (NPF > 0) ahead = read_ahead<NPF>(nodes, bs.W, seg);
             const float2 u = wu[tau];
             const StepConst<float> sc = step_const<MODEL, MathF32>(V, u.x, u.y);
             if constexpr (MODEL == 0) rk4_pair(V, sc, P.dt, st, rear);
             else rk4<MODEL, MathF32>(V, sc, P.dt, st);
-            Foot f;
-            if constexpr (NPF > 0) f = project_ahead<NPF>(nodes, bs.W, P.max_moves, st[0], st[1], seg, ahead);
-            else f = project(nodes, bs.W, P.max_moves, st[0], st[1], seg);
-            seg = f.seg;
             if (!rear) {
                 wst[2 * tau] = make_float4(st[0], st[1], st[2], st[3]);
                 wst[2 * tau + 1] = make_float4(st[4], st[5], 0.0f, 0.0f);
-                wf[tau] = make_float4(f.s, f.d, f.wL, f.wR);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                prog[ch] = tau + 1;
             }
+        }
+    } else if (proj_lane) {
+        const int t_end = min((pch + 1) * C, N);
+        for (int tau = pch * C; tau < t_end; ++tau) {
+            NodeAhead<(NPF > 0 ? NPF : 1)> ahead;
+            if constexpr (NPF > 0) ahead = read_ahead<NPF>(nodes, bs.W, seg);
+            // the dynamics lanes never wait, so this wait ends; the bound is a guard only
+            for (int spin = 0; prog[pch] <= tau && spin < (1 << 22); ++spin) __builtin_amdgcn_s_sleep(1);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            const float4 xy = wst[2 * tau];
+            Foot f;
+            if constexpr (NPF > 0) f = project_ahead<NPF>(nodes, bs.W, P.max_moves, xy.x, xy.y, seg, ahead);
+            else f = project(nodes, bs.W, P.max_moves, xy.x, xy.y, seg);
+            seg = f.seg;
+            wf[tau] = make_float4(f.s, f.d, f.wL, f.wR);
         }
     }
     __syncthreads();
@@ -2068,6 +2085,7 @@ LdsLayout make_layout(const Plan &pl, int maxopp, int ndisc) {
     L.rr_st = take(pl.N_max * 32);
     L.rr_f = take(pl.N_max * 16);
     L.rr_t = take(pl.N_max * 16);
+    L.rr_sync = take(NCP_MAX * 4);
     L.total = off;
     return L;
 }
