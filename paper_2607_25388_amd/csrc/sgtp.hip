@@ -730,12 +730,8 @@ __device__ void stage_block(const LaunchArgs &A, int item_idx, BlockState &bs, c
             oppc[tid] = make_float4(sN, dsum / (float)R.n_tail, (float)((double)P.w_long * alpha), gam);
         }
         __syncthreads();
-        for (int e = tid; e < total; e += nth) {
-            const int t = e / bs.n_opp + 1;  // tau = 1..N
-            const int jo = e - (t - 1) * bs.n_opp;
-            const int j = jo < it.agent ? jo : jo + 1;
-            const float4 pr = e == tid ? pre
-                                       : *(const float4 *)(A.pred_in + (size_t)(R.slot0 + j) * pstride + t * PRED_STRIDE);
+        // footprint rows of opponent j at step t in this vehicle's frame
+        auto footprint = [&](int t, int jo, int j, float4 pr) {
             const float4 T = oppT[jo];
             float px = pr.x, py = pr.y;
             const float pc = pr.z, psn = pr.w;
@@ -756,6 +752,17 @@ __device__ void stage_block(const LaunchArgs &A, int item_idx, BlockState &bs, c
                 const float cxj = __builtin_fmaf(P.off[b], pc, px), cyj = __builtin_fmaf(P.off[b], psn, py);
                 dst[1 + b] = make_float2(T.x * cxj - T.y * cyj + T.z, T.y * cxj + T.x * cyj + T.w);
             }
+        };
+        if (tid < total) {
+            const int t = tid / bs.n_opp + 1;
+            const int jo = tid - (t - 1) * bs.n_opp;
+            footprint(t, jo, jo < it.agent ? jo : jo + 1, pre);
+        }
+        for (int e = tid + nth; e < total; e += nth) {
+            const int t = e / bs.n_opp + 1;  // tau = 1..N
+            const int jo = e - (t - 1) * bs.n_opp;
+            const int j = jo < it.agent ? jo : jo + 1;
+            footprint(t, jo, j, *(const float4 *)(A.pred_in + (size_t)(R.slot0 + j) * pstride + t * PRED_STRIDE));
         }
     }
     __syncthreads();
