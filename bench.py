@@ -34,11 +34,10 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak
 # instructions of SQ_INSTS_VALU_*_F32.  They describe the kernel source with this SHA-256
 # only; any other source reports null.
 SWEEP_COUNTERS = {
-    "c2": {"source_sha256": "7710548e388a5e0619dedab86b51915a3690364fdbda0fc084f4335ff25f8c7b",
-           "hbm_bytes_per_launch": (354.125 * 1.99981 + 300.574) * 1024.0,
-           "hw_fp32_flop_per_launch": 1.2334e9, "valu_wave_insts_per_launch": 21.28e6},
+    "c2": {"source_sha256": "a1110f94e51e7b4958a13414532abc92cad4ae8408db933934cdedfa41f08764",
+           "hbm_bytes_per_launch": (387.991 * 1.99976 + 237.478) * 1024.0,
+           "hw_fp32_flop_per_launch": 1.2458e9, "valu_wave_insts_per_launch": 20.55e6},
 }
-
 
 def _source_sha256() -> str:
     import hashlib
