@@ -807,9 +807,8 @@ __device__ __forceinline__ float bound_term(const Foot &f) { return fminf(f.wR +
 // folded into `cur` (values are capped at cap^2: only smaller ones change any result;
 // a pair is skipped when the centres are too far apart for any disc pair to go below it).
 template <int NDISC>
-__device__ __forceinline__ float opp_min2(const KParams &P, const float2 *e, float X, float Y, const float *ax,
-                                          const float *ay, float cur) {
-    const float2 cg = e[0];
+__device__ __forceinline__ float opp_min2(const KParams &P, const float2 *e, float2 cg, float X, float Y,
+                                          const float *ax, const float *ay, float cur) {
     const float dx = X - cg.x, dy = Y - cg.y;
     if (dx * dx + dy * dy < P.skip2) {
 #pragma unroll
@@ -970,13 +969,20 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const B
             ch = fast_cos(st[2]);
             sh = fast_sin(st[2]);
         }
+        // the opponents' rows of this step (up to 3 opponents every centre is read first,
+        // all within the table; more would hold too many registers)
+        const float2 *ot = opp + tau * (L.n_opp_max * (NDISC + 1));
+        constexpr int NPRE = MAXOPP <= 3 ? MAXOPP : 1;
+        float2 cg[NPRE];
+#pragma unroll
+        for (int j = 0; j < NPRE; ++j) cg[j] = ot[j * (NDISC + 1)];
         float ax[NDISC], ay[NDISC];
         disc_centres<NDISC>(P, st[0], st[1], ch, sh, ax, ay);
 #pragma unroll
         for (int j = 0; j < MAXOPP; ++j)
             if (j < bs.n_opp)
-                g2[j] = opp_min2<NDISC>(P, opp + ((size_t)tau * L.n_opp_max + j) * (NDISC + 1), st[0], st[1], ax, ay,
-                                        g2[j]);
+                g2[j] = opp_min2<NDISC>(P, ot + j * (NDISC + 1), MAXOPP <= 3 ? cg[j < NPRE ? j : 0] : ot[j * (NDISC + 1)],
+                                        st[0], st[1], ax, ay, g2[j]);
         if (tau + 1 > bs.N - bs.n_tail) dsum += f.d;
         // (C re-read at every step: the step counts (c + 1) C are not kept in registers)
         int Cv = C;
