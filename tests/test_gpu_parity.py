@@ -143,7 +143,11 @@ PERTURB = {"pred_sig_lon": 0.5, "pred_sig_lat": 0.3}
 
 
 @pytest.mark.parametrize("name,K,L,over", [("c1", 1024, 3, None), ("c2", 1024, 2, None), ("c3", 512, 1, PERTURB),
-                                           ("c1", 1024, 2, PERTURB)])
+                                           ("c1", 1024, 2, PERTURB),
+                                           # full sizes, same kernels as the timed planning steps:
+                                           # mid-scale latency variant (3 x 16384 lanes), large-field
+                                           # throughput variant (10 x 65536 lanes)
+                                           ("c2", 16384, 5, None), ("c3", 65536, 1, None)])
 def test_plan_step_lockstep(planner, name, K, L, over):
     """Alg. 1 on the GPU; the oracle replays it adopting the GPU's choices phase by phase
     and must agree with each choice (or find it a near-tie)."""
