@@ -943,6 +943,14 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const B
         const float4 xr = xref[tau];
         NodeAhead<(NPF > 0 ? NPF : 1)> ahead;
         if constexpr (NPF > 0) ahead = read_ahead<NPF>(nodes, bs.W, seg);
+        // the opponents' rows of this step; the latency variants read them whole here
+        const float2 *ot = opp + tau * (L.n_opp_max * (NDISC + 1));
+        constexpr bool PRE_ALL = NPF > 0 && MAXOPP <= 3;
+        float2 orow[PRE_ALL ? MAXOPP * (NDISC + 1) : 1];
+        if constexpr (PRE_ALL) {
+#pragma unroll
+            for (int i = 0; i < MAXOPP * (NDISC + 1); ++i) orow[i] = ot[i];
+        }
         if (noise_out) {
             noise_out[2 * tau] = z.x;
             noise_out[2 * tau + 1] = z.y;
@@ -969,20 +977,28 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const B
             ch = fast_cos(st[2]);
             sh = fast_sin(st[2]);
         }
-        // the opponents' rows of this step (up to 3 opponents every centre is read first,
+        // (other variants with up to 3 opponents read every centre before the first test,
         // all within the table; more would hold too many registers)
-        const float2 *ot = opp + tau * (L.n_opp_max * (NDISC + 1));
-        constexpr int NPRE = MAXOPP <= 3 ? MAXOPP : 1;
+        constexpr int NPRE = (!PRE_ALL && MAXOPP <= 3) ? MAXOPP : 1;
         float2 cg[NPRE];
+        if constexpr (!PRE_ALL && MAXOPP <= 3) {
 #pragma unroll
-        for (int j = 0; j < NPRE; ++j) cg[j] = ot[j * (NDISC + 1)];
+            for (int j = 0; j < NPRE; ++j) cg[j] = ot[j * (NDISC + 1)];
+        }
         float ax[NDISC], ay[NDISC];
         disc_centres<NDISC>(P, st[0], st[1], ch, sh, ax, ay);
 #pragma unroll
-        for (int j = 0; j < MAXOPP; ++j)
-            if (j < bs.n_opp)
-                g2[j] = opp_min2<NDISC>(P, ot + j * (NDISC + 1), MAXOPP <= 3 ? cg[j < NPRE ? j : 0] : ot[j * (NDISC + 1)],
-                                        st[0], st[1], ax, ay, g2[j]);
+        for (int j = 0; j < MAXOPP; ++j) {
+            if (j < bs.n_opp) {
+                if constexpr (PRE_ALL) {
+                    g2[j] = opp_min2<NDISC>(P, orow + j * (NDISC + 1), orow[j * (NDISC + 1)], st[0], st[1], ax, ay,
+                                            g2[j]);
+                } else {
+                    const float2 c0 = MAXOPP <= 3 ? cg[j < NPRE ? j : 0] : ot[j * (NDISC + 1)];
+                    g2[j] = opp_min2<NDISC>(P, ot + j * (NDISC + 1), c0, st[0], st[1], ax, ay, g2[j]);
+                }
+            }
+        }
         if (tau + 1 > bs.N - bs.n_tail) dsum += f.d;
         // (C re-read at every step: the step counts (c + 1) C are not kept in registers)
         int Cv = C;
