@@ -124,7 +124,7 @@ typedef struct {
 /* Create a context on the current device with workspace for up to
  * max_agents_total vehicles over all races of one call, horizons up to max_N,
  * max_races races per call, track tables of up to max_track_nodes nodes and up to
- * max_K samples per best response (checkpoint slots: 512 bytes per 64 samples).
+ * max_K samples per best response (checkpoint slots: 576 bytes per 64 samples).
  * Allocates device memory (with sgtp_track_upload, plans and the autotuner). */
 int sgtp_ctx_create(sgtp_ctx **out, int max_agents_total, int max_N, int max_races, int max_track_nodes,
                     int max_K);

@@ -44,12 +44,12 @@ constexpr long long LPS2_MAX_SAMPLES = 32768;  // pair variant up to 1024 waves
 constexpr int NQ = 8;           // tile queues of the persistent sweep (one per XCD under round-robin dispatch)
 // Re-roll chunks: each lane keeps its state after every ceil(N / chunks) steps, so the
 // selected sample is re-rolled in that many pieces at once.  Latency variants (about
-// one wave per SIMD, registers to spare) keep 8, throughput variants 4.
-constexpr int NCP_MAX = 8;
+// one wave per SIMD, registers to spare) keep 10, throughput variants 4.
+constexpr int NCP_MAX = 10;
 template <int NPF>
-constexpr int ncp_of() { return NPF > 0 ? 8 : 4; }
-constexpr int CP_FLOATS = 64;   // export slot per group: up to 7 checkpoints x (6 states + segment), cost, violation
-constexpr int CP_COST = 62, CP_VIOL = 63;
+constexpr int ncp_of() { return NPF > 0 ? 10 : 4; }
+constexpr int CP_FLOATS = 72;   // export slot per group: up to 9 checkpoints x (6 states + segment), cost, violation
+constexpr int CP_COST = 70, CP_VIOL = 71;
 
 enum Mode { SWEEP = 0, WINNER = 1, NOMINAL = 2 };
 
