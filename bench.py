@@ -6,6 +6,10 @@ A step is one closed-loop planning step of the mid-scale race (3 vehicles on a
 (19 best responses = 12.45 M sample-steps), then every vehicle applies its first
 control through the vehicle model.  Inputs are resident on the GPU before the
 timed region.  Prints one JSON line.
+
+Other workloads (--workload): c3 (large field), c4 (256 batched races), c5 (learned
+proposal), race (closed-loop race evaluation, full size), race_small (the same at the
+paper's scale: kinematic bicycle, K = 128, H = 12).
 """
 
 from __future__ import annotations
@@ -262,23 +266,32 @@ def main():
 
     name = args.workload
     planner = sg.Planner(max_agents_total=2048, max_races=256)
-    if name == "race":
+    if name in ("race", "race_small"):
         # closed-loop race evaluation of the planner variants (Sec. IV-B metrics, Table II)
         from paper_2607_25388_amd import race_eval
         planner.close()
+        scale = "full" if name == "race" else "small"
+        sc = race_eval.SCALES[scale]
         n_games = 7 * 6 * 3
-        rp = sg.Planner(max_agents_total=n_games * 3, max_races=n_games, max_K=4096)
+        rp = sg.Planner(max_agents_total=n_games * 3, max_races=n_games, max_K=sc["K"])
         rp.enable_path_integral()
-        res = race_eval.evaluate(rp, race_eval.METHODS, 7, 6, 40, 4096, 5, 50.0,
+        res = race_eval.evaluate(rp, race_eval.METHODS, 7, 6, T_max=50.0, scale=scale,
                                  log=lambda m: print(m, file=sys.stderr, flush=True))
         rp.close()
+        if scale == "full":
+            desc = ("race evaluation: 42 trials (7 seeded 1.2 km x 12 m tracks x 6 starts), 3 vehicles (ego "
+                    "rearmost, opponents at 0.9 reference speed), every vehicle plans its own game (dynamic "
+                    "single-track model, 3 discs, N=40, K=4096, 5 IBR sweeps), 50 s, all 126 games batched in "
+                    "one plan per step")
+        else:
+            desc = ("race evaluation at the paper's scale: 42 trials (7 seeded 150 m x 2.5 m twisty tracks x 6 "
+                    "starts), 3 vehicles queued 2 m apart (ego rearmost, opponents at 0.9 reference speed), "
+                    "kinematic bicycle, point footprint (d_col 0.9 m), every vehicle plans its own game (N=12 "
+                    "over 1.2 s, K=128, 2 IBR sweeps), 50 s, a collision is contact of 0.58 m x 0.31 m bodies, "
+                    "all 126 games batched in one plan per step")
         rec = {"metric": METRIC, "value": res["sgtp"]["wins"], "unit": "win rate", "n_gpus": 1,
                "higher_is_better": True, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-               "config": {"workload": ("race evaluation: 42 trials (7 seeded 1.2 km x 12 m tracks x 6 starts), "
-                                       "3 vehicles (ego rearmost, opponents at 0.9 reference speed), every "
-                                       "vehicle plans its own game (N=40, K=4096, 5 IBR sweeps), 50 s, all "
-                                       "126 games batched in one plan per step")},
-               "race_eval": res}
+               "config": {"workload": desc}, "race_eval": res}
         print(json.dumps(rec), flush=True)
         return
     if name == "c5":

@@ -108,6 +108,19 @@ def default_params(N: int, n_disc: int = 3, model: int = 0) -> dict:
     )
 
 
+def small_scale_params(N: int = 12) -> dict:
+    """The paper's racing setup (Sec. IV-B): kinematic bicycle, H = 12 steps over 1.2 s,
+    sigma = (0.335, 0.025), the same cost weights, m_bd = 0.515 m, d_col = 0.9 m, g_safe =
+    1.0 m, a point footprint (eq. Dmin).  Vehicle constants and control bounds are those of
+    a 1:10 racing car (CoG-axle distances 0.15875 / 0.17145 m, |a| <= 9.51 m/s^2,
+    |delta| <= 0.4189 rad); the paper names the model but not its constants."""
+    p = default_params(N, 1, model=1)
+    p.update(dt=0.1, a_min=-9.51, a_max=9.51, d_min=-0.4189, d_max=0.4189, sigma_a=0.335, sigma_d=0.025,
+             g_safe=1.0, m_bd=0.515, d_col=0.9, lf=0.15875, lr=0.17145, v_eps=0.5,
+             n_tail=n_tail_from_fraction(0.3, N))
+    return p
+
+
 # ----------------------------------------------------------------------------
 # Tracks
 # ----------------------------------------------------------------------------
@@ -166,7 +179,8 @@ def _closure(L, lam, a, b, n_int):
 
 def make_fourier_track(length: float, width: float, seed: int, kappa_max: float = 0.05,
                        ds: float = 0.5, n_modes: int = 6, sub: int = 16,
-                       max_tries: int = 200, max_heading_dev: float = 1.2) -> Track:
+                       max_tries: int = 200, max_heading_dev: float = 1.2, v_max: float = 50.0,
+                       a_lat: float = 10.8, a_acc: float = 4.0, a_dec: float = 8.0) -> Track:
     """Closed track with curvature = 2*pi/L + a sum of n_modes random Fourier modes.
 
     Heading closes by construction; position closure is enforced by Newton on the
@@ -259,7 +273,7 @@ def make_fourier_track(length: float, width: float, seed: int, kappa_max: float 
         # place the track away from the origin so world coordinates are realistic
         x = x - x.min() + 50.0
         y = y - y.min() + 50.0
-        vref = speed_profile(k_n, ds, True)
+        vref = speed_profile(k_n, ds, True, v_max, a_lat, a_acc, a_dec)
         nodes = np.zeros((n, NODE_COLS))
         nodes[:, 0], nodes[:, 1], nodes[:, 2], nodes[:, 3] = x, y, th_n, k_n
         nodes[:, 4] = nodes[:, 5] = width / 2.0

@@ -4,8 +4,10 @@ Trials of one ego (rearmost) and two slower opponents (reference-speed scale 0.9
 seeded synthetic tracks.  Every vehicle runs the same planner and solves its own game
 with itself as the ego; all games of all trials are one batched plan, so one planning
 step of the whole evaluation is one plan run on the GPU.  A trial ends when the ego
-collides (footprint discs closer than d_col) or leaves the track, or at the time
-limit.
+collides or leaves the track, or at the time limit.  A collision is a breach of the
+planner's clearance (footprint discs closer than d_col) for the full-size races and
+contact of the car bodies (oriented rectangles) for the 1:10 cars, whose d_col = 0.9 m
+is a planning margin well outside the body; breaches of d_col are counted there too.
 
 Metrics (Sec. IV-B): Wins (progress gain above every opponent's by eps_s), CFW
 (collision-free share of the wins), FPR (share of opponents ahead of whom the ego ends),
@@ -80,13 +82,38 @@ def footprint_distance(X, params):
     return d
 
 
-def trial_metrics(s, d, X, u_ego, half_width, params, dt, ego=0):
+def body_contact(X, length, width, ego=0):
+    """Whether the ego's body -- a length x width rectangle centred on the CoG along the
+    heading -- overlaps each vehicle's.  X [T, n, 6] world states -> [T, n] (False at the
+    ego).  Separating-axis test: two rectangles are apart iff the projections of their
+    centres' offset on one of the four edge normals exceed the sum of the half extents."""
+    c, s = np.cos(X[..., 2]), np.sin(X[..., 2])
+    ax = np.stack([np.stack([c, s], -1), np.stack([-s, c], -1)], -2)  # [T, n, 2 axes, 2]
+    half = np.array([0.5 * length, 0.5 * width])
+    off = X[..., :2] - X[:, ego : ego + 1, :2]  # [T, n, 2]
+    apart = np.zeros(X.shape[:2], bool)
+    for axes in (ax[:, ego : ego + 1], ax):  # the ego's edge normals, then each vehicle's
+        for a in range(2):
+            w = axes[:, :, a]  # [T, n or 1, 2]
+            gap = np.abs((off * w).sum(-1))
+            r_e = (half * np.abs((ax[:, ego : ego + 1] * w[:, :, None, :]).sum(-1))).sum(-1)
+            r_j = (half * np.abs((ax * w[:, :, None, :]).sum(-1))).sum(-1)
+            apart |= gap > r_e + r_j
+    hit = ~apart
+    hit[:, ego] = False
+    return hit
+
+
+def trial_metrics(s, d, X, u_ego, half_width, params, dt, ego=0, contact=None):
     """Metrics of one trial from per-step records (steps 0..T-1 before each planning call):
     s [T, n] unwrapped progress, d [T, n] lateral offsets, X [T, n, 6] world states,
-    u_ego [T, 2] applied ego controls, half_width [T] at the ego."""
+    u_ego [T, 2] applied ego controls, half_width [T] at the ego.  contact = None ends the
+    trial at a breach of d_col; (length, width) ends it at body contact."""
     T, n = s.shape
     dist = footprint_distance(X, params)  # [T, n, n]
-    ego_hit = (dist[:, ego, :] < params["d_col"]).any(axis=1) | (np.abs(d[:, ego]) > half_width)
+    breach = (dist[:, ego, :] < params["d_col"]).any(axis=1)
+    hit = breach if contact is None else body_contact(X, *contact, ego=ego).any(axis=1)
+    ego_hit = hit | (np.abs(d[:, ego]) > half_width)
     hits = np.nonzero(ego_hit)[0]
     end = int(hits[0]) if len(hits) else T - 1  # last step that counts
     collided = len(hits) > 0
@@ -112,7 +139,9 @@ def trial_metrics(s, d, X, u_ego, half_width, params, dt, ego=0):
     du = np.diff(u_ego[: end + 1], axis=0)
     mcs = float((du * du).sum(axis=1).sum() / max(1, end)) if end > 0 else 0.0
     return dict(win=win, collided=collided, fpr=fpr, duration=(end + 1) * dt, segments=segs,
-                v_ego=X[: end + 1, ego, 3].tolist(), mcs=mcs)
+                v_ego=X[: end + 1, ego, 3].tolist(), mcs=mcs,
+                off_track=bool(np.abs(d[end, ego]) > half_width[end]),
+                d_col_breach=bool(breach[: end + 1].any()))
 
 
 def summarize(trials, T_max):
@@ -133,15 +162,34 @@ def summarize(trials, T_max):
         "v_ego_mean": float(np.mean(v)),
         "mcs": float(np.mean([t["mcs"] for t in trials])),
         "ego_collisions": int(sum(t["collided"] for t in trials)),
+        "off_track": int(sum(t.get("off_track", False) for t in trials)),
+        "d_col_breaches": int(sum(t.get("d_col_breach", False) for t in trials)),
     }
 
 
 # ---- batched closed loop on the GPU -------------------------------------------
 
+# Scales of the evaluation.  "full": full-size cars (dynamic single-track model, 3 discs)
+# on 1.2 km x 12 m tracks; "small": the paper's own setup (Sec. IV-B) at its scale -- the
+# kinematic bicycle, K = 128, H = 12 over 1.2 s, L_IBR = 2, point footprint with
+# d_col = 0.9 m, vehicles queued 2 m apart -- on twisty 150 m x 2.5 m loops (10 Fourier
+# modes, radii down to ~4.5 m, reference speed 5.5-8 m/s); a collision there is contact of
+# 0.58 m x 0.31 m car bodies.
+SCALES = {
+    "full": dict(N=40, K=4096, L=5, length=1200.0, width=12.0, spacing=10.0, track=None, contact=None,
+                 params=lambda N: inputs.default_params(N, 3)),
+    "small": dict(N=12, K=128, L=2, length=150.0, width=2.5, spacing=2.0,
+                  track=dict(ds=0.1, kappa_max=0.3, max_heading_dev=5.0, n_modes=10, max_tries=400,
+                             v_max=8.0, a_lat=7.0, a_acc=3.0, a_dec=5.0),
+                  contact=(0.58, 0.31), params=inputs.small_scale_params),
+}
+
+
 def make_trials(n_tracks: int, starts: int, N: int, n_veh: int = 3, length=1200.0, width=12.0,
-                spacing=10.0, track_seed0=1100, start_seed0=60000):
+                spacing=10.0, track_seed0=1100, start_seed0=60000, track_kw=None):
     """Seeded tracks and start queues (ego rearmost, opponents' reference speed x 0.9)."""
-    tracks = [inputs.make_fourier_track(length, width, track_seed0 + i) for i in range(n_tracks)]
+    tracks = [inputs.make_fourier_track(length, width, track_seed0 + i, **(track_kw or {}))
+              for i in range(n_tracks)]
     trials = []
     for ti, tr in enumerate(tracks):
         for k in range(starts):
@@ -151,9 +199,9 @@ def make_trials(n_tracks: int, starts: int, N: int, n_veh: int = 3, length=1200.
 
 
 def run(planner: sg.Planner, method: str, params: dict, tracks, trials, K: int, L_ibr: int, T_max: float,
-        track_id0: int = 0, options=None, log=None):
+        track_id0: int = 0, options=None, log=None, contact=None):
     """Run every trial for T_max seconds with `method`; returns (per-trial metrics,
-    planning-step times in ms)."""
+    planning-step times in ms).  `contact` as in trial_metrics."""
     import torch
     p = method_params(params, method)
     N, dt = p["N"], p["dt"]
@@ -209,16 +257,23 @@ def run(planner: sg.Planner, method: str, params: dict, tracks, trials, K: int, 
     out = []
     for t, (ti, race) in enumerate(trials):
         hw = np.full(steps, float(np.min(tracks[ti].nodes[:, 4:6])))  # half width (constant tracks)
-        out.append(trial_metrics(rec_s[:, t], rec_d[:, t], rec_x[:, t], rec_u[:, t, 0], hw, p, dt, ego=0))
+        out.append(trial_metrics(rec_s[:, t], rec_d[:, t], rec_x[:, t], rec_u[:, t, 0], hw, p, dt, ego=0,
+                                 contact=contact))
     return out, ct
 
 
-def evaluate(planner, methods=METHODS, n_tracks=7, starts=6, N=40, K=4096, L_ibr=5, T_max=50.0, log=None):
-    params = inputs.default_params(N, 3)
-    tracks, trials = make_trials(n_tracks, starts, N)
+def evaluate(planner, methods=METHODS, n_tracks=7, starts=6, N=None, K=None, L_ibr=None, T_max=50.0, log=None,
+             scale="full"):
+    sc = SCALES[scale]
+    N = sc["N"] if N is None else N
+    K = sc["K"] if K is None else K
+    L_ibr = sc["L"] if L_ibr is None else L_ibr
+    params = sc["params"](N)
+    tracks, trials = make_trials(n_tracks, starts, N, length=sc["length"], width=sc["width"],
+                                 spacing=sc["spacing"], track_kw=sc["track"])
     res = {}
     for m in methods:
-        per, ct = run(planner, m, params, tracks, trials, K, L_ibr, T_max, log=log)
+        per, ct = run(planner, m, params, tracks, trials, K, L_ibr, T_max, log=log, contact=sc["contact"])
         s = summarize(per, T_max)
         s["ct_ms"] = {"mean": float(ct.mean()), "std": float(ct.std()), "max": float(ct.max()),
                       "games_per_call": len(trials) * trials[0][1].n_agents}
@@ -234,17 +289,19 @@ def main():
     ap = argparse.ArgumentParser(description="closed-loop race evaluation of the planner variants")
     ap.add_argument("--tracks", type=int, default=7)
     ap.add_argument("--starts", type=int, default=6)
-    ap.add_argument("--K", type=int, default=4096)
-    ap.add_argument("--N", type=int, default=40)
-    ap.add_argument("--L", type=int, default=5)
+    ap.add_argument("--scale", choices=sorted(SCALES), default="full")
+    ap.add_argument("--K", type=int, default=None)
+    ap.add_argument("--N", type=int, default=None)
+    ap.add_argument("--L", type=int, default=None)
     ap.add_argument("--seconds", type=float, default=50.0)
     ap.add_argument("--methods", default=",".join(METHODS))
     a = ap.parse_args()
     n_games = a.tracks * a.starts * 3
-    planner = sg.Planner(max_agents_total=n_games * 3, max_races=n_games, max_K=a.K)
+    planner = sg.Planner(max_agents_total=n_games * 3, max_races=n_games,
+                         max_K=a.K if a.K is not None else SCALES[a.scale]["K"])
     planner.enable_path_integral()
     res = evaluate(planner, a.methods.split(","), a.tracks, a.starts, a.N, a.K, a.L, a.seconds,
-                   log=lambda m: print(m, flush=True))
+                   log=lambda m: print(m, flush=True), scale=a.scale)
     planner.close()
     print(json.dumps({"race_eval": res, "config": vars(a)}), flush=True)
 

@@ -92,3 +92,50 @@ def test_summary():
     assert s["d_mean_s"] == pytest.approx(110 / 3) and s["d_max_s"] == 50.0
     assert s["d_ratio"] == pytest.approx(110 / 150) and s["v_ego_mean"] == pytest.approx(20.0)
     assert s["ego_collisions"] == 1
+
+
+def _pair(x, y, psi_e, psi_j):
+    X = np.zeros((1, 2, 6))
+    X[0, 0, 2] = psi_e
+    X[0, 1, 0], X[0, 1, 1], X[0, 1, 2] = x, y, psi_j
+    return X
+
+
+@pytest.mark.parametrize("psi", [0.0, 0.7, -2.1])
+def test_body_contact_rectangles(psi):
+    """0.58 m x 0.31 m bodies: in line they touch below 0.58 m between centres, side by side
+    below 0.31 m, crossed at right angles below 0.29 + 0.155 m; a common rotation of the
+    scene changes nothing."""
+    Lb, Wb = 0.58, 0.31
+    c, s = math.cos(psi), math.sin(psi)
+
+    def hit(x, y, dpsi=0.0):  # offset (x, y) in the ego's frame, relative heading dpsi
+        return bool(RE.body_contact(_pair(c * x - s * y, s * x + c * y, psi, psi + dpsi), Lb, Wb)[0, 1])
+
+    assert hit(0.57, 0.0) and not hit(0.59, 0.0) and hit(-0.57, 0.0) and not hit(-0.59, 0.0)
+    assert hit(0.0, 0.30) and not hit(0.0, 0.32)
+    assert hit(0.44, 0.0, math.pi / 2) and not hit(0.45, 0.0, math.pi / 2)
+    assert hit(0.0, 0.44, math.pi / 2) and not hit(0.0, 0.45, math.pi / 2)
+    # corner to corner: offset (0.57, 0.30) overlaps, (0.59, 0.30) and (0.57, 0.32) do not
+    assert hit(0.57, 0.30) and not hit(0.59, 0.30) and not hit(0.57, 0.32)
+    # a 45 degree turn: the rotated body reaches 0.29 cos45 + 0.155 sin45 = 0.3147 m along x
+    r = 0.29 * math.cos(math.pi / 4) + 0.155 * math.sin(math.pi / 4)
+    assert hit(0.29 + r - 0.005, 0.0, math.pi / 4) and not hit(0.29 + r + 0.005, 0.0, math.pi / 4)
+    assert not bool(RE.body_contact(_pair(0.0, 0.0, psi, psi), Lb, Wb)[0, 0])  # never the ego itself
+
+
+def test_contact_criterion_ends_trials_at_touch_not_at_margin():
+    """With the 1:10 cars' point footprint (d_col = 0.9 m), trailing 0.7 m behind is a
+    breach of d_col but no contact; closing to 0.5 m is contact."""
+    from paper_2607_25388_amd.inputs import small_scale_params
+    Ps = small_scale_params()
+    T = 50
+    s, d, X = _lineup(T, [0.0, 0.7], [5.0, 5.0], [0.0, 0.0])
+    m = RE.trial_metrics(s, d, X, np.zeros((T, 2)), np.full(T, 1.25), Ps, 0.1, contact=(0.58, 0.31))
+    assert not m["collided"] and m["d_col_breach"] and m["duration"] == pytest.approx(T * 0.1)
+    m0 = RE.trial_metrics(s, d, X, np.zeros((T, 2)), np.full(T, 1.25), Ps, 0.1)
+    assert m0["collided"] and m0["duration"] == pytest.approx(0.1)
+    s, d, X = _lineup(T, [0.0, 0.9], [5.0, 3.0], [0.0, 0.0])  # closes 2 m/s: 0.1 m per record
+    m = RE.trial_metrics(s, d, X, np.zeros((T, 2)), np.full(T, 1.25), Ps, 0.1, contact=(0.58, 0.31))
+    assert m["collided"] and not m["off_track"]
+    assert m["duration"] == pytest.approx(5 * 0.1)  # gap 0.9 - 0.1 k < 0.58 first at k = 4
