@@ -41,6 +41,13 @@ constexpr int PRED_STRIDE = 8;  // x, y, cos psi, sin psi, s_rel, d, -, - in the
 constexpr int NODE_STRIDE = 10; // device node row: x, y, psi, nx, ny, wL, wR, vref, s, kappa
 constexpr unsigned long long KEY_NONE = ~0ull;
 constexpr long long LPS2_MAX_SAMPLES = 32768;  // pair variant up to 1024 waves
+// Split variant (launches of about one wave per SIMD or fewer): each sample runs on two
+// waves, dynamics on one and projection and scoring on the other, its states passing
+// through an LDS ring of SPLIT_RING steps.
+constexpr long long SPLIT_MAX_SAMPLES = 65536;  // up to 2048 waves
+constexpr int SPLIT_RING = 8;
+constexpr int SPLIT_AHEAD = 4;  // controls published ahead of the state being scored
+constexpr int SPLIT_FIN = 8;    // floats per sample handed from the dynamics to the scoring lane
 constexpr int NQ = 8;           // tile queues of the persistent sweep (one per XCD under round-robin dispatch)
 // Re-roll chunks: each lane keeps its state after every ceil(N / chunks) steps, so the
 // selected sample is re-rolled in that many pieces at once.  Latency variants (about
@@ -110,6 +117,7 @@ struct LdsLayout {  // byte offsets of the staged tables, identical for every bl
     int ubar, xref, oppT, oppc, opp, nodes, prop;
     int rr_u, rr_st, rr_f, rr_t;  // re-roll scratch (rr_t: setup's reference recursion)
     int rr_sync;                  // re-roll: states written per piece (NCP_MAX ints)
+    int sp_ring, sp_uring, sp_sync, sp_fin;  // split variant: state and control rings, counters, final state
     int total;
     int n_opp_max, w_max, N_max;
 };
@@ -122,6 +130,7 @@ struct LaunchArgs {
     const ItemDev *items;
     int n_items, n_tiles, spl, phase;
     int lps;               // lanes per sample (2: the pair variant of small launches)
+    int split;             // 1: the split variant (two waves per sample)
     AgentRec *agents;
     const float4 *win;     // [slot][WIN_MAX][2]
     const float4 *xref;    // [slot][N_max]
@@ -1021,6 +1030,232 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const B
 }
 
 // ------------------------------------------------------------------------------
+// One sample on two waves (the split variant).  A lane of the workgroup's first half
+// integrates the dynamics, the longest dependent chain of a step.  Its partner lane in
+// the second half does the rest: it draws the perturbation, clips the controls and sums
+// the control terms SPLIT_AHEAD steps ahead, projects every state onto the raceline and
+// scores it (tracking, boundary, footprint distances, tail offsets), then takes the
+// terminal scoring.  Controls and states pass through LDS rings of SPLIT_RING steps;
+// uprod / prod count the controls and states written, cons the states consumed, per
+// wave pair, and each side re-reads a count only when its ring runs empty (or full).
+// The scoring side publishes the controls of step tau + SPLIT_AHEAD before it waits for
+// state tau, and a control slot is rewritten only after its state was published, so
+// both waits end; their bounds are guards only.  Checkpoints: states on the dynamics
+// lane, segments on the scoring lane.  Arithmetic per step as in lane_sample; only the
+// control terms are summed apart from the rest and added at the end.
+// ------------------------------------------------------------------------------
+template <int MODEL, int NDISC, int MAXOPP, int NPF>
+__device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, const BlockState &bs, char *lds,
+                                                         const LdsLayout &L, uint32_t k, float *noise_out, bool dyn) {
+    constexpr int TS = BLOCK / 2;
+    constexpr int NC = ncp_of<NPF>();
+    static_assert(SPLIT_AHEAD + 1 <= SPLIT_RING, "a control slot is rewritten only after its state was published");
+    const int i = threadIdx.x & (TS - 1);
+    const int w = (threadIdx.x >> 6) & 1;  // wave pair
+    const int lane = threadIdx.x & 63;
+    float4 *ring = (float4 *)(lds + L.sp_ring);    // [SPLIT_RING][TS]: X, Y, PSI, VX after the step
+    float2 *uring = (float2 *)(lds + L.sp_uring);  // [SPLIT_RING][TS]: controls of the step
+    volatile int *prod = (volatile int *)(lds + L.sp_sync);
+    volatile int *cons = prod + 2;
+    volatile int *uprod = prod + 6;
+    float *fin = (float *)(lds + L.sp_fin);  // [TS][SPLIT_FIN]: final state
+    const int C = (bs.N + NC - 1) / NC;
+    if (threadIdx.x < 8) prod[threadIdx.x] = 0;
+    __syncthreads();
+    // each side's values, set and used only on that side (one barrier, outside both)
+    float cp[NC - 1][6];                                   // dynamics: checkpointed states
+    float J, Ju, rho_bd, dsum, s, g2[MAXOPP];              // scoring
+    bool limit;
+    int cseg[NC - 1];
+    if (dyn) {
+        const VehConst<float> V = veh_f32(P);
+        float st[6] = {0.0f, 0.0f, 0.0f, bs.vx0, bs.vy0, bs.om0};
+#pragma unroll
+        for (int c = 0; c < NC - 1; ++c)
+#pragma unroll
+            for (int j = 0; j < 6; ++j) cp[c][j] = 0.0f;
+        int useen = 0, seen = 0;  // the scoring side's counts as last read
+        for (int tau = 0; tau < bs.N; ++tau) {
+            if (useen <= tau) {
+                for (int spin = 0; spin < (1 << 22); ++spin) {
+                    useen = uprod[w];
+                    if (useen > tau) break;
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            }
+            const float2 u = uring[(tau % SPLIT_RING) * TS + i];
+            const StepConst<float> sc = step_const<MODEL, MathF32>(V, u.x, u.y);
+            rk4<MODEL, MathF32>(V, sc, P.dt, st);
+            if (tau - seen >= SPLIT_RING) {
+                for (int spin = 0; spin < (1 << 22); ++spin) {
+                    seen = cons[w];
+                    if (tau - seen < SPLIT_RING) break;
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            }
+            ring[(tau % SPLIT_RING) * TS + i] = make_float4(st[0], st[1], st[2], st[3]);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (lane == 0) prod[w] = tau + 1;
+            int Cv = C;
+            asm volatile("" : "+s"(Cv));
+#pragma unroll
+            for (int c = 0; c < NC - 1; ++c) {
+                if (tau + 1 == (c + 1) * Cv) {
+#pragma unroll
+                    for (int j = 0; j < 6; ++j) cp[c][j] = st[j];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 6; ++j) fin[i * SPLIT_FIN + j] = st[j];
+    } else {
+        const float2 *ubar = (const float2 *)(lds + L.ubar);
+        const float4 *xref = (const float4 *)(lds + L.xref);
+        const float2 *opp = (const float2 *)(lds + L.opp);
+        const float4 *nodes = (const float4 *)(lds + L.nodes);
+        int seg = bs.seg0;
+        J = 0.0f;
+        Ju = 0.0f;
+        rho_bd = INFINITY;
+        dsum = 0.0f;
+        s = 0.0f;
+#pragma unroll
+        for (int j = 0; j < MAXOPP; ++j) g2[j] = P.cap2;
+        limit = false;
+#pragma unroll
+        for (int c = 0; c < NC - 1; ++c) cseg[c] = 0;
+        // controls of step t, in step order (one Philox call per pair of steps), published
+        float2 up = make_float2(0.0f, 0.0f), zn = up;
+        int t_u = 0;
+        auto control = [&]() {
+            const int t = t_u++;
+            float2 z;
+            if ((t & 1) == 0) {
+                const uint4 r = philox4x32_10(make_uint4(k, (uint32_t)(t >> 1), bs.ctr2, bs.ctr3), bs.key0, bs.key1);
+                z = gauss_pair(r.x, r.y);
+                zn = gauss_pair(r.z, r.w);
+            } else {
+                z = zn;
+            }
+            const float2 u = controls_k(P, bs, lds, L, k, t, ubar[t], z.x, z.y);
+            Ju += ctrl_term(P, u);
+            if (t >= 1) Ju += rate_term(P, u, up);
+            up = u;
+            uring[(t % SPLIT_RING) * TS + i] = u;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (lane == 0) uprod[w] = t + 1;
+        };
+        const int ahead0 = bs.N < SPLIT_AHEAD ? bs.N : SPLIT_AHEAD;
+        for (int t = 0; t < ahead0; ++t) control();
+        int seen = 0;  // the dynamics side's count as last read
+        for (int tau = 0; tau < bs.N; ++tau) {
+            if (tau + SPLIT_AHEAD < bs.N) control();
+            // reads that do not depend on this step's state go first
+            const float4 xr = xref[tau];
+            NodeAhead<NPF> ahead = read_ahead<NPF>(nodes, bs.W, seg);
+            const float2 *ot = opp + tau * (L.n_opp_max * (NDISC + 1));
+            float2 orow[MAXOPP * (NDISC + 1)];
+#pragma unroll
+            for (int j = 0; j < MAXOPP * (NDISC + 1); ++j) orow[j] = ot[j];
+            if (seen <= tau) {
+                for (int spin = 0; spin < (1 << 22); ++spin) {
+                    seen = prod[w];
+                    if (seen > tau) break;
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            }
+            const float4 sv = ring[(tau % SPLIT_RING) * TS + i];
+            const float st4[4] = {sv.x, sv.y, sv.z, sv.w};
+            const Foot f = project_ahead<NPF>(nodes, bs.W, P.max_moves, sv.x, sv.y, seg, ahead);
+            seg = f.seg;
+            limit |= f.limit;
+            s = f.s;
+            J += track_term(P, st4, xr);
+            rho_bd = fminf(rho_bd, bound_term(f));
+            float ch = 1.0f, sh = 0.0f;
+            if (NDISC > 1) {
+                ch = fast_cos(sv.z);
+                sh = fast_sin(sv.z);
+            }
+            float ax[NDISC], ay[NDISC];
+            disc_centres<NDISC>(P, sv.x, sv.y, ch, sh, ax, ay);
+#pragma unroll
+            for (int j = 0; j < MAXOPP; ++j) {
+                if (j < bs.n_opp)
+                    g2[j] = opp_min2<NDISC>(P, orow + j * (NDISC + 1), orow[j * (NDISC + 1)], sv.x, sv.y, ax, ay,
+                                            g2[j]);
+            }
+            if (tau + 1 > bs.N - bs.n_tail) dsum += f.d;
+            int Cv = C;
+            asm volatile("" : "+s"(Cv));
+#pragma unroll
+            for (int c = 0; c < NC - 1; ++c) {
+                if (tau + 1 == (c + 1) * Cv) cseg[c] = seg;
+            }
+            // the state is used: its ring entry may be overwritten
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (lane == 0) cons[w] = tau + 1;
+        }
+        if (noise_out) {  // debug output only: the perturbations drawn again, outside the loop
+            for (int m = 0; 2 * m < bs.N; ++m) {
+                const uint4 r = philox4x32_10(make_uint4(k, (uint32_t)m, bs.ctr2, bs.ctr3), bs.key0, bs.key1);
+                const float2 z0 = gauss_pair(r.x, r.y), z1 = gauss_pair(r.z, r.w);
+                noise_out[4 * m] = z0.x;
+                noise_out[4 * m + 1] = z0.y;
+                if (2 * m + 1 < bs.N) {
+                    noise_out[4 * m + 2] = z1.x;
+                    noise_out[4 * m + 3] = z1.y;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // one result object for both sides, written field by field
+    SampleResult res;
+    const float *fo = fin + i * SPLIT_FIN;  // the final state, read where it lies
+    if (dyn) {
+        res.cost = 0.0f;
+        res.viol = 0.0f;
+        res.h = false;
+        res.flags = 0;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) res.st[j] = fo[j];
+#pragma unroll
+        for (int c = 0; c < NC - 1; ++c) {
+#pragma unroll
+            for (int j = 0; j < 6; ++j) res.cp[c][j] = cp[c][j];
+            res.cp[c][6] = 0.0f;
+        }
+    } else {
+        const SampleResult t = terminal<MAXOPP>(P, bs, lds, L, J + Ju, rho_bd, dsum, s, g2, limit, fo);
+        res.cost = t.cost;
+        res.viol = t.viol;
+        res.h = t.h;
+        res.flags = t.flags;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) res.st[j] = t.st[j];
+#pragma unroll
+        for (int c = 0; c < NC - 1; ++c) {
+#pragma unroll
+            for (int j = 0; j < 6; ++j) res.cp[c][j] = 0.0f;
+            res.cp[c][6] = __int_as_float(cseg[c]);
+        }
+    }
+    return res;
+}
+
+template <int MODEL, int NDISC, int MAXOPP, int NPF, int LPS, int SPL>
+__device__ __forceinline__ SampleResult run_sample(const KParams &P, const BlockState &bs, char *lds,
+                                                  const LdsLayout &L, uint32_t k, float *noise_out, bool rear,
+                                                  bool dyn) {
+    if constexpr (SPL != 0) return lane_sample_split<MODEL, NDISC, MAXOPP, NPF>(P, bs, lds, L, k, noise_out, dyn);
+    else return lane_sample<MODEL, NDISC, MAXOPP, NPF, LPS>(P, bs, lds, L, k, noise_out, rear);
+}
+
+// ------------------------------------------------------------------------------
 // One sample re-rolled by a whole workgroup for its outputs: controls and output
 // writes in parallel over the horizon, the dynamics and the projection serially (in
 // ncp_of<NPF>() pieces at once when the sample's checkpoints are given).  MODE WINNER
@@ -1217,11 +1452,13 @@ __device__ __forceinline__ void pi_accumulate(const KParams &P, const BlockState
 // path-integral update every tile leaves its weighted partial sums instead, and the
 // last workgroup combines them in tile order, adopts the weighted mean sequence and
 // rolls it out noise-free.
-template <int MODEL, int NDISC, int MAXOPP, int NPF = 0, int LPS = 1>
+template <int MODEL, int NDISC, int MAXOPP, int NPF = 0, int LPS = 1, int SPL = 0>
 __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int item, const BlockState &bs, char *lds,
                                            int *s_last) {
-    constexpr int G = 64 / LPS;  // samples per wave = checkpoint group
+    constexpr int G = SPL ? 64 : 64 / LPS;  // samples per wave (per wave pair when split) = checkpoint group
+    constexpr int TS = SPL ? BLOCK / 2 : BLOCK;  // samples per pass of the workgroup (one lane each: LPS = 1)
     const bool rear = LPS == 2 && (threadIdx.x & 1);
+    const bool dyn = SPL && (int)threadIdx.x < BLOCK / 2;  // the split variant's dynamics lanes
     const int lane = threadIdx.x & 63;
     const bool pi = A.P.update == 1;
     const int t0 = A.items[item].tile0;
@@ -1230,28 +1467,53 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
     const int pstride = 2 * A.L.N_max + 2;
     PiAcc pa{INFINITY, 0.0f, 0.0f, 0.0f};
     for (int r = 0; r < A.spl; ++r) {
-        const uint32_t k = LPS == 1 ? (uint32_t)((local_tile * A.spl + r) * BLOCK + threadIdx.x)
+        const uint32_t k = LPS == 1 ? (uint32_t)((local_tile * A.spl + r) * TS + (threadIdx.x & (TS - 1)))
                                     : (uint32_t)(local_tile * (BLOCK / 2) + (threadIdx.x >> 1));
         const bool valid = k < (uint32_t)bs.K;
-        float *nz = (A.dbg_noise && valid && !rear) ? A.dbg_noise + (size_t)k * bs.N * 2 : nullptr;
+        // (the split variant draws the perturbation on the scoring lane)
+        float *nz = (A.dbg_noise && valid && !rear && !dyn) ? A.dbg_noise + (size_t)k * bs.N * 2 : nullptr;
         const SampleResult res =
-            lane_sample<MODEL, NDISC, MAXOPP, NPF, LPS>(A.P, bs, lds, A.L, valid ? k : 0u, nz, rear);
+            run_sample<MODEL, NDISC, MAXOPP, NPF, LPS, SPL>(A.P, bs, lds, A.L, valid ? k : 0u, nz, rear, dyn);
         unsigned long long key;
-        if (pi) {
+        if (dyn) {
+            key = KEY_NONE;  // scored by the partner lane
+        } else if (pi) {
             const float S = res.cost + A.P.w_viol * res.viol;
             key = valid ? make_key(isfinite(S), isfinite(S) ? S : 0.0f, k) : KEY_NONE;
         } else {
             key = valid ? make_key(res.h, res.h ? res.cost : res.viol, k) : KEY_NONE;
         }
         const unsigned long long wmin = wave_min_u64(key);
-        const unsigned long long feas = __ballot(valid && res.h && !rear);
+        const unsigned long long feas = __ballot(valid && res.h && !rear && !dyn);
         if (lane == 0) {
             if (wmin != KEY_NONE) atomicMin(A.keys + bs.slot, wmin);
             const int cnt = __popcll(feas);
             if (cnt) atomicAdd(A.nfeas + bs.slot, cnt);
         }
         if (pi) {
-            pi_accumulate(A.P, bs, lds, A.L, valid ? k : 0u, valid, res, pa);
+            pi_accumulate(A.P, bs, lds, A.L, valid ? k : 0u, valid && !dyn, res, pa);
+        } else if (SPL) {
+            // the scoring wave names its best lane; the two partner lanes export their parts
+            int *best = (int *)(lds + A.L.sp_sync) + 4;
+            if (!dyn) {
+                const unsigned long long b = __ballot(valid && key == wmin);
+                if (lane == 0) best[(threadIdx.x >> 6) & 1] = (wmin != KEY_NONE && b) ? __builtin_ctzll(b) : -1;
+            }
+            __syncthreads();
+            if (valid && lane == best[(threadIdx.x >> 6) & 1]) {
+                float *slot = A.cp_slots + ((size_t)A.items[item].group0 + k / G) * CP_FLOATS;
+                if (dyn) {  // states on the dynamics lane; segments and score on the scoring lane
+#pragma unroll
+                    for (int c = 0; c < ncp_of<NPF>() - 1; ++c)
+#pragma unroll
+                        for (int i = 0; i < 6; ++i) slot[7 * c + i] = res.cp[c][i];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < ncp_of<NPF>() - 1; ++c) slot[7 * c + 6] = res.cp[c][6];
+                    slot[CP_COST] = res.cost;
+                    slot[CP_VIOL] = res.viol;
+                }
+            }
         } else if (valid && key == wmin && !rear) {  // the wave's best sample exports checkpoints and score
             float *slot = A.cp_slots + ((size_t)A.items[item].group0 + k / G) * CP_FLOATS;
 #pragma unroll
@@ -1261,7 +1523,7 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
             slot[CP_COST] = res.cost;
             slot[CP_VIOL] = res.viol;
         }
-        if (valid && !rear) {
+        if (valid && !rear && !dyn) {
             if (A.dbg_cost) A.dbg_cost[k] = res.cost;
             if (A.dbg_viol) A.dbg_viol[k] = res.viol;
             if (A.dbg_flags) A.dbg_flags[k] = res.flags;
@@ -1375,7 +1637,7 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
 }
 
 // Sweep with one workgroup per tile.
-template <int MODEL, int NDISC, int MAXOPP, int NPF = 0, int LPS = 1>
+template <int MODEL, int NDISC, int MAXOPP, int NPF = 0, int LPS = 1, int SPL = 0>
 __global__ void __launch_bounds__(BLOCK) k_sweep(LaunchArgs A) {
     extern __shared__ __align__(16) char lds[];
     __shared__ int s_last;
@@ -1383,7 +1645,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(LaunchArgs A) {
     const int item = find_item(A.items, A.n_items, tile);
     BlockState bs;
     stage_block<NDISC>(A, item, bs, lds);
-    sweep_tile<MODEL, NDISC, MAXOPP, NPF, LPS>(A, tile, item, bs, lds, &s_last);
+    sweep_tile<MODEL, NDISC, MAXOPP, NPF, LPS, SPL>(A, tile, item, bs, lds, &s_last);
 }
 
 // Persistent sweep: a fixed grid of workgroups pulls chunks of tiles from NQ queues
@@ -2009,11 +2271,16 @@ struct Plan {  // host image of one launch sequence's descriptors
     int N_max = 0, n_opp_max = 0, w_max = 0, agents_total = 0;
     int tiles_all = 0, tiles_ego = 0;
     int lps = 1;          // lanes per sample
+    int split = 0;        // two waves per sample
     int tile_samples = 0;  // samples per tile: BLOCK x samples per lane / lanes per sample
 };
 
-int build_plan(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_races, int spl, Plan &pl,
-               int one_agent = -1) {
+LdsLayout make_layout(const Plan &pl, int maxopp, int ndisc);
+int maxopp_bucket(int n_opp);
+constexpr int LDS_BUDGET = 58 * 1024;
+
+int build_plan_once(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_races, int spl, Plan &pl,
+                    int one_agent, bool allow_split) {
     if (!races || n_races < 1) return fail(c, SGTP_EINVAL, "no races");
     if (n_races > c->max_races) return fail(c, SGTP_ESHAPE, "n_races exceeds the context");
     // lanes per sample: the pair variant when the launch stays well below one wave per SIMD
@@ -2026,9 +2293,10 @@ int build_plan(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_
             nopp = std::max(nopp, races[r].n_agents - 1);
         }
         pl.lps = (spl == 1 && p->model == 0 && p->update == 0 && nopp <= 3 && samples <= LPS2_MAX_SAMPLES) ? 2 : 1;
-        pl.tile_samples = BLOCK * spl / pl.lps;
+        pl.split = (allow_split && pl.lps == 1 && spl == 1 && nopp <= 3 && samples <= SPLIT_MAX_SAMPLES) ? 1 : 0;
+        pl.tile_samples = BLOCK * spl / (pl.split ? 2 : pl.lps);
     }
-    const int gsz = 64 / pl.lps;  // samples per wave = checkpoint group
+    const int gsz = 64 / pl.lps;  // samples per wave (per wave pair when split) = checkpoint group
     int slot = 0;
     long long group_total = 0;
     double wneed = 0;
@@ -2090,6 +2358,15 @@ int build_plan(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_
     return SGTP_OK;
 }
 
+// The plan of one launch sequence; the split variant only where its LDS ring fits.
+int build_plan(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_races, int spl, Plan &pl,
+               int one_agent = -1) {
+    int rc = build_plan_once(c, p, races, n_races, spl, pl, one_agent, true);
+    if (rc || !pl.split || make_layout(pl, maxopp_bucket(pl.n_opp_max), p->n_disc).total <= LDS_BUDGET) return rc;
+    pl = Plan();
+    return build_plan_once(c, p, races, n_races, spl, pl, one_agent, false);
+}
+
 LdsLayout make_layout(const Plan &pl, int maxopp, int ndisc) {
     LdsLayout L{};
     int off = 0;
@@ -2115,6 +2392,12 @@ LdsLayout make_layout(const Plan &pl, int maxopp, int ndisc) {
     L.rr_f = take(pl.N_max * 16);
     L.rr_t = take(pl.N_max * 16);
     L.rr_sync = take(NCP_MAX * 4);
+    if (pl.split) {
+        L.sp_ring = take(SPLIT_RING * (BLOCK / 2) * 16);
+        L.sp_uring = take(SPLIT_RING * (BLOCK / 2) * 8);
+        L.sp_sync = take(8 * 4);            // prod[2], cons[2], best lane[2], uprod[2]
+        L.sp_fin = take((BLOCK / 2) * SPLIT_FIN * 4);  // per sample: final state
+    }
     L.total = off;
     return L;
 }
@@ -2169,7 +2452,10 @@ void launch_sweep_t(const LaunchArgs &A, int grid, hipStream_t st, int *occ) {
     } else if (grid == 0) {
         // about one wave per SIMD or fewer (small games): the latency variant reads ahead
         constexpr int LAT_WAVES = 1536;
-        if (MODEL == 0 && MAXOPP <= 3 && A.lps == 2)
+        if (MAXOPP <= 3 && A.split)
+            hipLaunchKernelGGL((k_sweep<MODEL, NDISC, MAXOPP <= 3 ? MAXOPP : 3, 6, 1, 1>), dim3(A.n_tiles),
+                               dim3(BLOCK), A.L.total, st, A);
+        else if (MODEL == 0 && MAXOPP <= 3 && A.lps == 2)
             hipLaunchKernelGGL((k_sweep<0, NDISC, MAXOPP <= 3 ? MAXOPP : 3, 6, 2>), dim3(A.n_tiles), dim3(BLOCK),
                                A.L.total, st, A);
         else if (MAXOPP <= 3 && A.n_tiles * (BLOCK / 64) <= LAT_WAVES)
@@ -2256,7 +2542,7 @@ struct Runner {
         mo = maxopp_bucket(pl.n_opp_max);
         A.P = make_kparams(p);
         A.L = make_layout(pl, mo, p->n_disc);
-        if (A.L.total > 58 * 1024) return fail(c, SGTP_ESHAPE, "staged tables exceed the LDS budget");
+        if (A.L.total > LDS_BUDGET) return fail(c, SGTP_ESHAPE, "staged tables exceed the LDS budget");
         rc = upload_plan(c, pl, st, &d_races, &d_all, &d_ego, &d_one);
         if (rc) return rc;
         A.tracks = c->d_tracks;
@@ -2271,6 +2557,7 @@ struct Runner {
     A.pi_part = c->d_pi;
         A.spl = 1;
         A.lps = pl.lps;
+        A.split = pl.split;
         return SGTP_OK;
     }
     // projection, frames, windows, references, initial predictions (into pred[0])
@@ -2522,7 +2809,8 @@ const char *sgtp_last_error(const sgtp_ctx *c) { return c ? c->err.c_str() : "nu
 int sgtp_ctx_enable_path_integral(sgtp_ctx *c) {
     if (!c) return SGTP_EINVAL;
     if (c->d_pi) return SGTP_OK;
-    const long long tiles = c->max_groups / (BLOCK / 64) + c->max_agents;
+    // tiles of BLOCK / 2 samples (the split variant), one partial tile per vehicle
+    const long long tiles = c->max_groups / (BLOCK / 128) + c->max_agents;
     const size_t bytes = sizeof(float) * (size_t)tiles * (size_t)(2 * c->max_N + 2);
     if (hipMalloc((void **)&c->d_pi, bytes) != hipSuccess) {
         c->d_pi = nullptr;
@@ -2690,7 +2978,8 @@ int sgtp_plan_create(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, 
         delete P;
         return rc;
     }
-    if (P->pl.lps == 2) P->opt.persistent = o.persistent = 0;  // the pair variant runs one workgroup per tile
+    // the pair and split variants run one workgroup per tile
+    if (P->pl.lps == 2 || P->pl.split) P->opt.persistent = o.persistent = 0;
     layout_queues(P->pl, P->pl.all, P->qb_all, P->ql_all);
     layout_queues(P->pl, P->pl.ego, P->qb_ego, P->ql_ego);
     P->pl.tiles_all = P->ql_all[NQ - 1] + P->qb_all[NQ - 1];
@@ -2699,7 +2988,7 @@ int sgtp_plan_create(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, 
     LaunchArgs &A = P->base;
     A.P = make_kparams(p);
     A.L = make_layout(P->pl, P->mo, p->n_disc);
-    if (A.L.total > 58 * 1024) {
+    if (A.L.total > LDS_BUDGET) {
         delete P;
         return fail(c, SGTP_ESHAPE, "staged tables exceed the LDS budget");
     }
@@ -2733,6 +3022,7 @@ int sgtp_plan_create(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, 
     A.pi_part = c->d_pi;
     A.spl = o.samples_per_lane;
     A.lps = P->pl.lps;
+    A.split = P->pl.split;
     A.chunk = o.tiles_per_fetch;
     if (o.persistent) {
         int occ = 1, dev = 0, cus = 0;

@@ -144,8 +144,10 @@ PERTURB = {"pred_sig_lon": 0.5, "pred_sig_lat": 0.3}
 
 @pytest.mark.parametrize("name,K,L,over", [("c1", 1024, 3, None), ("c2", 1024, 2, None), ("c3", 512, 1, PERTURB),
                                            ("c1", 1024, 2, PERTURB),
+                                           # two waves per sample (3 x 11111 samples, ragged last tile)
+                                           ("c2", 11111, 2, None), ("c2", 11111, 1, PERTURB),
                                            # full sizes, same kernels as the timed planning steps:
-                                           # mid-scale latency variant (3 x 16384 lanes), large-field
+                                           # mid-scale split variant (3 x 16384 samples), large-field
                                            # throughput variant (10 x 65536 lanes)
                                            ("c2", 16384, 5, None), ("c3", 65536, 1, None)])
 def test_plan_step_lockstep(planner, name, K, L, over):
