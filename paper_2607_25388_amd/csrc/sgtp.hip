@@ -1032,17 +1032,17 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const B
 // ------------------------------------------------------------------------------
 // One sample on two waves (the split variant).  A lane of the workgroup's first half
 // integrates the dynamics, the longest dependent chain of a step.  Its partner lane in
-// the second half does the rest: it draws the perturbation, clips the controls and sums
-// the control terms SPLIT_AHEAD steps ahead, projects every state onto the raceline and
-// scores it (tracking, boundary, footprint distances, tail offsets), then takes the
-// terminal scoring.  Controls and states pass through LDS rings of SPLIT_RING steps;
-// uprod / prod count the controls and states written, cons the states consumed, per
-// wave pair, and each side re-reads a count only when its ring runs empty (or full).
+// the second half does the rest: it draws the perturbation and clips the controls
+// SPLIT_AHEAD steps ahead, projects every state onto the raceline and scores it
+// (tracking, control and rate terms, boundary, footprint distances, tail offsets), then
+// takes the terminal scoring.  Controls and states pass through LDS rings of SPLIT_RING
+// steps; uprod / prod count the controls and states written, cons the states consumed,
+// per wave pair, and each side re-reads a count only when its ring runs empty (or full).
 // The scoring side publishes the controls of step tau + SPLIT_AHEAD before it waits for
 // state tau, and a control slot is rewritten only after its state was published, so
 // both waits end; their bounds are guards only.  Checkpoints: states on the dynamics
-// lane, segments on the scoring lane.  Arithmetic per step as in lane_sample; only the
-// control terms are summed apart from the rest and added at the end.
+// lane, segments on the scoring lane.  Arithmetic and summation order as in lane_sample:
+// the two variants give the same bits.
 // ------------------------------------------------------------------------------
 template <int MODEL, int NDISC, int MAXOPP, int NPF>
 __device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, const BlockState &bs, char *lds,
@@ -1064,7 +1064,7 @@ __device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, cons
     __syncthreads();
     // each side's values, set and used only on that side (one barrier, outside both)
     float cp[NC - 1][6];                                   // dynamics: checkpointed states
-    float J, Ju, rho_bd, dsum, s, g2[MAXOPP];              // scoring
+    float J, rho_bd, dsum, s, g2[MAXOPP];                  // scoring
     bool limit;
     int cseg[NC - 1];
     if (dyn) {
@@ -1117,7 +1117,6 @@ __device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, cons
         const float4 *nodes = (const float4 *)(lds + L.nodes);
         int seg = bs.seg0;
         J = 0.0f;
-        Ju = 0.0f;
         rho_bd = INFINITY;
         dsum = 0.0f;
         s = 0.0f;
@@ -1127,7 +1126,7 @@ __device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, cons
 #pragma unroll
         for (int c = 0; c < NC - 1; ++c) cseg[c] = 0;
         // controls of step t, in step order (one Philox call per pair of steps), published
-        float2 up = make_float2(0.0f, 0.0f), zn = up;
+        float2 zn = make_float2(0.0f, 0.0f);
         int t_u = 0;
         auto control = [&]() {
             const int t = t_u++;
@@ -1139,20 +1138,19 @@ __device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, cons
             } else {
                 z = zn;
             }
-            const float2 u = controls_k(P, bs, lds, L, k, t, ubar[t], z.x, z.y);
-            Ju += ctrl_term(P, u);
-            if (t >= 1) Ju += rate_term(P, u, up);
-            up = u;
-            uring[(t % SPLIT_RING) * TS + i] = u;
+            uring[(t % SPLIT_RING) * TS + i] = controls_k(P, bs, lds, L, k, t, ubar[t], z.x, z.y);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             if (lane == 0) uprod[w] = t + 1;
         };
         const int ahead0 = bs.N < SPLIT_AHEAD ? bs.N : SPLIT_AHEAD;
         for (int t = 0; t < ahead0; ++t) control();
         int seen = 0;  // the dynamics side's count as last read
+        float2 up = make_float2(0.0f, 0.0f);
         for (int tau = 0; tau < bs.N; ++tau) {
             if (tau + SPLIT_AHEAD < bs.N) control();
-            // reads that do not depend on this step's state go first
+            // reads that do not depend on this step's state go first (the step's control is
+            // still in its slot: it is rewritten SPLIT_RING - SPLIT_AHEAD iterations later)
+            const float2 u = uring[(tau % SPLIT_RING) * TS + i];
             const float4 xr = xref[tau];
             NodeAhead<NPF> ahead = read_ahead<NPF>(nodes, bs.W, seg);
             const float2 *ot = opp + tau * (L.n_opp_max * (NDISC + 1));
@@ -1173,7 +1171,11 @@ __device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, cons
             seg = f.seg;
             limit |= f.limit;
             s = f.s;
+            // the terms summed in the one-lane order, so that both variants give the same bits
             J += track_term(P, st4, xr);
+            J += ctrl_term(P, u);
+            if (tau >= 1) J += rate_term(P, u, up);
+            up = u;
             rho_bd = fminf(rho_bd, bound_term(f));
             float ch = 1.0f, sh = 0.0f;
             if (NDISC > 1) {
@@ -1230,7 +1232,7 @@ __device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, cons
             res.cp[c][6] = 0.0f;
         }
     } else {
-        const SampleResult t = terminal<MAXOPP>(P, bs, lds, L, J + Ju, rho_bd, dsum, s, g2, limit, fo);
+        const SampleResult t = terminal<MAXOPP>(P, bs, lds, L, J, rho_bd, dsum, s, g2, limit, fo);
         res.cost = t.cost;
         res.viol = t.viol;
         res.h = t.h;
@@ -2283,8 +2285,10 @@ int build_plan_once(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, i
                     int one_agent, bool allow_split) {
     if (!races || n_races < 1) return fail(c, SGTP_EINVAL, "no races");
     if (n_races > c->max_races) return fail(c, SGTP_ESHAPE, "n_races exceeds the context");
-    // lanes per sample: the pair variant when the launch stays well below one wave per SIMD
-    // (dynamic model, feasibility selection, at most 3 opponents, one sample per lane)
+    // launches of about one wave per SIMD or fewer (at most 3 opponents, one sample per
+    // lane): the split variant where its rings fit in LDS, else the pair variant (dynamic
+    // model, feasibility selection); both measured faster than one lane per sample there,
+    // the split one the faster of the two
     {
         long long samples = 0;
         int nopp = 0;
@@ -2292,8 +2296,9 @@ int build_plan_once(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, i
             samples += (long long)std::max(races[r].K, 0) * std::max(races[r].n_agents, 0);
             nopp = std::max(nopp, races[r].n_agents - 1);
         }
-        pl.lps = (spl == 1 && p->model == 0 && p->update == 0 && nopp <= 3 && samples <= LPS2_MAX_SAMPLES) ? 2 : 1;
-        pl.split = (allow_split && pl.lps == 1 && spl == 1 && nopp <= 3 && samples <= SPLIT_MAX_SAMPLES) ? 1 : 0;
+        pl.split = (allow_split && spl == 1 && nopp <= 3 && samples <= SPLIT_MAX_SAMPLES) ? 1 : 0;
+        pl.lps = (!pl.split && spl == 1 && p->model == 0 && p->update == 0 && nopp <= 3 &&
+                  samples <= LPS2_MAX_SAMPLES) ? 2 : 1;
         pl.tile_samples = BLOCK * spl / (pl.split ? 2 : pl.lps);
     }
     const int gsz = 64 / pl.lps;  // samples per wave (per wave pair when split) = checkpoint group

@@ -254,9 +254,10 @@ def test_argument_errors(planner):
 @pytest.mark.parametrize("name,agent,K,N", [("c1", 0, 2048, None), ("c2", 1, 2048, None), ("c2", 2, 777, None),
                                             ("c1", 1, 1001, 21)])
 def test_pair_variant_matches_one_lane_variant(planner, name, agent, K, N):
-    """Small launches run each sample on a pair of lanes (one axle and one Gaussian pair
-    each); the same samples of a large launch run on one lane.  Both must give the same
-    bits for every per-sample output (ragged K and an odd horizon included)."""
+    """Small launches run each sample on two waves (the dynamics on one, perturbation,
+    projection and scoring on the other; or, where those rings do not fit in LDS, on a
+    pair of lanes); the same samples of a large launch run on one lane.  Both must give
+    the same bits for every per-sample output (ragged K and an odd horizon included)."""
     tr, race, params, _, w = PY.workload(name)
     if N is not None:
         race = inputs.make_race(tr, race.x.shape[0], N, 10.0, False, 3000, 2000)
