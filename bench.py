@@ -28,19 +28,19 @@ METRIC = "sample·steps/s per IBR sweep; plan latency p50/p99; learned vs plain 
 PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak
 
 # Hardware counters of the dominant sweep kernel at the mid-scale race (k_sweep in its
-# one-wave-per-SIMD variant, the schedule the autotuner picks), medians over the timed
-# eager launches of `bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-learned
-# --roofline-steps 2 --copy-calibration 256` under rocprofv3 --pmc, weighted like the
-# timed launches (6 all-vehicle sweeps, 1 ego sweep per planning step).  HBM bytes:
-# FETCH_SIZE 354.1 KiB x 2.000 + WRITE_SIZE 300.6 KiB x 1.000 per launch, the factors being
+# split variant, two waves per sample), medians over the timed eager launches of
+# `bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-learned --roofline-steps 2
+# --copy-calibration 256` under rocprofv3 --pmc, weighted like the timed launches (6
+# all-vehicle sweeps, 1 ego sweep per planning step).  HBM bytes: FETCH_SIZE 454.9 KiB x
+# 2.000 + WRITE_SIZE 315.2 KiB x 1.000 per launch, the factors being
 # 256 MiB over what the same counter reads for the 256 MiB elementwise copy (131087 KiB
 # fetched, 262144 KiB written).  FP32 FLOPs: 64 x (ADD + MUL + TRANS + 2 FMA) wave
 # instructions of SQ_INSTS_VALU_*_F32.  They describe the kernel source with this SHA-256
 # only; any other source reports null.
 SWEEP_COUNTERS = {
-    "c2": {"source_sha256": "a1110f94e51e7b4958a13414532abc92cad4ae8408db933934cdedfa41f08764",
-           "hbm_bytes_per_launch": (387.991 * 1.99976 + 237.478) * 1024.0,
-           "hw_fp32_flop_per_launch": 1.2458e9, "valu_wave_insts_per_launch": 20.55e6},
+    "c2": {"source_sha256": "ac313621658f951a717bc73b34f47e25a87b3ca516a34725bc682f0288fcae73",
+           "hbm_bytes_per_launch": (454.866 * 1.99977 + 315.234) * 1024.0,
+           "hw_fp32_flop_per_launch": 1.2483e9, "valu_wave_insts_per_launch": 22.09e6},
 }
 
 def _source_sha256() -> str:
