@@ -45,8 +45,9 @@ constexpr long long LPS2_MAX_SAMPLES = 32768;  // pair variant up to 1024 waves
 // waves, dynamics on one and projection and scoring on the other, its states passing
 // through an LDS ring of SPLIT_RING steps.
 constexpr long long SPLIT_MAX_SAMPLES = 65536;  // up to 2048 waves
-constexpr int SPLIT_RING = 8;
-constexpr int SPLIT_AHEAD = 4;  // controls published ahead of the state being scored
+constexpr int SPLIT_RING = 4;
+constexpr int SPLIT_AHEAD = 2;  // controls published ahead of the state being scored (2 and a
+                                // ring of 4 measured faster than 1, 3, 4 or 6 and a ring of 8)
 constexpr int SPLIT_FIN = 8;    // floats per sample handed from the dynamics to the scoring lane
 constexpr int NQ = 8;           // tile queues of the persistent sweep (one per XCD under round-robin dispatch)
 // Re-roll chunks: each lane keeps its state after every ceil(N / chunks) steps, so the
