@@ -143,7 +143,7 @@ def test_adam_first_step_and_training_reduces_loss():
             losses.append(float(loss.item()))
     print(losses)
     # the likelihood of a fit with shrinking scales rises far above the start; single
-    # Adam steps can still spike, so the last values are judged by their median
+    # Adam steps can still spike, so the last values are assessed by their median
     assert min(losses[1:]) < losses[0] - 50.0, losses
     assert float(np.median(losses[-3:])) < losses[0] - 10.0, losses
     m.close()
