@@ -252,8 +252,11 @@ def test_argument_errors(planner):
 
 
 @pytest.mark.parametrize("name,agent,K,N", [("c1", 0, 2048, None), ("c2", 1, 2048, None), ("c2", 2, 777, None),
-                                            ("c1", 1, 1001, 21)])
-def test_pair_variant_matches_one_lane_variant(planner, name, agent, K, N):
+                                            ("c1", 1, 1001, 21),
+                                            # horizons shorter than the control look-ahead of the
+                                            # two-wave variant, and one step longer
+                                            ("c1", 0, 300, 1), ("c2", 1, 513, 2), ("c2", 0, 129, 3)])
+def test_small_launch_variants_match_one_lane_variant(planner, name, agent, K, N):
     """Small launches run each sample on two waves (the dynamics on one, perturbation,
     projection and scoring on the other; or, where those rings do not fit in LDS, on a
     pair of lanes); the same samples of a large launch run on one lane.  Both must give
@@ -268,7 +271,7 @@ def test_pair_variant_matches_one_lane_variant(planner, name, agent, K, N):
         assert np.array_equal(small[nm].view(np.uint8), large[nm][:K].view(np.uint8)), nm
     # the selection over the first K samples: the small launch's choice is its own argmin
     r = PY.oracle_for(tr, params).rollout_cost(race, agent, 1, K)
-    PY.check_choice(small["choice"], r, params, f"{name} pair variant")
+    PY.check_choice(small["choice"], r, params, f"{name} small-launch variant")
 
 
 @pytest.mark.parametrize("name,agent,K", [("c2", 0, 2048), ("c3", 3, 1000)])
