@@ -286,3 +286,25 @@ def test_rollout_cost_with_prediction_perturbation(planner, name, agent, K):
     # where some sample comes within the safety distance, the cost sees the perturbation too
     if np.any(r0["rho_obs"] < params["g_safe"]):
         assert not np.array_equal(g["cost"], g0["cost"])
+
+
+def test_lds_fallback_when_split_rings_do_not_fit(planner):
+    """A raceline with 0.1 m nodes makes the staged window so long (~1300 nodes at N = 40)
+    that the two-wave variant's LDS rings no longer fit in the 58 KiB budget: the plan is
+    built again without them (here the pair variant) and must still give the one-lane
+    bits and the oracle's choice."""
+    import paper_2607_25388_amd.sgtp as sg
+    budget, rings = 58 * 1024, 4 * 128 * 16 + 4 * 128 * 8 + 32 + 128 * 8 * 4
+    tr = inputs.make_fourier_track(300.0, 10.0, 1000, ds=0.1)
+    params = inputs.default_params(40, 1)
+    race = inputs.make_race(tr, 2, 40, 10.0, False, 3001, 2001)
+    plan = planner.plan(params, [PY.build(planner, tr, race, params, 1024)], 1, sg.plan_options(), trace=False)
+    info = plan.info()
+    plan.close()
+    assert info["lds_bytes"] <= budget < info["lds_bytes"] + rings, info
+    small = PY.gpu_rollout(planner, params, PY.build(planner, tr, race, params, 1024), 0, 1, want_noise=True)
+    large = PY.gpu_rollout(planner, params, PY.build(planner, tr, race, params, 40000), 0, 1, want_noise=True)
+    for nm in ("cost", "viol", "flags", "x_final", "noise"):
+        assert np.array_equal(small[nm].view(np.uint8), large[nm][:1024].view(np.uint8)), nm
+    r = PY.oracle_for(tr, params).rollout_cost(race, 0, 1, 1024)
+    PY.check_choice(small["choice"], r, params, "LDS fallback")
