@@ -221,10 +221,17 @@ int sgtp_plan_destroy(sgtp_plan *plan);
 
 /* Time candidate schedules (one workgroup per tile with 1 or 2 samples per lane;
  * persistent with 1, 2, 4 tiles per fetch at full or 2-per-CU occupancy) on real
- * planning steps of these races and return the fastest in *best (use_graph set).
- * The races' u_nom and s_abs are saved and restored; allocates temporary memory. */
+ * planning steps of these races and return the fastest in *best (use_graph set) and
+ * its median step time in *best_ms (may be NULL).  The races' u_nom and s_abs are saved
+ * and restored; allocates temporary memory.  The result is kept in the context, keyed
+ * by model, footprint discs, opponent-count bucket (1, 3, 9, 15), longest horizon,
+ * floor(log2) of the total samples and of the race count, and update rule; a later
+ * call with the same key returns it at once (no timing, no allocation, nothing
+ * enqueued). */
 int sgtp_autotune(sgtp_ctx *ctx, const sgtp_params *p, const sgtp_race *races, int n_races, int L_ibr,
                   float *u_apply, sgtp_plan_options *best, double *best_ms, void *stream);
+/* Drop every schedule sgtp_autotune has kept in this context. */
+int sgtp_autotune_forget(sgtp_ctx *ctx);
 
 /* ---- learned proposal (project extension; network in sgtp_mlp_*) ------------ */
 

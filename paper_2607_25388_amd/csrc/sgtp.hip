@@ -25,7 +25,9 @@
 #include <algorithm>
 #include <type_traits>
 #include <cmath>
+#include <array>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -2146,8 +2148,17 @@ struct TrackHost {
     double length = 0, psi_lap = 0, ds_min = 0, vmax = 0, inner_factor = 1;
 };
 
+// Autotuner cache key: model, discs, opponent bucket, longest horizon, log2 of the total
+// samples, log2 of the race count, update rule (the device is the context's own).
+using TuneKey = std::array<long long, 7>;
+struct TuneEntry {
+    sgtp_plan_options opt;
+    double ms;
+};
+
 struct sgtp_ctx {
     int device = 0;
+    std::map<TuneKey, TuneEntry> tune_cache;  // schedules found by sgtp_autotune
     int max_agents = 0, max_N = 0, max_races = 0, max_nodes = 0;
     std::string err;
     TrackHost tracks[MAX_TRACKS];
@@ -3127,6 +3138,32 @@ int sgtp_autotune(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int
     if (!c) return SGTP_EINVAL;
     if (!best) return fail(c, SGTP_EINVAL, "best is NULL");
     if (!races || n_races < 1) return fail(c, SGTP_EINVAL, "no races");
+    // a schedule found before for this kind of workload is returned without timing
+    TuneKey key{};
+    {
+        long long samples = 0;
+        int N = 0, nopp = 0;
+        for (int r = 0; r < n_races; ++r) {
+            samples += (long long)std::max(races[r].K, 0) * std::max(races[r].n_agents, 0);
+            N = std::max(N, races[r].N);
+            nopp = std::max(nopp, races[r].n_agents - 1);
+        }
+        auto lg = [](long long v) {
+            long long b = 0;
+            while (v > 1) {
+                v >>= 1;
+                ++b;
+            }
+            return b;
+        };
+        key = TuneKey{p->model, p->n_disc, maxopp_bucket(nopp), N, lg(samples), lg(n_races), p->update};
+        const auto hit = c->tune_cache.find(key);
+        if (hit != c->tune_cache.end()) {
+            *best = hit->second.opt;
+            if (best_ms) *best_ms = hit->second.ms;
+            return SGTP_OK;
+        }
+    }
     hipStream_t st = (hipStream_t)stream;
     // the search runs real planning steps: save and restore the mutable race state
     std::vector<void *> saved;
@@ -3212,6 +3249,13 @@ int sgtp_autotune(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int
     best_o.use_graph = 1;
     *best = best_o;
     if (best_ms) *best_ms = best_t;
+    c->tune_cache[key] = TuneEntry{best_o, best_t};
+    return SGTP_OK;
+}
+
+int sgtp_autotune_forget(sgtp_ctx *c) {
+    if (!c) return SGTP_EINVAL;
+    c->tune_cache.clear();
     return SGTP_OK;
 }
 

@@ -107,6 +107,7 @@ def load():
         lib.sgtp_plan_destroy.argtypes = [vp]
         lib.sgtp_autotune.argtypes = [vp, P(Params), P(Race), C.c_int, C.c_int, vp, P(PlanOptions),
                                       P(C.c_double), vp]
+        lib.sgtp_autotune_forget.argtypes = [vp]
         lib.sgtp_features.argtypes = [vp, P(Params), P(Race), C.c_int, vp, vp]
         lib.sgtp_proposal_from_outputs.argtypes = [vp, P(Params), P(Race), C.c_int, vp, C.c_int, C.c_int, vp]
         lib.sgtp_mlp_create.argtypes = [C.c_int, P(vp)]
@@ -305,6 +306,10 @@ class Planner:
         self._check(self.lib.sgtp_autotune(self.ctx, C.byref(P), arr, len(races), L_ibr, _ptr(u), C.byref(best),
                                            C.byref(ms), _stream()), "sgtp_autotune")
         return best, ms.value
+
+    def autotune_forget(self):
+        """Drop the schedules the autotuner has kept in this context."""
+        self._check(self.lib.sgtp_autotune_forget(self.ctx), "sgtp_autotune_forget")
 
     def features(self, params: dict, races):
         import torch

@@ -2,6 +2,8 @@
 autotuner.  The per-vehicle computation does not depend on the launch schedule, so every
 schedule must give the same bits as planning each race on its own."""
 
+import time
+
 import numpy as np
 import pytest
 
@@ -138,8 +140,21 @@ def test_graph_with_closed_loop_advance(planner):
 def test_autotune_returns_a_valid_schedule(planner):
     tracks, races, specs, params, rts = _batch(planner, 5, 93)
     before = [r.u_nom.cpu().numpy().copy() for r in rts]
+    t0 = time.perf_counter()
     best, ms = planner.autotune(params, rts, 1)
+    t_search = time.perf_counter() - t0
     assert ms > 0 and best.use_graph == 1
     assert best.samples_per_lane in (1, 2) and best.tiles_per_fetch in (1, 2, 4)
     for r, b in zip(rts, before):  # state restored
         np.testing.assert_array_equal(r.u_nom.cpu().numpy(), b)
+    # the same kind of workload again: the kept schedule, returned without timing
+    t0 = time.perf_counter()
+    best2, ms2 = planner.autotune(params, rts, 1)
+    assert time.perf_counter() - t0 < 0.2 * t_search
+    assert (best2.persistent, best2.blocks_per_cu, best2.tiles_per_fetch, best2.samples_per_lane, best2.use_graph) == \
+        (best.persistent, best.blocks_per_cu, best.tiles_per_fetch, best.samples_per_lane, best.use_graph)
+    assert ms2 == ms
+    # after forgetting, the search runs again (and times again)
+    planner.autotune_forget()
+    best3, ms3 = planner.autotune(params, rts, 1)
+    assert ms3 > 0 and best3.use_graph == 1
