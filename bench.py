@@ -32,14 +32,14 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak
 # `bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-learned --roofline-steps 2
 # --copy-calibration 256` under rocprofv3 --pmc, weighted like the timed launches (6
 # all-vehicle sweeps, 1 ego sweep per planning step).  HBM bytes: FETCH_SIZE 447.4 KiB x
-# 2.000 + WRITE_SIZE 321.8 KiB x 1.000 per launch, the factors being
+# 2.000 + WRITE_SIZE 312.9 KiB x 1.000 per launch, the factors being
 # 256 MiB over what the same counter reads for the 256 MiB elementwise copy (131087 KiB
 # fetched, 262144 KiB written).  FP32 FLOPs: 64 x (ADD + MUL + TRANS + 2 FMA) wave
 # instructions of SQ_INSTS_VALU_*_F32.  They describe the kernel source with this SHA-256
 # only; any other source reports null.
 SWEEP_COUNTERS = {
-    "c2": {"source_sha256": "fdb5a2e4d54578bd2f26e59be39f671d0574e115a413772489f5e8ef10e7300c",
-           "hbm_bytes_per_launch": (447.393 * 1.99976 + 321.830) * 1024.0,
+    "c2": {"source_sha256": "3268250d50ca64fb12a766db77544b6c2f07c528177391b5f1d000cc1df26e02",
+           "hbm_bytes_per_launch": (447.446 * 1.99976 + 312.917) * 1024.0,
            "hw_fp32_flop_per_launch": 1.2483e9, "valu_wave_insts_per_launch": 22.06e6},
 }
 
