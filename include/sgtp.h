@@ -187,7 +187,13 @@ int sgtp_advance(sgtp_ctx *ctx, const sgtp_params *p, const sgtp_race *races, in
  * output arrays, uploads their descriptors once and runs Alg. 1 for all races per
  * call: one setup launch, then one sweep launch per phase covering every vehicle
  * of every race.  Tiles of BLOCK = 256 samples (x samples_per_lane) are the unit
- * of work; a persistent sweep keeps a fixed grid of workgroups that pull chunks of
+ * of work; small plans (at most 65536 samples over all vehicles, at most 3
+ * opponents, one sample per lane) run 128-sample tiles with each sample on two waves
+ * (dynamics on one; perturbation, projection and scoring on the other), or, where
+ * those LDS rings do not fit, with each sample on a pair of lanes (dynamic model,
+ * feasibility selection, at most 32768 samples); these plans run one workgroup per
+ * tile (persistent is ignored).  Every variant gives the same per-sample bits.  A
+ * persistent sweep keeps a fixed grid of workgroups that pull chunks of
  * tiles from 8 queues (vehicles assigned longest-first; a workgroup serves its own
  * queue first, then steals), re-staging LDS only when the vehicle changes.  With
  * use_graph the whole planning step is captured once into a hipGraph and replayed
