@@ -139,3 +139,24 @@ def test_contact_criterion_ends_trials_at_touch_not_at_margin():
     m = RE.trial_metrics(s, d, X, np.zeros((T, 2)), np.full(T, 1.25), Ps, 0.1, contact=(0.58, 0.31))
     assert m["collided"] and not m["off_track"]
     assert m["duration"] == pytest.approx(5 * 0.1)  # gap 0.9 - 0.1 k < 0.58 first at k = 4
+
+
+def test_small_scale_setup_is_the_papers():
+    """The paper-scale evaluation uses the constants Sec. IV-B prints: K = 128 samples over
+    a 1.2 s horizon of H = 12 steps, sigma = (0.335, 0.025), Q, R, S, w_game = 60,
+    s_contest = 8 m, s_role = 1 m, mu_tail = 0.3, g_safe = 1.0 m, L_IBR = 2,
+    m_bd = 0.515 m, d_col = 0.9 m, game weights (1, 2, 10, 50), 2 m queue spacing,
+    three vehicles; a point footprint (eq. Dmin) and the kinematic bicycle."""
+    from paper_2607_25388_amd.inputs import small_scale_params
+    sc = RE.SCALES["small"]
+    p = sc["params"](sc["N"])
+    assert sc["K"] == 128 and sc["N"] == 12 and sc["L"] == 2 and sc["spacing"] == 2.0
+    assert p["N"] == 12 and p["dt"] * p["N"] == pytest.approx(1.2)
+    assert (p["sigma_a"], p["sigma_d"]) == (0.335, 0.025)
+    assert p["Q"] == [60.0, 60.0, 47.75, 39.48] and p["R"] == [8.43, 20.0] and p["S"] == [1.0, 19.26]
+    assert (p["w_game"], p["s_contest"], p["s_role"], p["g_safe"]) == (60.0, 8.0, 1.0, 1.0)
+    assert (p["w_contest"], p["w_long"], p["w_block"], p["w_safety"]) == (1.0, 2.0, 10.0, 50.0)
+    assert (p["m_bd"], p["d_col"]) == (0.515, 0.9)
+    assert p["n_tail"] == math.ceil(0.3 * 12)
+    assert p["model"] == 1 and p["n_disc"] == 1 and p["disc_off"][0] == 0.0
+    assert small_scale_params(12) == p
