@@ -255,7 +255,9 @@ def test_argument_errors(planner):
                                             ("c1", 1, 1001, 21),
                                             # horizons shorter than the control look-ahead of the
                                             # two-wave variant, and one step longer
-                                            ("c1", 0, 300, 1), ("c2", 1, 513, 2), ("c2", 0, 129, 3)])
+                                            ("c1", 0, 300, 1), ("c2", 1, 513, 2), ("c2", 0, 129, 3),
+                                            # the longest horizon the library takes
+                                            ("c2", 2, 2048, 64)])
 def test_small_launch_variants_match_one_lane_variant(planner, name, agent, K, N):
     """Small launches run each sample on two waves (the dynamics on one, perturbation,
     projection and scoring on the other; or, where those rings do not fit in LDS, on a
