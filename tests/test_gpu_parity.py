@@ -123,10 +123,20 @@ def test_open_straight_track(planner):
     PY.check_choice(g["choice"], r, params, "straight")
 
 
+def _paper_scale_race():
+    """Three 1:10 cars queued 2 m apart on a twisty 150 m x 2.5 m loop with the paper's
+    own setup (Sec. IV-B: kinematic bicycle, H = 12 over 1.2 s, point footprint)."""
+    from paper_2607_25388_amd import race_eval as RE
+    sc = RE.SCALES["small"]
+    tr = inputs.make_fourier_track(sc["length"], sc["width"], 1106, **sc["track"])
+    race = inputs.make_race(tr, 3, sc["N"], sc["spacing"], False, 60600, 60600)
+    return tr, race, sc["params"](sc["N"])
+
+
 def _plan(planner, name, K, L, params_over=None):
     import torch
     import paper_2607_25388_amd.sgtp as sg
-    tr, race, params, _, w = PY.workload(name)
+    tr, race, params = _paper_scale_race() if name == "paper" else PY.workload(name)[:3]
     if params_over:
         params = dict(params, **params_over)
     rt = PY.build(planner, tr, race, params, K)
@@ -149,7 +159,11 @@ PERTURB = {"pred_sig_lon": 0.5, "pred_sig_lat": 0.3}
                                            # full sizes, same kernels as the timed planning steps:
                                            # mid-scale split variant (3 x 16384 samples), large-field
                                            # throughput variant (10 x 65536 lanes)
-                                           ("c2", 16384, 5, None), ("c3", 65536, 1, None)])
+                                           ("c2", 16384, 5, None), ("c3", 65536, 1, None),
+                                           # the paper's own setup: K = 128, L = 2, plain and with
+                                           # the severe prediction perturbation of Table III
+                                           ("paper", 128, 2, None),
+                                           ("paper", 128, 2, {"pred_sig_lon": 0.08, "pred_sig_lat": 0.04})])
 def test_plan_step_lockstep(planner, name, K, L, over):
     """Alg. 1 on the GPU; the oracle replays it adopting the GPU's choices phase by phase
     and must agree with each choice (or find it a near-tie)."""
