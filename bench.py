@@ -217,8 +217,8 @@ def _races_for(name, sg, inputs, planner):
         L = 5
         per_step = sum(((L + 1) * sp["n_agents"] + 1) * sp["K"] * sp["N"] for sp in specs)
         desc = ("c4: 256 seeded races, 2-10 vehicles (uniform), K in {4096, 16384, 65536}, N in {20, 40, 50}, "
-                "5 IBR sweeps + init + extra ego per race, 3-disc footprint, one persistent launch per sweep, "
-                "hipGraph planning step, autotuned schedule, closed loop")
+                "5 IBR sweeps + init + extra ego per race, 3-disc footprint, one launch per sweep covering every "
+                "race, hipGraph planning step, autotuned schedule, closed loop")
         return rts, params, L, per_step, desc, sum(sp["n_agents"] for sp in specs)
     w = inputs.WORKLOADS[name]
     tr, race, params = inputs.workload_inputs(name)
