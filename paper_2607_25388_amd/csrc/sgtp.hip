@@ -1657,7 +1657,11 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(LaunchArgs A) {
 // (its own first, then the others), restaging LDS only when the vehicle changes.
 // Every workgroup leaves once all queues are exhausted.
 template <int MODEL, int NDISC, int MAXOPP>
-__global__ void __launch_bounds__(BLOCK) k_sweep_persistent(LaunchArgs A) {
+// (at least four waves per SIMD, as the one-workgroup-per-tile throughput kernels reach by
+// themselves: left alone the queue state takes it to ~200 registers and half that
+// occupancy; capped, its spills stay outside the sample loop -- measured +2 % on the
+// 256-race batch, where the tuner then prefers it)
+__global__ void __launch_bounds__(BLOCK, 4) k_sweep_persistent(LaunchArgs A) {
     extern __shared__ __align__(16) char lds[];
     __shared__ int s_last;
     __shared__ int s_fetch[2];
