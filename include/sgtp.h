@@ -231,7 +231,7 @@ int sgtp_plan_destroy(sgtp_plan *plan);
  * its median step time in *best_ms (may be NULL).  The races' u_nom and s_abs are saved
  * and restored; allocates temporary memory.  The result is kept in the context, keyed
  * by model, footprint discs, opponent-count bucket (1, 3, 9, 15), longest horizon,
- * floor(log2) of the total samples and of the race count, and update rule; a later
+ * floor(log2) of the total samples and of the race count, update rule and L_ibr; a later
  * call with the same key returns it at once (no timing, no allocation, nothing
  * enqueued). */
 int sgtp_autotune(sgtp_ctx *ctx, const sgtp_params *p, const sgtp_race *races, int n_races, int L_ibr,

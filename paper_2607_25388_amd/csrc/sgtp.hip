@@ -2153,8 +2153,9 @@ struct TrackHost {
 };
 
 // Autotuner cache key: model, discs, opponent bucket, longest horizon, log2 of the total
-// samples, log2 of the race count, update rule (the device is the context's own).
-using TuneKey = std::array<long long, 7>;
+// samples, log2 of the race count, update rule, IBR sweeps (the device is the context's
+// own).
+using TuneKey = std::array<long long, 8>;
 struct TuneEntry {
     sgtp_plan_options opt;
     double ms;
@@ -3160,7 +3161,7 @@ int sgtp_autotune(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int
             }
             return b;
         };
-        key = TuneKey{p->model, p->n_disc, maxopp_bucket(nopp), N, lg(samples), lg(n_races), p->update};
+        key = TuneKey{p->model, p->n_disc, maxopp_bucket(nopp), N, lg(samples), lg(n_races), p->update, L_ibr};
         const auto hit = c->tune_cache.find(key);
         if (hit != c->tune_cache.end()) {
             *best = hit->second.opt;
