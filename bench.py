@@ -32,15 +32,15 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak
 # `bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-learned --roofline-steps 2
 # --copy-calibration 256` under rocprofv3 --pmc, weighted like the timed launches (6
 # all-vehicle sweeps, 1 ego sweep per planning step).  HBM bytes: FETCH_SIZE 460.0 KiB x
-# 2.000 + WRITE_SIZE 318.4 KiB x 1.000 per launch, the factors being
+# 2.000 + WRITE_SIZE 321.2 KiB x 1.000 per launch, the factors being
 # 256 MiB over what the same counter reads for the 256 MiB elementwise copy (131087 KiB
 # fetched, 262144 KiB written).  FP32 FLOPs: 64 x (ADD + MUL + TRANS + 2 FMA) wave
 # instructions of SQ_INSTS_VALU_*_F32.  They describe the kernel source with this SHA-256
 # only; any other source reports null.
 SWEEP_COUNTERS = {
-    "c2": {"source_sha256": "d5453d31235d9c26d5e02cad1f5f8fa30037b079035acb485c55953f8f546246",
-           "hbm_bytes_per_launch": (460.062 * 1.99976 + 318.397) * 1024.0,
-           "hw_fp32_flop_per_launch": 1.2483e9, "valu_wave_insts_per_launch": 22.06e6},
+    "c2": {"source_sha256": "693eb70a80538a91de084ea1e8c13ffb07b6111bdf2748c5af08dee5ff65c652",
+           "hbm_bytes_per_launch": (460.062 * 1.99976 + 321.237) * 1024.0,
+           "hw_fp32_flop_per_launch": 1.2483e9, "valu_wave_insts_per_launch": 22.02e6},
 }
 
 def _source_sha256() -> str:

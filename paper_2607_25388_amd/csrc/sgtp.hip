@@ -1043,7 +1043,8 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const B
 // per wave pair, and each side re-reads a count only when its ring runs empty (or full).
 // The scoring side publishes the controls of step tau + SPLIT_AHEAD before it waits for
 // state tau, and a control slot is rewritten only after its state was published, so
-// both waits end; their bounds are guards only.  Checkpoints: states on the dynamics
+// both waits end; their bounds are guards only (a wait polls every 256 cycles: shorter
+// sleeps took issue slots from the wave sharing the SIMD, longer ones woke late).  Checkpoints: states on the dynamics
 // lane, segments on the scoring lane.  Arithmetic and summation order as in lane_sample:
 // the two variants give the same bits.
 // ------------------------------------------------------------------------------
@@ -1083,7 +1084,7 @@ __device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, cons
                 for (int spin = 0; spin < (1 << 22); ++spin) {
                     useen = uprod[w];
                     if (useen > tau) break;
-                    __builtin_amdgcn_s_sleep(1);
+                    __builtin_amdgcn_s_sleep(4);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
@@ -1094,7 +1095,7 @@ __device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, cons
                 for (int spin = 0; spin < (1 << 22); ++spin) {
                     seen = cons[w];
                     if (tau - seen < SPLIT_RING) break;
-                    __builtin_amdgcn_s_sleep(1);
+                    __builtin_amdgcn_s_sleep(4);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
@@ -1164,7 +1165,7 @@ __device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, cons
                 for (int spin = 0; spin < (1 << 22); ++spin) {
                     seen = prod[w];
                     if (seen > tau) break;
-                    __builtin_amdgcn_s_sleep(1);
+                    __builtin_amdgcn_s_sleep(4);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
