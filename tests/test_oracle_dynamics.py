@@ -156,3 +156,98 @@ def test_rk4_matches_dop853_under_zero_order_hold(oracle_lib):
     e2 = np.max(np.abs(xh - xi))
     assert e1 < 2e-4
     assert 10.0 < e1 / e2 < 22.0, (e1, e2)
+
+
+def _axle_loads(p):
+    L = p["lf"] + p["lr"]
+    return L, p["m"] * p["g"] * p["lr"] / L, p["m"] * p["g"] * p["lf"] / L
+
+
+def test_single_track_linear_step_response_matches_matrix_exponential(oracle_lib):
+    """Small steering step at constant speed: the lateral states (v_y, omega) follow the
+    linear bicycle model x' = A x + b delta (cornering stiffness = initial slope B C mu F_z
+    of the tyre curve) with the exact zero-order-hold solution x(t) = A^-1 (e^{At} - I) b
+    delta.  A depends on m, I_z, l_f, l_r, both stiffnesses and the v_x omega coupling of
+    v_y', so a swapped inertia, a misplaced axle distance or a sign error fails."""
+    from scipy.linalg import expm
+
+    dt = 0.002
+    orc, p = make(0, dt=dt)
+    m, Iz, lf, lr = p["m"], p["Iz"], p["lf"], p["lr"]
+    L, Fzf, Fzr = _axle_loads(p)
+    Cf = p["B"] * p["C"] * p["mu"] * Fzf
+    Cr = p["B"] * p["C"] * p["mu"] * Fzr
+    for V in (12.0, 30.0):
+        A = np.array([[-(Cf + Cr) / (m * V), (lr * Cr - lf * Cf) / (m * V) - V],
+                      [(lr * Cr - lf * Cf) / (Iz * V), -(lf * lf * Cf + lr * lr * Cr) / (Iz * V)]])
+        b = np.array([Cf / m, lf * Cf / Iz])
+        delta = 1e-5
+        x = np.array([0.0, 0.0, 0.0, V, 0.0, 0.0])
+        n = 500  # 1 s: several time constants of the lateral modes
+        worst = 0.0
+        peak = 0.0
+        for i in range(1, n + 1):
+            x = orc.step(x, [0.0, delta])
+            if i % 25 == 0:
+                t = i * dt
+                lin = np.linalg.solve(A, (expm(A * t) - np.eye(2)) @ b) * delta
+                worst = max(worst, np.max(np.abs(x[4:6] - lin) / np.abs(lin).max()))
+                peak = max(peak, np.abs(lin).max())
+        # nonlinearity O((B alpha)^2) ~ 1e-8 and RK4 error at dt = 2 ms are far below this
+        assert worst < 1e-6, (V, worst)
+        assert peak > 0.0
+        # the longitudinal speed changes only at second order in delta
+        assert abs(x[3] - V) < 1e-6
+
+
+def test_magic_formula_peak_force_at_its_closed_form_slip(oracle_lib):
+    """F_y = mu F_z sin(C atan(B alpha)) reaches its maximum mu F_z at
+    alpha* = tan(pi / (2 C)) / B.  With omega = 0, delta = 0 and a lateral velocity
+    v_y = -v_x tan(alpha*), both axles slide at alpha*: v_y' = mu g exactly (the axle
+    loads sum to m g), omega' = 0 (l_f F_zf = l_r F_zr) and v_x' = 0."""
+    orc, p = make(0)
+    a_star = math.tan(math.pi / (2.0 * p["C"])) / p["B"]
+    V = 20.0
+    dx = orc.deriv(np.array([0.0, 0.0, 0.0, V, -V * math.tan(a_star), 0.0]), np.array([0.0, 0.0]))
+    assert dx[4] == pytest.approx(p["mu"] * p["g"], rel=1e-12)
+    assert dx[5] == pytest.approx(0.0, abs=1e-9)
+    assert dx[3] == pytest.approx(0.0, abs=1e-12)
+    # below and above alpha* the force is smaller (a peak, not a plateau)
+    for f in (0.8, 1.25):
+        d2 = orc.deriv(np.array([0.0, 0.0, 0.0, V, -V * math.tan(f * a_star), 0.0]), np.array([0.0, 0.0]))
+        assert d2[4] < dx[4] - 1e-3
+    # far beyond the peak the force tends to mu F_z sin(C pi / 2)
+    d3 = orc.deriv(np.array([0.0, 0.0, 0.0, V, -V * math.tan(1.5), 0.0]), np.array([0.0, 0.0]))
+    far = p["mu"] * p["g"] * math.sin(p["C"] * math.atan(p["B"] * 1.5))
+    assert d3[4] == pytest.approx(far, rel=1e-12)
+    assert d3[4] < p["mu"] * p["g"] * 0.99
+
+
+def test_front_axle_force_enters_each_rate_with_its_own_lever(oracle_lib):
+    """Front wheel at the peak slip (delta = alpha*, v_y = omega = 0, so the rear axle
+    carries no force): F_yf = mu F_zf.  Its components isolate the terms of f:
+    v_x' = a - F_yf sin(delta) / m, v_y' = F_yf cos(delta) / m, omega' = l_f F_yf cos(delta) / I_z."""
+    orc, p = make(0)
+    a_star = math.tan(math.pi / (2.0 * p["C"])) / p["B"]
+    L, Fzf, _ = _axle_loads(p)
+    F = p["mu"] * Fzf
+    for a in (0.0, 2.5):
+        dx = orc.deriv(np.array([0.0, 0.0, 0.3, 15.0, 0.0, 0.0]), np.array([a, a_star]))
+        assert dx[3] == pytest.approx(a - F * math.sin(a_star) / p["m"], rel=1e-12, abs=1e-12)
+        assert dx[4] == pytest.approx(F * math.cos(a_star) / p["m"], rel=1e-12)
+        assert dx[5] == pytest.approx(p["lf"] * F * math.cos(a_star) / p["Iz"], rel=1e-12)
+        # position rates: the velocity rotated by the heading
+        assert dx[0] == pytest.approx(15.0 * math.cos(0.3), rel=1e-14)
+        assert dx[1] == pytest.approx(15.0 * math.sin(0.3), rel=1e-14)
+    # the rear axle alone (rear slip alpha* from omega, v_y chosen so the front slip is 0)
+    lf, lr = p["lf"], p["lr"]
+    V = 15.0
+    # front: v_y + l_f omega = 0; rear: -(v_y - l_r omega) / V = tan(alpha*) -> omega L = V tan(alpha*)
+    om = V * math.tan(a_star) / (lf + lr)
+    vy = -lf * om
+    _, _, Fzr = _axle_loads(p)
+    dx = orc.deriv(np.array([0.0, 0.0, 0.0, V, vy, om]), np.array([0.0, 0.0]))
+    Fr = p["mu"] * Fzr
+    assert dx[4] == pytest.approx(Fr / p["m"] - V * om, rel=1e-12)
+    assert dx[5] == pytest.approx(-lr * Fr / p["Iz"], rel=1e-12)
+    assert dx[3] == pytest.approx(vy * om, rel=1e-12)

@@ -117,3 +117,57 @@ def test_features_on_straight_and_circle_tracks(oracle_lib):
     race2 = make_race(ct, 2, 20, 10.0, False, 7, 8)
     X2 = features(orc2, race2)
     np.testing.assert_allclose(X2[:, 30:], 20.0 / 40.0, rtol=1e-12)
+
+
+def _identity_net(a, c, w, b3):
+    """A network whose output is known without evaluating GELU: the tanh-form GELU g
+    satisfies g(u) - g(-u) = u (tanh is odd), so with hidden pairs (g(u), g(-u)) the
+    next layer recovers u exactly.  Layer 1: u = a . x + c; layer 2 pre-activations
+    (u, -u); output_j = w_j (g(u) - g(-u)) + b3_j = w_j u + b3_j.  Shapes d_in = len(a),
+    d_h = 2, d_out = len(w) make a transposed weight or a misplaced bias fail."""
+    a = np.asarray(a, float)
+    W1 = np.stack([a, -a], axis=1)                   # [d_in][2]
+    b1 = np.array([c, -c])
+    W2 = np.array([[1.0, -1.0], [-1.0, 1.0]])        # pre2 = (h0 - h1, h1 - h0)
+    b2 = np.zeros(2)
+    w = np.asarray(w, float)
+    W3 = np.stack([w, -w], axis=0)                   # [2][d_out]
+    return MlpOracle(W1, b1, W2, b2, W3, np.asarray(b3, float))
+
+
+def test_mlp_forward_wiring_on_a_network_with_a_closed_form(oracle_lib):
+    a, c = [0.7, -1.3, 0.25], 0.4
+    w = np.linspace(-2.0, 1.5, 8)
+    b3 = np.linspace(0.5, -0.5, 8)
+    m = _identity_net(a, c, w, b3)
+    X = np.array([[0.1, 0.2, 0.3], [-1.0, 0.5, 2.0], [3.0, -2.0, 0.0], [0.0, 0.0, 0.0]])
+    u = X @ np.array(a) + c
+    out, (pre1, h1, pre2, h2) = m.forward(X, intermediates=True)
+    np.testing.assert_allclose(out, u[:, None] * w[None, :] + b3[None, :], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(pre1, np.stack([u, -u], 1), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(pre2, np.stack([u, -u], 1), rtol=0, atol=1e-13)
+    # hidden activations: g(u) + g(-u) = u tanh(c (u + k u^3)) >= 0, and g(u) - g(-u) = u
+    np.testing.assert_allclose(h1[:, 0] - h1[:, 1], u, rtol=0, atol=1e-14)
+    assert np.all(h1[:, 0] + h1[:, 1] >= 0.0)
+
+
+def test_mlp_activation_is_the_tanh_form_of_gelu(oracle_lib):
+    """The activation read out through the network (output = g(x)) against the exact GELU
+    x Phi(x) (scipy's erf): the tanh form of Hendrycks and Gimpel stays within 4.8e-4 of
+    it everywhere, while a wrong constant (sqrt(2/pi) -> 0.8, 0.044715 -> 0.04) does not;
+    g(0) = 0, g(x) -> x for large x and -> 0 for very negative x."""
+    from scipy.special import erf
+
+    # layer 1: (x, -x); layer 2: (g(x) - g(-x), 0) = (x, 0); output g(x) - g(0) = g(x)
+    W1 = np.array([[1.0, -1.0]]); b1 = np.zeros(2)
+    W2 = np.array([[1.0, 0.0], [-1.0, 0.0]]); b2 = np.zeros(2)
+    W3 = np.array([[1.0], [0.0]]); b3 = np.zeros(1)
+    m = MlpOracle(W1, b1, W2, b2, W3, b3)
+    x = np.linspace(-8.0, 8.0, 4001)
+    g = m.forward(x[:, None])[:, 0]
+    exact = 0.5 * x * (1.0 + erf(x / math.sqrt(2.0)))
+    dev = np.abs(g - exact).max()
+    assert 4.0e-4 < dev < 4.8e-4, dev
+    assert g[2000] == 0.0
+    assert g[-1] == pytest.approx(8.0, abs=1e-12)
+    assert abs(g[0]) < 1e-12
