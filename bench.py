@@ -267,7 +267,7 @@ def main():
     name = args.workload
     planner = sg.Planner(max_agents_total=2048, max_races=256)
     if name in ("race", "race_small"):
-        # closed-loop race evaluation of the planner variants (Sec. IV-B metrics, Table II)
+        # closed-loop race evaluation of the planner variants (Sec. IV-C metrics, Table I)
         from paper_2607_25388_amd import race_eval
         planner.close()
         scale = "full" if name == "race" else "small"

@@ -74,7 +74,7 @@ typedef struct {
     int update, pad1;
     double mppi_lambda, mppi_w_viol;
     /* perturbation of the opponents' predicted positions (robustness experiment,
-     * Sec. IV-C, Table III): standard deviations along / across the predicted heading */
+     * Sec. IV-F, Table II): standard deviations along / across the predicted heading */
     double pred_sig_lon, pred_sig_lat;
 } ref_params;
 
@@ -845,8 +845,8 @@ static void agent_setup(const ref_track *T, const ref_params *p, const ref_race 
     ref_reference(T, p, seg, s, R->v_scale[i], A->xr);
 }
 
-/* Perturbed opponent prediction (robustness to prediction uncertainty, Sec. IV-C, Table
- * III; the paper cites its perturbation model without details).  Reading: every predicted
+/* Perturbed opponent prediction (robustness to prediction uncertainty, Sec. IV-F, Table
+ * II; the paper cites its perturbation model without details).  Reading: every predicted
  * position tau = 1..N of opponent j, as seen by `observer` in `phase`, moves by
  * sigma_lon z0 along the predicted heading and sigma_lat z1 across it, with (z0, z1) the
  * Gaussian pair of the first two words of Philox(counter = (2^31 | j, tau,

@@ -1,4 +1,4 @@
-"""Closed-loop race evaluation (Sec. IV: racing scenarios, evaluation metrics, Table II).
+"""Closed-loop race evaluation (Sec. IV: racing scenarios, evaluation metrics, Table I).
 
 Trials of one ego (rearmost) and two slower opponents (reference-speed scale 0.9) on
 seeded synthetic tracks.  Every vehicle runs the same planner and solves its own game
@@ -9,7 +9,7 @@ planner's clearance (footprint discs closer than d_col) for the full-size races 
 contact of the car bodies (oriented rectangles) for the 1:10 cars, whose d_col = 0.9 m
 is a planning margin well outside the body; breaches of d_col are counted there too.
 
-Metrics (Sec. IV-B): Wins (progress gain above every opponent's by eps_s), CFW
+Metrics (Sec. IV-C): Wins (progress gain above every opponent's by eps_s), CFW
 (collision-free share of the wins), FPR (share of opponents ahead of whom the ego ends),
 CSD (mean duration of close-interaction segments), D_mean / D_max / D_ratio (trial
 durations), mean ego speed, MCS (mean squared control change), CT (wall-clock time of a
@@ -18,7 +18,7 @@ planning call).
 Methods: "sgtp" (feasibility selection with the game-aware cost), "sgtp_wo_gc" (the
 same without the game-aware cost, w_game = 0), "ga_ibr_mppi" (path-integral update with
 the game-aware cost, no feasibility selection), "sgtp_mild" / "sgtp_severe" (SGTP with
-the opponents' predicted positions perturbed, Table III).
+the opponents' predicted positions perturbed, Table II).
 """
 
 from __future__ import annotations
@@ -46,7 +46,7 @@ def csd_box(params):
 
 METHODS = ("sgtp", "sgtp_wo_gc", "ga_ibr_mppi", "sgtp_mild", "sgtp_severe")
 
-# opponent-prediction perturbation of Table III, (sigma_lon, sigma_lat) at the paper's
+# opponent-prediction perturbation of Table II, (sigma_lon, sigma_lat) at the paper's
 # vehicle scale, carried over by the ratio of the collision thresholds
 PERTURB_LEVELS = {"mild": (0.03, 0.015), "severe": (0.08, 0.04)}
 

@@ -1,5 +1,5 @@
 """Pins of the oracle's opponent-prediction perturbation (robustness experiment,
-Sec. IV-C, Table III; reading in the oracle's header comment): each predicted position
+Sec. IV-F, Table II; reading in the oracle's header comment): each predicted position
 moves by sigma_lon z0 along and sigma_lat z1 across the predicted heading, (z0, z1) the
 Gaussian pair of a Philox call with a counter of its own."""
 

@@ -1,4 +1,4 @@
-"""Host-side race metrics (Sec. IV-B) on constructed trajectories with known answers."""
+"""Host-side race metrics (Sec. IV-C) on constructed trajectories with known answers."""
 
 import math
 
