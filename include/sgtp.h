@@ -27,7 +27,11 @@
  *   - A context is bound to the device current at creation and must be used
  *     from one host thread at a time.  Calls on one context must be issued on
  *     one stream (the context owns workspace that successive calls reuse).
- *   - The three planning calls allocate nothing and never synchronise the host.
+ *   - The three planning calls allocate nothing.  They do not synchronise the host
+ *     except in one case: the descriptor images of each call pass through a ring of
+ *     8 pinned staging buffers, each guarded by an event, and a call that comes
+ *     round to a buffer whose previous copy has not completed waits for that event
+ *     (hipEventSynchronize) before it reuses the buffer.
  *
  * Frames and units: world frame in metres and radians; states are
  * (x, y, psi, v_x, v_y, omega) at the centre of gravity (the kinematic model
@@ -46,6 +50,10 @@ extern "C" {
 #define SGTP_ETRACK (-3)  /* unknown track id, or track does not fit the kernels */
 #define SGTP_EDEVICE (-4) /* HIP runtime or launch error */
 #define SGTP_ENOMEM (-5)  /* device allocation failed (context creation only) */
+
+/* Bits of the context status word (sgtp_ctx_status). */
+#define SGTP_STATUS_WAIT_GAVE_UP 1   /* a sample's bounded LDS wait gave up: that sample was scored non-finite */
+#define SGTP_STATUS_REROLL_GAVE_UP 2 /* a winner re-roll's bounded LDS wait gave up: its outputs are unreliable */
 
 #define SGTP_MAX_AGENTS 16 /* vehicles per race */
 #define SGTP_MAX_N 64      /* horizon steps */
@@ -84,7 +92,7 @@ typedef struct {
     float mppi_lambda;         /* temperature (> 0) */
     float mppi_w_viol;         /* weight of the violation nu in the score (>= 0) */
     /* Perturbation of the opponents' predicted positions (robustness experiment, Sec.
-     * IV-C, Table III): each predicted position tau = 1..N of opponent j, as staged for
+     * IV-F, Table II): each predicted position tau = 1..N of opponent j, as staged for
      * vehicle i in a phase, moves by pred_sig_lon z0 along and pred_sig_lat z1 across the
      * predicted heading, (z0, z1) the Box-Muller pair of Philox(counter = (2^31 | j, tau,
      * i | phase << 16, plan_step), key = seed).  0, 0 = off. */
@@ -130,6 +138,18 @@ int sgtp_ctx_create(sgtp_ctx **out, int max_agents_total, int max_N, int max_rac
                     int max_K);
 int sgtp_ctx_destroy(sgtp_ctx *ctx);
 const char *sgtp_last_error(const sgtp_ctx *ctx);
+/* The two-wave sweep variant (and the winner re-roll) pass states and controls between
+ * waves of a workgroup through LDS and wait for each other with bounded polls.  Both
+ * waits always end by construction; should one give up all the same, the kernel scores
+ * that sample non-finite (so it is never selected) and raises a bit of the context's
+ * status word (SGTP_STATUS_*).  sgtp_ctx_status waits for `stream`, copies the word to
+ * *flags, clears it when `clear` != 0 and, when it is not zero, sets the text of
+ * sgtp_last_error. */
+int sgtp_ctx_status(sgtp_ctx *ctx, int *flags, int clear, void *stream);
+/* Polls of those bounded waits before they give up (default 2^22, each about 256 cycles
+ * apart); takes effect for calls and plans made afterwards.  For tests of the give-up
+ * path: a limit of a few polls makes the waits give up while every kernel still ends. */
+int sgtp_ctx_set_poll_limit(sgtp_ctx *ctx, int polls);
 /* Allocate the per-tile partial sums of the path-integral update (params.update = 1):
  * (2 max_N + 2) floats per 256 samples of the context's capacity.  Synchronous; calls
  * with update = 1 fail with SGTP_EINVAL before it.  A choice record of that update

@@ -82,6 +82,7 @@ struct KParams {
     float g_safe, m_bd, d_col;
     float inv_lambda, w_viol;                                // path-integral update
     float pred_sig_lon, pred_sig_lat;                        // opponent-prediction perturbation
+    int spin_limit;  // polls of a bounded LDS wait (split variant, winner re-roll) before it gives up
 };
 
 struct TrackDev {
@@ -162,6 +163,7 @@ struct LaunchArgs {
     float *dbg_noise;
     float *cp_slots;       // [group][CP_FLOATS] checkpoints of each wave's best sample
     float *pi_part;        // [tile][2 N_max + 2] path-integral partial sums, or NULL
+    int *status;           // context status word: bits SGTP_STATUS_* set when a bounded wait gave up
 };
 
 // ------------------------------------------------------------------------------
@@ -173,6 +175,9 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
         if (r > 0) {
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
+            // the round keys are bumped in place at every call (scalar adds): kept for the
+            // whole sample loop, twenty of them were spilled and reloaded with v_readlane
+            asm volatile("" : "+s"(k0), "+s"(k1));
         }
         const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
@@ -249,16 +254,7 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 
 // atan: odd polynomial fitted on [0, 1] (max error 3.3e-7), reflected via pi/2 - atan(1/x).
 // (A 6-term fit with 1.8e-6 error moved chaotic sliding samples past the 1e-3 state tolerance.)
-// UNIFORM: the reciprocal of the range reduction only when some lane of the wave needs
-// it (saves issue slots where many waves share a SIMD; a single wave waits on the branch
-// instead); the selected value is the same either way.
-template <bool UNIFORM = false>
-__device__ __forceinline__ float fast_atan(float x) {
-    const float ax = fabsf(x);
-    const bool inv = ax > 1.0f;
-    float t = ax;
-    if (!UNIFORM || __builtin_amdgcn_ballot_w64(inv)) t = inv ? fast_rcp(ax) : ax;
-    const float t2 = t * t;
+__device__ __forceinline__ float atan_poly(float t, float t2) {
     float p = 0x1.be6b36p-8f;
     p = __builtin_fmaf(p, t2, -0x1.134946p-5f);
     p = __builtin_fmaf(p, t2, 0x1.46238ap-4f);
@@ -266,7 +262,19 @@ __device__ __forceinline__ float fast_atan(float x) {
     p = __builtin_fmaf(p, t2, 0x1.95aa02p-3f);
     p = __builtin_fmaf(p, t2, -0x1.552b7cp-2f);
     p = __builtin_fmaf(p, t2, 0x1.ffff7ep-1f);
-    float r = p * t;
+    return p * t;
+}
+// UNIFORM: when no lane of the wave has |x| > 1, the odd polynomial of x itself (no range
+// reduction, no sign handling: p(x^2) x equals copysign(p(|x|^2) |x|, x) bit for bit), taken
+// as a real branch -- saves issue slots where several waves share a SIMD; a wave alone on its
+// SIMD takes the branch-free form instead.  Both forms give the same value.
+template <bool UNIFORM = false>
+__device__ __forceinline__ float fast_atan(float x) {
+    const float ax = fabsf(x);
+    const bool inv = ax > 1.0f;
+    if (UNIFORM && __builtin_expect(__builtin_amdgcn_ballot_w64(inv) == 0, 1)) return atan_poly(x, x * x);
+    const float t = inv ? fast_rcp(ax) : ax;
+    float r = atan_poly(t, t * t);
     r = inv ? (1.57079637f - r) : r;
     return copysignf(r, x);
 }
@@ -286,6 +294,11 @@ struct MathF32 {
     static __device__ __forceinline__ T to_rev(T x) { return x * 0.159154943f; }
     static __device__ __forceinline__ T sin_rev(T x) { return __builtin_amdgcn_sinf(x); }
     static __device__ __forceinline__ T cos_rev(T x) { return __builtin_amdgcn_cosf(x); }
+    // max(x, 0) as one median (0 for a NaN, like x > 0 ? x : 0; +inf becomes the largest
+    // finite value, which only a state that is already non-finite reaches)
+    static __device__ __forceinline__ T pos_(T x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 3.40282347e38f); }
+    // max(x, lo) of a value pos_ returned (never NaN)
+    static __device__ __forceinline__ T floor_(T x, T lo) { return fmaxf(x, lo); }
 };
 
 // MathF32 with the wave-uniform atan range reduction (throughput kernels)
@@ -302,6 +315,8 @@ struct MathF64 {
     static __device__ __forceinline__ T to_rev(T x) { return x; }
     static __device__ __forceinline__ T sin_rev(T x) { return ::sin(x); }
     static __device__ __forceinline__ T cos_rev(T x) { return ::cos(x); }
+    static __device__ __forceinline__ T pos_(T x) { return x > 0.0 ? x : 0.0; }
+    static __device__ __forceinline__ T floor_(T x, T lo) { return x > lo ? x : lo; }
 };
 
 template <typename T>
@@ -372,11 +387,11 @@ __device__ __forceinline__ void deriv(const VehConst<typename M::T> &V, const St
                                       typename M::T psi, typename M::T vx_, typename M::T vy, typename M::T om,
                                       typename M::T d[6]) {
     using T = typename M::T;
-    const T vx = vx_ > T(0) ? vx_ : T(0);
+    const T vx = M::pos_(vx_);
     const T pr = M::to_rev(psi);
     const T cp = M::cos_rev(pr), sp = M::sin_rev(pr);
     if (MODEL == 0) {
-        const T inv_vh = M::rcp_(vx > V.v_eps ? vx : V.v_eps);
+        const T inv_vh = M::rcp_(M::floor_(vx, V.v_eps));
         const T Fyf = tyre_force<M>(V, V.lf, c.delta, V.muFzf, vy, om, inv_vh);
         const T Fyr = tyre_force<M>(V, -V.lr, T(0), V.muFzr, vy, om, inv_vh);
         deriv_rates<M>(V, c, vx, vy, om, cp, sp, Fyf, Fyr, d);
@@ -400,10 +415,10 @@ __device__ __forceinline__ float dpp_swap_f32(float v) {
 // everything else is computed by both lanes alike.  Same values as deriv<0, MathF32>.
 __device__ __forceinline__ void deriv_pair(const VehConst<float> &V, const StepConst<float> &c, float psi, float vx_,
                                            float vy, float om, bool rear, float d[6]) {
-    const float vx = vx_ > 0.0f ? vx_ : 0.0f;
+    const float vx = MathF32::pos_(vx_);
     const float pr = MathF32::to_rev(psi);
     const float cp = MathF32::cos_rev(pr), sp = MathF32::sin_rev(pr);
-    const float inv_vh = MathF32::rcp_(vx > V.v_eps ? vx : V.v_eps);
+    const float inv_vh = MathF32::rcp_(MathF32::floor_(vx, V.v_eps));
     const float F = tyre_force<MathF32>(V, rear ? -V.lr : V.lf, rear ? 0.0f : c.delta, rear ? V.muFzr : V.muFzf, vy,
                                         om, inv_vh);
     const float Fo = dpp_swap_f32(F);
@@ -478,7 +493,10 @@ __device__ __forceinline__ VehConst<float> veh_f32(const KParams &P) {
 }
 
 // Pi_U: box clip; a NaN stays NaN so that the sample is flagged non-finite
-__device__ __forceinline__ float clip_keep_nan(float v, float lo, float hi) { return v < lo ? lo : (v > hi ? hi : v); }
+__device__ __forceinline__ float clip_keep_nan(float v, float lo, float hi) {
+    const float c = __builtin_amdgcn_fmed3f(v, lo, hi);
+    return v != v ? v : c;
+}
 
 // ------------------------------------------------------------------------------
 // Frenet projection on the staged raceline window (normal-interpolated polyline)
@@ -999,9 +1017,13 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const B
         }
         float ax[NDISC], ay[NDISC];
         disc_centres<NDISC>(P, st[0], st[1], ch, sh, ax, ay);
+        // opponent count compared on the scalar unit at every step (held as one compare mask
+        // per opponent, the masks were spilled and reloaded with v_readlane)
+        int n_opp = bs.n_opp;
+        asm volatile("" : "+s"(n_opp));
 #pragma unroll
         for (int j = 0; j < MAXOPP; ++j) {
-            if (j < bs.n_opp) {
+            if (j < n_opp) {
                 if constexpr (PRE_ALL) {
                     g2[j] = opp_min2<NDISC>(P, orow + j * (NDISC + 1), orow[j * (NDISC + 1)], st[0], st[1], ax, ay,
                                             g2[j]);
@@ -1050,7 +1072,8 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const B
 // ------------------------------------------------------------------------------
 template <int MODEL, int NDISC, int MAXOPP, int NPF>
 __device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, const BlockState &bs, char *lds,
-                                                         const LdsLayout &L, uint32_t k, float *noise_out, bool dyn) {
+                                                         const LdsLayout &L, uint32_t k, float *noise_out, bool dyn,
+                                                         int *status) {
     constexpr int TS = BLOCK / 2;
     constexpr int NC = ncp_of<NPF>();
     static_assert(SPLIT_AHEAD + 1 <= SPLIT_RING, "a control slot is rewritten only after its state was published");
@@ -1071,6 +1094,9 @@ __device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, cons
     float J, rho_bd, dsum, s, g2[MAXOPP];                  // scoring
     bool limit;
     int cseg[NC - 1];
+    // a wait that gave up (its partner did not advance within P.spin_limit polls): the
+    // sample's values are then unreliable, so it is scored non-finite (never selected)
+    bool stalled = false;
     if (dyn) {
         const VehConst<float> V = veh_f32(P);
         float st[6] = {0.0f, 0.0f, 0.0f, bs.vx0, bs.vy0, bs.om0};
@@ -1081,22 +1107,24 @@ __device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, cons
         int useen = 0, seen = 0;  // the scoring side's counts as last read
         for (int tau = 0; tau < bs.N; ++tau) {
             if (useen <= tau) {
-                for (int spin = 0; spin < (1 << 22); ++spin) {
+                for (int spin = 0; spin < P.spin_limit; ++spin) {
                     useen = uprod[w];
                     if (useen > tau) break;
                     __builtin_amdgcn_s_sleep(4);
                 }
+                stalled |= useen <= tau;
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
             const float2 u = uring[(tau % SPLIT_RING) * TS + i];
             const StepConst<float> sc = step_const<MODEL, MathF32>(V, u.x, u.y);
             rk4<MODEL, MathF32>(V, sc, P.dt, st);
             if (tau - seen >= SPLIT_RING) {
-                for (int spin = 0; spin < (1 << 22); ++spin) {
+                for (int spin = 0; spin < P.spin_limit; ++spin) {
                     seen = cons[w];
                     if (tau - seen < SPLIT_RING) break;
                     __builtin_amdgcn_s_sleep(4);
                 }
+                stalled |= tau - seen >= SPLIT_RING;
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
             ring[(tau % SPLIT_RING) * TS + i] = make_float4(st[0], st[1], st[2], st[3]);
@@ -1114,6 +1142,7 @@ __device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, cons
         }
 #pragma unroll
         for (int j = 0; j < 6; ++j) fin[i * SPLIT_FIN + j] = st[j];
+        fin[i * SPLIT_FIN + 6] = stalled ? 1.0f : 0.0f;
     } else {
         const float2 *ubar = (const float2 *)(lds + L.ubar);
         const float4 *xref = (const float4 *)(lds + L.xref);
@@ -1162,11 +1191,12 @@ __device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, cons
 #pragma unroll
             for (int j = 0; j < MAXOPP * (NDISC + 1); ++j) orow[j] = ot[j];
             if (seen <= tau) {
-                for (int spin = 0; spin < (1 << 22); ++spin) {
+                for (int spin = 0; spin < P.spin_limit; ++spin) {
                     seen = prod[w];
                     if (seen > tau) break;
                     __builtin_amdgcn_s_sleep(4);
                 }
+                stalled |= seen <= tau;
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
             const float4 sv = ring[(tau % SPLIT_RING) * TS + i];
@@ -1188,9 +1218,11 @@ __device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, cons
             }
             float ax[NDISC], ay[NDISC];
             disc_centres<NDISC>(P, sv.x, sv.y, ch, sh, ax, ay);
+            int n_opp = bs.n_opp;
+            asm volatile("" : "+s"(n_opp));
 #pragma unroll
             for (int j = 0; j < MAXOPP; ++j) {
-                if (j < bs.n_opp)
+                if (j < n_opp)
                     g2[j] = opp_min2<NDISC>(P, orow + j * (NDISC + 1), orow[j * (NDISC + 1)], sv.x, sv.y, ax, ay,
                                             g2[j]);
             }
@@ -1241,6 +1273,13 @@ __device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, cons
         res.viol = t.viol;
         res.h = t.h;
         res.flags = t.flags;
+        if (stalled || fo[6] != 0.0f) {  // either side gave up a wait
+            res.cost = __builtin_nanf("");
+            res.viol = INFINITY;
+            res.h = false;
+            res.flags = (unsigned char)((t.flags & 8) | 16);
+            atomicOr(status, SGTP_STATUS_WAIT_GAVE_UP);
+        }
 #pragma unroll
         for (int j = 0; j < 6; ++j) res.st[j] = t.st[j];
 #pragma unroll
@@ -1256,8 +1295,8 @@ __device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, cons
 template <int MODEL, int NDISC, int MAXOPP, int NPF, int LPS, int SPL>
 __device__ __forceinline__ SampleResult run_sample(const KParams &P, const BlockState &bs, char *lds,
                                                   const LdsLayout &L, uint32_t k, float *noise_out, bool rear,
-                                                  bool dyn) {
-    if constexpr (SPL != 0) return lane_sample_split<MODEL, NDISC, MAXOPP, NPF>(P, bs, lds, L, k, noise_out, dyn);
+                                                  bool dyn, int *status) {
+    if constexpr (SPL != 0) return lane_sample_split<MODEL, NDISC, MAXOPP, NPF>(P, bs, lds, L, k, noise_out, dyn, status);
     else return lane_sample<MODEL, NDISC, MAXOPP, NPF, LPS>(P, bs, lds, L, k, noise_out, rear);
 }
 
@@ -1278,7 +1317,8 @@ struct RerollOut {
 
 template <int MODEL, int MODE, int NPF = 0>
 __device__ void reroll_block(const KParams &P, const LdsLayout &L, const BlockState &bs, char *lds,
-                             const AgentRec &rec, uint32_t k, const RerollOut &out, const float *cps = nullptr) {
+                             const AgentRec &rec, uint32_t k, const RerollOut &out, int *status,
+                             const float *cps = nullptr) {
     const int tid = threadIdx.x, nth = blockDim.x, N = bs.N;
     const float2 *ubar = (const float2 *)(lds + L.ubar);
     const float4 *nodes = (const float4 *)(lds + L.nodes);
@@ -1348,8 +1388,10 @@ __device__ void reroll_block(const KParams &P, const LdsLayout &L, const BlockSt
         for (int tau = pch * C; tau < t_end; ++tau) {
             NodeAhead<(NPF > 0 ? NPF : 1)> ahead;
             if constexpr (NPF > 0) ahead = read_ahead<NPF>(nodes, bs.W, seg);
-            // the dynamics lanes never wait, so this wait ends; the bound is a guard only
-            for (int spin = 0; prog[pch] <= tau && spin < (1 << 22); ++spin) __builtin_amdgcn_s_sleep(1);
+            // the dynamics lanes never wait, so this wait ends; if it gives up all the same
+            // (bound P.spin_limit) the outputs are unreliable and the status word says so
+            for (int spin = 0; prog[pch] <= tau && spin < P.spin_limit; ++spin) __builtin_amdgcn_s_sleep(1);
+            if (prog[pch] <= tau) atomicOr(status, SGTP_STATUS_REROLL_GAVE_UP);
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             const float4 xy = wst[2 * tau];
             Foot f;
@@ -1479,7 +1521,7 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
         // (the split variant draws the perturbation on the scoring lane)
         float *nz = (A.dbg_noise && valid && !rear && !dyn) ? A.dbg_noise + (size_t)k * bs.N * 2 : nullptr;
         const SampleResult res =
-            run_sample<MODEL, NDISC, MAXOPP, NPF, LPS, SPL>(A.P, bs, lds, A.L, valid ? k : 0u, nz, rear, dyn);
+            run_sample<MODEL, NDISC, MAXOPP, NPF, LPS, SPL>(A.P, bs, lds, A.L, valid ? k : 0u, nz, rear, dyn, A.status);
         unsigned long long key;
         if (dyn) {
             key = KEY_NONE;  // scored by the partner lane
@@ -1618,10 +1660,10 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
             if ((int)threadIdx.x < 2 * bs.N) ub[threadIdx.x] = sums[1 + threadIdx.x] / sums[0];
         }
         __syncthreads();
-        reroll_block<MODEL, NOMINAL, NPF>(A.P, A.L, bs, lds, rec, 0u, out);
+        reroll_block<MODEL, NOMINAL, NPF>(A.P, A.L, bs, lds, rec, 0u, out, A.status);
     } else {
         const float *cps = A.cp_slots + ((size_t)it.group0 + k / G) * CP_FLOATS;  // k's lane exported them
-        reroll_block<MODEL, WINNER, NPF>(A.P, A.L, bs, lds, rec, k, out, cps);
+        reroll_block<MODEL, WINNER, NPF>(A.P, A.L, bs, lds, rec, k, out, A.status, cps);
         res.cost = cps[CP_COST];
         res.viol = cps[CP_VIOL];
     }
@@ -1914,7 +1956,7 @@ __global__ void __launch_bounds__(BLOCK) k_setup(LaunchArgs A, int w_limit) {
         const AgentRec rec = s_rec;
         RerollOut out{};
         out.pred = A.pred_out + (size_t)it.slot * (A.L.N_max + 1) * PRED_STRIDE;
-        reroll_block<MODEL, NOMINAL, 6>(A.P, A.L, bs, lds, rec, 0u, out);
+        reroll_block<MODEL, NOMINAL, 6>(A.P, A.L, bs, lds, rec, 0u, out, A.status);
         return;
     }
 
@@ -2180,6 +2222,8 @@ struct sgtp_ctx {
     long long max_groups = 0;
     float *d_pi = nullptr;     // path-integral partial sums per tile (sgtp_ctx_enable_path_integral)
     long long pi_tiles = 0;
+    int *d_status = nullptr;   // SGTP_STATUS_* bits raised by the kernels (read by sgtp_ctx_status)
+    int spin_limit = 1 << 22;  // polls of a bounded LDS wait before it gives up
     // descriptor uploads: pinned ring, each slot guarded by an event
     static constexpr int RING = 8;
     char *h_stage[RING] = {};
@@ -2555,6 +2599,7 @@ struct Runner {
     LaunchArgs A{};
     RaceDev *d_races = nullptr;
     ItemDev *d_all = nullptr, *d_ego = nullptr, *d_one = nullptr;
+    float *pred[2] = {nullptr, nullptr};  // prediction buffers read / written by the sweeps
     int mo = 1;
 
     int init(const sgtp_race *races, int n_races, int one_agent = -1) {
@@ -2564,6 +2609,7 @@ struct Runner {
         if (rc) return rc;
         mo = maxopp_bucket(pl.n_opp_max);
         A.P = make_kparams(p);
+        A.P.spin_limit = c->spin_limit;
         A.L = make_layout(pl, mo, p->n_disc);
         if (A.L.total > LDS_BUDGET) return fail(c, SGTP_ESHAPE, "staged tables exceed the LDS budget");
         rc = upload_plan(c, pl, st, &d_races, &d_all, &d_ego, &d_one);
@@ -2577,10 +2623,13 @@ struct Runner {
         A.nfeas = c->d_nfeas;
         A.counters = c->d_counters;
         A.cp_slots = c->d_cp;
-    A.pi_part = c->d_pi;
+        A.pi_part = c->d_pi;
+        A.status = c->d_status;
         A.spl = 1;
         A.lps = pl.lps;
         A.split = pl.split;
+        pred[0] = c->d_pred[0];
+        pred[1] = c->d_pred[1];
         return SGTP_OK;
     }
     // projection, frames, windows, references, initial predictions (into pred[0])
@@ -2588,7 +2637,7 @@ struct Runner {
         LaunchArgs a = A;
         a.items = d_all;
         a.n_items = (int)pl.all.size();
-        a.pred_out = c->d_pred[0];
+        a.pred_out = pred[0];
         if (p->model == 0)
             hipLaunchKernelGGL(k_setup<0>, dim3(2 * a.n_items), dim3(BLOCK), A.L.total, st, a, pl.w_max);
         else
@@ -2606,22 +2655,23 @@ struct Runner {
         a.n_items = (int)host_items.size();
         a.n_tiles = n_tiles;
         a.phase = phase;
-        a.pred_in = c->d_pred[par];
-        a.pred_out = c->d_pred[par ^ 1];
+        a.pred_in = pred[par];
+        a.pred_out = pred[par ^ 1];
         a.choice = choice;
         a.choice_base = choice_base;
         a.adopt = adopt;
         a.final_mode = final_mode;
         a.u_apply = (float2 *)u_apply;
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (c->timing) {
+        const bool timed = c->timing;
+        if (timed) {
             HIPCHK(c, hipEventCreate(&e0));
             HIPCHK(c, hipEventCreate(&e1));
             HIPCHK(c, hipEventRecord(e0, st));
         }
         dispatch_sweep(p->model, p->n_disc, mo, a, st);
         HIPCHK(c, hipGetLastError());
-        if (c->timing) {
+        if (timed) {
             HIPCHK(c, hipEventRecord(e1, st));
             c->ev_pairs.push_back(e0);
             c->ev_pairs.push_back(e1);
@@ -2792,6 +2842,7 @@ int sgtp_ctx_create(sgtp_ctx **out, int max_agents_total, int max_N, int max_rac
     al((void **)&c->d_keys, sizeof(unsigned long long) * max_agents_total);
     al((void **)&c->d_nfeas, sizeof(int) * max_agents_total);
     al((void **)&c->d_counters, sizeof(int) * max_agents_total);
+    al((void **)&c->d_status, sizeof(int));
     c->max_groups = (long long)max_agents_total * ((max_K + 63) / 64);
     al((void **)&c->d_cp, sizeof(float) * CP_FLOATS * 2 * (size_t)c->max_groups);  // 2: pair variant groups of 32
     c->desc_bytes = ((sizeof(RaceDev) * max_races + 255) & ~size_t(255)) +
@@ -2814,8 +2865,8 @@ int sgtp_ctx_destroy(sgtp_ctx *c) {
     (void)hipDeviceSynchronize();
     for (auto &t : c->tracks)
         if (t.d_nodes) (void)hipFree(t.d_nodes);
-    void *bufs[] = {c->d_tracks, c->d_agents, c->d_win,      c->d_xref, c->d_pred[0], c->d_pred[1],
-                    c->d_keys,   c->d_nfeas,  c->d_counters, c->d_cp,   c->d_desc,   c->d_pi};
+    void *bufs[] = {c->d_tracks, c->d_agents,   c->d_win, c->d_xref, c->d_pred[0], c->d_pred[1], c->d_keys,
+                    c->d_nfeas,  c->d_counters, c->d_cp,  c->d_desc, c->d_pi,      c->d_status};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (int i = 0; i < sgtp_ctx::RING; ++i) {
@@ -2828,6 +2879,33 @@ int sgtp_ctx_destroy(sgtp_ctx *c) {
 }
 
 const char *sgtp_last_error(const sgtp_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int sgtp_ctx_status(sgtp_ctx *c, int *flags, int clear, void *stream) {
+    if (!c || !flags) return SGTP_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    int v = 0;
+    HIPCHK(c, hipMemcpyAsync(&v, c->d_status, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (clear && v) {
+        const int zero = 0;
+        HIPCHK(c, hipMemcpy(c->d_status, &zero, sizeof(int), hipMemcpyHostToDevice));
+    }
+    *flags = v;
+    if (v) {
+        std::string m = "kernel status:";
+        if (v & SGTP_STATUS_WAIT_GAVE_UP)
+            m += " a sample's bounded LDS wait gave up (the sample was scored non-finite)";
+        if (v & SGTP_STATUS_REROLL_GAVE_UP) m += " a winner re-roll's bounded LDS wait gave up (outputs unreliable)";
+        c->err = m;
+    }
+    return SGTP_OK;
+}
+
+int sgtp_ctx_set_poll_limit(sgtp_ctx *c, int polls) {
+    if (!c || polls < 1) return SGTP_EINVAL;
+    c->spin_limit = polls;
+    return SGTP_OK;
+}
 
 int sgtp_ctx_enable_path_integral(sgtp_ctx *c) {
     if (!c) return SGTP_EINVAL;
@@ -3010,6 +3088,7 @@ int sgtp_plan_create(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, 
     P->mo = maxopp_bucket(P->pl.n_opp_max);
     LaunchArgs &A = P->base;
     A.P = make_kparams(p);
+    A.P.spin_limit = c->spin_limit;
     A.L = make_layout(P->pl, P->mo, p->n_disc);
     if (A.L.total > LDS_BUDGET) {
         delete P;
@@ -3043,6 +3122,7 @@ int sgtp_plan_create(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, 
     A.counters = c->d_counters;
     A.cp_slots = c->d_cp;
     A.pi_part = c->d_pi;
+    A.status = c->d_status;
     A.spl = o.samples_per_lane;
     A.lps = P->pl.lps;
     A.split = P->pl.split;

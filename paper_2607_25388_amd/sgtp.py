@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(PKG, "libsgtp.so")
 SGTP_MAX_AGENTS = 16
 SGTP_MAX_N = 64
 ERRORS = {-1: "EINVAL", -2: "ESHAPE", -3: "ETRACK", -4: "EDEVICE", -5: "ENOMEM"}
+SGTP_STATUS_WAIT_GAVE_UP = 1    # a sample's bounded LDS wait gave up (sample scored non-finite)
+SGTP_STATUS_REROLL_GAVE_UP = 2  # a winner re-roll's bounded LDS wait gave up (outputs unreliable)
 
 
 class Params(C.Structure):
@@ -92,6 +94,8 @@ def load():
         lib.sgtp_ctx_enable_path_integral.argtypes = [vp]
         lib.sgtp_last_error.argtypes = [vp]
         lib.sgtp_last_error.restype = C.c_char_p
+        lib.sgtp_ctx_status.argtypes = [vp, P(C.c_int), C.c_int, vp]
+        lib.sgtp_ctx_set_poll_limit.argtypes = [vp, C.c_int]
         lib.sgtp_track_upload.argtypes = [vp, C.c_int, vp, C.c_int, C.c_int, C.c_double, C.c_double]
         lib.sgtp_rollout_cost.argtypes = [vp, P(Params), P(Race), C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp]
         lib.sgtp_ibr_sweep.argtypes = [vp, P(Params), P(Race), C.c_int, C.c_int, C.c_int, vp, vp]
@@ -329,6 +333,16 @@ class Planner:
 
     def set_timing(self, on: bool):
         self._check(self.lib.sgtp_set_timing(self.ctx, 1 if on else 0), "sgtp_set_timing")
+
+    def status(self, clear=True) -> int:
+        """SGTP_STATUS_* bits the kernels raised (waits for the current stream); cleared by default."""
+        v = C.c_int()
+        self._check(self.lib.sgtp_ctx_status(self.ctx, C.byref(v), 1 if clear else 0, _stream()), "sgtp_ctx_status")
+        return v.value
+
+    def set_poll_limit(self, polls: int):
+        """Polls of the kernels' bounded LDS waits before they give up (tests of the give-up path)."""
+        self._check(self.lib.sgtp_ctx_set_poll_limit(self.ctx, int(polls)), "sgtp_ctx_set_poll_limit")
 
     def sweep_stats(self, reset=False):
         ms = C.c_double()

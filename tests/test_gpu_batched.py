@@ -158,3 +158,75 @@ def test_autotune_returns_a_valid_schedule(planner):
     planner.autotune_forget()
     best3, ms3 = planner.autotune(params, rts, 1)
     assert ms3 > 0 and best3.use_graph == 1
+
+
+def _p32(params):
+    """The parameter values the C ABI carries (float32), for float64 checks of the advance."""
+    return {k: ([float(np.float32(x)) for x in v] if isinstance(v, list) else
+                (float(np.float32(v)) if isinstance(v, float) else v)) for k, v in params.items()}
+
+
+def test_batched_graph_plan_matches_oracle_lockstep(planner):
+    """An uneven batch of the batched workload's kind -- 10 races of 2-10 vehicles, horizons
+    20/40/50, K in {300, 777, 1024, 2048}, a 3-disc footprint, egos other than vehicle 0 in
+    two races of three -- planned in one persistent launch per sweep with the planning step
+    and the closed-loop advance captured in a hipGraph.  Over two replays every race is
+    replayed by the oracle's Alg. 1 from the state the GPU started that step from,
+    adopting the GPU's choices: every choice agrees (or is a near-tie) and the first
+    controls, warm starts, trajectories, progress and advanced states match."""
+    import torch
+    import oracle
+    import parity as PY
+    import paper_2607_25388_amd.sgtp as sg
+    tracks, races, specs, params = inputs.batched_workload(
+        10, 77, K_override=lambda sp: [300, 777, 1024, 2048][sp["race"] % 4])
+    for rc, sp in zip(races, specs):
+        rc.ego = {0: 0, 1: rc.n_agents - 1, 2: rc.n_agents // 2}[sp["race"] % 3]
+    assert sorted({rc.n_agents for rc in races}) == [2, 3, 4, 5, 6, 8, 9, 10]
+    assert sorted({sp["N"] for sp in specs}) == [20, 40, 50]
+    for N, tr in tracks.items():
+        planner.upload_track(TRACK_ID[N], tr)
+    rts = [sg.race_from_inputs(rc, TRACK_ID[sp["N"]], sp["K"], sp["N"], inputs.n_tail_from_fraction(0.3, sp["N"]),
+                               plan_step=0) for rc, sp in zip(races, specs)]
+    L = 2
+    plan = planner.plan(params, rts, L, sg.plan_options(persistent=1, tiles_per_fetch=2, use_graph=1,
+                                                        include_advance=1))
+    state = [dict(x=rc.x.copy(), u=np.asarray(rc.u_nom, np.float64), s=rc.s_abs.copy()) for rc in races]
+    orcs, orcs32 = {}, {}
+    for N, tr in tracks.items():
+        p = dict(params, N=N, n_tail=inputs.n_tail_from_fraction(0.3, N))
+        orcs[N] = oracle.Oracle(tr, p)
+        orcs32[N] = oracle.Oracle(tr, _p32(p))
+    exact = total = 0
+    for step in range(2):
+        plan.run()
+        torch.cuda.synchronize()
+        gtr_all = plan.choices().copy()
+        u_all = plan.u_apply.cpu().numpy().astype(np.float64)
+        base = 0
+        for r, (rc, sp, rt) in enumerate(zip(races, specs, rts)):
+            n, N, K = rc.n_agents, sp["N"], sp["K"]
+            label = f"step {step} race {r} (n={n}, N={N}, K={K}, ego={rc.ego})"
+            print(label, flush=True)
+            gtr = gtr_all[:, base:base + n]
+            forced = PY.forced_from_trace(gtr, L, n, rc.ego)
+            ref = orcs[N].plan_step(rc, L, K=K, forced=forced, x=state[r]["x"], u_nom=state[r]["u"],
+                                    s_prev=state[r]["s"], plan_step=step)
+            exact += PY.check_lockstep(gtr, ref, forced, label)
+            total += int((forced >= 0).sum())
+            np.testing.assert_allclose(u_all[base:base + n], ref["u_apply"], atol=1e-5, err_msg=label)
+            u_next = rt.u_nom.cpu().numpy()
+            np.testing.assert_allclose(u_next, ref["u_next"], atol=1e-5, err_msg=label)
+            traj = rt.traj.cpu().numpy()
+            assert np.max(np.abs(traj[:, :, :2] - ref["traj"][:, :, :2])) < PY.TOL_STATE, label
+            s_abs = rt.s_abs.cpu().numpy()
+            np.testing.assert_allclose(s_abs, ref["s_abs"], atol=1e-6, err_msg=label)
+            # closed loop: the advanced state is the oracle's interval from the same controls
+            x_next = rt.x.cpu().numpy()
+            x_ref = orcs32[N].advance(state[r]["x"], u_all[base:base + n])
+            np.testing.assert_allclose(x_next, x_ref, rtol=0, atol=1e-9, err_msg=label)
+            state[r] = dict(x=x_next, u=u_next.astype(np.float64), s=s_abs)
+            base += n
+    plan.close()
+    print(f"identical choices {exact} of {total}")
+    assert exact >= total // 2

@@ -58,11 +58,72 @@ def test_rollout_cost_multi_disc_and_many_agents(planner, name, agent, K):
 
 
 def test_full_size_large_field_sampled(planner):
-    """C3 shape at full K = 65536 for one vehicle, every sample compared."""
-    tr, race, params, g, r = _run(planner, "c3", 4, 2, 65536)
+    """C3 shape at full K = 65536 for one vehicle, every sample compared, and all
+    65536 x 50 perturbation pairs bit for bit."""
+    tr, race, params, g, r = _run(planner, "c3", 4, 2, 65536, want_noise=True)
+    diff = np.count_nonzero(g["noise"].view(np.uint32) != r["noise"].view(np.uint32))
+    assert diff == 0, f"{diff} perturbations differ"
     st = PY.compare_samples(g, r, params, tr.width, "c3 full")
     PY.check_choice(g["choice"], r, params, "c3 full")
     print(st)
+
+
+def test_noise_bit_exact_late_in_the_counter_space(planner):
+    """Every field of the Philox counter away from zero: planning step 7, vehicle 9 of
+    ten, the extra-response phase 6 (L = 5), a ragged K."""
+    def late(rc):
+        rc.plan_step = 7
+        return rc
+    tr, race, params, _, w = PY.workload("c3")
+    race = late(copy.deepcopy(race))
+    rt = PY.build(planner, tr, race, params, 1999, plan_step=7)
+    g = PY.gpu_rollout(planner, params, rt, 9, 6, want_noise=True)
+    r = PY.oracle_for(tr, params).rollout_cost(race, 9, 6, 1999, noise=True)
+    diff = np.count_nonzero(g["noise"].view(np.uint32) != r["noise"].view(np.uint32))
+    assert diff == 0, f"{diff} perturbations differ"
+    # the counter fields do select a different stream
+    r0 = PY.oracle_for(tr, params).rollout_cost(race, 9, 6, 16, noise=True, plan_step=0)
+    assert not np.array_equal(r0["noise"], r["noise"][:16])
+    PY.compare_samples(g, r, params, tr.width, "late counter")
+    PY.check_choice(g["choice"], r, params, "late counter")
+
+
+def _field16():
+    """Sixteen vehicles (the most one race takes) on the large-field track, staggered grid."""
+    tr, _, params, _, w = PY.workload("c3")
+    race = inputs.make_race(tr, 16, w.N, 8.0, True, 3016, 2016)
+    return tr, race, params
+
+
+@pytest.mark.parametrize("agent", [0, 9, 15])
+def test_sixteen_vehicles_per_sample(planner, agent):
+    tr, race, params = _field16()
+    rt = PY.build(planner, tr, race, params, 1500)
+    g = PY.gpu_rollout(planner, params, rt, agent, 1, want_noise=True)
+    r = PY.oracle_for(tr, params).rollout_cost(race, agent, 1, 1500, noise=True)
+    assert np.array_equal(g["noise"].view(np.uint32), r["noise"].view(np.uint32))
+    PY.compare_samples(g, r, params, tr.width, f"16 vehicles a{agent}")
+    PY.check_choice(g["choice"], r, params, f"16 vehicles a{agent}")
+
+
+def test_sixteen_vehicles_plan_step_lockstep(planner):
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    tr, race, params = _field16()
+    race.ego = 3
+    K, L = 768, 1
+    rt = PY.build(planner, tr, race, params, K)
+    n = race.n_agents
+    trace = torch.zeros((L + 2) * n * sg.CHOICE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    u_apply = planner.plan_step(params, [rt], L, trace=trace).cpu().numpy()
+    torch.cuda.synchronize()
+    gtr = sg.choices_to_numpy(trace).reshape(L + 2, n)
+    forced = PY.forced_from_trace(gtr, L, n, race.ego)
+    ref = PY.oracle_for(tr, params).plan_step(race, L, K=K, forced=forced)
+    PY.check_lockstep(gtr, ref, forced, "16 vehicles")
+    np.testing.assert_allclose(u_apply, ref["u_apply"], atol=1e-5)
+    np.testing.assert_allclose(rt.u_nom.cpu().numpy(), ref["u_next"], atol=1e-5)
+    assert np.max(np.abs(rt.traj.cpu().numpy()[:, :, :2] - ref["traj"][:, :, :2])) < PY.TOL_STATE
 
 
 def test_kinematic_model(planner):
@@ -133,12 +194,13 @@ def _paper_scale_race():
     return tr, race, sc["params"](sc["N"])
 
 
-def _plan(planner, name, K, L, params_over=None):
+def _plan(planner, name, K, L, params_over=None, ego=0):
     import torch
     import paper_2607_25388_amd.sgtp as sg
     tr, race, params = _paper_scale_race() if name == "paper" else PY.workload(name)[:3]
     if params_over:
         params = dict(params, **params_over)
+    race.ego = ego
     rt = PY.build(planner, tr, race, params, K)
     n = race.n_agents
     trace = torch.zeros((L + 2) * n * sg.CHOICE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
@@ -152,45 +214,29 @@ def _plan(planner, name, K, L, params_over=None):
 PERTURB = {"pred_sig_lon": 0.5, "pred_sig_lat": 0.3}
 
 
-@pytest.mark.parametrize("name,K,L,over", [("c1", 1024, 3, None), ("c2", 1024, 2, None), ("c3", 512, 1, PERTURB),
-                                           ("c1", 1024, 2, PERTURB),
-                                           # two waves per sample (3 x 11111 samples, ragged last tile)
-                                           ("c2", 11111, 2, None), ("c2", 11111, 1, PERTURB),
-                                           # full sizes, same kernels as the timed planning steps:
-                                           # mid-scale split variant (3 x 16384 samples), large-field
-                                           # throughput variant (10 x 65536 lanes)
-                                           ("c2", 16384, 5, None), ("c3", 65536, 1, None),
-                                           # the paper's own setup: K = 128, L = 2, plain and with
-                                           # the severe prediction perturbation of Table III
-                                           ("paper", 128, 2, None),
-                                           ("paper", 128, 2, {"pred_sig_lon": 0.08, "pred_sig_lat": 0.04})])
-def test_plan_step_lockstep(planner, name, K, L, over):
+@pytest.mark.parametrize("name,K,L,over,ego", [
+    ("c1", 1024, 3, None, 0), ("c2", 1024, 2, None, 0), ("c3", 512, 1, PERTURB, 0), ("c1", 1024, 2, PERTURB, 0),
+    # the ego is not vehicle 0: the final phase then writes the ego's first control from
+    # its extra response and every other vehicle's from its last sweep
+    ("c1", 1024, 2, None, 1), ("c2", 1024, 2, None, 2), ("c3", 512, 2, None, 7),
+    # two waves per sample (3 x 11111 samples, ragged last tile)
+    ("c2", 11111, 2, None, 0), ("c2", 11111, 1, PERTURB, 1),
+    # full sizes, same kernels as the timed planning steps: mid-scale split variant
+    # (3 x 16384 samples), large-field throughput variant (10 x 65536 lanes)
+    ("c2", 16384, 5, None, 0), ("c3", 65536, 1, None, 0),
+    # the paper's own setup: K = 128, L = 2, plain and with the severe prediction
+    # perturbation of Table II
+    ("paper", 128, 2, None, 0), ("paper", 128, 2, {"pred_sig_lon": 0.08, "pred_sig_lat": 0.04}, 0),
+    ("paper", 128, 2, None, 2)])
+def test_plan_step_lockstep(planner, name, K, L, over, ego):
     """Alg. 1 on the GPU; the oracle replays it adopting the GPU's choices phase by phase
     and must agree with each choice (or find it a near-tie)."""
-    tr, race, params, rt, gtr, u_apply = _plan(planner, name, K, L, over)
+    tr, race, params, rt, gtr, u_apply = _plan(planner, name, K, L, over, ego)
     n = race.n_agents
-    forced = np.full((L + 2, n), -1, np.int32)
-    for ph in range(L + 2):
-        for i in range(n):
-            if ph <= L or i == race.ego:
-                forced[ph, i] = gtr[ph, i]["k"]
+    forced = PY.forced_from_trace(gtr, L, n, race.ego)
     orc = PY.oracle_for(tr, params)
     ref = orc.plan_step(race, L, K=K, forced=forced)
-    exact = 0
-    for ph in range(L + 2):
-        for i in range(n):
-            if forced[ph, i] < 0:
-                continue
-            rc = ref["trace"][ph][i]
-            gc = gtr[ph, i]
-            assert int(gc["fallback"]) == rc["fallback"], (ph, i)
-            if int(gc["k"]) == rc["k"]:
-                exact += 1
-            elif not rc["fallback"]:
-                assert rc["flags_used"] & 4, (ph, i)
-                assert (rc["cost_used"] - rc["cost"]) / rc["scale_used"] <= PY.TOL_COST, (ph, i, rc, gc)
-            if not rc["fallback"]:
-                assert abs(float(gc["cost"]) - rc["cost_used"]) <= PY.TOL_COST * rc["scale_used"], (ph, i)
+    exact = PY.check_lockstep(gtr, ref, forced, name)
     assert exact >= (L + 1) * n // 2
     np.testing.assert_allclose(u_apply, ref["u_apply"], atol=1e-5)
     np.testing.assert_allclose(rt.u_nom.cpu().numpy(), ref["u_next"], atol=1e-5)
@@ -324,3 +370,36 @@ def test_lds_fallback_when_split_rings_do_not_fit(planner):
         assert np.array_equal(small[nm].view(np.uint8), large[nm][:1024].view(np.uint8)), nm
     r = PY.oracle_for(tr, params).rollout_cost(race, 0, 1, 1024)
     PY.check_choice(small["choice"], r, params, "LDS fallback")
+
+
+def test_bounded_wait_give_up_is_reported_and_never_selected(planner):
+    """The two-wave variant's LDS waits always end by construction; their poll bound is a
+    guard.  With the bound set from the host to a single poll, waits give up while every
+    kernel still ends: the affected samples come out non-finite (never selected), the
+    context's status word says so, every other sample keeps the one-lane bits, and with
+    the default bound the status stays clear."""
+    import paper_2607_25388_amd.sgtp as sg
+    tr, race, params, _, w = PY.workload("c2")
+    K = 4096  # two-wave variant (small launch, 2 opponents)
+    ref = PY.gpu_rollout(planner, params, PY.build(planner, tr, race, params, 40000), 1, 1, want_noise=False)
+    assert planner.status() == 0
+    planner.set_poll_limit(1)
+    try:
+        g = PY.gpu_rollout(planner, params, PY.build(planner, tr, race, params, K), 1, 1, want_noise=False)
+        st = planner.status()
+    finally:
+        planner.set_poll_limit(1 << 22)
+    gave_up = (g["flags"] & 16) > 0
+    print(f"status {st}, samples scored non-finite {int(gave_up.sum())} of {K}", flush=True)
+    assert st & sg.SGTP_STATUS_WAIT_GAVE_UP
+    assert gave_up.any() and np.all(np.isinf(g["viol"][gave_up]))
+    assert not np.any(g["flags"][gave_up] & 7)
+    ok = ~gave_up
+    for nm in ("cost", "viol", "flags", "x_final"):
+        assert np.array_equal(g[nm][ok].view(np.uint8), ref[nm][:K][ok].view(np.uint8)), nm
+    k = int(g["choice"]["k"])
+    if ok.any() and (ref["flags"][:K][ok] & 4).any():
+        assert not gave_up[k]
+    # default bound again: a clean run leaves the status clear
+    PY.gpu_rollout(planner, params, PY.build(planner, tr, race, params, K), 1, 1, want_noise=False)
+    assert planner.status() == 0
