@@ -179,6 +179,25 @@ int sgtp_rollout_cost(sgtp_ctx *ctx, const sgtp_params *p, const sgtp_race *race
                       float *cost, unsigned char *flags, float *viol, double *x_final, float *noise,
                       sgtp_choice *out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): sgtp_rollout_cost with the same
+ * arguments, outputs and bits, whose kernels keep every scratch buffer (vehicle records,
+ * raceline windows, reference states, predictions, selection keys and counters,
+ * checkpoint slots, the call's descriptors) in one static device array of about 1.5 MB
+ * per GPU instead of the context's workspace.  It calls no hipMalloc, hipFree or other
+ * device-allocating routine, uses no host staging buffer (descriptors are kernel
+ * arguments) and never synchronises; the context supplies the uploaded tracks, the
+ * parameters' checks, the status word and the error text.  Limits: K <= SGTP_NOALLOC_MAX_K,
+ * the library's vehicle and horizon limits (not the context's), update = 0 (feasibility
+ * selection).  Larger inputs fail with SGTP_ESHAPE, other limits with SGTP_EINVAL, before
+ * anything is enqueued.  The array is shared by every call on a GPU and keeps the last
+ * call's contents (each call rewrites what it reads): calls that overlap on one GPU, on
+ * any stream or context, race and must not be issued. */
+#define SGTP_NOALLOC_MAX_K 65536
+int sgtp_rollout_cost_noalloc(sgtp_ctx *ctx, const sgtp_params *p, const sgtp_race *race, int agent, int phase,
+                              float *cost, unsigned char *flags, float *viol, double *x_final, float *noise,
+                              sgtp_choice *out, void *stream);
+
 /* One Jacobi sweep (phase 0..L) over all vehicles of all races, or the extra ego
  * response (phase = L+1, pass ego_only = 1): every participating vehicle answers
  * the noise-free rollouts of its opponents' current nominals, then adopts its

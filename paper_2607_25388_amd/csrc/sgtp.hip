@@ -28,6 +28,7 @@
 #include <array>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2160,6 +2161,22 @@ __global__ void k_proposal(const RaceDev *races, const ItemDev *items, int n_ite
 }
 
 // Advance the Philox counter word of every race (planning-step index).
+// Descriptor image of a one-vehicle call passed by value and written to device memory
+// (the allocation-free entry point: no host staging buffer, no copy from the host).
+constexpr int NOALLOC_MAX_ITEMS = SGTP_MAX_AGENTS;
+struct DescImage {
+    RaceDev race;
+    ItemDev all[NOALLOC_MAX_ITEMS];
+    ItemDev one;
+    int n_all;
+};
+__global__ void k_write_desc(DescImage img, RaceDev *races, ItemDev *all, ItemDev *one) {
+    const int t = threadIdx.x;
+    if (t == 0) races[0] = img.race;
+    if (t < img.n_all) all[t] = img.all[t];
+    if (t == 0) one[0] = img.one;
+}
+
 __global__ void k_bump_step(RaceDev *races, int n_races) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n_races) races[i].plan_step += 1u;
@@ -2185,6 +2202,48 @@ __global__ void k_advance(const RaceDev *races, const ItemDev *items, int n_item
 }
 
 }  // namespace
+
+// ==============================================================================
+// Allocation-free best response (sgtp_rollout_cost_noalloc): every scratch buffer of
+// its kernels -- vehicle records, raceline windows, reference states, predictions,
+// selection keys and counters, checkpoint slots and the call's descriptors -- lies in
+// one static device array, at most SGTP_NOALLOC_MAX_K samples and SGTP_MAX_AGENTS
+// vehicles, about 1.5 MB per GPU.  Host code never uses the array's name as an
+// address: the address of each device's copy is taken once per device, when a context
+// is created there (map_scratch), and that pointer is what the kernels receive.
+// ==============================================================================
+namespace {
+struct NoallocLayout {
+    size_t agents, win, xref, pred0, pred1, keys, nfeas, counters, cp, races, all, one, total;
+};
+constexpr size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+constexpr NoallocLayout noalloc_layout() {
+    NoallocLayout S{};
+    size_t o = 0;
+    auto take = [&o](size_t bytes) {
+        const size_t r = o;
+        o += al256(bytes);
+        return r;
+    };
+    S.agents = take(sizeof(AgentRec) * SGTP_MAX_AGENTS);
+    S.win = take(sizeof(float4) * 2 * WIN_MAX * SGTP_MAX_AGENTS);
+    S.xref = take(sizeof(float4) * SGTP_MAX_N * SGTP_MAX_AGENTS);
+    S.pred0 = take(sizeof(float) * PRED_STRIDE * (SGTP_MAX_N + 1) * SGTP_MAX_AGENTS);
+    S.pred1 = take(sizeof(float) * PRED_STRIDE * (SGTP_MAX_N + 1) * SGTP_MAX_AGENTS);
+    S.keys = take(sizeof(unsigned long long) * SGTP_MAX_AGENTS);
+    S.nfeas = take(sizeof(int) * SGTP_MAX_AGENTS);
+    S.counters = take(sizeof(int) * SGTP_MAX_AGENTS);
+    // checkpoint slots of one vehicle's samples in groups of 32 (the pair variant's groups)
+    S.cp = take(sizeof(float) * CP_FLOATS * (SGTP_NOALLOC_MAX_K / 32));
+    S.races = take(sizeof(RaceDev));
+    S.all = take(sizeof(ItemDev) * NOALLOC_MAX_ITEMS);
+    S.one = take(sizeof(ItemDev));
+    S.total = o;
+    return S;
+}
+}  // namespace
+
+static __device__ __align__(256) char scratch[noalloc_layout().total];
 
 // ==============================================================================
 // Host side: context, validation, launches, C ABI
@@ -2241,6 +2300,28 @@ struct sgtp_ctx {
 };
 
 namespace {
+
+// The address of each device's copy of `scratch`, taken once per device with that device
+// current (at context creation); host code passes these pointers, never the array's name.
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+int map_scratch(int dev) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return SGTP_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return SGTP_OK;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SGTP_EDEVICE;
+    g_scratch_ptr[dev] = (char *)ptr;
+    return SGTP_OK;
+}
+
+char *scratch_of(int dev) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
 
 int fail(sgtp_ctx *c, int code, const std::string &msg) {
     if (c) c->err = msg;
@@ -2344,9 +2425,9 @@ int maxopp_bucket(int n_opp);
 constexpr int LDS_BUDGET = 58 * 1024;
 
 int build_plan_once(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_races, int spl, Plan &pl,
-                    int one_agent, bool allow_split) {
+                    int one_agent, bool allow_split, bool ctx_limits) {
     if (!races || n_races < 1) return fail(c, SGTP_EINVAL, "no races");
-    if (n_races > c->max_races) return fail(c, SGTP_ESHAPE, "n_races exceeds the context");
+    if (ctx_limits && n_races > c->max_races) return fail(c, SGTP_ESHAPE, "n_races exceeds the context");
     // launches of about one wave per SIMD or fewer (at most 3 opponents, one sample per
     // lane): the split variant where its rings fit in LDS, else the pair variant (dynamic
     // model, feasibility selection); both measured faster than one lane per sample there,
@@ -2372,7 +2453,7 @@ int build_plan_once(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, i
         if (s.n_agents < 1 || s.n_agents > SGTP_MAX_AGENTS) return fail(c, SGTP_EINVAL, "n_agents out of range");
         if (s.ego < 0 || s.ego >= s.n_agents) return fail(c, SGTP_EINVAL, "ego out of range");
         if (s.N < 1 || s.N > SGTP_MAX_N) return fail(c, SGTP_EINVAL, "N out of range");
-        if (s.N > c->max_N) return fail(c, SGTP_ESHAPE, "N exceeds the context");
+        if (ctx_limits && s.N > c->max_N) return fail(c, SGTP_ESHAPE, "N exceeds the context");
         if (s.n_tail < 1 || s.n_tail > s.N) return fail(c, SGTP_EINVAL, "n_tail out of range");
         if (s.K < 1 || s.K > SGTP_MAX_K) return fail(c, SGTP_EINVAL, "K out of range");
         if (!s.x || !s.s_abs || !s.v_scale || !s.u_nom) return fail(c, SGTP_EINVAL, "null race array");
@@ -2416,8 +2497,9 @@ int build_plan_once(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, i
         const double reach = vb * Th + 0.5 * std::max(0.0, (double)p->a_max) * Th * Th + 10.0;
         wneed = std::max(wneed, WIN_BACK + std::ceil(T.inner_factor * reach / T.ds_min) + 8.0);
     }
-    if (slot > c->max_agents) return fail(c, SGTP_ESHAPE, "total vehicles exceed the context");
-    if (group_total > c->max_groups * pl.lps) return fail(c, SGTP_ESHAPE, "total samples exceed the context (max_K)");
+    if (ctx_limits && slot > c->max_agents) return fail(c, SGTP_ESHAPE, "total vehicles exceed the context");
+    if (ctx_limits && group_total > c->max_groups * pl.lps)
+        return fail(c, SGTP_ESHAPE, "total samples exceed the context (max_K)");
     if (p->update == 1 && (long long)pl.tiles_all > c->pi_tiles)
         return fail(c, SGTP_ESHAPE, "tiles exceed the path-integral buffer");
     pl.agents_total = slot;
@@ -2427,11 +2509,11 @@ int build_plan_once(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, i
 
 // The plan of one launch sequence; the split variant only where its LDS ring fits.
 int build_plan(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_races, int spl, Plan &pl,
-               int one_agent = -1) {
-    int rc = build_plan_once(c, p, races, n_races, spl, pl, one_agent, true);
+               int one_agent = -1, bool ctx_limits = true) {
+    int rc = build_plan_once(c, p, races, n_races, spl, pl, one_agent, true, ctx_limits);
     if (rc || !pl.split || make_layout(pl, maxopp_bucket(pl.n_opp_max), p->n_disc).total <= LDS_BUDGET) return rc;
     pl = Plan();
-    return build_plan_once(c, p, races, n_races, spl, pl, one_agent, false);
+    return build_plan_once(c, p, races, n_races, spl, pl, one_agent, false, ctx_limits);
 }
 
 LdsLayout make_layout(const Plan &pl, int maxopp, int ndisc) {
@@ -2600,6 +2682,7 @@ struct Runner {
     RaceDev *d_races = nullptr;
     ItemDev *d_all = nullptr, *d_ego = nullptr, *d_one = nullptr;
     float *pred[2] = {nullptr, nullptr};  // prediction buffers read / written by the sweeps
+    bool allow_timing = true;             // sgtp_set_timing events (not for the allocation-free call)
     int mo = 1;
 
     int init(const sgtp_race *races, int n_races, int one_agent = -1) {
@@ -2630,6 +2713,53 @@ struct Runner {
         A.split = pl.split;
         pred[0] = c->d_pred[0];
         pred[1] = c->d_pred[1];
+        return SGTP_OK;
+    }
+    // One vehicle's best response with every scratch buffer in the static device array at
+    // `base` (noalloc_layout); the descriptors are written there by a kernel.
+    int init_static(const sgtp_race *race, int agent, char *base) {
+        int rc = check_params(c, p);
+        if (rc) return rc;
+        if (p->update != 0) return fail(c, SGTP_EINVAL, "the allocation-free entry point takes update = 0 only");
+        rc = build_plan(c, p, race, 1, 1, pl, agent, false);
+        if (rc) return rc;
+        if (pl.all.size() > (size_t)NOALLOC_MAX_ITEMS || pl.one.size() != 1)
+            return fail(c, SGTP_EINVAL, "bad vehicle count for the allocation-free entry point");
+        mo = maxopp_bucket(pl.n_opp_max);
+        A.P = make_kparams(p);
+        A.P.spin_limit = c->spin_limit;
+        A.L = make_layout(pl, mo, p->n_disc);
+        if (A.L.total > LDS_BUDGET) return fail(c, SGTP_ESHAPE, "staged tables exceed the LDS budget");
+        const NoallocLayout S = noalloc_layout();
+        DescImage img{};
+        img.race = pl.races[0];
+        img.n_all = (int)pl.all.size();
+        for (int i = 0; i < img.n_all; ++i) img.all[i] = pl.all[i];
+        img.one = pl.one[0];
+        img.one.group0 = 0;  // only this vehicle samples: its checkpoint groups start the array
+        d_races = (RaceDev *)(base + S.races);
+        d_all = (ItemDev *)(base + S.all);
+        d_one = (ItemDev *)(base + S.one);
+        d_ego = nullptr;
+        hipLaunchKernelGGL(k_write_desc, dim3(1), dim3(64), 0, st, img, d_races, d_all, d_one);
+        HIPCHK(c, hipGetLastError());
+        A.tracks = c->d_tracks;
+        A.races = d_races;
+        A.agents = (AgentRec *)(base + S.agents);
+        A.win = (float4 *)(base + S.win);
+        A.xref = (float4 *)(base + S.xref);
+        A.keys = (unsigned long long *)(base + S.keys);
+        A.nfeas = (int *)(base + S.nfeas);
+        A.counters = (int *)(base + S.counters);
+        A.cp_slots = (float *)(base + S.cp);
+        A.pi_part = nullptr;
+        A.status = c->d_status;
+        A.spl = 1;
+        A.lps = pl.lps;
+        A.split = pl.split;
+        pred[0] = (float *)(base + S.pred0);
+        pred[1] = (float *)(base + S.pred1);
+        allow_timing = false;
         return SGTP_OK;
     }
     // projection, frames, windows, references, initial predictions (into pred[0])
@@ -2663,7 +2793,7 @@ struct Runner {
         a.final_mode = final_mode;
         a.u_apply = (float2 *)u_apply;
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        const bool timed = c->timing;
+        const bool timed = c->timing && allow_timing;
         if (timed) {
             HIPCHK(c, hipEventCreate(&e0));
             HIPCHK(c, hipEventCreate(&e1));
@@ -2825,7 +2955,8 @@ int sgtp_ctx_create(sgtp_ctx **out, int max_agents_total, int max_N, int max_rac
     c->max_races = max_races;
     c->max_nodes = max_track_nodes;
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1 || hipGetDevice(&c->device) != hipSuccess) {
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1 || hipGetDevice(&c->device) != hipSuccess ||
+        map_scratch(c->device) != SGTP_OK) {
         delete c;
         return SGTP_EDEVICE;
     }
@@ -2973,6 +3104,35 @@ int sgtp_rollout_cost(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *race, 
     if (phase < 0 || phase > 0xffff) return fail(c, SGTP_EINVAL, "phase out of range");
     Runner r{c, p, (hipStream_t)stream};
     int rc = r.init(race, 1, agent);
+    if (rc) return rc;
+    rc = r.setup_all();
+    if (rc) return rc;
+    LaunchArgs dbg = r.A;
+    dbg.dbg_cost = cost;
+    dbg.dbg_flags = flags;
+    dbg.dbg_viol = viol;
+    dbg.dbg_xfinal = x_final;
+    dbg.dbg_noise = noise;
+    const int tiles = (race->K + r.pl.tile_samples - 1) / r.pl.tile_samples;
+    return r.sweep(r.d_one, r.pl.one, tiles, phase, 0, out, r.pl.all[agent].slot, 0, 0, nullptr, &dbg);
+}
+
+int sgtp_rollout_cost_noalloc(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *race, int agent, int phase,
+                              float *cost, unsigned char *flags, float *viol, double *x_final, float *noise,
+                              sgtp_choice *out, void *stream) {
+    if (!c) return SGTP_EINVAL;
+    if (!race) return fail(c, SGTP_EINVAL, "race is NULL");
+    if (agent < 0 || agent >= race->n_agents) return fail(c, SGTP_EINVAL, "agent out of range");
+    if (phase < 0 || phase > 0xffff) return fail(c, SGTP_EINVAL, "phase out of range");
+    if (race->K > SGTP_NOALLOC_MAX_K)
+        return fail(c, SGTP_ESHAPE, "K exceeds the allocation-free entry point's maximum (SGTP_NOALLOC_MAX_K)");
+    int dev = -1;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev != c->device) return fail(c, SGTP_EDEVICE, "the context's device is not the current device");
+    char *base = scratch_of(dev);
+    if (!base) return fail(c, SGTP_EDEVICE, "static scratch not mapped on this device");
+    Runner r{c, p, (hipStream_t)stream};
+    int rc = r.init_static(race, agent, base);
     if (rc) return rc;
     rc = r.setup_all();
     if (rc) return rc;

@@ -98,6 +98,7 @@ def load():
         lib.sgtp_ctx_set_poll_limit.argtypes = [vp, C.c_int]
         lib.sgtp_track_upload.argtypes = [vp, C.c_int, vp, C.c_int, C.c_int, C.c_double, C.c_double]
         lib.sgtp_rollout_cost.argtypes = [vp, P(Params), P(Race), C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp]
+        lib.sgtp_rollout_cost_noalloc.argtypes = lib.sgtp_rollout_cost.argtypes
         lib.sgtp_ibr_sweep.argtypes = [vp, P(Params), P(Race), C.c_int, C.c_int, C.c_int, vp, vp]
         lib.sgtp_plan_step.argtypes = [vp, P(Params), P(Race), C.c_int, C.c_int, vp, vp, vp]
         lib.sgtp_advance.argtypes = [vp, P(Params), P(Race), C.c_int, vp, vp]
@@ -247,7 +248,10 @@ class Planner:
                                                1 if track.closed else 0, float(track.length),
                                                float(track.psi_lap)), "sgtp_track_upload")
 
-    def rollout_cost(self, params: dict, race: RaceTensors, agent: int, phase: int, want_noise=False):
+    def rollout_cost(self, params: dict, race: RaceTensors, agent: int, phase: int, want_noise=False,
+                     noalloc=False):
+        """One best response with per-sample outputs (sgtp_rollout_cost; with noalloc, the
+        allocation-free sgtp_rollout_cost_noalloc, whose scratch is a static device array)."""
         import torch
         K, N = race.K, race.N
         dev = race.x.device
@@ -259,10 +263,10 @@ class Planner:
                    choice=torch.zeros(CHOICE_DTYPE.itemsize, dtype=torch.uint8, device=dev))
         P = make_params(params)
         R = race.struct()
-        rc = self.lib.sgtp_rollout_cost(self.ctx, C.byref(P), C.byref(R), agent, phase, _ptr(out["cost"]),
-                                        _ptr(out["flags"]), _ptr(out["viol"]), _ptr(out["x_final"]),
-                                        _ptr(out["noise"]), _ptr(out["choice"]), _stream())
-        self._check(rc, "sgtp_rollout_cost")
+        fn = self.lib.sgtp_rollout_cost_noalloc if noalloc else self.lib.sgtp_rollout_cost
+        rc = fn(self.ctx, C.byref(P), C.byref(R), agent, phase, _ptr(out["cost"]), _ptr(out["flags"]),
+                _ptr(out["viol"]), _ptr(out["x_final"]), _ptr(out["noise"]), _ptr(out["choice"]), _stream())
+        self._check(rc, "sgtp_rollout_cost_noalloc" if noalloc else "sgtp_rollout_cost")
         return out
 
     def ibr_sweep(self, params: dict, races, phase: int, ego_only: bool = False):
