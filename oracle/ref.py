@@ -27,6 +27,8 @@ def build(force: bool = True) -> str:
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
+    from . import opcount  # the op-counting build of the same source
+    opcount.build(force)
     return LIB
 
 

@@ -50,6 +50,18 @@
 #define REF_MAX_OPP 15
 #define REF_MAX_N 64
 
+/* Scalar types of the per-sample arithmetic (perturbation, rollout, projection and
+ * scoring of one candidate): double and float here.  opcount.cpp compiles this file as
+ * C++ with operation-counting types in their place (REF_COUNTING) to count that work per
+ * sample-step.  Values that do not depend on the candidate (parameters, raceline rows,
+ * opponent predictions, the vehicle's current state) stay double and are not counted. */
+#ifndef REF_COUNTING
+typedef double real;
+typedef float real32;
+#define REF_D(x) (x)
+#define REF_F(x) (x)
+#endif
+
 /* ------------------------------------------------------------------------ */
 /* Interface types (mirrored by ctypes in ref.py)                            */
 /* ------------------------------------------------------------------------ */
@@ -177,53 +189,53 @@ void ref_gauss_pair(uint32_t r_even, uint32_t r_odd, float out[2])
     const float C8 = 0x1.e1f506p+5f, C10 = -0x1.a6d1f2p+4f;
 
     /* ---- radius ---- */
-    float u1 = (float)(2u * (r_even >> 9) + 1u) * 0x1p-24f;
-    uint32_t b = bits_from_f(u1);
+    real32 u1 = (real32)(float)(2u * (r_even >> 9) + 1u) * 0x1p-24f;
+    uint32_t b = bits_from_f(REF_F(u1));
     int e = (int)((b >> 23) & 0xffu) - 127;
-    float m = f_from_bits((b & 0x7fffffu) | 0x3f800000u); /* [1, 2) */
+    real32 m = f_from_bits((b & 0x7fffffu) | 0x3f800000u); /* [1, 2) */
     if (m > SQRT2) {
         m = m * 0.5f;
         e = e + 1;
     }
-    float f = m - 1.0f;
-    float z = f / (m + 1.0f);
-    float w = z * z;
-    float p = fmaf(L13, w, L11);
+    real32 f = m - 1.0f;
+    real32 z = f / (m + 1.0f);
+    real32 w = z * z;
+    real32 p = fmaf(L13, w, L11);
     p = fmaf(p, w, L9);
     p = fmaf(p, w, L7);
     p = fmaf(p, w, L5);
     p = fmaf(p, w, L3);
     p = p * w;
-    float lnm = fmaf(z, p, z + z);
-    float ef = (float)e;
-    float lnu = fmaf(ef, LN2_HI, fmaf(ef, LN2_LO, lnm));
-    float rho = sqrtf(-2.0f * lnu);
+    real32 lnm = fmaf(z, p, z + z);
+    real32 ef = (real32)(float)e;
+    real32 lnu = fmaf(ef, LN2_HI, fmaf(ef, LN2_LO, lnm));
+    real32 rho = sqrtf(-2.0f * lnu);
 
     /* ---- angle ---- */
     uint32_t j = r_odd >> 8;                       /* u2 = j * 2^-24 */
     uint32_t q = (j + (1u << 21)) >> 22;           /* nearest quarter turn */
     int32_t ri = (int32_t)j - (int32_t)(q << 22);  /* remainder in [-2^21, 2^21) */
-    float r = (float)ri * 0x1p-24f;                /* turns, |r| <= 1/8 */
-    float r2 = r * r;
-    float ps = fmaf(S9, r2, S7);
+    real32 r = (real32)(float)ri * 0x1p-24f;      /* turns, |r| <= 1/8 */
+    real32 r2 = r * r;
+    real32 ps = fmaf(S9, r2, S7);
     ps = fmaf(ps, r2, S5);
     ps = fmaf(ps, r2, S3);
     ps = fmaf(ps, r2, S1);
-    float sn = ps * r;
-    float pc = fmaf(C10, r2, C8);
+    real32 sn = ps * r;
+    real32 pc = fmaf(C10, r2, C8);
     pc = fmaf(pc, r2, C6);
     pc = fmaf(pc, r2, C4);
     pc = fmaf(pc, r2, C2);
-    float cs = fmaf(pc, r2, 1.0f);
-    float sin_t, cos_t;
+    real32 cs = fmaf(pc, r2, 1.0f);
+    real32 sin_t, cos_t;
     switch (q & 3u) {
     case 0: sin_t = sn; cos_t = cs; break;
     case 1: sin_t = cs; cos_t = -sn; break;
     case 2: sin_t = -sn; cos_t = -cs; break;
     default: sin_t = -cs; cos_t = sn; break;
     }
-    out[0] = rho * cos_t;
-    out[1] = rho * sin_t;
+    out[0] = REF_F(rho * cos_t);
+    out[1] = REF_F(rho * sin_t);
 }
 
 /* Perturbations of sample k, steps 0..N-1, as float32 [N][2]. */
@@ -246,15 +258,15 @@ void ref_noise_seq(unsigned long long seed, unsigned int plan_step, int agent, i
 /* ------------------------------------------------------------------------ */
 
 /* x = (x, y, psi, vx, vy, omega); u = (a, delta). */
-void ref_deriv(const ref_params *p, const double *x, const double *u, double *dx)
+void ref_deriv(const ref_params *p, const real *x, const real *u, real *dx)
 {
     const double L = p->lf + p->lr;
     /* negative speeds reached inside an RK4 stage do not move the vehicle backwards */
-    const double psi = x[2], vx = fmax(x[3], 0.0), vy = x[4], om = x[5];
-    const double a = u[0], delta = u[1];
+    const real psi = x[2], vx = fmax(x[3], 0.0), vy = x[4], om = x[5];
+    const real a = u[0], delta = u[1];
     if (p->model == 1) {
         /* kinematic bicycle, reference point at the centre of gravity */
-        double beta = atan(p->lr * tan(delta) / L);
+        real beta = atan(p->lr * tan(delta) / L);
         dx[0] = vx * cos(psi + beta);
         dx[1] = vx * sin(psi + beta);
         dx[2] = vx * sin(beta) / p->lr;
@@ -264,25 +276,26 @@ void ref_deriv(const ref_params *p, const double *x, const double *u, double *dx
         return;
     }
     /* dynamic single-track with F_y = mu F_z sin(C atan(B alpha)) */
-    double vh = fmax(vx, p->v_eps);
-    double alpha_f = delta - atan((vy + p->lf * om) / vh);
-    double alpha_r = -atan((vy - p->lr * om) / vh);
+    real vh = fmax(vx, p->v_eps);
+    real alpha_f = delta - atan((vy + p->lf * om) / vh);
+    real alpha_r = -atan((vy - p->lr * om) / vh);
     double Fzf = p->m * p->g * p->lr / L;
     double Fzr = p->m * p->g * p->lf / L;
-    double Fyf = p->mu * Fzf * sin(p->C * atan(p->B * alpha_f));
-    double Fyr = p->mu * Fzr * sin(p->C * atan(p->B * alpha_r));
-    dx[0] = vx * cos(psi) - vy * sin(psi);
-    dx[1] = vx * sin(psi) + vy * cos(psi);
+    real Fyf = p->mu * Fzf * sin(p->C * atan(p->B * alpha_f));
+    real Fyr = p->mu * Fzr * sin(p->C * atan(p->B * alpha_r));
+    const real cpsi = cos(psi), spsi = sin(psi), cdel = cos(delta), sdel = sin(delta);
+    dx[0] = vx * cpsi - vy * spsi;
+    dx[1] = vx * spsi + vy * cpsi;
     dx[2] = om;
-    dx[3] = a - Fyf * sin(delta) / p->m + vy * om;
-    dx[4] = (Fyr + Fyf * cos(delta)) / p->m - vx * om;
-    dx[5] = (p->lf * Fyf * cos(delta) - p->lr * Fyr) / p->Iz;
+    dx[3] = a - Fyf * sdel / p->m + vy * om;
+    dx[4] = (Fyr + Fyf * cdel) / p->m - vx * om;
+    dx[5] = (p->lf * Fyf * cdel - p->lr * Fyr) / p->Iz;
 }
 
 /* One control interval: classic RK4 with u held, then v_x <- max(v_x, 0). */
-void ref_step(const ref_params *p, double *x, const double *u)
+void ref_step(const ref_params *p, real *x, const real *u)
 {
-    double k1[6], k2[6], k3[6], k4[6], xt[6];
+    real k1[6], k2[6], k3[6], k4[6], xt[6];
     const double h = p->dt;
     ref_deriv(p, x, u, k1);
     for (int i = 0; i < 6; ++i) xt[i] = x[i] + 0.5 * h * k1[i];
@@ -329,7 +342,7 @@ static node_t node_at(const ref_track *T, long i)
 }
 
 /* Position of p relative to the normal line at node i: > 0 ahead of it. */
-static double ahead_of(const ref_track *T, long i, const double *p)
+static real ahead_of(const ref_track *T, long i, const real *p)
 {
     node_t nd = node_at(T, i);
     double nx = -sin(nd.psi), ny = cos(nd.psi);
@@ -337,30 +350,30 @@ static double ahead_of(const ref_track *T, long i, const double *p)
 }
 
 typedef struct {
-    double s, d, t, wL, wR;
+    real s, d, t, wL, wR;
 } foot_t;
 
 /* Foot of p on segment i with linearly interpolated normals. */
-static foot_t foot_on_segment(const ref_track *T, long i, const double *p)
+static foot_t foot_on_segment(const ref_track *T, long i, const real *p)
 {
     node_t a = node_at(T, i), b = node_at(T, i + 1);
     double n0x = -sin(a.psi), n0y = cos(a.psi);
     double n1x = -sin(b.psi), n1y = cos(b.psi);
-    double rx = p[0] - a.x, ry = p[1] - a.y;
+    real rx = p[0] - a.x, ry = p[1] - a.y;
     double Dx = b.x - a.x, Dy = b.y - a.y;
     double dnx = n1x - n0x, dny = n1y - n0y;
     /* cross(r - t D, n0 + t dn) = C + B t + A t^2 */
-    double Cc = rx * n0y - ry * n0x;
-    double Bc = (rx * dny - ry * dnx) - (Dx * n0y - Dy * n0x);
+    real Cc = rx * n0y - ry * n0x;
+    real Bc = (rx * dny - ry * dnx) - (Dx * n0y - Dy * n0x);
     double Ac = -(Dx * dny - Dy * dnx);
-    double disc = Bc * Bc - 4.0 * Ac * Cc;
+    real disc = Bc * Bc - 4.0 * Ac * Cc;
     if (disc < 0.0) disc = 0.0;
-    double den = -Bc - copysign(sqrt(disc), Bc);
-    double t = (den != 0.0) ? 2.0 * Cc / den : 0.0;
+    real den = -Bc - copysign(sqrt(disc), Bc);
+    real t = (den != 0.0) ? 2.0 * Cc / den : (real)0.0;
     if (!(t >= 0.0)) t = 0.0; /* also maps NaN to 0 */
     if (t > 1.0) t = 1.0;
-    double cx = a.x + t * Dx, cy = a.y + t * Dy;
-    double nx = n0x + t * dnx, ny = n0y + t * dny;
+    real cx = a.x + t * Dx, cy = a.y + t * Dy;
+    real nx = n0x + t * dnx, ny = n0y + t * dny;
     foot_t f;
     f.t = t;
     f.d = ((p[0] - cx) * nx + (p[1] - cy) * ny) / sqrt(nx * nx + ny * ny);
@@ -375,7 +388,7 @@ static int can_retreat(const ref_track *T, long i) { return T->closed || i > 0; 
 
 /* Local search from segment `seg`; returns the new segment, sets *limit when the
  * point is still outside the segment's normal lines after the search. */
-static long walk(const ref_track *T, int max_moves, const double *p, long seg, int *limit)
+static long walk(const ref_track *T, int max_moves, const real *p, long seg, int *limit)
 {
     long i = seg;
     int moves = 0;
@@ -394,16 +407,17 @@ static long walk(const ref_track *T, int max_moves, const double *p, long seg, i
 /* Global projection: among segments whose normal lines enclose p, the one with the
  * smallest |d| (lowest index on ties); if none encloses p, the segment starting at
  * the nearest node.  Returns the segment in [0, n) and writes (s, d, t). */
-long ref_project_global(const ref_track *T, const double *p, double *out3)
+long ref_project_global(const ref_track *T, const double *p_in, double *out3)
 {
+    const real p[2] = {p_in[0], p_in[1]};
     long nseg = T->closed ? T->n : T->n - 1;
     long best = -1;
     double best_ad = INFINITY;
     for (long i = 0; i < nseg; ++i) {
         if (ahead_of(T, i, p) >= 0.0 && ahead_of(T, i + 1, p) <= 0.0) {
             foot_t f = foot_on_segment(T, i, p);
-            if (fabs(f.d) < best_ad) {
-                best_ad = fabs(f.d);
+            if (fabs(REF_D(f.d)) < best_ad) {
+                best_ad = fabs(REF_D(f.d));
                 best = i;
             }
         }
@@ -412,7 +426,7 @@ long ref_project_global(const ref_track *T, const double *p, double *out3)
         double bd = INFINITY;
         for (long i = 0; i < nseg; ++i) {
             node_t nd = node_at(T, i);
-            double dd = (p[0] - nd.x) * (p[0] - nd.x) + (p[1] - nd.y) * (p[1] - nd.y);
+            double dd = (p_in[0] - nd.x) * (p_in[0] - nd.x) + (p_in[1] - nd.y) * (p_in[1] - nd.y);
             if (dd < bd) {
                 bd = dd;
                 best = i;
@@ -420,23 +434,24 @@ long ref_project_global(const ref_track *T, const double *p, double *out3)
         }
     }
     foot_t f = foot_on_segment(T, best, p);
-    out3[0] = f.s;
-    out3[1] = f.d;
-    out3[2] = f.t;
+    out3[0] = REF_D(f.s);
+    out3[1] = REF_D(f.d);
+    out3[2] = REF_D(f.t);
     return best;
 }
 
 /* Local projection from a segment hint: out = (s, d, t, wL, wR, limit). */
-long ref_project_walk(const ref_track *T, int max_moves, const double *p, long seg, double *out6)
+long ref_project_walk(const ref_track *T, int max_moves, const double *p_in, long seg, double *out6)
 {
+    const real p[2] = {p_in[0], p_in[1]};
     int limit = 0;
     long i = walk(T, max_moves, p, seg, &limit);
     foot_t f = foot_on_segment(T, i, p);
-    out6[0] = f.s;
-    out6[1] = f.d;
-    out6[2] = f.t;
-    out6[3] = f.wL;
-    out6[4] = f.wR;
+    out6[0] = REF_D(f.s);
+    out6[1] = REF_D(f.d);
+    out6[2] = REF_D(f.t);
+    out6[3] = REF_D(f.wL);
+    out6[4] = REF_D(f.wR);
     out6[5] = (double)limit;
     return i;
 }
@@ -489,29 +504,29 @@ void ref_reference(const ref_track *T, const ref_params *p, long seg0, double s0
 /* Rollouts                                                                  */
 /* ------------------------------------------------------------------------ */
 
-static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
+static real clampd(real v, double lo, double hi) { return v < lo ? (real)lo : (v > hi ? (real)hi : v); }
 
 /* Noise-free rollout of a control sequence (already admissible after clipping):
  * traj[tau] = (x, y, psi, vx, vy, omega, s, d) for tau = 0..N (tau = 0 is x0). */
 void ref_rollout_controls(const ref_track *T, const ref_params *p, const double *x0, long seg0, double s0,
                           double d0, const double *U, double *traj)
 {
-    double x[6];
-    memcpy(x, x0, sizeof x);
+    real x[6];
+    for (int i = 0; i < 6; ++i) x[i] = x0[i];
     long seg = seg0;
     for (int i = 0; i < 6; ++i) traj[i] = x0[i];
     traj[6] = s0;
     traj[7] = d0;
     for (int tau = 0; tau < p->N; ++tau) {
-        double u[2] = {clampd(U[2 * tau], p->a_min, p->a_max), clampd(U[2 * tau + 1], p->d_min, p->d_max)};
+        real u[2] = {clampd(U[2 * tau], p->a_min, p->a_max), clampd(U[2 * tau + 1], p->d_min, p->d_max)};
         ref_step(p, x, u);
         int limit;
         seg = walk(T, p->max_moves, x, seg, &limit);
         foot_t f = foot_on_segment(T, seg, x);
         double *o = traj + 8 * (tau + 1);
-        for (int i = 0; i < 6; ++i) o[i] = x[i];
-        o[6] = f.s;
-        o[7] = f.d;
+        for (int i = 0; i < 6; ++i) o[i] = REF_D(x[i]);
+        o[6] = REF_D(f.s);
+        o[7] = REF_D(f.d);
     }
 }
 
@@ -533,10 +548,10 @@ typedef struct {
 } ref_br_in;
 
 typedef struct {
-    double cost, scale, viol, rho_bd, rho_obs, s_final, contest_margin, max_abs_d;
-    double x_final[6];
+    real cost, scale, viol, rho_bd, rho_obs, s_final, contest_margin, max_abs_d;
+    real x_final[6];
     int flags;
-    double U[2 * REF_MAX_N];
+    real U[2 * REF_MAX_N];
 } sample_res;
 
 /* One candidate: perturb, clip, roll out, score, check (Sec. III-A, III-B). */
@@ -548,28 +563,29 @@ static void evaluate_sample(const ref_track *T, const ref_params *p, const ref_b
     ref_noise_seq(in->seed, in->plan_step, in->agent, in->phase, k, N, z);
     if (noise_out) memcpy(noise_out, z, sizeof(float) * 2 * N);
 
-    double x[6];
-    memcpy(x, in->x0, sizeof x);
+    real x[6];
+    for (int i = 0; i < 6; ++i) x[i] = in->x0[i];
     long seg = in->seg0;
-    double J = 0.0, rho_bd = INFINITY, dsum = 0.0, max_abs_d = 0.0;
-    double g[REF_MAX_OPP];
-    for (int j = 0; j < in->n_opp; ++j) g[j] = INFINITY;
-    double up[2] = {0.0, 0.0};
-    double s = in->s0;
+    real J = 0.0, rho_bd = INFINITY, dsum = 0.0, max_abs_d = 0.0;
+    real g2[REF_MAX_OPP]; /* squared footprint distances; d_min of eq. (Dmin) is the root of their minimum */
+    for (int j = 0; j < in->n_opp; ++j) g2[j] = INFINITY;
+    real up[2] = {0.0, 0.0};
+    real s = in->s0;
     int any_limit = 0;
 
     /* learned proposal: samples k < K_prop are drawn about the proposal mean with its
      * scales, the others about the nominal with the plain scales */
     const int use_prop = in->prop && k < in->K_prop;
     for (int tau = 0; tau < N; ++tau) {
-        double u[2];
+        real u[2];
+        const real za = (double)z[2 * tau], zd = (double)z[2 * tau + 1];
         if (use_prop) {
             const double *q = in->prop + 4 * tau;
-            u[0] = clampd(q[0] + q[2] * (double)z[2 * tau], p->a_min, p->a_max);
-            u[1] = clampd(q[1] + q[3] * (double)z[2 * tau + 1], p->d_min, p->d_max);
+            u[0] = clampd(q[0] + q[2] * za, p->a_min, p->a_max);
+            u[1] = clampd(q[1] + q[3] * zd, p->d_min, p->d_max);
         } else {
-            u[0] = clampd(in->ubar[2 * tau] + p->sigma_a * (double)z[2 * tau], p->a_min, p->a_max);
-            u[1] = clampd(in->ubar[2 * tau + 1] + p->sigma_d * (double)z[2 * tau + 1], p->d_min, p->d_max);
+            u[0] = clampd(in->ubar[2 * tau] + p->sigma_a * za, p->a_min, p->a_max);
+            u[1] = clampd(in->ubar[2 * tau + 1] + p->sigma_d * zd, p->d_min, p->d_max);
         }
         res->U[2 * tau] = u[0];
         res->U[2 * tau + 1] = u[1];
@@ -584,33 +600,40 @@ static void evaluate_sample(const ref_track *T, const ref_params *p, const ref_b
 
         /* tracking and control cost, eq. (ctrack) */
         const double *xr = in->xr + 4 * tau;
-        double ex = x[0] - xr[0], ey = x[1] - xr[1];
-        double epsi = remainder(x[2] - xr[2], 2.0 * M_PI);
-        double ev = x[3] - xr[3];
+        real ex = x[0] - xr[0], ey = x[1] - xr[1];
+        real epsi = remainder(x[2] - xr[2], 2.0 * M_PI);
+        real ev = x[3] - xr[3];
         J += p->Q[0] * ex * ex + p->Q[1] * ey * ey + p->Q[2] * epsi * epsi + p->Q[3] * ev * ev;
         J += p->R[0] * u[0] * u[0] + p->R[1] * u[1] * u[1];
         if (tau >= 1) {
-            double da = u[0] - up[0], dd = u[1] - up[1];
+            real da = u[0] - up[0], dd = u[1] - up[1];
             J += p->S[0] * da * da + p->S[1] * dd * dd;
         }
         up[0] = u[0];
         up[1] = u[1];
 
         /* boundary clearance, eq. (selection-boundary) */
-        double rb = fmin(f.wR + f.d, f.wL - f.d);
+        real rb = fmin(f.wR + f.d, f.wL - f.d);
         if (rb < rho_bd || rb != rb) rho_bd = rb;
 
-        /* time-aligned footprint distance to each opponent, eq. (Dmin) */
-        double ch = cos(x[2]), sh = sin(x[2]);
+        /* time-aligned footprint distance to each opponent, eq. (Dmin): the smallest
+         * disc-centre distance over disc pairs and steps, taken as the root of the smallest
+         * squared distance (the root is monotone, so both give the same value) */
+        real ch = cos(x[2]), sh = sin(x[2]);
+        real cax[4], cay[4]; /* own disc centres */
+        for (int a = 0; a < p->n_disc; ++a) {
+            cax[a] = x[0] + p->disc_off[a] * ch;
+            cay[a] = x[1] + p->disc_off[a] * sh;
+        }
         for (int j = 0; j < in->n_opp; ++j) {
             const double *o = in->opp_traj + 8 * ((size_t)j * (N + 1) + tau + 1);
             double och = cos(o[2]), osh = sin(o[2]);
             for (int a = 0; a < p->n_disc; ++a) {
-                double cax = x[0] + p->disc_off[a] * ch, cay = x[1] + p->disc_off[a] * sh;
                 for (int b = 0; b < p->n_disc; ++b) {
                     double cbx = o[0] + p->disc_off[b] * och, cby = o[1] + p->disc_off[b] * osh;
-                    double dist = sqrt((cax - cbx) * (cax - cbx) + (cay - cby) * (cay - cby));
-                    if (dist < g[j] || dist != dist) g[j] = dist;
+                    real ddx = cax[a] - cbx, ddy = cay[a] - cby;
+                    real dist2 = ddx * ddx + ddy * ddy;
+                    if (dist2 < g2[j] || dist2 != dist2) g2[j] = dist2;
                 }
             }
         }
@@ -620,30 +643,32 @@ static void evaluate_sample(const ref_track *T, const ref_params *p, const ref_b
     }
 
     /* game-aware cost, eqs. (game_cost), (c_contest), (c_long), (c_block), (c_safety) */
-    double cgame = 0.0, cgame_abs = 0.0, rho_obs = INFINITY, cmargin = INFINITY;
-    double dbar_i = dsum / (double)p->n_tail;
+    real g[REF_MAX_OPP];
+    for (int j = 0; j < in->n_opp; ++j) g[j] = sqrt(g2[j]);
+    real cgame = 0.0, cgame_abs = 0.0, rho_obs = INFINITY, cmargin = INFINITY;
+    real dbar_i = dsum / (double)p->n_tail;
     for (int j = 0; j < in->n_opp; ++j) {
         const double *oj = in->opp_traj + 8 * ((size_t)j * (N + 1));
         double sN_j = oj[8 * N + 6];
         double dbar_j = 0.0;
         for (int tau = N - p->n_tail + 1; tau <= N; ++tau) dbar_j += oj[8 * tau + 7];
         dbar_j /= (double)p->n_tail;
-        double dsN = s - sN_j;           /* terminal progress gap */
+        real dsN = s - sN_j;           /* terminal progress gap */
         double ds0 = in->s0 - in->opp_s0[j]; /* current progress gap */
         double alpha = 1.0 / (1.0 + fabs(ds0) / (p->s_contest + p->eps_alpha));
         double gamma = (ds0 > p->s_role && ds0 < p->s_contest) ? p->w_block : 0.0;
-        double c_contest = (fabs(dsN) < p->s_contest) ? -p->w_contest : 0.0;
-        double c_long = -p->w_long * alpha * dsN;
-        double c_block = -gamma / (1.0 + fabs(dbar_i - dbar_j));
-        double sh = fmax(0.0, p->g_safe - g[j]);
-        double c_safety = p->w_safety * sh * sh;
+        real c_contest = (fabs(dsN) < p->s_contest) ? (real)-p->w_contest : (real)0.0;
+        real c_long = -p->w_long * alpha * dsN;
+        real c_block = -gamma / (1.0 + fabs(dbar_i - dbar_j));
+        real sh = fmax(0.0, p->g_safe - g[j]);
+        real c_safety = p->w_safety * sh * sh;
         cgame += c_contest + c_long + c_block + c_safety;
         cgame_abs += fabs(c_contest) + fabs(c_long) + fabs(c_block) + fabs(c_safety);
         if (g[j] < rho_obs || g[j] != g[j]) rho_obs = g[j];
-        double cm = fabs(fabs(dsN) - p->s_contest);
+        real cm = fabs(fabs(dsN) - p->s_contest);
         if (cm < cmargin) cmargin = cm;
     }
-    double c = J + in->w_game * cgame; /* eq. (allc) */
+    real c = J + in->w_game * cgame; /* eq. (allc) */
 
     int flags = 0;
     int finite = isfinite(c) && !isnan(rho_bd) && !isnan(rho_obs);
@@ -651,7 +676,7 @@ static void evaluate_sample(const ref_track *T, const ref_params *p, const ref_b
     if (rho_bd >= p->m_bd) flags |= F_B;
     if (rho_obs >= p->d_col) flags |= F_O;
     if (any_limit) flags |= F_LIMIT;
-    double viol = fmax(0.0, p->m_bd - rho_bd) + fmax(0.0, p->d_col - rho_obs);
+    real viol = fmax(0.0, p->m_bd - rho_bd) + fmax(0.0, p->d_col - rho_obs);
     if (!finite) {
         flags |= F_NONFINITE;
         flags &= ~(F_B | F_O);
@@ -667,7 +692,7 @@ static void evaluate_sample(const ref_track *T, const ref_params *p, const ref_b
     res->s_final = s;
     res->contest_margin = cmargin;
     res->max_abs_d = max_abs_d;
-    memcpy(res->x_final, x, sizeof x);
+    for (int i = 0; i < 6; ++i) res->x_final[i] = x[i];
     res->flags = flags;
 }
 
@@ -780,22 +805,24 @@ int ref_best_response(const ref_track *T, const ref_params *p, const ref_br_in *
     for (int k = 0; k < K; ++k) {
         sample_res r;
         evaluate_sample(T, p, in, k, &r, (out && out->noise) ? out->noise + (size_t)k * 2 * N : NULL);
-        cost[k] = r.cost;
-        viol[k] = r.viol;
+        cost[k] = REF_D(r.cost);
+        viol[k] = REF_D(r.viol);
         flags[k] = r.flags;
-        scale[k] = r.scale;
-        if (Uall) memcpy(Uall + (size_t)k * 2 * N, r.U, sizeof(double) * 2 * N);
+        scale[k] = REF_D(r.scale);
+        if (Uall)
+            for (int t = 0; t < 2 * N; ++t) Uall[(size_t)k * 2 * N + t] = REF_D(r.U[t]);
         if (out) {
-            if (out->cost) out->cost[k] = r.cost;
-            if (out->scale) out->scale[k] = r.scale;
-            if (out->viol) out->viol[k] = r.viol;
-            if (out->rho_bd) out->rho_bd[k] = r.rho_bd;
-            if (out->rho_obs) out->rho_obs[k] = r.rho_obs;
-            if (out->s_final) out->s_final[k] = r.s_final;
-            if (out->contest_margin) out->contest_margin[k] = r.contest_margin;
-            if (out->max_abs_d) out->max_abs_d[k] = r.max_abs_d;
+            if (out->cost) out->cost[k] = REF_D(r.cost);
+            if (out->scale) out->scale[k] = REF_D(r.scale);
+            if (out->viol) out->viol[k] = REF_D(r.viol);
+            if (out->rho_bd) out->rho_bd[k] = REF_D(r.rho_bd);
+            if (out->rho_obs) out->rho_obs[k] = REF_D(r.rho_obs);
+            if (out->s_final) out->s_final[k] = REF_D(r.s_final);
+            if (out->contest_margin) out->contest_margin[k] = REF_D(r.contest_margin);
+            if (out->max_abs_d) out->max_abs_d[k] = REF_D(r.max_abs_d);
             if (out->flags) out->flags[k] = r.flags;
-            if (out->x_final) memcpy(out->x_final + 6 * (size_t)k, r.x_final, sizeof r.x_final);
+            if (out->x_final)
+                for (int i = 0; i < 6; ++i) out->x_final[6 * (size_t)k + i] = REF_D(r.x_final[i]);
         }
     }
     if (pi_update) {
@@ -813,7 +840,7 @@ int ref_best_response(const ref_track *T, const ref_params *p, const ref_br_in *
     if (U_out) {
         sample_res r;
         evaluate_sample(T, p, in, ku, &r, NULL);
-        memcpy(U_out, r.U, sizeof(double) * 2 * N);
+        for (int t = 0; t < 2 * N; ++t) U_out[t] = REF_D(r.U[t]);
     }
     free(cost); free(viol); free(flags); free(scale);
     return 0;
@@ -1027,7 +1054,12 @@ int ref_plan_step(const ref_track *T, const ref_params *p, const ref_race *R, in
 /* Closed loop: every agent applies its first control for one interval. */
 void ref_advance(const ref_params *p, int n, double *x, const double *u)
 {
-    for (int i = 0; i < n; ++i) ref_step(p, x + 6 * i, u + 2 * i);
+    for (int i = 0; i < n; ++i) {
+        real xi[6], ui[2] = {u[2 * i], u[2 * i + 1]};
+        for (int j = 0; j < 6; ++j) xi[j] = x[6 * i + j];
+        ref_step(p, xi, ui);
+        for (int j = 0; j < 6; ++j) x[6 * i + j] = REF_D(xi[j]);
+    }
 }
 
 /* ------------------------------------------------------------------------ */
