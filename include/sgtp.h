@@ -49,7 +49,7 @@ extern "C" {
 #define SGTP_ESHAPE (-2)  /* size beyond what the context was created for */
 #define SGTP_ETRACK (-3)  /* unknown track id, or track does not fit the kernels */
 #define SGTP_EDEVICE (-4) /* HIP runtime or launch error */
-#define SGTP_ENOMEM (-5)  /* device allocation failed (context creation only) */
+#define SGTP_ENOMEM (-5)  /* device allocation failed (calls that allocate: context, plans, autotune) */
 
 /* Bits of the context status word (sgtp_ctx_status). */
 #define SGTP_STATUS_WAIT_GAVE_UP 1   /* a sample's bounded LDS wait gave up: that sample was scored non-finite */
@@ -325,6 +325,20 @@ int sgtp_mlp_forward(sgtp_mlp *m, const float *X, int B, float *out, int ld_out,
  * receive copies when not NULL. */
 int sgtp_mlp_grad(sgtp_mlp *m, const float *X, const float *U, int B, int N, float sig_a, float sig_d, float *loss,
                   float *grads, void *stream);
+/* The BF16 operands and float32 outputs of the last sgtp_mlp_grad call, B rows each,
+ * copied into DEVICE dst (stream-ordered): SGTP_MLP_WS_H1 / _H2 the hidden activations
+ * GELU(z) as BF16 [B][256]; _OUT the outputs float32 [B][256] (columns 200..255 zero);
+ * _D3 the output gradient as BF16 [B][256] (columns of steps >= N and 200..255 zero);
+ * _D2 / _D1 the gradients w.r.t. the pre-activations of layers 2 and 1 as BF16
+ * [B][256].  They stay until the next sgtp_mlp_grad.  SGTP_EINVAL before the first
+ * gradient call or for an unknown tensor. */
+#define SGTP_MLP_WS_H1 0
+#define SGTP_MLP_WS_H2 1
+#define SGTP_MLP_WS_OUT 2
+#define SGTP_MLP_WS_D3 3
+#define SGTP_MLP_WS_D2 4
+#define SGTP_MLP_WS_D1 5
+int sgtp_mlp_workspace(sgtp_mlp *m, int which, void *dst, void *stream);
 /* One Adam step with the last gradients (bias-corrected moments). */
 int sgtp_mlp_adam(sgtp_mlp *m, float lr, float beta1, float beta2, float eps, void *stream);
 /* Make every planning step of `plan` compute the proposal tables itself: after the
@@ -348,6 +362,20 @@ int sgtp_set_timing(sgtp_ctx *ctx, int on);
 /* Sum of measured sweep-kernel durations [ms] and launch count since the last
  * reset; synchronises the events.  reset != 0 clears the counters afterwards. */
 int sgtp_sweep_stats(sgtp_ctx *ctx, double *total_ms, long long *launches, long long *sample_steps, int reset);
+
+/* The Gaussian transform of the sampler on given Philox words: out[2 i], out[2 i + 1] =
+ * the pair (z_a, z_delta) of (r_even[i], r_odd[i]) (all DEVICE, n pairs) -- u1 = (2 (r_even
+ * >> 9) + 1) 2^-24, u2 = (r_odd >> 8) 2^-24, z = sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2),
+ * the float32 operation sequence of the samplers (Sec. III draws i.i.d. Gaussian
+ * perturbations; the sequence is fixed so that they are reproducible bit for bit). */
+int sgtp_gauss_pairs(const unsigned int *r_even, const unsigned int *r_odd, float *out, int n, void *stream);
+
+/* A kernel with a known FP32 instruction mix, for checking hardware-counter formulas:
+ * n_waves workgroups of one 64-lane wave; every lane runs `iters` iterations of exactly one
+ * v_add_f32, v_mul_f32, v_fma_f32 and v_exp_f32 (scalar loop control), then three
+ * v_add_f32 and one store to out[64 n_waves] (DEVICE).  Per wave: ADD_F32 = iters + 3,
+ * MUL_F32 = FMA_F32 = TRANS_F32 = iters wave-instructions. */
+int sgtp_counter_probe_fp32(float *out, int n_waves, int iters, void *stream);
 
 int sgtp_abi_version(void);
 

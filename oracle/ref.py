@@ -94,7 +94,7 @@ class BrIn(C.Structure):
 
 
 class Mlp(C.Structure):
-    _fields_ = [("d_in", C.c_int), ("d_h", C.c_int), ("d_out", C.c_int), ("pad0", C.c_int)] + \
+    _fields_ = [("d_in", C.c_int), ("d_h", C.c_int), ("d_out", C.c_int), ("bf16", C.c_int)] + \
                [(nm, C.POINTER(C.c_double)) for nm in ("W1", "b1", "W2", "b2", "W3", "b3")]
 
 
@@ -117,6 +117,7 @@ def load(rebuild: bool = False):
         P = C.POINTER
         lib.ref_philox4x32_10.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
         lib.ref_gauss_pair.argtypes = [C.c_uint32, C.c_uint32, P(C.c_float)]
+        lib.ref_gauss_pairs.argtypes = [C.c_int, P(C.c_uint32), P(C.c_uint32), P(C.c_float)]
         lib.ref_noise_seq.argtypes = [C.c_ulonglong, C.c_uint, C.c_int, C.c_int, C.c_int, C.c_int, P(C.c_float)]
         lib.ref_deriv.argtypes = [P(Params), P(C.c_double), P(C.c_double), P(C.c_double)]
         lib.ref_step.argtypes = [P(Params), P(C.c_double), P(C.c_double)]
@@ -147,6 +148,8 @@ def load(rebuild: bool = False):
                                     P(C.c_double), P(C.c_double)]
         lib.ref_mlp_nll.restype = C.c_double
         lib.ref_mlp_backward.argtypes = [P(Mlp), C.c_int, P(C.c_double), P(C.c_double)] + [P(C.c_double)] * 6
+        lib.ref_mlp_forward_ex.argtypes = [P(Mlp), C.c_int] + [P(C.c_double)] * 8
+        lib.ref_mlp_backward_ex.argtypes = [P(Mlp), C.c_int] + [P(C.c_double)] * 14
         _lib = lib
     return _lib
 
@@ -197,6 +200,16 @@ class Oracle:
         o = (C.c_float * 2)()
         self.lib.ref_gauss_pair(r_even & 0xffffffff, r_odd & 0xffffffff, o)
         return np.float32(o[0]), np.float32(o[1])
+
+    def gauss_pairs(self, r_even, r_odd):
+        """The transform on arrays of word pairs; returns [n, 2] float32."""
+        re = np.ascontiguousarray(r_even, np.uint32)
+        ro = np.ascontiguousarray(r_odd, np.uint32)
+        out = np.zeros((re.size, 2), np.float32)
+        P = C.POINTER(C.c_uint32)
+        self.lib.ref_gauss_pairs(int(re.size), re.ctypes.data_as(P), ro.ctypes.data_as(P),
+                                 out.ctypes.data_as(C.POINTER(C.c_float)))
+        return out
 
     def noise(self, seed, plan_step, agent, phase, k, N=None):
         N = self.N if N is None else N
@@ -382,12 +395,14 @@ class Oracle:
 class MlpOracle:
     """Float64 MLP with the planner's output parameterisation; weights W[l] are [fan_in][fan_out]."""
 
-    def __init__(self, W1, b1, W2, b2, W3, b3):
+    def __init__(self, W1, b1, W2, b2, W3, b3, bf16=False):
+        """bf16: round every matrix-product operand to bfloat16 (the network's specified
+        operand precision) and accumulate in float64."""
         self.lib = load()
         self.arrs = [np.ascontiguousarray(a, np.float64) for a in (W1, b1, W2, b2, W3, b3)]
         self.d_in, self.d_h = self.arrs[0].shape
         self.d_out = self.arrs[4].shape[1]
-        self.M = Mlp(self.d_in, self.d_h, self.d_out, 0, *[_dp(a) for a in self.arrs])
+        self.M = Mlp(self.d_in, self.d_h, self.d_out, 1 if bf16 else 0, *[_dp(a) for a in self.arrs])
 
     def forward(self, X, intermediates=False):
         X = np.ascontiguousarray(X, np.float64)
@@ -399,6 +414,27 @@ class MlpOracle:
             return out, inter
         self.lib.ref_mlp_forward(C.byref(self.M), B, _dp(X), _dp(out), None, None, None, None)
         return out
+
+    def lockstep(self, X, h1=None, h2=None, d_out=None, d2=None, d1=None):
+        """Forward (and, given d_out, backward) continuing from another implementation's
+        hidden activations h1, h2 and pre-activation gradients d2, d1 wherever given.
+        Returns dict: out, pre1, h1, pre2, h2 and, with d_out, d2_pre, d1_pre (before
+        rounding) and grads [W1, b1, W2, b2, W3, b3]."""
+        X = np.ascontiguousarray(X, np.float64)
+        B = X.shape[0]
+        keep = [None if a is None else np.ascontiguousarray(a, np.float64) for a in (h1, h2, d_out, d2, d1)]
+        h1p, h2p, dop, d2p, d1p = [None if a is None else _dp(a) for a in keep]
+        res = {k: np.zeros((B, self.d_h)) for k in ("pre1", "h1", "pre2", "h2")}
+        res["out"] = np.zeros((B, self.d_out))
+        self.lib.ref_mlp_forward_ex(C.byref(self.M), B, _dp(X), h1p, h2p, _dp(res["out"]), _dp(res["pre1"]),
+                                    _dp(res["h1"]), _dp(res["pre2"]), _dp(res["h2"]))
+        if d_out is not None:
+            res["d2_pre"], res["d1_pre"] = np.zeros((B, self.d_h)), np.zeros((B, self.d_h))
+            grads = [np.zeros_like(a) for a in self.arrs]
+            self.lib.ref_mlp_backward_ex(C.byref(self.M), B, _dp(X), h1p, h2p, dop, d2p, d1p, _dp(res["d2_pre"]),
+                                         _dp(res["d1_pre"]), *[_dp(g) for g in grads])
+            res["grads"] = grads
+        return res
 
     def nll(self, out, U, sig_a, sig_d, grad=True):
         out = np.ascontiguousarray(out, np.float64)

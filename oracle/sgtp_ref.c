@@ -238,6 +238,12 @@ void ref_gauss_pair(uint32_t r_even, uint32_t r_odd, float out[2])
     out[1] = REF_F(rho * sin_t);
 }
 
+/* The transform on n given word pairs: out[2 i], out[2 i + 1]. */
+void ref_gauss_pairs(int n, const uint32_t *r_even, const uint32_t *r_odd, float *out)
+{
+    for (int i = 0; i < n; ++i) ref_gauss_pair(r_even[i], r_odd[i], out + 2 * (size_t)i);
+}
+
 /* Perturbations of sample k, steps 0..N-1, as float32 [N][2]. */
 void ref_noise_seq(unsigned long long seed, unsigned int plan_step, int agent, int phase, int k, int N,
                    float *z)
@@ -1167,10 +1173,27 @@ int ref_features(const ref_track *T, const ref_params *p, const ref_race *R, dou
 #define MLP_LS_MIN (-4.0)
 #define MLP_LS_MAX 1.0
 
+/* bf16 != 0: every matrix-product operand (inputs, weights, hidden activations, and in
+ * the backward pass the output gradient and both hidden-layer gradients) is rounded to
+ * bfloat16 first, as the learned-proposal workload specifies (BF16 operands, FP32
+ * accumulation; a product of two bfloat16 values is exact in float32, so only the
+ * accumulation order and its rounding remain between this and an FP32 accumulator). */
 typedef struct {
-    int d_in, d_h, d_out, pad0;
+    int d_in, d_h, d_out, bf16;
     const double *W1, *b1, *W2, *b2, *W3, *b3;
 } ref_mlp;
+
+/* Round to float32 (nearest), then to bfloat16 (nearest, ties to even). */
+static double to_bf16(double x)
+{
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) != 0x7f800000u) u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+static double q_op(const ref_mlp *M, double x) { return M->bf16 ? to_bf16(x) : x; }
 
 static double gelu(double x)
 {
@@ -1185,9 +1208,13 @@ static double gelu_grad(double x)
     return 0.5 * (1.0 + t) + 0.5 * x * (1.0 - t * t) * c * (1.0 + 3.0 * 0.044715 * x * x);
 }
 
-/* Forward of B rows; optional intermediates: pre1/h1/pre2/h2 [B][d_h]. */
-void ref_mlp_forward(const ref_mlp *M, int B, const double *X, double *out, double *pre1, double *h1, double *pre2,
-                     double *h2)
+/* Forward of B rows; optional intermediates: pre1/h1/pre2/h2 [B][d_h].  h1_in / h2_in
+ * (optional, [B][d_h]): hidden activations to continue from in place of the network's
+ * own roundings of GELU(pre1) / GELU(pre2) (a lockstep comparison adopts another
+ * implementation's rounding decisions after checking them); pre1 / pre2 are computed
+ * from the layer inputs either way. */
+void ref_mlp_forward_ex(const ref_mlp *M, int B, const double *X, const double *h1_in, const double *h2_in,
+                        double *out, double *pre1, double *h1, double *pre2, double *h2)
 {
     const int di = M->d_in, dh = M->d_h, dn = M->d_out;
     double *a1 = (double *)malloc(sizeof(double) * dh), *z1 = (double *)malloc(sizeof(double) * dh);
@@ -1196,19 +1223,19 @@ void ref_mlp_forward(const ref_mlp *M, int B, const double *X, double *out, doub
         const double *x = X + (size_t)b * di;
         for (int j = 0; j < dh; ++j) {
             double acc = M->b1[j];
-            for (int k = 0; k < di; ++k) acc += x[k] * M->W1[(size_t)k * dh + j];
+            for (int k = 0; k < di; ++k) acc += q_op(M, x[k]) * q_op(M, M->W1[(size_t)k * dh + j]);
             z1[j] = acc;
-            a1[j] = gelu(acc);
+            a1[j] = h1_in ? h1_in[(size_t)b * dh + j] : q_op(M, gelu(acc));
         }
         for (int j = 0; j < dh; ++j) {
             double acc = M->b2[j];
-            for (int k = 0; k < dh; ++k) acc += a1[k] * M->W2[(size_t)k * dh + j];
+            for (int k = 0; k < dh; ++k) acc += a1[k] * q_op(M, M->W2[(size_t)k * dh + j]);
             z2[j] = acc;
-            a2[j] = gelu(acc);
+            a2[j] = h2_in ? h2_in[(size_t)b * dh + j] : q_op(M, gelu(acc));
         }
         for (int j = 0; j < dn; ++j) {
             double acc = M->b3[j];
-            for (int k = 0; k < dh; ++k) acc += a2[k] * M->W3[(size_t)k * dn + j];
+            for (int k = 0; k < dh; ++k) acc += a2[k] * q_op(M, M->W3[(size_t)k * dn + j]);
             out[(size_t)b * dn + j] = acc;
         }
         if (pre1) memcpy(pre1 + (size_t)b * dh, z1, sizeof(double) * dh);
@@ -1217,6 +1244,12 @@ void ref_mlp_forward(const ref_mlp *M, int B, const double *X, double *out, doub
         if (h2) memcpy(h2 + (size_t)b * dh, a2, sizeof(double) * dh);
     }
     free(a1); free(z1); free(a2); free(z2);
+}
+
+void ref_mlp_forward(const ref_mlp *M, int B, const double *X, double *out, double *pre1, double *h1, double *pre2,
+                     double *h2)
+{
+    ref_mlp_forward_ex(M, B, X, NULL, NULL, out, pre1, h1, pre2, h2);
 }
 
 /* Proposal of one row of network outputs (N steps): (mu_a, mu_d, sigma_a, sigma_d).
@@ -1265,21 +1298,28 @@ double ref_mlp_nll(const double *out, int B, int N, int d_out, double sig_a, dou
     return L / B;
 }
 
-/* Back-propagation of d_out through the MLP: gradients of W1..b3 (same layouts). */
-void ref_mlp_backward(const ref_mlp *M, int B, const double *X, const double *d_out, double *gW1, double *gb1,
-                      double *gW2, double *gb2, double *gW3, double *gb3)
+/* Back-propagation of d_out through the MLP: gradients of W1..b3 (same layouts).
+ * Optional lockstep inputs ([B][d_h]): h1_in / h2_in as in ref_mlp_forward_ex, and d2_in /
+ * d1_in in place of the network's own roundings of the pre-activation gradients of layers
+ * 2 and 1; d2_pre / d1_pre (optional outputs, [B][d_h]) receive those gradients before
+ * rounding. */
+void ref_mlp_backward_ex(const ref_mlp *M, int B, const double *X, const double *h1_in, const double *h2_in,
+                         const double *d_out, const double *d2_in, const double *d1_in, double *d2_pre,
+                         double *d1_pre, double *gW1, double *gb1, double *gW2, double *gb2, double *gW3,
+                         double *gb3)
 {
     const int di = M->d_in, dh = M->d_h, dn = M->d_out;
     double *pre1 = (double *)malloc(sizeof(double) * (size_t)B * dh), *h1 = (double *)malloc(sizeof(double) * (size_t)B * dh);
     double *pre2 = (double *)malloc(sizeof(double) * (size_t)B * dh), *h2 = (double *)malloc(sizeof(double) * (size_t)B * dh);
     double *out = (double *)malloc(sizeof(double) * (size_t)B * dn);
     double *d2 = (double *)malloc(sizeof(double) * dh), *d1 = (double *)malloc(sizeof(double) * dh);
-    ref_mlp_forward(M, B, X, out, pre1, h1, pre2, h2);
+    ref_mlp_forward_ex(M, B, X, h1_in, h2_in, out, pre1, h1, pre2, h2);
     memset(gW1, 0, sizeof(double) * di * dh); memset(gb1, 0, sizeof(double) * dh);
     memset(gW2, 0, sizeof(double) * dh * dh); memset(gb2, 0, sizeof(double) * dh);
     memset(gW3, 0, sizeof(double) * dh * dn); memset(gb3, 0, sizeof(double) * dn);
+    double *g = (double *)malloc(sizeof(double) * dn);
     for (int b = 0; b < B; ++b) {
-        const double *g = d_out + (size_t)b * dn;
+        for (int j = 0; j < dn; ++j) g[j] = q_op(M, d_out[(size_t)b * dn + j]);
         const double *a2 = h2 + (size_t)b * dh, *a1 = h1 + (size_t)b * dh, *x = X + (size_t)b * di;
         for (int j = 0; j < dn; ++j) {
             gb3[j] += g[j];
@@ -1287,8 +1327,10 @@ void ref_mlp_backward(const ref_mlp *M, int B, const double *X, const double *d_
         }
         for (int k = 0; k < dh; ++k) {
             double acc = 0.0;
-            for (int j = 0; j < dn; ++j) acc += M->W3[(size_t)k * dn + j] * g[j];
-            d2[k] = acc * gelu_grad(pre2[(size_t)b * dh + k]);
+            for (int j = 0; j < dn; ++j) acc += q_op(M, M->W3[(size_t)k * dn + j]) * g[j];
+            const double v = acc * gelu_grad(pre2[(size_t)b * dh + k]);
+            if (d2_pre) d2_pre[(size_t)b * dh + k] = v;
+            d2[k] = d2_in ? d2_in[(size_t)b * dh + k] : q_op(M, v);
         }
         for (int j = 0; j < dh; ++j) {
             gb2[j] += d2[j];
@@ -1296,15 +1338,24 @@ void ref_mlp_backward(const ref_mlp *M, int B, const double *X, const double *d_
         }
         for (int k = 0; k < dh; ++k) {
             double acc = 0.0;
-            for (int j = 0; j < dh; ++j) acc += M->W2[(size_t)k * dh + j] * d2[j];
-            d1[k] = acc * gelu_grad(pre1[(size_t)b * dh + k]);
+            for (int j = 0; j < dh; ++j) acc += q_op(M, M->W2[(size_t)k * dh + j]) * d2[j];
+            const double v = acc * gelu_grad(pre1[(size_t)b * dh + k]);
+            if (d1_pre) d1_pre[(size_t)b * dh + k] = v;
+            d1[k] = d1_in ? d1_in[(size_t)b * dh + k] : q_op(M, v);
         }
         for (int j = 0; j < dh; ++j) {
             gb1[j] += d1[j];
-            for (int k = 0; k < di; ++k) gW1[(size_t)k * dh + j] += x[k] * d1[j];
+            for (int k = 0; k < di; ++k) gW1[(size_t)k * dh + j] += q_op(M, x[k]) * d1[j];
         }
     }
+    free(g);
     free(pre1); free(h1); free(pre2); free(h2); free(out); free(d2); free(d1);
+}
+
+void ref_mlp_backward(const ref_mlp *M, int B, const double *X, const double *d_out, double *gW1, double *gb1,
+                      double *gW2, double *gb2, double *gW3, double *gb3)
+{
+    ref_mlp_backward_ex(M, B, X, NULL, NULL, d_out, NULL, NULL, NULL, NULL, gW1, gb1, gW2, gb2, gW3, gb3);
 }
 
 int ref_abi_version(void) { return 2; }

@@ -9,7 +9,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRCS = [os.path.join(PKG, "csrc", f) for f in ("sgtp.hip", "mlp.hip")]
+SRCS = [os.path.join(PKG, "csrc", f) for f in ("sgtp.hip", "mlp.hip", "probe.hip")]
 LIB = os.path.join(PKG, "libsgtp.so")
 ARCH = os.environ.get("SGTP_OFFLOAD_ARCH", "gfx950")
 

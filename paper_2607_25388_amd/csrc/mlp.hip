@@ -282,6 +282,12 @@ __global__ void k_colsum(const bf16 *D, int B, int ld, int ncols, float *dst) {
     atomicAdd(&dst[c], s);
 }
 
+// zero n floats (a kernel, not a memset node, so the gradient step can be captured and replayed)
+__global__ void k_zero(float *p, int n) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) p[e] = 0.0f;
+}
+
 // copy a [rows][cols] block of a float32 matrix with row stride lds into packed storage
 __global__ void k_pack(const float *S, int rows, int cols, int lds, float *dst) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -311,9 +317,10 @@ struct sgtp_mlp {
     bf16 *W1 = nullptr, *W2 = nullptr, *W3 = nullptr;              // BF16 operands
     bf16 *W1T = nullptr, *W2T = nullptr, *W3T = nullptr;           // transposed (fused forward)
     float *b3p = nullptr;
-    bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *D = nullptr, *D1 = nullptr;
+    bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *D = nullptr, *D2 = nullptr, *D1 = nullptr;
     float *PRE1 = nullptr, *PRE2 = nullptr, *OUT = nullptr, *DH = nullptr, *GW = nullptr, *loss = nullptr;
     int adam_t = 0;
+    int last_B = 0;  // rows of the last sgtp_mlp_grad (its workspace tensors stay until the next call)
 };
 
 namespace {
@@ -379,6 +386,7 @@ int sgtp_mlp_create(int B_max, sgtp_mlp **out) {
     al((void **)&m->H1, (size_t)B_max * D_H * 2);
     al((void **)&m->H2, (size_t)B_max * D_H * 2);
     al((void **)&m->D, (size_t)B_max * D_OUTP * 2);
+    al((void **)&m->D2, (size_t)B_max * D_H * 2);
     al((void **)&m->D1, (size_t)B_max * D_H * 2);
     al((void **)&m->PRE1, (size_t)B_max * D_H * 4);
     al((void **)&m->PRE2, (size_t)B_max * D_H * 4);
@@ -398,7 +406,8 @@ int sgtp_mlp_destroy(sgtp_mlp *m) {
     if (!m) return SGTP_EINVAL;
     (void)hipDeviceSynchronize();
     void *bufs[] = {m->P,  m->G,  m->Mm, m->Vv,   m->W1,   m->W2,  m->W3, m->b3p, m->X,    m->H1,   m->H2,
-                    m->D,  m->D1, m->PRE1, m->PRE2, m->OUT, m->DH, m->GW,  m->loss, m->W1T, m->W2T, m->W3T};
+                    m->D,  m->D1, m->PRE1, m->PRE2, m->OUT, m->DH, m->GW,  m->loss, m->W1T, m->W2T, m->W3T,
+                    m->D2};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete m;
@@ -456,9 +465,9 @@ int sgtp_mlp_grad(sgtp_mlp *m, const float *X, const float *U, int B, int N, flo
     hipStream_t st = (hipStream_t)stream;
     int rc = forward(m, X, D_IN, B, m->OUT, D_OUTP, D_OUTP, st);
     if (rc) return rc;
-    MCHK(m, hipMemsetAsync(m->loss, 0, 4, st));
-    MCHK(m, hipMemsetAsync(m->G, 0, P_TOTAL * 4, st));
-    MCHK(m, hipMemsetAsync(m->GW, 0, (size_t)D_H * D_OUTP * 4, st));
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, m->loss, 1);
+    hipLaunchKernelGGL(k_zero, dim3((P_TOTAL + 255) / 256), dim3(256), 0, st, m->G, (int)P_TOTAL);
+    hipLaunchKernelGGL(k_zero, dim3((D_H * D_OUTP + 255) / 256), dim3(256), 0, st, m->GW, D_H * D_OUTP);
     const int sp = k_splits(B), rb = (B + 255) / 256;
     hipLaunchKernelGGL(k_nll, dim3((B * 128 + 255) / 256), dim3(256), 0, st, m->OUT, D_OUTP, U, B, N, sig_a, sig_d,
                        m->D, D_OUTP, m->loss);
@@ -467,18 +476,37 @@ int sgtp_mlp_grad(sgtp_mlp *m, const float *X, const float *U, int B, int N, flo
     hipLaunchKernelGGL(k_pack, dim3((D_H * D_OUT + 255) / 256), dim3(256), 0, st, m->GW, D_H, D_OUT, D_OUTP, m->G + P_W3);
     hipLaunchKernelGGL(k_colsum, dim3(1, rb), dim3(256), 0, st, m->D, B, D_OUTP, D_OUT, m->G + P_B3);
     gemm(st, m->D, D_OUTP, 1, m->W3, 1, D_OUTP, B, D_H, D_OUTP, nullptr, m->DH, D_H, nullptr, 0);
-    hipLaunchKernelGGL(k_gelu_back, dim3((B * D_H + 255) / 256), dim3(256), 0, st, m->DH, m->PRE2, B * D_H, m->D1);
-    // layer 2: gW2 = H1^T D1, gb2, dH1 = D1 W2^T
-    gemm(st, m->H1, 1, D_H, m->D1, D_H, 1, D_H, D_H, B, nullptr, m->G + P_W2, D_H, nullptr, 0, sp);
-    hipLaunchKernelGGL(k_colsum, dim3(1, rb), dim3(256), 0, st, m->D1, B, D_H, D_H, m->G + P_B2);
-    gemm(st, m->D1, D_H, 1, m->W2, 1, D_H, B, D_H, D_H, nullptr, m->DH, D_H, nullptr, 0);
+    hipLaunchKernelGGL(k_gelu_back, dim3((B * D_H + 255) / 256), dim3(256), 0, st, m->DH, m->PRE2, B * D_H, m->D2);
+    // layer 2: gW2 = H1^T D2, gb2, dH1 = D2 W2^T
+    gemm(st, m->H1, 1, D_H, m->D2, D_H, 1, D_H, D_H, B, nullptr, m->G + P_W2, D_H, nullptr, 0, sp);
+    hipLaunchKernelGGL(k_colsum, dim3(1, rb), dim3(256), 0, st, m->D2, B, D_H, D_H, m->G + P_B2);
+    gemm(st, m->D2, D_H, 1, m->W2, 1, D_H, B, D_H, D_H, nullptr, m->DH, D_H, nullptr, 0);
     hipLaunchKernelGGL(k_gelu_back, dim3((B * D_H + 255) / 256), dim3(256), 0, st, m->DH, m->PRE1, B * D_H, m->D1);
     // layer 1: gW1 = X^T D1, gb1
     gemm(st, m->X, 1, D_INP, m->D1, D_H, 1, D_IN, D_H, B, nullptr, m->G + P_W1, D_H, nullptr, 0, sp);
     hipLaunchKernelGGL(k_colsum, dim3(1, rb), dim3(256), 0, st, m->D1, B, D_H, D_H, m->G + P_B1);
     MCHK(m, hipGetLastError());
+    m->last_B = B;
     if (loss) MCHK(m, hipMemcpyAsync(loss, m->loss, 4, hipMemcpyDeviceToDevice, st));
     if (grads) MCHK(m, hipMemcpyAsync(grads, m->G, P_TOTAL * 4, hipMemcpyDeviceToDevice, st));
+    return SGTP_OK;
+}
+
+int sgtp_mlp_workspace(sgtp_mlp *m, int which, void *dst, void *stream) {
+    if (!m || !dst) return SGTP_EINVAL;
+    if (m->last_B < 1) return mfail(m, SGTP_EINVAL, "no gradient computed yet");
+    const void *src = nullptr;
+    size_t row = 0;
+    switch (which) {
+        case SGTP_MLP_WS_H1: src = m->H1; row = D_H * 2; break;
+        case SGTP_MLP_WS_H2: src = m->H2; row = D_H * 2; break;
+        case SGTP_MLP_WS_OUT: src = m->OUT; row = D_OUTP * 4; break;
+        case SGTP_MLP_WS_D3: src = m->D; row = D_OUTP * 2; break;
+        case SGTP_MLP_WS_D2: src = m->D2; row = D_H * 2; break;
+        case SGTP_MLP_WS_D1: src = m->D1; row = D_H * 2; break;
+        default: return mfail(m, SGTP_EINVAL, "unknown workspace tensor");
+    }
+    MCHK(m, hipMemcpyAsync(dst, src, row * m->last_B, hipMemcpyDeviceToDevice, (hipStream_t)stream));
     return SGTP_OK;
 }
 

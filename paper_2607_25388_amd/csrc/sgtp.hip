@@ -70,7 +70,9 @@ enum Mode { SWEEP = 0, WINNER = 1, NOMINAL = 2 };
 struct KParams {
     // read in the sample loop (kept together: their scalar loads and registers stay compact)
     float dt, half_dt, dt6;
-    float lf, lr, inv_m, inv_Iz, muFzf, muFzr, B, C, v_eps, C_rev;  // dynamic single-track
+    // dynamic single-track: the axles' peak forces mu F_z enter the rates only through
+    // kf_m = mu F_zf / m, kf_Iz = mu F_zf l_f / I_z, kr_m = mu F_zr / m, kr_Iz = mu F_zr l_r / I_z
+    float lf, lr, kf_m, kf_Iz, kr_m, kr_Iz, B, C, v_eps, C_rev;
     float lr_over_L, inv_lr;                                 // kinematic bicycle
     float a_min, a_max, d_min, d_max, sigma_a, sigma_d;
     float Q0, Q1, Q2, Q3, R0, R1, S0, S1;
@@ -188,6 +190,25 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
     return c;
 }
 
+// IEEE division and square root for the operand ranges of the transform below (normal,
+// finite, no zero divisor, square roots of positive normal values only): the hardware
+// estimate refined by the same fused steps as the general correctly rounded sequences,
+// without their scaling and special-value steps, which never act in these ranges -- the
+// results are the IEEE ones bit for bit.
+__device__ __forceinline__ float div_rn_normal(float n, float d) {
+    float r = __builtin_amdgcn_rcpf(d);
+    r = __builtin_fmaf(__builtin_fmaf(-d, r, 1.0f), r, r);
+    float q = n * r;
+    q = __builtin_fmaf(__builtin_fmaf(-d, q, n), r, q);
+    return __builtin_fmaf(__builtin_fmaf(-d, q, n), r, q);
+}
+__device__ __forceinline__ float sqrt_rn_normal(float x) {
+    const float s = __builtin_amdgcn_sqrtf(x);  // within 1 ulp
+    const float s_dn = __uint_as_float(__float_as_uint(s) - 1u), s_up = __uint_as_float(__float_as_uint(s) + 1u);
+    float r = __builtin_fmaf(-s_dn, s, x) <= 0.0f ? s_dn : s;
+    return __builtin_fmaf(-s_up, s, x) > 0.0f ? s_up : r;
+}
+
 // Gaussian pair from two 32-bit words.  The float32 operation sequence is fixed
 // (IEEE round-to-nearest add, mul, fma, div, sqrt; no contraction), so the
 // perturbations are reproducible bit for bit on any IEEE-conforming device.
@@ -195,22 +216,22 @@ __device__ __forceinline__ float2 gauss_pair(uint32_t r_even, uint32_t r_odd) {
 #pragma clang fp contract(off)
     const float L3 = 0x1.555556p-1f, L5 = 0x1.99999ap-2f, L7 = 0x1.24924ap-2f;
     const float L9 = 0x1.c71c72p-3f, L11 = 0x1.745d18p-3f, L13 = 0x1.3b13b2p-3f;
-    const float LN2_HI = 0x1.62e4p-1f, LN2_LO = 0x1.7f7d1cp-20f, SQRT2 = 0x1.6a09e6p+0f;
+    const float LN2_HI = 0x1.62e4p-1f, LN2_LO = 0x1.7f7d1cp-20f;
     const float S1 = 0x1.921fb6p+2f, S3 = -0x1.4abbcep+5f, S5 = 0x1.466bc6p+6f;
     const float S7 = -0x1.32d2ccp+6f, S9 = 0x1.507834p+5f;
     const float C2 = -0x1.3bd3ccp+4f, C4 = 0x1.03c1f0p+6f, C6 = -0x1.55d3c8p+6f;
     const float C8 = 0x1.e1f506p+5f, C10 = -0x1.a6d1f2p+4f;
     // radius sqrt(-2 ln u1), u1 = (2*(r_even >> 9) + 1) 2^-24, ln by exponent split + atanh series
     const float u1 = (float)(2u * (r_even >> 9) + 1u) * 0x1p-24f;
-    const uint32_t b = __float_as_uint(u1);
-    int e = (int)((b >> 23) & 0xffu) - 127;
-    float m = __uint_as_float((b & 0x7fffffu) | 0x3f800000u);
-    if (m > SQRT2) {
-        m = m * 0.5f;
-        e = e + 1;
-    }
+    // u1 = m 2^e with m in [sqrt(1/2), sqrt 2]: m > SQRT2 (the float just below sqrt 2) is
+    // halved.  In integer form: adding 2^23 - 0x3504f4 to the bits carries into the
+    // exponent exactly when the mantissa field exceeds that of SQRT2, and the mantissa of
+    // m is then the low 23 bits plus the bits of the float above sqrt(1/2).
+    const uint32_t b = __float_as_uint(u1) + 0x4afb0cu;
+    const int e = (int)(b >> 23) - 127;
+    const float m = __uint_as_float((b & 0x7fffffu) + 0x3f3504f4u);
     const float f = m - 1.0f;
-    const float z = f / (m + 1.0f);
+    const float z = div_rn_normal(f, m + 1.0f);  // f in [-0.293, 0.415], m + 1 in [1.707, 2.415]
     const float w = z * z;
     float p = __builtin_fmaf(L13, w, L11);
     p = __builtin_fmaf(p, w, L9);
@@ -221,7 +242,7 @@ __device__ __forceinline__ float2 gauss_pair(uint32_t r_even, uint32_t r_odd) {
     const float lnm = __builtin_fmaf(z, p, z + z);
     const float ef = (float)e;
     const float lnu = __builtin_fmaf(ef, LN2_HI, __builtin_fmaf(ef, LN2_LO, lnm));
-    const float rho = __builtin_sqrtf(-2.0f * lnu);
+    const float rho = sqrt_rn_normal(-2.0f * lnu);  // -2 ln u1 in [1.1e-7, 33.3]
     // angle 2 pi u2, u2 = (r_odd >> 8) 2^-24: exact quarter-turn split, Taylor polynomials
     const uint32_t j = r_odd >> 8;
     const uint32_t q = (j + (1u << 21)) >> 22;
@@ -253,7 +274,9 @@ __device__ __forceinline__ float2 gauss_pair(uint32_t r_even, uint32_t r_odd) {
 // ------------------------------------------------------------------------------
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// atan: odd polynomial fitted on [0, 1] (max error 3.3e-7), reflected via pi/2 - atan(1/x).
+// atan: odd polynomial of degree 13 on [0, 1], reflected via pi/2 - atan(1/x).  Its
+// coefficients are a minimax (equal-ripple) fit of the absolute error on [0, 1], rounded to
+// float32: 2.55e-7 in exact arithmetic, 3.1e-7 evaluated in float32 (4e-7 with the reflection).
 // (A 6-term fit with 1.8e-6 error moved chaotic sliding samples past the 1e-3 state tolerance.)
 __device__ __forceinline__ float atan_poly(float t, float t2) {
     float p = 0x1.be6b36p-8f;
@@ -295,6 +318,7 @@ struct MathF32 {
     static __device__ __forceinline__ T to_rev(T x) { return x * 0.159154943f; }
     static __device__ __forceinline__ T sin_rev(T x) { return __builtin_amdgcn_sinf(x); }
     static __device__ __forceinline__ T cos_rev(T x) { return __builtin_amdgcn_cosf(x); }
+    static __device__ __forceinline__ T fma_(T a, T b, T c) { return __builtin_fmaf(a, b, c); }
     // max(x, 0) as one median (0 for a NaN, like x > 0 ? x : 0; +inf becomes the largest
     // finite value, which only a state that is already non-finite reaches)
     static __device__ __forceinline__ T pos_(T x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 3.40282347e38f); }
@@ -316,21 +340,23 @@ struct MathF64 {
     static __device__ __forceinline__ T to_rev(T x) { return x; }
     static __device__ __forceinline__ T sin_rev(T x) { return ::sin(x); }
     static __device__ __forceinline__ T cos_rev(T x) { return ::cos(x); }
+    static __device__ __forceinline__ T fma_(T a, T b, T c) { return ::fma(a, b, c); }
     static __device__ __forceinline__ T pos_(T x) { return x > 0.0 ? x : 0.0; }
     static __device__ __forceinline__ T floor_(T x, T lo) { return x > lo ? x : lo; }
 };
 
 template <typename T>
 struct VehConst {
-    T lf, lr, inv_m, inv_Iz, muFzf, muFzr, B, C, v_eps, lr_over_L, inv_lr;
+    T lf, lr, kf_m, kf_Iz, kr_m, kr_Iz, B, C, v_eps, lr_over_L, inv_lr;
     T Cs;  // C scaled to the angle unit of M::sin_rev
 };
 
 // Per control interval: functions of the held control (a, delta).
 template <typename T>
 struct StepConst {
-    T a, delta, sd, cd;  // dynamic: delta, sin delta, cos delta
-    T kc, ks, kw;        // kinematic: cos beta, sin beta, sin(beta)/l_r
+    T a, delta;
+    T kf3, kf4, kf5;  // dynamic: kf_m sin delta, kf_m cos delta, kf_Iz cos delta
+    T kc, ks, kw;     // kinematic: cos beta, sin beta, sin(beta)/l_r
 };
 
 template <int MODEL, class M>
@@ -341,46 +367,52 @@ __device__ __forceinline__ StepConst<typename M::T> step_const(const VehConst<ty
     c.a = a;
     c.delta = delta;
     if (MODEL == 0) {
-        c.sd = M::sin_(delta);
-        c.cd = M::cos_(delta);
+        const T sd = M::sin_(delta), cd = M::cos_(delta);
+        c.kf3 = V.kf_m * sd;
+        c.kf4 = V.kf_m * cd;
+        c.kf5 = V.kf_Iz * cd;
         c.kc = c.ks = c.kw = T(0);
     } else {
         const T beta = M::atan_(V.lr_over_L * (M::sin_(delta) * M::rcp_(M::cos_(delta))));
         c.kc = M::cos_(beta);
         c.ks = M::sin_(beta);
         c.kw = c.ks * V.inv_lr;
-        c.sd = c.cd = T(0);
+        c.kf3 = c.kf4 = c.kf5 = T(0);
     }
     return c;
 }
 
-// Lateral force of one axle: slip angle alpha = delta_axle - atan((v_y + l om) / v_hat)
-// (l = l_f for the front axle, -l_r for the rear one, whose steering angle is 0) and
-// F_y = mu F_z sin(C atan(B alpha)).  Both axles go through this one expression, so the
-// two-lane evaluation below gives the same bits as the one-lane one.
+// Lateral force of one axle over its peak mu F_z: slip angle alpha = delta_axle -
+// atan((v_y + l om) / v_hat) (l = l_f for the front axle, -l_r for the rear one, whose
+// steering angle is 0) and F_y / (mu F_z) = sin(C atan(B alpha)).  Both axles go through
+// this one expression, so the two-lane evaluation below gives the same bits as the
+// one-lane one.
 template <class M>
 __device__ __forceinline__ typename M::T tyre_force(const VehConst<typename M::T> &V, typename M::T l,
-                                                     typename M::T delta_axle, typename M::T muFz, typename M::T vy,
-                                                     typename M::T om, typename M::T inv_vh) {
+                                                     typename M::T delta_axle, typename M::T vy, typename M::T om,
+                                                     typename M::T inv_vh) {
     using T = typename M::T;
     const T alpha = delta_axle - M::atan_((vy + l * om) * inv_vh);
-    return muFz * M::sin_rev(V.Cs * M::atan_(V.B * alpha));
+    return M::sin_rev(V.Cs * M::atan_(V.B * alpha));
 }
 
 // Vehicle model f (Sec. II).  MODEL 0: dynamic single-track with
 // F_y = mu F_z sin(C atan(B alpha)); MODEL 1: kinematic bicycle at the CoG.
 // Position rates use max(v_x, 0), so no stage of RK4 moves the car backwards.
+// Sf, Sr: the axles' forces over their peaks (tyre_force); v_x' = a - F_yf sin(delta) / m
+// + v_y om, v_y' = (F_yr + F_yf cos(delta)) / m - v_x om, om' = (l_f F_yf cos(delta) -
+// l_r F_yr) / I_z with the force scales folded into kf3..kf5, kr_m and kr_Iz.
 template <class M>
 __device__ __forceinline__ void deriv_rates(const VehConst<typename M::T> &V, const StepConst<typename M::T> &c,
                                             typename M::T vx, typename M::T vy, typename M::T om, typename M::T cp,
-                                            typename M::T sp, typename M::T Fyf, typename M::T Fyr,
+                                            typename M::T sp, typename M::T Sf, typename M::T Sr,
                                             typename M::T d[6]) {
     d[0] = vx * cp - vy * sp;
     d[1] = vx * sp + vy * cp;
     d[2] = om;
-    d[3] = c.a - Fyf * c.sd * V.inv_m + vy * om;
-    d[4] = (Fyr + Fyf * c.cd) * V.inv_m - vx * om;
-    d[5] = (V.lf * Fyf * c.cd - V.lr * Fyr) * V.inv_Iz;
+    d[3] = M::fma_(vy, om, M::fma_(-Sf, c.kf3, c.a));
+    d[4] = M::fma_(Sf, c.kf4, M::fma_(Sr, V.kr_m, -(vx * om)));
+    d[5] = M::fma_(Sf, c.kf5, -(Sr * V.kr_Iz));
 }
 
 template <int MODEL, class M>
@@ -393,8 +425,8 @@ __device__ __forceinline__ void deriv(const VehConst<typename M::T> &V, const St
     const T cp = M::cos_rev(pr), sp = M::sin_rev(pr);
     if (MODEL == 0) {
         const T inv_vh = M::rcp_(M::floor_(vx, V.v_eps));
-        const T Fyf = tyre_force<M>(V, V.lf, c.delta, V.muFzf, vy, om, inv_vh);
-        const T Fyr = tyre_force<M>(V, -V.lr, T(0), V.muFzr, vy, om, inv_vh);
+        const T Fyf = tyre_force<M>(V, V.lf, c.delta, vy, om, inv_vh);
+        const T Fyr = tyre_force<M>(V, -V.lr, T(0), vy, om, inv_vh);
         deriv_rates<M>(V, c, vx, vy, om, cp, sp, Fyf, Fyr, d);
     } else {
         d[0] = vx * (cp * c.kc - sp * c.ks);
@@ -420,8 +452,7 @@ __device__ __forceinline__ void deriv_pair(const VehConst<float> &V, const StepC
     const float pr = MathF32::to_rev(psi);
     const float cp = MathF32::cos_rev(pr), sp = MathF32::sin_rev(pr);
     const float inv_vh = MathF32::rcp_(MathF32::floor_(vx, V.v_eps));
-    const float F = tyre_force<MathF32>(V, rear ? -V.lr : V.lf, rear ? 0.0f : c.delta, rear ? V.muFzr : V.muFzf, vy,
-                                        om, inv_vh);
+    const float F = tyre_force<MathF32>(V, rear ? -V.lr : V.lf, rear ? 0.0f : c.delta, vy, om, inv_vh);
     const float Fo = dpp_swap_f32(F);
     deriv_rates<MathF32>(V, c, vx, vy, om, cp, sp, rear ? Fo : F, rear ? F : Fo, d);
 }
@@ -472,8 +503,8 @@ __device__ __forceinline__ T sreg(T v) {
 __device__ __forceinline__ KParams loop_params(const KParams &P_in) {
     KParams P = P_in;
     P.dt = sreg(P.dt); P.half_dt = sreg(P.half_dt); P.dt6 = sreg(P.dt6);
-    P.lf = sreg(P.lf); P.lr = sreg(P.lr); P.inv_m = sreg(P.inv_m); P.inv_Iz = sreg(P.inv_Iz);
-    P.muFzf = sreg(P.muFzf); P.muFzr = sreg(P.muFzr); P.B = sreg(P.B); P.C = sreg(P.C);
+    P.lf = sreg(P.lf); P.lr = sreg(P.lr); P.kf_m = sreg(P.kf_m); P.kf_Iz = sreg(P.kf_Iz);
+    P.kr_m = sreg(P.kr_m); P.kr_Iz = sreg(P.kr_Iz); P.B = sreg(P.B); P.C = sreg(P.C);
     P.v_eps = sreg(P.v_eps); P.C_rev = sreg(P.C_rev); P.lr_over_L = sreg(P.lr_over_L); P.inv_lr = sreg(P.inv_lr);
     P.a_min = sreg(P.a_min); P.a_max = sreg(P.a_max); P.d_min = sreg(P.d_min); P.d_max = sreg(P.d_max);
     P.sigma_a = sreg(P.sigma_a); P.sigma_d = sreg(P.sigma_d);
@@ -487,7 +518,7 @@ __device__ __forceinline__ KParams loop_params(const KParams &P_in) {
 
 __device__ __forceinline__ VehConst<float> veh_f32(const KParams &P) {
     VehConst<float> V;
-    V.lf = P.lf; V.lr = P.lr; V.inv_m = P.inv_m; V.inv_Iz = P.inv_Iz; V.muFzf = P.muFzf; V.muFzr = P.muFzr;
+    V.lf = P.lf; V.lr = P.lr; V.kf_m = P.kf_m; V.kf_Iz = P.kf_Iz; V.kr_m = P.kr_m; V.kr_Iz = P.kr_Iz;
     V.B = P.B; V.C = P.C; V.v_eps = P.v_eps; V.lr_over_L = P.lr_over_L; V.inv_lr = P.inv_lr;
     V.Cs = P.C_rev;
     return V;
@@ -542,27 +573,33 @@ __device__ __forceinline__ Foot foot_on(const float4 *__restrict__ nodes, float 
 // Segment search from `seg` (at most max_moves moves, inside the window), then the foot.
 // The search carries only the signed distances; the geometry rows of the final segment
 // are read again together with its second rows.
+// (The move budget and the window's ends are folded into one bound on the row address per
+// direction, so a move costs the row read, the normal-line test, two compares and one add.)
 __device__ __forceinline__ Foot project(const float4 *__restrict__ nodes, int W, int max_moves, float X, float Y,
                                         int seg) {
-    int moves = 0;
-    float g1 = ahead_of(nodes[2 * seg + 2], X, Y);
+    const int seg0 = seg;
+    const float4 *q = nodes + 2 * seg + 2;  // geometry row of node seg + 1
+    const float4 *const q_hi = nodes + 2 * min(seg0 + max_moves, W - 2) + 2;
+    float g1 = ahead_of(*q, X, Y);
     float g0;
     bool fwd = false;
-    while (moves < max_moves && seg + 1 <= W - 2 && g1 > 0.0f) {
-        ++seg;
-        ++moves;
+    while (q < q_hi && g1 > 0.0f) {
+        q += 2;
         g0 = g1;
-        g1 = ahead_of(nodes[2 * seg + 2], X, Y);
+        g1 = ahead_of(*q, X, Y);
         fwd = true;
     }
-    if (!fwd) g0 = ahead_of(nodes[2 * seg], X, Y);
-    while (moves < max_moves && seg > 0 && g0 < 0.0f) {
-        --seg;
-        ++moves;
+    seg = (int)(q - nodes) / 2 - 1;
+    q -= 2;  // geometry row of node seg
+    if (!fwd) g0 = ahead_of(*q, X, Y);
+    const float4 *const q_lo = nodes + 2 * max(0, seg - (max_moves - (seg - seg0)));
+    while (q > q_lo && g0 < 0.0f) {
+        q -= 2;
         g1 = g0;
-        g0 = ahead_of(nodes[2 * seg], X, Y);
+        g0 = ahead_of(*q, X, Y);
     }
-    return foot_on(nodes, X, Y, seg, nodes[2 * seg], nodes[2 * seg + 2], g0, g1);
+    seg = (int)(q - nodes) / 2;
+    return foot_on(nodes, X, Y, seg, q[0], q[2], g0, g1);
 }
 
 // The same search with the geometry rows of segments seg .. seg + NPF - 1 read ahead
@@ -2161,6 +2198,12 @@ __global__ void k_proposal(const RaceDev *races, const ItemDev *items, int n_ite
 }
 
 // Advance the Philox counter word of every race (planning-step index).
+// The Gaussian transform on given words (instrumentation: checks of the float32 spec).
+__global__ void k_gauss_pairs(const uint32_t *re, const uint32_t *ro, float2 *out, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = gauss_pair(re[i], ro[i]);
+}
+
 // Descriptor image of a one-vehicle call passed by value and written to device memory
 // (the allocation-free entry point: no host staging buffer, no copy from the host).
 constexpr int NOALLOC_MAX_ITEMS = SGTP_MAX_AGENTS;
@@ -2361,10 +2404,11 @@ KParams make_kparams(const sgtp_params *p) {
     k.skip2 = (float)(sk * sk);
     const double L = (double)p->lf + (double)p->lr;
     k.lf = p->lf; k.lr = p->lr;
-    k.inv_m = (float)(1.0 / p->m);
-    k.inv_Iz = (float)(1.0 / p->Iz);
-    k.muFzf = (float)((double)p->mu * p->m * p->g * p->lr / L);
-    k.muFzr = (float)((double)p->mu * p->m * p->g * p->lf / L);
+    const double muFzf = (double)p->mu * p->m * p->g * p->lr / L, muFzr = (double)p->mu * p->m * p->g * p->lf / L;
+    k.kf_m = (float)(muFzf / p->m);
+    k.kf_Iz = (float)(muFzf * p->lf / p->Iz);
+    k.kr_m = (float)(muFzr / p->m);
+    k.kr_Iz = (float)(muFzr * p->lr / p->Iz);
     k.B = p->B; k.C = p->C; k.v_eps = p->v_eps;
     k.C_rev = (float)((double)p->C / (2.0 * M_PI));
     k.lr_over_L = (float)(p->lr / L);
@@ -2380,9 +2424,12 @@ KParams make_kparams(const sgtp_params *p) {
 VehConst<double> make_veh64(const sgtp_params *p) {
     VehConst<double> V;
     const double L = (double)p->lf + (double)p->lr;
-    V.lf = p->lf; V.lr = p->lr; V.inv_m = 1.0 / p->m; V.inv_Iz = 1.0 / p->Iz;
-    V.muFzf = (double)p->mu * p->m * p->g * p->lr / L;
-    V.muFzr = (double)p->mu * p->m * p->g * p->lf / L;
+    V.lf = p->lf; V.lr = p->lr;
+    const double muFzf = (double)p->mu * p->m * p->g * p->lr / L, muFzr = (double)p->mu * p->m * p->g * p->lf / L;
+    V.kf_m = muFzf / p->m;
+    V.kf_Iz = muFzf * p->lf / p->Iz;
+    V.kr_m = muFzr / p->m;
+    V.kr_Iz = muFzr * p->lr / p->Iz;
     V.B = p->B; V.C = p->C; V.v_eps = p->v_eps; V.lr_over_L = p->lr / L; V.inv_lr = 1.0 / p->lr;
     V.Cs = p->C;
     return V;
@@ -3146,6 +3193,14 @@ int sgtp_rollout_cost_noalloc(sgtp_ctx *c, const sgtp_params *p, const sgtp_race
     return r.sweep(r.d_one, r.pl.one, tiles, phase, 0, out, r.pl.all[agent].slot, 0, 0, nullptr, &dbg);
 }
 
+int sgtp_gauss_pairs(const unsigned int *r_even, const unsigned int *r_odd, float *out, int n, void *stream) {
+    if (!r_even || !r_odd || !out || n < 0) return SGTP_EINVAL;
+    if (n == 0) return SGTP_OK;
+    hipLaunchKernelGGL(k_gauss_pairs, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                       (const uint32_t *)r_even, (const uint32_t *)r_odd, (float2 *)out, n);
+    return hipGetLastError() == hipSuccess ? SGTP_OK : SGTP_EDEVICE;
+}
+
 int sgtp_ibr_sweep(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int n_races, int phase, int ego_only,
                    sgtp_choice *out, void *stream) {
     if (!c) return SGTP_EINVAL;
@@ -3411,18 +3466,17 @@ int sgtp_autotune(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int
         }
     }
     hipStream_t st = (hipStream_t)stream;
-    // the search runs real planning steps: save and restore the mutable race state
-    std::vector<void *> saved;
+    // the search runs real planning steps: save and restore the mutable race state (the
+    // state is restored and the buffers freed on every exit path, failed candidates included)
     std::vector<size_t> sizes;
     for (int r = 0; r < n_races; ++r) {
         sizes.push_back((size_t)races[r].n_agents * races[r].N * 2 * sizeof(float));
         sizes.push_back((size_t)races[r].n_agents * sizeof(double));
     }
-    for (size_t i = 0; i < sizes.size(); ++i) {
-        void *b = nullptr;
-        HIPCHK(c, hipMalloc(&b, sizes[i]));
-        saved.push_back(b);
-    }
+    std::vector<void *> saved(sizes.size(), nullptr);
+    int rc = SGTP_OK;
+    for (size_t i = 0; i < sizes.size() && !rc; ++i)
+        if (hipMalloc(&saved[i], sizes[i]) != hipSuccess) rc = fail(c, SGTP_ENOMEM, "autotune: save buffers");
     auto save_restore = [&](bool save) -> int {
         for (int r = 0; r < n_races; ++r) {
             void *un = races[r].u_nom, *sa = races[r].s_abs;
@@ -3433,7 +3487,11 @@ int sgtp_autotune(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int
         }
         return SGTP_OK;
     };
-    int rc = save_restore(true);
+    bool have_saved = false;
+    if (!rc) {
+        rc = save_restore(true);
+        have_saved = rc == SGTP_OK;
+    }
     std::vector<sgtp_plan_options> cand;
     for (int spl : {1, 2}) {
         sgtp_plan_options o{};
@@ -3453,9 +3511,9 @@ int sgtp_autotune(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int
         }
     double best_t = INFINITY;
     sgtp_plan_options best_o = cand[0];
-    hipEvent_t e0, e1;
-    HIPCHK(c, hipEventCreate(&e0));
-    HIPCHK(c, hipEventCreate(&e1));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = fail(c, SGTP_EDEVICE, "autotune: events");
     for (const sgtp_plan_options &o : cand) {
         if (rc) break;
         sgtp_plan *P = nullptr;
@@ -3486,11 +3544,15 @@ int sgtp_autotune(sgtp_ctx *c, const sgtp_params *p, const sgtp_race *races, int
             best_o = o;
         }
     }
-    if (!rc) rc = save_restore(false);
+    if (have_saved) {
+        const int rr = save_restore(false);
+        if (!rc) rc = rr;
+    }
     (void)hipStreamSynchronize(st);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    for (void *b : saved) (void)hipFree(b);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    for (void *b : saved)
+        if (b) (void)hipFree(b);
     if (rc) return rc;
     best_o.use_graph = 1;
     *best = best_o;

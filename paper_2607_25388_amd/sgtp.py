@@ -105,6 +105,8 @@ def load():
         lib.sgtp_set_timing.argtypes = [vp, C.c_int]
         lib.sgtp_sweep_stats.argtypes = [vp, P(C.c_double), P(C.c_longlong), P(C.c_longlong), C.c_int]
         lib.sgtp_abi_version.restype = C.c_int
+        lib.sgtp_counter_probe_fp32.argtypes = [vp, C.c_int, C.c_int, vp]
+        lib.sgtp_gauss_pairs.argtypes = [vp, vp, vp, C.c_int, vp]
         lib.sgtp_plan_create.argtypes = [vp, P(Params), P(Race), C.c_int, C.c_int, vp, vp, P(PlanOptions), P(vp), vp]
         lib.sgtp_plan_run.argtypes = [vp, vp]
         lib.sgtp_plan_set_step.argtypes = [vp, C.c_uint]
@@ -127,6 +129,7 @@ def load():
         lib.sgtp_mlp_forward.argtypes = [vp, vp, C.c_int, vp, C.c_int, vp]
         lib.sgtp_mlp_grad.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_float, C.c_float, vp, vp, vp]
         lib.sgtp_mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+        lib.sgtp_mlp_workspace.argtypes = [vp, C.c_int, vp, vp]
         lib.sgtp_gemm_bf16.argtypes = [vp, C.c_longlong, C.c_longlong, vp, C.c_longlong, C.c_longlong, C.c_int,
                                        C.c_int, C.c_int, vp, vp, C.c_longlong, vp]
         _lib = lib
@@ -357,6 +360,27 @@ class Planner:
         return ms.value, n.value, ss.value
 
 
+def gauss_pairs(r_even, r_odd):
+    """The sampler's Gaussian transform on device uint32 word tensors; returns [n, 2] float32."""
+    import torch
+    n = int(r_even.numel())
+    out = torch.empty((n, 2), dtype=torch.float32, device=r_even.device)
+    rc = load().sgtp_gauss_pairs(_ptr(r_even), _ptr(r_odd), _ptr(out), n, _stream())
+    if rc != 0:
+        raise RuntimeError(f"sgtp_gauss_pairs failed: {ERRORS.get(rc, rc)}")
+    return out
+
+
+def counter_probe_fp32(n_waves: int, iters: int):
+    """Run the known-mix FP32 kernel (instrumentation); returns its output tensor."""
+    import torch
+    out = torch.empty(64 * n_waves, dtype=torch.float32, device="cuda")
+    rc = load().sgtp_counter_probe_fp32(_ptr(out), int(n_waves), int(iters), _stream())
+    if rc != 0:
+        raise RuntimeError(f"sgtp_counter_probe_fp32 failed: {ERRORS.get(rc, rc)}")
+    return out
+
+
 def choices_to_numpy(t) -> np.ndarray:
     """Decode a uint8 device buffer of sgtp_choice records."""
     return np.frombuffer(t.cpu().numpy().tobytes(), dtype=CHOICE_DTYPE)
@@ -496,7 +520,21 @@ class Mlp:
         g = torch.empty(self.n_params, dtype=torch.float32, device=X.device) if want_grads else None
         self._check(self.lib.sgtp_mlp_grad(self.h, _ptr(X), _ptr(U), X.shape[0], U.shape[1], float(sig_a),
                                            float(sig_d), _ptr(loss), _ptr(g), _stream()), "sgtp_mlp_grad")
+        self._last_B = X.shape[0]
         return loss, g
+
+    WORKSPACE = {"h1": (0, "bf16"), "h2": (1, "bf16"), "out": (2, "f32"), "d3": (3, "bf16"), "d2": (4, "bf16"),
+                 "d1": (5, "bf16")}
+
+    def workspace(self, name):
+        """A tensor of the last grad() call ([B][256]; see sgtp_mlp_workspace), as float32."""
+        import torch
+        which, kind = self.WORKSPACE[name]
+        if not getattr(self, "_last_B", 0):
+            raise RuntimeError("no gradient computed yet")
+        t = torch.empty((self._last_B, 256), dtype=torch.bfloat16 if kind == "bf16" else torch.float32, device="cuda")
+        self._check(self.lib.sgtp_mlp_workspace(self.h, which, _ptr(t), _stream()), "sgtp_mlp_workspace")
+        return t.float()
 
     def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         self._check(self.lib.sgtp_mlp_adam(self.h, lr, beta1, beta2, eps, _stream()), "sgtp_mlp_adam")

@@ -403,3 +403,22 @@ def test_bounded_wait_give_up_is_reported_and_never_selected(planner):
     # default bound again: a clean run leaves the status clear
     PY.gpu_rollout(planner, params, PY.build(planner, tr, race, params, K), 1, 1, want_noise=False)
     assert planner.status() == 0
+
+
+def test_gaussian_transform_bit_exact_for_every_radius_and_angle(planner):
+    """Every value the sampler's transform can take apart: all 2^23 radius words (angle 0)
+    and all 2^24 angle words (one radius) give the oracle's float32 pair bit for bit."""
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    tr, race, params, _, w = PY.workload("c1")
+    orc = PY.oracle_for(tr, params)
+    cases = [(np.arange(1 << 23, dtype=np.uint64) << 9, np.zeros(1 << 23, np.uint64)),
+             (np.full(1 << 24, 0x5a5a5a5a, np.uint64) & 0xfffffe00, np.arange(1 << 24, dtype=np.uint64) << 8)]
+    for re, ro in cases:
+        re32, ro32 = re.astype(np.uint32), ro.astype(np.uint32)
+        g = sg.gauss_pairs(torch.as_tensor(re32.view(np.int32)).cuda(), torch.as_tensor(ro32.view(np.int32)).cuda())
+        torch.cuda.synchronize()
+        gv = g.cpu().numpy()
+        r = orc.gauss_pairs(re32, ro32)
+        diff = np.count_nonzero(gv.view(np.uint32) != r.view(np.uint32))
+        assert diff == 0, f"{diff} of {gv.size} values differ"
