@@ -30,21 +30,25 @@ sys.path.insert(0, ROOT)
 METRIC = "sample·steps/s per IBR sweep; plan latency p50/p99; learned vs plain cost"
 PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak
 
-# Hardware counters of the dominant sweep kernel at the mid-scale race (k_sweep in its
-# split variant, two waves per sample), medians over the timed eager launches of
-# `bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-learned --roofline-steps 2
-# --copy-calibration 256` under rocprofv3 --pmc, weighted like the timed launches (6
-# all-vehicle sweeps, 1 ego sweep per planning step).  HBM bytes: FETCH_SIZE 460.0 KiB x
-# 2.000 + WRITE_SIZE 321.2 KiB x 1.000 per launch, the factors being
-# 256 MiB over what the same counter reads for the 256 MiB elementwise copy (131087 KiB
-# fetched, 262144 KiB written).  FP32 FLOPs: 64 x (ADD + MUL + TRANS + 2 FMA) wave
-# instructions of SQ_INSTS_VALU_*_F32.  They describe the kernel source with this SHA-256
-# only; any other source reports null.
+# Hardware counters of the dominant sweep kernel of the 256-race batch (k_sweep<0, 3, 9, 0,
+# 1, 0>, one workgroup per tile of 2 x 256 samples), means over the 35 launches (5 planning
+# steps of 6 all-vehicle sweeps and 1 ego sweep) of `bench.py --workload c4 --steps 3
+# --warmup 1 --no-cpu-baseline --no-learned --no-extra --roofline-steps 1 --schedule
+# 0,0,1,2 --copy-calibration 256` under rocprofv3 --pmc (profiles/sweep_c4_counters.md).
+# HBM bytes: FETCH_SIZE 115393.1 KiB x 2.000 + WRITE_SIZE 118345.0 KiB x 1.000 per launch,
+# the factors being 256 MiB over what the same counter reads for the 256 MiB elementwise
+# copy of that run (131087.6 KiB fetched, 262144 KiB written).  FP32 FLOPs: 64 x
+# SQ_INSTS_VALU_FLOPS_FP32, which counts ADD + MUL + TRANS + 2 FMA wave instructions (checked
+# on the known-mix kernel of --counter-probe, profiles/counter_probe_fp32.md).  They
+# describe the kernel source with this SHA-256 and this schedule only; anything else
+# reports null.
 SWEEP_COUNTERS = {
-    "c2": {"source_sha256": "693eb70a80538a91de084ea1e8c13ffb07b6111bdf2748c5af08dee5ff65c652",
-           "hbm_bytes_per_launch": (460.062 * 1.99976 + 321.237) * 1024.0,
-           "hw_fp32_flop_per_launch": 1.2483e9, "valu_wave_insts_per_launch": 22.02e6},
+    "c4": {"source_sha256": "f121723f393dccc4cfc2b4c9000c9c4855089091115c10a7c281d7c9c4a87df4",
+           "hbm_bytes_per_launch": (115393.086 * 1.99976 + 118345.048) * 1024.0,
+           "hw_fp32_flop_per_launch": 64 * 15129959988.5, "valu_wave_insts_per_launch": 15007320407.2,
+           "schedule": {"persistent": 0, "blocks_per_cu": 0, "tiles_per_fetch": 1, "samples_per_lane": 2}},
 }
+
 
 def _source_sha256() -> str:
     import hashlib
@@ -174,6 +178,69 @@ def _latency(plan, steps, warmup=10):
     return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)), "mean": float(lat.mean())}
 
 
+PEAK_BF16_TFLOPS = 2500.0  # MI355X published dense BF16 matrix peak
+PEAK_HBM_GBPS = 8000.0
+
+
+def _progress(msg: str):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def _events_ms(fn, reps: int) -> float:
+    """Mean milliseconds of fn() over reps launches, HIP events on the current stream."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def mfma_block(mlp, data, params) -> dict:
+    """Matrix-core use of the proposal network: one training step (graph replay of gather,
+    gradient and Adam at 4096 rows), its largest products alone, and the forward pass at
+    planning and at large batch.  FLOPs are the products' 2 M N K; bytes the BF16 operands
+    read once and the float32 result written once."""
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    from paper_2607_25388_amd import learned
+    out = {}
+    tr = learned.Trainer(mlp, data, params, batch=4096, lr=1e-4, seed=99, graph=True)
+    ms = _events_ms(tr.step, 50)
+    tr.close()
+    flop = learned.TRAIN_FLOP_PER_ROW * 4096
+    out["train_step"] = {"rows": 4096, "ms": ms, "flop": flop, "tflops": flop / ms / 1e9,
+                         "mfma_frac": flop / ms / 1e9 / PEAK_BF16_TFLOPS,
+                         "timing": "HIP events over 50 graph replays (index draw + gather + gradient + Adam)"}
+
+    def gemm_case(M, N, K):
+        A = torch.randn((M, K), device="cuda").to(torch.bfloat16)
+        B = torch.randn((K, N), device="cuda").to(torch.bfloat16)
+        C = torch.empty((M, N), device="cuda")
+        ms = _events_ms(lambda: sg.gemm_bf16(A, (K, 1), B, (N, 1), M, N, K, out=C), 20)
+        fl, by = 2.0 * M * N * K, 2.0 * (M * K + K * N) + 4.0 * M * N
+        return {"M": M, "N": N, "K": K, "ms": ms, "tflops": fl / ms / 1e9, "mfma_frac": fl / ms / 1e9 / PEAK_BF16_TFLOPS,
+                "hbm_gbps": by / ms / 1e6, "hbm_frac": by / ms / 1e6 / PEAK_HBM_GBPS,
+                "roof": "hbm" if fl / by < PEAK_BF16_TFLOPS / PEAK_HBM_GBPS * 1e3 else "mfma"}
+
+    out["gemm"] = [gemm_case(4096, 256, 256), gemm_case(65536, 256, 256), gemm_case(16384, 1024, 1024)]
+    fwd = {}
+    for rows in (1536, 65536):
+        X = torch.randn((rows, 50), device="cuda")
+        Y = torch.empty((rows, 200), device="cuda")
+        ms = _events_ms(lambda: mlp.forward(X, out=Y), 20)
+        fl = rows * 2.0 * (50 * 256 + 256 * 256 + 256 * 200)
+        fwd[str(rows)] = {"ms": ms, "tflops": fl / ms / 1e9, "mfma_frac": fl / ms / 1e9 / PEAK_BF16_TFLOPS,
+                          "kernel": "fused three-layer" if rows <= 4096 else "tiled products"}
+    out["forward"] = fwd
+    return out
+
+
 def learned_block(planner, n_examples: int, iters: int, eval_races: int = 32, lat_steps: int = 100):
     """Learned proposal against the plain sampler on races of the mid-scale kind with N = 50:
     train the network on the plain planner's own selections (closed loop, 256 races), then on
@@ -197,6 +264,7 @@ def learned_block(planner, n_examples: int, iters: int, eval_races: int = 32, la
     data = learned.collect(planner, params, rts, L, steps)
     torch.cuda.synchronize()
     t_collect = time.perf_counter() - t0
+    _progress(f"learned: {int(data.X.shape[0])} training sequences collected in {t_collect:.1f} s")
     del rts
     mlp = sg.Mlp(4096, seed=1)
     t1 = time.perf_counter()
@@ -205,6 +273,11 @@ def learned_block(planner, n_examples: int, iters: int, eval_races: int = 32, la
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     n_ex = int(data.X.shape[0])
+    _progress(f"learned: {iters + iters // 2} Adam steps in {t_train:.1f} s")
+    big = sg.Mlp(65536, mlp.get_params())
+    mfma = mfma_block(big, data, params)
+    big.close()
+    _progress("learned: matrix-core timings done")
     del data
 
     _, hold, _ = inputs.learned_races(eval_races, 1_000_000, N=N)
@@ -219,6 +292,7 @@ def learned_block(planner, n_examples: int, iters: int, eval_races: int = 32, la
         rec["K4"].append(learned.best_response_costs(planner, params, rts, K // 4))
         rec["L4"].append(learned.best_response_costs(planner, params, rts, K // 4, K_PROP, mlp))
     plan.close()
+    _progress("learned: held-out best responses done")
     cat = {k: (np.concatenate([c for c, f in v]), np.concatenate([f for c, f in v])) for k, v in rec.items()}
     gp, sp = learned.cost_gap(*cat["K4"], *cat["K"])
     gl, sl = learned.cost_gap(*cat["L4"], *cat["K"])
@@ -244,7 +318,10 @@ def learned_block(planner, n_examples: int, iters: int, eval_races: int = 32, la
                      f"{L} IBR sweeps), {n_ex} selected sequences; {eval_races} held-out races, best responses "
                      f"at 5 closed-loop instants"),
         "train": {"examples": n_ex, "collect_s": t_collect, "adam_iters": iters + iters // 2, "batch": 4096,
-                  "train_s": t_train, "loss_first": losses[0], "loss_last": losses[-1]},
+                  "train_s": t_train, "loss_first": losses[0], "loss_last": losses[-1],
+                  "step": "graph replay of gather, gradient and Adam"},
+        "mfma_frac": mfma["train_step"]["mfma_frac"],
+        "mfma": mfma,
         "cost": {"cases": int(len(gl)), "plain_K4_mean_gap": float(gp.mean()), "plain_K4_sum_gap": sp,
                  "learned_K4_mean_gap": float(gl.mean()), "learned_K4_sum_gap": sl,
                  "learned_K4_not_worse_frac": float(np.mean(gl <= 0.0)),
@@ -359,7 +436,8 @@ def measure(planner, name: str, steps: int, warmup: int, roofline_steps: int, mo
                                    "sample-steps of each race"},
     }
     cnt = SWEEP_COUNTERS.get(name)
-    if cnt and cnt["source_sha256"] == _source_sha256():
+    sched = rec["config"].get("schedule", {})
+    if cnt and cnt["source_sha256"] == _source_sha256() and all(sched.get(k) == v for k, v in cnt["schedule"].items()):
         avg_s = sweep_ms * 1e-3 / max(1, sweep_launches)
         rec["roofline"]["traffic"] = cnt["hbm_bytes_per_launch"]
         rec["roofline"]["traffic_unit"] = "bytes per sweep launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)"
@@ -445,6 +523,23 @@ def main():
                    race_eval=res)
         print(json.dumps(rec), flush=True)
         return
+    if name == "mlp":
+        # the proposal network's matrix-core timings alone, on seeded synthetic rows
+        from paper_2607_25388_amd import learned
+        g = torch.Generator(device="cuda")
+        g.manual_seed(5)
+        M = 200000
+        X = torch.randn((M, 50), device="cuda", generator=g)
+        U = torch.stack([torch.rand((M, 50), device="cuda", generator=g) * 12.0 - 8.0,
+                         torch.rand((M, 50), device="cuda", generator=g) * 0.8 - 0.4], -1).contiguous()
+        mlp = sg.Mlp(65536, seed=1)
+        mf = mfma_block(mlp, learned.Dataset(X, U, None, None), {"sigma_a": 1.5, "sigma_d": 0.08})
+        mlp.close()
+        rec = dict(base, value=mf["train_step"]["mfma_frac"], unit="fraction of BF16 matrix peak (training step)",
+                   dtype="bf16 operands, f32 accumulation", config={"workload": "proposal network 50-256-256-200, "
+                   "training step of 4096 rows, products and forward passes alone"}, mfma=mf)
+        print(json.dumps(rec), flush=True)
+        return
     planner = sg.Planner(max_agents_total=2048, max_races=256)
     if name == "c5":
         lb = learned_block(planner, max(args.learned_examples, 1000000), max(args.learned_iters, 20000),
@@ -458,6 +553,7 @@ def main():
 
     m = measure(planner, name, args.steps, args.warmup, args.roofline_steps, args.mode, not args.no_autotune,
                 args.schedule)
+    _progress(f"{name}: {m['value']:.4g} sample-steps/s, {m['ms_per_step']:.3f} ms per step")
     rec = dict(base, value=m["value"], unit="sample·steps/s", steps=args.steps, warmup=args.warmup,
                ms_per_step=m["ms_per_step"], scaling="weak", dtype="f32", config=m["config"],
                plan_latency_ms=m["plan_latency_ms"], sweep_kernel=m["sweep_kernel"], roofline=m["roofline"])
@@ -472,6 +568,7 @@ def main():
         rec["workloads"] = {}
         for extra, st in (("c3", 100), ("c2", 200)):
             e = measure(planner, extra, st, 5, 5)
+            _progress(f"{extra}: {e['value']:.4g} sample-steps/s")
             rec["workloads"][extra] = {k: e[k] for k in ("value", "ms_per_step", "plan_latency_ms", "sweep_kernel",
                                                          "roofline")}
             rec["workloads"][extra]["config"] = e["config"]["workload"]
@@ -480,7 +577,9 @@ def main():
     if not args.no_cpu_baseline:
         K_cpu = 256 if name in ("c3", "c4") else 2048
         rec["cpu_baseline"] = cpu_baseline(name, args.cpu_seconds, K_cpu)
+        _progress(f"cpu baseline: {rec['cpu_baseline']['value']:.4g} sample-steps/s")
         rec["cpu_baseline_1core"] = cpu_baseline(name, args.cpu_seconds, K_cpu, threads=1)
+        _progress(f"cpu baseline, 1 thread: {rec['cpu_baseline_1core']['value']:.4g} sample-steps/s")
     rec["context"] = ("the paper reports 0.095 s mean computation time per planning call (K=128, H=12, 3 vehicles, "
                       "L_IBR=2) on an NVIDIA RTX 4060 (Sec. IV-B, Table I): about 1.1-1.6e5 sample-steps/s; a "
                       "different machine and workload, not the target")

@@ -55,6 +55,7 @@ struct GemmArgs {
     const float *bias;  // [N] or NULL
     float *C;           // [M][ldc] float32 result (pre-activation), or NULL
     long long ldc;
+    long long c_split;  // split K: slice z writes its partial product to C + z c_split
     bf16 *H;            // [M][ldh] BF16 GELU(result), or NULL
     long long ldh;
 };
@@ -81,7 +82,8 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
-    // split K: slice z of gridDim.z covers [kbeg, kend) and adds its partial product into C
+    // split K: slice z of gridDim.z covers [kbeg, kend) and writes its partial product to its
+    // own slice of C (summed afterwards in slice order: the result does not depend on timing)
     const int kslice = ((g.K + 32 * gridDim.z - 1) / (32 * gridDim.z)) * 32;
     const int kbeg = blockIdx.z * kslice, kend = min(g.K, kbeg + kslice);
     for (int k0 = kbeg; k0 < kend; k0 += 32) {
@@ -124,7 +126,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
                 if (m < g.M && n < g.N) {
                     float x = acc[i][j][v];
                     if (gridDim.z > 1) {
-                        atomicAdd(&g.C[(long long)m * g.ldc + n], x);
+                        g.C[blockIdx.z * g.c_split + (long long)m * g.ldc + n] = x;
                         continue;
                     }
                     if (g.bias) x += g.bias[n];
@@ -236,7 +238,7 @@ __global__ void __launch_bounds__(256) k_mlp_fwd16(const float *X, int ldx, int 
 // 0.5 log 2 pi dropped; steps t >= N do not enter) and its gradient w.r.t. the outputs,
 // as BF16 for the products.  One thread per (row, step < 64, channel).
 __global__ void k_nll(const float *out, int ldo, const float *U, int B, int N, float sig_a, float sig_d, bf16 *dout,
-                      int ldd, float *loss_sum) {
+                      int ldd, float *loss_part) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = e >> 7, t = (e >> 1) & 63, c = e & 1;
     float contrib = 0.0f;
@@ -260,9 +262,9 @@ __global__ void k_nll(const float *out, int ldo, const float *U, int B, int N, f
             g[4 * t + 2 + c] = (bf16)0.0f;
         }
     }
-    // wave reduction of the loss, one atomic per wave
+    // wave reduction of the loss; one partial per wave (summed in order by k_loss_total)
     for (int off = 32; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off);
-    if ((threadIdx.x & 63) == 0) atomicAdd(loss_sum, contrib / (float)B);
+    if ((threadIdx.x & 63) == 0) loss_part[e >> 6] = contrib;
 }
 
 // dpre = dh * gelu'(pre) as BF16
@@ -271,41 +273,62 @@ __global__ void k_gelu_back(const float *dh, const float *pre, int n, bf16 *dpre
     if (e < n) dpre[e] = (bf16)(dh[e] * gelu_grad_f(pre[e]));
 }
 
-// column sums of a BF16 [B][ld] matrix added into float32 dst[ncols] (bias gradients; dst
-// cleared beforehand): block x covers 256 columns, block y a slice of 256 rows
-__global__ void k_colsum(const bf16 *D, int B, int ld, int ncols, float *dst) {
+// column sums of a BF16 [B][ld] matrix over slices of 256 rows (bias gradients): block y
+// writes the sums of its slice to part[y][ncols]; k_sum_slices adds the slices in order
+__global__ void k_colsum(const bf16 *D, int B, int ld, int ncols, float *part) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncols) return;
     const int b0 = blockIdx.y * 256, b1 = min(B, b0 + 256);
     float s = 0.0f;
     for (int b = b0; b < b1; ++b) s += (float)D[(long long)b * ld + c];
-    atomicAdd(&dst[c], s);
+    part[(long long)blockIdx.y * ncols + c] = s;
 }
 
-// zero n floats (a kernel, not a memset node, so the gradient step can be captured and replayed)
-__global__ void k_zero(float *p, int n) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n) p[e] = 0.0f;
-}
-
-// copy a [rows][cols] block of a float32 matrix with row stride lds into packed storage
-__global__ void k_pack(const float *S, int rows, int cols, int lds, float *dst) {
+// dst[r][c] (row stride ldd) = sum over z = 0 .. n_slices-1, in that order, of
+// src[z][r][c] (slice stride zs, row stride lds), for r < rows, c < cols
+__global__ void k_sum_slices(const float *src, int n_slices, long long zs, int rows, int cols, int lds, float *dst,
+                             int ldd) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= rows * cols) return;
     const int r = e / cols, c = e % cols;
-    dst[e] = S[(long long)r * lds + c];
+    const float *p = src + (long long)r * lds + c;
+    float s = p[0];
+    for (int z = 1; z < n_slices; ++z) s += p[z * zs];
+    dst[(long long)r * ldd + c] = s;
 }
 
+// loss = (sum of the per-wave partials, in a fixed order) / B: one block of 256 threads
+__global__ void k_loss_total(const float *part, int n, int B, float *loss) {
+    __shared__ float red[256];
+    float s = 0.0f;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = red[0] / (float)B;
+}
+
+// Adam step number t = *t_prev + 1 read on the device (so a captured training step can be
+// replayed); k_step_count advances it after the step
 __global__ void k_adam(float *P, const float *G, float *m, float *v, int n, float lr, float b1, float b2, float eps,
-                       float bc1, float bc2) {
+                       const int *t_prev) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
+    const float t = (float)(*t_prev + 1);
+    const float bc1 = 1.0f - powf(b1, t), bc2 = 1.0f - powf(b2, t);
     const float g = G[e];
     const float mm = b1 * m[e] + (1.0f - b1) * g;
     const float vv = b2 * v[e] + (1.0f - b2) * g * g;
     m[e] = mm;
     v[e] = vv;
     P[e] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+}
+
+__global__ void k_step_count(int *t) {
+    if (threadIdx.x == 0) *t += 1;
 }
 
 }  // namespace
@@ -318,8 +341,11 @@ struct sgtp_mlp {
     bf16 *W1T = nullptr, *W2T = nullptr, *W3T = nullptr;           // transposed (fused forward)
     float *b3p = nullptr;
     bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *D = nullptr, *D2 = nullptr, *D1 = nullptr;
-    float *PRE1 = nullptr, *PRE2 = nullptr, *OUT = nullptr, *DH = nullptr, *GW = nullptr, *loss = nullptr;
-    int adam_t = 0;
+    float *PRE1 = nullptr, *PRE2 = nullptr, *OUT = nullptr, *DH = nullptr, *loss = nullptr;
+    float *PART = nullptr;  // split-K partial products of the weight gradients [64][256][256]
+    float *CS = nullptr;    // bias-gradient partial sums [ceil(B_max / 256)][256]
+    float *LP = nullptr;    // per-wave loss partials [2 B_max + 4]
+    int *adam_t = nullptr;  // device: Adam steps taken
     int last_B = 0;  // rows of the last sgtp_mlp_grad (its workspace tensors stay until the next call)
 };
 
@@ -336,13 +362,32 @@ int mfail(sgtp_mlp *m, int code, const std::string &s) {
     } while (0)
 
 void gemm(hipStream_t st, const bf16 *A, long long a_m, long long a_k, const bf16 *B, long long b_k, long long b_n,
-          int M, int N, int K, const float *bias, float *C, long long ldc, bf16 *H, long long ldh, int splits = 1) {
-    GemmArgs g{A, a_m, a_k, B, b_k, b_n, M, N, K, bias, C, ldc, H, ldh};
+          int M, int N, int K, const float *bias, float *C, long long ldc, bf16 *H, long long ldh) {
+    GemmArgs g{A, a_m, a_k, B, b_k, b_n, M, N, K, bias, C, ldc, 0, H, ldh};
+    hipLaunchKernelGGL(k_gemm_bf16, dim3((N + 63) / 64, (M + 63) / 64, 1), dim3(256), 0, st, g);
+}
+
+// weight gradient dst[M][ldd] (first N columns) = A B with K split into `splits` slices:
+// partial products into m->PART, summed in slice order
+void gemm_wgrad(sgtp_mlp *m, hipStream_t st, const bf16 *A, long long a_m, long long a_k, const bf16 *B, long long b_k,
+                long long b_n, int M, int N, int K, float *dst, int ldd, int splits) {
+    GemmArgs g{A, a_m, a_k, B, b_k, b_n, M, N, K, nullptr, m->PART, N, (long long)M * N, nullptr, 0};
     hipLaunchKernelGGL(k_gemm_bf16, dim3((N + 63) / 64, (M + 63) / 64, splits), dim3(256), 0, st, g);
+    hipLaunchKernelGGL(k_sum_slices, dim3((M * N + 255) / 256), dim3(256), 0, st, m->PART, splits, (long long)M * N, M,
+                       N, N, dst, ldd);
+}
+
+// bias gradient dst[ncols] = column sums of the BF16 [B][ld] matrix D, in a fixed order
+void bias_grad(sgtp_mlp *m, hipStream_t st, const bf16 *D, int B, int ld, int ncols, float *dst) {
+    const int rb = (B + 255) / 256;
+    hipLaunchKernelGGL(k_colsum, dim3((ncols + 255) / 256, rb), dim3(256), 0, st, D, B, ld, ncols, m->CS);
+    hipLaunchKernelGGL(k_sum_slices, dim3((ncols + 255) / 256), dim3(256), 0, st, m->CS, rb, (long long)ncols, 1,
+                       ncols, ncols, dst, ncols);
 }
 
 // K split of a weight-gradient product (K = batch): about 512 rows per slice, at most 64 slices
-int k_splits(int K) { return std::max(1, std::min(64, (K + 511) / 512)); }
+constexpr int MAX_SPLITS = 64;
+int k_splits(int K) { return std::max(1, std::min(MAX_SPLITS, (K + 511) / 512)); }
 
 // forward of B rows (features float32 [B][ldx]) into out[B][ldo], n_out columns (200, or
 // 256 with the zero padding for the loss)
@@ -392,7 +437,10 @@ int sgtp_mlp_create(int B_max, sgtp_mlp **out) {
     al((void **)&m->PRE2, (size_t)B_max * D_H * 4);
     al((void **)&m->OUT, (size_t)B_max * D_OUTP * 4);
     al((void **)&m->DH, (size_t)B_max * D_H * 4);
-    al((void **)&m->GW, (size_t)D_H * D_OUTP * 4);
+    al((void **)&m->PART, (size_t)MAX_SPLITS * D_H * D_OUTP * 4);
+    al((void **)&m->CS, (size_t)((B_max + 255) / 256) * D_OUTP * 4);
+    al((void **)&m->LP, (size_t)(2 * B_max + 4) * 4);
+    al((void **)&m->adam_t, 4);
     al((void **)&m->loss, 4);
     if (!ok) {
         sgtp_mlp_destroy(m);
@@ -406,8 +454,8 @@ int sgtp_mlp_destroy(sgtp_mlp *m) {
     if (!m) return SGTP_EINVAL;
     (void)hipDeviceSynchronize();
     void *bufs[] = {m->P,  m->G,  m->Mm, m->Vv,   m->W1,   m->W2,  m->W3, m->b3p, m->X,    m->H1,   m->H2,
-                    m->D,  m->D1, m->PRE1, m->PRE2, m->OUT, m->DH, m->GW,  m->loss, m->W1T, m->W2T, m->W3T,
-                    m->D2};
+                    m->D,  m->D1, m->PRE1, m->PRE2, m->OUT, m->DH, m->PART, m->loss, m->W1T, m->W2T, m->W3T,
+                    m->D2, m->CS, m->LP, m->adam_t};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete m;
@@ -425,7 +473,7 @@ int sgtp_mlp_set_params(sgtp_mlp *m, const float *host) {
     MCHK(m, hipMemcpy(m->P, host, P_TOTAL * 4, hipMemcpyHostToDevice));
     MCHK(m, hipMemset(m->Mm, 0, P_TOTAL * 4));
     MCHK(m, hipMemset(m->Vv, 0, P_TOTAL * 4));
-    m->adam_t = 0;
+    MCHK(m, hipMemset(m->adam_t, 0, 4));
     hipLaunchKernelGGL(k_refresh_bf16, dim3((D_H * D_OUTP + 255) / 256), dim3(256), 0, nullptr, m->P, m->W1, m->W2,
                        m->W3, m->b3p);
     hipLaunchKernelGGL(k_refresh_bf16_t, dim3((D_H * D_H + 255) / 256), dim3(256), 0, nullptr, m->P, m->W1T, m->W2T,
@@ -465,26 +513,24 @@ int sgtp_mlp_grad(sgtp_mlp *m, const float *X, const float *U, int B, int N, flo
     hipStream_t st = (hipStream_t)stream;
     int rc = forward(m, X, D_IN, B, m->OUT, D_OUTP, D_OUTP, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, m->loss, 1);
-    hipLaunchKernelGGL(k_zero, dim3((P_TOTAL + 255) / 256), dim3(256), 0, st, m->G, (int)P_TOTAL);
-    hipLaunchKernelGGL(k_zero, dim3((D_H * D_OUTP + 255) / 256), dim3(256), 0, st, m->GW, D_H * D_OUTP);
-    const int sp = k_splits(B), rb = (B + 255) / 256;
-    hipLaunchKernelGGL(k_nll, dim3((B * 128 + 255) / 256), dim3(256), 0, st, m->OUT, D_OUTP, U, B, N, sig_a, sig_d,
-                       m->D, D_OUTP, m->loss);
+    const int sp = k_splits(B);
+    const int nll_blocks = (B * 128 + 255) / 256;
+    hipLaunchKernelGGL(k_nll, dim3(nll_blocks), dim3(256), 0, st, m->OUT, D_OUTP, U, B, N, sig_a, sig_d, m->D, D_OUTP,
+                       m->LP);
+    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, st, m->LP, 4 * nll_blocks, B, m->loss);
     // layer 3: gW3 = H2^T D, gb3 = column sums of D, dH2 = D W3^T
-    gemm(st, m->H2, 1, D_H, m->D, D_OUTP, 1, D_H, D_OUTP, B, nullptr, m->GW, D_OUTP, nullptr, 0, sp);
-    hipLaunchKernelGGL(k_pack, dim3((D_H * D_OUT + 255) / 256), dim3(256), 0, st, m->GW, D_H, D_OUT, D_OUTP, m->G + P_W3);
-    hipLaunchKernelGGL(k_colsum, dim3(1, rb), dim3(256), 0, st, m->D, B, D_OUTP, D_OUT, m->G + P_B3);
+    gemm_wgrad(m, st, m->H2, 1, D_H, m->D, D_OUTP, 1, D_H, D_OUT, B, m->G + P_W3, D_OUT, sp);
+    bias_grad(m, st, m->D, B, D_OUTP, D_OUT, m->G + P_B3);
     gemm(st, m->D, D_OUTP, 1, m->W3, 1, D_OUTP, B, D_H, D_OUTP, nullptr, m->DH, D_H, nullptr, 0);
     hipLaunchKernelGGL(k_gelu_back, dim3((B * D_H + 255) / 256), dim3(256), 0, st, m->DH, m->PRE2, B * D_H, m->D2);
     // layer 2: gW2 = H1^T D2, gb2, dH1 = D2 W2^T
-    gemm(st, m->H1, 1, D_H, m->D2, D_H, 1, D_H, D_H, B, nullptr, m->G + P_W2, D_H, nullptr, 0, sp);
-    hipLaunchKernelGGL(k_colsum, dim3(1, rb), dim3(256), 0, st, m->D2, B, D_H, D_H, m->G + P_B2);
+    gemm_wgrad(m, st, m->H1, 1, D_H, m->D2, D_H, 1, D_H, D_H, B, m->G + P_W2, D_H, sp);
+    bias_grad(m, st, m->D2, B, D_H, D_H, m->G + P_B2);
     gemm(st, m->D2, D_H, 1, m->W2, 1, D_H, B, D_H, D_H, nullptr, m->DH, D_H, nullptr, 0);
     hipLaunchKernelGGL(k_gelu_back, dim3((B * D_H + 255) / 256), dim3(256), 0, st, m->DH, m->PRE1, B * D_H, m->D1);
     // layer 1: gW1 = X^T D1, gb1
-    gemm(st, m->X, 1, D_INP, m->D1, D_H, 1, D_IN, D_H, B, nullptr, m->G + P_W1, D_H, nullptr, 0, sp);
-    hipLaunchKernelGGL(k_colsum, dim3(1, rb), dim3(256), 0, st, m->D1, B, D_H, D_H, m->G + P_B1);
+    gemm_wgrad(m, st, m->X, 1, D_INP, m->D1, D_H, 1, D_IN, D_H, B, m->G + P_W1, D_H, sp);
+    bias_grad(m, st, m->D1, B, D_H, D_H, m->G + P_B1);
     MCHK(m, hipGetLastError());
     m->last_B = B;
     if (loss) MCHK(m, hipMemcpyAsync(loss, m->loss, 4, hipMemcpyDeviceToDevice, st));
@@ -513,14 +559,13 @@ int sgtp_mlp_workspace(sgtp_mlp *m, int which, void *dst, void *stream) {
 int sgtp_mlp_adam(sgtp_mlp *m, float lr, float beta1, float beta2, float eps, void *stream) {
     if (!m) return SGTP_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    m->adam_t += 1;
-    const float bc1 = 1.0f - std::pow(beta1, (float)m->adam_t), bc2 = 1.0f - std::pow(beta2, (float)m->adam_t);
     hipLaunchKernelGGL(k_adam, dim3((P_TOTAL + 255) / 256), dim3(256), 0, st, m->P, m->G, m->Mm, m->Vv, (int)P_TOTAL,
-                       lr, beta1, beta2, eps, bc1, bc2);
+                       lr, beta1, beta2, eps, m->adam_t);
     hipLaunchKernelGGL(k_refresh_bf16, dim3((D_H * D_OUTP + 255) / 256), dim3(256), 0, st, m->P, m->W1, m->W2, m->W3,
                        m->b3p);
     hipLaunchKernelGGL(k_refresh_bf16_t, dim3((D_H * D_H + 255) / 256), dim3(256), 0, st, m->P, m->W1T, m->W2T,
                        m->W3T);
+    hipLaunchKernelGGL(k_step_count, dim3(1), dim3(64), 0, st, m->adam_t);
     MCHK(m, hipGetLastError());
     return SGTP_OK;
 }

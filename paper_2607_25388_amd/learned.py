@@ -66,23 +66,69 @@ def collect(planner: sg.Planner, params: dict, races, L_ibr: int, steps: int, re
     return Dataset(X, U.contiguous(), Ubar, U_sel)
 
 
+# matrix-product FLOP per row of one training step (forward, the weight gradients of the
+# three layers and the input gradients of layers 3 and 2)
+TRAIN_FLOP_PER_ROW = 2 * (50 * 256 + 256 * 256 + 256 * 200) * 2 + 2 * (200 * 256 + 256 * 256)
+
+
+class Trainer:
+    """Adam on random minibatches of a data set.  Each step draws `batch` row indices
+    (torch's device generator, seeded), gathers the rows into fixed buffers and runs
+    sgtp_mlp_grad and sgtp_mlp_adam; with graph=True the gather, gradient and Adam launches
+    are captured once in a hipGraph and each step is one index draw plus one replay.  The
+    network's reductions run in a fixed order, so both ways give the same bits."""
+
+    def __init__(self, mlp: sg.Mlp, data: Dataset, params: dict, batch: int = 1024, lr: float = 1e-3,
+                 seed: int = 0, graph: bool = True):
+        import torch
+        self.mlp, self.data, self.lr = mlp, data, lr
+        self.M = data.X.shape[0]
+        self.batch = min(batch, self.M, mlp.B_max)
+        dev = data.X.device
+        self.gen = torch.Generator(device=dev)
+        self.gen.manual_seed(seed)
+        self.sig = (params["sigma_a"], params["sigma_d"])
+        self.idx = torch.zeros(self.batch, dtype=torch.long, device=dev)
+        self.Xb = torch.empty((self.batch,) + tuple(data.X.shape[1:]), dtype=data.X.dtype, device=dev)
+        self.Ub = torch.empty((self.batch,) + tuple(data.U.shape[1:]), dtype=data.U.dtype, device=dev)
+        self.graph = None
+        if graph:
+            self.graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.graph):
+                self.loss = self._launch()
+
+    def _launch(self):
+        import torch
+        torch.index_select(self.data.X, 0, self.idx, out=self.Xb)
+        torch.index_select(self.data.U, 0, self.idx, out=self.Ub)
+        loss, _ = self.mlp.grad(self.Xb, self.Ub, *self.sig)
+        self.mlp.adam(lr=self.lr)
+        return loss
+
+    def step(self):
+        """One training step; returns the (device) loss of its minibatch before the update."""
+        import torch
+        torch.randint(0, self.M, (self.batch,), generator=self.gen, out=self.idx)
+        if self.graph is not None:
+            self.graph.replay()
+            return self.loss
+        return self._launch()
+
+    def close(self):
+        self.graph = None
+
+
 def train(mlp: sg.Mlp, data: Dataset, params: dict, iters: int, batch: int = 1024, lr: float = 1e-3,
-          seed: int = 0, log_every: int = 0):
+          seed: int = 0, log_every: int = 0, graph: bool = True):
     """Adam on random minibatches of the data set (Gaussian negative log-likelihood of the
     targets); returns the losses at every log point (and the last)."""
-    import torch
-    M = data.X.shape[0]
-    batch = min(batch, M, mlp.B_max)
-    gen = torch.Generator(device=data.X.device)
-    gen.manual_seed(seed)
+    tr = Trainer(mlp, data, params, batch, lr, seed, graph)
     losses = []
     for it in range(iters):
-        idx = torch.randint(0, M, (batch,), device=data.X.device, generator=gen)
-        loss, _ = mlp.grad(data.X.index_select(0, idx), data.U.index_select(0, idx), params["sigma_a"],
-                           params["sigma_d"])
-        mlp.adam(lr=lr)
+        loss = tr.step()
         if (log_every and it % log_every == 0) or it == iters - 1:
             losses.append(float(loss.item()))
+    tr.close()
     return losses
 
 

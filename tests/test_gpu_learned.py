@@ -130,6 +130,40 @@ def test_adam_first_step_and_training_reduces_loss():
     m.close()
 
 
+def test_training_step_graph_replays_match_eager_steps():
+    """A training step captured once in a hipGraph (minibatch gather, gradient, Adam) and
+    replayed gives, bit for bit, the loss and the parameters of the same steps launched one
+    by one, with unrelated eager work and synchronisation between the replays.  The batch
+    of 1000 rows splits the weight-gradient products into two K slices and the bias sums
+    into four row slices, all reduced in a fixed order."""
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    from paper_2607_25388_amd import learned
+    flat, _ = _net(seed=13, scale3=3.0)
+    rng = np.random.default_rng(4)
+    M, N = 3000, 40
+    X = torch.as_tensor(rng.standard_normal((M, 50)).astype(np.float32)).cuda()
+    U = torch.as_tensor(np.stack([rng.uniform(-8, 4, (M, N)), rng.uniform(-0.4, 0.4, (M, N))], -1)
+                        .astype(np.float32)).cuda()
+    data = learned.Dataset(X, U, None, None)
+    params = {"sigma_a": 1.5, "sigma_d": 0.08}
+    ma, mb = sg.Mlp(1024, flat), sg.Mlp(1024, flat)
+    ta = learned.Trainer(ma, data, params, batch=1000, lr=1e-3, seed=3, graph=True)
+    tb = learned.Trainer(mb, data, params, batch=1000, lr=1e-3, seed=3, graph=False)
+    for it in range(6):
+        la = float(ta.step().item())
+        torch.ones(4096, device="cuda").sum().item()
+        lb = float(tb.step().item())
+        torch.cuda.synchronize()
+        assert la == lb, (it, la, lb)
+        pa, pb = ma.get_params(), mb.get_params()
+        assert np.array_equal(pa.view(np.uint32), pb.view(np.uint32)), (it, np.abs(pa - pb).max())
+    assert not np.array_equal(pa, flat)
+    ta.close()
+    ma.close()
+    mb.close()
+
+
 @pytest.mark.parametrize("name", ["c2", "c3"])
 def test_features_match_oracle(planner, name):
     import torch
