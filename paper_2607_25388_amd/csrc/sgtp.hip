@@ -303,6 +303,23 @@ __device__ __forceinline__ float fast_atan(float x) {
     return copysignf(r, x);
 }
 
+// atan of a slip angle's argument (v_y + l om) / v_x, which stays within 1/4 in all but a
+// few samples: there an odd quintic whose coefficients are a minimax (equal-ripple) fit of
+// the absolute error on [0, 1/4] rounded to float32 (1.2e-7 exact, 1.4e-7 evaluated in
+// float32), beyond it the general atan.  The choice is per lane -- a branch that diverges
+// only in waves holding both cases -- so a sample's value never depends on the other
+// lanes of its wave.
+template <bool UNIFORM = false>
+__device__ __forceinline__ float atan_slip(float x) {
+    if (__builtin_expect(fabsf(x) <= 0.25f, 1)) {
+        const float x2 = x * x;
+        float p = __builtin_fmaf(0x1.7b89a0p-3f, x2, -0x1.54dfd2p-2f);
+        p = __builtin_fmaf(p, x2, 0x1.ffff8cp-1f);
+        return p * x;
+    }
+    return fast_atan<UNIFORM>(x);
+}
+
 // sin/cos through the transcendental unit (argument in revolutions)
 __device__ __forceinline__ float fast_sin(float x) { return __builtin_amdgcn_sinf(x * 0.159154943f); }
 __device__ __forceinline__ float fast_cos(float x) { return __builtin_amdgcn_cosf(x * 0.159154943f); }
@@ -312,6 +329,7 @@ __device__ __forceinline__ float fast_cos(float x) { return __builtin_amdgcn_cos
 struct MathF32 {
     using T = float;
     static __device__ __forceinline__ T atan_(T x) { return fast_atan<false>(x); }
+    static __device__ __forceinline__ T atan_slip_(T x) { return atan_slip<false>(x); }
     static __device__ __forceinline__ T sin_(T x) { return fast_sin(x); }
     static __device__ __forceinline__ T cos_(T x) { return fast_cos(x); }
     static __device__ __forceinline__ T rcp_(T x) { return fast_rcp(x); }
@@ -329,11 +347,13 @@ struct MathF32 {
 // MathF32 with the wave-uniform atan range reduction (throughput kernels)
 struct MathF32U : MathF32 {
     static __device__ __forceinline__ T atan_(T x) { return fast_atan<true>(x); }
+    static __device__ __forceinline__ T atan_slip_(T x) { return atan_slip<true>(x); }
 };
 
 struct MathF64 {
     using T = double;
     static __device__ __forceinline__ T atan_(T x) { return ::atan(x); }
+    static __device__ __forceinline__ T atan_slip_(T x) { return ::atan(x); }
     static __device__ __forceinline__ T sin_(T x) { return ::sin(x); }
     static __device__ __forceinline__ T cos_(T x) { return ::cos(x); }
     static __device__ __forceinline__ T rcp_(T x) { return 1.0 / x; }
@@ -392,7 +412,7 @@ __device__ __forceinline__ typename M::T tyre_force(const VehConst<typename M::T
                                                      typename M::T delta_axle, typename M::T vy, typename M::T om,
                                                      typename M::T inv_vh) {
     using T = typename M::T;
-    const T alpha = delta_axle - M::atan_((vy + l * om) * inv_vh);
+    const T alpha = delta_axle - M::atan_slip_((vy + l * om) * inv_vh);
     return M::sin_rev(V.Cs * M::atan_(V.B * alpha));
 }
 

@@ -230,3 +230,58 @@ def test_batched_graph_plan_matches_oracle_lockstep(planner):
     plan.close()
     print(f"identical choices {exact} of {total}")
     assert exact >= total // 2
+
+
+def test_full_batch_in_the_timed_configuration_matches_oracle_on_sampled_races():
+    """The 256-race batch at full size (K up to 65536, 1535 vehicles) planned the way the
+    benchmark times it -- one workgroup per tile, two samples per lane, the planning step
+    and the closed-loop advance captured in a hipGraph -- for one step; four races spread
+    over the batch (2 vehicles at K = 65536, 10 vehicles, a 20-step horizon, the last race)
+    are replayed by the oracle's Alg. 1 in lockstep: every choice agrees or is a near-tie,
+    and the first controls, warm starts, trajectories, progress and advanced states match."""
+    import torch
+    import oracle
+    import parity as PY
+    import paper_2607_25388_amd.sgtp as sg
+    tracks, races, specs, params = inputs.batched_workload(256)
+    p = sg.Planner(max_agents_total=2048, max_races=256)
+    try:
+        for N, tr in tracks.items():
+            p.upload_track(TRACK_ID[N], tr)
+        rts = [sg.race_from_inputs(rc, TRACK_ID[sp["N"]], sp["K"], sp["N"], inputs.n_tail_from_fraction(0.3, sp["N"]))
+               for rc, sp in zip(races, specs)]
+        L = 5
+        plan = p.plan(params, rts, L, sg.plan_options(persistent=0, tiles_per_fetch=1, samples_per_lane=2,
+                                                      use_graph=1, include_advance=1))
+        plan.run()
+        torch.cuda.synchronize()
+        gtr_all = plan.choices().copy()
+        u_all = plan.u_apply.cpu().numpy().astype(np.float64)
+        plan.close()
+        offs = np.concatenate([[0], np.cumsum([rc.n_agents for rc in races])])
+        sample = [102, 58, 74, 255]
+        assert specs[102]["K"] == 65536 and specs[58]["n_agents"] == 10 and specs[74]["N"] == 20
+        exact = total = 0
+        for r in sample:
+            rc, sp, rt = races[r], specs[r], rts[r]
+            n, N, K = rc.n_agents, sp["N"], sp["K"]
+            label = f"race {r} (n={n}, N={N}, K={K})"
+            print(label, flush=True)
+            base = int(offs[r])
+            pr = dict(params, N=N, n_tail=inputs.n_tail_from_fraction(0.3, N))
+            gtr = gtr_all[:, base:base + n]
+            forced = PY.forced_from_trace(gtr, L, n, rc.ego)
+            ref = oracle.Oracle(tracks[N], pr).plan_step(rc, L, K=K, forced=forced, plan_step=0)
+            exact += PY.check_lockstep(gtr, ref, forced, label)
+            total += int((forced >= 0).sum())
+            np.testing.assert_allclose(u_all[base:base + n], ref["u_apply"], atol=1e-5, err_msg=label)
+            np.testing.assert_allclose(rt.u_nom.cpu().numpy(), ref["u_next"], atol=1e-5, err_msg=label)
+            traj = rt.traj.cpu().numpy()
+            assert np.max(np.abs(traj[:, :, :2] - ref["traj"][:, :, :2])) < PY.TOL_STATE, label
+            np.testing.assert_allclose(rt.s_abs.cpu().numpy(), ref["s_abs"], atol=1e-6, err_msg=label)
+            x_ref = oracle.Oracle(tracks[N], _p32(pr)).advance(rc.x, u_all[base:base + n])
+            np.testing.assert_allclose(rt.x.cpu().numpy(), x_ref, rtol=0, atol=1e-9, err_msg=label)
+        print(f"identical choices {exact} of {total}")
+        assert exact >= total // 2
+    finally:
+        p.close()
