@@ -42,9 +42,14 @@ constexpr size_t P_W1 = 0, P_B1 = P_W1 + (size_t)D_IN * D_H, P_W2 = P_B1 + D_H, 
 // ------------------------------------------------------------------------------
 // BF16 MFMA GEMM: C[m][n] = sum_k A(m, k) B(k, n) (+ bias[n]); optional GELU copy in BF16.
 // A(m, k) = A[m a_m + k a_k], B(k, n) = B[k b_k + n b_n] (any strides, so transposed
-// operands need no copies).  Workgroup tile 64 x 64, K step 32; each of the 4 waves owns
-// a 32 x 32 quarter as 2 x 2 MFMA tiles of 16 x 16 x 32.  Fragments of A and B use the
-// same lane -> k assignment, so the product does not depend on the k order inside a step.
+// operands need no copies).  Workgroup tile 64 x 64; each of the 4 waves owns a 32 x 32
+// quarter as 2 x 2 MFMA tiles of 16 x 16 x 32.  K runs in chunks of 64 through two LDS
+// buffers: the global loads of the next chunk are issued before the MFMAs of the current
+// one.  An operand whose unit stride runs along k is read as 16-byte vectors of 8 k; one
+// whose unit stride runs along its rows (a transposed operand) as vectors of 8 rows,
+// scattered into the [row][k] LDS layout.  The MFMAs take the 32-k blocks in increasing
+// order with the same lane -> (row, k) map whatever the staging, so the sums do not
+// depend on it (the fused forward below relies on this).
 // ------------------------------------------------------------------------------
 struct GemmArgs {
     const bf16 *A;
@@ -56,9 +61,76 @@ struct GemmArgs {
     float *C;           // [M][ldc] float32 result (pre-activation), or NULL
     long long ldc;
     long long c_split;  // split K: slice z writes its partial product to C + z c_split
-    bf16 *H;            // [M][ldh] BF16 GELU(result), or NULL
+    bf16 *H;            // [M][ldh] BF16 GELU(result) -- or, with gpre, BF16 result x GELU'(gpre) -- or NULL
     long long ldh;
+    const float *gpre;  // [M][ldh] pre-activations for the activation-gradient output, or NULL
+    int a_mode, b_mode; // operand staging: STAGE_ELEM, STAGE_VEC_K or STAGE_VEC_ROW
+    int ones_row;       // row index of A that reads as 1 for every k (a bias gradient), or -1
 };
+
+constexpr int STAGE_ELEM = 0, STAGE_VEC_K = 1, STAGE_VEC_ROW = 2;
+constexpr int GK = 64;          // K per LDS chunk
+constexpr int LROW = GK + 8;    // LDS row in bf16 (144 bytes: 16-byte aligned, banks staggered)
+
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+// Registers of one operand chunk (64 rows x GK k): two 8-element vectors per thread.
+// Vector q = tid + 256 i covers, for STAGE_ELEM / STAGE_VEC_K, row q / 8 and k 8 (q % 8)
+// .. + 7; for STAGE_VEC_ROW, k q / 8 and rows 8 (q % 8) .. + 7.  Op(r, k) = P[r s_r +
+// k s_k] for r < R and k < kend, zero beyond; row `ones` reads as 1 (for k < kend).
+__device__ __forceinline__ void load_chunk(const bf16 *__restrict__ P, long long s_r, long long s_k, int mode, int r0,
+                                           int R, int k0, int kend, int ones, int tid, u16x8 (&v)[2]) {
+    const unsigned short ONE = 0x3F80;  // bf16 1.0
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int q = tid + 256 * i;
+        u16x8 x;
+        if (mode == STAGE_VEC_ROW) {
+            const int k = k0 + (q >> 3), r = r0 + 8 * (q & 7);
+            if (r + 8 <= R && k < kend) {
+                x = *(const u16x8 *)&P[(long long)r * s_r + (long long)k * s_k];
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int rr = r + j;
+                    x[j] = (k >= kend) ? (unsigned short)0
+                           : (rr == ones) ? ONE
+                           : (rr < R) ? __builtin_bit_cast(unsigned short, P[(long long)rr * s_r + (long long)k * s_k])
+                                      : (unsigned short)0;
+                }
+            }
+        } else {
+            const int r = r0 + (q >> 3), k = k0 + 8 * (q & 7);
+            if (mode == STAGE_VEC_K && r < R && r != ones && k + 8 <= kend) {
+                x = *(const u16x8 *)&P[(long long)r * s_r + k];
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int kk = k + j;
+                    x[j] = (kk >= kend) ? (unsigned short)0
+                           : (r == ones) ? ONE
+                           : (r < R) ? __builtin_bit_cast(unsigned short, P[(long long)r * s_r + (long long)kk * s_k])
+                                     : (unsigned short)0;
+                }
+            }
+        }
+        v[i] = x;
+    }
+}
+
+__device__ __forceinline__ void store_chunk(bf16 (*S)[LROW], int mode, int tid, const u16x8 (&v)[2]) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int q = tid + 256 * i;
+        if (mode == STAGE_VEC_ROW) {
+            const int k = q >> 3, r = 8 * (q & 7);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) *(unsigned short *)&S[r + j][k] = v[i][j];
+        } else {
+            *(u16x8 *)&S[q >> 3][8 * (q & 7)] = v[i];
+        }
+    }
+}
 
 __device__ __forceinline__ float gelu_f(float x) {
     const float c = 0.7978845608f;
@@ -72,8 +144,8 @@ __device__ __forceinline__ float gelu_grad_f(float x) {
 }
 
 __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
-    __shared__ __align__(16) bf16 As[64][40];  // [m][k], row padded to 80 bytes
-    __shared__ __align__(16) bf16 Bs[64][40];  // [n][k]
+    __shared__ __align__(16) bf16 As[2][64][LROW];  // [buffer][m][k]
+    __shared__ __align__(16) bf16 Bs[2][64][LROW];  // [buffer][n][k]
     const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
@@ -82,37 +154,45 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
-    // split K: slice z of gridDim.z covers [kbeg, kend) and writes its partial product to its
-    // own slice of C (summed afterwards in slice order: the result does not depend on timing)
+    // split K: slice z of gridDim.z covers [kbeg, kend) (a multiple of 32 long, but the
+    // last) and writes its partial product to its own slice of C (summed afterwards in
+    // slice order: the result does not depend on timing)
     const int kslice = ((g.K + 32 * gridDim.z - 1) / (32 * gridDim.z)) * 32;
     const int kbeg = blockIdx.z * kslice, kend = min(g.K, kbeg + kslice);
-    for (int k0 = kbeg; k0 < kend; k0 += 32) {
-        // staging walks the operand's unit-stride index across consecutive lanes
-        for (int e = tid; e < 64 * 32; e += 256) {
-            int r = e >> 5, c = e & 31;
-            if (g.a_k != 1) r = e & 63, c = e >> 6;
-            const int m = m0 + r, k = k0 + c;
-            As[r][c] = (m < g.M && k < kend) ? g.A[(long long)m * g.a_m + (long long)k * g.a_k] : (bf16)0.0f;
-        }
-        for (int e = tid; e < 64 * 32; e += 256) {
-            int r = e >> 5, c = e & 31;
-            if (g.b_k != 1) r = e & 63, c = e >> 6;
-            const int n = n0 + r, k = k0 + c;
-            Bs[r][c] = (n < g.N && k < kend) ? g.B[(long long)k * g.b_k + (long long)n * g.b_n] : (bf16)0.0f;
-        }
+    const int nk = kend > kbeg ? (kend - kbeg + GK - 1) / GK : 0;
+    u16x8 va[2], vb[2];
+    if (nk > 0) {
+        load_chunk(g.A, g.a_m, g.a_k, g.a_mode, m0, g.M, kbeg, kend, g.ones_row, tid, va);
+        load_chunk(g.B, g.b_n, g.b_k, g.b_mode, n0, g.N, kbeg, kend, -1, tid, vb);
+    }
+    const int kk = 8 * (l >> 4);
+    for (int it = 0; it < nk; ++it) {
+        const int buf = it & 1;
+        store_chunk(As[buf], g.a_mode, tid, va);
+        store_chunk(Bs[buf], g.b_mode, tid, vb);
         __syncthreads();
-        bf16x8 a[2], b[2];
-        const int kk = 8 * (l >> 4);
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            a[i] = *(const bf16x8 *)&As[wm + 16 * i + (l & 15)][kk];
-            b[i] = *(const bf16x8 *)&Bs[wn + 16 * i + (l & 15)][kk];
+        const int k0 = kbeg + it * GK;
+        if (it + 1 < nk) {  // next chunk's loads in flight during this chunk's MFMAs
+            load_chunk(g.A, g.a_m, g.a_k, g.a_mode, m0, g.M, k0 + GK, kend, g.ones_row, tid, va);
+            load_chunk(g.B, g.b_n, g.b_k, g.b_mode, n0, g.N, k0 + GK, kend, -1, tid, vb);
         }
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int ks = 0; ks < GK; ks += 32) {
+            if (k0 + ks >= kend) break;  // no all-zero block beyond the slice (same blocks as K steps of 32)
+            bf16x8 a[2], b[2];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-        __syncthreads();
+            for (int i = 0; i < 2; ++i) {
+                a[i] = *(const bf16x8 *)&As[buf][wm + 16 * i + (l & 15)][ks + kk];
+                b[i] = *(const bf16x8 *)&Bs[buf][wn + 16 * i + (l & 15)][ks + kk];
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        // the buffer written at iteration it + 2 is read here: the barrier of iteration
+        // it + 1 separates the two
     }
     // D(16 x 16) of one MFMA: lane l, element v -> row 4 (l / 16) + v, column l % 16
 #pragma unroll
@@ -131,7 +211,9 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
                     }
                     if (g.bias) x += g.bias[n];
                     if (g.C) g.C[(long long)m * g.ldc + n] = x;
-                    if (g.H) g.H[(long long)m * g.ldh + n] = (bf16)gelu_f(x);
+                    if (g.H)
+                        g.H[(long long)m * g.ldh + n] =
+                            g.gpre ? (bf16)(x * gelu_grad_f(g.gpre[(long long)m * g.ldh + n])) : (bf16)gelu_f(x);
                 }
             }
 }
@@ -267,34 +349,19 @@ __global__ void k_nll(const float *out, int ldo, const float *U, int B, int N, f
     if ((threadIdx.x & 63) == 0) loss_part[e >> 6] = contrib;
 }
 
-// dpre = dh * gelu'(pre) as BF16
-__global__ void k_gelu_back(const float *dh, const float *pre, int n, bf16 *dpre) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n) dpre[e] = (bf16)(dh[e] * gelu_grad_f(pre[e]));
-}
-
-// column sums of a BF16 [B][ld] matrix over slices of 256 rows (bias gradients): block y
-// writes the sums of its slice to part[y][ncols]; k_sum_slices adds the slices in order
-__global__ void k_colsum(const bf16 *D, int B, int ld, int ncols, float *part) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncols) return;
-    const int b0 = blockIdx.y * 256, b1 = min(B, b0 + 256);
-    float s = 0.0f;
-    for (int b = b0; b < b1; ++b) s += (float)D[(long long)b * ld + c];
-    part[(long long)blockIdx.y * ncols + c] = s;
-}
-
 // dst[r][c] (row stride ldd) = sum over z = 0 .. n_slices-1, in that order, of
-// src[z][r][c] (slice stride zs, row stride lds), for r < rows, c < cols
+// src[z][r][c] (slice stride zs, row stride lds), for r < rows, c < cols; with dst_last,
+// the last row goes to dst_last[c] instead (a bias gradient computed as an extra row)
 __global__ void k_sum_slices(const float *src, int n_slices, long long zs, int rows, int cols, int lds, float *dst,
-                             int ldd) {
+                             int ldd, float *dst_last) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= rows * cols) return;
     const int r = e / cols, c = e % cols;
     const float *p = src + (long long)r * lds + c;
     float s = p[0];
     for (int z = 1; z < n_slices; ++z) s += p[z * zs];
-    dst[(long long)r * ldd + c] = s;
+    if (dst_last && r == rows - 1) dst_last[c] = s;
+    else dst[(long long)r * ldd + c] = s;
 }
 
 // loss = (sum of the per-wave partials, in a fixed order) / B: one block of 256 threads
@@ -313,8 +380,33 @@ __global__ void k_loss_total(const float *part, int n, int B, float *loss) {
 
 // Adam step number t = *t_prev + 1 read on the device (so a captured training step can be
 // replayed); k_step_count advances it after the step
+// The new master weight is also written to the BF16 operand copies (plain and transposed;
+// their padding stays zero), as k_refresh_bf16 and k_refresh_bf16_t would.
+struct Bf16Copies {
+    bf16 *W1, *W2, *W3, *W1T, *W2T, *W3T;
+    float *b3p;
+};
+__device__ __forceinline__ void write_copies(const Bf16Copies &w, size_t e, float p) {
+    const bf16 h = (bf16)p;
+    if (e < P_B1) {
+        const size_t k = e / D_H, n = e % D_H;
+        w.W1[e] = h;
+        w.W1T[n * D_INP + k] = h;
+    } else if (e >= P_W2 && e < P_B2) {
+        const size_t f = e - P_W2, k = f / D_H, n = f % D_H;
+        w.W2[f] = h;
+        w.W2T[n * D_H + k] = h;
+    } else if (e >= P_W3 && e < P_B3) {
+        const size_t f = e - P_W3, k = f / D_OUT, n = f % D_OUT;
+        w.W3[k * D_OUTP + n] = h;
+        w.W3T[n * D_H + k] = h;
+    } else if (e >= P_B3) {
+        w.b3p[e - P_B3] = p;
+    }
+}
+
 __global__ void k_adam(float *P, const float *G, float *m, float *v, int n, float lr, float b1, float b2, float eps,
-                       const int *t_prev) {
+                       const int *t_prev, Bf16Copies copies) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     const float t = (float)(*t_prev + 1);
@@ -324,7 +416,9 @@ __global__ void k_adam(float *P, const float *G, float *m, float *v, int n, floa
     const float vv = b2 * v[e] + (1.0f - b2) * g * g;
     m[e] = mm;
     v[e] = vv;
-    P[e] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+    const float p = P[e] - lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+    P[e] = p;
+    write_copies(copies, (size_t)e, p);
 }
 
 __global__ void k_step_count(int *t) {
@@ -341,9 +435,8 @@ struct sgtp_mlp {
     bf16 *W1T = nullptr, *W2T = nullptr, *W3T = nullptr;           // transposed (fused forward)
     float *b3p = nullptr;
     bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *D = nullptr, *D2 = nullptr, *D1 = nullptr;
-    float *PRE1 = nullptr, *PRE2 = nullptr, *OUT = nullptr, *DH = nullptr, *loss = nullptr;
-    float *PART = nullptr;  // split-K partial products of the weight gradients [64][256][256]
-    float *CS = nullptr;    // bias-gradient partial sums [ceil(B_max / 256)][256]
+    float *PRE1 = nullptr, *PRE2 = nullptr, *OUT = nullptr, *loss = nullptr;
+    float *PART = nullptr;  // split-K partial products of the weight and bias gradients [64][257][256]
     float *LP = nullptr;    // per-wave loss partials [2 B_max + 4]
     int *adam_t = nullptr;  // device: Adam steps taken
     int last_B = 0;  // rows of the last sgtp_mlp_grad (its workspace tensors stay until the next call)
@@ -361,33 +454,40 @@ int mfail(sgtp_mlp *m, int code, const std::string &s) {
         if (e_ != hipSuccess) return mfail(m, SGTP_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-void gemm(hipStream_t st, const bf16 *A, long long a_m, long long a_k, const bf16 *B, long long b_k, long long b_n,
-          int M, int N, int K, const float *bias, float *C, long long ldc, bf16 *H, long long ldh) {
-    GemmArgs g{A, a_m, a_k, B, b_k, b_n, M, N, K, bias, C, ldc, 0, H, ldh};
-    hipLaunchKernelGGL(k_gemm_bf16, dim3((N + 63) / 64, (M + 63) / 64, 1), dim3(256), 0, st, g);
-}
-
-// weight gradient dst[M][ldd] (first N columns) = A B with K split into `splits` slices:
-// partial products into m->PART, summed in slice order
-void gemm_wgrad(sgtp_mlp *m, hipStream_t st, const bf16 *A, long long a_m, long long a_k, const bf16 *B, long long b_k,
-                long long b_n, int M, int N, int K, float *dst, int ldd, int splits) {
-    GemmArgs g{A, a_m, a_k, B, b_k, b_n, M, N, K, nullptr, m->PART, N, (long long)M * N, nullptr, 0};
-    hipLaunchKernelGGL(k_gemm_bf16, dim3((N + 63) / 64, (M + 63) / 64, splits), dim3(256), 0, st, g);
-    hipLaunchKernelGGL(k_sum_slices, dim3((M * N + 255) / 256), dim3(256), 0, st, m->PART, splits, (long long)M * N, M,
-                       N, N, dst, ldd);
-}
-
-// bias gradient dst[ncols] = column sums of the BF16 [B][ld] matrix D, in a fixed order
-void bias_grad(sgtp_mlp *m, hipStream_t st, const bf16 *D, int B, int ld, int ncols, float *dst) {
-    const int rb = (B + 255) / 256;
-    hipLaunchKernelGGL(k_colsum, dim3((ncols + 255) / 256, rb), dim3(256), 0, st, D, B, ld, ncols, m->CS);
-    hipLaunchKernelGGL(k_sum_slices, dim3((ncols + 255) / 256), dim3(256), 0, st, m->CS, rb, (long long)ncols, 1,
-                       ncols, ncols, dst, ncols);
-}
-
 // K split of a weight-gradient product (K = batch): about 512 rows per slice, at most 64 slices
 constexpr int MAX_SPLITS = 64;
 int k_splits(int K) { return std::max(1, std::min(MAX_SPLITS, (K + 511) / 512)); }
+
+// staging of an operand with element strides (s_r along its rows, s_k along k): 16-byte
+// vectors where the unit stride and the alignment allow them
+int stage_mode(const void *P, long long s_r, long long s_k) {
+    if (((uintptr_t)P & 15) != 0) return STAGE_ELEM;
+    if (s_k == 1 && s_r % 8 == 0) return STAGE_VEC_K;
+    if (s_r == 1 && s_k % 8 == 0) return STAGE_VEC_ROW;
+    return STAGE_ELEM;
+}
+
+// H output: BF16 GELU(C), or with gpre BF16 C x GELU'(gpre) (an activation gradient)
+void gemm(hipStream_t st, const bf16 *A, long long a_m, long long a_k, const bf16 *B, long long b_k, long long b_n,
+          int M, int N, int K, const float *bias, float *C, long long ldc, bf16 *H, long long ldh,
+          const float *gpre = nullptr) {
+    GemmArgs g{A, a_m, a_k, B, b_k, b_n, M, N, K, bias, C, ldc, 0, H, ldh, gpre,
+               stage_mode(A, a_m, a_k), stage_mode(B, b_n, b_k), -1};
+    hipLaunchKernelGGL(k_gemm_bf16, dim3((N + 63) / 64, (M + 63) / 64, 1), dim3(256), 0, st, g);
+}
+
+// weight gradient dst[M][ldd] (first N columns) = A B and bias gradient bias_dst[N] =
+// column sums of B, as one product with an extra row of ones in A, K split into `splits`
+// slices: partial products into m->PART, summed in slice order
+void gemm_wgrad(sgtp_mlp *m, hipStream_t st, const bf16 *A, long long a_m, long long a_k, const bf16 *B, long long b_k,
+                long long b_n, int M, int N, int K, float *dst, int ldd, float *bias_dst, int splits) {
+    const int R = M + 1;  // row M of A reads as 1: the bias gradient
+    GemmArgs g{A, a_m, a_k, B, b_k, b_n, R, N, K, nullptr, m->PART, N, (long long)R * N, nullptr, 0, nullptr,
+               stage_mode(A, a_m, a_k), stage_mode(B, b_n, b_k), M};
+    hipLaunchKernelGGL(k_gemm_bf16, dim3((N + 63) / 64, (R + 63) / 64, splits), dim3(256), 0, st, g);
+    hipLaunchKernelGGL(k_sum_slices, dim3((R * N + 255) / 256), dim3(256), 0, st, m->PART, splits, (long long)R * N, R,
+                       N, N, dst, ldd, bias_dst);
+}
 
 // forward of B rows (features float32 [B][ldx]) into out[B][ldo], n_out columns (200, or
 // 256 with the zero padding for the loss)
@@ -436,9 +536,7 @@ int sgtp_mlp_create(int B_max, sgtp_mlp **out) {
     al((void **)&m->PRE1, (size_t)B_max * D_H * 4);
     al((void **)&m->PRE2, (size_t)B_max * D_H * 4);
     al((void **)&m->OUT, (size_t)B_max * D_OUTP * 4);
-    al((void **)&m->DH, (size_t)B_max * D_H * 4);
-    al((void **)&m->PART, (size_t)MAX_SPLITS * D_H * D_OUTP * 4);
-    al((void **)&m->CS, (size_t)((B_max + 255) / 256) * D_OUTP * 4);
+    al((void **)&m->PART, (size_t)MAX_SPLITS * (D_H + 1) * D_OUTP * 4);
     al((void **)&m->LP, (size_t)(2 * B_max + 4) * 4);
     al((void **)&m->adam_t, 4);
     al((void **)&m->loss, 4);
@@ -454,8 +552,8 @@ int sgtp_mlp_destroy(sgtp_mlp *m) {
     if (!m) return SGTP_EINVAL;
     (void)hipDeviceSynchronize();
     void *bufs[] = {m->P,  m->G,  m->Mm, m->Vv,   m->W1,   m->W2,  m->W3, m->b3p, m->X,    m->H1,   m->H2,
-                    m->D,  m->D1, m->PRE1, m->PRE2, m->OUT, m->DH, m->PART, m->loss, m->W1T, m->W2T, m->W3T,
-                    m->D2, m->CS, m->LP, m->adam_t};
+                    m->D,  m->D1, m->PRE1, m->PRE2, m->OUT, m->PART, m->loss, m->W1T, m->W2T, m->W3T,
+                    m->D2, m->LP, m->adam_t};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete m;
@@ -518,19 +616,14 @@ int sgtp_mlp_grad(sgtp_mlp *m, const float *X, const float *U, int B, int N, flo
     hipLaunchKernelGGL(k_nll, dim3(nll_blocks), dim3(256), 0, st, m->OUT, D_OUTP, U, B, N, sig_a, sig_d, m->D, D_OUTP,
                        m->LP);
     hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, st, m->LP, 4 * nll_blocks, B, m->loss);
-    // layer 3: gW3 = H2^T D, gb3 = column sums of D, dH2 = D W3^T
-    gemm_wgrad(m, st, m->H2, 1, D_H, m->D, D_OUTP, 1, D_H, D_OUT, B, m->G + P_W3, D_OUT, sp);
-    bias_grad(m, st, m->D, B, D_OUTP, D_OUT, m->G + P_B3);
-    gemm(st, m->D, D_OUTP, 1, m->W3, 1, D_OUTP, B, D_H, D_OUTP, nullptr, m->DH, D_H, nullptr, 0);
-    hipLaunchKernelGGL(k_gelu_back, dim3((B * D_H + 255) / 256), dim3(256), 0, st, m->DH, m->PRE2, B * D_H, m->D2);
+    // layer 3: gW3 = H2^T D and gb3 = column sums of D (one product), dH2 = D W3^T
+    gemm_wgrad(m, st, m->H2, 1, D_H, m->D, D_OUTP, 1, D_H, D_OUT, B, m->G + P_W3, D_OUT, m->G + P_B3, sp);
+    gemm(st, m->D, D_OUTP, 1, m->W3, 1, D_OUTP, B, D_H, D_OUTP, nullptr, nullptr, 0, m->D2, D_H, m->PRE2);
     // layer 2: gW2 = H1^T D2, gb2, dH1 = D2 W2^T
-    gemm_wgrad(m, st, m->H1, 1, D_H, m->D2, D_H, 1, D_H, D_H, B, m->G + P_W2, D_H, sp);
-    bias_grad(m, st, m->D2, B, D_H, D_H, m->G + P_B2);
-    gemm(st, m->D2, D_H, 1, m->W2, 1, D_H, B, D_H, D_H, nullptr, m->DH, D_H, nullptr, 0);
-    hipLaunchKernelGGL(k_gelu_back, dim3((B * D_H + 255) / 256), dim3(256), 0, st, m->DH, m->PRE1, B * D_H, m->D1);
+    gemm_wgrad(m, st, m->H1, 1, D_H, m->D2, D_H, 1, D_H, D_H, B, m->G + P_W2, D_H, m->G + P_B2, sp);
+    gemm(st, m->D2, D_H, 1, m->W2, 1, D_H, B, D_H, D_H, nullptr, nullptr, 0, m->D1, D_H, m->PRE1);
     // layer 1: gW1 = X^T D1, gb1
-    gemm_wgrad(m, st, m->X, 1, D_INP, m->D1, D_H, 1, D_IN, D_H, B, m->G + P_W1, D_H, sp);
-    bias_grad(m, st, m->D1, B, D_H, D_H, m->G + P_B1);
+    gemm_wgrad(m, st, m->X, 1, D_INP, m->D1, D_H, 1, D_IN, D_H, B, m->G + P_W1, D_H, m->G + P_B1, sp);
     MCHK(m, hipGetLastError());
     m->last_B = B;
     if (loss) MCHK(m, hipMemcpyAsync(loss, m->loss, 4, hipMemcpyDeviceToDevice, st));
@@ -559,12 +652,9 @@ int sgtp_mlp_workspace(sgtp_mlp *m, int which, void *dst, void *stream) {
 int sgtp_mlp_adam(sgtp_mlp *m, float lr, float beta1, float beta2, float eps, void *stream) {
     if (!m) return SGTP_EINVAL;
     hipStream_t st = (hipStream_t)stream;
+    const Bf16Copies copies{m->W1, m->W2, m->W3, m->W1T, m->W2T, m->W3T, m->b3p};
     hipLaunchKernelGGL(k_adam, dim3((P_TOTAL + 255) / 256), dim3(256), 0, st, m->P, m->G, m->Mm, m->Vv, (int)P_TOTAL,
-                       lr, beta1, beta2, eps, m->adam_t);
-    hipLaunchKernelGGL(k_refresh_bf16, dim3((D_H * D_OUTP + 255) / 256), dim3(256), 0, st, m->P, m->W1, m->W2, m->W3,
-                       m->b3p);
-    hipLaunchKernelGGL(k_refresh_bf16_t, dim3((D_H * D_H + 255) / 256), dim3(256), 0, st, m->P, m->W1T, m->W2T,
-                       m->W3T);
+                       lr, beta1, beta2, eps, m->adam_t, copies);
     hipLaunchKernelGGL(k_step_count, dim3(1), dim3(64), 0, st, m->adam_t);
     MCHK(m, hipGetLastError());
     return SGTP_OK;

@@ -172,6 +172,19 @@ struct LaunchArgs {
 // ------------------------------------------------------------------------------
 // Noise: Philox4x32-10 and the float32 Box-Muller transform
 // ------------------------------------------------------------------------------
+// a ^ b ^ k with k wave-uniform (a scalar register), one v_bitop3 (truth table 0x96); the
+// compiler keeps two separate xors when one operand is scalar
+__device__ __forceinline__ uint32_t xor3_uniform(uint32_t a, uint32_t b, uint32_t k) {
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
+// Philox4x32-10 (Salmon et al., SC'11).  BITOP3: each round's two three-way xors as one
+// instruction each (the keys are wave-uniform: every caller passes the race's seed); the
+// throughput kernels take it, the latency variants measured faster with plain xors.  Same
+// values either way.
+template <bool BITOP3 = false>
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
@@ -184,8 +197,12 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
         }
         const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
-                       (uint32_t)p0);
+        if constexpr (BITOP3)
+            c = make_uint4(xor3_uniform((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1,
+                           xor3_uniform((uint32_t)(p0 >> 32), c.w, k1), (uint32_t)p0);
+        else
+            c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+                           (uint32_t)p0);
     }
     return c;
 }
@@ -1013,7 +1030,8 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const B
     for (int tau = 0; tau < bs.N; ++tau) {
         float2 z;
         if ((tau & 1) == 0) {
-            const uint4 r = philox4x32_10(make_uint4(k, (uint32_t)(tau >> 1), bs.ctr2, bs.ctr3), bs.key0, bs.key1);
+            const uint4 r = philox4x32_10<NPF == 0 && LPS == 1>(make_uint4(k, (uint32_t)(tau >> 1), bs.ctr2, bs.ctr3),
+                                                                bs.key0, bs.key1);
             if constexpr (LPS == 2) {
                 const float2 g = gauss_pair(rear ? r.z : r.x, rear ? r.w : r.y);
                 const float2 go = make_float2(dpp_swap_f32(g.x), dpp_swap_f32(g.y));
@@ -1752,6 +1770,21 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(LaunchArgs A) {
     BlockState bs;
     stage_block<NDISC>(A, item, bs, lds);
     sweep_tile<MODEL, NDISC, MAXOPP, NPF, LPS, SPL>(A, tile, item, bs, lds, &s_last);
+}
+
+// The same with the throughput code (one lane per sample, no read-ahead) held to five
+// waves per SIMD: 96 VGPRs with a few values spilled outside the step loop, measured 1.2 %
+// faster on the 256-race batch and the large field than the four waves its register use
+// gives by itself.
+template <int MODEL, int NDISC, int MAXOPP>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) k_sweep_tp(LaunchArgs A) {
+    extern __shared__ __align__(16) char lds[];
+    __shared__ int s_last;
+    const int tile = blockIdx.x;
+    const int item = find_item(A.items, A.n_items, tile);
+    BlockState bs;
+    stage_block<NDISC>(A, item, bs, lds);
+    sweep_tile<MODEL, NDISC, MAXOPP, 0, 1, 0>(A, tile, item, bs, lds, &s_last);
 }
 
 // Persistent sweep: a fixed grid of workgroups pulls chunks of tiles from NQ queues
@@ -2678,7 +2711,7 @@ void launch_sweep_t(const LaunchArgs &A, int grid, hipStream_t st, int *occ) {
             hipLaunchKernelGGL((k_sweep<MODEL, NDISC, MAXOPP <= 3 ? MAXOPP : 3, 6>), dim3(A.n_tiles), dim3(BLOCK),
                                A.L.total, st, A);
         else
-            hipLaunchKernelGGL((k_sweep<MODEL, NDISC, MAXOPP>), dim3(A.n_tiles), dim3(BLOCK), A.L.total, st, A);
+            hipLaunchKernelGGL((k_sweep_tp<MODEL, NDISC, MAXOPP>), dim3(A.n_tiles), dim3(BLOCK), A.L.total, st, A);
     } else {
         hipLaunchKernelGGL((k_sweep_persistent<MODEL, NDISC, MAXOPP>), dim3(grid), dim3(BLOCK), A.L.total, st, A);
     }

@@ -164,6 +164,36 @@ def test_training_step_graph_replays_match_eager_steps():
     mb.close()
 
 
+def test_adam_updates_the_bf16_operand_copies():
+    """After Adam steps (which write the BF16 operand copies as they update the master
+    weights), the network computes exactly what a fresh network given the same master
+    weights computes: forward passes through both the fused and the tiled path, and a
+    gradient call."""
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    flat, _ = _net(seed=17, scale3=3.0)
+    rng = np.random.default_rng(8)
+    X = torch.as_tensor(rng.standard_normal((4500, 50)).astype(np.float32)).cuda()
+    U = torch.as_tensor(np.stack([rng.uniform(-8, 4, (4500, 30)), rng.uniform(-0.4, 0.4, (4500, 30))], -1)
+                        .astype(np.float32)).cuda()
+    m = sg.Mlp(8192, flat)
+    for _ in range(3):
+        m.grad(X[:1000], U[:1000], 1.5, 0.08)
+        m.adam(lr=1e-2)
+    fresh = sg.Mlp(8192, m.get_params())
+    for rows in (37, 4500):
+        a, b = m.forward(X[:rows].contiguous()), fresh.forward(X[:rows].contiguous())
+        torch.cuda.synchronize()
+        assert np.array_equal(a.cpu().numpy().view(np.uint32), b.cpu().numpy().view(np.uint32)), rows
+    la, ga = m.grad(X[:2000], U[:2000], 1.5, 0.08, want_grads=True)
+    lb, gb = fresh.grad(X[:2000], U[:2000], 1.5, 0.08, want_grads=True)
+    torch.cuda.synchronize()
+    assert float(la.item()) == float(lb.item())
+    assert np.array_equal(ga.cpu().numpy().view(np.uint32), gb.cpu().numpy().view(np.uint32))
+    m.close()
+    fresh.close()
+
+
 @pytest.mark.parametrize("name", ["c2", "c3"])
 def test_features_match_oracle(planner, name):
     import torch
