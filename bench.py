@@ -30,23 +30,28 @@ sys.path.insert(0, ROOT)
 METRIC = "sample·steps/s per IBR sweep; plan latency p50/p99; learned vs plain cost"
 PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak
 
-# Hardware counters of the dominant sweep kernel of the 256-race batch (k_sweep<0, 3, 9, 0,
-# 1, 0>, one workgroup per tile of 2 x 256 samples), means over the 35 launches (5 planning
-# steps of 6 all-vehicle sweeps and 1 ego sweep) of `bench.py --workload c4 --steps 3
-# --warmup 1 --no-cpu-baseline --no-learned --no-extra --roofline-steps 1 --schedule
-# 0,0,1,2 --copy-calibration 256` under rocprofv3 --pmc (profiles/sweep_c4_counters.md).
-# HBM bytes: FETCH_SIZE 115393.1 KiB x 2.000 + WRITE_SIZE 118345.0 KiB x 1.000 per launch,
-# the factors being 256 MiB over what the same counter reads for the 256 MiB elementwise
-# copy of that run (131087.6 KiB fetched, 262144 KiB written).  FP32 FLOPs: 64 x
-# SQ_INSTS_VALU_FLOPS_FP32, which counts ADD + MUL + TRANS + 2 FMA wave instructions (checked
-# on the known-mix kernel of --counter-probe, profiles/counter_probe_fp32.md).  They
-# describe the kernel source with this SHA-256 and this schedule only; anything else
-# reports null.
+# Hardware counters of the dominant sweep kernel, means per launch over every launch of
+# that kernel in `bench.py --workload W ... --copy-calibration 256` under rocprofv3 --pmc
+# (one counter group per run; commands and tables in profiles/sweep_<W>_counters.md):
+# c4 k_sweep<0, 3, 9, 0, 1, 0> (one workgroup per tile of 2 x 256 samples), c3
+# k_sweep_persistent<0, 3, 9>, c2 k_sweep<0, 3, 3, 6, 1, 1> (split variant).  HBM bytes =
+# 2.000 x FETCH_SIZE + 1.000 x WRITE_SIZE (KiB), the factors being 256 MiB over what each
+# counter reads for the 256 MiB elementwise copy of the same runs (131087.6 KiB fetched,
+# 262144 KiB written).  FP32 FLOPs = 64 x SQ_INSTS_VALU_FLOPS_FP32, which counts ADD + MUL +
+# TRANS + 2 FMA wave instructions (checked on the known-mix kernel of --counter-probe,
+# profiles/counter_probe_fp32.md).  They describe the kernel source with this SHA-256 and
+# the listed schedule fields only; anything else reports null.
+_SRC = "5086176d57ba8f4eefd8353a750c4bfaaf6bdfa91a9b1a1b009e3a24a4155b42"
 SWEEP_COUNTERS = {
-    "c4": {"source_sha256": "f121723f393dccc4cfc2b4c9000c9c4855089091115c10a7c281d7c9c4a87df4",
-           "hbm_bytes_per_launch": (115393.086 * 1.99976 + 118345.048) * 1024.0,
-           "hw_fp32_flop_per_launch": 64 * 15129959988.5, "valu_wave_insts_per_launch": 15007320407.2,
-           "schedule": {"persistent": 0, "blocks_per_cu": 0, "tiles_per_fetch": 1, "samples_per_lane": 2}},
+    "c4": {"source_sha256": _SRC, "hbm_bytes_per_launch": (115369.775 * 1.99976 + 118307.641) * 1024.0,
+           "hw_fp32_flop_per_launch": 64 * 14136872671.3, "valu_wave_insts_per_launch": 14356466521.0,
+           "schedule": {"persistent": 0, "tiles_per_fetch": 1, "samples_per_lane": 2}},
+    "c3": {"source_sha256": _SRC, "hbm_bytes_per_launch": (4285.724 * 1.99976 + 50073.731) * 1024.0,
+           "hw_fp32_flop_per_launch": 64 * 285963049.9, "valu_wave_insts_per_launch": 293049799.2,
+           "schedule": {"persistent": 1, "tiles_per_fetch": 1, "samples_per_lane": 1}},
+    "c2": {"source_sha256": _SRC, "hbm_bytes_per_launch": (449.2 * 1.99976 + 312.0) * 1024.0,
+           "hw_fp32_flop_per_launch": 64 * 16737196.9, "valu_wave_insts_per_launch": 19671218.1,
+           "schedule": {"samples_per_lane": 1}},
 }
 
 

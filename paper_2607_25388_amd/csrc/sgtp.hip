@@ -1772,21 +1772,6 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(LaunchArgs A) {
     sweep_tile<MODEL, NDISC, MAXOPP, NPF, LPS, SPL>(A, tile, item, bs, lds, &s_last);
 }
 
-// The same with the throughput code (one lane per sample, no read-ahead) held to five
-// waves per SIMD: 96 VGPRs with a few values spilled outside the step loop, measured 1.2 %
-// faster on the 256-race batch and the large field than the four waves its register use
-// gives by itself.
-template <int MODEL, int NDISC, int MAXOPP>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) k_sweep_tp(LaunchArgs A) {
-    extern __shared__ __align__(16) char lds[];
-    __shared__ int s_last;
-    const int tile = blockIdx.x;
-    const int item = find_item(A.items, A.n_items, tile);
-    BlockState bs;
-    stage_block<NDISC>(A, item, bs, lds);
-    sweep_tile<MODEL, NDISC, MAXOPP, 0, 1, 0>(A, tile, item, bs, lds, &s_last);
-}
-
 // Persistent sweep: a fixed grid of workgroups pulls chunks of tiles from NQ queues
 // (its own first, then the others), restaging LDS only when the vehicle changes.
 // Every workgroup leaves once all queues are exhausted.
@@ -2711,7 +2696,7 @@ void launch_sweep_t(const LaunchArgs &A, int grid, hipStream_t st, int *occ) {
             hipLaunchKernelGGL((k_sweep<MODEL, NDISC, MAXOPP <= 3 ? MAXOPP : 3, 6>), dim3(A.n_tiles), dim3(BLOCK),
                                A.L.total, st, A);
         else
-            hipLaunchKernelGGL((k_sweep_tp<MODEL, NDISC, MAXOPP>), dim3(A.n_tiles), dim3(BLOCK), A.L.total, st, A);
+            hipLaunchKernelGGL((k_sweep<MODEL, NDISC, MAXOPP>), dim3(A.n_tiles), dim3(BLOCK), A.L.total, st, A);
     } else {
         hipLaunchKernelGGL((k_sweep_persistent<MODEL, NDISC, MAXOPP>), dim3(grid), dim3(BLOCK), A.L.total, st, A);
     }
