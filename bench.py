@@ -10,9 +10,9 @@ the mid-scale race (c2) and the large field (c3) as extra entries, the learned p
 against the plain sampler at the learned-proposal workload's size, and the CPU oracle
 timed on a sample of the same workload.
 
-Other workloads (--workload): c1, c2, c3 alone, c5 (learned proposal only), race
-(closed-loop race evaluation, full size), race_small (the same at the paper's scale:
-kinematic bicycle, K = 128, H = 12).
+Other workloads (--workload): c1, c2, c3 alone, c5 (learned proposal only), mlp (the
+proposal network's matrix-core timings), race (closed-loop race evaluation, full size),
+race_small (the same at the paper's scale: kinematic bicycle, K = 128, H = 12).
 """
 
 from __future__ import annotations
