@@ -263,12 +263,14 @@ def run(planner: sg.Planner, method: str, params: dict, tracks, trials, K: int, 
 
 
 def evaluate(planner, methods=METHODS, n_tracks=7, starts=6, N=None, K=None, L_ibr=None, T_max=50.0, log=None,
-             scale="full"):
+             scale="full", sigma_scale=1.0):
+    """sigma_scale multiplies the sampling scales sigma_a, sigma_d (a diagnostic ablation)."""
     sc = SCALES[scale]
     N = sc["N"] if N is None else N
     K = sc["K"] if K is None else K
     L_ibr = sc["L"] if L_ibr is None else L_ibr
     params = sc["params"](N)
+    params = dict(params, sigma_a=params["sigma_a"] * sigma_scale, sigma_d=params["sigma_d"] * sigma_scale)
     tracks, trials = make_trials(n_tracks, starts, N, length=sc["length"], width=sc["width"],
                                  spacing=sc["spacing"], track_kw=sc["track"])
     res = {}
@@ -295,13 +297,14 @@ def main():
     ap.add_argument("--L", type=int, default=None)
     ap.add_argument("--seconds", type=float, default=50.0)
     ap.add_argument("--methods", default=",".join(METHODS))
+    ap.add_argument("--sigma-scale", type=float, default=1.0, help="multiply the sampling scales (ablation)")
     a = ap.parse_args()
     n_games = a.tracks * a.starts * 3
     planner = sg.Planner(max_agents_total=n_games * 3, max_races=n_games,
                          max_K=a.K if a.K is not None else SCALES[a.scale]["K"])
     planner.enable_path_integral()
     res = evaluate(planner, a.methods.split(","), a.tracks, a.starts, a.N, a.K, a.L, a.seconds,
-                   log=lambda m: print(m, flush=True), scale=a.scale)
+                   log=lambda m: print(m, flush=True), scale=a.scale, sigma_scale=a.sigma_scale)
     planner.close()
     print(json.dumps({"race_eval": res, "config": vars(a)}), flush=True)
 
