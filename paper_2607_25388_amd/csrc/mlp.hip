@@ -87,7 +87,7 @@ __device__ __forceinline__ void load_chunk(const bf16 *__restrict__ P, long long
         u16x8 x;
         if (mode == STAGE_VEC_ROW) {
             const int k = k0 + (q >> 3), r = r0 + 8 * (q & 7);
-            if (r + 8 <= R && k < kend) {
+            if (r + 8 <= R && (ones < r || ones >= r + 8) && k < kend) {
                 x = *(const u16x8 *)&P[(long long)r * s_r + (long long)k * s_k];
             } else {
 #pragma unroll
