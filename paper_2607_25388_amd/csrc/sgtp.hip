@@ -52,6 +52,13 @@ constexpr int SPLIT_RING = 4;
 constexpr int SPLIT_AHEAD = 2;  // controls published ahead of the state being scored (2 and a
                                 // ring of 4 measured faster than 1, 3, 4 or 6 and a ring of 8)
 constexpr int SPLIT_FIN = 8;    // floats per sample handed from the dynamics to the scoring lane
+// The split variant's roles by wave: even waves integrate the dynamics, odd waves score,
+// wave 2j + 1 partnering wave 2j.  A workgroup's four waves occupy the CU's four SIMDs in
+// a fixed cyclic order, and the next workgroup resident on the same CU starts one SIMD
+// further along it (measured); with the roles in halves, two resident workgroups put two
+// dynamics chains on one SIMD, with alternating roles every SIMD holds one chain and one
+// scoring wave.  Virtual thread index: role x 128 + wave pair x 64 + lane.
+__device__ __forceinline__ int split_vt(int t) { return ((t >> 6) & 1) * (BLOCK / 2) + ((t >> 7) << 6) + (t & 63); }
 constexpr int NQ = 8;           // tile queues of the persistent sweep (one per XCD under round-robin dispatch)
 // Re-roll chunks: each lane keeps its state after every ceil(N / chunks) steps, so the
 // selected sample is re-rolled in that many pieces at once.  Latency variants (about
@@ -1131,9 +1138,9 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const B
 }
 
 // ------------------------------------------------------------------------------
-// One sample on two waves (the split variant).  A lane of the workgroup's first half
-// integrates the dynamics, the longest dependent chain of a step.  Its partner lane in
-// the second half does the rest: it draws the perturbation and clips the controls
+// One sample on two waves (the split variant).  A lane of an even wave integrates the
+// dynamics, the longest dependent chain of a step.  Its partner lane in the next (odd)
+// wave does the rest: it draws the perturbation and clips the controls
 // SPLIT_AHEAD steps ahead, projects every state onto the raceline and scores it
 // (tracking, control and rate terms, boundary, footprint distances, tail offsets), then
 // takes the terminal scoring.  Controls and states pass through LDS rings of SPLIT_RING
@@ -1153,8 +1160,9 @@ __device__ __forceinline__ SampleResult lane_sample_split(const KParams &P, cons
     constexpr int TS = BLOCK / 2;
     constexpr int NC = ncp_of<NPF>();
     static_assert(SPLIT_AHEAD + 1 <= SPLIT_RING, "a control slot is rewritten only after its state was published");
-    const int i = threadIdx.x & (TS - 1);
-    const int w = (threadIdx.x >> 6) & 1;  // wave pair
+    const int vt = split_vt(threadIdx.x);
+    const int i = vt & (TS - 1);
+    const int w = (vt >> 6) & 1;  // wave pair
     const int lane = threadIdx.x & 63;
     float4 *ring = (float4 *)(lds + L.sp_ring);    // [SPLIT_RING][TS]: X, Y, PSI, VX after the step
     float2 *uring = (float2 *)(lds + L.sp_uring);  // [SPLIT_RING][TS]: controls of the step
@@ -1582,7 +1590,8 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
     constexpr int G = SPL ? 64 : 64 / LPS;  // samples per wave (per wave pair when split) = checkpoint group
     constexpr int TS = SPL ? BLOCK / 2 : BLOCK;  // samples per pass of the workgroup (one lane each: LPS = 1)
     const bool rear = LPS == 2 && (threadIdx.x & 1);
-    const bool dyn = SPL && (int)threadIdx.x < BLOCK / 2;  // the split variant's dynamics lanes
+    const int vt = SPL ? split_vt(threadIdx.x) : (int)threadIdx.x;
+    const bool dyn = SPL && vt < BLOCK / 2;  // the split variant's dynamics lanes
     const int lane = threadIdx.x & 63;
     const bool pi = A.P.update == 1;
     const int t0 = A.items[item].tile0;
@@ -1591,7 +1600,7 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
     const int pstride = 2 * A.L.N_max + 2;
     PiAcc pa{INFINITY, 0.0f, 0.0f, 0.0f};
     for (int r = 0; r < A.spl; ++r) {
-        const uint32_t k = LPS == 1 ? (uint32_t)((local_tile * A.spl + r) * TS + (threadIdx.x & (TS - 1)))
+        const uint32_t k = LPS == 1 ? (uint32_t)((local_tile * A.spl + r) * TS + (vt & (TS - 1)))
                                     : (uint32_t)(local_tile * (BLOCK / 2) + (threadIdx.x >> 1));
         const bool valid = k < (uint32_t)bs.K;
         // (the split variant draws the perturbation on the scoring lane)
@@ -1621,10 +1630,10 @@ __device__ __forceinline__ void sweep_tile(const LaunchArgs &A, int tile, int it
             int *best = (int *)(lds + A.L.sp_sync) + 4;
             if (!dyn) {
                 const unsigned long long b = __ballot(valid && key == wmin);
-                if (lane == 0) best[(threadIdx.x >> 6) & 1] = (wmin != KEY_NONE && b) ? __builtin_ctzll(b) : -1;
+                if (lane == 0) best[(vt >> 6) & 1] = (wmin != KEY_NONE && b) ? __builtin_ctzll(b) : -1;
             }
             __syncthreads();
-            if (valid && lane == best[(threadIdx.x >> 6) & 1]) {
+            if (valid && lane == best[(vt >> 6) & 1]) {
                 float *slot = A.cp_slots + ((size_t)A.items[item].group0 + k / G) * CP_FLOATS;
                 if (dyn) {  // states on the dynamics lane; segments and score on the scoring lane
 #pragma unroll
