@@ -560,6 +560,18 @@ __device__ __forceinline__ KParams loop_params(const KParams &P_in) {
     return P;
 }
 
+// A uniform value copied into a vector register (an opaque copy).  On this hardware an
+// instruction that reads a scalar register is never issued in the same cycle as another
+// wave's instruction, while float add, multiply and fma with vector, literal or inline
+// operands are (measured with the issue counters), so the few constants the dynamics
+// read many times per step are held in vector registers where registers allow.
+template <class T>
+__device__ __forceinline__ T vreg(T v) {
+    static_assert(sizeof(T) == 4, "32-bit values only");
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 __device__ __forceinline__ VehConst<float> veh_f32(const KParams &P) {
     VehConst<float> V;
     V.lf = P.lf; V.lr = P.lr; V.kf_m = P.kf_m; V.kf_Iz = P.kf_Iz; V.kr_m = P.kr_m; V.kr_Iz = P.kr_Iz;
@@ -1006,8 +1018,6 @@ template <int MODEL, int NDISC, int MAXOPP, int NPF = 0, int LPS = 1>
 __device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const BlockState &bs, const char *lds,
                                                    const LdsLayout &L, uint32_t k, float *noise_out,
                                                    bool rear = false) {
-    // (throughput variants: parameters in single scalar registers; the latency variants,
-    // one wave per SIMD, measured faster with the compiler's own allocation)
     // parameters in single scalar registers, except in the one-lane latency variant
     // (about one wave per SIMD), which measured faster with the compiler's own allocation
     const KParams P = (NPF > 0 && LPS == 1) ? P_in : loop_params(P_in);
@@ -1015,7 +1025,12 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const B
     const float4 *xref = (const float4 *)(lds + L.xref);
     const float2 *opp = (const float2 *)(lds + L.opp);
     const float4 *nodes = (const float4 *)(lds + L.nodes);
-    const VehConst<float> V = veh_f32(P);
+    VehConst<float> V = veh_f32(P);
+    float h = P.dt;
+    if constexpr (NPF == 0 && LPS == 1) {  // throughput variants: the dynamics' hot constants
+        V.B = vreg(V.B); V.Cs = vreg(V.Cs); V.lf = vreg(V.lf); V.lr = vreg(V.lr);
+        V.kr_m = vreg(V.kr_m); V.kr_Iz = vreg(V.kr_Iz); h = vreg(h);
+    }
 
     float st[6] = {0.0f, 0.0f, 0.0f, bs.vx0, bs.vy0, bs.om0};
     int seg = bs.seg0;
@@ -1073,7 +1088,7 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const B
         using MS = typename std::conditional<NPF == 0, MathF32U, MathF32>::type;
         const StepConst<float> sc = step_const<MODEL, MS>(V, u.x, u.y);
         if constexpr (LPS == 2 && MODEL == 0) rk4_pair(V, sc, P.dt, st, rear);
-        else rk4<MODEL, MS>(V, sc, P.dt, st);
+        else rk4<MODEL, MS>(V, sc, h, st);
         Foot f;
         if constexpr (NPF > 0) f = project_ahead<NPF>(nodes, bs.W, P.max_moves, st[0], st[1], seg, ahead);
         else f = project(nodes, bs.W, P.max_moves, st[0], st[1], seg);
