@@ -459,14 +459,13 @@ __device__ __forceinline__ void deriv_rates(const VehConst<typename M::T> &V, co
     d[5] = M::fma_(Sf, c.kf5, -(Sr * V.kr_Iz));
 }
 
+// f at a state whose heading cosine and sine (cp, sp) are given
 template <int MODEL, class M>
-__device__ __forceinline__ void deriv(const VehConst<typename M::T> &V, const StepConst<typename M::T> &c,
-                                      typename M::T psi, typename M::T vx_, typename M::T vy, typename M::T om,
-                                      typename M::T d[6]) {
+__device__ __forceinline__ void deriv_cs(const VehConst<typename M::T> &V, const StepConst<typename M::T> &c,
+                                         typename M::T cp, typename M::T sp, typename M::T vx_, typename M::T vy,
+                                         typename M::T om, typename M::T d[6]) {
     using T = typename M::T;
     const T vx = M::pos_(vx_);
-    const T pr = M::to_rev(psi);
-    const T cp = M::cos_rev(pr), sp = M::sin_rev(pr);
     if (MODEL == 0) {
         const T inv_vh = M::rcp_(M::floor_(vx, V.v_eps));
         const T Fyf = tyre_force<M>(V, V.lf, c.delta, vy, om, inv_vh);
@@ -480,6 +479,14 @@ __device__ __forceinline__ void deriv(const VehConst<typename M::T> &V, const St
         d[4] = T(0);
         d[5] = T(0);
     }
+}
+
+template <int MODEL, class M>
+__device__ __forceinline__ void deriv(const VehConst<typename M::T> &V, const StepConst<typename M::T> &c,
+                                      typename M::T psi, typename M::T vx_, typename M::T vy, typename M::T om,
+                                      typename M::T d[6]) {
+    const typename M::T pr = M::to_rev(psi);
+    deriv_cs<MODEL, M>(V, c, M::cos_rev(pr), M::sin_rev(pr), vx_, vy, om, d);
 }
 
 // Value of the neighbouring lane of a pair (quad permute [1, 0, 3, 2]).
@@ -502,13 +509,17 @@ __device__ __forceinline__ void deriv_pair(const VehConst<float> &V, const StepC
 }
 
 // Classic RK4 over one interval with the control held, then v_x <- max(v_x, 0).
-template <int MODEL, class M>
+// CS: the heading's cosine and sine at the start of the interval are given (cp0, sp0: the
+// values M::cos_rev / M::sin_rev give for s[2], so the result does not change)
+template <int MODEL, class M, bool CS = false>
 __device__ __forceinline__ void rk4(const VehConst<typename M::T> &V, const StepConst<typename M::T> &c,
-                                    typename M::T h, typename M::T s[6]) {
+                                    typename M::T h, typename M::T s[6], typename M::T cp0 = typename M::T(0),
+                                    typename M::T sp0 = typename M::T(0)) {
     using T = typename M::T;
     T k1[6], k2[6], k3[6], k4[6];
     const T hh = T(0.5) * h;
-    deriv<MODEL, M>(V, c, s[2], s[3], s[4], s[5], k1);
+    if constexpr (CS) deriv_cs<MODEL, M>(V, c, cp0, sp0, s[3], s[4], s[5], k1);
+    else deriv<MODEL, M>(V, c, s[2], s[3], s[4], s[5], k1);
     deriv<MODEL, M>(V, c, s[2] + hh * k1[2], s[3] + hh * k1[3], s[4] + hh * k1[4], s[5] + hh * k1[5], k2);
     deriv<MODEL, M>(V, c, s[2] + hh * k2[2], s[3] + hh * k2[3], s[4] + hh * k2[4], s[5] + hh * k2[5], k3);
     deriv<MODEL, M>(V, c, s[2] + h * k3[2], s[3] + h * k3[3], s[4] + h * k3[4], s[5] + h * k3[5], k4);
@@ -1049,6 +1060,14 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const B
     const int C = (bs.N + NC - 1) / NC;
 
     float2 zn = make_float2(0.0f, 0.0f);  // perturbation of the odd step of a Philox call
+    // throughput variants: the heading's cosine and sine after a step (the footprint's) are
+    // the first RK4 stage's of the next step, computed once
+    constexpr bool HCS = NPF == 0 && LPS == 1;
+    float hc = 0.0f, hs = 0.0f;
+    if constexpr (HCS) {
+        hc = fast_cos(st[2]);
+        hs = fast_sin(st[2]);
+    }
     for (int tau = 0; tau < bs.N; ++tau) {
         float2 z;
         if ((tau & 1) == 0) {
@@ -1088,6 +1107,7 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const B
         using MS = typename std::conditional<NPF == 0, MathF32U, MathF32>::type;
         const StepConst<float> sc = step_const<MODEL, MS>(V, u.x, u.y);
         if constexpr (LPS == 2 && MODEL == 0) rk4_pair(V, sc, P.dt, st, rear);
+        else if constexpr (HCS) rk4<MODEL, MS, true>(V, sc, h, st, hc, hs);
         else rk4<MODEL, MS>(V, sc, h, st);
         Foot f;
         if constexpr (NPF > 0) f = project_ahead<NPF>(nodes, bs.W, P.max_moves, st[0], st[1], seg, ahead);
@@ -1101,7 +1121,12 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const B
         up = u;
         rho_bd = fminf(rho_bd, bound_term(f));
         float ch = 1.0f, sh = 0.0f;
-        if (NDISC > 1) {
+        if constexpr (HCS) {
+            hc = fast_cos(st[2]);
+            hs = fast_sin(st[2]);
+            ch = hc;
+            sh = hs;
+        } else if (NDISC > 1) {
             ch = fast_cos(st[2]);
             sh = fast_sin(st[2]);
         }
