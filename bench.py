@@ -482,6 +482,9 @@ def main():
     ap.add_argument("--counter-probe", default="", metavar="WAVES,ITERS",
                     help="only run the known-mix FP32 kernel (for checking counter formulas under rocprofv3) "
                          "and print the instruction counts it must produce")
+    ap.add_argument("--issue-probe", default="", metavar="BLOCKS,ITERS",
+                    help="only run the issue-class probe kernels (fma with vector or scalar operands, min, sin) "
+                         "for reading which instructions the SIMDs pair (SQ_ACTIVE_INST_VALU2 under rocprofv3)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed region, one elementwise copy of MIB MiB (reads and writes MIB MiB): "
                          "the reference kernel for scaling hardware byte counters")
@@ -504,6 +507,27 @@ def main():
                "fp32_flop (64 x (ADD + MUL + TRANS + 2 FMA))": 64 * waves * (5 * iters + 3)}
         print(json.dumps({"counter_probe": {"waves": waves, "iters": iters, "launches": 3,
                                             "expected_per_launch": exp}}), flush=True)
+        return
+    if args.issue_probe:
+        # four waves per SIMD at 1024 workgroups; per kind: one warm-up launch, then two timed
+        blocks, iters = (int(x) for x in args.issue_probe.split(","))
+        kinds = ("fma, vector operands", "fma, one scalar operand", "min", "sin (transcendental)")
+        out = torch.empty(256 * blocks, dtype=torch.float32, device="cuda")
+        res = {}
+        for kind, label in enumerate(kinds):
+            sg.issue_probe(kind, blocks, iters // 10, out)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record()
+            for _ in range(2):
+                sg.issue_probe(kind, blocks, iters, out)
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms = ev[0].elapsed_time(ev[1]) / 2
+            simds = 1024  # 256 CUs x 4 SIMDs
+            insts = 8.0 * iters * blocks * 4 / simds  # per SIMD
+            res[label] = {"ms": ms, "ns_per_wave_instruction_per_simd": ms * 1e6 / insts}
+        print(json.dumps({"issue_probe": {"blocks": blocks, "iters": iters, "launches_per_kind": 3,
+                                          "results": res}}), flush=True)
         return
     name = args.workload
     base = {"metric": METRIC, "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "data": "synthetic"}

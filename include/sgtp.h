@@ -377,6 +377,15 @@ int sgtp_gauss_pairs(const unsigned int *r_even, const unsigned int *r_odd, floa
  * MUL_F32 = FMA_F32 = TRANS_F32 = iters wave-instructions. */
 int sgtp_counter_probe_fp32(float *out, int n_waves, int iters, void *stream);
 
+/* Issue-class probe: n_blocks workgroups of 256 lanes (four waves); every lane runs `iters`
+ * iterations of eight independent instructions of one kind, then seven v_add_f32 and one
+ * store to out[256 n_blocks] (DEVICE).  kind 0: v_fma_f32 with vector operands, 1: v_fma_f32
+ * with one scalar operand, 2: v_min_f32, 3: v_sin_f32.  Per wave: SQ_INSTS_VALU = 8 iters +
+ * 7 (+ the store's address arithmetic).  Timed alone and read with SQ_ACTIVE_INST_VALU2 (the
+ * issue cycles in which a SIMD issued two VALU instructions), it shows which instruction
+ * forms are paired across waves.  Returns SGTP_EINVAL for a kind outside 0..3. */
+int sgtp_issue_probe(float *out, int kind, int n_blocks, int iters, void *stream);
+
 int sgtp_abi_version(void);
 
 #ifdef __cplusplus

@@ -1,6 +1,6 @@
-// probe.hip -- a kernel with a known FP32 instruction mix, for checking how the hardware
-// counters (rocprofv3 SQ_INSTS_VALU_*_F32) count the sweep kernels' work.  Instrumentation
-// of the library, not part of the planner.
+// probe.hip -- kernels with a known instruction mix, for checking how the hardware counters
+// (rocprofv3 SQ_INSTS_VALU_*) count the sweep kernels' work and which instructions the
+// SIMDs issue together.  Instrumentation of the library, not part of the planner.
 //
 // Every lane of every wave runs `iters` iterations of exactly one v_add_f32, one
 // v_mul_f32, one v_fma_f32 and one v_exp_f32 (written as inline assembly so the compiler
@@ -24,10 +24,59 @@ __global__ void __launch_bounds__(64) k_probe_fp32(float *out, int iters) {
     out[blockIdx.x * 64 + threadIdx.x] = ((a + m) + f) + e;
 }
 
+// Issue-class probe: every lane runs `iters` iterations of eight independent instructions
+// of one kind (inline assembly, scalar loop control), then combines its eight values with
+// seven v_add_f32 and stores them.  KIND 0: v_fma_f32 with vector operands; 1: v_fma_f32
+// with one scalar operand; 2: v_min_f32; 3: v_sin_f32 (a transcendental).
+template <int KIND>
+__global__ void __launch_bounds__(256) k_probe_issue(float *out, int iters) {
+    float a0 = (float)threadIdx.x * 1e-3f, a1 = a0 + 0.1f, a2 = a0 + 0.2f, a3 = a0 + 0.3f, a4 = a0 + 0.4f,
+          a5 = a0 + 0.5f, a6 = a0 + 0.6f, a7 = a0 + 0.7f;
+    const float b = 0.999999f, c = 1e-7f;
+    for (int i = 0; i < iters; ++i) {
+        if (KIND == 0) {
+            asm volatile("v_fma_f32 %0, %0, %8, %9\n v_fma_f32 %1, %1, %8, %9\n v_fma_f32 %2, %2, %8, %9\n"
+                         "v_fma_f32 %3, %3, %8, %9\n v_fma_f32 %4, %4, %8, %9\n v_fma_f32 %5, %5, %8, %9\n"
+                         "v_fma_f32 %6, %6, %8, %9\n v_fma_f32 %7, %7, %8, %9"
+                         : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7)
+                         : "v"(b), "v"(c));
+        } else if (KIND == 1) {
+            asm volatile("v_fma_f32 %0, %0, %8, %9\n v_fma_f32 %1, %1, %8, %9\n v_fma_f32 %2, %2, %8, %9\n"
+                         "v_fma_f32 %3, %3, %8, %9\n v_fma_f32 %4, %4, %8, %9\n v_fma_f32 %5, %5, %8, %9\n"
+                         "v_fma_f32 %6, %6, %8, %9\n v_fma_f32 %7, %7, %8, %9"
+                         : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7)
+                         : "s"(b), "v"(c));
+        } else if (KIND == 2) {
+            asm volatile("v_min_f32 %0, %0, %8\n v_min_f32 %1, %1, %8\n v_min_f32 %2, %2, %8\n"
+                         "v_min_f32 %3, %3, %8\n v_min_f32 %4, %4, %8\n v_min_f32 %5, %5, %8\n"
+                         "v_min_f32 %6, %6, %8\n v_min_f32 %7, %7, %8"
+                         : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7)
+                         : "v"(b));
+        } else {
+            asm volatile("v_sin_f32 %0, %0\n v_sin_f32 %1, %1\n v_sin_f32 %2, %2\n v_sin_f32 %3, %3\n"
+                         "v_sin_f32 %4, %4\n v_sin_f32 %5, %5\n v_sin_f32 %6, %6\n v_sin_f32 %7, %7\n s_nop 1"
+                         : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7));
+        }
+    }
+    out[blockIdx.x * 256 + threadIdx.x] = ((((((a0 + a1) + a2) + a3) + a4) + a5) + a6) + a7;
+}
+
 }  // namespace
 
 extern "C" int sgtp_counter_probe_fp32(float *out, int n_waves, int iters, void *stream) {
     if (!out || n_waves < 1 || iters < 0) return SGTP_EINVAL;
     hipLaunchKernelGGL(k_probe_fp32, dim3(n_waves), dim3(64), 0, (hipStream_t)stream, out, iters);
+    return hipGetLastError() == hipSuccess ? SGTP_OK : SGTP_EDEVICE;
+}
+
+extern "C" int sgtp_issue_probe(float *out, int kind, int n_blocks, int iters, void *stream) {
+    if (!out || kind < 0 || kind > 3 || n_blocks < 1 || iters < 0) return SGTP_EINVAL;
+    const hipStream_t st = (hipStream_t)stream;
+    switch (kind) {
+    case 0: hipLaunchKernelGGL(k_probe_issue<0>, dim3(n_blocks), dim3(256), 0, st, out, iters); break;
+    case 1: hipLaunchKernelGGL(k_probe_issue<1>, dim3(n_blocks), dim3(256), 0, st, out, iters); break;
+    case 2: hipLaunchKernelGGL(k_probe_issue<2>, dim3(n_blocks), dim3(256), 0, st, out, iters); break;
+    default: hipLaunchKernelGGL(k_probe_issue<3>, dim3(n_blocks), dim3(256), 0, st, out, iters); break;
+    }
     return hipGetLastError() == hipSuccess ? SGTP_OK : SGTP_EDEVICE;
 }

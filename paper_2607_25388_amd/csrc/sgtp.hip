@@ -330,17 +330,25 @@ __device__ __forceinline__ float fast_atan(float x) {
 // atan of a slip angle's argument (v_y + l om) / v_x, which stays within 1/4 in all but a
 // few samples: there an odd quintic whose coefficients are a minimax (equal-ripple) fit of
 // the absolute error on [0, 1/4] rounded to float32 (1.2e-7 exact, 1.4e-7 evaluated in
-// float32), beyond it the general atan.  The choice is per lane -- a branch that diverges
-// only in waves holding both cases -- so a sample's value never depends on the other
-// lanes of its wave.
+// float32), beyond it the general atan.  The choice is per lane, so a sample's value never
+// depends on the other lanes of its wave: a branch that diverges only in waves holding both
+// cases, or (UNIFORM) a wave-uniform test for the common case of a wave with no argument
+// beyond 1/4 and both forms selected per lane otherwise.
+__device__ __forceinline__ float atan_quintic(float x) {
+    const float x2 = x * x;
+    float p = __builtin_fmaf(0x1.7b89a0p-3f, x2, -0x1.54dfd2p-2f);
+    p = __builtin_fmaf(p, x2, 0x1.ffff8cp-1f);
+    return p * x;
+}
 template <bool UNIFORM = false>
 __device__ __forceinline__ float atan_slip(float x) {
-    if (__builtin_expect(fabsf(x) <= 0.25f, 1)) {
-        const float x2 = x * x;
-        float p = __builtin_fmaf(0x1.7b89a0p-3f, x2, -0x1.54dfd2p-2f);
-        p = __builtin_fmaf(p, x2, 0x1.ffff8cp-1f);
-        return p * x;
+    const bool small = fabsf(x) <= 0.25f;
+    if (UNIFORM) {
+        if (__builtin_expect(__builtin_amdgcn_ballot_w64(!small) == 0, 1)) return atan_quintic(x);
+        const float q = atan_quintic(x), g = fast_atan<true>(x);
+        return small ? q : g;
     }
+    if (__builtin_expect(small, 1)) return atan_quintic(x);
     return fast_atan<UNIFORM>(x);
 }
 

@@ -106,6 +106,7 @@ def load():
         lib.sgtp_sweep_stats.argtypes = [vp, P(C.c_double), P(C.c_longlong), P(C.c_longlong), C.c_int]
         lib.sgtp_abi_version.restype = C.c_int
         lib.sgtp_counter_probe_fp32.argtypes = [vp, C.c_int, C.c_int, vp]
+        lib.sgtp_issue_probe.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp]
         lib.sgtp_gauss_pairs.argtypes = [vp, vp, vp, C.c_int, vp]
         lib.sgtp_plan_create.argtypes = [vp, P(Params), P(Race), C.c_int, C.c_int, vp, vp, P(PlanOptions), P(vp), vp]
         lib.sgtp_plan_run.argtypes = [vp, vp]
@@ -378,6 +379,17 @@ def counter_probe_fp32(n_waves: int, iters: int):
     rc = load().sgtp_counter_probe_fp32(_ptr(out), int(n_waves), int(iters), _stream())
     if rc != 0:
         raise RuntimeError(f"sgtp_counter_probe_fp32 failed: {ERRORS.get(rc, rc)}")
+    return out
+
+
+def issue_probe(kind: int, n_blocks: int, iters: int, out=None):
+    """Run the issue-class probe kernel `kind` (instrumentation); returns its output tensor."""
+    import torch
+    if out is None:
+        out = torch.empty(256 * n_blocks, dtype=torch.float32, device="cuda")
+    rc = load().sgtp_issue_probe(_ptr(out), int(kind), int(n_blocks), int(iters), _stream())
+    if rc != 0:
+        raise RuntimeError(f"sgtp_issue_probe failed: {ERRORS.get(rc, rc)}")
     return out
 
 
