@@ -483,7 +483,8 @@ def main():
                     help="only run the known-mix FP32 kernel (for checking counter formulas under rocprofv3) "
                          "and print the instruction counts it must produce")
     ap.add_argument("--issue-probe", default="", metavar="BLOCKS,ITERS",
-                    help="only run the issue-class probe kernels (fma with vector or scalar operands, min, sin) "
+                    help="only run the issue-class probe kernels (fma with vector or scalar operands, min, sin, mul, "
+                         "xor, cndmask, med3, mad_u64_u32) "
                          "for reading which instructions the SIMDs pair (SQ_ACTIVE_INST_VALU2 under rocprofv3)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed region, one elementwise copy of MIB MiB (reads and writes MIB MiB): "
@@ -511,7 +512,8 @@ def main():
     if args.issue_probe:
         # four waves per SIMD at 1024 workgroups; per kind: one warm-up launch, then two timed
         blocks, iters = (int(x) for x in args.issue_probe.split(","))
-        kinds = ("fma, vector operands", "fma, one scalar operand", "min", "sin (transcendental)")
+        kinds = ("fma, vector operands", "fma, one scalar operand", "min", "sin (transcendental)",
+                 "mul, literal", "xor", "cndmask, scalar mask", "med3", "mad_u64_u32")
         out = torch.empty(256 * blocks, dtype=torch.float32, device="cuda")
         res = {}
         for kind, label in enumerate(kinds):

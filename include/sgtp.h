@@ -380,10 +380,11 @@ int sgtp_counter_probe_fp32(float *out, int n_waves, int iters, void *stream);
 /* Issue-class probe: n_blocks workgroups of 256 lanes (four waves); every lane runs `iters`
  * iterations of eight independent instructions of one kind, then seven v_add_f32 and one
  * store to out[256 n_blocks] (DEVICE).  kind 0: v_fma_f32 with vector operands, 1: v_fma_f32
- * with one scalar operand, 2: v_min_f32, 3: v_sin_f32.  Per wave: SQ_INSTS_VALU = 8 iters +
- * 7 (+ the store's address arithmetic).  Timed alone and read with SQ_ACTIVE_INST_VALU2 (the
- * issue cycles in which a SIMD issued two VALU instructions), it shows which instruction
- * forms are paired across waves.  Returns SGTP_EINVAL for a kind outside 0..3. */
+ * with one scalar operand, 2: v_min_f32, 3: v_sin_f32, 4: v_mul_f32 with a literal, 5:
+ * v_xor_b32, 6: v_cndmask_b32 on a scalar mask, 7: v_med3_f32, 8: v_mad_u64_u32.  Per wave:
+ * SQ_INSTS_VALU = 8 iters + 7 (+ the store's address arithmetic).  Timed alone and read with SQ_ACTIVE_INST_VALU2 (the issue cycles in which a
+ * SIMD issued two VALU instructions), it shows which instruction forms are paired across
+ * waves.  Returns SGTP_EINVAL for a kind outside 0..8. */
 int sgtp_issue_probe(float *out, int kind, int n_blocks, int iters, void *stream);
 
 int sgtp_abi_version(void);

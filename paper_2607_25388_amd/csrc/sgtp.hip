@@ -949,21 +949,32 @@ __device__ __forceinline__ float bound_term(const Foot &f) { return fminf(f.wR +
 // Squared footprint distance to one opponent at one step (eq. Dmin over disc pairs),
 // folded into `cur` (values are capped at cap^2: only smaller ones change any result;
 // a pair is skipped when the centres are too far apart for any disc pair to go below it).
-template <int NDISC>
+// UNIFORM: one wave-wide test skips the pairs when no lane is close (the common case);
+// otherwise every lane computes them and the close lanes keep the result, so each lane
+// gets the value of the per-lane form.
+template <int NDISC, bool UNIFORM = false>
 __device__ __forceinline__ float opp_min2(const KParams &P, const float2 *e, float2 cg, float X, float Y,
                                           const float *ax, const float *ay, float cur) {
     const float dx = X - cg.x, dy = Y - cg.y;
-    if (dx * dx + dy * dy < P.skip2) {
+    const bool close = dx * dx + dy * dy < P.skip2;
+    auto pairs = [&](float m) {
 #pragma unroll
         for (int a = 0; a < NDISC; ++a) {
 #pragma unroll
             for (int b = 0; b < NDISC; ++b) {
                 const float2 c = e[1 + b];
                 const float qx = ax[a] - c.x, qy = ay[a] - c.y;
-                cur = fminf(cur, qx * qx + qy * qy);
+                m = fminf(m, qx * qx + qy * qy);
             }
         }
+        return m;
+    };
+    if (UNIFORM) {
+        if (__builtin_expect(__builtin_amdgcn_ballot_w64(close) == 0, 1)) return cur;
+        const float m = pairs(cur);
+        return close ? m : cur;
     }
+    if (close) cur = pairs(cur);
     return cur;
 }
 
@@ -1160,7 +1171,8 @@ __device__ __forceinline__ SampleResult lane_sample(const KParams &P_in, const B
                                             g2[j]);
                 } else {
                     const float2 c0 = MAXOPP <= 3 ? cg[j < NPRE ? j : 0] : ot[j * (NDISC + 1)];
-                    g2[j] = opp_min2<NDISC>(P, ot + j * (NDISC + 1), c0, st[0], st[1], ax, ay, g2[j]);
+                    g2[j] = opp_min2<NDISC, NPF == 0 && LPS == 1>(P, ot + j * (NDISC + 1), c0, st[0], st[1], ax,
+                                                                  ay, g2[j]);
                 }
             }
         }
@@ -1827,7 +1839,7 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
 
 // Sweep with one workgroup per tile.
 template <int MODEL, int NDISC, int MAXOPP, int NPF = 0, int LPS = 1, int SPL = 0>
-__global__ void __launch_bounds__(BLOCK) k_sweep(LaunchArgs A) {
+__global__ void __launch_bounds__(BLOCK, (NPF == 0 && LPS == 1 && SPL == 0) ? 4 : 1) k_sweep(LaunchArgs A) {
     extern __shared__ __align__(16) char lds[];
     __shared__ int s_last;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
