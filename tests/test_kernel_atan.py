@@ -26,7 +26,7 @@ def coefficients(start="float atan_poly(float t, float t2)", stop="return p * t;
 
 def slip_coefficients():
     """The quintic's coefficients, highest degree first (as Horner takes them)."""
-    return coefficients("float atan_slip(float x)", "return p * x;")
+    return coefficients("float atan_quintic(float x)", "return p * x;")
 
 
 def f32(x):
