@@ -37,24 +37,24 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak
 # kernel with one sample per lane and k_sweep_persistent<0, 3, 9> (one record per schedule),
 # c2 k_sweep<0, 3, 3, 6, 1, 1> (split variant).  HBM bytes =
 # 2.000 x FETCH_SIZE + 1.000 x WRITE_SIZE (KiB), the factors being 256 MiB over what each
-# counter reads for the 256 MiB elementwise copy of the same runs (131087.7 KiB fetched,
-# 262144 KiB written).  FP32 FLOPs = 64 x SQ_INSTS_VALU_FLOPS_FP32, which counts ADD + MUL +
+# counter reads for the 256 MiB elementwise copy of the same runs (131087.5-131091.5 KiB
+# fetched, 262144 KiB written).  FP32 FLOPs = 64 x SQ_INSTS_VALU_FLOPS_FP32, which counts ADD + MUL +
 # TRANS + 2 FMA wave instructions (checked on the known-mix kernel of --counter-probe,
 # profiles/counter_probe_fp32.md).  They describe the kernel source with this SHA-256 and
 # the listed schedule fields only; anything else reports null.
-_SRC = "c4486c0c6d4434db3a4b88a76cc11c728c149579721e9ede031deb3caef30b4c"
+_SRC = "c421a252ca21e8a5f1751fb601b572e87825a5350e304be1ac9bedfc9a12d3ff"
 SWEEP_COUNTERS = {
-    "c4": [{"source_sha256": _SRC, "hbm_bytes_per_launch": (16585.913 * 1.99976 + 118372.220) * 1024.0,
-            "hw_fp32_flop_per_launch": 64 * 14136872671.3, "valu_wave_insts_per_launch": 14351972783.3,
+    "c4": [{"source_sha256": _SRC, "hbm_bytes_per_launch": (16584.821 * 1.99977 + 118349.394) * 1024.0,
+            "hw_fp32_flop_per_launch": 64 * 14070694659.9, "valu_wave_insts_per_launch": 14309969213.1,
             "schedule": {"persistent": 0, "tiles_per_fetch": 1, "samples_per_lane": 2}}],
-    "c3": [{"source_sha256": _SRC, "hbm_bytes_per_launch": (532.104 * 1.99976 + 1799.768) * 1024.0,
-            "hw_fp32_flop_per_launch": 64 * 286309898.4, "valu_wave_insts_per_launch": 293881101.9,
+    "c3": [{"source_sha256": _SRC, "hbm_bytes_per_launch": (525.500 * 1.99977 + 1799.415) * 1024.0,
+            "hw_fp32_flop_per_launch": 64 * 284971384.1, "valu_wave_insts_per_launch": 292403205.4,
             "schedule": {"persistent": 0, "tiles_per_fetch": 1, "samples_per_lane": 1}},
-           {"source_sha256": _SRC, "hbm_bytes_per_launch": (4281.604 * 1.99976 + 50073.513) * 1024.0,
-            "hw_fp32_flop_per_launch": 64 * 285963058.1, "valu_wave_insts_per_launch": 293049694.2,
+           {"source_sha256": _SRC, "hbm_bytes_per_launch": (6430.919 * 1.99977 + 59507.453) * 1024.0,
+            "hw_fp32_flop_per_launch": 64 * 284633401.6, "valu_wave_insts_per_launch": 291140176.1,
             "schedule": {"persistent": 1, "tiles_per_fetch": 1, "samples_per_lane": 1}}],
-    "c2": [{"source_sha256": _SRC, "hbm_bytes_per_launch": (376.485 * 1.99976 + 306.760) * 1024.0,
-            "hw_fp32_flop_per_launch": 64 * 16737196.9, "valu_wave_insts_per_launch": 19342086.1,
+    "c2": [{"source_sha256": _SRC, "hbm_bytes_per_launch": (376.493 * 1.99977 + 309.205) * 1024.0,
+            "hw_fp32_flop_per_launch": 64 * 16737196.9, "valu_wave_insts_per_launch": 19342399.3,
             "schedule": {"samples_per_lane": 1}}],
 }
 
