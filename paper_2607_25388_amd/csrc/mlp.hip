@@ -344,28 +344,14 @@ __global__ void k_nll(const float *out, int ldo, const float *U, int B, int N, f
             g[4 * t + 2 + c] = (bf16)0.0f;
         }
     }
-    // wave reduction of the loss; one partial per wave (summed in order by k_loss_total)
+    // wave reduction of the loss; one partial per wave (summed in order by k_grad_finish)
     for (int off = 32; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off);
     if ((threadIdx.x & 63) == 0) loss_part[e >> 6] = contrib;
 }
 
-// dst[r][c] (row stride ldd) = sum over z = 0 .. n_slices-1, in that order, of
-// src[z][r][c] (slice stride zs, row stride lds), for r < rows, c < cols; with dst_last,
-// the last row goes to dst_last[c] instead (a bias gradient computed as an extra row)
-__global__ void k_sum_slices(const float *src, int n_slices, long long zs, int rows, int cols, int lds, float *dst,
-                             int ldd, float *dst_last) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= rows * cols) return;
-    const int r = e / cols, c = e % cols;
-    const float *p = src + (long long)r * lds + c;
-    float s = p[0];
-    for (int z = 1; z < n_slices; ++z) s += p[z * zs];
-    if (dst_last && r == rows - 1) dst_last[c] = s;
-    else dst[(long long)r * ldd + c] = s;
-}
-
-// loss = (sum of the per-wave partials, in a fixed order) / B: one block of 256 threads
-__global__ void k_loss_total(const float *part, int n, int B, float *loss) {
+// loss = (sum of the per-wave partials, in a fixed order) / B, by one block of 256 threads;
+// also written to loss2 when it is given
+__device__ __forceinline__ void loss_total(const float *part, int n, int B, float *loss, float *loss2) {
     __shared__ float red[256];
     float s = 0.0f;
     for (int i = threadIdx.x; i < n; i += 256) s += part[i];
@@ -375,7 +361,46 @@ __global__ void k_loss_total(const float *part, int n, int B, float *loss) {
         if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) loss[0] = red[0] / (float)B;
+    if (threadIdx.x == 0) {
+        loss[0] = red[0] / (float)B;
+        if (loss2) loss2[0] = red[0] / (float)B;
+    }
+}
+
+// One launch that ends the gradient: the slice sums of the three weight-and-bias gradient
+// products (dst[r][c] = the sum over slices z = 0, 1, ... in that order of src[z][r][c]; with
+// dst_last the last row, the bias gradient, goes to dst_last[c]) and, in the last block,
+// the loss.  Blocks [first[l], first[l + 1]) sum product l.
+struct SliceSum {
+    const float *src;
+    long long zs;
+    int rows, cols, lds, ldd;
+    float *dst, *dst_last;
+};
+struct FinishArgs {
+    SliceSum s[3];
+    int first[4];  // block ranges; block first[3] computes the loss
+    int n_slices;
+    const float *lp;
+    int n_lp, B;
+    float *loss, *loss2;
+};
+__global__ void k_grad_finish(FinishArgs f) {
+    const int blk = blockIdx.x;
+    if (blk >= f.first[3]) {
+        loss_total(f.lp, f.n_lp, f.B, f.loss, f.loss2);
+        return;
+    }
+    const int l = blk < f.first[1] ? 0 : blk < f.first[2] ? 1 : 2;
+    const SliceSum &d = f.s[l];
+    const int e = (blk - f.first[l]) * blockDim.x + threadIdx.x;
+    if (e >= d.rows * d.cols) return;
+    const int r = e / d.cols, c = e % d.cols;
+    const float *q = d.src + (long long)r * d.lds + c;
+    float v = q[0];
+    for (int z = 1; z < f.n_slices; ++z) v += q[z * d.zs];
+    if (d.dst_last && r == d.rows - 1) d.dst_last[c] = v;
+    else d.dst[(long long)r * d.ldd + c] = v;
 }
 
 // Adam step number t = *t_prev + 1 read on the device (so a captured training step can be
@@ -436,7 +461,7 @@ struct sgtp_mlp {
     float *b3p = nullptr;
     bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *D = nullptr, *D2 = nullptr, *D1 = nullptr;
     float *PRE1 = nullptr, *PRE2 = nullptr, *OUT = nullptr, *loss = nullptr;
-    float *PART = nullptr;  // split-K partial products of the weight and bias gradients [64][257][256]
+    float *PART = nullptr;  // split-K partial products of the weight and bias gradients [3][64][257][256]
     float *LP = nullptr;    // per-wave loss partials [2 B_max + 4]
     int *adam_t = nullptr;  // device: Adam steps taken
     int last_B = 0;  // rows of the last sgtp_mlp_grad (its workspace tensors stay until the next call)
@@ -478,15 +503,16 @@ void gemm(hipStream_t st, const bf16 *A, long long a_m, long long a_k, const bf1
 
 // weight gradient dst[M][ldd] (first N columns) = A B and bias gradient bias_dst[N] =
 // column sums of B, as one product with an extra row of ones in A, K split into `splits`
-// slices: partial products into m->PART, summed in slice order
-void gemm_wgrad(sgtp_mlp *m, hipStream_t st, const bf16 *A, long long a_m, long long a_k, const bf16 *B, long long b_k,
-                long long b_n, int M, int N, int K, float *dst, int ldd, float *bias_dst, int splits) {
+// slices: partial products into `part` [splits][M + 1][N]; the slices are summed in order
+// by k_grad_finish (its descriptor is returned)
+SliceSum gemm_wgrad(hipStream_t st, float *part, const bf16 *A, long long a_m, long long a_k, const bf16 *B,
+                    long long b_k, long long b_n, int M, int N, int K, float *dst, int ldd, float *bias_dst,
+                    int splits) {
     const int R = M + 1;  // row M of A reads as 1: the bias gradient
-    GemmArgs g{A, a_m, a_k, B, b_k, b_n, R, N, K, nullptr, m->PART, N, (long long)R * N, nullptr, 0, nullptr,
+    GemmArgs g{A, a_m, a_k, B, b_k, b_n, R, N, K, nullptr, part, N, (long long)R * N, nullptr, 0, nullptr,
                stage_mode(A, a_m, a_k), stage_mode(B, b_n, b_k), M};
     hipLaunchKernelGGL(k_gemm_bf16, dim3((N + 63) / 64, (R + 63) / 64, splits), dim3(256), 0, st, g);
-    hipLaunchKernelGGL(k_sum_slices, dim3((R * N + 255) / 256), dim3(256), 0, st, m->PART, splits, (long long)R * N, R,
-                       N, N, dst, ldd, bias_dst);
+    return SliceSum{part, (long long)R * N, R, N, N, ldd, dst, bias_dst};
 }
 
 // forward of B rows (features float32 [B][ldx]) into out[B][ldo], n_out columns (200, or
@@ -536,7 +562,7 @@ int sgtp_mlp_create(int B_max, sgtp_mlp **out) {
     al((void **)&m->PRE1, (size_t)B_max * D_H * 4);
     al((void **)&m->PRE2, (size_t)B_max * D_H * 4);
     al((void **)&m->OUT, (size_t)B_max * D_OUTP * 4);
-    al((void **)&m->PART, (size_t)MAX_SPLITS * (D_H + 1) * D_OUTP * 4);
+    al((void **)&m->PART, (size_t)3 * MAX_SPLITS * (D_H + 1) * D_OUTP * 4);
     al((void **)&m->LP, (size_t)(2 * B_max + 4) * 4);
     al((void **)&m->adam_t, 4);
     al((void **)&m->loss, 4);
@@ -615,18 +641,32 @@ int sgtp_mlp_grad(sgtp_mlp *m, const float *X, const float *U, int B, int N, flo
     const int nll_blocks = (B * 128 + 255) / 256;
     hipLaunchKernelGGL(k_nll, dim3(nll_blocks), dim3(256), 0, st, m->OUT, D_OUTP, U, B, N, sig_a, sig_d, m->D, D_OUTP,
                        m->LP);
-    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, st, m->LP, 4 * nll_blocks, B, m->loss);
+    // partial products of the three weight-and-bias gradients go to separate thirds of PART
+    const size_t third = (size_t)MAX_SPLITS * (D_H + 1) * D_OUTP;
+    FinishArgs fa{};
     // layer 3: gW3 = H2^T D and gb3 = column sums of D (one product), dH2 = D W3^T
-    gemm_wgrad(m, st, m->H2, 1, D_H, m->D, D_OUTP, 1, D_H, D_OUT, B, m->G + P_W3, D_OUT, m->G + P_B3, sp);
+    fa.s[0] = gemm_wgrad(st, m->PART, m->H2, 1, D_H, m->D, D_OUTP, 1, D_H, D_OUT, B, m->G + P_W3, D_OUT,
+                         m->G + P_B3, sp);
     gemm(st, m->D, D_OUTP, 1, m->W3, 1, D_OUTP, B, D_H, D_OUTP, nullptr, nullptr, 0, m->D2, D_H, m->PRE2);
     // layer 2: gW2 = H1^T D2, gb2, dH1 = D2 W2^T
-    gemm_wgrad(m, st, m->H1, 1, D_H, m->D2, D_H, 1, D_H, D_H, B, m->G + P_W2, D_H, m->G + P_B2, sp);
+    fa.s[1] = gemm_wgrad(st, m->PART + third, m->H1, 1, D_H, m->D2, D_H, 1, D_H, D_H, B, m->G + P_W2, D_H,
+                         m->G + P_B2, sp);
     gemm(st, m->D2, D_H, 1, m->W2, 1, D_H, B, D_H, D_H, nullptr, nullptr, 0, m->D1, D_H, m->PRE1);
     // layer 1: gW1 = X^T D1, gb1
-    gemm_wgrad(m, st, m->X, 1, D_INP, m->D1, D_H, 1, D_IN, D_H, B, m->G + P_W1, D_H, m->G + P_B1, sp);
+    fa.s[2] = gemm_wgrad(st, m->PART + 2 * third, m->X, 1, D_INP, m->D1, D_H, 1, D_IN, D_H, B, m->G + P_W1, D_H,
+                         m->G + P_B1, sp);
+    // the slice sums and the loss in one launch
+    fa.first[0] = 0;
+    for (int l = 0; l < 3; ++l) fa.first[l + 1] = fa.first[l] + (fa.s[l].rows * fa.s[l].cols + 255) / 256;
+    fa.n_slices = sp;
+    fa.lp = m->LP;
+    fa.n_lp = 4 * nll_blocks;
+    fa.B = B;
+    fa.loss = m->loss;
+    fa.loss2 = loss;
+    hipLaunchKernelGGL(k_grad_finish, dim3(fa.first[3] + 1), dim3(256), 0, st, fa);
     MCHK(m, hipGetLastError());
     m->last_B = B;
-    if (loss) MCHK(m, hipMemcpyAsync(loss, m->loss, 4, hipMemcpyDeviceToDevice, st));
     if (grads) MCHK(m, hipMemcpyAsync(grads, m->G, P_TOTAL * 4, hipMemcpyDeviceToDevice, st));
     return SGTP_OK;
 }
