@@ -330,15 +330,27 @@ int sgtp_mlp_grad(sgtp_mlp *m, const float *X, const float *U, int B, int N, flo
  * GELU(z) as BF16 [B][256]; _OUT the outputs float32 [B][256] (columns 200..255 zero);
  * _D3 the output gradient as BF16 [B][256] (columns of steps >= N and 200..255 zero);
  * _D2 / _D1 the gradients w.r.t. the pre-activations of layers 2 and 1 as BF16
- * [B][256].  They stay until the next sgtp_mlp_grad.  SGTP_EINVAL before the first
- * gradient call or for an unknown tensor. */
+ * [B][256]; _IDX the data-set rows the last sgtp_mlp_grad_sampled drew, int32 [B]
+ * (SGTP_EINVAL after a plain sgtp_mlp_grad).  They stay until the next gradient call.
+ * SGTP_EINVAL before the first gradient call or for an unknown tensor. */
 #define SGTP_MLP_WS_H1 0
 #define SGTP_MLP_WS_H2 1
 #define SGTP_MLP_WS_OUT 2
 #define SGTP_MLP_WS_D3 3
 #define SGTP_MLP_WS_D2 4
 #define SGTP_MLP_WS_D1 5
+#define SGTP_MLP_WS_IDX 6
 int sgtp_mlp_workspace(sgtp_mlp *m, int which, void *dst, void *stream);
+/* sgtp_mlp_grad on B rows drawn on the device from a data set of M rows (a training
+ * minibatch with no host step, so a captured training step draws new rows on every
+ * replay): row b is data row floor(r M / 2^32), r the first word of Philox4x32-10 at
+ * counter (b, t, 0, 0) with key (seed & 0xffffffff, seed >> 32), t the number of Adam
+ * steps the network has taken.  X_all float32 [M][50] and U_all float32 [M][N][2]
+ * (DEVICE, row-major); the rows are gathered inside (features straight to BF16) and the
+ * gradient is that of sgtp_mlp_grad on them, bit for bit.  SGTP_ESHAPE for M outside
+ * [1, 2^31 - 1], otherwise the errors of sgtp_mlp_grad. */
+int sgtp_mlp_grad_sampled(sgtp_mlp *m, const float *X_all, const float *U_all, long long M, int B, int N,
+                          unsigned long long seed, float sig_a, float sig_d, float *loss, float *grads, void *stream);
 /* One Adam step with the last gradients (bias-corrected moments). */
 int sgtp_mlp_adam(sgtp_mlp *m, float lr, float beta1, float beta2, float eps, void *stream);
 /* Make every planning step of `plan` compute the proposal tables itself: after the

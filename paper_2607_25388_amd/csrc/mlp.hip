@@ -225,6 +225,33 @@ __global__ void k_to_bf16_rows(const float *X, int B, int din, int ldx, bf16 *Y,
     Y[(long long)b * ldy + c] = (c < din) ? (bf16)X[(long long)b * ldx + c] : (bf16)0.0f;
 }
 
+// Philox4x32-10 (Salmon et al., SC'11: two 32 x 32 -> 64-bit products per round, Weyl key
+// schedule): the counter-based generator of the minibatch draw
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Minibatch row b: data row i = floor(r M / 2^32), r the first Philox word at counter
+// (b, t, 0, 0), t the Adam steps taken (read on the device); its features as BF16 operands
+// [b][64] (zero padding) and its targets [b][N][2].  One block of 128 threads per row.
+__global__ void k_gather_sampled(const float *X_all, const float *U_all, long long M, int N, uint32_t k0,
+                                 uint32_t k1, const int *t, bf16 *Xb, float *Ub, int *idx) {
+    const int b = blockIdx.x;
+    const uint4 r = philox4x32_10(make_uint4((uint32_t)b, (uint32_t)*t, 0u, 0u), k0, k1);
+    const long long i = (long long)(((unsigned long long)r.x * (unsigned long long)M) >> 32);
+    if (threadIdx.x == 0) idx[b] = (int)i;
+    if (threadIdx.x < D_INP)
+        Xb[(long long)b * D_INP + threadIdx.x] =
+            threadIdx.x < D_IN ? (bf16)X_all[i * D_IN + threadIdx.x] : (bf16)0.0f;
+    for (int e = threadIdx.x; e < 2 * N; e += blockDim.x) Ub[(long long)b * 2 * N + e] = U_all[i * 2 * N + e];
+}
+
 // packed float32 weights -> BF16 GEMM operands (W3 padded to 256 columns)
 __global__ void k_refresh_bf16(const float *P, bf16 *W1, bf16 *W2, bf16 *W3, float *b3p) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -464,7 +491,10 @@ struct sgtp_mlp {
     float *PART = nullptr;  // split-K partial products of the weight and bias gradients [3][64][257][256]
     float *LP = nullptr;    // per-wave loss partials [2 B_max + 4]
     int *adam_t = nullptr;  // device: Adam steps taken
+    float *UB = nullptr;    // gathered targets of a sampled gradient [B_max][N_H][2]
+    int *IDX = nullptr;     // rows drawn by the last sampled gradient [B_max]
     int last_B = 0;  // rows of the last sgtp_mlp_grad (its workspace tensors stay until the next call)
+    bool last_sampled = false;  // the last gradient drew its rows on the device
 };
 
 namespace {
@@ -517,13 +547,17 @@ SliceSum gemm_wgrad(hipStream_t st, float *part, const bf16 *A, long long a_m, l
 
 // forward of B rows (features float32 [B][ldx]) into out[B][ldo], n_out columns (200, or
 // 256 with the zero padding for the loss)
-int forward(sgtp_mlp *m, const float *X, int ldx, int B, float *out, int ldo, int n_out, hipStream_t st) {
-    hipLaunchKernelGGL(k_to_bf16_rows, dim3((B * D_INP + 255) / 256), dim3(256), 0, st, X, B, D_IN, ldx, m->X, D_INP);
+// (products only: the BF16 operands are already in m->X)
+int forward_bf16(sgtp_mlp *m, int B, float *out, int ldo, int n_out, hipStream_t st) {
     gemm(st, m->X, D_INP, 1, m->W1, D_H, 1, B, D_H, D_IN, m->P + P_B1, m->PRE1, D_H, m->H1, D_H);
     gemm(st, m->H1, D_H, 1, m->W2, D_H, 1, B, D_H, D_H, m->P + P_B2, m->PRE2, D_H, m->H2, D_H);
     gemm(st, m->H2, D_H, 1, m->W3, D_OUTP, 1, B, n_out, D_H, m->b3p, out, ldo, nullptr, 0);
     MCHK(m, hipGetLastError());
     return SGTP_OK;
+}
+int forward(sgtp_mlp *m, const float *X, int ldx, int B, float *out, int ldo, int n_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_bf16_rows, dim3((B * D_INP + 255) / 256), dim3(256), 0, st, X, B, D_IN, ldx, m->X, D_INP);
+    return forward_bf16(m, B, out, ldo, n_out, st);
 }
 
 }  // namespace
@@ -565,6 +599,8 @@ int sgtp_mlp_create(int B_max, sgtp_mlp **out) {
     al((void **)&m->PART, (size_t)3 * MAX_SPLITS * (D_H + 1) * D_OUTP * 4);
     al((void **)&m->LP, (size_t)(2 * B_max + 4) * 4);
     al((void **)&m->adam_t, 4);
+    al((void **)&m->UB, (size_t)B_max * N_H * 2 * 4);
+    al((void **)&m->IDX, (size_t)B_max * 4);
     al((void **)&m->loss, 4);
     if (!ok) {
         sgtp_mlp_destroy(m);
@@ -579,7 +615,7 @@ int sgtp_mlp_destroy(sgtp_mlp *m) {
     (void)hipDeviceSynchronize();
     void *bufs[] = {m->P,  m->G,  m->Mm, m->Vv,   m->W1,   m->W2,  m->W3, m->b3p, m->X,    m->H1,   m->H2,
                     m->D,  m->D1, m->PRE1, m->PRE2, m->OUT, m->PART, m->loss, m->W1T, m->W2T, m->W3T,
-                    m->D2, m->LP, m->adam_t};
+                    m->D2, m->LP, m->adam_t, m->UB, m->IDX};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete m;
@@ -628,14 +664,11 @@ int sgtp_mlp_forward(sgtp_mlp *m, const float *X, int B, float *out, int ld_out,
     return forward(m, X, D_IN, B, out, ld_out, D_OUT, st);
 }
 
-int sgtp_mlp_grad(sgtp_mlp *m, const float *X, const float *U, int B, int N, float sig_a, float sig_d, float *loss,
-                  float *grads, void *stream) {
-    if (!m || !X || !U) return SGTP_EINVAL;
-    if (B < 1 || B > m->B_max) return mfail(m, SGTP_ESHAPE, "batch larger than the network workspace");
-    if (N < 1 || N > N_H) return mfail(m, SGTP_ESHAPE, "horizon outside [1, 50]");
-    if (!(sig_a > 0.0f) || !(sig_d > 0.0f)) return mfail(m, SGTP_EINVAL, "plain scales must be positive");
-    hipStream_t st = (hipStream_t)stream;
-    int rc = forward(m, X, D_IN, B, m->OUT, D_OUTP, D_OUTP, st);
+namespace {
+// The gradient once the BF16 operands of the B rows are in m->X (targets U [B][N][2])
+int grad_rows(sgtp_mlp *m, const float *U, int B, int N, float sig_a, float sig_d, float *loss, float *grads,
+              hipStream_t st) {
+    int rc = forward_bf16(m, B, m->OUT, D_OUTP, D_OUTP, st);
     if (rc) return rc;
     const int sp = k_splits(B);
     const int nll_blocks = (B * 128 + 255) / 256;
@@ -671,6 +704,37 @@ int sgtp_mlp_grad(sgtp_mlp *m, const float *X, const float *U, int B, int N, flo
     return SGTP_OK;
 }
 
+int check_grad_args(sgtp_mlp *m, int B, int N, float sig_a, float sig_d) {
+    if (B < 1 || B > m->B_max) return mfail(m, SGTP_ESHAPE, "batch larger than the network workspace");
+    if (N < 1 || N > N_H) return mfail(m, SGTP_ESHAPE, "horizon outside [1, 50]");
+    if (!(sig_a > 0.0f) || !(sig_d > 0.0f)) return mfail(m, SGTP_EINVAL, "plain scales must be positive");
+    return SGTP_OK;
+}
+}  // namespace
+
+int sgtp_mlp_grad(sgtp_mlp *m, const float *X, const float *U, int B, int N, float sig_a, float sig_d, float *loss,
+                  float *grads, void *stream) {
+    if (!m || !X || !U) return SGTP_EINVAL;
+    if (int rc = check_grad_args(m, B, N, sig_a, sig_d)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_to_bf16_rows, dim3((B * D_INP + 255) / 256), dim3(256), 0, st, X, B, D_IN, D_IN, m->X,
+                       D_INP);
+    m->last_sampled = false;
+    return grad_rows(m, U, B, N, sig_a, sig_d, loss, grads, st);
+}
+
+int sgtp_mlp_grad_sampled(sgtp_mlp *m, const float *X_all, const float *U_all, long long M, int B, int N,
+                          unsigned long long seed, float sig_a, float sig_d, float *loss, float *grads, void *stream) {
+    if (!m || !X_all || !U_all) return SGTP_EINVAL;
+    if (M < 1 || M > 0x7fffffffLL) return mfail(m, SGTP_ESHAPE, "data set rows outside [1, 2^31 - 1]");
+    if (int rc = check_grad_args(m, B, N, sig_a, sig_d)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_gather_sampled, dim3(B), dim3(128), 0, st, X_all, U_all, M, N, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), m->adam_t, m->X, m->UB, m->IDX);
+    m->last_sampled = true;
+    return grad_rows(m, m->UB, B, N, sig_a, sig_d, loss, grads, st);
+}
+
 int sgtp_mlp_workspace(sgtp_mlp *m, int which, void *dst, void *stream) {
     if (!m || !dst) return SGTP_EINVAL;
     if (m->last_B < 1) return mfail(m, SGTP_EINVAL, "no gradient computed yet");
@@ -683,6 +747,11 @@ int sgtp_mlp_workspace(sgtp_mlp *m, int which, void *dst, void *stream) {
         case SGTP_MLP_WS_D3: src = m->D; row = D_OUTP * 2; break;
         case SGTP_MLP_WS_D2: src = m->D2; row = D_H * 2; break;
         case SGTP_MLP_WS_D1: src = m->D1; row = D_H * 2; break;
+        case SGTP_MLP_WS_IDX:
+            if (!m->last_sampled) return mfail(m, SGTP_EINVAL, "the last gradient did not draw its rows");
+            src = m->IDX;
+            row = 4;
+            break;
         default: return mfail(m, SGTP_EINVAL, "unknown workspace tensor");
     }
     MCHK(m, hipMemcpyAsync(dst, src, row * m->last_B, hipMemcpyDeviceToDevice, (hipStream_t)stream));

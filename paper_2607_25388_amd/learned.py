@@ -72,11 +72,12 @@ TRAIN_FLOP_PER_ROW = 2 * (50 * 256 + 256 * 256 + 256 * 200) * 2 + 2 * (200 * 256
 
 
 class Trainer:
-    """Adam on random minibatches of a data set.  Each step draws `batch` row indices
-    (torch's device generator, seeded), gathers the rows into fixed buffers and runs
-    sgtp_mlp_grad and sgtp_mlp_adam; with graph=True the gather, gradient and Adam launches
-    are captured once in a hipGraph and each step is one index draw plus one replay.  The
-    network's reductions run in a fixed order, so both ways give the same bits."""
+    """Adam on random minibatches of a data set.  Each step draws `batch` rows on the device
+    (sgtp_mlp_grad_sampled: Philox at counter (row, Adam step), so nothing runs on the host
+    between steps), gathers them inside the library and runs the gradient and
+    sgtp_mlp_adam; with graph=True both are captured once in a hipGraph and each step is
+    one replay.  The network's reductions run in a fixed order, so both ways give the same
+    bits."""
 
     def __init__(self, mlp: sg.Mlp, data: Dataset, params: dict, batch: int = 1024, lr: float = 1e-3,
                  seed: int = 0, graph: bool = True):
@@ -84,13 +85,8 @@ class Trainer:
         self.mlp, self.data, self.lr = mlp, data, lr
         self.M = data.X.shape[0]
         self.batch = min(batch, self.M, mlp.B_max)
-        dev = data.X.device
-        self.gen = torch.Generator(device=dev)
-        self.gen.manual_seed(seed)
+        self.seed = int(seed)
         self.sig = (params["sigma_a"], params["sigma_d"])
-        self.idx = torch.zeros(self.batch, dtype=torch.long, device=dev)
-        self.Xb = torch.empty((self.batch,) + tuple(data.X.shape[1:]), dtype=data.X.dtype, device=dev)
-        self.Ub = torch.empty((self.batch,) + tuple(data.U.shape[1:]), dtype=data.U.dtype, device=dev)
         self.graph = None
         if graph:
             self.graph = torch.cuda.CUDAGraph()
@@ -98,17 +94,12 @@ class Trainer:
                 self.loss = self._launch()
 
     def _launch(self):
-        import torch
-        torch.index_select(self.data.X, 0, self.idx, out=self.Xb)
-        torch.index_select(self.data.U, 0, self.idx, out=self.Ub)
-        loss, _ = self.mlp.grad(self.Xb, self.Ub, *self.sig)
+        loss, _ = self.mlp.grad_sampled(self.data.X, self.data.U, self.batch, self.seed, *self.sig)
         self.mlp.adam(lr=self.lr)
         return loss
 
     def step(self):
         """One training step; returns the (device) loss of its minibatch before the update."""
-        import torch
-        torch.randint(0, self.M, (self.batch,), generator=self.gen, out=self.idx)
         if self.graph is not None:
             self.graph.replay()
             return self.loss

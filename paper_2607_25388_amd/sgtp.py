@@ -131,6 +131,8 @@ def load():
         lib.sgtp_mlp_grad.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_float, C.c_float, vp, vp, vp]
         lib.sgtp_mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]
         lib.sgtp_mlp_workspace.argtypes = [vp, C.c_int, vp, vp]
+        lib.sgtp_mlp_grad_sampled.argtypes = [vp, vp, vp, C.c_longlong, C.c_int, C.c_int, C.c_ulonglong, C.c_float,
+                                              C.c_float, vp, vp, vp]
         lib.sgtp_gemm_bf16.argtypes = [vp, C.c_longlong, C.c_longlong, vp, C.c_longlong, C.c_longlong, C.c_int,
                                        C.c_int, C.c_int, vp, vp, C.c_longlong, vp]
         _lib = lib
@@ -535,15 +537,34 @@ class Mlp:
         self._last_B = X.shape[0]
         return loss, g
 
+    def grad_sampled(self, X_all, U_all, B, seed, sig_a, sig_d, want_grads=False):
+        """grad() on B rows of the data set (X_all [M][50], U_all [M][N][2]) drawn on the device
+        (see sgtp_mlp_grad_sampled); (loss tensor [1], gradient tensor or None)."""
+        import torch
+        X_all, U_all = X_all.contiguous(), U_all.contiguous()
+        loss = torch.empty(1, dtype=torch.float32, device=X_all.device)
+        g = torch.empty(self.n_params, dtype=torch.float32, device=X_all.device) if want_grads else None
+        self._check(self.lib.sgtp_mlp_grad_sampled(self.h, _ptr(X_all), _ptr(U_all), X_all.shape[0], int(B),
+                                                   U_all.shape[1], int(seed) & (2 ** 64 - 1), float(sig_a),
+                                                   float(sig_d), _ptr(loss), _ptr(g), _stream()),
+                    "sgtp_mlp_grad_sampled")
+        self._last_B = int(B)
+        return loss, g
+
     WORKSPACE = {"h1": (0, "bf16"), "h2": (1, "bf16"), "out": (2, "f32"), "d3": (3, "bf16"), "d2": (4, "bf16"),
-                 "d1": (5, "bf16")}
+                 "d1": (5, "bf16"), "idx": (6, "i32")}
 
     def workspace(self, name):
-        """A tensor of the last grad() call ([B][256]; see sgtp_mlp_workspace), as float32."""
+        """A tensor of the last gradient call (see sgtp_mlp_workspace): [B][256] as float32,
+        or for "idx" the drawn data-set rows as int32 [B]."""
         import torch
         which, kind = self.WORKSPACE[name]
         if not getattr(self, "_last_B", 0):
             raise RuntimeError("no gradient computed yet")
+        if kind == "i32":
+            t = torch.empty(self._last_B, dtype=torch.int32, device="cuda")
+            self._check(self.lib.sgtp_mlp_workspace(self.h, which, _ptr(t), _stream()), "sgtp_mlp_workspace")
+            return t
         t = torch.empty((self._last_B, 256), dtype=torch.bfloat16 if kind == "bf16" else torch.float32, device="cuda")
         self._check(self.lib.sgtp_mlp_workspace(self.h, which, _ptr(t), _stream()), "sgtp_mlp_workspace")
         return t.float()

@@ -164,6 +164,56 @@ def test_training_step_graph_replays_match_eager_steps():
     mb.close()
 
 
+def test_sampled_gradient_draws_its_rows_and_matches_the_plain_gradient(oracle_lib):
+    """sgtp_mlp_grad_sampled: the rows it draws are floor(r M / 2^32) with r the first
+    Philox4x32-10 word at counter (row, Adam step, 0, 0) and the seed's two halves as key
+    (checked against the oracle's Philox), and its loss and gradient equal those of
+    sgtp_mlp_grad on the same rows gathered on the host, bit for bit; after an Adam step
+    the next call draws other rows."""
+    import ctypes as C
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    flat, _ = _net(seed=21, scale3=3.0)
+    rng = np.random.default_rng(11)
+    M, N, B, seed = 2777, 40, 700, 0x1234_5678_9ABC_DEF0
+    X = torch.as_tensor(rng.standard_normal((M, 50)).astype(np.float32)).cuda()
+    U = torch.as_tensor(np.stack([rng.uniform(-8, 4, (M, N)), rng.uniform(-0.4, 0.4, (M, N))], -1)
+                        .astype(np.float32)).cuda()
+    params = {"sigma_a": 1.5, "sigma_d": 0.08}
+    m = sg.Mlp(1024, flat)
+    lib = oracle_lib
+    lib.ref_philox4x32_10.argtypes = [C.POINTER(C.c_uint32)] * 3
+    key = (C.c_uint32 * 2)(seed & 0xFFFFFFFF, seed >> 32)
+
+    def expected_rows(step):
+        rows = []
+        for b in range(B):
+            c = (C.c_uint32 * 4)(b, step, 0, 0)
+            o = (C.c_uint32 * 4)()
+            lib.ref_philox4x32_10(c, key, o)
+            rows.append((o[0] * M) >> 32)
+        return np.array(rows)
+
+    try:
+        for step in range(2):
+            print(f"sampled gradient, Adam step {step}", flush=True)
+            ls, gs = m.grad_sampled(X, U, B, seed, params["sigma_a"], params["sigma_d"], want_grads=True)
+            idx = m.workspace("idx").cpu().numpy().astype(np.int64)
+            assert np.array_equal(idx, expected_rows(step))
+            sel = torch.as_tensor(idx).cuda()
+            lp, gp = m.grad(X.index_select(0, sel), U.index_select(0, sel), params["sigma_a"], params["sigma_d"],
+                            want_grads=True)
+            torch.cuda.synchronize()
+            assert ls.item() == lp.item()
+            assert np.array_equal(gs.cpu().numpy().view(np.uint32), gp.cpu().numpy().view(np.uint32))
+            with pytest.raises(RuntimeError):
+                m.workspace("idx")  # the last call (plain) drew no rows
+            m.adam(lr=1e-3)
+        assert not np.array_equal(expected_rows(0), expected_rows(1))
+    finally:
+        m.close()
+
+
 def test_adam_updates_the_bf16_operand_copies():
     """After Adam steps (which write the BF16 operand copies as they update the master
     weights), the network computes exactly what a fresh network given the same master
