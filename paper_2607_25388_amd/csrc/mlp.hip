@@ -293,11 +293,16 @@ __device__ __forceinline__ f32x4 mfma_rows16(const bf16 *A, int lda, const bf16 
     return acc;
 }
 
-// Fused forward of 16 rows per workgroup (batches of planning size): the three layers run
-// back to back with the hidden activations in LDS (BF16, as the tiled path stores them).
-__global__ void __launch_bounds__(256) k_mlp_fwd16(const float *X, int ldx, int B, const bf16 *W1T, const bf16 *W2T,
-                                                  const bf16 *W3T, const float *b1, const float *b2,
-                                                  const float *b3, float *out, int ldo, int n_out) {
+// Fused forward of 16 rows per workgroup: the three layers run back to back with the
+// hidden activations in LDS (BF16, as the tiled path stores them).  TRAIN: the input rows
+// are the BF16 operands already in Xb ([B][64]), and the pre-activations (float32) and
+// activations (BF16) of both hidden layers are also written out ([B][256] each), as the
+// tiled products write them for the backward pass.
+template <bool TRAIN>
+__global__ void __launch_bounds__(256) k_mlp_fwd16(const float *X, int ldx, const bf16 *Xb, int B, const bf16 *W1T,
+                                                  const bf16 *W2T, const bf16 *W3T, const float *b1, const float *b2,
+                                                  const float *b3, float *out, int ldo, int n_out, float *pre1,
+                                                  bf16 *h1o, float *pre2, bf16 *h2o) {
     constexpr int LX = D_INP + 8, LH = D_H + 8;  // padded rows (16-byte aligned)
     __shared__ __align__(16) bf16 xs[16 * LX];
     __shared__ __align__(16) bf16 h1[16 * LH];
@@ -305,7 +310,8 @@ __global__ void __launch_bounds__(256) k_mlp_fwd16(const float *X, int ldx, int 
     const int r0 = blockIdx.x * 16, tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     for (int e = tid; e < 16 * D_INP; e += 256) {
         const int r = e / D_INP, c = e % D_INP;
-        xs[r * LX + c] = (r0 + r < B && c < D_IN) ? (bf16)X[(long long)(r0 + r) * ldx + c] : (bf16)0.0f;
+        if (TRAIN) xs[r * LX + c] = (r0 + r < B) ? Xb[(long long)(r0 + r) * D_INP + c] : (bf16)0.0f;
+        else xs[r * LX + c] = (r0 + r < B && c < D_IN) ? (bf16)X[(long long)(r0 + r) * ldx + c] : (bf16)0.0f;
     }
     __syncthreads();
 #pragma unroll
@@ -315,7 +321,13 @@ __global__ void __launch_bounds__(256) k_mlp_fwd16(const float *X, int ldx, int 
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = 4 * (l >> 4) + v, col = n0 + (l & 15);
-            h1[row * LH + col] = (bf16)gelu_f(acc[v] + b1[col]);
+            const float x = acc[v] + b1[col];
+            const bf16 h = (bf16)gelu_f(x);
+            h1[row * LH + col] = h;
+            if (TRAIN && r0 + row < B) {
+                pre1[(long long)(r0 + row) * D_H + col] = x;
+                h1o[(long long)(r0 + row) * D_H + col] = h;
+            }
         }
     }
     __syncthreads();
@@ -326,7 +338,13 @@ __global__ void __launch_bounds__(256) k_mlp_fwd16(const float *X, int ldx, int 
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = 4 * (l >> 4) + v, col = n0 + (l & 15);
-            h2[row * LH + col] = (bf16)gelu_f(acc[v] + b2[col]);
+            const float x = acc[v] + b2[col];
+            const bf16 h = (bf16)gelu_f(x);
+            h2[row * LH + col] = h;
+            if (TRAIN && r0 + row < B) {
+                pre2[(long long)(r0 + row) * D_H + col] = x;
+                h2o[(long long)(r0 + row) * D_H + col] = h;
+            }
         }
     }
     __syncthreads();
@@ -656,8 +674,9 @@ int sgtp_mlp_forward(sgtp_mlp *m, const float *X, int B, float *out, int ld_out,
     if (ld_out < D_OUT) return mfail(m, SGTP_EINVAL, "ld_out < 200");
     hipStream_t st = (hipStream_t)stream;
     if (B <= FUSED_MAX_ROWS) {  // planning-size batches: one fused kernel
-        hipLaunchKernelGGL(k_mlp_fwd16, dim3((B + 15) / 16), dim3(256), 0, st, X, D_IN, B, m->W1T, m->W2T, m->W3T,
-                           m->P + P_B1, m->P + P_B2, m->P + P_B3, out, ld_out, D_OUT);
+        hipLaunchKernelGGL(k_mlp_fwd16<false>, dim3((B + 15) / 16), dim3(256), 0, st, X, D_IN, nullptr, B, m->W1T,
+                           m->W2T, m->W3T, m->P + P_B1, m->P + P_B2, m->P + P_B3, out, ld_out, D_OUT, nullptr, nullptr,
+                           nullptr, nullptr);
         MCHK(m, hipGetLastError());
         return SGTP_OK;
     }
@@ -665,11 +684,22 @@ int sgtp_mlp_forward(sgtp_mlp *m, const float *X, int B, float *out, int ld_out,
 }
 
 namespace {
+// Training batches up to this many rows take the fused forward (one launch, the hidden
+// layers written out for the backward pass); larger ones the tiled products.  Both give
+// the same bits.
+constexpr int FUSED_TRAIN_MAX = 8192;
+
 // The gradient once the BF16 operands of the B rows are in m->X (targets U [B][N][2])
 int grad_rows(sgtp_mlp *m, const float *U, int B, int N, float sig_a, float sig_d, float *loss, float *grads,
               hipStream_t st) {
-    int rc = forward_bf16(m, B, m->OUT, D_OUTP, D_OUTP, st);
-    if (rc) return rc;
+    if (B <= FUSED_TRAIN_MAX) {
+        hipLaunchKernelGGL(k_mlp_fwd16<true>, dim3((B + 15) / 16), dim3(256), 0, st, nullptr, 0, m->X, B, m->W1T,
+                           m->W2T, m->W3T, m->P + P_B1, m->P + P_B2, m->b3p, m->OUT, D_OUTP, D_OUTP, m->PRE1, m->H1,
+                           m->PRE2, m->H2);
+    } else {
+        int rc = forward_bf16(m, B, m->OUT, D_OUTP, D_OUTP, st);
+        if (rc) return rc;
+    }
     const int sp = k_splits(B);
     const int nll_blocks = (B * 128 + 255) / 256;
     hipLaunchKernelGGL(k_nll, dim3(nll_blocks), dim3(256), 0, st, m->OUT, D_OUTP, U, B, N, sig_a, sig_d, m->D, D_OUTP,

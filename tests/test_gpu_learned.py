@@ -60,14 +60,16 @@ def _net(seed=3, scale3=1.0):
 
 
 @pytest.mark.parametrize("B,N,scale3", [(200, 50, 3.0), (1500, 40, 3.0), (64, 20, 3.0), (333, 50, 10.0),
-                                        (4500, 50, 3.0)])
+                                        (4500, 50, 3.0), (8500, 30, 3.0)])
 def test_mlp_gradient_step_matches_oracle_lockstep(B, N, scale3):
     """Loss, outputs and every parameter gradient of one gradient call against the oracle's
     network in its BF16-operand mode, element by element: each BF16 hidden activation and
     gradient of the kernels must be a rounding within the derived bound of the oracle's
     value (and the oracle continues from it); outputs, loss and gradients are then within
     the float32-accumulation bound of the oracle's.  The forward entry point (fused kernel
-    up to 4096 rows, tiled products above) returns the gradient call's outputs bit for bit."""
+    up to 4096 rows, tiled products above) returns the gradient call's outputs bit for bit;
+    the gradient call's own forward is the fused kernel up to 8192 rows (every case but the
+    last) and the tiled products above."""
     import torch
     import paper_2607_25388_amd.sgtp as sg
     flat, P = _net(seed=B, scale3=scale3)
