@@ -419,13 +419,12 @@ __device__ __forceinline__ void loss_total(const float *part, int n, int B, floa
 struct SliceSum {
     const float *src;
     long long zs;
-    int rows, cols, lds, ldd;
+    int n_slices, rows, cols, lds, ldd;
     float *dst, *dst_last;
 };
 struct FinishArgs {
     SliceSum s[3];
     int first[4];  // block ranges; block first[3] computes the loss
-    int n_slices;
     const float *lp;
     int n_lp, B;
     float *loss, *loss2;
@@ -443,7 +442,7 @@ __global__ void k_grad_finish(FinishArgs f) {
     const int r = e / d.cols, c = e % d.cols;
     const float *q = d.src + (long long)r * d.lds + c;
     float v = q[0];
-    for (int z = 1; z < f.n_slices; ++z) v += q[z * d.zs];
+    for (int z = 1; z < d.n_slices; ++z) v += q[z * d.zs];
     if (d.dst_last && r == d.rows - 1) d.dst_last[c] = v;
     else d.dst[(long long)r * d.ldd + c] = v;
 }
@@ -527,9 +526,14 @@ int mfail(sgtp_mlp *m, int code, const std::string &s) {
         if (e_ != hipSuccess) return mfail(m, SGTP_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-// K split of a weight-gradient product (K = batch): about 512 rows per slice, at most 64 slices
+// K split of a weight-gradient product (K = batch, output (M + 1) x N): enough slices for
+// about 512 workgroups, each slice at least one 64-k chunk, at most 64 slices
 constexpr int MAX_SPLITS = 64;
-int k_splits(int K) { return std::max(1, std::min(MAX_SPLITS, (K + 511) / 512)); }
+int k_splits(int M, int N, int K) {
+    const int tiles = ((N + 63) / 64) * ((M + 1 + 63) / 64);
+    const int s = std::min((512 + tiles - 1) / tiles, std::max(1, K / 64));
+    return std::max(1, std::min(MAX_SPLITS, s));
+}
 
 // staging of an operand with element strides (s_r along its rows, s_k along k): 16-byte
 // vectors where the unit stride and the alignment allow them
@@ -560,7 +564,7 @@ SliceSum gemm_wgrad(hipStream_t st, float *part, const bf16 *A, long long a_m, l
     GemmArgs g{A, a_m, a_k, B, b_k, b_n, R, N, K, nullptr, part, N, (long long)R * N, nullptr, 0, nullptr,
                stage_mode(A, a_m, a_k), stage_mode(B, b_n, b_k), M};
     hipLaunchKernelGGL(k_gemm_bf16, dim3((N + 63) / 64, (R + 63) / 64, splits), dim3(256), 0, st, g);
-    return SliceSum{part, (long long)R * N, R, N, N, ldd, dst, bias_dst};
+    return SliceSum{part, (long long)R * N, splits, R, N, N, ldd, dst, bias_dst};
 }
 
 // forward of B rows (features float32 [B][ldx]) into out[B][ldo], n_out columns (200, or
@@ -700,7 +704,6 @@ int grad_rows(sgtp_mlp *m, const float *U, int B, int N, float sig_a, float sig_
         int rc = forward_bf16(m, B, m->OUT, D_OUTP, D_OUTP, st);
         if (rc) return rc;
     }
-    const int sp = k_splits(B);
     const int nll_blocks = (B * 128 + 255) / 256;
     hipLaunchKernelGGL(k_nll, dim3(nll_blocks), dim3(256), 0, st, m->OUT, D_OUTP, U, B, N, sig_a, sig_d, m->D, D_OUTP,
                        m->LP);
@@ -709,19 +712,18 @@ int grad_rows(sgtp_mlp *m, const float *U, int B, int N, float sig_a, float sig_
     FinishArgs fa{};
     // layer 3: gW3 = H2^T D and gb3 = column sums of D (one product), dH2 = D W3^T
     fa.s[0] = gemm_wgrad(st, m->PART, m->H2, 1, D_H, m->D, D_OUTP, 1, D_H, D_OUT, B, m->G + P_W3, D_OUT,
-                         m->G + P_B3, sp);
+                         m->G + P_B3, k_splits(D_H, D_OUT, B));
     gemm(st, m->D, D_OUTP, 1, m->W3, 1, D_OUTP, B, D_H, D_OUTP, nullptr, nullptr, 0, m->D2, D_H, m->PRE2);
     // layer 2: gW2 = H1^T D2, gb2, dH1 = D2 W2^T
     fa.s[1] = gemm_wgrad(st, m->PART + third, m->H1, 1, D_H, m->D2, D_H, 1, D_H, D_H, B, m->G + P_W2, D_H,
-                         m->G + P_B2, sp);
+                         m->G + P_B2, k_splits(D_H, D_H, B));
     gemm(st, m->D2, D_H, 1, m->W2, 1, D_H, B, D_H, D_H, nullptr, nullptr, 0, m->D1, D_H, m->PRE1);
     // layer 1: gW1 = X^T D1, gb1
     fa.s[2] = gemm_wgrad(st, m->PART + 2 * third, m->X, 1, D_INP, m->D1, D_H, 1, D_IN, D_H, B, m->G + P_W1, D_H,
-                         m->G + P_B1, sp);
+                         m->G + P_B1, k_splits(D_IN, D_H, B));
     // the slice sums and the loss in one launch
     fa.first[0] = 0;
     for (int l = 0; l < 3; ++l) fa.first[l + 1] = fa.first[l] + (fa.s[l].rows * fa.s[l].cols + 255) / 256;
-    fa.n_slices = sp;
     fa.lp = m->LP;
     fa.n_lp = 4 * nll_blocks;
     fa.B = B;
