@@ -441,8 +441,19 @@ __global__ void k_grad_finish(FinishArgs f) {
     if (e >= d.rows * d.cols) return;
     const int r = e / d.cols, c = e % d.cols;
     const float *q = d.src + (long long)r * d.lds + c;
+    // loads issued up to 32 at a time, added in slice order (the sum is the same as one at
+    // a time)
+    constexpr int G = 32;
+    const int n = d.n_slices;
     float v = q[0];
-    for (int z = 1; z < d.n_slices; ++z) v += q[z * d.zs];
+    for (int z = 1; z < n; z += G) {
+        float t[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) t[j] = z + j < n ? q[(z + j) * d.zs] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            if (z + j < n) v += t[j];
+    }
     if (d.dst_last && r == d.rows - 1) d.dst_last[c] = v;
     else d.dst[(long long)r * d.ldd + c] = v;
 }
