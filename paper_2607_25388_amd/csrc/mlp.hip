@@ -34,6 +34,10 @@ constexpr int D_OUTP = 256;          // padded output width
 constexpr int N_H = SGTP_MLP_OUT / 4;
 constexpr float A_SCALE = 4.0f, D_SCALE = 0.2f, LS_MIN = -4.0f, LS_MAX = 1.0f;
 constexpr int FUSED_MAX_ROWS = 4096;  // forward batches up to this size use the fused kernel
+// waves per workgroup of the fused forward: one 16-column tile per wave and layer (16 rows
+// per workgroup leave one workgroup per CU at planning and training batch sizes, so the
+// waves are what hides the latency)
+constexpr int FWD_WAVES = 16;
 
 // packed float32 parameter layout (the oracle's): W1[50][256] b1 W2[256][256] b2 W3[256][200] b3
 constexpr size_t P_W1 = 0, P_B1 = P_W1 + (size_t)D_IN * D_H, P_W2 = P_B1 + D_H, P_B2 = P_W2 + (size_t)D_H * D_H,
@@ -293,30 +297,86 @@ __device__ __forceinline__ f32x4 mfma_rows16(const bf16 *A, int lda, const bf16 
     return acc;
 }
 
+// Gaussian negative log-likelihood of target u for step t < 64, channel c (0 acceleration,
+// 1 steering) of one row whose outputs are o[256] (mean over B rows; constant 0.5 log 2 pi
+// dropped; steps t >= N do not enter): its term is returned, its gradient w.r.t. the
+// outputs written as BF16 to g[4 t + c] (mean) and g[4 t + 2 + c] (log scale).
+__device__ __forceinline__ float nll_term(const float *o, const float *u_row, int t, int c, int N, float sig_a,
+                                          float sig_d, int B, bf16 *g) {
+    if (t >= N) {
+        g[4 * t + c] = (bf16)0.0f;
+        g[4 * t + 2 + c] = (bf16)0.0f;
+        return 0.0f;
+    }
+    const float scale = c ? D_SCALE : A_SCALE;
+    const float lsp = logf(c ? sig_d : sig_a);
+    const float mu = scale * o[4 * t + c];
+    const float raw = o[4 * t + 2 + c];
+    const float cl = fminf(fmaxf(raw, LS_MIN), LS_MAX);
+    const float ls = lsp + cl;
+    const float inv_s2 = expf(-2.0f * ls);
+    const float res = u_row[2 * t + c] - mu;
+    g[4 * t + c] = (bf16)(-scale * res * inv_s2 / (float)B);
+    g[4 * t + 2 + c] = (bf16)((raw > LS_MIN && raw < LS_MAX) ? (1.0f - res * res * inv_s2) / (float)B : 0.0f);
+    return 0.5f * res * res * inv_s2 + ls;
+}
+
+// What a training forward also does: where its rows come from (row b of X and U, or, with
+// M > 0, a data-set row drawn as k_gather_sampled draws it, recorded in idx), the rows'
+// BF16 operands it leaves for the backward pass, and the loss gradient it ends with.
+struct TrainIn {
+    const float *U;  // targets [.][N][2], rows indexed like the features
+    long long M;     // data-set rows when the minibatch is drawn, else 0
+    uint32_t k0, k1;
+    const int *t;    // Adam steps taken (the draw's counter)
+    int *idx;        // [B] drawn rows
+    bf16 *Xb;        // [B][64] BF16 features (zero padding)
+    int N;
+    float sig_a, sig_d;
+    bf16 *dout;       // [B][256] loss gradient w.r.t. the outputs
+    float *loss_part; // [2 B] loss partials: row b steps 0-31 at 2 b, steps 32-63 at 2 b + 1
+};
+
 // Fused forward of 16 rows per workgroup: the three layers run back to back with the
-// hidden activations in LDS (BF16, as the tiled path stores them).  TRAIN: the input rows
-// are the BF16 operands already in Xb ([B][64]), and the pre-activations (float32) and
-// activations (BF16) of both hidden layers are also written out ([B][256] each), as the
-// tiled products write them for the backward pass.
-template <bool TRAIN>
-__global__ void __launch_bounds__(256) k_mlp_fwd16(const float *X, int ldx, const bf16 *Xb, int B, const bf16 *W1T,
-                                                  const bf16 *W2T, const bf16 *W3T, const float *b1, const float *b2,
-                                                  const float *b3, float *out, int ldo, int n_out, float *pre1,
-                                                  bf16 *h1o, float *pre2, bf16 *h2o) {
-    constexpr int LX = D_INP + 8, LH = D_H + 8;  // padded rows (16-byte aligned)
+// hidden activations in LDS (BF16, as the tiled path stores them).  TRAIN: the rows are
+// fetched (drawn or not) from X, their BF16 operands written to Xb; the pre-activations
+// (float32) and activations (BF16) of both hidden layers are also written out ([B][256]
+// each), as the tiled products write them for the backward pass; and the loss and its
+// gradient are taken from the output tile, as k_nll takes them (same lane -> (step,
+// channel) map, same per-wave sums).
+template <bool TRAIN, int NW>
+__global__ void __launch_bounds__(64 * NW) k_mlp_fwd16(const float *X, int ldx, int B, const bf16 *W1T, const bf16 *W2T,
+                                                  const bf16 *W3T, const float *b1, const float *b2, const float *b3,
+                                                  float *out, int ldo, int n_out, float *pre1, bf16 *h1o, float *pre2,
+                                                  bf16 *h2o, TrainIn ti) {
+    constexpr int LX = D_INP + 8, LH = D_H + 8, LO = D_OUTP + 4;  // padded rows
     __shared__ __align__(16) bf16 xs[16 * LX];
     __shared__ __align__(16) bf16 h1[16 * LH];
     __shared__ __align__(16) bf16 h2[16 * LH];
+    __shared__ float os[TRAIN ? 16 * LO : 1];
+    __shared__ long long src[16];
     const int r0 = blockIdx.x * 16, tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-    for (int e = tid; e < 16 * D_INP; e += 256) {
+    if (tid < 16) {
+        const int b = r0 + tid;
+        long long i = b;
+        if (TRAIN && ti.M > 0 && b < B) {
+            const uint4 r = philox4x32_10(make_uint4((uint32_t)b, (uint32_t)*ti.t, 0u, 0u), ti.k0, ti.k1);
+            i = (long long)(((unsigned long long)r.x * (unsigned long long)ti.M) >> 32);
+            ti.idx[b] = (int)i;
+        }
+        src[tid] = i;
+    }
+    __syncthreads();
+    for (int e = tid; e < 16 * D_INP; e += 64 * NW) {
         const int r = e / D_INP, c = e % D_INP;
-        if (TRAIN) xs[r * LX + c] = (r0 + r < B) ? Xb[(long long)(r0 + r) * D_INP + c] : (bf16)0.0f;
-        else xs[r * LX + c] = (r0 + r < B && c < D_IN) ? (bf16)X[(long long)(r0 + r) * ldx + c] : (bf16)0.0f;
+        const bf16 v = (r0 + r < B && c < D_IN) ? (bf16)X[src[r] * ldx + c] : (bf16)0.0f;
+        xs[r * LX + c] = v;
+        if (TRAIN && r0 + r < B) ti.Xb[(long long)(r0 + r) * D_INP + c] = v;
     }
     __syncthreads();
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {  // layer 1: each wave 4 column tiles of 16
-        const int n0 = 16 * (4 * w + jj);
+    for (int jj = 0; jj < 16 / NW; ++jj) {  // layer 1: 16 column tiles of 16 over the NW waves
+        const int n0 = 16 * (w + NW * jj);
         const f32x4 acc = mfma_rows16(xs, LX, W1T, D_INP, n0, l);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -332,8 +392,8 @@ __global__ void __launch_bounds__(256) k_mlp_fwd16(const float *X, int ldx, cons
     }
     __syncthreads();
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {  // layer 2
-        const int n0 = 16 * (4 * w + jj);
+    for (int jj = 0; jj < 16 / NW; ++jj) {  // layer 2
+        const int n0 = 16 * (w + NW * jj);
         const f32x4 acc = mfma_rows16(h1, LH, W2T, D_H, n0, l);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -349,47 +409,44 @@ __global__ void __launch_bounds__(256) k_mlp_fwd16(const float *X, int ldx, cons
     }
     __syncthreads();
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {  // layer 3 (columns >= n_out dropped)
-        const int n0 = 16 * (4 * w + jj);
+    for (int jj = 0; jj < 16 / NW; ++jj) {  // layer 3 (columns >= n_out dropped)
+        const int n0 = 16 * (w + NW * jj);
         if (n0 >= n_out) continue;
         const f32x4 acc = mfma_rows16(h2, LH, W3T, D_H, n0, l);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = 4 * (l >> 4) + v, col = n0 + (l & 15);
-            if (r0 + row < B && col < n_out) out[(long long)(r0 + row) * ldo + col] = acc[v] + b3[col];
+            const float o = acc[v] + b3[col];
+            if (TRAIN) os[row * LO + col] = o;
+            if (r0 + row < B && col < n_out) out[(long long)(r0 + row) * ldo + col] = o;
+        }
+    }
+    if (TRAIN) {
+        __syncthreads();
+        // 32 groups of 64 (step, channel) pairs: row vg / 2, steps 32 (vg & 1) + 0..31
+        for (int vg = w; vg < 32; vg += NW) {
+            const int row = vg >> 1, b = r0 + row;
+            if (b >= B) break;
+            const int t = 32 * (vg & 1) + (l >> 1), c = l & 1;
+            float contrib = nll_term(os + row * LO, ti.U + src[row] * 2 * ti.N, t, c, ti.N, ti.sig_a, ti.sig_d, B,
+                                     ti.dout + (long long)b * D_OUTP);
+            for (int off = 32; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off);
+            if (l == 0) ti.loss_part[2 * b + (vg & 1)] = contrib;
         }
     }
 }
 
-// Gaussian negative log-likelihood of the targets U[B][N][2] (mean over rows, constant
-// 0.5 log 2 pi dropped; steps t >= N do not enter) and its gradient w.r.t. the outputs,
-// as BF16 for the products.  One thread per (row, step < 64, channel).
+// The same loss and gradient from outputs in memory (the tiled path), targets U[B][N][2].
+// One thread per (row, step < 64, channel); one partial per wave, summed in order by
+// k_grad_finish.
 __global__ void k_nll(const float *out, int ldo, const float *U, int B, int N, float sig_a, float sig_d, bf16 *dout,
                       int ldd, float *loss_part) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = e >> 7, t = (e >> 1) & 63, c = e & 1;
     float contrib = 0.0f;
-    if (b < B && 4 * t < ldd) {
-        bf16 *g = dout + (long long)b * ldd;
-        if (t < N) {
-            const float *o = out + (long long)b * ldo;
-            const float scale = c ? D_SCALE : A_SCALE;
-            const float lsp = logf(c ? sig_d : sig_a);
-            const float mu = scale * o[4 * t + c];
-            const float raw = o[4 * t + 2 + c];
-            const float cl = fminf(fmaxf(raw, LS_MIN), LS_MAX);
-            const float ls = lsp + cl;
-            const float inv_s2 = expf(-2.0f * ls);
-            const float res = U[((long long)b * N + t) * 2 + c] - mu;
-            contrib = 0.5f * res * res * inv_s2 + ls;
-            g[4 * t + c] = (bf16)(-scale * res * inv_s2 / (float)B);
-            g[4 * t + 2 + c] = (bf16)((raw > LS_MIN && raw < LS_MAX) ? (1.0f - res * res * inv_s2) / (float)B : 0.0f);
-        } else {
-            g[4 * t + c] = (bf16)0.0f;
-            g[4 * t + 2 + c] = (bf16)0.0f;
-        }
-    }
-    // wave reduction of the loss; one partial per wave (summed in order by k_grad_finish)
+    if (b < B && 4 * t < ldd)
+        contrib = nll_term(out + (long long)b * ldo, U + (long long)b * N * 2, t, c, N, sig_a, sig_d, B,
+                           dout + (long long)b * ldd);
     for (int off = 32; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off);
     if ((threadIdx.x & 63) == 0) loss_part[e >> 6] = contrib;
 }
@@ -689,9 +746,9 @@ int sgtp_mlp_forward(sgtp_mlp *m, const float *X, int B, float *out, int ld_out,
     if (ld_out < D_OUT) return mfail(m, SGTP_EINVAL, "ld_out < 200");
     hipStream_t st = (hipStream_t)stream;
     if (B <= FUSED_MAX_ROWS) {  // planning-size batches: one fused kernel
-        hipLaunchKernelGGL(k_mlp_fwd16<false>, dim3((B + 15) / 16), dim3(256), 0, st, X, D_IN, nullptr, B, m->W1T,
-                           m->W2T, m->W3T, m->P + P_B1, m->P + P_B2, m->P + P_B3, out, ld_out, D_OUT, nullptr, nullptr,
-                           nullptr, nullptr);
+        hipLaunchKernelGGL((k_mlp_fwd16<false, FWD_WAVES>), dim3((B + 15) / 16), dim3(64 * FWD_WAVES), 0, st, X, D_IN, B, m->W1T, m->W2T,
+                           m->W3T, m->P + P_B1, m->P + P_B2, m->P + P_B3, out, ld_out, D_OUT, nullptr, nullptr, nullptr,
+                           nullptr, TrainIn{});
         MCHK(m, hipGetLastError());
         return SGTP_OK;
     }
@@ -704,20 +761,40 @@ namespace {
 // the same bits.
 constexpr int FUSED_TRAIN_MAX = 8192;
 
-// The gradient once the BF16 operands of the B rows are in m->X (targets U [B][N][2])
-int grad_rows(sgtp_mlp *m, const float *U, int B, int N, float sig_a, float sig_d, float *loss, float *grads,
+// Where the B rows of a gradient come from: features X [.][50] and targets U [.][N][2],
+// row b of each, or (M > 0) rows drawn from a data set of M rows with Philox key (k0, k1)
+struct RowSrc {
+    const float *X, *U;
+    long long M;
+    uint32_t k0, k1;
+};
+
+int grad_rows(sgtp_mlp *m, const RowSrc &rs, int B, int N, float sig_a, float sig_d, float *loss, float *grads,
               hipStream_t st) {
-    if (B <= FUSED_TRAIN_MAX) {
-        hipLaunchKernelGGL(k_mlp_fwd16<true>, dim3((B + 15) / 16), dim3(256), 0, st, nullptr, 0, m->X, B, m->W1T,
-                           m->W2T, m->W3T, m->P + P_B1, m->P + P_B2, m->b3p, m->OUT, D_OUTP, D_OUTP, m->PRE1, m->H1,
-                           m->PRE2, m->H2);
+    int n_lp;
+    if (B <= FUSED_TRAIN_MAX) {  // fetch, forward and loss gradient in one launch
+        const TrainIn ti{rs.U, rs.M, rs.k0, rs.k1, m->adam_t, m->IDX, m->X, N, sig_a, sig_d, m->D, m->LP};
+        hipLaunchKernelGGL((k_mlp_fwd16<true, FWD_WAVES>), dim3((B + 15) / 16), dim3(64 * FWD_WAVES), 0, st, rs.X, D_IN, B, m->W1T, m->W2T,
+                           m->W3T, m->P + P_B1, m->P + P_B2, m->b3p, m->OUT, D_OUTP, D_OUTP, m->PRE1, m->H1, m->PRE2,
+                           m->H2, ti);
+        n_lp = 2 * B;
     } else {
+        const float *U = rs.U;
+        if (rs.M > 0) {
+            hipLaunchKernelGGL(k_gather_sampled, dim3(B), dim3(128), 0, st, rs.X, rs.U, rs.M, N, rs.k0, rs.k1,
+                               m->adam_t, m->X, m->UB, m->IDX);
+            U = m->UB;
+        } else {
+            hipLaunchKernelGGL(k_to_bf16_rows, dim3((B * D_INP + 255) / 256), dim3(256), 0, st, rs.X, B, D_IN, D_IN,
+                               m->X, D_INP);
+        }
         int rc = forward_bf16(m, B, m->OUT, D_OUTP, D_OUTP, st);
         if (rc) return rc;
+        const int nll_blocks = (B * 128 + 255) / 256;
+        hipLaunchKernelGGL(k_nll, dim3(nll_blocks), dim3(256), 0, st, m->OUT, D_OUTP, U, B, N, sig_a, sig_d, m->D,
+                           D_OUTP, m->LP);
+        n_lp = 4 * nll_blocks;
     }
-    const int nll_blocks = (B * 128 + 255) / 256;
-    hipLaunchKernelGGL(k_nll, dim3(nll_blocks), dim3(256), 0, st, m->OUT, D_OUTP, U, B, N, sig_a, sig_d, m->D, D_OUTP,
-                       m->LP);
     // partial products of the three weight-and-bias gradients go to separate thirds of PART
     const size_t third = (size_t)MAX_SPLITS * (D_H + 1) * D_OUTP;
     FinishArgs fa{};
@@ -736,7 +813,7 @@ int grad_rows(sgtp_mlp *m, const float *U, int B, int N, float sig_a, float sig_
     fa.first[0] = 0;
     for (int l = 0; l < 3; ++l) fa.first[l + 1] = fa.first[l] + (fa.s[l].rows * fa.s[l].cols + 255) / 256;
     fa.lp = m->LP;
-    fa.n_lp = 4 * nll_blocks;
+    fa.n_lp = n_lp;
     fa.B = B;
     fa.loss = m->loss;
     fa.loss2 = loss;
@@ -759,11 +836,8 @@ int sgtp_mlp_grad(sgtp_mlp *m, const float *X, const float *U, int B, int N, flo
                   float *grads, void *stream) {
     if (!m || !X || !U) return SGTP_EINVAL;
     if (int rc = check_grad_args(m, B, N, sig_a, sig_d)) return rc;
-    hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_to_bf16_rows, dim3((B * D_INP + 255) / 256), dim3(256), 0, st, X, B, D_IN, D_IN, m->X,
-                       D_INP);
     m->last_sampled = false;
-    return grad_rows(m, U, B, N, sig_a, sig_d, loss, grads, st);
+    return grad_rows(m, RowSrc{X, U, 0, 0, 0}, B, N, sig_a, sig_d, loss, grads, (hipStream_t)stream);
 }
 
 int sgtp_mlp_grad_sampled(sgtp_mlp *m, const float *X_all, const float *U_all, long long M, int B, int N,
@@ -771,11 +845,9 @@ int sgtp_mlp_grad_sampled(sgtp_mlp *m, const float *X_all, const float *U_all, l
     if (!m || !X_all || !U_all) return SGTP_EINVAL;
     if (M < 1 || M > 0x7fffffffLL) return mfail(m, SGTP_ESHAPE, "data set rows outside [1, 2^31 - 1]");
     if (int rc = check_grad_args(m, B, N, sig_a, sig_d)) return rc;
-    hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_gather_sampled, dim3(B), dim3(128), 0, st, X_all, U_all, M, N, (uint32_t)seed,
-                       (uint32_t)(seed >> 32), m->adam_t, m->X, m->UB, m->IDX);
     m->last_sampled = true;
-    return grad_rows(m, m->UB, B, N, sig_a, sig_d, loss, grads, st);
+    return grad_rows(m, RowSrc{X_all, U_all, M, (uint32_t)seed, (uint32_t)(seed >> 32)}, B, N, sig_a, sig_d, loss,
+                     grads, (hipStream_t)stream);
 }
 
 int sgtp_mlp_workspace(sgtp_mlp *m, int which, void *dst, void *stream) {

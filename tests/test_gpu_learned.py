@@ -166,23 +166,25 @@ def test_training_step_graph_replays_match_eager_steps():
     mb.close()
 
 
-def test_sampled_gradient_draws_its_rows_and_matches_the_plain_gradient(oracle_lib):
+@pytest.mark.parametrize("M,B,B_max", [(2777, 700, 1024), (12000, 8500, 8704)])
+def test_sampled_gradient_draws_its_rows_and_matches_the_plain_gradient(oracle_lib, M, B, B_max):
     """sgtp_mlp_grad_sampled: the rows it draws are floor(r M / 2^32) with r the first
     Philox4x32-10 word at counter (row, Adam step, 0, 0) and the seed's two halves as key
     (checked against the oracle's Philox), and its loss and gradient equal those of
     sgtp_mlp_grad on the same rows gathered on the host, bit for bit; after an Adam step
-    the next call draws other rows."""
+    the next call draws other rows.  700 rows take the fused forward (which draws and
+    fetches the rows itself), 8500 the tiled products after a gather kernel."""
     import ctypes as C
     import torch
     import paper_2607_25388_amd.sgtp as sg
     flat, _ = _net(seed=21, scale3=3.0)
     rng = np.random.default_rng(11)
-    M, N, B, seed = 2777, 40, 700, 0x1234_5678_9ABC_DEF0
+    N, seed = 40, 0x1234_5678_9ABC_DEF0
     X = torch.as_tensor(rng.standard_normal((M, 50)).astype(np.float32)).cuda()
     U = torch.as_tensor(np.stack([rng.uniform(-8, 4, (M, N)), rng.uniform(-0.4, 0.4, (M, N))], -1)
                         .astype(np.float32)).cuda()
     params = {"sigma_a": 1.5, "sigma_d": 0.08}
-    m = sg.Mlp(1024, flat)
+    m = sg.Mlp(B_max, flat)
     lib = oracle_lib
     lib.ref_philox4x32_10.argtypes = [C.POINTER(C.c_uint32)] * 3
     key = (C.c_uint32 * 2)(seed & 0xFFFFFFFF, seed >> 32)
@@ -198,7 +200,7 @@ def test_sampled_gradient_draws_its_rows_and_matches_the_plain_gradient(oracle_l
 
     try:
         for step in range(2):
-            print(f"sampled gradient, Adam step {step}", flush=True)
+            print(f"sampled gradient, {B} of {M} rows, Adam step {step}", flush=True)
             ls, gs = m.grad_sampled(X, U, B, seed, params["sigma_a"], params["sigma_d"], want_grads=True)
             idx = m.workspace("idx").cpu().numpy().astype(np.int64)
             assert np.array_equal(idx, expected_rows(step))
