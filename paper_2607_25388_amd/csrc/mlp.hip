@@ -147,10 +147,11 @@ __device__ __forceinline__ float gelu_grad_f(float x) {
     return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * c * (1.0f + 3.0f * 0.044715f * x * x);
 }
 
-__global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
+// One 64 x 64 tile (column tile bx, row tile by) of K slice bz of nz.
+__device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bx, int by, int bz, int nz) {
     __shared__ __align__(16) bf16 As[2][64][LROW];  // [buffer][m][k]
     __shared__ __align__(16) bf16 Bs[2][64][LROW];  // [buffer][n][k]
-    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int m0 = by * 64, n0 = bx * 64;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
     f32x4 acc[2][2];
@@ -158,11 +159,11 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
-    // split K: slice z of gridDim.z covers [kbeg, kend) (a multiple of 32 long, but the
+    // split K: slice bz of nz covers [kbeg, kend) (a multiple of 32 long, but the
     // last) and writes its partial product to its own slice of C (summed afterwards in
     // slice order: the result does not depend on timing)
-    const int kslice = ((g.K + 32 * gridDim.z - 1) / (32 * gridDim.z)) * 32;
-    const int kbeg = blockIdx.z * kslice, kend = min(g.K, kbeg + kslice);
+    const int kslice = ((g.K + 32 * nz - 1) / (32 * nz)) * 32;
+    const int kbeg = bz * kslice, kend = min(g.K, kbeg + kslice);
     const int nk = kend > kbeg ? (kend - kbeg + GK - 1) / GK : 0;
     u16x8 va[2], vb[2];
     if (nk > 0) {
@@ -209,8 +210,8 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
                 const int n = n0 + wn + 16 * j + (l & 15);
                 if (m < g.M && n < g.N) {
                     float x = acc[i][j][v];
-                    if (gridDim.z > 1) {
-                        g.C[blockIdx.z * g.c_split + (long long)m * g.ldc + n] = x;
+                    if (nz > 1) {
+                        g.C[bz * g.c_split + (long long)m * g.ldc + n] = x;
                         continue;
                     }
                     if (g.bias) x += g.bias[n];
@@ -220,6 +221,24 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
                             g.gpre ? (bf16)(x * gelu_grad_f(g.gpre[(long long)m * g.ldh + n])) : (bf16)gelu_f(x);
                 }
             }
+}
+
+__global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
+    gemm_tile(g, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.z);
+}
+
+// Up to three independent products in one launch: blocks [first[p], first[p + 1]) are
+// product p's grid gx[p] x gy[p] x gz[p] (x fastest), each block as k_gemm_bf16's.
+struct GemmGroup {
+    GemmArgs g[3];
+    int gx[3], gy[3], gz[3];
+    int first[4];
+};
+__global__ void __launch_bounds__(256) k_gemm_bf16_group(GemmGroup gg) {
+    const int bid = blockIdx.x;
+    const int p = bid < gg.first[1] ? 0 : bid < gg.first[2] ? 1 : 2;
+    const int q = bid - gg.first[p], gx = gg.gx[p], gy = gg.gy[p];
+    gemm_tile(gg.g[p], q % gx, (q / gx) % gy, q / (gx * gy), gg.gz[p]);
 }
 
 __global__ void k_to_bf16_rows(const float *X, int B, int din, int ldx, bf16 *Y, int ldy) {
@@ -451,6 +470,56 @@ __global__ void k_nll(const float *out, int ldo, const float *U, int B, int N, f
     if ((threadIdx.x & 63) == 0) loss_part[e >> 6] = contrib;
 }
 
+// Fused input gradients of 16 rows per workgroup, the backward counterpart of k_mlp_fwd16:
+// D2 = BF16((D W3^T) GELU'(pre2)), kept in LDS, then D1 = BF16((D2 W2^T) GELU'(pre1));
+// both written out for the weight gradients.  Same lane -> (row, k) map and k order as the
+// tiled products, so the same bits.
+__global__ void __launch_bounds__(64 * FWD_WAVES) k_mlp_bwd16(const bf16 *D, const bf16 *W3, const bf16 *W2,
+                                                             const float *pre2, const float *pre1, int B, bf16 *D2,
+                                                             bf16 *D1) {
+    constexpr int NW = FWD_WAVES, LH = D_H + 8;
+    __shared__ __align__(16) bf16 ds[16 * LH];
+    __shared__ __align__(16) bf16 d2s[16 * LH];
+    const int r0 = blockIdx.x * 16, tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    for (int e = tid; e < 16 * (D_OUTP / 8); e += 64 * NW) {  // 16-byte vectors of 8 columns
+        const int r = e / (D_OUTP / 8), c = 8 * (e % (D_OUTP / 8));
+        u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (r0 + r < B) v = *(const u16x8 *)&D[(long long)(r0 + r) * D_OUTP + c];
+        *(u16x8 *)&ds[r * LH + c] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < 16 / NW; ++jj) {  // D2: 16 column tiles of 16 over the NW waves
+        const int n0 = 16 * (w + NW * jj);
+        const f32x4 acc = mfma_rows16(ds, LH, W3, D_OUTP, n0, l);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 4 * (l >> 4) + v, col = n0 + (l & 15);
+            bf16 h = (bf16)0.0f;
+            if (r0 + row < B) {
+                const long long o = (long long)(r0 + row) * D_H + col;
+                h = (bf16)(acc[v] * gelu_grad_f(pre2[o]));
+                D2[o] = h;
+            }
+            d2s[row * LH + col] = h;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < 16 / NW; ++jj) {  // D1
+        const int n0 = 16 * (w + NW * jj);
+        const f32x4 acc = mfma_rows16(d2s, LH, W2, D_H, n0, l);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 4 * (l >> 4) + v, col = n0 + (l & 15);
+            if (r0 + row < B) {
+                const long long o = (long long)(r0 + row) * D_H + col;
+                D1[o] = (bf16)(acc[v] * gelu_grad_f(pre1[o]));
+            }
+        }
+    }
+}
+
 // loss = (sum of the per-wave partials, in a fixed order) / B, by one block of 256 threads;
 // also written to loss2 when it is given
 __device__ __forceinline__ void loss_total(const float *part, int n, int B, float *loss, float *loss2) {
@@ -624,14 +693,18 @@ void gemm(hipStream_t st, const bf16 *A, long long a_m, long long a_k, const bf1
 // weight gradient dst[M][ldd] (first N columns) = A B and bias gradient bias_dst[N] =
 // column sums of B, as one product with an extra row of ones in A, K split into `splits`
 // slices: partial products into `part` [splits][M + 1][N]; the slices are summed in order
-// by k_grad_finish (its descriptor is returned)
-SliceSum gemm_wgrad(hipStream_t st, float *part, const bf16 *A, long long a_m, long long a_k, const bf16 *B,
+// by k_grad_finish (its descriptor is returned).  The product becomes member p of the
+// group launch grp.
+SliceSum gemm_wgrad(GemmGroup &grp, int p, float *part, const bf16 *A, long long a_m, long long a_k, const bf16 *B,
                     long long b_k, long long b_n, int M, int N, int K, float *dst, int ldd, float *bias_dst,
                     int splits) {
     const int R = M + 1;  // row M of A reads as 1: the bias gradient
-    GemmArgs g{A, a_m, a_k, B, b_k, b_n, R, N, K, nullptr, part, N, (long long)R * N, nullptr, 0, nullptr,
-               stage_mode(A, a_m, a_k), stage_mode(B, b_n, b_k), M};
-    hipLaunchKernelGGL(k_gemm_bf16, dim3((N + 63) / 64, (R + 63) / 64, splits), dim3(256), 0, st, g);
+    grp.g[p] = GemmArgs{A, a_m, a_k, B, b_k, b_n, R, N, K, nullptr, part, N, (long long)R * N, nullptr, 0, nullptr,
+                        stage_mode(A, a_m, a_k), stage_mode(B, b_n, b_k), M};
+    grp.gx[p] = (N + 63) / 64;
+    grp.gy[p] = (R + 63) / 64;
+    grp.gz[p] = splits;
+    grp.first[p + 1] = grp.first[p] + grp.gx[p] * grp.gy[p] * splits;
     return SliceSum{part, (long long)R * N, splits, R, N, N, ldd, dst, bias_dst};
 }
 
@@ -746,9 +819,9 @@ int sgtp_mlp_forward(sgtp_mlp *m, const float *X, int B, float *out, int ld_out,
     if (ld_out < D_OUT) return mfail(m, SGTP_EINVAL, "ld_out < 200");
     hipStream_t st = (hipStream_t)stream;
     if (B <= FUSED_MAX_ROWS) {  // planning-size batches: one fused kernel
-        hipLaunchKernelGGL((k_mlp_fwd16<false, FWD_WAVES>), dim3((B + 15) / 16), dim3(64 * FWD_WAVES), 0, st, X, D_IN, B, m->W1T, m->W2T,
-                           m->W3T, m->P + P_B1, m->P + P_B2, m->P + P_B3, out, ld_out, D_OUT, nullptr, nullptr, nullptr,
-                           nullptr, TrainIn{});
+        hipLaunchKernelGGL((k_mlp_fwd16<false, FWD_WAVES>), dim3((B + 15) / 16), dim3(64 * FWD_WAVES), 0, st, X,
+                           D_IN, B, m->W1T, m->W2T, m->W3T, m->P + P_B1, m->P + P_B2, m->P + P_B3, out, ld_out, D_OUT,
+                           nullptr, nullptr, nullptr, nullptr, TrainIn{});
         MCHK(m, hipGetLastError());
         return SGTP_OK;
     }
@@ -774,9 +847,9 @@ int grad_rows(sgtp_mlp *m, const RowSrc &rs, int B, int N, float sig_a, float si
     int n_lp;
     if (B <= FUSED_TRAIN_MAX) {  // fetch, forward and loss gradient in one launch
         const TrainIn ti{rs.U, rs.M, rs.k0, rs.k1, m->adam_t, m->IDX, m->X, N, sig_a, sig_d, m->D, m->LP};
-        hipLaunchKernelGGL((k_mlp_fwd16<true, FWD_WAVES>), dim3((B + 15) / 16), dim3(64 * FWD_WAVES), 0, st, rs.X, D_IN, B, m->W1T, m->W2T,
-                           m->W3T, m->P + P_B1, m->P + P_B2, m->b3p, m->OUT, D_OUTP, D_OUTP, m->PRE1, m->H1, m->PRE2,
-                           m->H2, ti);
+        hipLaunchKernelGGL((k_mlp_fwd16<true, FWD_WAVES>), dim3((B + 15) / 16), dim3(64 * FWD_WAVES), 0, st, rs.X,
+                           D_IN, B, m->W1T, m->W2T, m->W3T, m->P + P_B1, m->P + P_B2, m->b3p, m->OUT, D_OUTP, D_OUTP,
+                           m->PRE1, m->H1, m->PRE2, m->H2, ti);
         n_lp = 2 * B;
     } else {
         const float *U = rs.U;
@@ -797,18 +870,24 @@ int grad_rows(sgtp_mlp *m, const RowSrc &rs, int B, int N, float sig_a, float si
     }
     // partial products of the three weight-and-bias gradients go to separate thirds of PART
     const size_t third = (size_t)MAX_SPLITS * (D_H + 1) * D_OUTP;
+    if (B <= FUSED_TRAIN_MAX) {  // dH2 = D W3^T and dH1 = D2 W2^T in one launch
+        hipLaunchKernelGGL(k_mlp_bwd16, dim3((B + 15) / 16), dim3(64 * FWD_WAVES), 0, st, m->D, m->W3, m->W2,
+                           m->PRE2, m->PRE1, B, m->D2, m->D1);
+    } else {
+        gemm(st, m->D, D_OUTP, 1, m->W3, 1, D_OUTP, B, D_H, D_OUTP, nullptr, nullptr, 0, m->D2, D_H, m->PRE2);
+        gemm(st, m->D2, D_H, 1, m->W2, 1, D_H, B, D_H, D_H, nullptr, nullptr, 0, m->D1, D_H, m->PRE1);
+    }
     FinishArgs fa{};
-    // layer 3: gW3 = H2^T D and gb3 = column sums of D (one product), dH2 = D W3^T
-    fa.s[0] = gemm_wgrad(st, m->PART, m->H2, 1, D_H, m->D, D_OUTP, 1, D_H, D_OUT, B, m->G + P_W3, D_OUT,
+    GemmGroup grp{};
+    // gW3 = H2^T D and gb3 = column sums of D (one product); gW2 = H1^T D2, gb2;
+    // gW1 = X^T D1, gb1
+    fa.s[0] = gemm_wgrad(grp, 0, m->PART, m->H2, 1, D_H, m->D, D_OUTP, 1, D_H, D_OUT, B, m->G + P_W3, D_OUT,
                          m->G + P_B3, k_splits(D_H, D_OUT, B));
-    gemm(st, m->D, D_OUTP, 1, m->W3, 1, D_OUTP, B, D_H, D_OUTP, nullptr, nullptr, 0, m->D2, D_H, m->PRE2);
-    // layer 2: gW2 = H1^T D2, gb2, dH1 = D2 W2^T
-    fa.s[1] = gemm_wgrad(st, m->PART + third, m->H1, 1, D_H, m->D2, D_H, 1, D_H, D_H, B, m->G + P_W2, D_H,
+    fa.s[1] = gemm_wgrad(grp, 1, m->PART + third, m->H1, 1, D_H, m->D2, D_H, 1, D_H, D_H, B, m->G + P_W2, D_H,
                          m->G + P_B2, k_splits(D_H, D_H, B));
-    gemm(st, m->D2, D_H, 1, m->W2, 1, D_H, B, D_H, D_H, nullptr, nullptr, 0, m->D1, D_H, m->PRE1);
-    // layer 1: gW1 = X^T D1, gb1
-    fa.s[2] = gemm_wgrad(st, m->PART + 2 * third, m->X, 1, D_INP, m->D1, D_H, 1, D_IN, D_H, B, m->G + P_W1, D_H,
-                         m->G + P_B1, k_splits(D_IN, D_H, B));
+    fa.s[2] = gemm_wgrad(grp, 2, m->PART + 2 * third, m->X, 1, D_INP, m->D1, D_H, 1, D_IN, D_H, B, m->G + P_W1,
+                         D_H, m->G + P_B1, k_splits(D_IN, D_H, B));
+    hipLaunchKernelGGL(k_gemm_bf16_group, dim3(grp.first[3]), dim3(256), 0, st, grp);
     // the slice sums and the loss in one launch
     fa.first[0] = 0;
     for (int l = 0; l < 3; ++l) fa.first[l + 1] = fa.first[l] + (fa.s[l].rows * fa.s[l].cols + 255) / 256;
