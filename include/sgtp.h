@@ -353,6 +353,14 @@ int sgtp_mlp_grad_sampled(sgtp_mlp *m, const float *X_all, const float *U_all, l
                           unsigned long long seed, float sig_a, float sig_d, float *loss, float *grads, void *stream);
 /* One Adam step with the last gradients (bias-corrected moments). */
 int sgtp_mlp_adam(sgtp_mlp *m, float lr, float beta1, float beta2, float eps, void *stream);
+/* One training step: sgtp_mlp_grad_sampled (loss, DEVICE, 1 value, when not NULL) followed
+ * by sgtp_mlp_adam, with the same results bit for bit, but each parameter takes its Adam
+ * step as soon as its gradient is summed (one launch fewer, the gradient not read back).
+ * The gradient is still left for sgtp_mlp_workspace and a later sgtp_mlp_adam.  Errors as
+ * sgtp_mlp_grad_sampled. */
+int sgtp_mlp_train_step_sampled(sgtp_mlp *m, const float *X_all, const float *U_all, long long M, int B, int N,
+                                unsigned long long seed, float sig_a, float sig_d, float lr, float beta1, float beta2,
+                                float eps, float *loss, void *stream);
 /* Make every planning step of `plan` compute the proposal tables itself: after the
  * setup, the features of every vehicle, the network's forward pass and the tables of
  * the races created with prop != NULL (their K_prop samples come from the proposal).

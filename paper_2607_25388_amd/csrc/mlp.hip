@@ -538,52 +538,6 @@ __device__ __forceinline__ void loss_total(const float *part, int n, int B, floa
     }
 }
 
-// One launch that ends the gradient: the slice sums of the three weight-and-bias gradient
-// products (dst[r][c] = the sum over slices z = 0, 1, ... in that order of src[z][r][c]; with
-// dst_last the last row, the bias gradient, goes to dst_last[c]) and, in the last block,
-// the loss.  Blocks [first[l], first[l + 1]) sum product l.
-struct SliceSum {
-    const float *src;
-    long long zs;
-    int n_slices, rows, cols, lds, ldd;
-    float *dst, *dst_last;
-};
-struct FinishArgs {
-    SliceSum s[3];
-    int first[4];  // block ranges; block first[3] computes the loss
-    const float *lp;
-    int n_lp, B;
-    float *loss, *loss2;
-};
-__global__ void k_grad_finish(FinishArgs f) {
-    const int blk = blockIdx.x;
-    if (blk >= f.first[3]) {
-        loss_total(f.lp, f.n_lp, f.B, f.loss, f.loss2);
-        return;
-    }
-    const int l = blk < f.first[1] ? 0 : blk < f.first[2] ? 1 : 2;
-    const SliceSum &d = f.s[l];
-    const int e = (blk - f.first[l]) * blockDim.x + threadIdx.x;
-    if (e >= d.rows * d.cols) return;
-    const int r = e / d.cols, c = e % d.cols;
-    const float *q = d.src + (long long)r * d.lds + c;
-    // loads issued up to 32 at a time, added in slice order (the sum is the same as one at
-    // a time)
-    constexpr int G = 32;
-    const int n = d.n_slices;
-    float v = q[0];
-    for (int z = 1; z < n; z += G) {
-        float t[G];
-#pragma unroll
-        for (int j = 0; j < G; ++j) t[j] = z + j < n ? q[(z + j) * d.zs] : 0.0f;
-#pragma unroll
-        for (int j = 0; j < G; ++j)
-            if (z + j < n) v += t[j];
-    }
-    if (d.dst_last && r == d.rows - 1) d.dst_last[c] = v;
-    else d.dst[(long long)r * d.ldd + c] = v;
-}
-
 // Adam step number t = *t_prev + 1 read on the device (so a captured training step can be
 // replayed); k_step_count advances it after the step
 // The new master weight is also written to the BF16 operand copies (plain and transposed;
@@ -611,20 +565,80 @@ __device__ __forceinline__ void write_copies(const Bf16Copies &w, size_t e, floa
     }
 }
 
-__global__ void k_adam(float *P, const float *G, float *m, float *v, int n, float lr, float b1, float b2, float eps,
-                       const int *t_prev, Bf16Copies copies) {
+struct AdamArgs {
+    float *P, *m, *v;
+    float lr, b1, b2, eps;
+    const int *t_prev;
+    Bf16Copies copies;
+};
+// Adam on parameter e with gradient g (bias-corrected moments, step t = *t_prev + 1)
+__device__ __forceinline__ void adam_update(const AdamArgs &a, size_t e, float g) {
+    const float t = (float)(*a.t_prev + 1);
+    const float bc1 = 1.0f - powf(a.b1, t), bc2 = 1.0f - powf(a.b2, t);
+    const float mm = a.b1 * a.m[e] + (1.0f - a.b1) * g;
+    const float vv = a.b2 * a.v[e] + (1.0f - a.b2) * g * g;
+    a.m[e] = mm;
+    a.v[e] = vv;
+    const float p = a.P[e] - a.lr * (mm / bc1) / (sqrtf(vv / bc2) + a.eps);
+    a.P[e] = p;
+    write_copies(a.copies, e, p);
+}
+
+// One launch that ends the gradient: the slice sums of the three weight-and-bias gradient
+// products (dst[r][c] = the sum over slices z = 0, 1, ... in that order of src[z][r][c]; with
+// dst_last the last row, the bias gradient, goes to dst_last[c]) and, in the last block,
+// the loss.  Blocks [first[l], first[l + 1]) sum product l.  With adam_on, each gradient
+// value also takes its Adam step at once (parameter index = its offset in G).
+struct SliceSum {
+    const float *src;
+    long long zs;
+    int n_slices, rows, cols, lds, ldd;
+    float *dst, *dst_last;
+};
+struct FinishArgs {
+    SliceSum s[3];
+    int first[4];  // block ranges; block first[3] computes the loss
+    const float *lp;
+    int n_lp, B;
+    float *loss, *loss2;
+    const float *G;
+    int adam_on;
+    AdamArgs adam;
+};
+__global__ void k_grad_finish(FinishArgs f) {
+    const int blk = blockIdx.x;
+    if (blk >= f.first[3]) {
+        loss_total(f.lp, f.n_lp, f.B, f.loss, f.loss2);
+        return;
+    }
+    const int l = blk < f.first[1] ? 0 : blk < f.first[2] ? 1 : 2;
+    const SliceSum &d = f.s[l];
+    const int e = (blk - f.first[l]) * blockDim.x + threadIdx.x;
+    if (e >= d.rows * d.cols) return;
+    const int r = e / d.cols, c = e % d.cols;
+    const float *q = d.src + (long long)r * d.lds + c;
+    // loads issued up to 32 at a time, added in slice order (the sum is the same as one at
+    // a time)
+    constexpr int G = 32;
+    const int n = d.n_slices;
+    float v = q[0];
+    for (int z = 1; z < n; z += G) {
+        float t[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) t[j] = z + j < n ? q[(z + j) * d.zs] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            if (z + j < n) v += t[j];
+    }
+    float *dp = (d.dst_last && r == d.rows - 1) ? d.dst_last + c : d.dst + (long long)r * d.ldd + c;
+    *dp = v;
+    if (f.adam_on) adam_update(f.adam, (size_t)(dp - f.G), v);
+}
+
+__global__ void k_adam(AdamArgs a, const float *G, int n) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
-    const float t = (float)(*t_prev + 1);
-    const float bc1 = 1.0f - powf(b1, t), bc2 = 1.0f - powf(b2, t);
-    const float g = G[e];
-    const float mm = b1 * m[e] + (1.0f - b1) * g;
-    const float vv = b2 * v[e] + (1.0f - b2) * g * g;
-    m[e] = mm;
-    v[e] = vv;
-    const float p = P[e] - lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
-    P[e] = p;
-    write_copies(copies, (size_t)e, p);
+    adam_update(a, (size_t)e, G[e]);
 }
 
 __global__ void k_step_count(int *t) {
@@ -842,8 +856,16 @@ struct RowSrc {
     uint32_t k0, k1;
 };
 
+// Adam's arguments over the network's parameters and moments
+AdamArgs adam_args(sgtp_mlp *m, float lr, float beta1, float beta2, float eps) {
+    return AdamArgs{m->P, m->Mm, m->Vv, lr, beta1, beta2, eps, m->adam_t,
+                    Bf16Copies{m->W1, m->W2, m->W3, m->W1T, m->W2T, m->W3T, m->b3p}};
+}
+
+// The gradient of B rows into m->G (and the loss); with ad, each gradient value also takes
+// its Adam step inside the slice-sum launch (the step count is the caller's to advance).
 int grad_rows(sgtp_mlp *m, const RowSrc &rs, int B, int N, float sig_a, float sig_d, float *loss, float *grads,
-              hipStream_t st) {
+              hipStream_t st, const AdamArgs *ad = nullptr) {
     int n_lp;
     if (B <= FUSED_TRAIN_MAX) {  // fetch, forward and loss gradient in one launch
         const TrainIn ti{rs.U, rs.M, rs.k0, rs.k1, m->adam_t, m->IDX, m->X, N, sig_a, sig_d, m->D, m->LP};
@@ -896,6 +918,9 @@ int grad_rows(sgtp_mlp *m, const RowSrc &rs, int B, int N, float sig_a, float si
     fa.B = B;
     fa.loss = m->loss;
     fa.loss2 = loss;
+    fa.G = m->G;
+    fa.adam_on = ad != nullptr;
+    if (ad) fa.adam = *ad;
     hipLaunchKernelGGL(k_grad_finish, dim3(fa.first[3] + 1), dim3(256), 0, st, fa);
     MCHK(m, hipGetLastError());
     m->last_B = B;
@@ -955,9 +980,25 @@ int sgtp_mlp_workspace(sgtp_mlp *m, int which, void *dst, void *stream) {
 int sgtp_mlp_adam(sgtp_mlp *m, float lr, float beta1, float beta2, float eps, void *stream) {
     if (!m) return SGTP_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    const Bf16Copies copies{m->W1, m->W2, m->W3, m->W1T, m->W2T, m->W3T, m->b3p};
-    hipLaunchKernelGGL(k_adam, dim3((P_TOTAL + 255) / 256), dim3(256), 0, st, m->P, m->G, m->Mm, m->Vv, (int)P_TOTAL,
-                       lr, beta1, beta2, eps, m->adam_t, copies);
+    hipLaunchKernelGGL(k_adam, dim3((P_TOTAL + 255) / 256), dim3(256), 0, st, adam_args(m, lr, beta1, beta2, eps),
+                       m->G, (int)P_TOTAL);
+    hipLaunchKernelGGL(k_step_count, dim3(1), dim3(64), 0, st, m->adam_t);
+    MCHK(m, hipGetLastError());
+    return SGTP_OK;
+}
+
+int sgtp_mlp_train_step_sampled(sgtp_mlp *m, const float *X_all, const float *U_all, long long M, int B, int N,
+                                unsigned long long seed, float sig_a, float sig_d, float lr, float beta1, float beta2,
+                                float eps, float *loss, void *stream) {
+    if (!m || !X_all || !U_all) return SGTP_EINVAL;
+    if (M < 1 || M > 0x7fffffffLL) return mfail(m, SGTP_ESHAPE, "data set rows outside [1, 2^31 - 1]");
+    if (int rc = check_grad_args(m, B, N, sig_a, sig_d)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    m->last_sampled = true;
+    const AdamArgs ad = adam_args(m, lr, beta1, beta2, eps);
+    if (int rc = grad_rows(m, RowSrc{X_all, U_all, M, (uint32_t)seed, (uint32_t)(seed >> 32)}, B, N, sig_a, sig_d,
+                           loss, nullptr, st, &ad))
+        return rc;
     hipLaunchKernelGGL(k_step_count, dim3(1), dim3(64), 0, st, m->adam_t);
     MCHK(m, hipGetLastError());
     return SGTP_OK;

@@ -73,11 +73,11 @@ TRAIN_FLOP_PER_ROW = 2 * (50 * 256 + 256 * 256 + 256 * 200) * 2 + 2 * (200 * 256
 
 class Trainer:
     """Adam on random minibatches of a data set.  Each step draws `batch` rows on the device
-    (sgtp_mlp_grad_sampled: Philox at counter (row, Adam step), so nothing runs on the host
-    between steps), gathers them inside the library and runs the gradient and
-    sgtp_mlp_adam; with graph=True both are captured once in a hipGraph and each step is
-    one replay.  The network's reductions run in a fixed order, so both ways give the same
-    bits."""
+    (Philox at counter (row, Adam step), so nothing runs on the host between steps), fetches
+    them inside the library and runs the gradient and the Adam step as one call
+    (sgtp_mlp_train_step_sampled); with graph=True it is captured once in a hipGraph and
+    each step is one replay.  The network's reductions run in a fixed order, so both ways
+    give the same bits."""
 
     def __init__(self, mlp: sg.Mlp, data: Dataset, params: dict, batch: int = 1024, lr: float = 1e-3,
                  seed: int = 0, graph: bool = True):
@@ -94,9 +94,7 @@ class Trainer:
                 self.loss = self._launch()
 
     def _launch(self):
-        loss, _ = self.mlp.grad_sampled(self.data.X, self.data.U, self.batch, self.seed, *self.sig)
-        self.mlp.adam(lr=self.lr)
-        return loss
+        return self.mlp.train_step_sampled(self.data.X, self.data.U, self.batch, self.seed, *self.sig, lr=self.lr)
 
     def step(self):
         """One training step; returns the (device) loss of its minibatch before the update."""

@@ -133,6 +133,9 @@ def load():
         lib.sgtp_mlp_workspace.argtypes = [vp, C.c_int, vp, vp]
         lib.sgtp_mlp_grad_sampled.argtypes = [vp, vp, vp, C.c_longlong, C.c_int, C.c_int, C.c_ulonglong, C.c_float,
                                               C.c_float, vp, vp, vp]
+        lib.sgtp_mlp_train_step_sampled.argtypes = [vp, vp, vp, C.c_longlong, C.c_int, C.c_int, C.c_ulonglong,
+                                                    C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float,
+                                                    vp, vp]
         lib.sgtp_gemm_bf16.argtypes = [vp, C.c_longlong, C.c_longlong, vp, C.c_longlong, C.c_longlong, C.c_int,
                                        C.c_int, C.c_int, vp, vp, C.c_longlong, vp]
         _lib = lib
@@ -550,6 +553,19 @@ class Mlp:
                     "sgtp_mlp_grad_sampled")
         self._last_B = int(B)
         return loss, g
+
+    def train_step_sampled(self, X_all, U_all, B, seed, sig_a, sig_d, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        """grad_sampled() and adam() as one call (see sgtp_mlp_train_step_sampled); the loss
+        tensor [1] of the minibatch before the update."""
+        import torch
+        X_all, U_all = X_all.contiguous(), U_all.contiguous()
+        loss = torch.empty(1, dtype=torch.float32, device=X_all.device)
+        self._check(self.lib.sgtp_mlp_train_step_sampled(self.h, _ptr(X_all), _ptr(U_all), X_all.shape[0], int(B),
+                                                         U_all.shape[1], int(seed) & (2 ** 64 - 1), float(sig_a),
+                                                         float(sig_d), lr, beta1, beta2, eps, _ptr(loss), _stream()),
+                    "sgtp_mlp_train_step_sampled")
+        self._last_B = int(B)
+        return loss
 
     WORKSPACE = {"h1": (0, "bf16"), "h2": (1, "bf16"), "out": (2, "f32"), "d3": (3, "bf16"), "d2": (4, "bf16"),
                  "d1": (5, "bf16"), "idx": (6, "i32")}

@@ -218,6 +218,43 @@ def test_sampled_gradient_draws_its_rows_and_matches_the_plain_gradient(oracle_l
         m.close()
 
 
+@pytest.mark.parametrize("M,B,B_max", [(2777, 700, 1024), (12000, 8500, 8704)])
+def test_combined_training_step_equals_gradient_then_adam(M, B, B_max):
+    """sgtp_mlp_train_step_sampled (Adam inside the slice-sum launch) gives the same loss,
+    drawn rows, parameters and moments' effect as sgtp_mlp_grad_sampled followed by
+    sgtp_mlp_adam, bit for bit, over three steps (so the step count advances the same way);
+    700 rows take the fused kernels, 8500 the tiled products."""
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    flat, _ = _net(seed=31, scale3=3.0)
+    rng = np.random.default_rng(12)
+    N, seed = 50, 0x0DDB_A11C_0FFE_E123
+    X = torch.as_tensor(rng.standard_normal((M, 50)).astype(np.float32)).cuda()
+    U = torch.as_tensor(np.stack([rng.uniform(-8, 4, (M, N)), rng.uniform(-0.4, 0.4, (M, N))], -1)
+                        .astype(np.float32)).cuda()
+    sa, sd, lr = 1.5, 0.08, 3e-3
+    ma, mb = sg.Mlp(B_max, flat), sg.Mlp(B_max, flat)
+    try:
+        for step in range(3):
+            print(f"combined training step, {B} of {M} rows, step {step}", flush=True)
+            la, _ = ma.grad_sampled(X, U, B, seed, sa, sd)
+            ma.adam(lr=lr)
+            lb = mb.train_step_sampled(X, U, B, seed, sa, sd, lr=lr)
+            torch.cuda.synchronize()
+            assert la.item() == lb.item(), (step, la.item(), lb.item())
+            assert np.array_equal(ma.workspace("idx").cpu().numpy(), mb.workspace("idx").cpu().numpy())
+            pa, pb = ma.get_params(), mb.get_params()
+            assert np.array_equal(pa.view(np.uint32), pb.view(np.uint32)), (step, np.abs(pa - pb).max())
+        assert not np.array_equal(pa, flat)
+        # the BF16 operand copies moved with the master weights: the next forward agrees
+        fa = ma.forward(X[:300])
+        fb = mb.forward(X[:300])
+        assert torch.equal(fa, fb)
+    finally:
+        ma.close()
+        mb.close()
+
+
 def test_adam_updates_the_bf16_operand_copies():
     """After Adam steps (which write the BF16 operand copies as they update the master
     weights), the network computes exactly what a fresh network given the same master
