@@ -302,26 +302,33 @@ __global__ void k_refresh_bf16_t(const float *P, bf16 *W1T, bf16 *W2T, bf16 *W3T
     }
 }
 
-// One 16 x (K) x (16 j .. 16 j + 15) product step of the fused forward: A rows from LDS,
-// B fragments from the transposed weights; same lane -> (row, k) map and k order as
-// k_gemm_bf16, so the sums are the same.
-__device__ __forceinline__ f32x4 mfma_rows16(const bf16 *A, int lda, const bf16 *WT, int K, int n0, int l) {
+// One 16 x K x 16 product step of the fused kernels (output columns n0 .. n0 + 15): the
+// B fragments of a lane come from the transposed weights (row n0 + l % 16, k 32 i + 8 (l /
+// 16) .. + 7 for i = 0 .. K/32 - 1) and are loaded first, so a wave can fetch them ahead
+// of the barrier or epilogue before its product; the A rows come from LDS.  Same lane ->
+// (row, k) map and k order as k_gemm_bf16, so the sums are the same.
+template <int K>
+__device__ __forceinline__ void load_frags(const bf16 *__restrict__ WT, int n0, int l, bf16x8 (&b)[K / 32]) {
+#pragma unroll
+    for (int i = 0; i < K / 32; ++i) b[i] = *(const bf16x8 *)&WT[(size_t)(n0 + (l & 15)) * K + 32 * i + 8 * (l >> 4)];
+}
+template <int K>
+__device__ __forceinline__ f32x4 mfma_frags(const bf16 *A, int lda, const bf16x8 (&b)[K / 32], int l) {
     f32x4 acc = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = 0; k0 < K; k0 += 32) {
-        const int kk = k0 + 8 * (l >> 4);
-        const bf16x8 a = *(const bf16x8 *)&A[(l & 15) * lda + kk];
-        const bf16x8 b = *(const bf16x8 *)&WT[(size_t)(n0 + (l & 15)) * K + kk];
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < K / 32; ++i) {
+        const bf16x8 a = *(const bf16x8 *)&A[(l & 15) * lda + 32 * i + 8 * (l >> 4)];
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[i], acc, 0, 0, 0);
     }
     return acc;
 }
 
 // Gaussian negative log-likelihood of target u for step t < 64, channel c (0 acceleration,
 // 1 steering) of one row whose outputs are o[256] (mean over B rows; constant 0.5 log 2 pi
-// dropped; steps t >= N do not enter): its term is returned, its gradient w.r.t. the
-// outputs written as BF16 to g[4 t + c] (mean) and g[4 t + 2 + c] (log scale).
-__device__ __forceinline__ float nll_term(const float *o, const float *u_row, int t, int c, int N, float sig_a,
-                                          float sig_d, int B, bf16 *g) {
+// dropped; steps t >= N do not enter, u unused): its term is returned, its gradient w.r.t.
+// the outputs written as BF16 to g[4 t + c] (mean) and g[4 t + 2 + c] (log scale).
+__device__ __forceinline__ float nll_term(const float *o, float u, int t, int c, int N, float sig_a, float sig_d,
+                                          int B, bf16 *g) {
     if (t >= N) {
         g[4 * t + c] = (bf16)0.0f;
         g[4 * t + 2 + c] = (bf16)0.0f;
@@ -334,7 +341,7 @@ __device__ __forceinline__ float nll_term(const float *o, const float *u_row, in
     const float cl = fminf(fmaxf(raw, LS_MIN), LS_MAX);
     const float ls = lsp + cl;
     const float inv_s2 = expf(-2.0f * ls);
-    const float res = u_row[2 * t + c] - mu;
+    const float res = u - mu;
     g[4 * t + c] = (bf16)(-scale * res * inv_s2 / (float)B);
     g[4 * t + 2 + c] = (bf16)((raw > LS_MIN && raw < LS_MAX) ? (1.0f - res * res * inv_s2) / (float)B : 0.0f);
     return 0.5f * res * res * inv_s2 + ls;
@@ -363,11 +370,13 @@ struct TrainIn {
 // each), as the tiled products write them for the backward pass; and the loss and its
 // gradient are taken from the output tile, as k_nll takes them (same lane -> (step,
 // channel) map, same per-wave sums).
-template <bool TRAIN, int NW>
-__global__ void __launch_bounds__(64 * NW) k_mlp_fwd16(const float *X, int ldx, int B, const bf16 *W1T, const bf16 *W2T,
-                                                  const bf16 *W3T, const float *b1, const float *b2, const float *b3,
-                                                  float *out, int ldo, int n_out, float *pre1, bf16 *h1o, float *pre2,
-                                                  bf16 *h2o, TrainIn ti) {
+template <bool TRAIN>
+__global__ void __launch_bounds__(64 * FWD_WAVES) k_mlp_fwd16(const float *X, int ldx, int B, const bf16 *W1T,
+                                                             const bf16 *W2T, const bf16 *W3T, const float *b1,
+                                                             const float *b2, const float *b3, float *out, int ldo,
+                                                             int n_out, float *pre1, bf16 *h1o, float *pre2,
+                                                             bf16 *h2o, TrainIn ti) {
+    static_assert(FWD_WAVES == 16, "one 16-column tile per wave and layer");
     constexpr int LX = D_INP + 8, LH = D_H + 8, LO = D_OUTP + 4;  // padded rows
     __shared__ __align__(16) bf16 xs[16 * LX];
     __shared__ __align__(16) bf16 h1[16 * LH];
@@ -375,6 +384,15 @@ __global__ void __launch_bounds__(64 * NW) k_mlp_fwd16(const float *X, int ldx, 
     __shared__ float os[TRAIN ? 16 * LO : 1];
     __shared__ long long src[16];
     const int r0 = blockIdx.x * 16, tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int n0 = 16 * w, col = n0 + (l & 15);  // this wave's output columns in every layer
+    const bool l3 = n0 < n_out;                  // layer 3 columns >= n_out are dropped
+    // the wave's weight fragments and biases of all three layers, fetched while the rows
+    // are drawn and fetched
+    bf16x8 f1[D_INP / 32], f2[D_H / 32], f3[D_H / 32];
+    load_frags<D_INP>(W1T, n0, l, f1);
+    load_frags<D_H>(W2T, n0, l, f2);
+    if (l3) load_frags<D_H>(W3T, n0, l, f3);
+    const float c1 = b1[col], c2 = b2[col], c3 = col < n_out ? b3[col] : 0.0f;
     if (tid < 16) {
         const int b = r0 + tid;
         long long i = b;
@@ -386,21 +404,30 @@ __global__ void __launch_bounds__(64 * NW) k_mlp_fwd16(const float *X, int ldx, 
         src[tid] = i;
     }
     __syncthreads();
-    for (int e = tid; e < 16 * D_INP; e += 64 * NW) {
+    for (int e = tid; e < 16 * D_INP; e += 64 * FWD_WAVES) {
         const int r = e / D_INP, c = e % D_INP;
         const bf16 v = (r0 + r < B && c < D_IN) ? (bf16)X[src[r] * ldx + c] : (bf16)0.0f;
         xs[r * LX + c] = v;
         if (TRAIN && r0 + r < B) ti.Xb[(long long)(r0 + r) * D_INP + c] = v;
     }
-    __syncthreads();
+    // the targets the loss section below takes (its pairs (row, step, channel) of both of
+    // the wave's groups), fetched now
+    const int tt = 32 * (w & 1) + (l >> 1), cc = l & 1;
+    float u[2] = {0.0f, 0.0f};
+    if (TRAIN && tt < ti.N) {
 #pragma unroll
-    for (int jj = 0; jj < 16 / NW; ++jj) {  // layer 1: 16 column tiles of 16 over the NW waves
-        const int n0 = 16 * (w + NW * jj);
-        const f32x4 acc = mfma_rows16(xs, LX, W1T, D_INP, n0, l);
+        for (int j = 0; j < 2; ++j) {
+            const int row = (w >> 1) + 8 * j;
+            if (r0 + row < B) u[j] = ti.U[src[row] * 2 * ti.N + 2 * tt + cc];
+        }
+    }
+    __syncthreads();
+    {  // layer 1
+        const f32x4 acc = mfma_frags<D_INP>(xs, LX, f1, l);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int row = 4 * (l >> 4) + v, col = n0 + (l & 15);
-            const float x = acc[v] + b1[col];
+            const int row = 4 * (l >> 4) + v;
+            const float x = acc[v] + c1;
             const bf16 h = (bf16)gelu_f(x);
             h1[row * LH + col] = h;
             if (TRAIN && r0 + row < B) {
@@ -410,14 +437,12 @@ __global__ void __launch_bounds__(64 * NW) k_mlp_fwd16(const float *X, int ldx, 
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int jj = 0; jj < 16 / NW; ++jj) {  // layer 2
-        const int n0 = 16 * (w + NW * jj);
-        const f32x4 acc = mfma_rows16(h1, LH, W2T, D_H, n0, l);
+    {  // layer 2
+        const f32x4 acc = mfma_frags<D_H>(h1, LH, f2, l);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int row = 4 * (l >> 4) + v, col = n0 + (l & 15);
-            const float x = acc[v] + b2[col];
+            const int row = 4 * (l >> 4) + v;
+            const float x = acc[v] + c2;
             const bf16 h = (bf16)gelu_f(x);
             h2[row * LH + col] = h;
             if (TRAIN && r0 + row < B) {
@@ -427,27 +452,25 @@ __global__ void __launch_bounds__(64 * NW) k_mlp_fwd16(const float *X, int ldx, 
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int jj = 0; jj < 16 / NW; ++jj) {  // layer 3 (columns >= n_out dropped)
-        const int n0 = 16 * (w + NW * jj);
-        if (n0 >= n_out) continue;
-        const f32x4 acc = mfma_rows16(h2, LH, W3T, D_H, n0, l);
+    if (l3) {  // layer 3
+        const f32x4 acc = mfma_frags<D_H>(h2, LH, f3, l);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int row = 4 * (l >> 4) + v, col = n0 + (l & 15);
-            const float o = acc[v] + b3[col];
+            const int row = 4 * (l >> 4) + v;
+            const float o = acc[v] + c3;
             if (TRAIN) os[row * LO + col] = o;
             if (r0 + row < B && col < n_out) out[(long long)(r0 + row) * ldo + col] = o;
         }
     }
     if (TRAIN) {
         __syncthreads();
-        // 32 groups of 64 (step, channel) pairs: row vg / 2, steps 32 (vg & 1) + 0..31
-        for (int vg = w; vg < 32; vg += NW) {
-            const int row = vg >> 1, b = r0 + row;
+        // 32 groups of 64 (step, channel) pairs: row vg / 2, steps 32 (vg & 1) + 0..31; wave
+        // w takes groups w and w + 16 (rows w / 2 and w / 2 + 8)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int vg = w + 16 * j, row = vg >> 1, b = r0 + row;
             if (b >= B) break;
-            const int t = 32 * (vg & 1) + (l >> 1), c = l & 1;
-            float contrib = nll_term(os + row * LO, ti.U + src[row] * 2 * ti.N, t, c, ti.N, ti.sig_a, ti.sig_d, B,
+            float contrib = nll_term(os + row * LO, u[j], tt, cc, ti.N, ti.sig_a, ti.sig_d, B,
                                      ti.dout + (long long)b * D_OUTP);
             for (int off = 32; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off);
             if (l == 0) ti.loss_part[2 * b + (vg & 1)] = contrib;
@@ -464,8 +487,8 @@ __global__ void k_nll(const float *out, int ldo, const float *U, int B, int N, f
     const int b = e >> 7, t = (e >> 1) & 63, c = e & 1;
     float contrib = 0.0f;
     if (b < B && 4 * t < ldd)
-        contrib = nll_term(out + (long long)b * ldo, U + (long long)b * N * 2, t, c, N, sig_a, sig_d, B,
-                           dout + (long long)b * ldd);
+        contrib = nll_term(out + (long long)b * ldo, t < N ? U[((long long)b * N + t) * 2 + c] : 0.0f, t, c, N, sig_a,
+                           sig_d, B, dout + (long long)b * ldd);
     for (int off = 32; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off);
     if ((threadIdx.x & 63) == 0) loss_part[e >> 6] = contrib;
 }
@@ -477,45 +500,56 @@ __global__ void k_nll(const float *out, int ldo, const float *U, int B, int N, f
 __global__ void __launch_bounds__(64 * FWD_WAVES) k_mlp_bwd16(const bf16 *D, const bf16 *W3, const bf16 *W2,
                                                              const float *pre2, const float *pre1, int B, bf16 *D2,
                                                              bf16 *D1) {
-    constexpr int NW = FWD_WAVES, LH = D_H + 8;
+    static_assert(FWD_WAVES == 16, "one 16-column tile per wave and layer");
+    constexpr int LH = D_H + 8;
     __shared__ __align__(16) bf16 ds[16 * LH];
     __shared__ __align__(16) bf16 d2s[16 * LH];
     const int r0 = blockIdx.x * 16, tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-    for (int e = tid; e < 16 * (D_OUTP / 8); e += 64 * NW) {  // 16-byte vectors of 8 columns
+    const int n0 = 16 * w, col = n0 + (l & 15);
+    // everything that does not depend on the products first: the wave's weight fragments
+    // and GELU'(pre-activation) of its 4 x 2 elements (rows past B read row B - 1, unused)
+    bf16x8 f3[D_OUTP / 32], f2[D_H / 32];
+    load_frags<D_OUTP>(W3, n0, l, f3);
+    load_frags<D_H>(W2, n0, l, f2);
+    float q2[4], q1[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const long long o = (long long)min(r0 + 4 * (l >> 4) + v, B - 1) * D_H + col;
+        q2[v] = pre2[o];
+        q1[v] = pre1[o];
+    }
+    for (int e = tid; e < 16 * (D_OUTP / 8); e += 64 * FWD_WAVES) {  // 16-byte vectors of 8 columns
         const int r = e / (D_OUTP / 8), c = 8 * (e % (D_OUTP / 8));
         u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
         if (r0 + r < B) v = *(const u16x8 *)&D[(long long)(r0 + r) * D_OUTP + c];
         *(u16x8 *)&ds[r * LH + c] = v;
     }
-    __syncthreads();
 #pragma unroll
-    for (int jj = 0; jj < 16 / NW; ++jj) {  // D2: 16 column tiles of 16 over the NW waves
-        const int n0 = 16 * (w + NW * jj);
-        const f32x4 acc = mfma_rows16(ds, LH, W3, D_OUTP, n0, l);
+    for (int v = 0; v < 4; ++v) {
+        q2[v] = gelu_grad_f(q2[v]);
+        q1[v] = gelu_grad_f(q1[v]);
+    }
+    __syncthreads();
+    {  // D2
+        const f32x4 acc = mfma_frags<D_OUTP>(ds, LH, f3, l);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int row = 4 * (l >> 4) + v, col = n0 + (l & 15);
+            const int row = 4 * (l >> 4) + v;
             bf16 h = (bf16)0.0f;
             if (r0 + row < B) {
-                const long long o = (long long)(r0 + row) * D_H + col;
-                h = (bf16)(acc[v] * gelu_grad_f(pre2[o]));
-                D2[o] = h;
+                h = (bf16)(acc[v] * q2[v]);
+                D2[(long long)(r0 + row) * D_H + col] = h;
             }
             d2s[row * LH + col] = h;
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int jj = 0; jj < 16 / NW; ++jj) {  // D1
-        const int n0 = 16 * (w + NW * jj);
-        const f32x4 acc = mfma_rows16(d2s, LH, W2, D_H, n0, l);
+    {  // D1
+        const f32x4 acc = mfma_frags<D_H>(d2s, LH, f2, l);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int row = 4 * (l >> 4) + v, col = n0 + (l & 15);
-            if (r0 + row < B) {
-                const long long o = (long long)(r0 + row) * D_H + col;
-                D1[o] = (bf16)(acc[v] * gelu_grad_f(pre1[o]));
-            }
+            const int row = 4 * (l >> 4) + v;
+            if (r0 + row < B) D1[(long long)(r0 + row) * D_H + col] = (bf16)(acc[v] * q1[v]);
         }
     }
 }
@@ -833,7 +867,7 @@ int sgtp_mlp_forward(sgtp_mlp *m, const float *X, int B, float *out, int ld_out,
     if (ld_out < D_OUT) return mfail(m, SGTP_EINVAL, "ld_out < 200");
     hipStream_t st = (hipStream_t)stream;
     if (B <= FUSED_MAX_ROWS) {  // planning-size batches: one fused kernel
-        hipLaunchKernelGGL((k_mlp_fwd16<false, FWD_WAVES>), dim3((B + 15) / 16), dim3(64 * FWD_WAVES), 0, st, X,
+        hipLaunchKernelGGL(k_mlp_fwd16<false>, dim3((B + 15) / 16), dim3(64 * FWD_WAVES), 0, st, X,
                            D_IN, B, m->W1T, m->W2T, m->W3T, m->P + P_B1, m->P + P_B2, m->P + P_B3, out, ld_out, D_OUT,
                            nullptr, nullptr, nullptr, nullptr, TrainIn{});
         MCHK(m, hipGetLastError());
@@ -869,7 +903,7 @@ int grad_rows(sgtp_mlp *m, const RowSrc &rs, int B, int N, float sig_a, float si
     int n_lp;
     if (B <= FUSED_TRAIN_MAX) {  // fetch, forward and loss gradient in one launch
         const TrainIn ti{rs.U, rs.M, rs.k0, rs.k1, m->adam_t, m->IDX, m->X, N, sig_a, sig_d, m->D, m->LP};
-        hipLaunchKernelGGL((k_mlp_fwd16<true, FWD_WAVES>), dim3((B + 15) / 16), dim3(64 * FWD_WAVES), 0, st, rs.X,
+        hipLaunchKernelGGL(k_mlp_fwd16<true>, dim3((B + 15) / 16), dim3(64 * FWD_WAVES), 0, st, rs.X,
                            D_IN, B, m->W1T, m->W2T, m->W3T, m->P + P_B1, m->P + P_B2, m->b3p, m->OUT, D_OUTP, D_OUTP,
                            m->PRE1, m->H1, m->PRE2, m->H2, ti);
         n_lp = 2 * B;
