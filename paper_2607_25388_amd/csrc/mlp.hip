@@ -72,16 +72,19 @@ struct GemmArgs {
     int ones_row;       // row index of A that reads as 1 for every k (a bias gradient), or -1
 };
 
-constexpr int STAGE_ELEM = 0, STAGE_VEC_K = 1, STAGE_VEC_ROW = 2;
+// STAGE_BLK16: a row-blocked operand, Op(r, k) = P[r s_r + (k / 16) s_k + k % 16] (16
+// consecutive k of a row contiguous), staged as 16-byte vectors of k like STAGE_VEC_K
+constexpr int STAGE_ELEM = 0, STAGE_VEC_K = 1, STAGE_VEC_ROW = 2, STAGE_BLK16 = 3;
 constexpr int GK = 64;          // K per LDS chunk
 constexpr int LROW = GK + 8;    // LDS row in bf16 (144 bytes: 16-byte aligned, banks staggered)
 
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 // Registers of one operand chunk (64 rows x GK k): two 8-element vectors per thread.
-// Vector q = tid + 256 i covers, for STAGE_ELEM / STAGE_VEC_K, row q / 8 and k 8 (q % 8)
-// .. + 7; for STAGE_VEC_ROW, k q / 8 and rows 8 (q % 8) .. + 7.  Op(r, k) = P[r s_r +
-// k s_k] for r < R and k < kend, zero beyond; row `ones` reads as 1 (for k < kend).
+// Vector q = tid + 256 i covers, for STAGE_ELEM / STAGE_VEC_K / STAGE_BLK16, row q / 8 and
+// k 8 (q % 8) .. + 7; for STAGE_VEC_ROW, k q / 8 and rows 8 (q % 8) .. + 7.  Op(r, k) =
+// P[r s_r + k s_k] (STAGE_BLK16: P[r s_r + (k / 16) s_k + k % 16]) for r < R and k < kend,
+// zero beyond; row `ones` reads as 1 (for k < kend).
 __device__ __forceinline__ void load_chunk(const bf16 *__restrict__ P, long long s_r, long long s_k, int mode, int r0,
                                            int R, int k0, int kend, int ones, int tid, u16x8 (&v)[2]) {
     const unsigned short ONE = 0x3F80;  // bf16 1.0
@@ -105,15 +108,18 @@ __device__ __forceinline__ void load_chunk(const bf16 *__restrict__ P, long long
             }
         } else {
             const int r = r0 + (q >> 3), k = k0 + 8 * (q & 7);
-            if (mode == STAGE_VEC_K && r < R && r != ones && k + 8 <= kend) {
-                x = *(const u16x8 *)&P[(long long)r * s_r + k];
+            const bool blk = mode == STAGE_BLK16;
+            if ((mode == STAGE_VEC_K || blk) && r < R && r != ones && k + 8 <= kend) {
+                x = *(const u16x8 *)&P[(long long)r * s_r + (blk ? (long long)(k >> 4) * s_k + (k & 15) : k)];
             } else {
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     const int kk = k + j;
+                    const long long o = (long long)r * s_r + (blk ? (long long)(kk >> 4) * s_k + (kk & 15)
+                                                                  : (long long)kk * s_k);
                     x[j] = (kk >= kend) ? (unsigned short)0
                            : (r == ones) ? ONE
-                           : (r < R) ? __builtin_bit_cast(unsigned short, P[(long long)r * s_r + (long long)kk * s_k])
+                           : (r < R) ? __builtin_bit_cast(unsigned short, P[o])
                                      : (unsigned short)0;
                 }
             }
@@ -307,6 +313,17 @@ __global__ void k_refresh_bf16_t(const float *P, bf16 *W1T, bf16 *W2T, bf16 *W3T
 // 16) .. + 7 for i = 0 .. K/32 - 1) and are loaded first, so a wave can fetch them ahead
 // of the barrier or epilogue before its product; the A rows come from LDS.  Same lane ->
 // (row, k) map and k order as k_gemm_bf16, so the sums are the same.
+// four BF16 values (rows 4 g .. 4 g + 3 of one column of a row-blocked copy) as one
+// 8-byte store
+__device__ __forceinline__ void store_rows4(bf16 *dst, const bf16 (&h)[4]) {
+    ushort4 u;
+    u.x = __builtin_bit_cast(unsigned short, h[0]);
+    u.y = __builtin_bit_cast(unsigned short, h[1]);
+    u.z = __builtin_bit_cast(unsigned short, h[2]);
+    u.w = __builtin_bit_cast(unsigned short, h[3]);
+    *(ushort4 *)dst = u;
+}
+
 template <int K>
 __device__ __forceinline__ void load_frags(const bf16 *__restrict__ WT, int n0, int l, bf16x8 (&b)[K / 32]) {
 #pragma unroll
@@ -326,12 +343,17 @@ __device__ __forceinline__ f32x4 mfma_frags(const bf16 *A, int lda, const bf16x8
 // Gaussian negative log-likelihood of target u for step t < 64, channel c (0 acceleration,
 // 1 steering) of one row whose outputs are o[256] (mean over B rows; constant 0.5 log 2 pi
 // dropped; steps t >= N do not enter, u unused): its term is returned, its gradient w.r.t.
-// the outputs written as BF16 to g[4 t + c] (mean) and g[4 t + 2 + c] (log scale).
+// the outputs written as BF16 to g[4 t + c] (mean) and g[4 t + 2 + c] (log scale), and,
+// when gt is not NULL, also to gt[(4 t + c) ldt] and gt[(4 t + 2 + c) ldt].
 __device__ __forceinline__ float nll_term(const float *o, float u, int t, int c, int N, float sig_a, float sig_d,
-                                          int B, bf16 *g) {
+                                          int B, bf16 *g, bf16 *gt = nullptr, long long ldt = 0) {
     if (t >= N) {
         g[4 * t + c] = (bf16)0.0f;
         g[4 * t + 2 + c] = (bf16)0.0f;
+        if (gt) {
+            gt[(4 * t + c) * ldt] = (bf16)0.0f;
+            gt[(4 * t + 2 + c) * ldt] = (bf16)0.0f;
+        }
         return 0.0f;
     }
     const float scale = c ? D_SCALE : A_SCALE;
@@ -342,8 +364,14 @@ __device__ __forceinline__ float nll_term(const float *o, float u, int t, int c,
     const float ls = lsp + cl;
     const float inv_s2 = expf(-2.0f * ls);
     const float res = u - mu;
-    g[4 * t + c] = (bf16)(-scale * res * inv_s2 / (float)B);
-    g[4 * t + 2 + c] = (bf16)((raw > LS_MIN && raw < LS_MAX) ? (1.0f - res * res * inv_s2) / (float)B : 0.0f);
+    const bf16 gm = (bf16)(-scale * res * inv_s2 / (float)B);
+    const bf16 gs = (bf16)((raw > LS_MIN && raw < LS_MAX) ? (1.0f - res * res * inv_s2) / (float)B : 0.0f);
+    g[4 * t + c] = gm;
+    g[4 * t + 2 + c] = gs;
+    if (gt) {
+        gt[(4 * t + c) * ldt] = gm;
+        gt[(4 * t + 2 + c) * ldt] = gs;
+    }
     return 0.5f * res * res * inv_s2 + ls;
 }
 
@@ -361,6 +389,9 @@ struct TrainIn {
     float sig_a, sig_d;
     bf16 *dout;       // [B][256] loss gradient w.r.t. the outputs
     float *loss_part; // [2 B] loss partials: row b steps 0-31 at 2 b, steps 32-63 at 2 b + 1
+    // row-blocked copies [B / 16][columns][16] of the features, both hidden activations and
+    // the output gradient
+    bf16 *XB, *H1B, *H2B, *DB;
 };
 
 // Fused forward of 16 rows per workgroup: the three layers run back to back with the
@@ -382,6 +413,7 @@ __global__ void __launch_bounds__(64 * FWD_WAVES) k_mlp_fwd16(const float *X, in
     __shared__ __align__(16) bf16 h1[16 * LH];
     __shared__ __align__(16) bf16 h2[16 * LH];
     __shared__ float os[TRAIN ? 16 * LO : 1];
+    __shared__ __align__(16) bf16 dsb[TRAIN ? 16 * D_OUTP : 8];  // output gradient, row-blocked
     __shared__ long long src[16];
     const int r0 = blockIdx.x * 16, tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int n0 = 16 * w, col = n0 + (l & 15);  // this wave's output columns in every layer
@@ -422,34 +454,43 @@ __global__ void __launch_bounds__(64 * FWD_WAVES) k_mlp_fwd16(const float *X, in
         }
     }
     __syncthreads();
+    if (TRAIN)  // the rows' features into their row-blocked copy, 16 rows of a column contiguous
+        for (int e = tid; e < 16 * D_INP; e += 64 * FWD_WAVES)
+            ti.XB[(long long)r0 * D_INP + e] = xs[(e & 15) * LX + (e >> 4)];
     {  // layer 1
         const f32x4 acc = mfma_frags<D_INP>(xs, LX, f1, l);
+        bf16 hb[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = 4 * (l >> 4) + v;
             const float x = acc[v] + c1;
             const bf16 h = (bf16)gelu_f(x);
+            hb[v] = h;
             h1[row * LH + col] = h;
             if (TRAIN && r0 + row < B) {
                 pre1[(long long)(r0 + row) * D_H + col] = x;
                 h1o[(long long)(r0 + row) * D_H + col] = h;
             }
         }
+        if (TRAIN) store_rows4(ti.H1B + (long long)r0 * D_H + col * 16 + 4 * (l >> 4), hb);
     }
     __syncthreads();
     {  // layer 2
         const f32x4 acc = mfma_frags<D_H>(h1, LH, f2, l);
+        bf16 hb[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = 4 * (l >> 4) + v;
             const float x = acc[v] + c2;
             const bf16 h = (bf16)gelu_f(x);
+            hb[v] = h;
             h2[row * LH + col] = h;
             if (TRAIN && r0 + row < B) {
                 pre2[(long long)(r0 + row) * D_H + col] = x;
                 h2o[(long long)(r0 + row) * D_H + col] = h;
             }
         }
+        if (TRAIN) store_rows4(ti.H2B + (long long)r0 * D_H + col * 16 + 4 * (l >> 4), hb);
     }
     __syncthreads();
     if (l3) {  // layer 3
@@ -471,10 +512,14 @@ __global__ void __launch_bounds__(64 * FWD_WAVES) k_mlp_fwd16(const float *X, in
             const int vg = w + 16 * j, row = vg >> 1, b = r0 + row;
             if (b >= B) break;
             float contrib = nll_term(os + row * LO, u[j], tt, cc, ti.N, ti.sig_a, ti.sig_d, B,
-                                     ti.dout + (long long)b * D_OUTP);
+                                     ti.dout + (long long)b * D_OUTP, dsb + row, 16);
             for (int off = 32; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off);
             if (l == 0) ti.loss_part[2 * b + (vg & 1)] = contrib;
         }
+        __syncthreads();
+        // the output gradient's row-blocked copy: the block's 16 x 256 tile, contiguous
+        for (int e = tid; e < 16 * D_OUTP / 8; e += 64 * FWD_WAVES)
+            *(u16x8 *)&ti.DB[(long long)r0 * D_OUTP + 8 * e] = *(const u16x8 *)&dsb[8 * e];
     }
 }
 
@@ -499,7 +544,7 @@ __global__ void k_nll(const float *out, int ldo, const float *U, int B, int N, f
 // tiled products, so the same bits.
 __global__ void __launch_bounds__(64 * FWD_WAVES) k_mlp_bwd16(const bf16 *D, const bf16 *W3, const bf16 *W2,
                                                              const float *pre2, const float *pre1, int B, bf16 *D2,
-                                                             bf16 *D1) {
+                                                             bf16 *D1, bf16 *D2B, bf16 *D1B) {
     static_assert(FWD_WAVES == 16, "one 16-column tile per wave and layer");
     constexpr int LH = D_H + 8;
     __shared__ __align__(16) bf16 ds[16 * LH];
@@ -532,6 +577,7 @@ __global__ void __launch_bounds__(64 * FWD_WAVES) k_mlp_bwd16(const bf16 *D, con
     __syncthreads();
     {  // D2
         const f32x4 acc = mfma_frags<D_OUTP>(ds, LH, f3, l);
+        bf16 hb[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = 4 * (l >> 4) + v;
@@ -540,17 +586,22 @@ __global__ void __launch_bounds__(64 * FWD_WAVES) k_mlp_bwd16(const bf16 *D, con
                 h = (bf16)(acc[v] * q2[v]);
                 D2[(long long)(r0 + row) * D_H + col] = h;
             }
+            hb[v] = h;
             d2s[row * LH + col] = h;
         }
+        store_rows4(D2B + (long long)r0 * D_H + col * 16 + 4 * (l >> 4), hb);
     }
     __syncthreads();
     {  // D1
         const f32x4 acc = mfma_frags<D_H>(d2s, LH, f2, l);
+        bf16 hb[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = 4 * (l >> 4) + v;
-            if (r0 + row < B) D1[(long long)(r0 + row) * D_H + col] = (bf16)(acc[v] * q1[v]);
+            hb[v] = (bf16)(acc[v] * q1[v]);
+            if (r0 + row < B) D1[(long long)(r0 + row) * D_H + col] = hb[v];
         }
+        store_rows4(D1B + (long long)r0 * D_H + col * 16 + 4 * (l >> 4), hb);
     }
 }
 
@@ -695,6 +746,10 @@ struct sgtp_mlp {
     int *adam_t = nullptr;  // device: Adam steps taken
     float *UB = nullptr;    // gathered targets of a sampled gradient [B_max][N_H][2]
     int *IDX = nullptr;     // rows drawn by the last sampled gradient [B_max]
+    // row-blocked copies [B / 16][columns][16] of X, H1, H2, D, D2 and D1, written by the
+    // fused kernels (one contiguous block per workgroup) so the weight-gradient products
+    // (K = the batch) stage 16-byte vectors of k
+    bf16 *XB = nullptr, *H1B = nullptr, *H2B = nullptr, *DB = nullptr, *D2B = nullptr, *D1B = nullptr;
     int last_B = 0;  // rows of the last sgtp_mlp_grad (its workspace tensors stay until the next call)
     bool last_sampled = false;  // the last gradient drew its rows on the device
 };
@@ -742,13 +797,16 @@ void gemm(hipStream_t st, const bf16 *A, long long a_m, long long a_k, const bf1
 // column sums of B, as one product with an extra row of ones in A, K split into `splits`
 // slices: partial products into `part` [splits][M + 1][N]; the slices are summed in order
 // by k_grad_finish (its descriptor is returned).  The product becomes member p of the
-// group launch grp.
+// group launch grp.  blk_mode STAGE_BLK16: both operands row-blocked (strides as that
+// mode reads them).
 SliceSum gemm_wgrad(GemmGroup &grp, int p, float *part, const bf16 *A, long long a_m, long long a_k, const bf16 *B,
                     long long b_k, long long b_n, int M, int N, int K, float *dst, int ldd, float *bias_dst,
-                    int splits) {
+                    int splits, int blk_mode = -1) {
     const int R = M + 1;  // row M of A reads as 1: the bias gradient
+    const int am = blk_mode >= 0 ? blk_mode : stage_mode(A, a_m, a_k);
+    const int bm = blk_mode >= 0 ? blk_mode : stage_mode(B, b_n, b_k);
     grp.g[p] = GemmArgs{A, a_m, a_k, B, b_k, b_n, R, N, K, nullptr, part, N, (long long)R * N, nullptr, 0, nullptr,
-                        stage_mode(A, a_m, a_k), stage_mode(B, b_n, b_k), M};
+                        am, bm, M};
     grp.gx[p] = (N + 63) / 64;
     grp.gy[p] = (R + 63) / 64;
     grp.gz[p] = splits;
@@ -813,6 +871,13 @@ int sgtp_mlp_create(int B_max, sgtp_mlp **out) {
     al((void **)&m->UB, (size_t)B_max * N_H * 2 * 4);
     al((void **)&m->IDX, (size_t)B_max * 4);
     al((void **)&m->loss, 4);
+    const size_t rows16 = (size_t)(B_max + 15) / 16 * 16;
+    al((void **)&m->XB, rows16 * D_INP * 2);
+    al((void **)&m->H1B, rows16 * D_H * 2);
+    al((void **)&m->H2B, rows16 * D_H * 2);
+    al((void **)&m->DB, rows16 * D_OUTP * 2);
+    al((void **)&m->D2B, rows16 * D_H * 2);
+    al((void **)&m->D1B, rows16 * D_H * 2);
     if (!ok) {
         sgtp_mlp_destroy(m);
         return SGTP_ENOMEM;
@@ -826,7 +891,7 @@ int sgtp_mlp_destroy(sgtp_mlp *m) {
     (void)hipDeviceSynchronize();
     void *bufs[] = {m->P,  m->G,  m->Mm, m->Vv,   m->W1,   m->W2,  m->W3, m->b3p, m->X,    m->H1,   m->H2,
                     m->D,  m->D1, m->PRE1, m->PRE2, m->OUT, m->PART, m->loss, m->W1T, m->W2T, m->W3T,
-                    m->D2, m->LP, m->adam_t, m->UB, m->IDX};
+                    m->D2, m->LP, m->adam_t, m->UB, m->IDX, m->XB, m->H1B, m->H2B, m->DB, m->D2B, m->D1B};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete m;
@@ -902,7 +967,8 @@ int grad_rows(sgtp_mlp *m, const RowSrc &rs, int B, int N, float sig_a, float si
               hipStream_t st, const AdamArgs *ad = nullptr) {
     int n_lp;
     if (B <= FUSED_TRAIN_MAX) {  // fetch, forward and loss gradient in one launch
-        const TrainIn ti{rs.U, rs.M, rs.k0, rs.k1, m->adam_t, m->IDX, m->X, N, sig_a, sig_d, m->D, m->LP};
+        const TrainIn ti{rs.U,  rs.M,  rs.k0, rs.k1, m->adam_t, m->IDX, m->X, N,
+                         sig_a, sig_d, m->D,  m->LP, m->XB,  m->H1B,    m->H2B, m->DB};
         hipLaunchKernelGGL(k_mlp_fwd16<true>, dim3((B + 15) / 16), dim3(64 * FWD_WAVES), 0, st, rs.X,
                            D_IN, B, m->W1T, m->W2T, m->W3T, m->P + P_B1, m->P + P_B2, m->b3p, m->OUT, D_OUTP, D_OUTP,
                            m->PRE1, m->H1, m->PRE2, m->H2, ti);
@@ -928,7 +994,7 @@ int grad_rows(sgtp_mlp *m, const RowSrc &rs, int B, int N, float sig_a, float si
     const size_t third = (size_t)MAX_SPLITS * (D_H + 1) * D_OUTP;
     if (B <= FUSED_TRAIN_MAX) {  // dH2 = D W3^T and dH1 = D2 W2^T in one launch
         hipLaunchKernelGGL(k_mlp_bwd16, dim3((B + 15) / 16), dim3(64 * FWD_WAVES), 0, st, m->D, m->W3, m->W2,
-                           m->PRE2, m->PRE1, B, m->D2, m->D1);
+                           m->PRE2, m->PRE1, B, m->D2, m->D1, m->D2B, m->D1B);
     } else {
         gemm(st, m->D, D_OUTP, 1, m->W3, 1, D_OUTP, B, D_H, D_OUTP, nullptr, nullptr, 0, m->D2, D_H, m->PRE2);
         gemm(st, m->D2, D_H, 1, m->W2, 1, D_H, B, D_H, D_H, nullptr, nullptr, 0, m->D1, D_H, m->PRE1);
@@ -936,13 +1002,23 @@ int grad_rows(sgtp_mlp *m, const RowSrc &rs, int B, int N, float sig_a, float si
     FinishArgs fa{};
     GemmGroup grp{};
     // gW3 = H2^T D and gb3 = column sums of D (one product); gW2 = H1^T D2, gb2;
-    // gW1 = X^T D1, gb1
-    fa.s[0] = gemm_wgrad(grp, 0, m->PART, m->H2, 1, D_H, m->D, D_OUTP, 1, D_H, D_OUT, B, m->G + P_W3, D_OUT,
-                         m->G + P_B3, k_splits(D_H, D_OUT, B));
-    fa.s[1] = gemm_wgrad(grp, 1, m->PART + third, m->H1, 1, D_H, m->D2, D_H, 1, D_H, D_H, B, m->G + P_W2, D_H,
-                         m->G + P_B2, k_splits(D_H, D_H, B));
-    fa.s[2] = gemm_wgrad(grp, 2, m->PART + 2 * third, m->X, 1, D_INP, m->D1, D_H, 1, D_IN, D_H, B, m->G + P_W1,
-                         D_H, m->G + P_B1, k_splits(D_IN, D_H, B));
+    // gW1 = X^T D1, gb1.  After the fused kernels the operands are read from their
+    // row-blocked copies (same products, 16 consecutive k contiguous).
+    if (B <= FUSED_TRAIN_MAX) {
+        fa.s[0] = gemm_wgrad(grp, 0, m->PART, m->H2B, 16, 16 * D_H, m->DB, 16 * D_OUTP, 16, D_H, D_OUT, B,
+                             m->G + P_W3, D_OUT, m->G + P_B3, k_splits(D_H, D_OUT, B), STAGE_BLK16);
+        fa.s[1] = gemm_wgrad(grp, 1, m->PART + third, m->H1B, 16, 16 * D_H, m->D2B, 16 * D_H, 16, D_H, D_H, B,
+                             m->G + P_W2, D_H, m->G + P_B2, k_splits(D_H, D_H, B), STAGE_BLK16);
+        fa.s[2] = gemm_wgrad(grp, 2, m->PART + 2 * third, m->XB, 16, 16 * D_INP, m->D1B, 16 * D_H, 16, D_IN, D_H,
+                             B, m->G + P_W1, D_H, m->G + P_B1, k_splits(D_IN, D_H, B), STAGE_BLK16);
+    } else {
+        fa.s[0] = gemm_wgrad(grp, 0, m->PART, m->H2, 1, D_H, m->D, D_OUTP, 1, D_H, D_OUT, B, m->G + P_W3, D_OUT,
+                             m->G + P_B3, k_splits(D_H, D_OUT, B));
+        fa.s[1] = gemm_wgrad(grp, 1, m->PART + third, m->H1, 1, D_H, m->D2, D_H, 1, D_H, D_H, B, m->G + P_W2, D_H,
+                             m->G + P_B2, k_splits(D_H, D_H, B));
+        fa.s[2] = gemm_wgrad(grp, 2, m->PART + 2 * third, m->X, 1, D_INP, m->D1, D_H, 1, D_IN, D_H, B,
+                             m->G + P_W1, D_H, m->G + P_B1, k_splits(D_IN, D_H, B));
+    }
     hipLaunchKernelGGL(k_gemm_bf16_group, dim3(grp.first[3]), dim3(256), 0, st, grp);
     // the slice sums and the loss in one launch
     fa.first[0] = 0;
