@@ -766,13 +766,17 @@ int mfail(sgtp_mlp *m, int code, const std::string &s) {
         if (e_ != hipSuccess) return mfail(m, SGTP_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-// K split of a weight-gradient product (K = batch, output (M + 1) x N): enough slices for
-// about 512 workgroups, each slice at least one 64-k chunk, at most 64 slices
+// K split of a weight-gradient product (K = batch, output (M + 1) x N): slices of whole
+// 64-k chunks (a part-filled last chunk in every slice costs as much as a full one), three
+// per slice for the products of many tiles and two for the one of few (at a 4096-row
+// batch 22, 22 and 32 slices, 1008 workgroups in the grouped launch: measured faster than
+// 2 or 4 chunks, and than slices sized for a workgroup count), at most 64 slices
 constexpr int MAX_SPLITS = 64;
 int k_splits(int M, int N, int K) {
     const int tiles = ((N + 63) / 64) * ((M + 1 + 63) / 64);
-    const int s = std::min((512 + tiles - 1) / tiles, std::max(1, K / 64));
-    return std::max(1, std::min(MAX_SPLITS, s));
+    const int c = tiles >= 16 ? 3 : 2;
+    const int chunks = (K + 63) / 64;
+    return std::max(1, std::min(MAX_SPLITS, (chunks + c - 1) / c));
 }
 
 // staging of an operand with element strides (s_r along its rows, s_k along k): 16-byte
