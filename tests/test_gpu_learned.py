@@ -470,3 +470,31 @@ def test_fused_small_batch_forward_matches_tiled_products():
     torch.cuda.synchronize()
     assert np.array_equal(small.cpu().numpy().view(np.uint32), big[:37].cpu().numpy().view(np.uint32))
     m.close()
+
+
+def test_fused_training_forward_matches_tiled_products():
+    """Training batches up to 8192 rows run the forward (and the loss gradient) in the fused
+    kernel, larger ones in the tiled products and the loss kernel.  A row's activations and
+    outputs do not depend on the batch size, so the gradient calls on 8192 and 8193 rows of
+    the same data leave the same hidden activations and outputs in their first 8192 rows, bit
+    for bit."""
+    import torch
+    import paper_2607_25388_amd.sgtp as sg
+    flat, _ = _net(seed=41, scale3=3.0)
+    rng = np.random.default_rng(17)
+    n, N = 8193, 30
+    X = torch.as_tensor(rng.standard_normal((n, 50)).astype(np.float32)).cuda()
+    U = torch.as_tensor(np.stack([rng.uniform(-8, 4, (n, N)), rng.uniform(-0.4, 0.4, (n, N))], -1)
+                        .astype(np.float32)).cuda()
+    m = sg.Mlp(n, flat)
+    try:
+        got = {}
+        for B in (n - 1, n):
+            print(f"training forward, {B} rows", flush=True)
+            m.grad(X[:B].contiguous(), U[:B].contiguous(), 1.5, 0.08)
+            got[B] = {k: m.workspace(k)[: n - 1].cpu().numpy() for k in ("h1", "h2", "out")}
+        for k in ("h1", "h2", "out"):
+            a, b = got[n - 1][k], got[n][k]
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), (k, np.abs(a - b).max())
+    finally:
+        m.close()
