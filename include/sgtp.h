@@ -355,7 +355,8 @@ int sgtp_mlp_grad_sampled(sgtp_mlp *m, const float *X_all, const float *U_all, l
 int sgtp_mlp_adam(sgtp_mlp *m, float lr, float beta1, float beta2, float eps, void *stream);
 /* One training step: sgtp_mlp_grad_sampled (loss, DEVICE, 1 value, when not NULL) followed
  * by sgtp_mlp_adam, with the same results bit for bit, but each parameter takes its Adam
- * step as soon as its gradient is summed (one launch fewer, the gradient not read back).
+ * step as soon as its gradient is summed, and up to 8192 rows the step count advances
+ * inside the gradient's own launches (two launches fewer, the gradient not read back).
  * The gradient is still left for sgtp_mlp_workspace and a later sgtp_mlp_adam.  Errors as
  * sgtp_mlp_grad_sampled. */
 int sgtp_mlp_train_step_sampled(sgtp_mlp *m, const float *X_all, const float *U_all, long long M, int B, int N,

@@ -544,13 +544,16 @@ __global__ void k_nll(const float *out, int ldo, const float *U, int B, int N, f
 // tiled products, so the same bits.
 __global__ void __launch_bounds__(64 * FWD_WAVES) k_mlp_bwd16(const bf16 *D, const bf16 *W3, const bf16 *W2,
                                                              const float *pre2, const float *pre1, int B, bf16 *D2,
-                                                             bf16 *D1, bf16 *D2B, bf16 *D1B) {
+                                                             bf16 *D1, bf16 *D2B, bf16 *D1B, int *step_count) {
     static_assert(FWD_WAVES == 16, "one 16-column tile per wave and layer");
     constexpr int LH = D_H + 8;
     __shared__ __align__(16) bf16 ds[16 * LH];
     __shared__ __align__(16) bf16 d2s[16 * LH];
     const int r0 = blockIdx.x * 16, tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int n0 = 16 * w, col = n0 + (l & 15);
+    // in a combined training step, the Adam step count advances here: the forward before
+    // has drawn its rows with the old count, the Adam step after reads the new one
+    if (step_count && blockIdx.x == 0 && tid == 0) *step_count += 1;
     // everything that does not depend on the products first: the wave's weight fragments
     // and GELU'(pre-activation) of its 4 x 2 elements (rows past B read row B - 1, unused)
     bf16x8 f3[D_OUTP / 32], f2[D_H / 32];
@@ -655,10 +658,11 @@ struct AdamArgs {
     float lr, b1, b2, eps;
     const int *t_prev;
     Bf16Copies copies;
+    int t_add;  // step number t = *t_prev + t_add (0 when the count was already advanced)
 };
-// Adam on parameter e with gradient g (bias-corrected moments, step t = *t_prev + 1)
+// Adam on parameter e with gradient g (bias-corrected moments, step t)
 __device__ __forceinline__ void adam_update(const AdamArgs &a, size_t e, float g) {
-    const float t = (float)(*a.t_prev + 1);
+    const float t = (float)(*a.t_prev + a.t_add);
     const float bc1 = 1.0f - powf(a.b1, t), bc2 = 1.0f - powf(a.b2, t);
     const float mm = a.b1 * a.m[e] + (1.0f - a.b1) * g;
     const float vv = a.b2 * a.v[e] + (1.0f - a.b2) * g * g;
@@ -961,14 +965,16 @@ struct RowSrc {
 
 // Adam's arguments over the network's parameters and moments
 AdamArgs adam_args(sgtp_mlp *m, float lr, float beta1, float beta2, float eps) {
-    return AdamArgs{m->P, m->Mm, m->Vv, lr, beta1, beta2, eps, m->adam_t,
-                    Bf16Copies{m->W1, m->W2, m->W3, m->W1T, m->W2T, m->W3T, m->b3p}};
+    const Bf16Copies copies{m->W1, m->W2, m->W3, m->W1T, m->W2T, m->W3T, m->b3p};
+    return AdamArgs{m->P, m->Mm, m->Vv, lr, beta1, beta2, eps, m->adam_t, copies, 1};
 }
 
 // The gradient of B rows into m->G (and the loss); with ad, each gradient value also takes
-// its Adam step inside the slice-sum launch (the step count is the caller's to advance).
+// its Adam step inside the slice-sum launch, and *counted tells whether the step count was
+// advanced on the way (by the fused input-gradient kernel) or is the caller's to advance.
 int grad_rows(sgtp_mlp *m, const RowSrc &rs, int B, int N, float sig_a, float sig_d, float *loss, float *grads,
-              hipStream_t st, const AdamArgs *ad = nullptr) {
+              hipStream_t st, const AdamArgs *ad = nullptr, bool *counted = nullptr) {
+    if (counted) *counted = false;
     int n_lp;
     if (B <= FUSED_TRAIN_MAX) {  // fetch, forward and loss gradient in one launch
         const TrainIn ti{rs.U,  rs.M,  rs.k0, rs.k1, m->adam_t, m->IDX, m->X, N,
@@ -998,7 +1004,8 @@ int grad_rows(sgtp_mlp *m, const RowSrc &rs, int B, int N, float sig_a, float si
     const size_t third = (size_t)MAX_SPLITS * (D_H + 1) * D_OUTP;
     if (B <= FUSED_TRAIN_MAX) {  // dH2 = D W3^T and dH1 = D2 W2^T in one launch
         hipLaunchKernelGGL(k_mlp_bwd16, dim3((B + 15) / 16), dim3(64 * FWD_WAVES), 0, st, m->D, m->W3, m->W2,
-                           m->PRE2, m->PRE1, B, m->D2, m->D1, m->D2B, m->D1B);
+                           m->PRE2, m->PRE1, B, m->D2, m->D1, m->D2B, m->D1B, ad ? m->adam_t : nullptr);
+        if (counted) *counted = ad != nullptr;
     } else {
         gemm(st, m->D, D_OUTP, 1, m->W3, 1, D_OUTP, B, D_H, D_OUTP, nullptr, nullptr, 0, m->D2, D_H, m->PRE2);
         gemm(st, m->D2, D_H, 1, m->W2, 1, D_H, B, D_H, D_H, nullptr, nullptr, 0, m->D1, D_H, m->PRE1);
@@ -1034,7 +1041,10 @@ int grad_rows(sgtp_mlp *m, const RowSrc &rs, int B, int N, float sig_a, float si
     fa.loss2 = loss;
     fa.G = m->G;
     fa.adam_on = ad != nullptr;
-    if (ad) fa.adam = *ad;
+    if (ad) {
+        fa.adam = *ad;
+        if (counted && *counted) fa.adam.t_add = 0;
+    }
     hipLaunchKernelGGL(k_grad_finish, dim3(fa.first[3] + 1), dim3(256), 0, st, fa);
     MCHK(m, hipGetLastError());
     m->last_B = B;
@@ -1110,10 +1120,11 @@ int sgtp_mlp_train_step_sampled(sgtp_mlp *m, const float *X_all, const float *U_
     hipStream_t st = (hipStream_t)stream;
     m->last_sampled = true;
     const AdamArgs ad = adam_args(m, lr, beta1, beta2, eps);
+    bool counted = false;
     if (int rc = grad_rows(m, RowSrc{X_all, U_all, M, (uint32_t)seed, (uint32_t)(seed >> 32)}, B, N, sig_a, sig_d,
-                           loss, nullptr, st, &ad))
+                           loss, nullptr, st, &ad, &counted))
         return rc;
-    hipLaunchKernelGGL(k_step_count, dim3(1), dim3(64), 0, st, m->adam_t);
+    if (!counted) hipLaunchKernelGGL(k_step_count, dim3(1), dim3(64), 0, st, m->adam_t);
     MCHK(m, hipGetLastError());
     return SGTP_OK;
 }
