@@ -247,6 +247,14 @@ __global__ void __launch_bounds__(256) k_gemm_bf16_group(GemmGroup gg) {
     gemm_tile(gg.g[p], q % gx, (q / gx) % gy, q / (gx * gy), gg.gz[p]);
 }
 
+// a row-blocked copy [B / 16][C][16] back to rows [B][C]
+__global__ void k_unblock(const bf16 *src, int C, int B, bf16 *dst) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)B * C) return;
+    const int b = (int)(e / C), c = (int)(e % C);
+    dst[e] = src[((long long)(b >> 4) * C + c) * 16 + (b & 15)];
+}
+
 __global__ void k_to_bf16_rows(const float *X, int B, int din, int ldx, bf16 *Y, int ldy) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = e / ldy, c = e % ldy;
@@ -440,7 +448,7 @@ __global__ void __launch_bounds__(64 * FWD_WAVES) k_mlp_fwd16(const float *X, in
         const int r = e / D_INP, c = e % D_INP;
         const bf16 v = (r0 + r < B && c < D_IN) ? (bf16)X[src[r] * ldx + c] : (bf16)0.0f;
         xs[r * LX + c] = v;
-        if (TRAIN && r0 + r < B) ti.Xb[(long long)(r0 + r) * D_INP + c] = v;
+        if (TRAIN && ti.Xb && r0 + r < B) ti.Xb[(long long)(r0 + r) * D_INP + c] = v;
     }
     // the targets the loss section below takes (its pairs (row, step, channel) of both of
     // the wave's groups), fetched now
@@ -469,7 +477,7 @@ __global__ void __launch_bounds__(64 * FWD_WAVES) k_mlp_fwd16(const float *X, in
             h1[row * LH + col] = h;
             if (TRAIN && r0 + row < B) {
                 pre1[(long long)(r0 + row) * D_H + col] = x;
-                h1o[(long long)(r0 + row) * D_H + col] = h;
+                if (h1o) h1o[(long long)(r0 + row) * D_H + col] = h;
             }
         }
         if (TRAIN) store_rows4(ti.H1B + (long long)r0 * D_H + col * 16 + 4 * (l >> 4), hb);
@@ -487,7 +495,7 @@ __global__ void __launch_bounds__(64 * FWD_WAVES) k_mlp_fwd16(const float *X, in
             h2[row * LH + col] = h;
             if (TRAIN && r0 + row < B) {
                 pre2[(long long)(r0 + row) * D_H + col] = x;
-                h2o[(long long)(r0 + row) * D_H + col] = h;
+                if (h2o) h2o[(long long)(r0 + row) * D_H + col] = h;
             }
         }
         if (TRAIN) store_rows4(ti.H2B + (long long)r0 * D_H + col * 16 + 4 * (l >> 4), hb);
@@ -587,7 +595,7 @@ __global__ void __launch_bounds__(64 * FWD_WAVES) k_mlp_bwd16(const bf16 *D, con
             bf16 h = (bf16)0.0f;
             if (r0 + row < B) {
                 h = (bf16)(acc[v] * q2[v]);
-                D2[(long long)(r0 + row) * D_H + col] = h;
+                if (D2) D2[(long long)(r0 + row) * D_H + col] = h;
             }
             hb[v] = h;
             d2s[row * LH + col] = h;
@@ -602,7 +610,7 @@ __global__ void __launch_bounds__(64 * FWD_WAVES) k_mlp_bwd16(const bf16 *D, con
         for (int v = 0; v < 4; ++v) {
             const int row = 4 * (l >> 4) + v;
             hb[v] = (bf16)(acc[v] * q1[v]);
-            if (r0 + row < B) D1[(long long)(r0 + row) * D_H + col] = hb[v];
+            if (D1 && r0 + row < B) D1[(long long)(r0 + row) * D_H + col] = hb[v];
         }
         store_rows4(D1B + (long long)r0 * D_H + col * 16 + 4 * (l >> 4), hb);
     }
@@ -756,6 +764,7 @@ struct sgtp_mlp {
     bf16 *XB = nullptr, *H1B = nullptr, *H2B = nullptr, *DB = nullptr, *D2B = nullptr, *D1B = nullptr;
     int last_B = 0;  // rows of the last sgtp_mlp_grad (its workspace tensors stay until the next call)
     bool last_sampled = false;  // the last gradient drew its rows on the device
+    bool last_blocked = false;  // the last gradient left H1, H2, D2 and D1 only row-blocked
 };
 
 namespace {
@@ -977,11 +986,14 @@ int grad_rows(sgtp_mlp *m, const RowSrc &rs, int B, int N, float sig_a, float si
     if (counted) *counted = false;
     int n_lp;
     if (B <= FUSED_TRAIN_MAX) {  // fetch, forward and loss gradient in one launch
-        const TrainIn ti{rs.U,  rs.M,  rs.k0, rs.k1, m->adam_t, m->IDX, m->X, N,
-                         sig_a, sig_d, m->D,  m->LP, m->XB,  m->H1B,    m->H2B, m->DB};
+        // the weight gradients read the row-blocked copies; the row layouts of the features,
+        // hidden activations and input gradients are not written (sgtp_mlp_workspace
+        // rebuilds them from the blocked copies)
+        const TrainIn ti{rs.U,  rs.M,  rs.k0, rs.k1, m->adam_t, m->IDX, nullptr, N,
+                         sig_a, sig_d, m->D,  m->LP, m->XB,  m->H1B,    m->H2B,  m->DB};
         hipLaunchKernelGGL(k_mlp_fwd16<true>, dim3((B + 15) / 16), dim3(64 * FWD_WAVES), 0, st, rs.X,
                            D_IN, B, m->W1T, m->W2T, m->W3T, m->P + P_B1, m->P + P_B2, m->b3p, m->OUT, D_OUTP, D_OUTP,
-                           m->PRE1, m->H1, m->PRE2, m->H2, ti);
+                           m->PRE1, nullptr, m->PRE2, nullptr, ti);
         n_lp = 2 * B;
     } else {
         const float *U = rs.U;
@@ -1004,7 +1016,7 @@ int grad_rows(sgtp_mlp *m, const RowSrc &rs, int B, int N, float sig_a, float si
     const size_t third = (size_t)MAX_SPLITS * (D_H + 1) * D_OUTP;
     if (B <= FUSED_TRAIN_MAX) {  // dH2 = D W3^T and dH1 = D2 W2^T in one launch
         hipLaunchKernelGGL(k_mlp_bwd16, dim3((B + 15) / 16), dim3(64 * FWD_WAVES), 0, st, m->D, m->W3, m->W2,
-                           m->PRE2, m->PRE1, B, m->D2, m->D1, m->D2B, m->D1B, ad ? m->adam_t : nullptr);
+                           m->PRE2, m->PRE1, B, nullptr, nullptr, m->D2B, m->D1B, ad ? m->adam_t : nullptr);
         if (counted) *counted = ad != nullptr;
     } else {
         gemm(st, m->D, D_OUTP, 1, m->W3, 1, D_OUTP, B, D_H, D_OUTP, nullptr, nullptr, 0, m->D2, D_H, m->PRE2);
@@ -1048,6 +1060,7 @@ int grad_rows(sgtp_mlp *m, const RowSrc &rs, int B, int N, float sig_a, float si
     hipLaunchKernelGGL(k_grad_finish, dim3(fa.first[3] + 1), dim3(256), 0, st, fa);
     MCHK(m, hipGetLastError());
     m->last_B = B;
+    m->last_blocked = B <= FUSED_TRAIN_MAX;
     if (grads) MCHK(m, hipMemcpyAsync(grads, m->G, P_TOTAL * 4, hipMemcpyDeviceToDevice, st));
     return SGTP_OK;
 }
@@ -1083,6 +1096,16 @@ int sgtp_mlp_workspace(sgtp_mlp *m, int which, void *dst, void *stream) {
     if (m->last_B < 1) return mfail(m, SGTP_EINVAL, "no gradient computed yet");
     const void *src = nullptr;
     size_t row = 0;
+    if (m->last_blocked && (which == SGTP_MLP_WS_H1 || which == SGTP_MLP_WS_H2 || which == SGTP_MLP_WS_D2 ||
+                            which == SGTP_MLP_WS_D1)) {
+        const bf16 *blk = which == SGTP_MLP_WS_H1 ? m->H1B : which == SGTP_MLP_WS_H2 ? m->H2B
+                          : which == SGTP_MLP_WS_D2 ? m->D2B : m->D1B;
+        const long long n = (long long)m->last_B * D_H;
+        hipLaunchKernelGGL(k_unblock, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, blk, D_H,
+                           m->last_B, (bf16 *)dst);
+        MCHK(m, hipGetLastError());
+        return SGTP_OK;
+    }
     switch (which) {
         case SGTP_MLP_WS_H1: src = m->H1; row = D_H * 2; break;
         case SGTP_MLP_WS_H2: src = m->H2; row = D_H * 2; break;
